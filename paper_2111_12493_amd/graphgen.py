@@ -1,0 +1,392 @@
+"""Seeded synthetic input graphs for k-bisimulation summarization.
+
+This module only *produces inputs*: labeled directed graphs in CSR form with a
+type (vertex-label) list per vertex.  It holds none of the summarization
+arithmetic, so both the CPU oracle and the HIP path can consume the same
+graphs.  Every generator takes an explicit seed and uses numpy's PCG64
+generator, so a (config, seed) pair names one graph on every machine running
+the same numpy.
+
+Graph model (Sec. 2.2, labeled property graphs): directed edges (v, l, w) with
+one edge label l each; a vertex carries a *set* of vertex labels ("types"),
+possibly empty.  Multi-edges, duplicate triples and duplicate type ids are
+allowed in the input; the method has set semantics so they never change a
+result (they exercise the de-duplication).
+
+Workload shapes (stand-ins for the paper's LUBM/BSBM/DyLDO data, which are not
+available): uniform random graphs, R-MAT power-law graphs with Zipf-skewed
+type and edge-label alphabets, and long directed chains that force many
+refinement iterations (long k-chaining, Sec. 3.3).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Graph:
+    """A labeled directed graph in CSR form (host numpy arrays).
+
+    row_off[v]..row_off[v+1] index the out-edges of v in ``tgt``/``lab``;
+    typ_off[v]..typ_off[v+1] index v's type ids in ``typ``.  ``alive`` is None
+    (all vertices alive) or a uint8 mask; dead vertices must have no incident
+    edges.
+    """
+
+    n: int
+    row_off: np.ndarray  # uint64 [n+1]
+    tgt: np.ndarray      # uint32 [m]
+    lab: np.ndarray      # uint32 [m]
+    typ_off: np.ndarray  # uint64 [n+1]
+    typ: np.ndarray      # uint32 [sum |types|]
+    alive: Optional[np.ndarray] = None  # uint8 [n] or None
+    n_labels: int = 0
+    n_types: int = 0
+
+    @property
+    def m(self) -> int:
+        return int(self.tgt.shape[0])
+
+    def src(self) -> np.ndarray:
+        """Source vertex of every edge (expanded from the CSR offsets)."""
+        deg = np.diff(self.row_off).astype(np.int64)
+        return np.repeat(np.arange(self.n, dtype=np.uint32), deg)
+
+    def types_of(self, v: int) -> List[int]:
+        return [int(x) for x in self.typ[int(self.typ_off[v]):int(self.typ_off[v + 1])]]
+
+    def out_edges(self, v: int) -> List[Tuple[int, int]]:
+        a, b = int(self.row_off[v]), int(self.row_off[v + 1])
+        return [(int(self.lab[e]), int(self.tgt[e])) for e in range(a, b)]
+
+
+def from_edges(n: int, src, dst, lab, types: Optional[Sequence[Sequence[int]]] = None,
+               typ_off=None, typ=None, alive=None, n_labels: int = 0,
+               n_types: int = 0) -> Graph:
+    """Build a CSR graph from an edge list.
+
+    Edges keep their relative input order within a source (stable sort), so
+    the CSR is a deterministic function of the edge list.
+    """
+    src = np.asarray(src, dtype=np.int64).reshape(-1)
+    dst = np.asarray(dst, dtype=np.int64).reshape(-1)
+    lab = np.asarray(lab, dtype=np.int64).reshape(-1)
+    if not (src.shape == dst.shape == lab.shape):
+        raise ValueError("src, dst, lab must have equal length")
+    if src.size and (src.min() < 0 or src.max() >= n or dst.min() < 0 or dst.max() >= n):
+        raise ValueError("edge endpoint out of range")
+    order = np.argsort(src, kind="stable")
+    counts = np.bincount(src, minlength=n).astype(np.uint64)
+    row_off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(counts, out=row_off[1:])
+    if types is not None:
+        lens = np.array([len(t) for t in types], dtype=np.uint64)
+        typ_off = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(lens, out=typ_off[1:])
+        flat = [int(x) for t in types for x in t]
+        typ = np.array(flat, dtype=np.uint32)
+    elif typ_off is None:
+        typ_off = np.zeros(n + 1, dtype=np.uint64)
+        typ = np.zeros(0, dtype=np.uint32)
+    g = Graph(n=n, row_off=row_off, tgt=dst[order].astype(np.uint32),
+              lab=lab[order].astype(np.uint32),
+              typ_off=np.asarray(typ_off, dtype=np.uint64),
+              typ=np.asarray(typ, dtype=np.uint32),
+              alive=None if alive is None else np.asarray(alive, dtype=np.uint8),
+              n_labels=int(n_labels) if n_labels else (int(lab.max()) + 1 if lab.size else 0),
+              n_types=int(n_types))
+    if g.n_types == 0 and g.typ.size:
+        g.n_types = int(g.typ.max()) + 1
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Samplers
+# ---------------------------------------------------------------------------
+
+def zipf_sample(rng: np.random.Generator, k: int, s: float, size: int) -> np.ndarray:
+    """Draw ``size`` ids from a finite Zipf law on {0..k-1}: P(i) ~ (i+1)^-s."""
+    w = 1.0 / np.power(np.arange(1, k + 1, dtype=np.float64), s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = rng.random(size)
+    out = np.searchsorted(cdf, u, side="right")
+    return np.minimum(out, k - 1).astype(np.uint32)
+
+
+def zipf_type_lists(rng: np.random.Generator, n: int, k: int, s: float,
+                    lo: int, hi: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Per-vertex type lists: count uniform in {lo..hi}, ids Zipf(k, s).
+
+    Ids are drawn without replacement where a few redraws manage it; any
+    duplicate left over stays in the list (set semantics make it harmless and
+    it exercises the type de-duplication).
+    """
+    cnt = rng.integers(lo, hi + 1, size=n).astype(np.int64)
+    total = int(cnt.sum())
+    ids = zipf_sample(rng, k, s, total).astype(np.int64)
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(cnt, out=off[1:])
+    owner = np.repeat(np.arange(n, dtype=np.int64), cnt)
+    for _ in range(4):
+        key = owner * (k + 1) + ids
+        order = np.lexsort((np.arange(total), key))
+        dup = np.zeros(total, dtype=bool)
+        ks = key[order]
+        dup[order[1:]] = ks[1:] == ks[:-1]
+        nd = int(dup.sum())
+        if nd == 0:
+            break
+        ids[dup] = zipf_sample(rng, k, s, nd)
+    return off.astype(np.uint64), ids.astype(np.uint32)
+
+
+def rmat_edges(rng: np.random.Generator, scale: int, m: int, a: float, b: float,
+               c: float, chunk: int = 1 << 24) -> Tuple[np.ndarray, np.ndarray]:
+    """R-MAT edge endpoints (Chakrabarti et al.): ``scale`` recursive quadrant
+    choices with probabilities (a, b, c, 1-a-b-c); no noise, no permutation."""
+    src = np.zeros(m, dtype=np.uint32)
+    dst = np.zeros(m, dtype=np.uint32)
+    ab, abc = a + b, a + b + c
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        s = np.zeros(hi - lo, dtype=np.uint32)
+        d = np.zeros(hi - lo, dtype=np.uint32)
+        for _ in range(scale):
+            r = rng.random(hi - lo, dtype=np.float32)
+            ubit = (r >= ab).astype(np.uint32)
+            vbit = ((r >= a) & (r < ab)) | (r >= abc)
+            s = (s << 1) | ubit
+            d = (d << 1) | vbit.astype(np.uint32)
+        src[lo:hi] = s
+        dst[lo:hi] = d
+    return src, dst
+
+
+# ---------------------------------------------------------------------------
+# Workload graphs
+# ---------------------------------------------------------------------------
+
+def uniform_graph(n: int, m: int, n_types: int, n_labels: int, types_lo: int = 1,
+                  types_hi: int = 3, s_types: float = 1.0, s_labels: float = 1.0,
+                  seed: int = 1, self_loops: bool = False) -> Graph:
+    """Uniform random directed labeled graph: endpoints i.i.d. uniform
+    (resampled while u == w unless self loops are allowed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    src = rng.integers(0, n, size=m, dtype=np.int64)
+    dst = rng.integers(0, n, size=m, dtype=np.int64)
+    if not self_loops:
+        bad = src == dst
+        while bad.any():
+            dst[bad] = rng.integers(0, n, size=int(bad.sum()), dtype=np.int64)
+            bad = src == dst
+    lab = zipf_sample(rng, n_labels, s_labels, m)
+    typ_off, typ = zipf_type_lists(rng, n, n_types, s_types, types_lo, types_hi)
+    return from_edges(n, src, dst, lab, typ_off=typ_off, typ=typ,
+                      n_labels=n_labels, n_types=n_types)
+
+
+def rmat_graph(scale: int, m: int, n_types: int, n_labels: int, types_lo: int = 0,
+               types_hi: int = 4, s_types: float = 1.1, s_labels: float = 1.1,
+               a: float = 0.57, b: float = 0.19, c: float = 0.19,
+               seed: int = 2, n: Optional[int] = None) -> Graph:
+    """R-MAT graph on 2^scale vertices (or the first ``n`` of them, rejecting
+    edges with an endpoint >= n); self loops and duplicate edges are kept."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nv = (1 << scale) if n is None else int(n)
+    if n is None:
+        src, dst = rmat_edges(rng, scale, m, a, b, c)
+    else:
+        src_l, dst_l, have = [], [], 0
+        while have < m:
+            want = int((m - have) * 1.3) + 64
+            s, d = rmat_edges(rng, scale, want, a, b, c)
+            keep = (s < nv) & (d < nv)
+            s, d = s[keep], d[keep]
+            src_l.append(s)
+            dst_l.append(d)
+            have += s.size
+        src = np.concatenate(src_l)[:m]
+        dst = np.concatenate(dst_l)[:m]
+    lab = zipf_sample(rng, n_labels, s_labels, m)
+    typ_off, typ = zipf_type_lists(rng, nv, n_types, s_types, types_lo, types_hi)
+    return from_edges(nv, src, dst, lab, typ_off=typ_off, typ=typ,
+                      n_labels=n_labels, n_types=n_types)
+
+
+def append_chains(g: Graph, n_chains: int, length: int, type_id: int,
+                  label: int = 0) -> Graph:
+    """Append ``n_chains`` disjoint directed chains of ``length`` edges
+    (length+1 vertices each).  Chain vertices carry the single type
+    ``type_id`` and every chain edge has ``label``; the chains force the
+    refinement to run at least length+1 iterations to reach its fixpoint."""
+    n0 = g.n
+    per = length + 1
+    nv = n0 + n_chains * per
+    base = n0 + np.arange(n_chains, dtype=np.int64)[:, None] * per
+    step = np.arange(length, dtype=np.int64)[None, :]
+    csrc = (base + step).reshape(-1)
+    cdst = csrc + 1
+    src = np.concatenate([g.src().astype(np.int64), csrc])
+    dst = np.concatenate([g.tgt.astype(np.int64), cdst])
+    lab = np.concatenate([g.lab.astype(np.int64), np.full(csrc.size, label, dtype=np.int64)])
+    t_lens = np.concatenate([np.diff(g.typ_off).astype(np.int64),
+                             np.ones(n_chains * per, dtype=np.int64)])
+    typ_off = np.zeros(nv + 1, dtype=np.uint64)
+    np.cumsum(t_lens, out=typ_off[1:])
+    typ = np.concatenate([g.typ, np.full(n_chains * per, type_id, dtype=np.uint32)])
+    return from_edges(nv, src, dst, lab, typ_off=typ_off, typ=typ,
+                      n_labels=max(g.n_labels, label + 1),
+                      n_types=max(g.n_types, type_id + 1))
+
+
+def with_u16_labels(g: Graph) -> Graph:
+    """Same graph with labels stored as uint16 (alphabets of <= 65536 labels)."""
+    if g.lab.size and int(g.lab.max()) > 0xFFFF:
+        raise ValueError("labels do not fit in 16 bits")
+    return dataclasses.replace(g, lab=g.lab.astype(np.uint16))
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+CONFIGS = {
+    # 10,000 vertices, 50,000 uniform edges, 1-3 types of 8 (Zipf 1.0),
+    # 16 edge labels (Zipf 1.0), no self loops.
+    "uniform_10k_50k": dict(kind="uniform", n=10_000, m=50_000, n_types=8, n_labels=16,
+                            types_lo=1, types_hi=3, s_types=1.0, s_labels=1.0, seed=1),
+    # R-MAT scale 22, 2^25 edges, 256 types (Zipf 1.1, 0-4 per vertex), 64 edge
+    # labels (Zipf 1.1), plus 64 chains of 2,000 edges.
+    "rmat22_chains": dict(kind="rmat", scale=22, m=1 << 25, n_types=256, n_labels=64,
+                          types_lo=0, types_hi=4, s_types=1.1, s_labels=1.1, seed=2,
+                          chains=64, chain_len=2000),
+    # R-MAT scale 24, 2^27 edges, 128 types, 64 labels (Zipf 1.1): the resident
+    # base graph of the incremental / serving workload.
+    "rmat24": dict(kind="rmat", scale=24, m=1 << 27, n_types=128, n_labels=64,
+                   types_lo=0, types_hi=4, s_types=1.1, s_labels=1.1, seed=5),
+    # Reduced shapes of the same recipes, for tests that must stay fast.
+    "rmat16_chains": dict(kind="rmat", scale=16, m=1 << 19, n_types=256, n_labels=64,
+                          types_lo=0, types_hi=4, s_types=1.1, s_labels=1.1, seed=2,
+                          chains=8, chain_len=200),
+    "rmat18": dict(kind="rmat", scale=18, m=1 << 21, n_types=128, n_labels=64,
+                   types_lo=0, types_hi=4, s_types=1.1, s_labels=1.1, seed=5),
+}
+
+
+def make_config(name: str, seed: Optional[int] = None) -> Graph:
+    cfg = dict(CONFIGS[name])
+    if seed is not None:
+        cfg["seed"] = seed
+    kind = cfg.pop("kind")
+    if kind == "uniform":
+        return uniform_graph(**cfg)
+    chains = cfg.pop("chains", 0)
+    chain_len = cfg.pop("chain_len", 0)
+    g = rmat_graph(**cfg)
+    if chains:
+        # one reserved type id that the Zipf sampler never draws
+        g = append_chains(g, chains, chain_len, type_id=cfg["n_types"], label=0)
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Small structured graphs (closed-form block counts) and paper fixtures
+# ---------------------------------------------------------------------------
+
+def chain(length: int, typed_end: bool = False) -> Graph:
+    """Directed path 0 -> 1 -> ... -> length with one edge label."""
+    n = length + 1
+    src = np.arange(length)
+    types = [[] for _ in range(n)]
+    if typed_end:
+        types[-1] = [1]
+    return from_edges(n, src, src + 1, np.zeros(length, dtype=np.int64), types=types)
+
+
+def cycle(n: int, marked: bool = False) -> Graph:
+    """Directed n-cycle with one edge label; ``marked`` gives vertex 0 a
+    distinct type."""
+    src = np.arange(n)
+    types = [[] for _ in range(n)]
+    if marked:
+        types[0] = [7]
+    return from_edges(n, src, (src + 1) % n, np.zeros(n, dtype=np.int64), types=types)
+
+
+def out_star(leaves: int, label: int = 0) -> Graph:
+    """Vertex 0 with one edge of the same label to each of ``leaves`` leaves."""
+    n = leaves + 1
+    src = np.zeros(leaves, dtype=np.int64)
+    return from_edges(n, src, np.arange(1, n), np.full(leaves, label), types=[[] for _ in range(n)])
+
+
+def binary_tree(depth: int) -> Graph:
+    """Complete binary tree of the given depth, edges pointing to children."""
+    n = (1 << (depth + 1)) - 1
+    src, dst = [], []
+    for v in range(n):
+        for ch in (2 * v + 1, 2 * v + 2):
+            if ch < n:
+                src.append(v)
+                dst.append(ch)
+    return from_edges(n, src, dst, np.zeros(len(src), dtype=np.int64), types=[[] for _ in range(n)])
+
+
+# Label / type dictionaries for the paper's Sec. 2.2 example graph.
+PAPER_EXAMPLE_LABELS = {"author": 0, "title": 1, "name": 2}
+PAPER_EXAMPLE_TYPES = {"Proceedings": 0, "Person": 1}
+
+
+def paper_example(typed: bool = True) -> Graph:
+    """The labeled property graph of Sec. 2.2 (the figure next to the LPG
+    definition): v1 -author-> v2, v1 -title-> v3, v2 -name-> v4; v1 is a
+    Proceedings, v2 a Person, v3 and v4 carry no type.  Vertices are numbered
+    v1..v4 -> 0..3."""
+    L = PAPER_EXAMPLE_LABELS
+    T = PAPER_EXAMPLE_TYPES
+    types = [[T["Proceedings"]], [T["Person"]], [], []] if typed else [[], [], [], []]
+    return from_edges(4, [0, 0, 1], [1, 2, 3], [L["author"], L["title"], L["name"]],
+                      types=types, n_labels=3, n_types=2)
+
+
+FIG1_TYPES = {"Book": 0, "Person": 1, "Subject": 2, "Agent": 3}
+FIG1_LABELS = {"author": 0, "topic": 1}
+
+
+def fig1_scenario(after_change: bool) -> Graph:
+    """The evolving graph of the introduction, rebuilt from its text (the
+    figure itself is not available): two books v1, v7, each with an author
+    (v2, v8: Person) and a topic (v3, v9: Subject).  At time t+1 vertex v8 is
+    an Agent instead of a Person.  Vertices v1, v2, v3, v7, v8, v9 are
+    numbered 0..5."""
+    T, L = FIG1_TYPES, FIG1_LABELS
+    types = [[T["Book"]], [T["Person"]], [T["Subject"]],
+             [T["Book"]], [T["Agent"] if after_change else T["Person"]], [T["Subject"]]]
+    return from_edges(6, [0, 0, 3, 3], [1, 2, 4, 5],
+                      [L["author"], L["topic"], L["author"], L["topic"]], types=types,
+                      n_labels=2, n_types=4)
+
+
+def random_small_graph(rng: np.random.Generator, n: int, m: int, n_labels: int,
+                       n_types: int, max_types: int = 2, p_alive: float = 1.0) -> Graph:
+    """Small random multigraph (self loops and duplicate triples allowed) for
+    exhaustive comparisons.  With p_alive < 1 some vertices are dead; dead
+    vertices keep no incident edges."""
+    alive = (rng.random(n) < p_alive).astype(np.uint8) if p_alive < 1.0 else None
+    src = rng.integers(0, n, size=m)
+    dst = rng.integers(0, n, size=m)
+    lab = rng.integers(0, max(1, n_labels), size=m)
+    if alive is not None:
+        keep = (alive[src] == 1) & (alive[dst] == 1)
+        src, dst, lab = src[keep], dst[keep], lab[keep]
+    types = []
+    for _ in range(n):
+        c = int(rng.integers(0, max_types + 1)) if n_types > 0 else 0
+        types.append([int(x) for x in rng.integers(0, max(1, n_types), size=c)])
+    return from_edges(n, src, dst, lab, types=types, alive=alive,
+                      n_labels=max(1, n_labels), n_types=max(1, n_types))

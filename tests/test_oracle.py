@@ -1,0 +1,269 @@
+"""Pins for the CPU oracle (no GPU needed).
+
+The oracle is trusted only because these tests tie it to things outside
+itself: a published test vector for its mixer, the paper's worked example,
+closed-form block counts, a hash-free exact refinement written from the
+bisimulation definition, a pairwise brute force of that definition, and
+invariants of the refinement.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import oracle as orc
+from paper_2111_12493_amd import graphgen as gg
+
+MASK = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------- the mixer
+
+def test_mixer_matches_published_splitmix64_vector(golden):
+    rows = golden("splitmix64_seed1234567.txt")
+    state = int(rows["seed"][0][0])
+    inc = int(rows["increment"][0][0], 16)
+    expected = [int(k) for k in rows if k.isdigit()]
+    outs = []
+    for _ in range(len(expected)):
+        state = (state + inc) & MASK
+        outs.append(orc.mix(state))
+    assert outs == expected
+
+
+def test_mixer_is_a_bijection():
+    # invert each step: xorshift-right by s is undone by iterating it, and
+    # multiplication by an odd constant by its inverse mod 2^64
+    c1, c2 = 0xBF58476D1CE4E5B9, 0x94D049BB133111EB
+    i1, i2 = pow(c1, -1, 1 << 64), pow(c2, -1, 1 << 64)
+
+    def unxorshift(z, s):
+        x = z
+        for _ in range(64 // s + 1):
+            x = z ^ (x >> s)
+        return x
+
+    rng = np.random.default_rng(3)
+    for z in [0, 1, MASK] + [int(x) for x in rng.integers(0, 1 << 63, 200, dtype=np.uint64)]:
+        y = orc.mix(z)
+        x = unxorshift(y, 31)
+        x = (x * i2) & MASK
+        x = unxorshift(x, 27)
+        x = (x * i1) & MASK
+        x = unxorshift(x, 30)
+        assert x == z
+
+
+def test_type_hash_is_a_set_function():
+    # order and repeats of type ids do not matter; different sets differ
+    a = orc.type_hash([3, 1, 2])
+    assert a == orc.type_hash([1, 2, 3]) == orc.type_hash([2, 2, 3, 1, 1])
+    assert a != orc.type_hash([1, 2])
+    assert orc.type_hash([]) == orc.type_hash([5], untyped=True)
+
+
+def test_vertex_step_is_a_set_function():
+    h_prev = np.array([11, 22, 33, 44], dtype=np.uint64)
+    t = 999
+    base = orc.vertex_step(t, [1, 2], [0, 1], h_prev)
+    assert base == orc.vertex_step(t, [2, 1], [1, 0], h_prev)            # order
+    assert base == orc.vertex_step(t, [1, 2, 1, 2], [0, 1, 0, 1], h_prev)  # repeats
+    assert base != orc.vertex_step(t, [1, 2], [1, 0], h_prev)            # pairing
+    assert base != orc.vertex_step(t + 1, [1, 2], [0, 1], h_prev)        # own type
+    assert base != orc.vertex_step(t, [1], [0], h_prev)                  # a dropped pair
+
+
+# ------------------------------------------------------- paper fixtures
+
+def test_paper_worked_example(golden):
+    rows = golden("paper_example_k2.txt")
+    g = gg.paper_example()
+    r = orc.summarize(g, k_max=2, stop_at_fixpoint=False, untyped=True)
+    assert list(r["block_ids"]) == [int(x) for x in rows["untyped_block_ids"][0]]
+    assert list(r["blocks_per_iter"]) == [int(x) for x in rows["untyped_counts"][0]]
+    edges = sorted(zip(r["se_src"].tolist(), r["se_label"].tolist(), r["se_dst"].tolist()))
+    assert edges == [tuple(int(x) for x in e) for e in rows["edges"]]
+    rt = orc.summarize(g, k_max=2, stop_at_fixpoint=False, untyped=False)
+    assert list(rt["blocks_per_iter"]) == [int(x) for x in rows["typed_counts"][0]]
+    assert list(rt["block_ids"]) == [int(x) for x in rows["untyped_block_ids"][0]]
+    # with the fixpoint test the untyped run stops at k = 2, the typed at k = 1
+    assert orc.summarize(g, 10, True, True)["k_done"] == 2
+    assert orc.summarize(g, 10, True, False)["k_done"] == 1
+
+
+def test_fig1_scenario(golden):
+    rows = golden("fig1_scenario.txt")
+    for when, after in (("before", False), ("after", True)):
+        r = orc.summarize(gg.fig1_scenario(after), k_max=1, stop_at_fixpoint=False)
+        assert list(r["block_ids"]) == [int(x) for x in rows[when + "_block_ids"][0]]
+        assert r["n_blocks"] == int(rows[when + "_count_k1"][0][0])
+
+
+# ------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("L", [1, 2, 5, 17])
+def test_chain_counts(L):
+    g = gg.chain(L)
+    r = orc.summarize(g, k_max=L + 5, stop_at_fixpoint=True, untyped=True)
+    assert list(r["blocks_per_iter"]) == [min(k + 1, L + 1) for k in range(r["k_done"] + 1)]
+    assert r["k_done"] == L + 1 and r["fixpoint"] == 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 12])
+def test_cycles(n):
+    r = orc.summarize(gg.cycle(n), 20, True, False)
+    assert r["n_blocks"] == 1 and r["k_done"] == 1
+    if n >= 2:
+        rm = orc.summarize(gg.cycle(n, marked=True), n + 3, False, False)
+        assert list(rm["blocks_per_iter"]) == [min(k + 2, n) for k in range(n + 4)]
+
+
+def test_star_dedupe():
+    # a star with 5 leaves and one with 1 leaf are bisimilar: the edge set of
+    # a center is a *set* of (label, class) pairs
+    src = [0] * 5 + [6]
+    dst = [1, 2, 3, 4, 5, 7]
+    g = gg.from_edges(8, src, dst, [0] * 6, types=[[] for _ in range(8)])
+    r = orc.summarize(g, 5, True, True)
+    assert r["block_ids"][0] == r["block_ids"][6]
+    assert list(r["blocks_per_iter"]) == [1, 2, 2]
+    assert list(orc.summarize(gg.out_star(9), 5, True, True)["blocks_per_iter"]) == [1, 2, 2]
+
+
+@pytest.mark.parametrize("D", [1, 2, 4])
+def test_binary_tree(D):
+    r = orc.summarize(gg.binary_tree(D), D + 3, False, True)
+    assert list(r["blocks_per_iter"]) == [min(k + 1, D + 1) for k in range(D + 4)]
+
+
+def test_empty_and_edgeless():
+    g = gg.from_edges(0, [], [], [])
+    r = orc.summarize(g, 3)
+    assert r["n_blocks"] == 0 and r["k_done"] == 1 and list(r["blocks_per_iter"]) == [0, 0]
+    g = gg.from_edges(4, [], [], [], types=[[1], [], [1], [2, 1]])
+    r = orc.summarize(g, 3)
+    assert list(r["block_ids"]) == [0, 1, 0, 2] and r["k_done"] == 1
+
+
+# ------------------------------------ against the hash-free references
+
+def _check_against_exact(g, k_max, stop, untyped):
+    r = orc.summarize(g, k_max, stop, untyped)
+    levels, counts, k_done = exact.exact_refinement(g, k_max, stop, untyped)
+    assert r["k_done"] == k_done
+    assert list(r["blocks_per_iter"]) == counts
+    want = [0xFFFFFFFF if b is None else b for b in levels[k_done]]
+    assert list(r["block_ids"]) == want
+    assert r["n_blocks"] == counts[-1]
+    sizes = np.bincount(np.array([b for b in want if b != 0xFFFFFFFF], dtype=np.int64),
+                        minlength=r["n_blocks"])
+    assert list(r["block_sizes"]) == list(sizes)
+    edges = list(zip(r["se_src"].tolist(), r["se_label"].tolist(), r["se_dst"].tolist()))
+    assert edges == exact.quotient_edges(g, want)
+    return r
+
+
+def test_random_graphs_match_exact_refinement():
+    rng = np.random.default_rng(11)
+    for trial in range(150):
+        n = int(rng.integers(1, 40))
+        m = int(rng.integers(0, 4 * n + 1))
+        g = gg.random_small_graph(rng, n, m, n_labels=int(rng.integers(1, 4)),
+                                  n_types=int(rng.integers(1, 4)), max_types=2,
+                                  p_alive=1.0 if trial % 3 else 0.8)
+        _check_against_exact(g, 50, True, bool(trial % 2))
+        _check_against_exact(g, int(rng.integers(0, 4)), False, bool(trial % 2))
+
+
+def test_every_level_matches_exact_refinement():
+    rng = np.random.default_rng(12)
+    for _ in range(30):
+        g = gg.random_small_graph(rng, 30, 70, 3, 3)
+        levels, counts, kd = exact.exact_refinement(g, 12, False, False)
+        for k in range(0, 13):
+            r = orc.summarize(g, k, False, False)
+            assert list(r["block_ids"]) == levels[k]
+
+
+def test_exhaustive_two_vertex_graphs_match_definition():
+    # every graph on 2 vertices with <= 2 edge labels (8 possible triples)
+    # and every assignment of a type in {none, 0} to each vertex
+    triples = [(u, l, w) for u in range(2) for l in range(2) for w in range(2)]
+    for mask in range(1 << len(triples)):
+        es = [t for i, t in enumerate(triples) if mask >> i & 1]
+        for tmask in range(4):
+            types = [[0] if tmask >> v & 1 else [] for v in range(2)]
+            g = gg.from_edges(2, [e[0] for e in es], [e[2] for e in es], [e[1] for e in es],
+                              types=types, n_labels=2)
+            for k in (1, 2):
+                r = orc.summarize(g, k, False, False)
+                assert list(r["block_ids"]) == exact.brute_force_classes(g, k)
+
+
+def test_random_tiny_graphs_match_definition():
+    rng = np.random.default_rng(13)
+    for trial in range(300):
+        n = int(rng.integers(1, 8))
+        g = gg.random_small_graph(rng, n, int(rng.integers(0, 3 * n)), 2, 2, 1,
+                                  p_alive=1.0 if trial % 4 else 0.7)
+        k = int(rng.integers(0, 5))
+        untyped = bool(trial % 2)
+        r = orc.summarize(g, k, False, untyped)
+        bf = exact.brute_force_classes(g, k, untyped)
+        assert list(r["block_ids"]) == [0xFFFFFFFF if b is None else b for b in bf]
+
+
+def test_counterexample_to_printed_algorithm_is_separated():
+    # v has an a-edge to x (out-label 0) and a b-edge to y (out-label 1);
+    # v' has the same edges with the targets' out-labels swapped.  Labeled
+    # 2-bisimulation separates v and v' (the printed id_o track would not).
+    src = [0, 0, 1, 2, 3, 3, 4, 5]
+    dst = [1, 2, 6, 6, 4, 5, 6, 6]
+    lab = [0, 1, 2, 3, 0, 1, 3, 2]
+    g = gg.from_edges(7, src, dst, lab, types=[[] for _ in range(7)])
+    r = orc.summarize(g, 2, False, True)
+    assert r["block_ids"][0] != r["block_ids"][3]
+    assert exact.brute_force_classes(g, 2, True)[0] != exact.brute_force_classes(g, 2, True)[3]
+
+
+# ------------------------------------------------------- invariants
+
+def test_refinement_and_fixpoint_invariants():
+    g = gg.make_config("uniform_10k_50k")
+    r_prev = None
+    for k in range(0, 6):
+        r = orc.summarize(g, k, False)
+        if r_prev is not None:
+            # P_k refines P_{k-1}: block(k) -> block(k-1) is a function
+            f = {}
+            for b_new, b_old in zip(r["block_ids"].tolist(), r_prev["block_ids"].tolist()):
+                assert f.setdefault(b_new, b_old) == b_old
+            assert r["n_blocks"] >= r_prev["n_blocks"]
+        r_prev = r
+    full = orc.summarize(g, 100, True)
+    more = orc.summarize(g, full["k_done"] + 1, False)
+    assert list(more["block_ids"]) == list(full["block_ids"])
+    assert full["fixpoint"] == 1
+
+
+def test_uniform_config_collision_audit():
+    # the hash partition equals the hash-free exact partition on the
+    # uniform 10k/50k workload at every level up to its fixpoint
+    g = gg.make_config("uniform_10k_50k")
+    r = orc.summarize(g, 10, True)
+    levels, counts, kd = exact.exact_refinement(g, 10, True)
+    assert r["k_done"] == kd and list(r["blocks_per_iter"]) == counts
+    assert list(r["block_ids"]) == levels[kd]
+
+
+def test_determinism():
+    g = gg.make_config("uniform_10k_50k")
+    a = orc.summarize(g, 10)
+    b = orc.summarize(g, 10)
+    assert np.array_equal(a["hashes"], b["hashes"])
+
+
+def test_dead_vertex_edge_is_rejected():
+    g = gg.from_edges(3, [0], [1], [0], alive=np.array([1, 0, 1], dtype=np.uint8))
+    with pytest.raises(ValueError):
+        orc.summarize(g, 2)

@@ -1,0 +1,128 @@
+"""Planted mistakes in a copy of the oracle must be caught by the pins.
+
+Each case edits one line of a temporary copy of the C oracle (a dropped term,
+a wrong operand, a wrong index, an off-by-one), compiles it with gcc, swaps it
+in for the real oracle, and checks that the pin checks fail.  This runs on the
+CPU only and never touches the real oracle library.
+"""
+
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import oracle as orc
+from paper_2111_12493_amd import graphgen as gg
+
+MUTANTS = {
+    "drop_label_from_key": ("keys[i] = h_prev[tgt[i]] ^ bo_label_salt(lab[i]);",
+                            "keys[i] = h_prev[tgt[i]];"),
+    "no_key_dedupe": ("size_t u = unique_u64(keys, (size_t)deg);",
+                      "size_t u = (size_t)deg; qsort(keys, u, 8, cmp_u64);"),
+    "drop_own_type": ("return bo_mix(t_v ^ bo_mix(cs + sum));",
+                      "return bo_mix(bo_mix(cs + sum));"),
+    "wrong_gather_index": ("keys[i] = h_prev[tgt[i]] ^ bo_label_salt(lab[i]);",
+                           "keys[i] = h_prev[tgt[0]] ^ bo_label_salt(lab[i]);"),
+    "no_type_dedupe": ("size_t u = unique_u32(tmp, n_types);",
+                       "size_t u = n_types;"),
+    "fixpoint_off_by_one": ("if (blocks_per_iter[k] == blocks_per_iter[k - 1]) {",
+                            "if (k > 1 && blocks_per_iter[k - 1] == blocks_per_iter[k - 2]) {"),
+    "hash_classes_not_grouped": ("uint32_t m = (i > 0 && p[i].h == p[i - 1].h) ? minv[p[i - 1].v] : p[i].v;",
+                                 "uint32_t m = p[i].v;"),
+    "blocks_numbered_by_largest_vertex": ("for (uint32_t v = 0; v < n; v++)\n        if (is_min[v]) rank[v] = nb++;",
+                                          "for (uint32_t v = n; v-- > 0;)\n        if (is_min[v]) rank[v] = nb++;"),
+    "summary_edge_transposed": ("tr[ne].d = block_ids[tgt[e]];",
+                                "tr[ne].d = block_ids[v]; tr[ne].s = block_ids[tgt[e]];"),
+}
+
+# Mutations that keep a valid *set* hash change hash values but no partition.
+# The paper fixes no hash function, so nothing outside the written spec can
+# pin the values themselves ("parity unpinned" for raw hash values); these
+# cases document that blind spot instead of hiding it.
+UNPINNED_VALUE_MUTANTS = {
+    "sum_replaced_by_xor": ("for (size_t i = 0; i < u; i++) sum += bo_mix(keys[i] ^ ce);",
+                            "for (size_t i = 0; i < u; i++) sum ^= bo_mix(keys[i] ^ ce);"),
+}
+
+
+def _pins_hold() -> bool:
+    """A compact selection of the pin checks; False as soon as one fails."""
+    try:
+        g = gg.paper_example()
+        r = orc.summarize(g, 2, False, True)
+        if list(r["block_ids"]) != [0, 1, 2, 2] or list(r["blocks_per_iter"]) != [1, 3, 3]:
+            return False
+        rows = [(0, 0, 1), (0, 1, 2), (1, 2, 2)]
+        if list(zip(r["se_src"].tolist(), r["se_label"].tolist(), r["se_dst"].tolist())) != rows:
+            return False
+        for L in (1, 5):
+            r = orc.summarize(gg.chain(L), L + 5, True, True)
+            if r["k_done"] != L + 1:
+                return False
+        rng = np.random.default_rng(21)
+        for trial in range(60):
+            n = int(rng.integers(2, 30))
+            g = gg.random_small_graph(rng, n, int(rng.integers(0, 4 * n)), 3, 3, 3)
+            r = orc.summarize(g, 20, True, bool(trial % 2))
+            levels, counts, kd = exact.exact_refinement(g, 20, True, bool(trial % 2))
+            if r["k_done"] != kd or list(r["blocks_per_iter"]) != counts:
+                return False
+            if list(r["block_ids"]) != levels[kd]:
+                return False
+            es = list(zip(r["se_src"].tolist(), r["se_label"].tolist(), r["se_dst"].tolist()))
+            if es != exact.quotient_edges(g, levels[kd]):
+                return False
+        # a graph whose vertex has many equal keys: the mixer-sum must see a set
+        g = gg.from_edges(5, [0, 0, 0, 1], [2, 3, 4, 2], [0, 0, 0, 0], types=[[]] * 5)
+        r = orc.summarize(g, 3, True, True)
+        if r["block_ids"][0] != r["block_ids"][1]:
+            return False
+        return True
+    except ValueError:
+        return False
+
+
+def test_real_oracle_passes_the_pin_selection():
+    assert _pins_hold()
+
+
+def _compile_mutant(before, after, tmp_path):
+    src = open(orc.SRC).read()
+    assert src.count(before) >= 1, "mutation anchor not found"
+    mutated = src.replace(before, after, 1)
+    c = tmp_path / "mutant.c"
+    so = tmp_path / "libmutant.so"
+    c.write_text(mutated)
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-w", "-shared", "-fPIC", "-o", str(so), str(c)])
+    return str(so)
+
+
+def _pins_hold_with(lib_path):
+    saved = orc._lib
+    try:
+        orc._lib = orc.load(lib_path)
+        return _pins_hold()
+    finally:
+        orc._lib = saved
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    before, after = MUTANTS[name]
+    assert not _pins_hold_with(_compile_mutant(before, after, tmp_path)), \
+        "planted mistake went unnoticed: " + name
+
+
+@pytest.mark.parametrize("name", sorted(UNPINNED_VALUE_MUTANTS))
+def test_value_only_mutation_keeps_partitions(name, tmp_path):
+    before, after = UNPINNED_VALUE_MUTANTS[name]
+    so = _compile_mutant(before, after, tmp_path)
+    assert _pins_hold_with(so)
+    saved = orc._lib
+    try:
+        orc._lib = orc.load(so)
+        mutated = orc.summarize(gg.paper_example(), 2, False, True)["hashes"]
+    finally:
+        orc._lib = saved
+    assert not np.array_equal(mutated, orc.summarize(gg.paper_example(), 2, False, True)["hashes"])
