@@ -1,0 +1,221 @@
+/*
+ * bsim.h -- C ABI of the MI355X (gfx950) hash-based k-bisimulation library.
+ *
+ * The library computes labeled forward k-bisimulation summaries of labeled
+ * directed graphs with hash messages (paper Sec. 3.3, Algorithm 4; the
+ * partition it computes is the one of Sec. 2.5's forward bisimulation with
+ * the typed variant, chained as in Sec. 2.4's chaining parameterization):
+ *
+ *   h^0(v) = t(v)                                   hash of v's type set
+ *   h^k(v) = F(t(v), SET{ (l, h^{k-1}(w)) : (v, l, w) in E })
+ *
+ * with the 64-bit hash spec
+ *   M        = SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014)
+ *   C_T..C_E = M(1), M(2), M(3), M(4)
+ *   t(v)     = M(C_T + sum_{distinct types tau} M(C_T ^ tau))
+ *   salt(l)  = M(C_L + l)
+ *   h^k(v)   = M(t(v) ^ M(C_S + sum_{distinct q} M(q ^ C_E))),
+ *              q = h^{k-1}(w) ^ salt(l) over v's out-edges (v, l, w)
+ * All arithmetic wraps mod 2^64.  Blocks are numbered by first occurrence
+ * (the block holding the smallest vertex id is 0).  The refinement stops at
+ * the first k >= 1 whose block count equals that of k-1 (the partition is
+ * then stable: maximal bisimulation refining the type partition) or at k_max.
+ *
+ * Conventions for every call:
+ *  - Plain pointers and fixed-width integers only; no exceptions cross the
+ *    ABI.  Calls return BSIM_OK (0) or a negative status; on error every
+ *    output pointer is set to NULL and no state is modified.
+ *  - A bsim_ctx is bound to one device and one HIP stream (borrowed from
+ *    the caller).  All device work of a call is ordered on that stream; a
+ *    call returns after its results are complete.  A ctx is not thread safe:
+ *    use one ctx per host thread.
+ *  - Input arrays are borrowed for the duration of the call only.
+ *  - Every object returned by the library is owned by the library and freed
+ *    with the matching *_free call, before the ctx it came from.
+ */
+#ifndef BSIM_H
+#define BSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define BSIM_OK 0
+#define BSIM_E_INVALID (-1)     /* malformed input: CSR not monotone, bad sizes, edge to a dead vertex */
+#define BSIM_E_RANGE (-2)       /* an id or label out of its range */
+#define BSIM_E_NOMEM (-3)       /* device or host allocation failed */
+#define BSIM_E_DEVICE (-4)      /* a HIP runtime error; text in bsim_last_error */
+#define BSIM_E_UNSUPPORTED (-5) /* valid input outside this build's limits */
+#define BSIM_E_BUSY (-6)        /* server: request does not fit the memory budget now */
+
+/* ---- where an array lives ---------------------------------------------- */
+#define BSIM_MEM_HOST 0u
+#define BSIM_MEM_DEVICE 1u
+
+/* ---- bsim_params.flags ------------------------------------------------- */
+#define BSIM_STOP_AT_FIXPOINT 1u   /* stop when the block count stops growing */
+#define BSIM_KEEP_LEVELS 2u        /* keep h^0..h^k resident in the returned state */
+#define BSIM_UNTYPED 4u            /* ignore vertex types: t(v) = M(C_T) for all v */
+#define BSIM_RESULT_ON_HOST 8u     /* copy result arrays to host memory */
+#define BSIM_NO_SUMMARY_EDGES 16u  /* skip the quotient-edge output */
+
+typedef struct bsim_ctx bsim_ctx;
+typedef struct bsim_state bsim_state;
+
+/*
+ * A labeled directed graph in CSR form (Sec. 2.2 labeled property graphs:
+ * each vertex has a set of type ids, each edge one label).
+ *   row_off[n_vertices+1]  out-edge offsets, row_off[0] = 0, monotone,
+ *                          row_off[n] = n_edges (< 2^32 in this build)
+ *   targets[n_edges]       edge target vertex, < n_vertices
+ *   labels[n_edges]        edge label, uint16 (label_bytes 2) or uint32 (4)
+ *   type_off[n_vertices+1] offsets into type_ids (monotone)
+ *   type_ids[...]          vertex type ids; repeats allowed (set semantics)
+ *   alive[n_vertices]      NULL = all alive; else 0 marks a deleted vertex,
+ *                          which must have no incident edge
+ * Multi-edges and repeated triples are allowed and never change results.
+ * mem_kind says whether all arrays are host or device pointers.
+ */
+typedef struct {
+    uint32_t n_vertices;
+    uint32_t label_bytes;
+    uint64_t n_edges;
+    const uint32_t* row_off;
+    const uint32_t* targets;
+    const void* labels;
+    const uint32_t* type_off;
+    const uint32_t* type_ids;
+    const uint8_t* alive;
+    uint32_t mem_kind;
+    uint32_t reserved;
+} bsim_graph;
+
+typedef struct {
+    uint32_t k_max; /* iteration cap; UINT32_MAX = none (run to the fixpoint) */
+    uint32_t flags; /* BSIM_* flags above */
+} bsim_params;
+
+/*
+ * Result of a summarization (batch or incremental).  Arrays live where
+ * mem_kind says (device unless BSIM_RESULT_ON_HOST was requested), except
+ * blocks_per_iter, which is always host memory.
+ *   hashes[n_vertices]       h^{k_done}(v); 0 for dead vertices
+ *   block_ids[n_vertices]    first-occurrence block id; UINT32_MAX if dead
+ *   block_sizes[n_blocks]    vertices per block (the count payload, Sec. 3.1)
+ *   blocks_per_iter[k_done+1] number of blocks after iteration 0..k_done
+ *   se_src/se_label/se_dst[n_summary_edges]  distinct quotient edges
+ *                            (block(v), l, block(w)), sorted ascending by
+ *                            (src, label, dst) (summary graph, Sec. 2.6)
+ * Timings are device milliseconds of the call's phases.
+ */
+typedef struct {
+    uint32_t n_vertices;
+    uint32_t k_done;
+    uint32_t fixpoint;
+    uint32_t n_blocks;
+    uint64_t n_summary_edges;
+    uint32_t mem_kind;
+    uint32_t n_iter_launches; /* refinement-kernel launches issued */
+    uint64_t* hashes;
+    uint32_t* block_ids;
+    uint32_t* block_sizes;
+    uint32_t* blocks_per_iter;
+    uint32_t* se_src;
+    uint32_t* se_label;
+    uint32_t* se_dst;
+    float ms_stage;
+    float ms_iterate;
+    float ms_finalize;
+    float ms_total;
+    void* priv;
+} bsim_result;
+
+/* Operation codes of an update batch (the six change classes of Sec. 3.2
+ * arise from these: ADD_V/ADD_E give ADD-SG/ADD-PE, MOD_* give MOD-SG/MOD-PE,
+ * DEL_* give DEL-PE/DEL-SG). */
+#define BSIM_OP_ADD_V 1u /* new vertex, id = current n_vertices; types given */
+#define BSIM_OP_MOD_V 2u /* replace the type set of vertex u */
+#define BSIM_OP_DEL_V 3u /* delete vertex u and every edge incident to it */
+#define BSIM_OP_ADD_E 4u /* add edge (u, label, w); no-op if the triple exists */
+#define BSIM_OP_MOD_E 5u /* relabel one (u, label, w) to (u, new_label, w) */
+#define BSIM_OP_DEL_E 6u /* delete every copy of (u, label, w); no-op if absent */
+
+typedef struct {
+    uint32_t op;
+    uint32_t u;
+    uint32_t w;
+    uint32_t label;
+    uint32_t new_label;
+    uint32_t n_types;
+    const uint32_t* types; /* host pointer, n_types entries (ADD_V / MOD_V) */
+} bsim_update;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Bind a context to `device` and the HIP stream `hip_stream` (a hipStream_t;
+ * NULL = the device's null stream).  The stream stays owned by the caller. */
+int bsim_ctx_create(int device, void* hip_stream, bsim_ctx** out);
+void bsim_ctx_free(bsim_ctx* ctx);
+/* Text of the last error raised on this ctx ("" if none). */
+const char* bsim_last_error(const bsim_ctx* ctx);
+const char* bsim_status_string(int status);
+/* Tuning knobs (tile edge quota, vertex cap, chunk length); see the names
+ * in bsim_option_names().  Values outside the documented range give
+ * BSIM_E_RANGE. */
+int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value);
+int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value);
+const char* bsim_option_names(void);
+
+/* ---- batch summarization (Algorithm 4 with a fixpoint test) ------------- */
+
+/*
+ * Summarize `graph` with `params`.  On success *out holds the result; if
+ * state_out is non-NULL the call also returns a resident state (graph copy,
+ * per-level hashes, count tables) for bsim_apply_updates; the state then
+ * always keeps every level h^0..h^k (BSIM_KEEP_LEVELS is implied) and needs
+ * a finite k_max.
+ */
+int bsim_summarize(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* params,
+                   bsim_state** state_out, bsim_result** out);
+void bsim_result_free(bsim_result* result);
+
+/* Copy one result array to caller memory (host or device pointer, as
+ * dst_mem_kind says).  `field` is one of "hashes", "block_ids",
+ * "block_sizes", "se_src", "se_label", "se_dst". */
+int bsim_result_copy(const bsim_result* result, const char* field, void* dst,
+                     uint32_t dst_mem_kind);
+
+/* ---- incremental summarization (Sec. 3.2; Theorem 2) --------------------- */
+
+/*
+ * Apply an ordered batch of ADD/MOD/DEL operations to the resident state
+ * and return the updated summary.  The batch is all-or-nothing: on error
+ * the state is unchanged.  Contract: the result equals bsim_summarize of
+ * the updated graph (same vertex ids, alive mask and k) bit for bit --
+ * the incremental-equals-batch property of Theorem 2.
+ */
+int bsim_apply_updates(bsim_state* state, const bsim_update* ops, uint64_t n_ops,
+                       bsim_result** out);
+/* Current graph of a state as host CSR arrays (for checking); the caller
+ * frees them with bsim_host_free. */
+int bsim_state_graph(const bsim_state* state, bsim_graph* out_host_graph);
+void bsim_host_free(void* p);
+void bsim_state_free(bsim_state* state);
+
+/* ---- batched summarization (many independent graphs, one launch stream) -- */
+
+/*
+ * Summarize n_graphs independent graphs; outs[i] receives graph i's result,
+ * identical to a bsim_summarize call on that graph alone.
+ */
+int bsim_batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t n_graphs,
+                         const bsim_params* params, bsim_result** outs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSIM_H */

@@ -1,0 +1,272 @@
+"""Thin ctypes binding of the C ABI in ``include/bsim.h``.
+
+Argument marshalling only: every step of the summarization runs in the HIP
+library ``libbsim.so``.  PyTorch supplies device memory and the HIP stream.
+Loading fails loudly when the library has not been built -- there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbsim.so")
+
+# bsim.h constants
+OK = 0
+E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY = -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+STOP_AT_FIXPOINT, KEEP_LEVELS, UNTYPED, RESULT_ON_HOST, NO_SUMMARY_EDGES = 1, 2, 4, 8, 16
+K_UNBOUNDED = 0xFFFFFFFF
+OP_ADD_V, OP_MOD_V, OP_DEL_V, OP_ADD_E, OP_MOD_E, OP_DEL_E = 1, 2, 3, 4, 5, 6
+
+_p = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+
+class BsimGraph(ctypes.Structure):
+    _fields_ = [("n_vertices", _u32), ("label_bytes", _u32), ("n_edges", _u64),
+                ("row_off", _p), ("targets", _p), ("labels", _p), ("type_off", _p),
+                ("type_ids", _p), ("alive", _p), ("mem_kind", _u32), ("reserved", _u32)]
+
+
+class BsimParams(ctypes.Structure):
+    _fields_ = [("k_max", _u32), ("flags", _u32)]
+
+
+class BsimResult(ctypes.Structure):
+    _fields_ = [("n_vertices", _u32), ("k_done", _u32), ("fixpoint", _u32), ("n_blocks", _u32),
+                ("n_summary_edges", _u64), ("mem_kind", _u32), ("n_iter_launches", _u32),
+                ("hashes", _p), ("block_ids", _p), ("block_sizes", _p),
+                ("blocks_per_iter", ctypes.POINTER(_u32)), ("se_src", _p), ("se_label", _p),
+                ("se_dst", _p), ("ms_stage", ctypes.c_float), ("ms_iterate", ctypes.c_float),
+                ("ms_finalize", ctypes.c_float), ("ms_total", ctypes.c_float), ("priv", _p)]
+
+
+class BsimUpdate(ctypes.Structure):
+    _fields_ = [("op", _u32), ("u", _u32), ("w", _u32), ("label", _u32), ("new_label", _u32),
+                ("n_types", _u32), ("types", ctypes.POINTER(_u32))]
+
+
+EXPORTS = {
+    "bsim_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "bsim_ctx_create": (ctypes.c_int, [ctypes.c_int, _p, ctypes.POINTER(_p)]),
+    "bsim_ctx_free": (None, [_p]),
+    "bsim_last_error": (ctypes.c_char_p, [_p]),
+    "bsim_ctx_set_option": (ctypes.c_int, [_p, ctypes.c_char_p, ctypes.c_int64]),
+    "bsim_ctx_get_option": (ctypes.c_int, [_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
+    "bsim_option_names": (ctypes.c_char_p, []),
+    "bsim_summarize": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), ctypes.POINTER(BsimParams),
+                                      ctypes.POINTER(_p), ctypes.POINTER(ctypes.POINTER(BsimResult))]),
+    "bsim_result_free": (None, [ctypes.POINTER(BsimResult)]),
+    "bsim_result_copy": (ctypes.c_int, [ctypes.POINTER(BsimResult), ctypes.c_char_p, _p, _u32]),
+    "bsim_apply_updates": (ctypes.c_int, [_p, ctypes.POINTER(BsimUpdate), _u64,
+                                          ctypes.POINTER(ctypes.POINTER(BsimResult))]),
+    "bsim_state_graph": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph)]),
+    "bsim_host_free": (None, [_p]),
+    "bsim_state_free": (None, [_p]),
+    "bsim_batch_summarize": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), _u32,
+                                            ctypes.POINTER(BsimParams),
+                                            ctypes.POINTER(ctypes.POINTER(BsimResult))]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libbsim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbsim.so is not built; run `python -m paper_2111_12493_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class BsimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (lib().bsim_status_string(status).decode(), status, msg))
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.device = device
+        h = _p()
+        rc = lib().bsim_ctx_create(device, _p(stream.cuda_stream), ctypes.byref(h))
+        if rc != OK:
+            raise BsimError(rc, "context creation failed")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().bsim_ctx_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().bsim_last_error(self.handle).decode()
+
+    def check(self, rc: int):
+        if rc != OK:
+            raise BsimError(rc, self.last_error())
+
+    def set_option(self, name: str, value: int):
+        self.check(lib().bsim_ctx_set_option(self.handle, name.encode(), int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int64()
+        self.check(lib().bsim_ctx_get_option(self.handle, name.encode(), ctypes.byref(v)))
+        return int(v.value)
+
+
+class DeviceGraph:
+    """A graph whose CSR arrays are torch tensors on the GPU (bit-preserving
+    signed views of the unsigned arrays)."""
+
+    def __init__(self, g, device: str = "cuda"):
+        torch = _torch()
+        self.n = int(g.n)
+        self.m = int(g.m)
+        lab = np.ascontiguousarray(g.lab)
+        self.label_bytes = 2 if lab.dtype == np.uint16 else 4
+
+        def up(a, dt):
+            a = np.ascontiguousarray(a)
+            if a.size == 0:
+                a = np.zeros(1, dtype=a.dtype)
+            return torch.from_numpy(a.view(dt)).to(device)
+
+        self.row_off = up(np.asarray(g.row_off, dtype=np.uint32), np.int32)
+        self.tgt = up(np.asarray(g.tgt, dtype=np.uint32), np.int32)
+        self.lab = up(lab if self.label_bytes == 2 else lab.astype(np.uint32),
+                      np.int16 if self.label_bytes == 2 else np.int32)
+        self.type_off = up(np.asarray(g.typ_off, dtype=np.uint32), np.int32)
+        self.typ = up(np.asarray(g.typ, dtype=np.uint32), np.int32)
+        self.alive = None if g.alive is None else up(np.asarray(g.alive, dtype=np.uint8), np.uint8)
+
+    def struct(self) -> BsimGraph:
+        return BsimGraph(self.n, self.label_bytes, self.m, self.row_off.data_ptr(), self.tgt.data_ptr(),
+                         self.lab.data_ptr(), self.type_off.data_ptr(), self.typ.data_ptr(),
+                         self.alive.data_ptr() if self.alive is not None else None, MEM_DEVICE, 0)
+
+
+class HostGraph:
+    """A graph given as host numpy arrays (the library copies it)."""
+
+    def __init__(self, g):
+        self.n = int(g.n)
+        self.m = int(g.m)
+        lab = np.ascontiguousarray(g.lab)
+        self.label_bytes = 2 if lab.dtype == np.uint16 else 4
+        self.row_off = np.ascontiguousarray(g.row_off, dtype=np.uint32)
+        self.tgt = np.ascontiguousarray(g.tgt, dtype=np.uint32)
+        self.lab = lab if self.label_bytes == 2 else np.ascontiguousarray(lab, dtype=np.uint32)
+        self.type_off = np.ascontiguousarray(g.typ_off, dtype=np.uint32)
+        self.typ = np.ascontiguousarray(g.typ, dtype=np.uint32)
+        if self.typ.size == 0:
+            self.typ = np.zeros(1, dtype=np.uint32)
+        self.alive = None if g.alive is None else np.ascontiguousarray(g.alive, dtype=np.uint8)
+
+    def struct(self) -> BsimGraph:
+        def ptr(a):
+            return None if a is None else a.ctypes.data
+
+        return BsimGraph(self.n, self.label_bytes, self.m, ptr(self.row_off), ptr(self.tgt),
+                         ptr(self.lab), ptr(self.type_off), ptr(self.typ), ptr(self.alive),
+                         MEM_HOST, 0)
+
+
+class Result:
+    """Owner of a bsim_result; arrays are fetched to numpy on demand."""
+
+    FIELDS = {"hashes": np.uint64, "block_ids": np.uint32, "block_sizes": np.uint32,
+              "se_src": np.uint32, "se_label": np.uint32, "se_dst": np.uint32}
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+        r = ptr.contents
+        self.n_vertices = r.n_vertices
+        self.k_done = r.k_done
+        self.fixpoint = r.fixpoint
+        self.n_blocks = r.n_blocks
+        self.n_summary_edges = r.n_summary_edges
+        self.n_iter_launches = r.n_iter_launches
+        self.mem_kind = r.mem_kind
+        self.blocks_per_iter = np.array([r.blocks_per_iter[i] for i in range(r.k_done + 1)],
+                                        dtype=np.uint32)
+        self.ms_stage, self.ms_iterate = r.ms_stage, r.ms_iterate
+        self.ms_finalize, self.ms_total = r.ms_finalize, r.ms_total
+
+    def _len(self, field):
+        if field in ("hashes", "block_ids"):
+            return self.n_vertices
+        if field == "block_sizes":
+            return self.n_blocks
+        return self.n_summary_edges
+
+    def fetch(self, field: str) -> np.ndarray:
+        out = np.zeros(max(self._len(field), 1), dtype=self.FIELDS[field])
+        rc = lib().bsim_result_copy(self.ptr, field.encode(), out.ctypes.data, MEM_HOST)
+        if rc != OK:
+            raise BsimError(rc, "result copy of " + field)
+        return out[:self._len(field)]
+
+    def to_dict(self) -> Dict:
+        d = dict(k_done=self.k_done, fixpoint=self.fixpoint, n_blocks=self.n_blocks,
+                 blocks_per_iter=self.blocks_per_iter)
+        for f in self.FIELDS:
+            key = {"se_label": "se_label"}.get(f, f)
+            d[key] = self.fetch(f)
+        return d
+
+    def free(self):
+        if self.ptr:
+            lib().bsim_result_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
+              untyped: bool = False, summary_edges: bool = True, result_on_host: bool = False) -> Result:
+    """bsim_summarize on a DeviceGraph or HostGraph."""
+    flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
+            (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0)
+    gs = graph.struct()
+    params = BsimParams(int(k_max), flags)
+    out = ctypes.POINTER(BsimResult)()
+    ctx.check(lib().bsim_summarize(ctx.handle, ctypes.byref(gs), ctypes.byref(params), None,
+                                   ctypes.byref(out)))
+    return Result(out)

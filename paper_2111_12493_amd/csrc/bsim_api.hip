@@ -1,0 +1,163 @@
+// bsim_api.hip -- the C ABI (include/bsim.h): contexts, batch summarization
+// and results.  The call sequence of bsim_summarize follows Algorithm 4:
+// initialization (type hashes), k hash-messaging phases, FindAndMerge; the
+// phase loop stops at the fixpoint as described in bsim.h.
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "bsim_api_internal.h"
+
+using namespace bsim;
+
+extern "C" {
+
+const char* bsim_status_string(int status) {
+    switch (status) {
+        case BSIM_OK: return "ok";
+        case BSIM_E_INVALID: return "invalid input";
+        case BSIM_E_RANGE: return "id or label out of range";
+        case BSIM_E_NOMEM: return "out of memory";
+        case BSIM_E_DEVICE: return "HIP runtime error";
+        case BSIM_E_UNSUPPORTED: return "unsupported input";
+        case BSIM_E_BUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+int bsim_ctx_create(int device, void* hip_stream, bsim_ctx** out) {
+    if (!out) return BSIM_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BSIM_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return BSIM_E_DEVICE;
+    bsim_ctx* c = new (std::nothrow) bsim_ctx();
+    if (!c) return BSIM_E_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->status_host), 4 * sizeof(RunStatus),
+                      hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return BSIM_E_NOMEM;
+    }
+    // keep freed stream-ordered memory cached for later calls
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    *out = c;
+    return BSIM_OK;
+}
+
+void bsim_ctx_free(bsim_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+    delete ctx;
+}
+
+const char* bsim_last_error(const bsim_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+const char* bsim_option_names(void) {
+    return "chunk_max (refinement launches queued per status check, 1..4096)";
+}
+
+int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
+    if (!ctx || !name) return BSIM_E_INVALID;
+    if (!strcmp(name, "chunk_max")) {
+        if (value < 1 || value > 4096) return BSIM_E_RANGE;
+        ctx->chunk_max = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
+    return BSIM_E_INVALID;
+}
+
+int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
+    if (!ctx || !name || !value) return BSIM_E_INVALID;
+    if (!strcmp(name, "chunk_max")) {
+        *value = ctx->chunk_max;
+        return BSIM_OK;
+    }
+    return BSIM_E_INVALID;
+}
+
+int bsim_summarize(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* params,
+                   bsim_state** state_out, bsim_result** out) {
+    if (out) *out = nullptr;
+    if (state_out) *state_out = nullptr;
+    if (!ctx || !graph || !params || !out) return BSIM_E_INVALID;
+    try {
+        hip_check(hipSetDevice(ctx->device), "set device");
+        if (state_out) return summarize_with_state(ctx, *graph, *params, state_out, out);
+        *out = summarize_graph(ctx, *graph, *params, nullptr);
+        return BSIM_OK;
+    } catch (const DeviceError& e) {
+        ctx->err = e.msg;
+        (void)hipStreamSynchronize(ctx->stream);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        return BSIM_E_NOMEM;
+    }
+}
+
+void bsim_result_free(bsim_result* r) {
+    if (!r) return;
+    ResultPriv* p = static_cast<ResultPriv*>(r->priv);
+    if (p) {
+        if (p->device_ptrs.size()) {
+            (void)hipSetDevice(p->device);
+            for (void* q : p->device_ptrs) (void)hipFreeAsync(q, p->stream);
+            (void)hipStreamSynchronize(p->stream);
+        }
+        for (void* q : p->host_ptrs) free(q);
+        delete p;
+    }
+    delete r;
+}
+
+int bsim_result_copy(const bsim_result* r, const char* field, void* dst, uint32_t dst_mem_kind) {
+    if (!r || !field || !dst) return BSIM_E_INVALID;
+    const void* src = nullptr;
+    size_t bytes = 0;
+    if (!strcmp(field, "hashes")) {
+        src = r->hashes;
+        bytes = static_cast<size_t>(r->n_vertices) * 8;
+    } else if (!strcmp(field, "block_ids")) {
+        src = r->block_ids;
+        bytes = static_cast<size_t>(r->n_vertices) * 4;
+    } else if (!strcmp(field, "block_sizes")) {
+        src = r->block_sizes;
+        bytes = static_cast<size_t>(r->n_blocks) * 4;
+    } else if (!strcmp(field, "se_src")) {
+        src = r->se_src;
+        bytes = static_cast<size_t>(r->n_summary_edges) * 4;
+    } else if (!strcmp(field, "se_label")) {
+        src = r->se_label;
+        bytes = static_cast<size_t>(r->n_summary_edges) * 4;
+    } else if (!strcmp(field, "se_dst")) {
+        src = r->se_dst;
+        bytes = static_cast<size_t>(r->n_summary_edges) * 4;
+    } else {
+        return BSIM_E_INVALID;
+    }
+    if (bytes == 0) return BSIM_OK;
+    ResultPriv* p = static_cast<ResultPriv*>(r->priv);
+    if (r->mem_kind == BSIM_MEM_HOST && dst_mem_kind == BSIM_MEM_HOST) {
+        memcpy(dst, src, bytes);
+        return BSIM_OK;
+    }
+    hipMemcpyKind kind = r->mem_kind == BSIM_MEM_HOST
+                             ? hipMemcpyHostToDevice
+                             : (dst_mem_kind == BSIM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice);
+    if (hipSetDevice(p->device) != hipSuccess) return BSIM_E_DEVICE;
+    if (hipMemcpyAsync(dst, src, bytes, kind, p->stream) != hipSuccess) return BSIM_E_DEVICE;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return BSIM_E_DEVICE;
+    return BSIM_OK;
+}
+
+void bsim_host_free(void* p) { free(p); }
+
+}  // extern "C"

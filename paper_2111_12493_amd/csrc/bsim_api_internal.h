@@ -1,0 +1,68 @@
+// bsim_api_internal.h -- host-side objects behind the opaque ABI handles.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "bsim_internal.h"
+
+struct bsim_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bsim::RunStatus* status_host = nullptr;  // pinned, 4 entries
+    uint32_t chunk_max = 256;
+};
+
+namespace bsim {
+
+// Owner of a result's arrays.
+struct ResultPriv {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<void*> device_ptrs;
+    std::vector<void*> host_ptrs;
+    std::vector<uint32_t> blocks_per_iter;
+};
+
+// Device copies of the caller's graph when it arrives in host memory, or
+// the caller's device pointers as they are.
+struct DeviceGraph {
+    Staged g;
+};
+
+void upload_graph(const bsim_graph& in, Staged& g, Arena& arena, hipStream_t s);
+
+// Per-level hash storage handed to the refinement loop.  With `levels`
+// empty the loop double-buffers; otherwise levels[k] receives h^k.
+struct LevelSink {
+    std::vector<uint64_t*> levels;
+};
+
+struct LoopResult {
+    uint32_t k_done = 0;
+    uint32_t fixpoint = 0;
+    uint32_t launches = 0;
+    std::vector<uint32_t> blocks_per_iter;
+    const uint64_t* h_final = nullptr;
+};
+
+// Iterations 0..k_done on a staged graph.
+LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
+                          LevelSink* sink, Arena& arena);
+
+// Assemble a bsim_result from finalize output (takes ownership of `keep`).
+bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, const uint64_t* h,
+                         FinalOut& fo, Arena& keep, uint32_t flags);
+
+// Whole batch path for one graph.
+bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,
+                             void* unused);
+
+// Batch path that also returns a resident state for incremental updates.
+int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,
+                         bsim_state** state_out, bsim_result** out);
+
+void validate_params(const bsim_graph& graph, const bsim_params& p);
+
+}  // namespace bsim

@@ -1,0 +1,309 @@
+// bsim_final.hip -- finalize (a8): relabel the final hashes to dense block
+// ids, count block sizes, and build the summary graph's edges.
+//
+// Algorithm 4 ends with FindAndMerge: vertices with equal final identifiers
+// form one block.  Block ids are numbered by first occurrence (the block of
+// the smallest vertex is 0), which depends only on the partition:
+//   1. insert every alive vertex's hash into an open-addressing table of
+//      (hash, smallest vertex) slots (atomicMin on the vertex);
+//   2. a vertex is its block's representative iff it is the smallest vertex
+//      of its hash; an exclusive scan over representative flags gives each
+//      representative its block id;
+//   3. every vertex takes the id of its representative; sizes by atomics.
+// Summary edges (Sec. 2.6: edges between vertex summaries) are the distinct
+// (block(v), l, block(w)) triples: packed into one 64-bit key per edge,
+// sorted by an LSD radix sort over the used bits, de-duplicated and unpacked.
+#include "bsim_device.h"
+
+namespace bsim {
+
+namespace {
+
+struct FinSlot {
+    uint64_t key;
+    uint32_t minv;
+    uint32_t pad;
+};
+static_assert(sizeof(FinSlot) == 16, "slot layout");
+
+__global__ void __launch_bounds__(kBlock) k_fin_fill(FinSlot* tab, uint32_t slots) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < slots) {
+        tab[i].key = 0;
+        tab[i].minv = 0xFFFFFFFFu;
+        tab[i].pad = 0;
+    }
+}
+
+// Slot `mask + 1` is reserved for the hash value 0.
+__global__ void __launch_bounds__(kBlock) k_fin_insert(const uint64_t* __restrict__ h,
+                                                       const uint8_t* __restrict__ alive, uint32_t n,
+                                                       FinSlot* tab, uint32_t mask,
+                                                       uint32_t* __restrict__ slot_of) {
+    uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n || (alive && !alive[v])) return;
+    const uint64_t key = h[v];
+    uint32_t slot;
+    if (key == 0) {
+        slot = mask + 1;
+    } else {
+        slot = static_cast<uint32_t>(key) & mask;
+        for (;;) {
+            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot].key),
+                                               0ull, static_cast<unsigned long long>(key));
+            if (old == 0ull || old == key) break;
+            slot = (slot + 1) & mask;
+        }
+    }
+    atomicMin(&tab[slot].minv, v);
+    slot_of[v] = slot;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_rep(const uint8_t* __restrict__ alive, uint32_t n,
+                                                    const FinSlot* __restrict__ tab,
+                                                    const uint32_t* __restrict__ slot_of,
+                                                    uint32_t* __restrict__ rep) {
+    uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    rep[v] = (!alive || alive[v]) && tab[slot_of[v]].minv == v ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_ids(const uint8_t* __restrict__ alive, uint32_t n,
+                                                    const FinSlot* __restrict__ tab,
+                                                    const uint32_t* __restrict__ slot_of,
+                                                    const uint32_t* __restrict__ rank,
+                                                    uint32_t* __restrict__ block_ids,
+                                                    uint32_t* __restrict__ sizes) {
+    uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t bid = 0xFFFFFFFFu;
+    if (v < n && (!alive || alive[v])) bid = rank[tab[slot_of[v]].minv];
+    if (v < n) block_ids[v] = bid;
+    // one atomic per run of lanes sharing a block (common for big blocks)
+    const uint32_t lane = lane_id();
+    uint32_t prev = static_cast<uint32_t>(__shfl_up(static_cast<int>(bid), 1, 64));
+    bool head = (lane == 0) || prev != bid;
+    uint64_t heads = __ballot(head);
+    if (bid != 0xFFFFFFFFu && head) {
+        uint64_t later = heads & ~((2ull << lane) - 1);  // heads above this lane
+        uint32_t end = later ? static_cast<uint32_t>(__ffsll(static_cast<long long>(later)) - 1) : 64u;
+        atomicAdd(&sizes[bid], end - lane);
+    }
+}
+
+// ------------------------------------------------------------ edge keys
+
+struct KeyShared {
+    uint32_t off[kTileMaxVerts + 1];
+    uint32_t red[kBlock / 64];
+    alignas(8) uint8_t seg[kTileMaxEdges];
+};
+
+template <typename LabT>
+__global__ void __launch_bounds__(kBlock) k_edge_keys(
+    const uint32_t* __restrict__ row_off, const uint32_t* __restrict__ tgt,
+    const LabT* __restrict__ lab, const uint32_t* __restrict__ bid,
+    const uint32_t* __restrict__ tile_v0, const uint32_t* __restrict__ tile_v1, uint32_t n_tiles,
+    const uint32_t* __restrict__ hub_v, uint32_t n_hubs, int lb, int bb,
+    uint64_t* __restrict__ keys) {
+    __shared__ KeyShared S;
+    const uint32_t tid = threadIdx.x;
+    if (blockIdx.x < n_hubs) {
+        const uint32_t v = hub_v[blockIdx.x];
+        const uint64_t src = static_cast<uint64_t>(bid[v]) << (lb + bb);
+        for (uint32_t e = row_off[v] + tid; e < row_off[v + 1]; e += kBlock)
+            keys[e] = src | (static_cast<uint64_t>(lab[e]) << bb) | bid[tgt[e]];
+        return;
+    }
+    const uint32_t tile = blockIdx.x - n_hubs;
+    if (tile >= n_tiles) return;
+    const uint32_t v0 = tile_v0[tile], v1 = tile_v1[tile], nv = v1 - v0;
+    const uint32_t ebase = row_off[v0];
+    for (uint32_t i = tid; i <= nv; i += kBlock) S.off[i] = row_off[v0 + i] - ebase;
+    __syncthreads();
+    const uint32_t ne = S.off[nv];
+    tile_segments(nv, S.off, S.seg, S.red);
+    for (uint32_t j = tid; j < ne; j += kBlock) {
+        const uint32_t e = ebase + j;
+        const uint32_t v = v0 + S.seg[j];
+        keys[e] = (static_cast<uint64_t>(bid[v]) << (lb + bb)) |
+                  (static_cast<uint64_t>(lab[e]) << bb) | bid[tgt[e]];
+    }
+}
+
+// ------------------------------------------------------------ radix sort
+//
+// LSD radix sort of 64-bit keys, 8 bits per pass.  Each pass: per-block digit
+// histograms (digit-major, so one exclusive scan yields every block's output
+// offset per digit), then a stable scatter that ranks equal digits by wave
+// ballots (8 ballots isolate the lanes with the same digit).
+
+constexpr int kSortItems = 4;
+constexpr int kSortTile = kBlock * kSortItems;
+
+__global__ void __launch_bounds__(kBlock) k_sort_hist(const uint64_t* __restrict__ in, uint32_t m,
+                                                      int shift, uint32_t nblk,
+                                                      uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSortTile;
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        uint64_t j = base + static_cast<uint64_t>(r) * kBlock + threadIdx.x;
+        if (j < m) atomicAdd(&s_h[(in[j] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    hist[static_cast<uint64_t>(threadIdx.x) * nblk + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBlock) k_sort_scatter(const uint64_t* __restrict__ in,
+                                                         uint64_t* __restrict__ out, uint32_t m,
+                                                         int shift, uint32_t nblk,
+                                                         const uint32_t* __restrict__ offs) {
+    __shared__ uint32_t s_run[256];
+    __shared__ uint32_t s_cnt[kBlock / 64][256];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    s_run[tid] = offs[static_cast<uint64_t>(tid) * nblk + blockIdx.x];
+    for (int w = 0; w < kBlock / 64; w++) s_cnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        const uint64_t j = base + static_cast<uint64_t>(r) * kBlock + tid;
+        const bool valid = j < m;
+        const uint64_t key = valid ? in[j] : 0;
+        const uint32_t dig = static_cast<uint32_t>((key >> shift) & 0xFF);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const uint64_t bal = __ballot((dig >> b) & 1);
+            peers &= ((dig >> b) & 1) ? bal : ~bal;
+        }
+        const uint64_t below = peers & ((1ull << lane) - 1);
+        const uint32_t rank = static_cast<uint32_t>(__popcll(below));
+        if (valid && below == 0) s_cnt[wid][dig] = static_cast<uint32_t>(__popcll(peers));
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = s_run[dig] + rank;
+            for (uint32_t w = 0; w < wid; w++) pos += s_cnt[w][dig];
+            out[pos] = key;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kBlock / 64; w++) {
+            add += s_cnt[w][tid];
+            s_cnt[w][tid] = 0;
+        }
+        s_run[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_unique_flags(const uint64_t* __restrict__ keys, uint32_t m,
+                                                         uint32_t* __restrict__ flag) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_unpack(const uint64_t* __restrict__ keys, uint32_t m,
+                                                   const uint32_t* __restrict__ flag,
+                                                   const uint32_t* __restrict__ pos, int lb, int bb,
+                                                   uint32_t* __restrict__ s, uint32_t* __restrict__ l,
+                                                   uint32_t* __restrict__ d) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m || !flag[i]) return;
+    const uint64_t k = keys[i];
+    const uint32_t p = pos[i];
+    s[p] = static_cast<uint32_t>(k >> (lb + bb));
+    l[p] = static_cast<uint32_t>((k >> bb) & ((1ull << lb) - 1));
+    d[p] = static_cast<uint32_t>(k & ((1ull << bb) - 1));
+}
+
+}  // namespace
+
+// Sort m keys ascending on bits [0, bits); returns the buffer holding the
+// result (a or b).
+static uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Arena& arena,
+                            hipStream_t s) {
+    if (m <= 1) return a;
+    const uint32_t nblk = ceil_div(m, kSortTile);
+    uint32_t* hist = arena.alloc<uint32_t>(static_cast<size_t>(nblk) * 256);
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_sort_hist<<<nblk, kBlock, 0, s>>>(a, m, shift, nblk, hist);
+        scan_exclusive(hist, hist, nblk * 256, nullptr, arena, s);
+        k_sort_scatter<<<nblk, kBlock, 0, s>>>(a, b, m, shift, nblk, hist);
+        std::swap(a, b);
+    }
+    hip_check(hipGetLastError(), "radix sort launch");
+    return a;
+}
+
+void finalize(const Staged& g, const uint64_t* h, uint32_t tab_slots, bool want_edges,
+              FinalOut& out, Arena& arena, Arena& keep, hipStream_t s) {
+    (void)tab_slots;
+    const uint32_t n = g.n;
+    const uint32_t mask = std::max<uint32_t>(next_pow2(static_cast<uint64_t>(n) + n / 2 + 1), 64) - 1;
+    FinSlot* tab = arena.alloc<FinSlot>(static_cast<size_t>(mask) + 2);
+    uint32_t* slot_of = arena.alloc<uint32_t>(n);
+    uint32_t* rep = arena.alloc<uint32_t>(n);
+    uint32_t* rank = arena.alloc<uint32_t>(n);
+    uint32_t* total = arena.alloc<uint32_t>(1);
+    out.block_ids = keep.alloc<uint32_t>(n);
+    const uint32_t gb = std::max<uint32_t>(ceil_div(n, kBlock), 1);
+    k_fin_fill<<<ceil_div(mask + 2, kBlock), kBlock, 0, s>>>(tab, mask + 2);
+    if (n) {
+        k_fin_insert<<<gb, kBlock, 0, s>>>(h, g.alive, n, tab, mask, slot_of);
+        k_fin_rep<<<gb, kBlock, 0, s>>>(g.alive, n, tab, slot_of, rep);
+    }
+    scan_exclusive(rep, rank, n, total, arena, s);
+    uint32_t nb = 0;
+    hip_check(hipMemcpyAsync(&nb, total, 4, hipMemcpyDeviceToHost, s), "block count");
+    hip_check(hipStreamSynchronize(s), "block count sync");
+    out.n_blocks = nb;
+    out.block_sizes = keep.alloc<uint32_t>(nb);
+    hip_check(hipMemsetAsync(out.block_sizes, 0, static_cast<size_t>(nb) * 4 + 4, s), "sizes");
+    if (n) k_fin_ids<<<gb, kBlock, 0, s>>>(g.alive, n, tab, slot_of, rank, out.block_ids, out.block_sizes);
+    hip_check(hipGetLastError(), "finalize launch");
+    out.n_se = 0;
+    if (!want_edges || g.m == 0) {
+        out.se_src = keep.alloc<uint32_t>(1);
+        out.se_label = keep.alloc<uint32_t>(1);
+        out.se_dst = keep.alloc<uint32_t>(1);
+        return;
+    }
+    const int bb = std::max(1, bit_width(nb ? nb - 1 : 0));
+    const int lb = std::max(1, bit_width(g.max_label));
+    if (2 * bb + lb > 64)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "summary-edge triple does not fit 64 bits"};
+    const uint32_t m = static_cast<uint32_t>(g.m);
+    uint64_t* ka = arena.alloc<uint64_t>(m);
+    uint64_t* kb = arena.alloc<uint64_t>(m);
+    const uint32_t grid = std::max<uint32_t>(g.n_hubs + g.n_tiles, 1);
+    if (g.label_bytes == 2)
+        k_edge_keys<uint16_t><<<grid, kBlock, 0, s>>>(g.row_off, g.tgt,
+                                                      static_cast<const uint16_t*>(g.lab), out.block_ids,
+                                                      g.tile_v0, g.tile_v1, g.n_tiles, g.hub_v, g.n_hubs,
+                                                      lb, bb, ka);
+    else
+        k_edge_keys<uint32_t><<<grid, kBlock, 0, s>>>(g.row_off, g.tgt,
+                                                      static_cast<const uint32_t*>(g.lab), out.block_ids,
+                                                      g.tile_v0, g.tile_v1, g.n_tiles, g.hub_v, g.n_hubs,
+                                                      lb, bb, ka);
+    hip_check(hipGetLastError(), "edge key launch");
+    uint64_t* sorted = radix_sort(ka, kb, m, 2 * bb + lb, arena, s);
+    uint32_t* flag = arena.alloc<uint32_t>(m);
+    uint32_t* pos = arena.alloc<uint32_t>(m);
+    k_unique_flags<<<ceil_div(m, kBlock), kBlock, 0, s>>>(sorted, m, flag);
+    scan_exclusive(flag, pos, m, total, arena, s);
+    uint32_t nse = 0;
+    hip_check(hipMemcpyAsync(&nse, total, 4, hipMemcpyDeviceToHost, s), "edge count");
+    hip_check(hipStreamSynchronize(s), "edge count sync");
+    out.n_se = nse;
+    out.se_src = keep.alloc<uint32_t>(nse);
+    out.se_label = keep.alloc<uint32_t>(nse);
+    out.se_dst = keep.alloc<uint32_t>(nse);
+    k_unpack<<<ceil_div(m, kBlock), kBlock, 0, s>>>(sorted, m, flag, pos, lb, bb, out.se_src,
+                                                    out.se_label, out.se_dst);
+    hip_check(hipGetLastError(), "unpack launch");
+}
+
+}  // namespace bsim

@@ -1,0 +1,240 @@
+// bsim_internal.h -- shared definitions of the gfx950 k-bisimulation library.
+//
+// Everything here is integer-only.  The hash spec (see bsim.h) is written out
+// once more for the device; it follows the published SplitMix64 output
+// function (Steele, Lea & Flood, OOPSLA 2014).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "bsim.h"
+
+namespace bsim {
+
+// ---------------------------------------------------------------- hash spec
+
+__host__ __device__ constexpr uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr uint64_t kCT = mix64(1);  // type-set domain
+constexpr uint64_t kCL = mix64(2);  // edge-label salt domain
+constexpr uint64_t kCS = mix64(3);  // signature-sum domain
+constexpr uint64_t kCE = mix64(4);  // per-pair domain
+
+// ---------------------------------------------------------- launch geometry
+//
+// The refinement kernel works on "tiles": runs of consecutive vertices whose
+// out-edges are contiguous in the CSR.  A tile holds at most kTileMaxVerts
+// vertices and fewer than 2 * kTileQuota edges, so its per-vertex
+// de-duplication tables (two slots per edge) fit one block's LDS.  Vertices
+// with more than kTileQuota out-edges ("hubs") are split by the high bits of
+// their pair hashes into buckets that each fit the same LDS table.
+
+constexpr int kBlock = 256;              // threads per block (4 wave64s)
+constexpr int kTileQuota = 1024;         // tile boundaries every kTileQuota edges
+constexpr int kTileMaxEdges = 2 * kTileQuota;
+constexpr int kTileMaxVerts = 256;
+constexpr int kEdgesPerThread = kTileMaxEdges / kBlock;  // 8
+constexpr int kTableSlots = 2 * kTileMaxEdges;           // 4096 x 8 B = 32 KiB
+constexpr int kHubBucketTarget = 1536;   // expected distinct keys per hub bucket
+constexpr int kHubTableLimit = 3584;     // re-split a hub bucket beyond this
+constexpr uint32_t kHubMinDegree = kTileQuota + 1;
+constexpr int kStripes = 64;             // striped block counters per iteration
+constexpr int kStripeRing = 4;
+
+// Device-side status of a refinement run.
+struct RunStatus {
+    uint32_t done;      // sticky: set by the first launch that sees the stop condition
+    uint32_t k_done;
+    uint32_t fixpoint;
+    uint32_t error;     // staging validation error (BSIM_E_* as positive bits)
+    uint32_t max_label;
+    uint32_t max_types;
+    uint32_t pad[2];
+};
+
+constexpr uint32_t kErrInvalid = 1u;
+constexpr uint32_t kErrRange = 2u;
+
+// Arguments of one refinement launch (iteration k reads h^{k-1}, writes h^k).
+struct IterArgs {
+    const uint32_t* row_off;
+    const uint32_t* tgt;
+    const void* lab;
+    const uint64_t* t;      // type hashes t(v)
+    const uint64_t* salt;   // salt(l) for l <= max label
+    const uint64_t* h_prev;
+    uint64_t* h_next;
+    const uint8_t* alive;   // nullable
+    const uint32_t* tile_v0;
+    const uint32_t* tile_v1;
+    const uint32_t* hb_hub;     // hub block -> hub index
+    const uint32_t* hb_bucket;  // hub block -> bucket
+    const uint32_t* hub_v;
+    const uint32_t* hub_logb;
+    uint64_t* hub_acc;
+    uint32_t* hub_done;
+    uint64_t* tab_ins;      // count table receiving h^k (keys only, 0 = empty)
+    uint64_t* tab_clr;      // count table to clear for iteration k+1
+    uint32_t* zflag_ins;
+    uint32_t* zflag_clr;
+    uint32_t* stripes;      // [kStripeRing][kStripes]
+    uint32_t* totals;       // totals[k] = n_k
+    RunStatus* status;
+    uint32_t n_tiles;
+    uint32_t n_hub_blocks;
+    uint32_t tab_mask;
+    uint32_t k;
+    uint32_t k_max;
+    uint32_t stop;
+};
+
+// ------------------------------------------------------------ host helpers
+
+struct DeviceError {
+    int status;
+    std::string msg;
+};
+
+// Stream-ordered device allocations released together (error paths included).
+class Arena {
+  public:
+    explicit Arena(hipStream_t s) : stream_(s) {}
+    ~Arena() { release(); }
+    Arena(const Arena&) = delete;
+    Arena& operator=(const Arena&) = delete;
+    template <typename T>
+    T* alloc(size_t count) {
+        void* p = nullptr;
+        size_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 16;
+        bytes = (bytes + 255) & ~size_t(255);
+        if (hipMallocAsync(&p, bytes, stream_) != hipSuccess)
+            throw DeviceError{BSIM_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+        ptrs_.push_back(p);
+        return static_cast<T*>(p);
+    }
+    // Hand an allocation over to the caller (it leaves the arena).
+    void detach(void* p) {
+        for (auto& q : ptrs_)
+            if (q == p) q = nullptr;
+    }
+    void release() {
+        for (void* p : ptrs_)
+            if (p) (void)hipFreeAsync(p, stream_);
+        ptrs_.clear();
+    }
+
+  private:
+    hipStream_t stream_;
+    std::vector<void*> ptrs_;
+};
+
+inline void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess)
+        throw DeviceError{e == hipErrorOutOfMemory ? BSIM_E_NOMEM : BSIM_E_DEVICE,
+                          std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
+
+inline uint32_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return static_cast<uint32_t>(p);
+}
+
+inline int bit_width(uint64_t x) {
+    int b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+// ------------------------------------------------------- library internals
+
+// Exclusive prefix sum of n uint32 values (out may alias in); the total is
+// written to total_dev[0] when total_dev is non-null.
+void scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total_dev,
+                    Arena& arena, hipStream_t s);
+
+// Graph after staging: device CSR plus the tile / hub schedule.
+struct Staged {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    uint32_t label_bytes = 4;
+    const uint32_t* row_off = nullptr;
+    const uint32_t* tgt = nullptr;
+    const void* lab = nullptr;
+    const uint32_t* type_off = nullptr;
+    const uint32_t* type_ids = nullptr;
+    const uint8_t* alive = nullptr;
+    uint32_t max_label = 0;
+    uint64_t* salt = nullptr;
+    uint32_t n_tiles = 0;
+    uint32_t* tile_v0 = nullptr;
+    uint32_t* tile_v1 = nullptr;
+    uint32_t n_hubs = 0;
+    uint32_t n_hub_blocks = 0;
+    uint32_t* hub_v = nullptr;
+    uint32_t* hub_logb = nullptr;
+    uint32_t* hb_hub = nullptr;
+    uint32_t* hb_bucket = nullptr;
+    std::vector<uint32_t> host_hub_v;       // hub vertices, by degree descending
+    std::vector<uint32_t> host_hub_deg;
+};
+
+// Validate the CSR and build the tile / hub schedule (a1).  Throws
+// DeviceError with BSIM_E_INVALID / BSIM_E_RANGE on malformed input.
+void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena& arena,
+                 hipStream_t s);
+
+// Count-table and per-iteration buffers of one refinement run.
+struct RunBuffers {
+    uint64_t* t = nullptr;
+    uint64_t* h[2] = {nullptr, nullptr};
+    uint64_t* tab[2] = {nullptr, nullptr};
+    uint32_t* zflag = nullptr;     // [2]
+    uint32_t tab_mask = 0;
+    uint32_t* stripes = nullptr;   // [kStripeRing * kStripes]
+    uint32_t* totals = nullptr;    // [k_cap + 2]
+    uint32_t k_cap = 0;
+    uint64_t* hub_acc = nullptr;
+    uint32_t* hub_done = nullptr;
+    RunStatus* status = nullptr;
+};
+
+void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& rb, Arena& arena,
+                       hipStream_t s);
+
+// k = 0: type hashes, h^0 = t, count n_0.
+void launch_type_hash(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s);
+
+// One refinement launch computing h^k from h^{k-1}.
+void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
+                      bool stop, hipStream_t s);
+
+// Finalize (a8): block ids, block sizes, sorted distinct quotient edges.
+struct FinalOut {
+    uint32_t n_blocks = 0;
+    uint64_t n_se = 0;
+    uint32_t* block_ids = nullptr;
+    uint32_t* block_sizes = nullptr;
+    uint32_t* se_src = nullptr;
+    uint32_t* se_label = nullptr;
+    uint32_t* se_dst = nullptr;
+};
+
+void finalize(const Staged& g, const uint64_t* h, uint32_t tab_slots, bool want_edges,
+              FinalOut& out, Arena& arena, Arena& keep, hipStream_t s);
+
+}  // namespace bsim

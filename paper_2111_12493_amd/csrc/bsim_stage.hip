@@ -1,0 +1,348 @@
+// bsim_stage.hip -- staging of a graph for the refinement kernels (a1) and
+// the device prefix sum the library uses.
+//
+// Staging validates the CSR (paper Sec. 3.1 Phase 0 co-locates every vertex
+// with its out-edges; here that is the out-edge CSR itself), computes the
+// label salts, and cuts the vertex range into tiles and hub buckets:
+//   * a vertex with more than kTileQuota out-edges is a hub;
+//   * every other vertex belongs to exactly one tile, a run of consecutive
+//     non-hub vertices cut wherever a multiple of kTileQuota edges is
+//     crossed, every kTileMaxVerts vertices, and around hubs.  All vertex
+//     starts of a tile lie in one kTileQuota window of edges and its last
+//     vertex has at most kTileQuota edges, so a tile holds < 2 kTileQuota
+//     edges;
+//   * a hub of degree d is split into 2^b buckets by the top b bits of its
+//     pair hashes, with 2^b >= d / kHubBucketTarget.
+#include <algorithm>
+#include <numeric>
+
+#include "bsim_internal.h"
+
+namespace bsim {
+
+// ------------------------------------------------------------------ scan
+
+namespace {
+
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;  // 1024 values per block
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread across the block; returns the
+// thread's exclusive prefix and the block total in *total.
+__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
+    __shared__ uint32_t s_w[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(x);
+    if (lane == 63) s_w[wid] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; i++) {
+        if (i < wid) off += s_w[i];
+        tot += s_w[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - x;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
+                                                        uint32_t* __restrict__ sums) {
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile;
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t j = base + static_cast<uint64_t>(i) * kBlock + threadIdx.x;
+        if (j < n) x += in[j];
+    }
+    uint32_t tot;
+    (void)block_excl_scan(x, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_spine(uint32_t* __restrict__ sums, uint32_t nb,
+                                                    uint32_t* __restrict__ total) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nb; base += 1024) {
+        uint32_t j = base + threadIdx.x;
+        uint32_t x = j < nb ? sums[j] : 0;
+        uint32_t inc = wave_incl_scan(x);
+        if (lane == 63) s_w[wid] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (int i = 0; i < 16; i++) {
+            if (i < wid) off += s_w[i];
+            tot += s_w[i];
+        }
+        uint32_t carry = s_carry;
+        if (j < nb) sums[j] = carry + off + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = s_carry;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                      const uint32_t* __restrict__ sums) {
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile +
+                          static_cast<uint64_t>(threadIdx.x) * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        x += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(x, &tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+}
+
+}  // namespace
+
+void scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total_dev,
+                    Arena& arena, hipStream_t s) {
+    if (n == 0) {
+        if (total_dev) hip_check(hipMemsetAsync(total_dev, 0, sizeof(uint32_t), s), "scan");
+        return;
+    }
+    uint32_t nb = ceil_div(n, kScanTile);
+    uint32_t* sums = arena.alloc<uint32_t>(nb);
+    k_scan_reduce<<<nb, kBlock, 0, s>>>(in, n, sums);
+    k_scan_spine<<<1, 1024, 0, s>>>(sums, nb, total_dev);
+    k_scan_down<<<nb, kBlock, 0, s>>>(in, out, n, sums);
+    hip_check(hipGetLastError(), "scan launch");
+}
+
+// --------------------------------------------------------------- staging
+
+namespace {
+
+__global__ void __launch_bounds__(kBlock) k_stage_vertices(
+    const uint32_t* __restrict__ row_off, const uint32_t* __restrict__ type_off,
+    const uint8_t* __restrict__ alive, uint32_t n, uint64_t m, uint32_t* __restrict__ bnd,
+    uint32_t* __restrict__ hubf, RunStatus* status) {
+    uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    uint32_t a = row_off[v], b = row_off[v + 1];
+    uint32_t err = 0;
+    if (b < a) err |= kErrInvalid;
+    if (type_off[v + 1] < type_off[v]) err |= kErrInvalid;
+    if (v == 0 && (a != 0 || type_off[0] != 0)) err |= kErrInvalid;
+    if (v == n - 1 && static_cast<uint64_t>(b) != m) err |= kErrInvalid;
+    uint32_t d = b - a;
+    if (alive && !alive[v] && (d != 0)) err |= kErrInvalid;
+    uint32_t nt = type_off[v + 1] - type_off[v];
+    if (nt) atomicMax(&status->max_types, nt);
+    bool hub = (b >= a) && d > static_cast<uint32_t>(kTileQuota);
+    bool prev_hub = false;
+    bool cross = false;
+    if (v > 0) {
+        uint32_t pa = row_off[v - 1];
+        prev_hub = (a >= pa) && (a - pa) > static_cast<uint32_t>(kTileQuota);
+        cross = (a / kTileQuota) != (pa / kTileQuota);
+    }
+    bnd[v] = (v == 0 || hub || prev_hub || cross || (v % kTileMaxVerts) == 0) ? 1u : 0u;
+    hubf[v] = hub ? 1u : 0u;
+    if (err) atomicOr(&status->error, err);
+}
+
+template <typename LabT>
+__global__ void __launch_bounds__(kBlock) k_stage_edges(const uint32_t* __restrict__ tgt,
+                                                        const LabT* __restrict__ lab,
+                                                        const uint8_t* __restrict__ alive,
+                                                        uint32_t n, uint64_t m, RunStatus* status) {
+    uint32_t err = 0, mx = 0;
+    for (uint64_t e = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; e < m;
+         e += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        uint32_t w = tgt[e];
+        if (w >= n) err |= kErrRange;
+        else if (alive && !alive[w]) err |= kErrInvalid;
+        mx = max(mx, static_cast<uint32_t>(lab[e]));
+    }
+    // wave-reduce before touching global memory
+    for (int d = 32; d >= 1; d >>= 1) {
+        mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), d, 64)));
+        err |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(err), d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (mx) atomicMax(&status->max_label, mx);
+        if (err) atomicOr(&status->error, err);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_compact_flags(const uint32_t* __restrict__ flag,
+                                                          const uint32_t* __restrict__ pos,
+                                                          uint32_t n, uint32_t* __restrict__ out) {
+    uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v < n && flag[v]) out[pos[v]] = v;
+}
+
+// Tile p spans boundaries B[p]..B[p+1]; tiles that start at a hub are dropped.
+__global__ void __launch_bounds__(kBlock) k_tile_flags(const uint32_t* __restrict__ B, uint32_t nb,
+                                                       const uint32_t* __restrict__ hubf,
+                                                       uint32_t* __restrict__ keep) {
+    uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < nb) keep[p] = hubf[B[p]] ? 0u : 1u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_tile_emit(const uint32_t* __restrict__ B, uint32_t nb,
+                                                      uint32_t n, const uint32_t* __restrict__ keep,
+                                                      const uint32_t* __restrict__ pos,
+                                                      uint32_t* __restrict__ v0,
+                                                      uint32_t* __restrict__ v1) {
+    uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < nb && keep[p]) {
+        v0[pos[p]] = B[p];
+        v1[pos[p]] = (p + 1 < nb) ? B[p + 1] : n;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_hub_degrees(const uint32_t* __restrict__ row_off,
+                                                         const uint32_t* __restrict__ hubs,
+                                                         uint32_t nh, uint32_t* __restrict__ deg) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < nh) deg[i] = row_off[hubs[i] + 1] - row_off[hubs[i]];
+}
+
+__global__ void __launch_bounds__(kBlock) k_salt(uint64_t* salt, uint32_t count) {
+    uint32_t l = blockIdx.x * kBlock + threadIdx.x;
+    if (l < count) salt[l] = mix64(kCL + static_cast<uint64_t>(l));
+}
+
+}  // namespace
+
+void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena& arena,
+                 hipStream_t s) {
+    const uint32_t n = g.n;
+    hip_check(hipMemsetAsync(status_dev, 0, sizeof(RunStatus), s), "stage status");
+    uint32_t* bnd = arena.alloc<uint32_t>(n + 1);
+    uint32_t* hubf = arena.alloc<uint32_t>(n + 1);
+    uint32_t* pos = arena.alloc<uint32_t>(n + 1);
+    uint32_t* counts = arena.alloc<uint32_t>(4);
+    if (n > 0) {
+        k_stage_vertices<<<ceil_div(n, kBlock), kBlock, 0, s>>>(g.row_off, g.type_off, g.alive, n,
+                                                                g.m, bnd, hubf, status_dev);
+        if (g.m > 0) {
+            uint32_t nbk = std::min<uint64_t>(ceil_div(g.m, kBlock), 8192);
+            if (g.label_bytes == 2)
+                k_stage_edges<uint16_t><<<nbk, kBlock, 0, s>>>(
+                    g.tgt, static_cast<const uint16_t*>(g.lab), g.alive, n, g.m, status_dev);
+            else
+                k_stage_edges<uint32_t><<<nbk, kBlock, 0, s>>>(
+                    g.tgt, static_cast<const uint32_t*>(g.lab), g.alive, n, g.m, status_dev);
+        }
+        hip_check(hipGetLastError(), "stage launch");
+    }
+    // boundaries -> B[], hubs -> hub list
+    scan_exclusive(bnd, pos, n, counts + 0, arena, s);
+    uint32_t* B = arena.alloc<uint32_t>(n + 1);
+    if (n) k_compact_flags<<<ceil_div(n, kBlock), kBlock, 0, s>>>(bnd, pos, n, B);
+    uint32_t* hpos = arena.alloc<uint32_t>(n + 1);
+    scan_exclusive(hubf, hpos, n, counts + 1, arena, s);
+    uint32_t* hubs = arena.alloc<uint32_t>(n + 1);
+    if (n) k_compact_flags<<<ceil_div(n, kBlock), kBlock, 0, s>>>(hubf, hpos, n, hubs);
+    hip_check(hipMemcpyAsync(status_host, status_dev, sizeof(RunStatus), hipMemcpyDeviceToHost, s),
+              "stage status");
+    uint32_t hc[2];
+    hip_check(hipMemcpyAsync(hc, counts, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "stage counts");
+    hip_check(hipStreamSynchronize(s), "stage sync");
+    if (status_host->error & kErrRange)
+        throw DeviceError{BSIM_E_RANGE, "edge target out of range"};
+    if (status_host->error & kErrInvalid)
+        throw DeviceError{BSIM_E_INVALID, "malformed CSR or an edge touching a dead vertex"};
+    if (status_host->max_types > (1u << 16))
+        throw DeviceError{BSIM_E_UNSUPPORTED, "more than 65536 type ids on one vertex"};
+    if (status_host->max_label >= (1u << 24))
+        throw DeviceError{BSIM_E_UNSUPPORTED, "edge labels must be < 2^24"};
+    g.max_label = status_host->max_label;
+    const uint32_t nb = hc[0];
+    g.n_hubs = hc[1];
+
+    // tiles
+    uint32_t* keep = arena.alloc<uint32_t>(nb + 1);
+    uint32_t* tpos = arena.alloc<uint32_t>(nb + 1);
+    if (nb) k_tile_flags<<<ceil_div(nb, kBlock), kBlock, 0, s>>>(B, nb, hubf, keep);
+    scan_exclusive(keep, tpos, nb, counts + 2, arena, s);
+    uint32_t ntiles = 0;
+    hip_check(hipMemcpyAsync(&ntiles, counts + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "tiles");
+    hip_check(hipStreamSynchronize(s), "tiles sync");
+    g.n_tiles = ntiles;
+    g.tile_v0 = arena.alloc<uint32_t>(ntiles + 1);
+    g.tile_v1 = arena.alloc<uint32_t>(ntiles + 1);
+    if (nb)
+        k_tile_emit<<<ceil_div(nb, kBlock), kBlock, 0, s>>>(B, nb, n, keep, tpos, g.tile_v0,
+                                                            g.tile_v1);
+
+    // hubs: schedule on the host (few), largest first so long buckets start early
+    g.host_hub_v.assign(g.n_hubs, 0);
+    g.host_hub_deg.assign(g.n_hubs, 0);
+    if (g.n_hubs) {
+        uint32_t* hdeg = arena.alloc<uint32_t>(g.n_hubs);
+        k_hub_degrees<<<ceil_div(g.n_hubs, kBlock), kBlock, 0, s>>>(g.row_off, hubs, g.n_hubs, hdeg);
+        hip_check(hipMemcpyAsync(g.host_hub_v.data(), hubs, g.n_hubs * sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, s), "hubs");
+        hip_check(hipMemcpyAsync(g.host_hub_deg.data(), hdeg, g.n_hubs * sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, s), "hub degrees");
+        hip_check(hipStreamSynchronize(s), "hubs sync");
+        std::vector<uint32_t> order(g.n_hubs);
+        std::iota(order.begin(), order.end(), 0u);
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            return g.host_hub_deg[a] > g.host_hub_deg[b];
+        });
+        std::vector<uint32_t> hv(g.n_hubs), hd(g.n_hubs), hl(g.n_hubs);
+        std::vector<uint32_t> bh, bb;
+        for (uint32_t i = 0; i < g.n_hubs; i++) {
+            hv[i] = g.host_hub_v[order[i]];
+            hd[i] = g.host_hub_deg[order[i]];
+            uint32_t want = ceil_div(hd[i], kHubBucketTarget);
+            uint32_t logb = static_cast<uint32_t>(bit_width(next_pow2(want)) - 1);
+            hl[i] = logb;
+            for (uint32_t b = 0; b < (1u << logb); b++) {
+                bh.push_back(i);
+                bb.push_back(b);
+            }
+        }
+        g.host_hub_v = hv;
+        g.host_hub_deg = hd;
+        g.n_hub_blocks = static_cast<uint32_t>(bh.size());
+        g.hub_v = arena.alloc<uint32_t>(g.n_hubs);
+        g.hub_logb = arena.alloc<uint32_t>(g.n_hubs);
+        g.hb_hub = arena.alloc<uint32_t>(g.n_hub_blocks);
+        g.hb_bucket = arena.alloc<uint32_t>(g.n_hub_blocks);
+        hip_check(hipMemcpyAsync(g.hub_v, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, s), "hub v");
+        hip_check(hipMemcpyAsync(g.hub_logb, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s), "hub b");
+        hip_check(hipMemcpyAsync(g.hb_hub, bh.data(), bh.size() * 4, hipMemcpyHostToDevice, s), "hub blk");
+        hip_check(hipMemcpyAsync(g.hb_bucket, bb.data(), bb.size() * 4, hipMemcpyHostToDevice, s), "hub bkt");
+        hip_check(hipStreamSynchronize(s), "hub schedule sync");
+    } else {
+        g.n_hub_blocks = 0;
+    }
+
+    // label salts
+    uint32_t nsalt = g.max_label + 1;
+    g.salt = arena.alloc<uint64_t>(nsalt);
+    k_salt<<<ceil_div(nsalt, kBlock), kBlock, 0, s>>>(g.salt, nsalt);
+    hip_check(hipGetLastError(), "salt launch");
+}
+
+}  // namespace bsim

@@ -1,0 +1,241 @@
+// bsim_summarize.hip -- host driver of one batch summarization.
+//
+// Device round trips per call: one after staging (tile and hub counts), one
+// per queued chunk of refinement launches (the sticky done flag, read while
+// the next chunk is already queued), two in finalize (block and edge
+// counts).  Refinement launches are queued in chunks that double up to
+// ctx->chunk_max, so a run of thousands of iterations (long k-chaining)
+// costs only the kernels themselves plus a few early-exit launches.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "bsim_api_internal.h"
+
+namespace bsim {
+
+void validate_params(const bsim_graph& graph, const bsim_params& p) {
+    if (graph.label_bytes != 2 && graph.label_bytes != 4)
+        throw DeviceError{BSIM_E_INVALID, "label_bytes must be 2 or 4"};
+    if (graph.mem_kind != BSIM_MEM_HOST && graph.mem_kind != BSIM_MEM_DEVICE)
+        throw DeviceError{BSIM_E_INVALID, "unknown mem_kind"};
+    if (graph.n_edges >= (1ull << 32))
+        throw DeviceError{BSIM_E_UNSUPPORTED, "this build supports fewer than 2^32 edges"};
+    if (graph.n_vertices >= 0xFFFFFFFFu)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "too many vertices"};
+    if (!graph.row_off || !graph.type_off)
+        throw DeviceError{BSIM_E_INVALID, "row_off and type_off are required"};
+    if (graph.n_edges && (!graph.targets || !graph.labels))
+        throw DeviceError{BSIM_E_INVALID, "targets and labels are required"};
+    if (!(p.flags & BSIM_STOP_AT_FIXPOINT) && p.k_max > (1u << 24))
+        throw DeviceError{BSIM_E_INVALID, "without a fixpoint test k_max must be finite (< 2^24)"};
+    if (p.flags & ~(BSIM_STOP_AT_FIXPOINT | BSIM_KEEP_LEVELS | BSIM_UNTYPED | BSIM_RESULT_ON_HOST |
+                    BSIM_NO_SUMMARY_EDGES))
+        throw DeviceError{BSIM_E_INVALID, "unknown flag bits"};
+}
+
+void upload_graph(const bsim_graph& in, Staged& g, Arena& arena, hipStream_t s) {
+    g.n = in.n_vertices;
+    g.m = in.n_edges;
+    g.label_bytes = in.label_bytes;
+    if (in.mem_kind == BSIM_MEM_DEVICE) {
+        g.row_off = in.row_off;
+        g.tgt = in.targets;
+        g.lab = in.labels;
+        g.type_off = in.type_off;
+        g.type_ids = in.type_ids;
+        g.alive = in.alive;
+        return;
+    }
+    const size_t n = in.n_vertices, m = in.n_edges;
+    uint32_t* ro = arena.alloc<uint32_t>(n + 1);
+    hip_check(hipMemcpyAsync(ro, in.row_off, (n + 1) * 4, hipMemcpyHostToDevice, s), "upload row_off");
+    uint32_t* to = arena.alloc<uint32_t>(n + 1);
+    hip_check(hipMemcpyAsync(to, in.type_off, (n + 1) * 4, hipMemcpyHostToDevice, s), "upload type_off");
+    // type_off[n] tells how many type ids follow; read it from the host copy
+    const size_t nt = in.type_off[n];
+    uint32_t* ti = arena.alloc<uint32_t>(nt + 1);
+    if (nt) hip_check(hipMemcpyAsync(ti, in.type_ids, nt * 4, hipMemcpyHostToDevice, s), "upload types");
+    uint32_t* tg = arena.alloc<uint32_t>(m + 1);
+    void* lb = arena.alloc<uint8_t>(m * in.label_bytes + 4);
+    if (m) {
+        hip_check(hipMemcpyAsync(tg, in.targets, m * 4, hipMemcpyHostToDevice, s), "upload targets");
+        hip_check(hipMemcpyAsync(lb, in.labels, m * in.label_bytes, hipMemcpyHostToDevice, s), "upload labels");
+    }
+    uint8_t* al = nullptr;
+    if (in.alive) {
+        al = arena.alloc<uint8_t>(n + 1);
+        hip_check(hipMemcpyAsync(al, in.alive, n, hipMemcpyHostToDevice, s), "upload alive");
+    }
+    g.row_off = ro;
+    g.type_off = to;
+    g.type_ids = ti;
+    g.tgt = tg;
+    g.lab = lb;
+    g.alive = al;
+}
+
+LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
+                          LevelSink* sink, Arena& arena) {
+    (void)arena;
+    hipStream_t s = ctx->stream;
+    const bool stop = (p.flags & BSIM_STOP_AT_FIXPOINT) != 0;
+    const bool untyped = (p.flags & BSIM_UNTYPED) != 0;
+    if (sink && !sink->levels.empty()) rb.h[0] = sink->levels[0];
+    launch_type_hash(g, rb, untyped, s);
+
+    LoopResult lr;
+    const uint64_t k_last = static_cast<uint64_t>(p.k_max) + 1;  // this launch always sees the cap
+    uint64_t k = 1;
+    uint32_t chunk = 8;
+    int pending = -1;
+    hipEvent_t ev[2];
+    hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming), "event");
+    bool done = false;
+    try {
+        while (!done) {
+            if (k <= k_last) {
+                const uint32_t c = static_cast<uint32_t>(std::min<uint64_t>(chunk, k_last - k + 1));
+                for (uint32_t i = 0; i < c; i++, k++) {
+                    const uint32_t kk = static_cast<uint32_t>(k);
+                    if (sink && !sink->levels.empty()) {
+                        // keep every level: iteration kk reads levels[kk-1], writes levels[kk]
+                        const uint32_t top = static_cast<uint32_t>(sink->levels.size()) - 1;
+                        rb.h[(kk - 1) & 1] = sink->levels[std::min(kk - 1, top)];
+                        rb.h[kk & 1] = sink->levels[std::min(kk, top)];
+                    }
+                    launch_iteration(g, rb, kk, p.k_max, stop, s);
+                    lr.launches++;
+                }
+                const int slot = pending < 0 ? 0 : (pending ^ 1);
+                hip_check(hipMemcpyAsync(&ctx->status_host[slot], rb.status, sizeof(RunStatus),
+                                         hipMemcpyDeviceToHost, s), "status copy");
+                hip_check(hipEventRecord(ev[slot], s), "status event");
+                if (pending >= 0) {
+                    hip_check(hipEventSynchronize(ev[pending]), "status wait");
+                    done = ctx->status_host[pending].done != 0;
+                }
+                pending = slot;
+                chunk = std::min<uint32_t>(chunk * 2, ctx->chunk_max);
+            } else {
+                hip_check(hipEventSynchronize(ev[pending]), "status wait");
+                done = ctx->status_host[pending].done != 0;
+                if (!done) throw DeviceError{BSIM_E_DEVICE, "refinement did not reach its stop test"};
+            }
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        throw;
+    }
+    hip_check(hipStreamSynchronize(s), "loop sync");
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    RunStatus st;
+    hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
+    lr.k_done = st.k_done;
+    lr.fixpoint = st.fixpoint;
+    lr.blocks_per_iter.resize(static_cast<size_t>(lr.k_done) + 1);
+    hip_check(hipMemcpy(lr.blocks_per_iter.data(), rb.totals, (lr.k_done + 1) * 4, hipMemcpyDeviceToHost),
+              "block counts");
+    if (sink && !sink->levels.empty())
+        lr.h_final = sink->levels[std::min<size_t>(lr.k_done, sink->levels.size() - 1)];
+    else
+        lr.h_final = rb.h[lr.k_done & 1];
+    return lr;
+}
+
+bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, const uint64_t* h,
+                         FinalOut& fo, Arena& keep, uint32_t flags) {
+    hipStream_t s = ctx->stream;
+    bsim_result* r = new bsim_result();
+    ResultPriv* p = new ResultPriv();
+    memset(r, 0, sizeof(*r));
+    r->priv = p;
+    p->device = ctx->device;
+    p->stream = s;
+    p->blocks_per_iter = lr.blocks_per_iter;
+    r->n_vertices = g.n;
+    r->k_done = lr.k_done;
+    r->fixpoint = lr.fixpoint;
+    r->n_blocks = fo.n_blocks;
+    r->n_summary_edges = fo.n_se;
+    r->n_iter_launches = lr.launches;
+    r->blocks_per_iter = p->blocks_per_iter.data();
+    uint64_t* hashes = keep.alloc<uint64_t>(g.n);
+    if (g.n) hip_check(hipMemcpyAsync(hashes, h, static_cast<size_t>(g.n) * 8, hipMemcpyDeviceToDevice, s),
+                       "hashes");
+    void* dev[] = {hashes, fo.block_ids, fo.block_sizes, fo.se_src, fo.se_label, fo.se_dst};
+    if (flags & BSIM_RESULT_ON_HOST) {
+        const size_t sizes[] = {static_cast<size_t>(g.n) * 8, static_cast<size_t>(g.n) * 4,
+                                static_cast<size_t>(fo.n_blocks) * 4, fo.n_se * 4, fo.n_se * 4, fo.n_se * 4};
+        void* host[6];
+        for (int i = 0; i < 6; i++) {
+            host[i] = malloc(sizes[i] ? sizes[i] : 8);
+            if (!host[i]) throw DeviceError{BSIM_E_NOMEM, "host result allocation failed"};
+            p->host_ptrs.push_back(host[i]);
+            if (sizes[i])
+                hip_check(hipMemcpyAsync(host[i], dev[i], sizes[i], hipMemcpyDeviceToHost, s), "result copy");
+        }
+        hip_check(hipStreamSynchronize(s), "result sync");
+        keep.release();
+        r->mem_kind = BSIM_MEM_HOST;
+        r->hashes = static_cast<uint64_t*>(host[0]);
+        r->block_ids = static_cast<uint32_t*>(host[1]);
+        r->block_sizes = static_cast<uint32_t*>(host[2]);
+        r->se_src = static_cast<uint32_t*>(host[3]);
+        r->se_label = static_cast<uint32_t*>(host[4]);
+        r->se_dst = static_cast<uint32_t*>(host[5]);
+    } else {
+        for (void* q : dev) {
+            p->device_ptrs.push_back(q);
+            keep.detach(q);
+        }
+        r->mem_kind = BSIM_MEM_DEVICE;
+        r->hashes = hashes;
+        r->block_ids = fo.block_ids;
+        r->block_sizes = fo.block_sizes;
+        r->se_src = fo.se_src;
+        r->se_label = fo.se_label;
+        r->se_dst = fo.se_dst;
+    }
+    return r;
+}
+
+bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p, void*) {
+    validate_params(graph, p);
+    hipStream_t s = ctx->stream;
+    Arena arena(s), keep(s);
+    hipEvent_t ev[4];
+    for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; i++) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+    hip_check(hipEventRecord(ev[0], s), "event");
+    Staged g;
+    upload_graph(graph, g, arena, s);
+    RunStatus* stage_status = arena.alloc<RunStatus>(1);
+    stage_graph(g, stage_status, &ctx->status_host[3], arena, s);
+    RunBuffers rb;
+    alloc_run_buffers(g, p.k_max, (p.flags & BSIM_STOP_AT_FIXPOINT) != 0, rb, arena, s);
+    hip_check(hipEventRecord(ev[1], s), "event");
+    LoopResult lr = run_refinement(ctx, g, p, rb, nullptr, arena);
+    hip_check(hipEventRecord(ev[2], s), "event");
+    FinalOut fo;
+    finalize(g, lr.h_final, 0, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    bsim_result* r = make_result(ctx, g, lr, lr.h_final, fo, keep, p.flags);
+    hip_check(hipEventRecord(ev[3], s), "event");
+    hip_check(hipEventSynchronize(ev[3]), "event");
+    (void)hipEventElapsedTime(&r->ms_stage, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&r->ms_iterate, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&r->ms_finalize, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&r->ms_total, ev[0], ev[3]);
+    return r;
+}
+
+}  // namespace bsim
