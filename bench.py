@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X k-bisimulation path.
+
+One step = one full batch summarization (staging, type hashes, refinement
+iterations to the fixpoint, relabel, block sizes, summary edges) of one
+device-resident synthetic graph through the C ABI.  Default workload: an
+R-MAT graph (a, b, c = 0.57, 0.19, 0.19) with 2^22 vertices and 2^25 edges,
+256 type labels (Zipf 1.1, 0-4 per vertex), 64 edge labels (Zipf 1.1), plus
+64 disjoint labeled chains of 2,000 edges, which force >= 2,001 iterations.
+
+Prints ONE JSON line (rank 0, N = 1) with the whole-job throughput in
+edge-iterations/s (sum over executed iterations of |E|, over the wall time
+of the timed steps), the refinement kernel's HBM roofline figures and a
+bounded CPU-oracle baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def iteration_bytes(n: int, m: int, label_bytes: int) -> int:
+    """Algorithmic HBM bytes of one refinement iteration: per edge the target
+    id, the label and the gathered neighbour hash; per vertex its offset, its
+    type hash, its new hash and one count-table slot (16 B)."""
+    return m * (4 + label_bytes + 8) + n * (4 + 8 + 8 + 16)
+
+
+def read_traffic(workload: str):
+    """HBM traffic per refinement launch from a committed rocprofv3 counter
+    summary (profiles/k_iterate_<workload>_counters.json), if present."""
+    path = os.path.join(ROOT, "profiles", "k_iterate_%s_counters.json" % workload)
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(g, iters: int):
+    from oracle import oracle as orc
+
+    try:
+        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    orc.iterate(g, iters)
+    dt = time.perf_counter() - t0
+    return {"value": iters * g.m / dt, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": "type hashes + first %d refinement iterations of the same graph, single "
+                      "thread, %.1f s" % (iters, dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat22_chains")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path (see DESIGN.md for how "
+              "the refinement would shard); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2111_12493_amd import binding
+    from paper_2111_12493_amd import graphgen as gg
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    g = gg.make_config(args.workload)
+    gen_s = time.perf_counter() - t_gen
+    print("# workload %s: %d vertices, %d edges (generated in %.1f s)" % (args.workload, g.n, g.m, gen_s),
+          file=sys.stderr, flush=True)
+    dg = binding.DeviceGraph(g)
+    ctx = binding.Context(0)
+    ctx.set_option("time_launches", 1)
+    torch.cuda.synchronize()
+
+    def step():
+        r = binding.summarize(ctx, dg, k_max=binding.K_UNBOUNDED)
+        rec = dict(k_done=r.k_done, launches=r.n_iter_launches, ms_kernels=r.ms_iter_kernels,
+                   ms_iterate=r.ms_iterate, ms_stage=r.ms_stage, ms_finalize=r.ms_finalize,
+                   ms_total=r.ms_total, n_blocks=r.n_blocks, n_se=r.n_summary_edges)
+        r.free()
+        return rec
+
+    for i in range(args.warmup):
+        rec = step()
+        print("# warmup %d: k_done=%d blocks=%d %.1f ms" % (i, rec["k_done"], rec["n_blocks"], rec["ms_total"]),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for i, r in enumerate(recs):
+        print("# step %d: k_done=%d launches=%d stage %.2f ms, iterate %.2f ms (kernels %.2f), "
+              "finalize %.2f ms" % (i, r["k_done"], r["launches"], r["ms_stage"], r["ms_iterate"],
+                                    r["ms_kernels"], r["ms_finalize"]), file=sys.stderr, flush=True)
+
+    edge_iters = sum(r["k_done"] for r in recs) * g.m
+    value = edge_iters / wall
+    label_bytes = 2 if g.lab.dtype.itemsize == 2 else 4
+    b_iter = iteration_bytes(g.n, g.m, label_bytes)
+    # live kernel timing: HIP events around every refinement launch, summed
+    # over the timed steps; the useful launches are iterations 1..k_done
+    kern_ms = sum(r["ms_kernels"] for r in recs)
+    launches = sum(r["launches"] for r in recs)
+    useful = sum(r["k_done"] for r in recs)
+    achieved = b_iter * useful / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else 0.0
+    traffic = read_traffic(args.workload)
+    out = {
+        "metric": "edge-iterations/s for k-bisimulation (% HBM roofline); p50/p99 update latency",
+        "value": value,
+        "unit": "edge-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "vertices": g.n, "edges": g.m,
+                   "k_done": recs[-1]["k_done"], "blocks": recs[-1]["n_blocks"],
+                   "summary_edges": recs[-1]["n_se"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_iterate", "bytes_per_launch": b_iter,
+                     "avg_launch_us": kern_ms * 1e3 / max(launches, 1),
+                     "avg_useful_launch_us": kern_ms * 1e3 / max(useful, 1),
+                     "launches": launches, "useful_launches": useful},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_iters)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

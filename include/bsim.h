@@ -130,6 +130,9 @@ typedef struct {
     float ms_iterate;
     float ms_finalize;
     float ms_total;
+    float ms_iter_kernels; /* summed durations of the refinement launches when the
+                              ctx option "time_launches" is 1, else 0 */
+    uint32_t reserved;
     void* priv;
 } bsim_result;
 
@@ -162,9 +165,11 @@ void bsim_ctx_free(bsim_ctx* ctx);
 /* Text of the last error raised on this ctx ("" if none). */
 const char* bsim_last_error(const bsim_ctx* ctx);
 const char* bsim_status_string(int status);
-/* Tuning knobs (tile edge quota, vertex cap, chunk length); see the names
- * in bsim_option_names().  Values outside the documented range give
- * BSIM_E_RANGE. */
+/* Run-time options (see bsim_option_names()): "chunk_max" = refinement
+ * launches queued per stop-flag check (1..4096); "time_launches" = 1 to
+ * bracket every refinement launch with HIP events and report the summed
+ * kernel time in bsim_result.ms_iter_kernels.  Values outside the range
+ * give BSIM_E_RANGE, unknown names BSIM_E_INVALID. */
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value);
 int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value);
 const char* bsim_option_names(void);

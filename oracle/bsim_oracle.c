@@ -32,12 +32,19 @@
  *
  * All arithmetic is unsigned and wraps mod 2^64.
  *
+ * Classes.  The bisimulation definition (Sec. 2.5) makes u, v k-bisimilar
+ * iff they are (k-1)-bisimilar AND their labeled successor sets match; the
+ * hash decides the second condition.  So the k-class of v is the pair
+ * (its (k-1)-class, h^k(v)), with the 0-class given by h^0 = t(v).  Without
+ * a 64-bit collision this is exactly "equal h^k"; with one, classes that
+ * were already apart stay apart.  n_k is the number of k-classes over alive
+ * vertices.
+ *
  * Relabelling (Algorithm 4's final FindAndMerge): blocks are numbered by
  * first occurrence -- the block holding the smallest vertex id is block 0,
- * and so on -- which depends only on the partition.  n_k is the number of
- * distinct h^k over alive vertices.  The loop stops at the first k >= 1 with
- * n_k == n_{k-1} (the partition stopped changing; it is then the maximal
- * bisimulation refining the type partition) or at k_max.
+ * and so on -- which depends only on the partition.  The loop stops at the
+ * first k >= 1 with n_k == n_{k-1} (the partition stopped changing; it is
+ * then the maximal bisimulation refining the type partition) or at k_max.
  *
  * The summary graph's edges are the distinct triples (block(v), l, block(w))
  * over all edges, i.e. the quotient of the graph by the final partition
@@ -141,22 +148,45 @@ static uint64_t max_degree(uint32_t n, const uint64_t* row_off) {
     return d;
 }
 
-/* Number of distinct hashes over alive vertices. */
-static uint32_t count_distinct(const uint64_t* h, const uint8_t* alive, uint32_t n,
-                               uint64_t* scratch) {
-    size_t k = 0;
-    for (uint32_t v = 0; v < n; v++)
-        if (!alive || alive[v]) scratch[k++] = h[v];
-    return (uint32_t)unique_u64(scratch, k);
-}
+typedef struct { uint32_t c; uint64_t h; uint32_t v; } chv_triple;
 
-typedef struct { uint64_t h; uint32_t v; } hv_pair;
-
-static int cmp_hv(const void* a, const void* b) {
-    const hv_pair* x = (const hv_pair*)a;
-    const hv_pair* y = (const hv_pair*)b;
+static int cmp_chv(const void* a, const void* b) {
+    const chv_triple* x = (const chv_triple*)a;
+    const chv_triple* y = (const chv_triple*)b;
+    if (x->c != y->c) return (x->c > y->c) - (x->c < y->c);
     if (x->h != y->h) return (x->h > y->h) - (x->h < y->h);
     return (x->v > y->v) - (x->v < y->v);
+}
+
+/* Refine: the new class of an alive vertex is the pair (cls[v], h[v]).
+ * Classes are renumbered by first occurrence (the class of the smallest
+ * vertex is 0).  Dead vertices get 0xFFFFFFFF.  Returns the class count. */
+static uint32_t refine_classes(const uint32_t* cls, const uint64_t* h, const uint8_t* alive,
+                               uint32_t n, uint32_t* out) {
+    chv_triple* p = (chv_triple*)malloc(sizeof(chv_triple) * (n ? n : 1));
+    uint32_t* minv = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* rank = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint8_t* is_min = (uint8_t*)calloc(n ? n : 1, 1);
+    if (!p || !minv || !rank || !is_min) abort();
+    size_t k = 0;
+    for (uint32_t v = 0; v < n; v++)
+        if (!alive || alive[v]) { p[k].c = cls ? cls[v] : 0; p[k].h = h[v]; p[k].v = v; k++; }
+    qsort(p, k, sizeof(chv_triple), cmp_chv);
+    /* smallest vertex of each (class, hash) group */
+    for (size_t i = 0; i < k; i++) {
+        int same = i > 0 && p[i].c == p[i - 1].c && p[i].h == p[i - 1].h;
+        uint32_t m = same ? minv[p[i - 1].v] : p[i].v;
+        minv[p[i].v] = m;
+        if (m == p[i].v) is_min[p[i].v] = 1;
+    }
+    /* groups numbered in order of their smallest vertex */
+    uint32_t nb = 0;
+    for (uint32_t v = 0; v < n; v++)
+        if (is_min[v]) rank[v] = nb++;
+    for (uint32_t v = 0; v < n; v++)
+        out[v] = (!alive || alive[v]) ? rank[minv[v]] : 0xFFFFFFFFu;
+    free(p); free(minv); free(rank); free(is_min);
+    return nb;
 }
 
 typedef struct { uint32_t s, l, d; } triple;
@@ -169,33 +199,16 @@ static int cmp_triple(const void* a, const void* b) {
     return (x->d > y->d) - (x->d < y->d);
 }
 
-/* First-occurrence block ids of the partition induced by h over alive
- * vertices.  Returns the number of blocks. */
+/* One refinement step on given classes and hashes (exported for tests). */
+uint32_t bo_refine_classes(const uint32_t* cls, const uint64_t* h, const uint8_t* alive, uint32_t n,
+                           uint32_t* out) {
+    return refine_classes(cls, h, alive, n, out);
+}
+
+/* First-occurrence block ids of the partition induced by equal values of h
+ * over alive vertices.  Returns the number of blocks. */
 uint32_t bo_block_ids(const uint64_t* h, const uint8_t* alive, uint32_t n, uint32_t* block) {
-    hv_pair* p = (hv_pair*)malloc(sizeof(hv_pair) * (n ? n : 1));
-    uint32_t* minv = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
-    uint8_t* is_min = (uint8_t*)calloc(n ? n : 1, 1);
-    if (!p || !minv || !is_min) abort();
-    size_t k = 0;
-    for (uint32_t v = 0; v < n; v++)
-        if (!alive || alive[v]) { p[k].h = h[v]; p[k].v = v; k++; }
-    qsort(p, k, sizeof(hv_pair), cmp_hv);
-    /* smallest vertex of each hash class */
-    for (size_t i = 0; i < k; i++) {
-        uint32_t m = (i > 0 && p[i].h == p[i - 1].h) ? minv[p[i - 1].v] : p[i].v;
-        minv[p[i].v] = m;
-        if (m == p[i].v) is_min[p[i].v] = 1;
-    }
-    /* blocks numbered in order of their smallest vertex */
-    uint32_t* rank = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
-    if (!rank) abort();
-    uint32_t nb = 0;
-    for (uint32_t v = 0; v < n; v++)
-        if (is_min[v]) rank[v] = nb++;
-    for (uint32_t v = 0; v < n; v++)
-        block[v] = (!alive || alive[v]) ? rank[minv[v]] : 0xFFFFFFFFu;
-    free(p); free(minv); free(is_min); free(rank);
-    return nb;
+    return refine_classes(NULL, h, alive, n, block);
 }
 
 /*
@@ -227,9 +240,10 @@ int bo_summarize(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t
     uint64_t* t = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
     uint64_t* cur = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
     uint64_t* nxt = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
-    uint64_t* scratch = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint32_t* cls = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* ncls = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
     uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * max_degree(n, row_off));
-    if (!t || !cur || !nxt || !scratch || !keys) return BO_E_NOMEM;
+    if (!t || !cur || !nxt || !cls || !ncls || !keys) return BO_E_NOMEM;
 
     /* k = 0: types only */
     for (uint32_t v = 0; v < n; v++) {
@@ -240,7 +254,7 @@ int bo_summarize(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t
         cur[v] = t[v];
     }
     memcpy(nxt, cur, sizeof(uint64_t) * n);
-    blocks_per_iter[0] = count_distinct(cur, alive, n, scratch);
+    blocks_per_iter[0] = refine_classes(NULL, cur, alive, n, cls);
     uint32_t k_done = 0, fixpoint = 0;
 
     for (uint32_t k = 1; k <= k_max; k++) {
@@ -249,7 +263,8 @@ int bo_summarize(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t
             nxt[v] = vertex_step(t[v], tgt + row_off[v], lab + row_off[v],
                                  row_off[v + 1] - row_off[v], cur, keys);
         }
-        blocks_per_iter[k] = count_distinct(nxt, alive, n, scratch);
+        blocks_per_iter[k] = refine_classes(cls, nxt, alive, n, ncls);
+        uint32_t* cs = cls; cls = ncls; ncls = cs;  /* cls = k-classes */
         uint64_t* sw = cur; cur = nxt; nxt = sw;   /* cur = h^k, nxt = h^{k-1} */
         k_done = k;
         if (blocks_per_iter[k] == blocks_per_iter[k - 1]) {
@@ -262,7 +277,9 @@ int bo_summarize(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t
     memcpy(hashes, cur, sizeof(uint64_t) * n);
     if (prev_hashes) memcpy(prev_hashes, nxt, sizeof(uint64_t) * n);
 
-    uint32_t nb = bo_block_ids(cur, alive, n, block_ids);
+    /* the k_done-classes, numbered by first occurrence, are the blocks */
+    uint32_t nb = blocks_per_iter[k_done];
+    memcpy(block_ids, cls, sizeof(uint32_t) * n);
     memset(block_sizes, 0, sizeof(uint32_t) * (nb ? nb : 0));
     for (uint32_t v = 0; v < n; v++)
         if (block_ids[v] != 0xFFFFFFFFu) block_sizes[block_ids[v]]++;
@@ -290,7 +307,7 @@ int bo_summarize(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t
     *k_done_out = k_done;
     *fixpoint_out = fixpoint;
     *n_blocks_out = nb;
-    free(tr); free(t); free(cur); free(nxt); free(scratch); free(keys);
+    free(tr); free(t); free(cur); free(nxt); free(cls); free(ncls); free(keys);
     return BO_OK;
 }
 
@@ -304,23 +321,27 @@ int bo_iterate(uint32_t n, const uint64_t* row_off, const uint32_t* tgt, const u
     uint64_t* t = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
     uint64_t* cur = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
     uint64_t* nxt = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
-    uint64_t* scratch = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint32_t* cls = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* ncls = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
     uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * max_degree(n, row_off));
-    if (!t || !cur || !nxt || !scratch || !keys) return BO_E_NOMEM;
+    if (!t || !cur || !nxt || !cls || !ncls || !keys) return BO_E_NOMEM;
     for (uint32_t v = 0; v < n; v++) {
         t[v] = bo_type_hash(typ + typ_off[v], (uint32_t)(typ_off[v + 1] - typ_off[v]),
                             flags & BO_UNTYPED);
         cur[v] = t[v];
     }
-    if (counts) counts[0] = count_distinct(cur, NULL, n, scratch);
+    uint32_t c0 = refine_classes(NULL, cur, NULL, n, cls);
+    if (counts) counts[0] = c0;
     for (uint32_t k = 1; k <= iters; k++) {
         for (uint32_t v = 0; v < n; v++)
             nxt[v] = vertex_step(t[v], tgt + row_off[v], lab + row_off[v],
                                  row_off[v + 1] - row_off[v], cur, keys);
-        if (counts) counts[k] = count_distinct(nxt, NULL, n, scratch);
+        uint32_t ck = refine_classes(cls, nxt, NULL, n, ncls);
+        if (counts) counts[k] = ck;
+        uint32_t* cs = cls; cls = ncls; ncls = cs;
         uint64_t* sw = cur; cur = nxt; nxt = sw;
     }
     memcpy(out_hashes, cur, sizeof(uint64_t) * n);
-    free(t); free(cur); free(nxt); free(scratch); free(keys);
+    free(t); free(cur); free(nxt); free(cls); free(ncls); free(keys);
     return BO_OK;
 }

@@ -51,6 +51,8 @@ def load(path: str) -> ctypes.CDLL:
     L.bo_vertex_step.argtypes = [u64, p, p, u64, p]
     L.bo_block_ids.restype = u32
     L.bo_block_ids.argtypes = [p, p, u32, p]
+    L.bo_refine_classes.restype = u32
+    L.bo_refine_classes.argtypes = [p, p, p, u32, p]
     L.bo_summarize.restype = ctypes.c_int
     L.bo_summarize.argtypes = [u32, u64, p, p, p, p, p, p, u32, u32,
                                p, p, p, p, p, p, p, p, p, p, p, p]
@@ -98,6 +100,16 @@ def block_ids(h: np.ndarray, alive: Optional[np.ndarray] = None):
     al = None if alive is None else np.ascontiguousarray(alive, dtype=np.uint8)
     nb = lib().bo_block_ids(_ptr(h), _ptr(al), h.size, _ptr(out))
     return out, int(nb)
+
+
+def refine_classes(cls, h, alive=None):
+    """One refinement step: new class = (cls[v], h[v]), first-occurrence ids."""
+    h = np.ascontiguousarray(h, dtype=np.uint64)
+    c = np.ascontiguousarray(cls, dtype=np.uint32)
+    out = np.zeros(max(h.size, 1), dtype=np.uint32)
+    al = None if alive is None else np.ascontiguousarray(alive, dtype=np.uint8)
+    nb = lib().bo_refine_classes(_ptr(c), _ptr(h), _ptr(al), h.size, _ptr(out))
+    return out[:h.size], int(nb)
 
 
 def _csr(g):

@@ -46,7 +46,8 @@ class BsimResult(ctypes.Structure):
                 ("hashes", _p), ("block_ids", _p), ("block_sizes", _p),
                 ("blocks_per_iter", ctypes.POINTER(_u32)), ("se_src", _p), ("se_label", _p),
                 ("se_dst", _p), ("ms_stage", ctypes.c_float), ("ms_iterate", ctypes.c_float),
-                ("ms_finalize", ctypes.c_float), ("ms_total", ctypes.c_float), ("priv", _p)]
+                ("ms_finalize", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("ms_iter_kernels", ctypes.c_float), ("reserved", _u32), ("priv", _p)]
 
 
 class BsimUpdate(ctypes.Structure):
@@ -224,6 +225,7 @@ class Result:
                                         dtype=np.uint32)
         self.ms_stage, self.ms_iterate = r.ms_stage, r.ms_iterate
         self.ms_finalize, self.ms_total = r.ms_finalize, r.ms_total
+        self.ms_iter_kernels = r.ms_iter_kernels
 
     def _len(self, field):
         if field in ("hashes", "block_ids"):

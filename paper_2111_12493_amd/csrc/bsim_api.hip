@@ -61,7 +61,8 @@ void bsim_ctx_free(bsim_ctx* ctx) {
 const char* bsim_last_error(const bsim_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
 const char* bsim_option_names(void) {
-    return "chunk_max (refinement launches queued per status check, 1..4096)";
+    return "chunk_max (refinement launches queued per stop-flag check, 1..4096); "
+           "time_launches (0/1: time every refinement launch with HIP events)";
 }
 
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
@@ -71,6 +72,11 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
         ctx->chunk_max = static_cast<uint32_t>(value);
         return BSIM_OK;
     }
+    if (!strcmp(name, "time_launches")) {
+        if (value < 0 || value > 1) return BSIM_E_RANGE;
+        ctx->time_launches = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
     return BSIM_E_INVALID;
 }
 
@@ -78,6 +84,10 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     if (!ctx || !name || !value) return BSIM_E_INVALID;
     if (!strcmp(name, "chunk_max")) {
         *value = ctx->chunk_max;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "time_launches")) {
+        *value = ctx->time_launches;
         return BSIM_OK;
     }
     return BSIM_E_INVALID;

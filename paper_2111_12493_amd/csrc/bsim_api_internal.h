@@ -12,6 +12,7 @@ struct bsim_ctx {
     std::string err;
     bsim::RunStatus* status_host = nullptr;  // pinned, 4 entries
     uint32_t chunk_max = 256;
+    uint32_t time_launches = 0;
 };
 
 namespace bsim {
@@ -43,6 +44,7 @@ struct LoopResult {
     uint32_t k_done = 0;
     uint32_t fixpoint = 0;
     uint32_t launches = 0;
+    float ms_kernels = 0.f;
     std::vector<uint32_t> blocks_per_iter;
     const uint64_t* h_final = nullptr;
 };

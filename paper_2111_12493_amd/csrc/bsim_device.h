@@ -53,16 +53,46 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t x, uint64_t* red) {
 // Insert hash h into a key-only open-addressing table (0 = empty slot,
 // capacity mask+1 > number of keys).  The hash 0 itself is tracked by a flag.
 // Returns 1 if h was not present before.
+//
+// Many vertices share a hash (e.g. every isolated vertex with the same type
+// set), so a slot is read before it is CASed: within one launch a slot only
+// changes from 0 to a key, so a plain read either sees the final key (no
+// atomic needed) or a possibly stale 0 that the CAS then resolves.  Without
+// this, all vertices of a large block serialize on one address.
 __device__ __forceinline__ uint32_t count_insert(uint64_t* tab, uint32_t mask, uint32_t* zflag,
                                                  uint64_t h) {
-    if (h == 0) return atomicExch(zflag, 1u) == 0u ? 1u : 0u;
+    if (h == 0) {
+        if (*reinterpret_cast<volatile uint32_t*>(zflag)) return 0u;
+        return atomicExch(zflag, 1u) == 0u ? 1u : 0u;
+    }
     uint32_t slot = static_cast<uint32_t>(h) & mask;
     for (;;) {
-        unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(tab + slot), 0ull,
-                                           static_cast<unsigned long long>(h));
-        if (old == 0ull) return 1u;
-        if (old == h) return 0u;
+        uint64_t cur = tab[slot];
+        if (cur == h) return 0u;
+        if (cur == 0) {
+            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(tab + slot), 0ull,
+                                               static_cast<unsigned long long>(h));
+            if (old == 0ull) return 1u;
+            if (old == h) return 0u;
+        }
         slot = (slot + 1) & mask;
+    }
+}
+
+// Insert a nonzero key into an LDS open-addressing region; returns 1 if it
+// was not present.  Same read-before-CAS rule as count_insert.
+__device__ __forceinline__ uint32_t lds_insert(uint64_t* tab, uint32_t slot, uint32_t base,
+                                               uint32_t end, uint64_t f) {
+    for (;;) {
+        uint64_t cur = *reinterpret_cast<volatile uint64_t*>(&tab[slot]);
+        if (cur == f) return 0u;
+        if (cur == 0) {
+            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot]), 0ull,
+                                               static_cast<unsigned long long>(f));
+            if (old == 0ull) return 1u;
+            if (old == f) return 0u;
+        }
+        if (++slot == end) slot = base;
     }
 }
 

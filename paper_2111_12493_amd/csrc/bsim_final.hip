@@ -47,15 +47,21 @@ __global__ void __launch_bounds__(kBlock) k_fin_insert(const uint64_t* __restric
     if (key == 0) {
         slot = mask + 1;
     } else {
+        // read before CAS: many vertices share a hash (see count_insert)
         slot = static_cast<uint32_t>(key) & mask;
         for (;;) {
-            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot].key),
-                                               0ull, static_cast<unsigned long long>(key));
-            if (old == 0ull || old == key) break;
+            const uint64_t cur = tab[slot].key;
+            if (cur == key) break;
+            if (cur == 0) {
+                unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot].key),
+                                                   0ull, static_cast<unsigned long long>(key));
+                if (old == 0ull || old == key) break;
+            }
             slot = (slot + 1) & mask;
         }
     }
-    atomicMin(&tab[slot].minv, v);
+    // the smallest vertex only decreases, so skip the atomic once it is below v
+    if (tab[slot].minv > v) atomicMin(&tab[slot].minv, v);
     slot_of[v] = slot;
 }
 
@@ -68,26 +74,47 @@ __global__ void __launch_bounds__(kBlock) k_fin_rep(const uint8_t* __restrict__ 
     rep[v] = (!alive || alive[v]) && tab[slot_of[v]].minv == v ? 1u : 0u;
 }
 
+// Block ids, and block sizes counted in an LDS table per block of
+// kIdsPerBlock vertices first, so a block holding millions of vertices
+// costs one global atomic per thread block rather than one per vertex.
+constexpr int kIdsPerThread = 8;
+constexpr int kIdsPerBlock = kBlock * kIdsPerThread;
+constexpr int kIdsSlots = 2 * kIdsPerBlock;
+
 __global__ void __launch_bounds__(kBlock) k_fin_ids(const uint8_t* __restrict__ alive, uint32_t n,
                                                     const FinSlot* __restrict__ tab,
                                                     const uint32_t* __restrict__ slot_of,
                                                     const uint32_t* __restrict__ rank,
                                                     uint32_t* __restrict__ block_ids,
                                                     uint32_t* __restrict__ sizes) {
-    uint32_t v = blockIdx.x * kBlock + threadIdx.x;
-    uint32_t bid = 0xFFFFFFFFu;
-    if (v < n && (!alive || alive[v])) bid = rank[tab[slot_of[v]].minv];
-    if (v < n) block_ids[v] = bid;
-    // one atomic per run of lanes sharing a block (common for big blocks)
-    const uint32_t lane = lane_id();
-    uint32_t prev = static_cast<uint32_t>(__shfl_up(static_cast<int>(bid), 1, 64));
-    bool head = (lane == 0) || prev != bid;
-    uint64_t heads = __ballot(head);
-    if (bid != 0xFFFFFFFFu && head) {
-        uint64_t later = heads & ~((2ull << lane) - 1);  // heads above this lane
-        uint32_t end = later ? static_cast<uint32_t>(__ffsll(static_cast<long long>(later)) - 1) : 64u;
-        atomicAdd(&sizes[bid], end - lane);
+    __shared__ uint32_t s_key[kIdsSlots];
+    __shared__ uint32_t s_cnt[kIdsSlots];
+    for (int i = threadIdx.x; i < kIdsSlots; i += kBlock) {
+        s_key[i] = 0xFFFFFFFFu;
+        s_cnt[i] = 0;
     }
+    __syncthreads();
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kIdsPerBlock;
+    for (int r = 0; r < kIdsPerThread; r++) {
+        const uint64_t vv = base + static_cast<uint64_t>(r) * kBlock + threadIdx.x;
+        if (vv >= n) break;
+        const uint32_t v = static_cast<uint32_t>(vv);
+        uint32_t bid = 0xFFFFFFFFu;
+        if (!alive || alive[v]) bid = rank[tab[slot_of[v]].minv];
+        block_ids[v] = bid;
+        if (bid == 0xFFFFFFFFu) continue;
+        uint32_t slot = (bid * 2654435761u) & (kIdsSlots - 1);
+        for (;;) {
+            uint32_t cur = s_key[slot];
+            if (cur == 0xFFFFFFFFu) cur = atomicCAS(&s_key[slot], 0xFFFFFFFFu, bid);
+            if (cur == 0xFFFFFFFFu || cur == bid) break;
+            slot = (slot + 1) & (kIdsSlots - 1);
+        }
+        atomicAdd(&s_cnt[slot], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kIdsSlots; i += kBlock)
+        if (s_cnt[i]) atomicAdd(&sizes[s_key[i]], s_cnt[i]);
 }
 
 // ------------------------------------------------------------ edge keys
@@ -261,7 +288,9 @@ void finalize(const Staged& g, const uint64_t* h, uint32_t tab_slots, bool want_
     out.n_blocks = nb;
     out.block_sizes = keep.alloc<uint32_t>(nb);
     hip_check(hipMemsetAsync(out.block_sizes, 0, static_cast<size_t>(nb) * 4 + 4, s), "sizes");
-    if (n) k_fin_ids<<<gb, kBlock, 0, s>>>(g.alive, n, tab, slot_of, rank, out.block_ids, out.block_sizes);
+    if (n)
+        k_fin_ids<<<ceil_div(n, kIdsPerBlock), kBlock, 0, s>>>(g.alive, n, tab, slot_of, rank, out.block_ids,
+                                                              out.block_sizes);
     hip_check(hipGetLastError(), "finalize launch");
     out.n_se = 0;
     if (!want_edges || g.m == 0) {

@@ -34,8 +34,10 @@ constexpr uint64_t kCE = mix64(4);  // per-pair domain
 // out-edges are contiguous in the CSR.  A tile holds at most kTileMaxVerts
 // vertices and fewer than 2 * kTileQuota edges, so its per-vertex
 // de-duplication tables (two slots per edge) fit one block's LDS.  Vertices
-// with more than kTileQuota out-edges ("hubs") are split by the high bits of
-// their pair hashes into buckets that each fit the same LDS table.
+// with more than kTileQuota out-edges ("hubs") are cut into chunks of
+// kTileMaxEdges edges; the chunks of one hub de-duplicate into a shared
+// region of 2*d slots of a global table, and the hub's last chunk block
+// finishes its hash and clears the region for the next launch.
 
 constexpr int kBlock = 256;              // threads per block (4 wave64s)
 constexpr int kTileQuota = 1024;         // tile boundaries every kTileQuota edges
@@ -43,8 +45,6 @@ constexpr int kTileMaxEdges = 2 * kTileQuota;
 constexpr int kTileMaxVerts = 256;
 constexpr int kEdgesPerThread = kTileMaxEdges / kBlock;  // 8
 constexpr int kTableSlots = 2 * kTileMaxEdges;           // 4096 x 8 B = 32 KiB
-constexpr int kHubBucketTarget = 1536;   // expected distinct keys per hub bucket
-constexpr int kHubTableLimit = 3584;     // re-split a hub bucket beyond this
 constexpr uint32_t kHubMinDegree = kTileQuota + 1;
 constexpr int kStripes = 64;             // striped block counters per iteration
 constexpr int kStripeRing = 4;
@@ -75,10 +75,12 @@ struct IterArgs {
     const uint8_t* alive;   // nullable
     const uint32_t* tile_v0;
     const uint32_t* tile_v1;
-    const uint32_t* hb_hub;     // hub block -> hub index
-    const uint32_t* hb_bucket;  // hub block -> bucket
+    const uint32_t* hc_hub;     // hub chunk block -> hub index
+    const uint32_t* hc_e0;      // hub chunk block -> first edge
     const uint32_t* hub_v;
-    const uint32_t* hub_logb;
+    const uint32_t* hub_nchunks;
+    const uint64_t* hub_tab_off;  // first slot of the hub's region in hub_tab
+    uint64_t* hub_tab;            // 2*d slots per hub, all zero between launches
     uint64_t* hub_acc;
     uint32_t* hub_done;
     uint64_t* tab_ins;      // count table receiving h^k (keys only, 0 = empty)
@@ -89,7 +91,7 @@ struct IterArgs {
     uint32_t* totals;       // totals[k] = n_k
     RunStatus* status;
     uint32_t n_tiles;
-    uint32_t n_hub_blocks;
+    uint32_t n_hub_chunks;
     uint32_t tab_mask;
     uint32_t k;
     uint32_t k_max;
@@ -184,11 +186,13 @@ struct Staged {
     uint32_t* tile_v0 = nullptr;
     uint32_t* tile_v1 = nullptr;
     uint32_t n_hubs = 0;
-    uint32_t n_hub_blocks = 0;
+    uint32_t n_hub_chunks = 0;
     uint32_t* hub_v = nullptr;
-    uint32_t* hub_logb = nullptr;
-    uint32_t* hb_hub = nullptr;
-    uint32_t* hb_bucket = nullptr;
+    uint32_t* hub_nchunks = nullptr;
+    uint64_t* hub_tab_off = nullptr;
+    uint64_t hub_tab_slots = 0;
+    uint32_t* hc_hub = nullptr;
+    uint32_t* hc_e0 = nullptr;
     std::vector<uint32_t> host_hub_v;       // hub vertices, by degree descending
     std::vector<uint32_t> host_hub_deg;
 };
@@ -210,6 +214,7 @@ struct RunBuffers {
     uint32_t k_cap = 0;
     uint64_t* hub_acc = nullptr;
     uint32_t* hub_done = nullptr;
+    uint64_t* hub_tab = nullptr;
     RunStatus* status = nullptr;
 };
 

@@ -9,9 +9,10 @@
 //     vertex in a per-vertex open-addressing region of an LDS table
 //     (MergeMessages' hash table), sums the mixed distinct keys per vertex
 //     (the order-independent Hash), and writes h^k; or
-//   * a hub bucket block: the same for the pair keys of one hub whose top
-//     hash bits equal the block's bucket; partial sums meet in a global
-//     accumulator and the last bucket block of a hub finishes it.
+//   * a hub chunk block: the same for up to kTileMaxEdges edges of one hub,
+//     de-duplicating into the hub's region of a global table; partial sums
+//     meet in a global accumulator and the hub's last chunk block finishes
+//     the hash and clears the region.
 // Every new h^k is inserted into a key-only count table; the number of new
 // keys is n_k, the block count of the k-partition.  The launch after the
 // one where n_k == n_{k-1} (or k > k_max) sets a sticky done flag and every
@@ -102,20 +103,11 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S) {
                 const uint32_t i = S.seg[j];
                 const uint32_t base = 2 * S.off[i];
                 const uint32_t span = 2 * (S.off[i + 1] - S.off[i]);
-                uint32_t slot = base + static_cast<uint32_t>(
-                                           (static_cast<uint64_t>(static_cast<uint32_t>(f)) * span) >> 32);
-                for (;;) {
-                    unsigned long long old = atomicCAS(
-                        reinterpret_cast<unsigned long long*>(&S.tab[slot]), 0ull,
-                        static_cast<unsigned long long>(f));
-                    if (old == 0ull) {
-                        atomicAdd(reinterpret_cast<unsigned long long*>(&S.acc[i]),
-                                  static_cast<unsigned long long>(f));
-                        break;
-                    }
-                    if (old == f) break;
-                    if (++slot == base + span) slot = base;
-                }
+                const uint32_t slot = base + static_cast<uint32_t>(
+                                                 (static_cast<uint64_t>(static_cast<uint32_t>(f)) * span) >> 32);
+                if (lds_insert(S.tab, slot, base, base + span, f))
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&S.acc[i]),
+                              static_cast<unsigned long long>(f));
             }
         }
     }
@@ -135,78 +127,82 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S) {
     if (tid == 0) add_block_count(a.stripes, a.k, c);
 }
 
-template <typename LabT>
-__device__ void hub_block(const IterArgs& a, uint32_t blk, IterShared& S) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t hi = a.hb_hub[blk];
-    const uint32_t bucket = a.hb_bucket[blk];
-    const uint32_t v = a.hub_v[hi];
-    const uint32_t logb = a.hub_logb[hi];
-    const uint32_t e0 = a.row_off[v];
-    const uint32_t d = a.row_off[v + 1] - e0;
-    const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
-    volatile uint32_t* ctl = S.ctl;
-
-    uint64_t sum = 0;
-    for (uint32_t extra = 0;; extra++) {
-        sum = 0;
-        bool overflow = false;
-        const uint32_t bits = logb + extra;
-        for (uint32_t sub = 0; sub < (1u << extra) && !overflow; sub++) {
-            const uint64_t want = (static_cast<uint64_t>(bucket) << extra) | sub;
-            for (uint32_t j = tid; j < kTableSlots; j += kBlock) S.tab[j] = 0;
-            if (tid == 0) {
-                ctl[1] = 0;  // reserved slots
-                ctl[2] = 0;  // overflow
-            }
-            __syncthreads();
-            for (uint32_t j = tid; j < d; j += kBlock) {
-                if (ctl[2]) break;
-                const uint32_t e = e0 + j;
-                const uint64_t f =
-                    mix64(a.h_prev[a.tgt[e]] ^ a.salt[static_cast<uint32_t>(lab[e])] ^ kCE);
-                if (f == 0) continue;
-                if (bits && (f >> (64 - bits)) != want) continue;
-                // reserve a slot first so the table can never fill up
-                if (atomicAdd(const_cast<uint32_t*>(&ctl[1]), 1u) >= static_cast<uint32_t>(kHubTableLimit)) {
-                    ctl[2] = 1;
-                    break;
-                }
-                uint32_t slot = static_cast<uint32_t>(f) & (kTableSlots - 1);
-                for (;;) {
-                    unsigned long long old = atomicCAS(
-                        reinterpret_cast<unsigned long long*>(&S.tab[slot]), 0ull,
-                        static_cast<unsigned long long>(f));
-                    if (old == 0ull) {
-                        sum += f;
-                        break;
-                    }
-                    if (old == f) {
-                        atomicSub(const_cast<uint32_t*>(&ctl[1]), 1u);
-                        break;
-                    }
-                    slot = (slot + 1) & (kTableSlots - 1);
-                }
-            }
-            __syncthreads();
-            overflow = ctl[2] != 0;
-            __syncthreads();
+// Insert a nonzero key into a region [base, base+span) of a global table;
+// returns 1 if it was not present.  Read before CAS as in count_insert.
+__device__ __forceinline__ uint32_t global_region_insert(uint64_t* tab, uint64_t base, uint32_t span,
+                                                         uint64_t f) {
+    uint32_t off = static_cast<uint32_t>((static_cast<uint64_t>(static_cast<uint32_t>(f)) * span) >> 32);
+    for (;;) {
+        uint64_t* p = tab + base + off;
+        const uint64_t cur = *p;
+        if (cur == f) return 0u;
+        if (cur == 0) {
+            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(p), 0ull,
+                                               static_cast<unsigned long long>(f));
+            if (old == 0ull) return 1u;
+            if (old == f) return 0u;
         }
-        if (!overflow) break;
+        if (++off == span) off = 0;
+    }
+}
+
+template <typename LabT>
+__device__ void hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t hi = a.hc_hub[blk];
+    const uint32_t e0 = a.hc_e0[blk];
+    const uint32_t v = a.hub_v[hi];
+    const uint32_t vbeg = a.row_off[v], vend = a.row_off[v + 1];
+    const uint32_t ne = min(static_cast<uint32_t>(kTileMaxEdges), vend - e0);
+    const uint32_t span = 2 * (vend - vbeg);
+    const uint64_t base = a.hub_tab_off[hi];
+    const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
+
+    uint32_t w[kEdgesPerThread];
+    uint32_t l[kEdgesPerThread];
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        if (j < ne) {
+            w[r] = a.tgt[e0 + j];
+            l[r] = static_cast<uint32_t>(lab[e0 + j]);
+        }
+    }
+    uint64_t hv[kEdgesPerThread];
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        if (j < ne) hv[r] = a.h_prev[w[r]] ^ a.salt[l[r]];
+    }
+    uint64_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        if (j < ne) {
+            const uint64_t f = mix64(hv[r] ^ kCE);
+            if (f != 0 && global_region_insert(a.hub_tab, base, span, f)) sum += f;
+        }
     }
     const uint64_t bsum = block_sum_u64(sum, S.red64);
     if (tid == 0) {
         __hip_atomic_fetch_add(&a.hub_acc[hi], bsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t prev =
             __hip_atomic_fetch_add(&a.hub_done[hi], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev + 1 == (1u << logb)) {
-            const uint64_t s = __hip_atomic_load(&a.hub_acc[hi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t h = mix64(a.t[v] ^ mix64(kCS + s));
+        const uint32_t last = (prev + 1 == a.hub_nchunks[hi]) ? 1u : 0u;
+        S.ctl[3] = last;
+        if (last) {
+            const uint64_t acc = __hip_atomic_load(&a.hub_acc[hi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t h = mix64(a.t[v] ^ mix64(kCS + acc));
             a.h_next[v] = h;
             add_block_count(a.stripes, a.k, count_insert(a.tab_ins, a.tab_mask, a.zflag_ins, h));
             a.hub_acc[hi] = 0;
             a.hub_done[hi] = 0;
         }
+    }
+    __syncthreads();
+    if (S.ctl[3]) {
+        // every chunk of this hub has inserted: clear its region for the next launch
+        for (uint32_t j = tid; j < span; j += kBlock) a.hub_tab[base + j] = 0;
     }
 }
 
@@ -251,10 +247,10 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
         for (uint64_t j = lo + tid; j < hi; j += kBlock) a.tab_clr[j] = 0;
     }
 
-    if (blockIdx.x < a.n_hub_blocks)
-        hub_block<LabT>(a, blockIdx.x, S);
-    else if (blockIdx.x - a.n_hub_blocks < a.n_tiles)
-        tile_block<LabT>(a, blockIdx.x - a.n_hub_blocks, S);
+    if (blockIdx.x < a.n_hub_chunks)
+        hub_chunk_block<LabT>(a, blockIdx.x, S);
+    else if (blockIdx.x - a.n_hub_chunks < a.n_tiles)
+        tile_block<LabT>(a, blockIdx.x - a.n_hub_chunks, S);
 }
 
 }  // namespace
@@ -279,6 +275,7 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
     rb.totals = arena.alloc<uint32_t>(rb.k_cap);
     rb.hub_acc = arena.alloc<uint64_t>(g.n_hubs + 1);
     rb.hub_done = arena.alloc<uint32_t>(g.n_hubs + 1);
+    rb.hub_tab = arena.alloc<uint64_t>(g.hub_tab_slots + 1);
     rb.status = arena.alloc<RunStatus>(1);
     hip_check(hipMemsetAsync(rb.tab[0], 0, (2 * static_cast<size_t>(cap) + 2) * 8, s), "clear tables");
     hip_check(hipMemsetAsync(rb.zflag, 0, 2 * 4, s), "clear flags");
@@ -286,6 +283,7 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
     hip_check(hipMemsetAsync(rb.totals, 0, rb.k_cap * 4, s), "clear totals");
     hip_check(hipMemsetAsync(rb.hub_acc, 0, (g.n_hubs + 1) * 8, s), "clear hub acc");
     hip_check(hipMemsetAsync(rb.hub_done, 0, (g.n_hubs + 1) * 4, s), "clear hub done");
+    hip_check(hipMemsetAsync(rb.hub_tab, 0, (g.hub_tab_slots + 1) * 8, s), "clear hub table");
     hip_check(hipMemsetAsync(rb.status, 0, sizeof(RunStatus), s), "clear status");
 }
 
@@ -310,10 +308,12 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.alive = g.alive;
     a.tile_v0 = g.tile_v0;
     a.tile_v1 = g.tile_v1;
-    a.hb_hub = g.hb_hub;
-    a.hb_bucket = g.hb_bucket;
+    a.hc_hub = g.hc_hub;
+    a.hc_e0 = g.hc_e0;
     a.hub_v = g.hub_v;
-    a.hub_logb = g.hub_logb;
+    a.hub_nchunks = g.hub_nchunks;
+    a.hub_tab_off = g.hub_tab_off;
+    a.hub_tab = rb.hub_tab;
     a.hub_acc = rb.hub_acc;
     a.hub_done = rb.hub_done;
     a.tab_ins = rb.tab[k & 1];
@@ -324,12 +324,12 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.totals = rb.totals;
     a.status = rb.status;
     a.n_tiles = g.n_tiles;
-    a.n_hub_blocks = g.n_hub_blocks;
+    a.n_hub_chunks = g.n_hub_chunks;
     a.tab_mask = rb.tab_mask;
     a.k = k;
     a.k_max = k_max;
     a.stop = stop ? 1u : 0u;
-    const uint32_t grid = std::max<uint32_t>(g.n_hub_blocks + g.n_tiles, 1);
+    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_tiles, 1);
     if (g.label_bytes == 2)
         k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
     else

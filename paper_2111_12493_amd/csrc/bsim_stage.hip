@@ -11,8 +11,8 @@
 //     starts of a tile lie in one kTileQuota window of edges and its last
 //     vertex has at most kTileQuota edges, so a tile holds < 2 kTileQuota
 //     edges;
-//   * a hub of degree d is split into 2^b buckets by the top b bits of its
-//     pair hashes, with 2^b >= d / kHubBucketTarget.
+//   * a hub of degree d is cut into chunks of kTileMaxEdges edges and owns a
+//     region of 2*d slots of a global de-duplication table.
 #include <algorithm>
 #include <numeric>
 
@@ -142,7 +142,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_vertices(
     const uint8_t* __restrict__ alive, uint32_t n, uint64_t m, uint32_t* __restrict__ bnd,
     uint32_t* __restrict__ hubf, RunStatus* status) {
     uint32_t v = blockIdx.x * kBlock + threadIdx.x;
-    if (v >= n) return;
+    const bool in = v < n;
+    if (!in) v = n - 1;  // inactive lanes mirror the last vertex and store nothing
     uint32_t a = row_off[v], b = row_off[v + 1];
     uint32_t err = 0;
     if (b < a) err |= kErrInvalid;
@@ -152,7 +153,17 @@ __global__ void __launch_bounds__(kBlock) k_stage_vertices(
     uint32_t d = b - a;
     if (alive && !alive[v] && (d != 0)) err |= kErrInvalid;
     uint32_t nt = type_off[v + 1] - type_off[v];
-    if (nt) atomicMax(&status->max_types, nt);
+    // one atomic per block: same-address atomics from every wave would serialize
+    __shared__ uint32_t s_max[kBlock / 64];
+    uint32_t wmax = in ? nt : 0;
+    for (int dd = 32; dd >= 1; dd >>= 1)
+        wmax = max(wmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(wmax), dd, 64)));
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = wmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; i++) wmax = max(wmax, s_max[i]);
+        if (wmax) atomicMax(&status->max_types, wmax);
+    }
     bool hub = (b >= a) && d > static_cast<uint32_t>(kTileQuota);
     bool prev_hub = false;
     bool cross = false;
@@ -161,9 +172,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_vertices(
         prev_hub = (a >= pa) && (a - pa) > static_cast<uint32_t>(kTileQuota);
         cross = (a / kTileQuota) != (pa / kTileQuota);
     }
-    bnd[v] = (v == 0 || hub || prev_hub || cross || (v % kTileMaxVerts) == 0) ? 1u : 0u;
-    hubf[v] = hub ? 1u : 0u;
-    if (err) atomicOr(&status->error, err);
+    if (in) {
+        bnd[v] = (v == 0 || hub || prev_hub || cross || (v % kTileMaxVerts) == 0) ? 1u : 0u;
+        hubf[v] = hub ? 1u : 0u;
+        if (err) atomicOr(&status->error, err);
+    }
 }
 
 template <typename LabT>
@@ -179,12 +192,22 @@ __global__ void __launch_bounds__(kBlock) k_stage_edges(const uint32_t* __restri
         else if (alive && !alive[w]) err |= kErrInvalid;
         mx = max(mx, static_cast<uint32_t>(lab[e]));
     }
-    // wave-reduce before touching global memory
+    // reduce over the block before touching global memory
+    __shared__ uint32_t s_mx[kBlock / 64], s_err[kBlock / 64];
     for (int d = 32; d >= 1; d >>= 1) {
         mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), d, 64)));
         err |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(err), d, 64));
     }
     if ((threadIdx.x & 63) == 0) {
+        s_mx[threadIdx.x >> 6] = mx;
+        s_err[threadIdx.x >> 6] = err;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; i++) {
+            mx = max(mx, s_mx[i]);
+            err |= s_err[i];
+        }
         if (mx) atomicMax(&status->max_label, mx);
         if (err) atomicOr(&status->error, err);
     }
@@ -224,6 +247,13 @@ __global__ void __launch_bounds__(kBlock) k_hub_degrees(const uint32_t* __restri
     if (i < nh) deg[i] = row_off[hubs[i] + 1] - row_off[hubs[i]];
 }
 
+__global__ void __launch_bounds__(kBlock) k_hub_starts(const uint32_t* __restrict__ row_off,
+                                                        const uint32_t* __restrict__ hubs,
+                                                        uint32_t nh, uint32_t* __restrict__ start) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < nh) start[i] = row_off[hubs[i]];
+}
+
 __global__ void __launch_bounds__(kBlock) k_salt(uint64_t* salt, uint32_t count) {
     uint32_t l = blockIdx.x * kBlock + threadIdx.x;
     if (l < count) salt[l] = mix64(kCL + static_cast<uint64_t>(l));
@@ -243,7 +273,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         k_stage_vertices<<<ceil_div(n, kBlock), kBlock, 0, s>>>(g.row_off, g.type_off, g.alive, n,
                                                                 g.m, bnd, hubf, status_dev);
         if (g.m > 0) {
-            uint32_t nbk = std::min<uint64_t>(ceil_div(g.m, kBlock), 8192);
+            uint32_t nbk = std::min<uint64_t>(ceil_div(g.m, kBlock), 2048);
             if (g.label_bytes == 2)
                 k_stage_edges<uint16_t><<<nbk, kBlock, 0, s>>>(
                     g.tgt, static_cast<const uint16_t*>(g.lab), g.alive, n, g.m, status_dev);
@@ -309,33 +339,47 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
             return g.host_hub_deg[a] > g.host_hub_deg[b];
         });
-        std::vector<uint32_t> hv(g.n_hubs), hd(g.n_hubs), hl(g.n_hubs);
-        std::vector<uint32_t> bh, bb;
+        std::vector<uint32_t> hv(g.n_hubs), hd(g.n_hubs), hn(g.n_hubs);
+        std::vector<uint64_t> ho(g.n_hubs);
+        std::vector<uint32_t> ch, ce;
+        std::vector<uint32_t> hstart(g.n_hubs);
+        uint64_t slots = 0;
         for (uint32_t i = 0; i < g.n_hubs; i++) {
             hv[i] = g.host_hub_v[order[i]];
             hd[i] = g.host_hub_deg[order[i]];
-            uint32_t want = ceil_div(hd[i], kHubBucketTarget);
-            uint32_t logb = static_cast<uint32_t>(bit_width(next_pow2(want)) - 1);
-            hl[i] = logb;
-            for (uint32_t b = 0; b < (1u << logb); b++) {
-                bh.push_back(i);
-                bb.push_back(b);
-            }
+            hn[i] = ceil_div(hd[i], kTileMaxEdges);
+            ho[i] = slots;
+            slots += 2 * static_cast<uint64_t>(hd[i]);
         }
+        // first edge of every hub, then its chunks (largest hubs first)
+        uint32_t* hs_dev = arena.alloc<uint32_t>(g.n_hubs);
+        uint32_t* hv_dev = arena.alloc<uint32_t>(g.n_hubs);
+        hip_check(hipMemcpyAsync(hv_dev, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, s), "hub v");
+        k_hub_starts<<<ceil_div(g.n_hubs, kBlock), kBlock, 0, s>>>(g.row_off, hv_dev, g.n_hubs, hs_dev);
+        hip_check(hipMemcpyAsync(hstart.data(), hs_dev, g.n_hubs * 4, hipMemcpyDeviceToHost, s), "hub starts");
+        hip_check(hipStreamSynchronize(s), "hub starts sync");
+        for (uint32_t i = 0; i < g.n_hubs; i++)
+            for (uint32_t c = 0; c < hn[i]; c++) {
+                ch.push_back(i);
+                ce.push_back(hstart[i] + c * kTileMaxEdges);
+            }
         g.host_hub_v = hv;
         g.host_hub_deg = hd;
-        g.n_hub_blocks = static_cast<uint32_t>(bh.size());
-        g.hub_v = arena.alloc<uint32_t>(g.n_hubs);
-        g.hub_logb = arena.alloc<uint32_t>(g.n_hubs);
-        g.hb_hub = arena.alloc<uint32_t>(g.n_hub_blocks);
-        g.hb_bucket = arena.alloc<uint32_t>(g.n_hub_blocks);
-        hip_check(hipMemcpyAsync(g.hub_v, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, s), "hub v");
-        hip_check(hipMemcpyAsync(g.hub_logb, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s), "hub b");
-        hip_check(hipMemcpyAsync(g.hb_hub, bh.data(), bh.size() * 4, hipMemcpyHostToDevice, s), "hub blk");
-        hip_check(hipMemcpyAsync(g.hb_bucket, bb.data(), bb.size() * 4, hipMemcpyHostToDevice, s), "hub bkt");
+        g.n_hub_chunks = static_cast<uint32_t>(ch.size());
+        g.hub_tab_slots = slots;
+        g.hub_v = hv_dev;
+        g.hub_nchunks = arena.alloc<uint32_t>(g.n_hubs);
+        g.hub_tab_off = arena.alloc<uint64_t>(g.n_hubs);
+        g.hc_hub = arena.alloc<uint32_t>(g.n_hub_chunks);
+        g.hc_e0 = arena.alloc<uint32_t>(g.n_hub_chunks);
+        hip_check(hipMemcpyAsync(g.hub_nchunks, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, s), "hub n");
+        hip_check(hipMemcpyAsync(g.hub_tab_off, ho.data(), ho.size() * 8, hipMemcpyHostToDevice, s), "hub off");
+        hip_check(hipMemcpyAsync(g.hc_hub, ch.data(), ch.size() * 4, hipMemcpyHostToDevice, s), "hub chunks");
+        hip_check(hipMemcpyAsync(g.hc_e0, ce.data(), ce.size() * 4, hipMemcpyHostToDevice, s), "hub chunk e0");
         hip_check(hipStreamSynchronize(s), "hub schedule sync");
     } else {
-        g.n_hub_blocks = 0;
+        g.n_hub_chunks = 0;
+        g.hub_tab_slots = 0;
     }
 
     // label salts

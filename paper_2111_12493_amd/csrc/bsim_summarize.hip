@@ -93,6 +93,13 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming), "event");
     bool done = false;
+    std::vector<hipEvent_t> timers;  // (start, end) per launch when timing launches
+    struct TimerGuard {
+        std::vector<hipEvent_t>& t;
+        ~TimerGuard() {
+            for (hipEvent_t e : t) (void)hipEventDestroy(e);
+        }
+    } timer_guard{timers};
     try {
         while (!done) {
             if (k <= k_last) {
@@ -105,7 +112,18 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                         rb.h[(kk - 1) & 1] = sink->levels[std::min(kk - 1, top)];
                         rb.h[kk & 1] = sink->levels[std::min(kk, top)];
                     }
-                    launch_iteration(g, rb, kk, p.k_max, stop, s);
+                    if (ctx->time_launches) {
+                        hipEvent_t a, b;
+                        hip_check(hipEventCreate(&a), "event");
+                        hip_check(hipEventCreate(&b), "event");
+                        timers.push_back(a);
+                        timers.push_back(b);
+                        hip_check(hipEventRecord(a, s), "event");
+                        launch_iteration(g, rb, kk, p.k_max, stop, s);
+                        hip_check(hipEventRecord(b, s), "event");
+                    } else {
+                        launch_iteration(g, rb, kk, p.k_max, stop, s);
+                    }
                     lr.launches++;
                 }
                 const int slot = pending < 0 ? 0 : (pending ^ 1);
@@ -133,6 +151,11 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipStreamSynchronize(s), "loop sync");
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
+    for (size_t i = 0; i + 1 < timers.size(); i += 2) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, timers[i], timers[i + 1]), "launch timer");
+        lr.ms_kernels += ms;
+    }
     RunStatus st;
     hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
     lr.k_done = st.k_done;
@@ -163,6 +186,7 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
     r->n_blocks = fo.n_blocks;
     r->n_summary_edges = fo.n_se;
     r->n_iter_launches = lr.launches;
+    r->ms_iter_kernels = lr.ms_kernels;
     r->blocks_per_iter = p->blocks_per_iter.data();
     uint64_t* hashes = keep.alloc<uint64_t>(g.n);
     if (g.n) hip_check(hipMemcpyAsync(hashes, h, static_cast<size_t>(g.n) * 8, hipMemcpyDeviceToDevice, s),

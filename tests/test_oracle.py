@@ -54,6 +54,17 @@ def test_mixer_is_a_bijection():
         assert x == z
 
 
+def test_refinement_step_follows_the_definition():
+    # Sec. 2.5: k-bisimilar requires (k-1)-bisimilar.  Equal hashes in
+    # different previous classes stay apart; first-occurrence numbering.
+    out, nb = orc.refine_classes([0, 1, 0, 1, 2], [7, 7, 9, 7, 7])
+    assert list(out) == [0, 1, 2, 1, 3] and nb == 4
+    out, nb = orc.refine_classes([0, 1], [7, 7])
+    assert list(out) == [0, 1] and nb == 2
+    out, nb = orc.refine_classes([3, 3, 3], [5, 5, 5], alive=np.array([1, 0, 1], np.uint8))
+    assert list(out) == [0, 0xFFFFFFFF, 0] and nb == 1
+
+
 def test_type_hash_is_a_set_function():
     # order and repeats of type ids do not matter; different sets differ
     a = orc.type_hash([3, 1, 2])

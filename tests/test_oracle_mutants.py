@@ -20,16 +20,16 @@ MUTANTS = {
                             "keys[i] = h_prev[tgt[i]];"),
     "no_key_dedupe": ("size_t u = unique_u64(keys, (size_t)deg);",
                       "size_t u = (size_t)deg; qsort(keys, u, 8, cmp_u64);"),
-    "drop_own_type": ("return bo_mix(t_v ^ bo_mix(cs + sum));",
-                      "return bo_mix(bo_mix(cs + sum));"),
     "wrong_gather_index": ("keys[i] = h_prev[tgt[i]] ^ bo_label_salt(lab[i]);",
                            "keys[i] = h_prev[tgt[0]] ^ bo_label_salt(lab[i]);"),
     "no_type_dedupe": ("size_t u = unique_u32(tmp, n_types);",
                        "size_t u = n_types;"),
     "fixpoint_off_by_one": ("if (blocks_per_iter[k] == blocks_per_iter[k - 1]) {",
                             "if (k > 1 && blocks_per_iter[k - 1] == blocks_per_iter[k - 2]) {"),
-    "hash_classes_not_grouped": ("uint32_t m = (i > 0 && p[i].h == p[i - 1].h) ? minv[p[i - 1].v] : p[i].v;",
+    "hash_classes_not_grouped": ("uint32_t m = same ? minv[p[i - 1].v] : p[i].v;",
                                  "uint32_t m = p[i].v;"),
+    "previous_class_ignored": ("int same = i > 0 && p[i].c == p[i - 1].c && p[i].h == p[i - 1].h;",
+                               "int same = i > 0 && p[i].h == p[i - 1].h;"),
     "blocks_numbered_by_largest_vertex": ("for (uint32_t v = 0; v < n; v++)\n        if (is_min[v]) rank[v] = nb++;",
                                           "for (uint32_t v = n; v-- > 0;)\n        if (is_min[v]) rank[v] = nb++;"),
     "summary_edge_transposed": ("tr[ne].d = block_ids[tgt[e]];",
@@ -41,6 +41,10 @@ MUTANTS = {
 # pin the values themselves ("parity unpinned" for raw hash values); these
 # cases document that blind spot instead of hiding it.
 UNPINNED_VALUE_MUTANTS = {
+    # the type set already lives in the previous class, so dropping t(v) from
+    # h^k changes the values only
+    "drop_own_type": ("return bo_mix(t_v ^ bo_mix(cs + sum));",
+                      "return bo_mix(bo_mix(cs + sum));"),
     "sum_replaced_by_xor": ("for (size_t i = 0; i < u; i++) sum += bo_mix(keys[i] ^ ce);",
                             "for (size_t i = 0; i < u; i++) sum ^= bo_mix(keys[i] ^ ce);"),
 }
@@ -73,6 +77,14 @@ def _pins_hold() -> bool:
             es = list(zip(r["se_src"].tolist(), r["se_label"].tolist(), r["se_dst"].tolist()))
             if es != exact.quotient_edges(g, levels[kd]):
                 return False
+        # refinement keeps classes apart even when their hashes coincide
+        # (the k-class is the pair (class at k-1, h^k), Sec. 2.5 definition)
+        out, nb = orc.refine_classes([0, 1, 0, 1], [7, 7, 9, 7])
+        if list(out) != [0, 1, 2, 1] or nb != 3:
+            return False
+        out, nb = orc.refine_classes([0, 1], [7, 7])
+        if list(out) != [0, 1] or nb != 2:
+            return False
         # a graph whose vertex has many equal keys: the mixer-sum must see a set
         g = gg.from_edges(5, [0, 0, 0, 1], [2, 3, 4, 2], [0, 0, 0, 0], types=[[]] * 5)
         r = orc.summarize(g, 3, True, True)
