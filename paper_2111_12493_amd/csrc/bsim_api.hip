@@ -35,6 +35,7 @@ int bsim_ctx_create(int device, void* hip_stream, bsim_ctx** out) {
     if (!c) return BSIM_E_NOMEM;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    c->hub_table_slots = query_hub_table_slots(device);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->status_host), 4 * sizeof(RunStatus),
                       hipHostMallocDefault) != hipSuccess) {
         delete c;

@@ -13,6 +13,7 @@ struct bsim_ctx {
     bsim::RunStatus* status_host = nullptr;  // pinned, 4 entries
     uint32_t chunk_max = 256;
     uint32_t time_launches = 0;
+    uint32_t hub_table_slots = 8192;  // LDS slots per hub-bucket block on this device
 };
 
 namespace bsim {

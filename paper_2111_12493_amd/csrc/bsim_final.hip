@@ -2,14 +2,15 @@
 // ids, count block sizes, and build the summary graph's edges.
 //
 // Algorithm 4 ends with FindAndMerge: vertices with equal final identifiers
-// form one block.  Block ids are numbered by first occurrence (the block of
-// the smallest vertex is 0), which depends only on the partition:
-//   1. insert every alive vertex's hash into an open-addressing table of
-//      (hash, smallest vertex) slots (atomicMin on the vertex);
-//   2. a vertex is its block's representative iff it is the smallest vertex
-//      of its hash; an exclusive scan over representative flags gives each
-//      representative its block id;
-//   3. every vertex takes the id of its representative; sizes by atomics.
+// form one block.  The refinement loop already names every vertex's class
+// by a representative member; block ids are numbered by first occurrence
+// (the block of the smallest vertex is 0), which depends only on the
+// partition:
+//   1. the smallest vertex of each class (atomicMin per class);
+//   2. an exclusive scan over "v is its class's smallest vertex" flags gives
+//      every such vertex its block id;
+//   3. every vertex takes the id of its class's smallest vertex; block sizes
+//      are counted per thread block in LDS first.
 // Summary edges (Sec. 2.6: edges between vertex summaries) are the distinct
 // (block(v), l, block(w)) triples: packed into one 64-bit key per edge,
 // sorted by an LSD radix sort over the used bits, de-duplicated and unpacked.
@@ -19,59 +20,24 @@ namespace bsim {
 
 namespace {
 
-struct FinSlot {
-    uint64_t key;
-    uint32_t minv;
-    uint32_t pad;
-};
-static_assert(sizeof(FinSlot) == 16, "slot layout");
-
-__global__ void __launch_bounds__(kBlock) k_fin_fill(FinSlot* tab, uint32_t slots) {
-    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < slots) {
-        tab[i].key = 0;
-        tab[i].minv = 0xFFFFFFFFu;
-        tab[i].pad = 0;
-    }
-}
-
-// Slot `mask + 1` is reserved for the hash value 0.
-__global__ void __launch_bounds__(kBlock) k_fin_insert(const uint64_t* __restrict__ h,
-                                                       const uint8_t* __restrict__ alive, uint32_t n,
-                                                       FinSlot* tab, uint32_t mask,
-                                                       uint32_t* __restrict__ slot_of) {
+// Smallest vertex of every class (classes are named by their representative).
+__global__ void __launch_bounds__(kBlock) k_fin_min(const uint32_t* __restrict__ rep,
+                                                    const uint8_t* __restrict__ alive, uint32_t n,
+                                                    uint32_t* cmin) {
     uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     if (v >= n || (alive && !alive[v])) return;
-    const uint64_t key = h[v];
-    uint32_t slot;
-    if (key == 0) {
-        slot = mask + 1;
-    } else {
-        // read before CAS: many vertices share a hash (see count_insert)
-        slot = static_cast<uint32_t>(key) & mask;
-        for (;;) {
-            const uint64_t cur = tab[slot].key;
-            if (cur == key) break;
-            if (cur == 0) {
-                unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot].key),
-                                                   0ull, static_cast<unsigned long long>(key));
-                if (old == 0ull || old == key) break;
-            }
-            slot = (slot + 1) & mask;
-        }
-    }
-    // the smallest vertex only decreases, so skip the atomic once it is below v
-    if (tab[slot].minv > v) atomicMin(&tab[slot].minv, v);
-    slot_of[v] = slot;
+    const uint32_t r = rep[v];
+    // the minimum only decreases: skip the atomic once it is below v
+    if (cmin[r] > v) atomicMin(&cmin[r], v);
 }
 
-__global__ void __launch_bounds__(kBlock) k_fin_rep(const uint8_t* __restrict__ alive, uint32_t n,
-                                                    const FinSlot* __restrict__ tab,
-                                                    const uint32_t* __restrict__ slot_of,
-                                                    uint32_t* __restrict__ rep) {
+__global__ void __launch_bounds__(kBlock) k_fin_rep(const uint32_t* __restrict__ rep,
+                                                    const uint8_t* __restrict__ alive, uint32_t n,
+                                                    const uint32_t* __restrict__ cmin,
+                                                    uint32_t* __restrict__ isrep) {
     uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     if (v >= n) return;
-    rep[v] = (!alive || alive[v]) && tab[slot_of[v]].minv == v ? 1u : 0u;
+    isrep[v] = (!alive || alive[v]) && cmin[rep[v]] == v ? 1u : 0u;
 }
 
 // Block ids, and block sizes counted in an LDS table per block of
@@ -82,8 +48,8 @@ constexpr int kIdsPerBlock = kBlock * kIdsPerThread;
 constexpr int kIdsSlots = 2 * kIdsPerBlock;
 
 __global__ void __launch_bounds__(kBlock) k_fin_ids(const uint8_t* __restrict__ alive, uint32_t n,
-                                                    const FinSlot* __restrict__ tab,
-                                                    const uint32_t* __restrict__ slot_of,
+                                                    const uint32_t* __restrict__ rep,
+                                                    const uint32_t* __restrict__ cmin,
                                                     const uint32_t* __restrict__ rank,
                                                     uint32_t* __restrict__ block_ids,
                                                     uint32_t* __restrict__ sizes) {
@@ -100,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_fin_ids(const uint8_t* __restrict__ 
         if (vv >= n) break;
         const uint32_t v = static_cast<uint32_t>(vv);
         uint32_t bid = 0xFFFFFFFFu;
-        if (!alive || alive[v]) bid = rank[tab[slot_of[v]].minv];
+        if (!alive || alive[v]) bid = rank[cmin[rep[v]]];
         block_ids[v] = bid;
         if (bid == 0xFFFFFFFFu) continue;
         uint32_t slot = (bid * 2654435761u) & (kIdsSlots - 1);
@@ -264,32 +230,29 @@ static uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Aren
     return a;
 }
 
-void finalize(const Staged& g, const uint64_t* h, uint32_t tab_slots, bool want_edges,
-              FinalOut& out, Arena& arena, Arena& keep, hipStream_t s) {
-    (void)tab_slots;
+void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& out, Arena& arena,
+              Arena& keep, hipStream_t s) {
     const uint32_t n = g.n;
-    const uint32_t mask = std::max<uint32_t>(next_pow2(static_cast<uint64_t>(n) + n / 2 + 1), 64) - 1;
-    FinSlot* tab = arena.alloc<FinSlot>(static_cast<size_t>(mask) + 2);
-    uint32_t* slot_of = arena.alloc<uint32_t>(n);
-    uint32_t* rep = arena.alloc<uint32_t>(n);
+    uint32_t* cmin = arena.alloc<uint32_t>(n + 1);
+    uint32_t* isrep = arena.alloc<uint32_t>(n);
     uint32_t* rank = arena.alloc<uint32_t>(n);
     uint32_t* total = arena.alloc<uint32_t>(1);
     out.block_ids = keep.alloc<uint32_t>(n);
     const uint32_t gb = std::max<uint32_t>(ceil_div(n, kBlock), 1);
-    k_fin_fill<<<ceil_div(mask + 2, kBlock), kBlock, 0, s>>>(tab, mask + 2);
+    hip_check(hipMemsetAsync(cmin, 0xFF, (static_cast<size_t>(n) + 1) * 4, s), "class minima");
     if (n) {
-        k_fin_insert<<<gb, kBlock, 0, s>>>(h, g.alive, n, tab, mask, slot_of);
-        k_fin_rep<<<gb, kBlock, 0, s>>>(g.alive, n, tab, slot_of, rep);
+        k_fin_min<<<gb, kBlock, 0, s>>>(rep, g.alive, n, cmin);
+        k_fin_rep<<<gb, kBlock, 0, s>>>(rep, g.alive, n, cmin, isrep);
     }
-    scan_exclusive(rep, rank, n, total, arena, s);
+    scan_exclusive(isrep, rank, n, total, arena, s);
     uint32_t nb = 0;
     hip_check(hipMemcpyAsync(&nb, total, 4, hipMemcpyDeviceToHost, s), "block count");
     hip_check(hipStreamSynchronize(s), "block count sync");
     out.n_blocks = nb;
-    out.block_sizes = keep.alloc<uint32_t>(nb);
-    hip_check(hipMemsetAsync(out.block_sizes, 0, static_cast<size_t>(nb) * 4 + 4, s), "sizes");
+    out.block_sizes = keep.alloc<uint32_t>(nb + 1);
+    hip_check(hipMemsetAsync(out.block_sizes, 0, (static_cast<size_t>(nb) + 1) * 4, s), "sizes");
     if (n)
-        k_fin_ids<<<ceil_div(n, kIdsPerBlock), kBlock, 0, s>>>(g.alive, n, tab, slot_of, rank, out.block_ids,
+        k_fin_ids<<<ceil_div(n, kIdsPerBlock), kBlock, 0, s>>>(g.alive, n, rep, cmin, rank, out.block_ids,
                                                               out.block_sizes);
     hip_check(hipGetLastError(), "finalize launch");
     out.n_se = 0;

@@ -35,9 +35,17 @@ constexpr uint64_t kCE = mix64(4);  // per-pair domain
 // vertices and fewer than 2 * kTileQuota edges, so its per-vertex
 // de-duplication tables (two slots per edge) fit one block's LDS.  Vertices
 // with more than kTileQuota out-edges ("hubs") are cut into chunks of
-// kTileMaxEdges edges; the chunks of one hub de-duplicate into a shared
-// region of 2*d slots of a global table, and the hub's last chunk block
-// finishes its hash and clears the region for the next launch.
+// kTileMaxEdges edges whose blocks write their mixed pair keys to a per-hub
+// scratch area; a second launch de-duplicates each hub's keys in LDS, split
+// by the top key bits into buckets that fit a large LDS table.
+//
+// Classes.  Every alive vertex v keeps rep[v], a member of its current
+// class.  The k-class of v is (its (k-1)-class, h^k(v)) (the bisimulation
+// definition: k-bisimilar requires (k-1)-bisimilar), so after h^k is known
+// a vertex stays with its representative iff h^k(v) == h^k(rep[v]); the
+// others "split off" and meet the other members of their new class in a
+// global table keyed by (rep, h^k).  Only split-offs touch that table, so a
+// late iteration of a long chain run inserts a handful of keys.
 
 constexpr int kBlock = 256;              // threads per block (4 wave64s)
 constexpr int kTileQuota = 1024;         // tile boundaries every kTileQuota edges
@@ -46,15 +54,19 @@ constexpr int kTileMaxVerts = 256;
 constexpr int kEdgesPerThread = kTileMaxEdges / kBlock;  // 8
 constexpr int kTableSlots = 2 * kTileMaxEdges;           // 4096 x 8 B = 32 KiB
 constexpr uint32_t kHubMinDegree = kTileQuota + 1;
-constexpr int kStripes = 64;             // striped block counters per iteration
+constexpr int kHubBlock = 512;           // threads per hub-bucket block
+constexpr int kStripes = 64;             // striped per-level claim counters
 constexpr int kStripeRing = 4;
+constexpr int kListPerStripe = 4096;     // claimed split-table slots remembered per stripe
+constexpr uint32_t kNoRep = 0xFFFFFFFEu; // virtual class of every vertex before level 0
+constexpr int kZeroSlots = 64;           // classes whose hash is 0, per table
 
 // Device-side status of a refinement run.
 struct RunStatus {
     uint32_t done;      // sticky: set by the first launch that sees the stop condition
     uint32_t k_done;
     uint32_t fixpoint;
-    uint32_t error;     // staging validation error (BSIM_E_* as positive bits)
+    uint32_t error;     // validation / capacity error bits
     uint32_t max_label;
     uint32_t max_types;
     uint32_t pad[2];
@@ -62,40 +74,68 @@ struct RunStatus {
 
 constexpr uint32_t kErrInvalid = 1u;
 constexpr uint32_t kErrRange = 2u;
+constexpr uint32_t kErrZeroHash = 4u;   // more than kZeroSlots classes hashed to 0 at one level
 
-// Arguments of one refinement launch (iteration k reads h^{k-1}, writes h^k).
+// One slot of the split table: key = h^k, owner = ((rep + 1) << 32) | member.
+struct SplitSlot {
+    uint64_t key;
+    uint64_t owner;
+};
+
+// The split table of one level (two alternate by level parity).
+struct SplitTable {
+    SplitSlot* slots;     // cap slots, all zero between uses
+    uint64_t* zero;       // kZeroSlots owner words for the key 0
+    uint32_t* list;       // kStripes * kListPerStripe claimed slot indices
+    uint32_t mask;        // cap - 1
+};
+
+// Arguments of one refinement launch k: split test of level k-1, h^k.
 struct IterArgs {
     const uint32_t* row_off;
     const uint32_t* tgt;
     const void* lab;
     const uint64_t* t;      // type hashes t(v)
     const uint64_t* salt;   // salt(l) for l <= max label
-    const uint64_t* h_prev;
-    uint64_t* h_next;
+    const uint64_t* h_prev; // h^{k-1}
+    uint64_t* h_next;       // h^k
     const uint8_t* alive;   // nullable
+    uint32_t* rep;
     const uint32_t* tile_v0;
     const uint32_t* tile_v1;
     const uint32_t* hc_hub;     // hub chunk block -> hub index
     const uint32_t* hc_e0;      // hub chunk block -> first edge
     const uint32_t* hub_v;
-    const uint32_t* hub_nchunks;
-    const uint64_t* hub_tab_off;  // first slot of the hub's region in hub_tab
-    uint64_t* hub_tab;            // 2*d slots per hub, all zero between launches
-    uint64_t* hub_acc;
-    uint32_t* hub_done;
-    uint64_t* tab_ins;      // count table receiving h^k (keys only, 0 = empty)
-    uint64_t* tab_clr;      // count table to clear for iteration k+1
-    uint32_t* zflag_ins;
-    uint32_t* zflag_clr;
-    uint32_t* stripes;      // [kStripeRing][kStripes]
-    uint32_t* totals;       // totals[k] = n_k
+    const uint64_t* hub_key_off;  // first scratch key of the hub
+    uint64_t* hub_keys;
+    SplitTable test_tab;    // receives the split-offs of level k-1
+    SplitTable clr_tab;     // filled at level k-2, cleared here
+    uint32_t* lcnt;         // [kStripeRing][kStripes] claims per level
+    uint32_t* totals;       // totals[j] = n_j
     RunStatus* status;
     uint32_t n_tiles;
     uint32_t n_hub_chunks;
-    uint32_t tab_mask;
     uint32_t k;
     uint32_t k_max;
     uint32_t stop;
+};
+
+// Arguments of the hub-bucket launch of iteration k.
+struct HubArgs {
+    const uint64_t* t;
+    const uint64_t* hub_keys;
+    const uint64_t* hub_key_off;
+    const uint32_t* hub_v;
+    const uint32_t* hub_deg;
+    const uint32_t* hub_logb;
+    const uint32_t* hb_hub;
+    const uint32_t* hb_bucket;
+    uint64_t* hub_acc;
+    uint32_t* hub_done;
+    uint64_t* h_next;
+    RunStatus* status;
+    uint32_t table_slots;   // LDS slots (power of two)
+    uint32_t table_limit;   // re-split a bucket beyond this many keys
 };
 
 // ------------------------------------------------------------ host helpers
@@ -187,13 +227,18 @@ struct Staged {
     uint32_t* tile_v1 = nullptr;
     uint32_t n_hubs = 0;
     uint32_t n_hub_chunks = 0;
-    uint32_t* hub_v = nullptr;
-    uint32_t* hub_nchunks = nullptr;
-    uint64_t* hub_tab_off = nullptr;
-    uint64_t hub_tab_slots = 0;
+    uint32_t n_hub_blocks = 0;       // hub-bucket blocks of the second launch
+    uint32_t* hub_v = nullptr;       // by degree, descending
+    uint32_t* hub_deg = nullptr;
+    uint32_t* hub_logb = nullptr;
+    uint64_t* hub_key_off = nullptr;
+    uint64_t hub_keys_total = 0;
     uint32_t* hc_hub = nullptr;
     uint32_t* hc_e0 = nullptr;
-    std::vector<uint32_t> host_hub_v;       // hub vertices, by degree descending
+    uint32_t* hb_hub = nullptr;
+    uint32_t* hb_bucket = nullptr;
+    uint32_t hub_table_slots = 0;
+    std::vector<uint32_t> host_hub_v;
     std::vector<uint32_t> host_hub_deg;
 };
 
@@ -202,31 +247,36 @@ struct Staged {
 void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena& arena,
                  hipStream_t s);
 
-// Count-table and per-iteration buffers of one refinement run.
+// Per-run buffers of the refinement loop.
 struct RunBuffers {
     uint64_t* t = nullptr;
     uint64_t* h[2] = {nullptr, nullptr};
-    uint64_t* tab[2] = {nullptr, nullptr};
-    uint32_t* zflag = nullptr;     // [2]
-    uint32_t tab_mask = 0;
-    uint32_t* stripes = nullptr;   // [kStripeRing * kStripes]
-    uint32_t* totals = nullptr;    // [k_cap + 2]
+    uint32_t* rep = nullptr;
+    SplitTable tab[2];
+    uint32_t* lcnt = nullptr;      // [kStripeRing * kStripes]
+    uint32_t* totals = nullptr;    // [k_cap]
     uint32_t k_cap = 0;
+    uint64_t* hub_keys = nullptr;
     uint64_t* hub_acc = nullptr;
     uint32_t* hub_done = nullptr;
-    uint64_t* hub_tab = nullptr;
     RunStatus* status = nullptr;
 };
 
 void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& rb, Arena& arena,
                        hipStream_t s);
 
-// k = 0: type hashes, h^0 = t, count n_0.
-void launch_type_hash(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s);
+// Level 0: type hashes, h^0 = t, the type classes (rep) and n_0.
+void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s);
 
-// One refinement launch computing h^k from h^{k-1}.
+// Launch k: stop test, split test of level k-1, h^k (tiles and hub chunks).
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
                       bool stop, hipStream_t s);
+
+// Hub buckets of iteration k (only when the graph has hubs and k <= k_max).
+void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s);
+
+// LDS slots the hub-bucket launch can use on this device.
+uint32_t query_hub_table_slots(int device);
 
 // Finalize (a8): block ids, block sizes, sorted distinct quotient edges.
 struct FinalOut {
@@ -239,7 +289,8 @@ struct FinalOut {
     uint32_t* se_dst = nullptr;
 };
 
-void finalize(const Staged& g, const uint64_t* h, uint32_t tab_slots, bool want_edges,
-              FinalOut& out, Arena& arena, Arena& keep, hipStream_t s);
+// Blocks are the classes given by rep[] (first-occurrence numbering).
+void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& out, Arena& arena,
+              Arena& keep, hipStream_t s);
 
 }  // namespace bsim

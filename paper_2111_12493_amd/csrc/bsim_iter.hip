@@ -1,37 +1,136 @@
 // bsim_iter.hip -- the refinement loop (a2-a7).
 //
-// Iteration 0 hashes every vertex's type set (Algorithm 4's initialization:
-// the ID of the local schema).  Iteration k >= 1 is one launch of
-// k_iterate: every block first evaluates the stop test on the counts of the
-// previous launch, then either
-//   * a tile block: gathers h^{k-1} of its tile's out-edge targets
-//     (SignalMessages), de-duplicates the (label, hash) pair keys of each
-//     vertex in a per-vertex open-addressing region of an LDS table
-//     (MergeMessages' hash table), sums the mixed distinct keys per vertex
-//     (the order-independent Hash), and writes h^k; or
-//   * a hub chunk block: the same for up to kTileMaxEdges edges of one hub,
-//     de-duplicating into the hub's region of a global table; partial sums
-//     meet in a global accumulator and the hub's last chunk block finishes
-//     the hash and clears the region.
-// Every new h^k is inserted into a key-only count table; the number of new
-// keys is n_k, the block count of the k-partition.  The launch after the
-// one where n_k == n_{k-1} (or k > k_max) sets a sticky done flag and every
-// later launch returns at once, so the host can queue launches ahead.
+// Level 0 (k_init) hashes every vertex's type set (Algorithm 4's
+// initialization: the ID of the local schema) and groups vertices by it.
+// Launch k >= 1 (k_iterate) runs three phases in every block:
+//   0. stop test on the class count of level k-2, which is complete once
+//      launch k-1 has finished; recycling of counters and of the split table
+//      that level k-2 used;
+//   1. split test of level k-1 for the block's own vertices: a vertex whose
+//      h^{k-1} differs from its representative's joins (or founds) the class
+//      (rep, h^{k-1}) in the split table; the number of founded classes is
+//      n_{k-1} - n_{k-2};
+//   2. h^k: a tile block gathers h^{k-1} of its out-edge targets
+//      (SignalMessages), de-duplicates the (label, hash) pair keys of each
+//      vertex in a per-vertex open-addressing region of an LDS table
+//      (MergeMessages' hash table), sums the mixed distinct keys
+//      (the order-independent Hash) and writes h^k; a hub chunk block writes
+//      its mixed keys to the hub's scratch area instead.
+// Then k_hub de-duplicates each hub's scratch keys bucket by bucket in LDS;
+// the last bucket block of a hub finishes its h^k.
+//
+// The stop test lags the hashes by two launches, so once the block count
+// stops growing at level j, launch j+1 has computed h^{j+1} that is never
+// used and launch j+2 sets the sticky done flag; every later launch returns
+// at once, so the host can queue launches ahead.
 #include "bsim_device.h"
 
 namespace bsim {
 
 namespace {
 
-__global__ void __launch_bounds__(kBlock) k_type_hash(
-    const uint32_t* __restrict__ type_off, const uint32_t* __restrict__ type_ids,
-    const uint8_t* __restrict__ alive, uint32_t n, int untyped, uint64_t* __restrict__ t,
-    uint64_t* __restrict__ h0, uint64_t* tab, uint32_t mask, uint32_t* zflag, uint32_t* stripes) {
+// ------------------------------------------------------------ split table
+
+// Join the class (r, key) of the level's split table, founding it if needed.
+// Returns the owner word ((r + 1) << 32 | member) and sets *founded when this
+// call created the class.  Slots only ever go from empty to filled during a
+// launch, so every caller with the same (r, key) walks the same probe
+// sequence and stops at the same slot.
+__device__ uint64_t split_join(const SplitTable& T, uint32_t r, uint64_t key, uint32_t v,
+                               uint32_t* founded, uint32_t* slot_out, RunStatus* status) {
+    const uint64_t mine = (static_cast<uint64_t>(r + 1) << 32) | v;
+    *founded = 0;
+    if (key == 0) {
+        // the key 0 marks empty slots: its classes live in a short side array
+        for (uint32_t i = 0; i < kZeroSlots; i++) {
+            uint64_t o = T.zero[i];
+            if (o == 0) {
+                o = atomicCAS(reinterpret_cast<unsigned long long*>(&T.zero[i]), 0ull,
+                              static_cast<unsigned long long>(mine));
+                if (o == 0) {
+                    *founded = 1;
+                    o = mine;
+                }
+            }
+            if ((o >> 32) == static_cast<uint64_t>(r + 1)) {
+                *slot_out = 0xFFFFFFFFu;
+                return o;
+            }
+        }
+        atomicOr(&status->error, kErrZeroHash);
+        *slot_out = 0xFFFFFFFFu;
+        return mine;
+    }
+    uint32_t slot = static_cast<uint32_t>(key) & T.mask;
+    for (;;) {
+        SplitSlot* p = &T.slots[slot];
+        uint64_t cur = p->key;
+        if (cur == 0) {
+            cur = atomicCAS(reinterpret_cast<unsigned long long*>(&p->key), 0ull,
+                            static_cast<unsigned long long>(key));
+            if (cur == 0) cur = key;
+        }
+        if (cur == key) {
+            uint64_t o = p->owner;
+            if (o == 0) {
+                o = atomicCAS(reinterpret_cast<unsigned long long*>(&p->owner), 0ull,
+                              static_cast<unsigned long long>(mine));
+                if (o == 0) {
+                    *founded = 1;
+                    o = mine;
+                }
+            }
+            if ((o >> 32) == static_cast<uint64_t>(r + 1)) {
+                *slot_out = slot;
+                return o;
+            }
+        }
+        slot = (slot + 1) & T.mask;
+    }
+}
+
+// Count the classes founded by this block at `level` (stripe counter) and
+// remember their slots so the table can be cleared selectively.
+__device__ void record_founders(const SplitTable& T, uint32_t* lcnt, uint32_t level,
+                                uint32_t founded, uint32_t slot, uint32_t* s_red, uint32_t* s_base) {
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    const uint64_t ball = __ballot(founded != 0);
+    const uint32_t wcount = static_cast<uint32_t>(__popcll(ball));
+    const uint32_t wrank = static_cast<uint32_t>(__popcll(ball & ((1ull << lane) - 1)));
+    if (lane == 0) s_red[wid] = wcount;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; w++) {
+        if (w < static_cast<int>(wid)) off += s_red[w];
+        tot += s_red[w];
+    }
+    const uint32_t stripe = blockIdx.x & (kStripes - 1);
+    if (threadIdx.x == 0)
+        *s_base = tot ? atomicAdd(&lcnt[(level & (kStripeRing - 1)) * kStripes + stripe], tot) : 0;
+    __syncthreads();
+    if (founded) {
+        // every counted position is written (0xFFFFFFFF for the key-0 side array)
+        const uint32_t pos = *s_base + off + wrank;
+        if (pos < static_cast<uint32_t>(kListPerStripe)) T.list[stripe * kListPerStripe + pos] = slot;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ level 0
+
+__global__ void __launch_bounds__(kBlock) k_init(const uint32_t* __restrict__ type_off,
+                                                 const uint32_t* __restrict__ type_ids,
+                                                 const uint8_t* __restrict__ alive, uint32_t n,
+                                                 int untyped, uint64_t* __restrict__ t,
+                                                 uint64_t* __restrict__ h0, uint32_t* __restrict__ rep,
+                                                 SplitTable T, uint32_t* lcnt, RunStatus* status) {
     __shared__ uint32_t s_red[kBlock / 64];
+    __shared__ uint32_t s_base;
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
-    uint32_t fresh = 0;
+    uint32_t founded = 0, slot = 0xFFFFFFFFu;
     if (v < n) {
         uint64_t tv = 0;
+        uint32_t r = 0xFFFFFFFFu;
         if (!alive || alive[v]) {
             uint64_t sum = 0;
             if (!untyped) {
@@ -44,30 +143,50 @@ __global__ void __launch_bounds__(kBlock) k_type_hash(
                 }
             }
             tv = mix64(kCT + sum);
-            fresh = count_insert(tab, mask, zflag, tv);
+            r = static_cast<uint32_t>(split_join(T, kNoRep, tv, v, &founded, &slot, status));
         }
         t[v] = tv;
         h0[v] = tv;
+        rep[v] = r;
     }
-    uint32_t c = block_sum_u32(fresh, s_red);
-    if (threadIdx.x == 0) add_block_count(stripes, 0, c);
+    record_founders(T, lcnt, 0, founded, slot, s_red, &s_base);
 }
+
+// ------------------------------------------------------------ launch k
 
 struct IterShared {
     uint64_t tab[kTableSlots];
     uint64_t acc[kTileMaxVerts];
-    uint64_t red64[kBlock / 64];
     uint32_t off[kTileMaxVerts + 1];
     uint32_t red[kBlock / 64];
     uint32_t ctl[4];
     alignas(8) uint8_t seg[kTileMaxEdges];
 };
 
+// Split test of level k-1 for one owned vertex (h_prev holds h^{k-1}).
+__device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32_t* founded,
+                                           uint32_t* slot) {
+    *founded = 0;
+    *slot = 0xFFFFFFFFu;
+    if (a.alive && !a.alive[v]) return;
+    const uint32_t r = a.rep[v];
+    if (r == v) return;
+    const uint64_t hv = a.h_prev[v];
+    if (hv == a.h_prev[r]) return;
+    a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, r, hv, v, founded, slot, a.status));
+}
+
 template <typename LabT>
-__device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S) {
+__device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool test, bool hash) {
     const uint32_t tid = threadIdx.x;
     const uint32_t v0 = a.tile_v0[tile], v1 = a.tile_v1[tile];
     const uint32_t nv = v1 - v0;
+    if (test) {
+        uint32_t founded = 0, slot = 0xFFFFFFFFu;
+        if (tid < nv) split_test(a, v0 + tid, &founded, &slot);
+        record_founders(a.test_tab, a.lcnt, a.k - 1, founded, slot, S.red, &S.ctl[1]);
+    }
+    if (!hash) return;
     const uint32_t ebase = a.row_off[v0];
     for (uint32_t i = tid; i <= nv; i += kBlock) S.off[i] = a.row_off[v0 + i] - ebase;
     for (uint32_t i = tid; i < nv; i += kBlock) S.acc[i] = 0;
@@ -112,52 +231,29 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S) {
         }
     }
     __syncthreads();
-    uint32_t fresh = 0;
     if (tid < nv) {
         const uint32_t v = v0 + tid;
-        if (!a.alive || a.alive[v]) {
-            const uint64_t h = mix64(a.t[v] ^ mix64(kCS + S.acc[tid]));
-            a.h_next[v] = h;
-            fresh = count_insert(a.tab_ins, a.tab_mask, a.zflag_ins, h);
-        } else {
-            a.h_next[v] = 0;
-        }
-    }
-    const uint32_t c = block_sum_u32(fresh, S.red);
-    if (tid == 0) add_block_count(a.stripes, a.k, c);
-}
-
-// Insert a nonzero key into a region [base, base+span) of a global table;
-// returns 1 if it was not present.  Read before CAS as in count_insert.
-__device__ __forceinline__ uint32_t global_region_insert(uint64_t* tab, uint64_t base, uint32_t span,
-                                                         uint64_t f) {
-    uint32_t off = static_cast<uint32_t>((static_cast<uint64_t>(static_cast<uint32_t>(f)) * span) >> 32);
-    for (;;) {
-        uint64_t* p = tab + base + off;
-        const uint64_t cur = *p;
-        if (cur == f) return 0u;
-        if (cur == 0) {
-            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(p), 0ull,
-                                               static_cast<unsigned long long>(f));
-            if (old == 0ull) return 1u;
-            if (old == f) return 0u;
-        }
-        if (++off == span) off = 0;
+        a.h_next[v] = (!a.alive || a.alive[v]) ? mix64(a.t[v] ^ mix64(kCS + S.acc[tid])) : 0;
     }
 }
 
 template <typename LabT>
-__device__ void hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S) {
+__device__ void hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, bool test, bool hash) {
     const uint32_t tid = threadIdx.x;
     const uint32_t hi = a.hc_hub[blk];
     const uint32_t e0 = a.hc_e0[blk];
     const uint32_t v = a.hub_v[hi];
     const uint32_t vbeg = a.row_off[v], vend = a.row_off[v + 1];
+    if (test) {
+        // the hub's first chunk block owns the hub vertex's split test
+        uint32_t founded = 0, slot = 0xFFFFFFFFu;
+        if (tid == 0 && e0 == vbeg) split_test(a, v, &founded, &slot);
+        record_founders(a.test_tab, a.lcnt, a.k - 1, founded, slot, S.red, &S.ctl[1]);
+    }
+    if (!hash) return;
     const uint32_t ne = min(static_cast<uint32_t>(kTileMaxEdges), vend - e0);
-    const uint32_t span = 2 * (vend - vbeg);
-    const uint64_t base = a.hub_tab_off[hi];
+    uint64_t* __restrict__ out = a.hub_keys + a.hub_key_off[hi] + (e0 - vbeg);
     const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
-
     uint32_t w[kEdgesPerThread];
     uint32_t l[kEdgesPerThread];
 #pragma unroll
@@ -174,35 +270,10 @@ __device__ void hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S) 
         const uint32_t j = tid + r * kBlock;
         if (j < ne) hv[r] = a.h_prev[w[r]] ^ a.salt[l[r]];
     }
-    uint64_t sum = 0;
 #pragma unroll
     for (int r = 0; r < kEdgesPerThread; r++) {
         const uint32_t j = tid + r * kBlock;
-        if (j < ne) {
-            const uint64_t f = mix64(hv[r] ^ kCE);
-            if (f != 0 && global_region_insert(a.hub_tab, base, span, f)) sum += f;
-        }
-    }
-    const uint64_t bsum = block_sum_u64(sum, S.red64);
-    if (tid == 0) {
-        __hip_atomic_fetch_add(&a.hub_acc[hi], bsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t prev =
-            __hip_atomic_fetch_add(&a.hub_done[hi], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t last = (prev + 1 == a.hub_nchunks[hi]) ? 1u : 0u;
-        S.ctl[3] = last;
-        if (last) {
-            const uint64_t acc = __hip_atomic_load(&a.hub_acc[hi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t h = mix64(a.t[v] ^ mix64(kCS + acc));
-            a.h_next[v] = h;
-            add_block_count(a.stripes, a.k, count_insert(a.tab_ins, a.tab_mask, a.zflag_ins, h));
-            a.hub_acc[hi] = 0;
-            a.hub_done[hi] = 0;
-        }
-    }
-    __syncthreads();
-    if (S.ctl[3]) {
-        // every chunk of this hub has inserted: clear its region for the next launch
-        for (uint32_t j = tid; j < span; j += kBlock) a.hub_tab[base + j] = 0;
+        if (j < ne) out[j] = mix64(hv[r] ^ kCE);
     }
 }
 
@@ -210,50 +281,175 @@ template <typename LabT>
 __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
     __shared__ IterShared S;
     const uint32_t tid = threadIdx.x;
-    // ---- stop test on the previous launch's block count
+    const uint32_t k = a.k;
+    // ---- phase 0: stop test on level k-2
     if (tid < 64) {
-        uint32_t c = a.stripes[((a.k - 1) & (kStripeRing - 1)) * kStripes + tid];
-        c = wave_sum_u32(c);
-        if (tid == 0) {
-            uint32_t ex = *reinterpret_cast<volatile uint32_t*>(&a.status->done);
-            if (!ex) {
-                if (blockIdx.x == 0) a.totals[a.k - 1] = c;
-                const uint32_t fix = (a.k >= 2 && c == a.totals[a.k - 2]) ? 1u : 0u;
-                if ((a.stop && fix) || a.k > a.k_max) {
+        uint32_t ex = *reinterpret_cast<volatile uint32_t*>(&a.status->done);
+        if (!ex && k >= 2) {
+            const uint32_t lv = k - 2;
+            const uint32_t c = wave_sum_u32(a.lcnt[(lv & (kStripeRing - 1)) * kStripes + tid]);
+            const uint32_t nl = lv == 0 ? c : a.totals[lv - 1] + c;
+            if (tid == 0) {
+                if (blockIdx.x == 0) a.totals[lv] = nl;
+                const uint32_t fix = (lv >= 1 && c == 0) ? 1u : 0u;
+                if ((a.stop && fix) || lv >= a.k_max) {
                     ex = 1;
                     if (blockIdx.x == 0) {
-                        a.status->k_done = a.k - 1;
+                        a.status->k_done = lv;
                         a.status->fixpoint = fix;
                         a.status->done = 1;
                     }
                 }
             }
-            S.ctl[0] = ex;
         }
+        if (tid == 0) S.ctl[0] = ex;
     }
     __syncthreads();
     if (S.ctl[0]) return;
 
-    // ---- recycle the counters and the count table of iteration k+1
-    if (blockIdx.x == 0) {
-        if (tid < kStripes) a.stripes[((a.k + 1) & (kStripeRing - 1)) * kStripes + tid] = 0;
-        if (tid == 0) *a.zflag_clr = 0;
-    }
-    {
-        const uint64_t cap = static_cast<uint64_t>(a.tab_mask) + 1;
-        const uint64_t per = (cap + gridDim.x - 1) / gridDim.x;
-        const uint64_t lo = per * blockIdx.x;
-        const uint64_t hi = min(cap, lo + per);
-        for (uint64_t j = lo + tid; j < hi; j += kBlock) a.tab_clr[j] = 0;
+    // ---- recycling: counters of level k-3, split table of level k-2
+    if (blockIdx.x == 0 && tid < kStripes && k >= 3)
+        a.lcnt[((k - 3) & (kStripeRing - 1)) * kStripes + tid] = 0;
+    if (k >= 2) {
+        const uint32_t* cnt = a.lcnt + ((k - 2) & (kStripeRing - 1)) * kStripes;
+        bool overflow = false;
+        for (int st = 0; st < kStripes; st++) overflow |= cnt[st] > static_cast<uint32_t>(kListPerStripe);
+        if (blockIdx.x == 0 && tid < kZeroSlots) a.clr_tab.zero[tid] = 0;
+        if (overflow) {
+            const uint64_t cap = static_cast<uint64_t>(a.clr_tab.mask) + 1;
+            const uint64_t per = (cap + gridDim.x - 1) / gridDim.x;
+            const uint64_t lo = per * blockIdx.x, hi = min(cap, lo + per);
+            for (uint64_t j = lo + tid; j < hi; j += kBlock) {
+                a.clr_tab.slots[j].key = 0;
+                a.clr_tab.slots[j].owner = 0;
+            }
+        } else {
+            const uint64_t items = static_cast<uint64_t>(kStripes) * kListPerStripe;
+            for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + tid; i < items;
+                 i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+                const uint32_t st = static_cast<uint32_t>(i / kListPerStripe);
+                const uint32_t e = static_cast<uint32_t>(i % kListPerStripe);
+                if (e < cnt[st]) {
+                    const uint32_t idx = a.clr_tab.list[i];
+                    if (idx <= a.clr_tab.mask) {
+                        SplitSlot* p = &a.clr_tab.slots[idx];
+                        p->key = 0;
+                        p->owner = 0;
+                    }
+                }
+            }
+        }
     }
 
+    const bool test = k >= 2 && k - 1 <= a.k_max;
+    const bool hash = k <= a.k_max;
     if (blockIdx.x < a.n_hub_chunks)
-        hub_chunk_block<LabT>(a, blockIdx.x, S);
+        hub_chunk_block<LabT>(a, blockIdx.x, S, test, hash);
     else if (blockIdx.x - a.n_hub_chunks < a.n_tiles)
-        tile_block<LabT>(a, blockIdx.x - a.n_hub_chunks, S);
+        tile_block<LabT>(a, blockIdx.x - a.n_hub_chunks, S, test, hash);
+}
+
+// ------------------------------------------------------------ hub buckets
+
+__global__ void __launch_bounds__(kHubBlock) k_hub(HubArgs a) {
+    extern __shared__ uint64_t s_tab[];
+    __shared__ uint64_t s_red64[kHubBlock / 64];
+    __shared__ uint32_t s_ctl[4];
+    const uint32_t tid = threadIdx.x;
+    if (*reinterpret_cast<volatile uint32_t*>(&a.status->done)) return;
+    const uint32_t hi = a.hb_hub[blockIdx.x];
+    const uint32_t bucket = a.hb_bucket[blockIdx.x];
+    const uint32_t logb = a.hub_logb[hi];
+    const uint32_t d = a.hub_deg[hi];
+    const uint64_t* __restrict__ keys = a.hub_keys + a.hub_key_off[hi];
+    const uint32_t mask = a.table_slots - 1;
+    volatile uint32_t* ctl = s_ctl;
+
+    uint64_t sum = 0;
+    for (uint32_t extra = 0;; extra++) {
+        sum = 0;
+        bool overflow = false;
+        const uint32_t bits = logb + extra;
+        for (uint32_t sub = 0; sub < (1u << extra) && !overflow; sub++) {
+            const uint64_t want = (static_cast<uint64_t>(bucket) << extra) | sub;
+            for (uint32_t j = tid; j < a.table_slots; j += kHubBlock) s_tab[j] = 0;
+            if (tid == 0) {
+                ctl[1] = 0;  // reserved slots
+                ctl[2] = 0;  // overflow
+            }
+            __syncthreads();
+            for (uint32_t j0 = 0; j0 < d; j0 += 4 * kHubBlock) {
+                if (ctl[2]) break;
+                uint64_t f[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const uint32_t j = j0 + r * kHubBlock + tid;
+                    f[r] = j < d ? keys[j] : 0;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    if (f[r] == 0) continue;
+                    if (bits && (f[r] >> (64 - bits)) != want) continue;
+                    // reserve first so the table never fills up
+                    if (atomicAdd(const_cast<uint32_t*>(&ctl[1]), 1u) >= a.table_limit) {
+                        ctl[2] = 1;
+                        break;
+                    }
+                    const uint32_t slot = static_cast<uint32_t>(f[r]) & mask;
+                    if (lds_insert(s_tab, slot, 0, a.table_slots, f[r]))
+                        sum += f[r];
+                    else
+                        atomicSub(const_cast<uint32_t*>(&ctl[1]), 1u);
+                }
+            }
+            __syncthreads();
+            overflow = ctl[2] != 0;
+            __syncthreads();
+        }
+        if (!overflow) break;
+    }
+    // block sum
+    uint64_t x = wave_sum_u64(sum);
+    if (lane_id() == 0) s_red64[tid >> 6] = x;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t bsum = 0;
+        for (int i = 0; i < kHubBlock / 64; i++) bsum += s_red64[i];
+        __hip_atomic_fetch_add(&a.hub_acc[hi], bsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t prev =
+            __hip_atomic_fetch_add(&a.hub_done[hi], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev + 1 == (1u << logb)) {
+            const uint64_t acc = __hip_atomic_load(&a.hub_acc[hi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t v = a.hub_v[hi];
+            a.h_next[v] = mix64(a.t[v] ^ mix64(kCS + acc));
+            a.hub_acc[hi] = 0;
+            a.hub_done[hi] = 0;
+        }
+    }
 }
 
 }  // namespace
+
+uint32_t query_hub_table_slots(int device) {
+    int bytes = 0;
+    if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        bytes = 65536;
+    // keep room for the block's static LDS; at most 128 KiB of table
+    uint64_t avail = bytes > 4096 ? static_cast<uint64_t>(bytes) - 4096 : 4096;
+    uint64_t slots = std::min<uint64_t>(avail / 8, 16384);
+    uint32_t p = 1;
+    while (2ull * p <= slots) p <<= 1;
+    return p;
+}
+
+static SplitTable make_table(Arena& arena, uint32_t cap) {
+    SplitTable T;
+    T.slots = arena.alloc<SplitSlot>(cap);
+    T.zero = arena.alloc<uint64_t>(kZeroSlots);
+    T.list = arena.alloc<uint32_t>(static_cast<size_t>(kStripes) * kListPerStripe);
+    T.mask = cap - 1;
+    return T;
+}
 
 void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& rb, Arena& arena,
                        hipStream_t s) {
@@ -261,38 +457,37 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
     rb.t = arena.alloc<uint64_t>(n);
     rb.h[0] = arena.alloc<uint64_t>(n);
     rb.h[1] = arena.alloc<uint64_t>(n);
+    rb.rep = arena.alloc<uint32_t>(n);
     const uint32_t cap = std::max<uint32_t>(next_pow2(static_cast<uint64_t>(n) + n / 2 + 1), 64);
-    rb.tab_mask = cap - 1;
-    // one allocation of 2*cap keys; finalize reuses it as cap 16-byte slots
-    rb.tab[0] = arena.alloc<uint64_t>(2 * static_cast<size_t>(cap) + 2);
-    rb.tab[1] = rb.tab[0] + cap;
-    rb.zflag = arena.alloc<uint32_t>(2);
-    rb.stripes = arena.alloc<uint32_t>(kStripeRing * kStripes);
-    // k_done <= max(n, 1) when stopping at the fixpoint; the launch after
-    // k_done writes totals[k_done]
+    for (int i = 0; i < 2; i++) {
+        rb.tab[i] = make_table(arena, cap);
+        hip_check(hipMemsetAsync(rb.tab[i].slots, 0, static_cast<size_t>(cap) * sizeof(SplitSlot), s),
+                  "clear split table");
+        hip_check(hipMemsetAsync(rb.tab[i].zero, 0, kZeroSlots * 8, s), "clear zero slots");
+    }
+    rb.lcnt = arena.alloc<uint32_t>(kStripeRing * kStripes);
+    // level j's count is written by launch j+2 <= k_done+2; k_done <= max(n, 1)
+    // when stopping at the fixpoint, else k_max
     const uint64_t kc = stop ? std::min<uint64_t>(k_max, static_cast<uint64_t>(n) + 1) : k_max;
-    rb.k_cap = static_cast<uint32_t>(kc) + 2;
+    rb.k_cap = static_cast<uint32_t>(kc) + 3;
     rb.totals = arena.alloc<uint32_t>(rb.k_cap);
+    rb.hub_keys = arena.alloc<uint64_t>(g.hub_keys_total + 1);
     rb.hub_acc = arena.alloc<uint64_t>(g.n_hubs + 1);
     rb.hub_done = arena.alloc<uint32_t>(g.n_hubs + 1);
-    rb.hub_tab = arena.alloc<uint64_t>(g.hub_tab_slots + 1);
     rb.status = arena.alloc<RunStatus>(1);
-    hip_check(hipMemsetAsync(rb.tab[0], 0, (2 * static_cast<size_t>(cap) + 2) * 8, s), "clear tables");
-    hip_check(hipMemsetAsync(rb.zflag, 0, 2 * 4, s), "clear flags");
-    hip_check(hipMemsetAsync(rb.stripes, 0, kStripeRing * kStripes * 4, s), "clear stripes");
+    hip_check(hipMemsetAsync(rb.lcnt, 0, kStripeRing * kStripes * 4, s), "clear counters");
     hip_check(hipMemsetAsync(rb.totals, 0, rb.k_cap * 4, s), "clear totals");
     hip_check(hipMemsetAsync(rb.hub_acc, 0, (g.n_hubs + 1) * 8, s), "clear hub acc");
     hip_check(hipMemsetAsync(rb.hub_done, 0, (g.n_hubs + 1) * 4, s), "clear hub done");
-    hip_check(hipMemsetAsync(rb.hub_tab, 0, (g.hub_tab_slots + 1) * 8, s), "clear hub table");
     hip_check(hipMemsetAsync(rb.status, 0, sizeof(RunStatus), s), "clear status");
 }
 
-void launch_type_hash(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s) {
+void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s) {
     const uint32_t n = g.n;
-    k_type_hash<<<std::max<uint32_t>(ceil_div(n, kBlock), 1), kBlock, 0, s>>>(
-        g.type_off, g.type_ids, g.alive, n, untyped ? 1 : 0, rb.t, rb.h[0], rb.tab[0], rb.tab_mask,
-        rb.zflag + 0, rb.stripes);
-    hip_check(hipGetLastError(), "type hash launch");
+    k_init<<<std::max<uint32_t>(ceil_div(n, kBlock), 1), kBlock, 0, s>>>(
+        g.type_off, g.type_ids, g.alive, n, untyped ? 1 : 0, rb.t, rb.h[0], rb.rep, rb.tab[0], rb.lcnt,
+        rb.status);
+    hip_check(hipGetLastError(), "init launch");
 }
 
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
@@ -306,26 +501,21 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.h_prev = rb.h[(k - 1) & 1];
     a.h_next = rb.h[k & 1];
     a.alive = g.alive;
+    a.rep = rb.rep;
     a.tile_v0 = g.tile_v0;
     a.tile_v1 = g.tile_v1;
     a.hc_hub = g.hc_hub;
     a.hc_e0 = g.hc_e0;
     a.hub_v = g.hub_v;
-    a.hub_nchunks = g.hub_nchunks;
-    a.hub_tab_off = g.hub_tab_off;
-    a.hub_tab = rb.hub_tab;
-    a.hub_acc = rb.hub_acc;
-    a.hub_done = rb.hub_done;
-    a.tab_ins = rb.tab[k & 1];
-    a.tab_clr = rb.tab[(k + 1) & 1];
-    a.zflag_ins = rb.zflag + (k & 1);
-    a.zflag_clr = rb.zflag + ((k + 1) & 1);
-    a.stripes = rb.stripes;
+    a.hub_key_off = g.hub_key_off;
+    a.hub_keys = rb.hub_keys;
+    a.test_tab = rb.tab[(k - 1) & 1];
+    a.clr_tab = rb.tab[k & 1];
+    a.lcnt = rb.lcnt;
     a.totals = rb.totals;
     a.status = rb.status;
     a.n_tiles = g.n_tiles;
     a.n_hub_chunks = g.n_hub_chunks;
-    a.tab_mask = rb.tab_mask;
     a.k = k;
     a.k_max = k_max;
     a.stop = stop ? 1u : 0u;
@@ -335,6 +525,27 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     else
         k_iterate<uint32_t><<<grid, kBlock, 0, s>>>(a);
     hip_check(hipGetLastError(), "iteration launch");
+}
+
+void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s) {
+    if (g.n_hub_blocks == 0) return;
+    HubArgs a;
+    a.t = rb.t;
+    a.hub_keys = rb.hub_keys;
+    a.hub_key_off = g.hub_key_off;
+    a.hub_v = g.hub_v;
+    a.hub_deg = g.hub_deg;
+    a.hub_logb = g.hub_logb;
+    a.hb_hub = g.hb_hub;
+    a.hb_bucket = g.hb_bucket;
+    a.hub_acc = rb.hub_acc;
+    a.hub_done = rb.hub_done;
+    a.h_next = rb.h[k & 1];
+    a.status = rb.status;
+    a.table_slots = g.hub_table_slots;
+    a.table_limit = (g.hub_table_slots / 8) * 7;
+    k_hub<<<g.n_hub_blocks, kHubBlock, static_cast<size_t>(g.hub_table_slots) * 8, s>>>(a);
+    hip_check(hipGetLastError(), "hub launch");
 }
 
 }  // namespace bsim

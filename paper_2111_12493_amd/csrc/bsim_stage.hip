@@ -11,8 +11,9 @@
 //     starts of a tile lie in one kTileQuota window of edges and its last
 //     vertex has at most kTileQuota edges, so a tile holds < 2 kTileQuota
 //     edges;
-//   * a hub of degree d is cut into chunks of kTileMaxEdges edges and owns a
-//     region of 2*d slots of a global de-duplication table.
+//   * a hub of degree d is cut into chunks of kTileMaxEdges edges that write
+//     its mixed pair keys to d scratch slots, and into 2^b hash buckets that
+//     each fit the LDS table of the hub-bucket launch.
 #include <algorithm>
 #include <numeric>
 
@@ -339,47 +340,62 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
             return g.host_hub_deg[a] > g.host_hub_deg[b];
         });
-        std::vector<uint32_t> hv(g.n_hubs), hd(g.n_hubs), hn(g.n_hubs);
+        // a hub of degree d: ceil(d / kTileMaxEdges) chunk blocks, and 2^b
+        // bucket blocks so that a bucket expects at most 3/8 of the LDS slots
+        const uint64_t per_bucket = std::max<uint64_t>(1, (uint64_t(g.hub_table_slots) * 3) / 8);
+        std::vector<uint32_t> hv(g.n_hubs), hd(g.n_hubs), hl(g.n_hubs);
         std::vector<uint64_t> ho(g.n_hubs);
-        std::vector<uint32_t> ch, ce;
+        std::vector<uint32_t> ch, ce, bh, bb;
         std::vector<uint32_t> hstart(g.n_hubs);
-        uint64_t slots = 0;
+        uint64_t keys = 0;
         for (uint32_t i = 0; i < g.n_hubs; i++) {
             hv[i] = g.host_hub_v[order[i]];
             hd[i] = g.host_hub_deg[order[i]];
-            hn[i] = ceil_div(hd[i], kTileMaxEdges);
-            ho[i] = slots;
-            slots += 2 * static_cast<uint64_t>(hd[i]);
+            ho[i] = keys;
+            keys += hd[i];
+            const uint64_t want = (hd[i] + per_bucket - 1) / per_bucket;
+            hl[i] = static_cast<uint32_t>(bit_width(next_pow2(want)) - 1);
+            for (uint32_t b = 0; b < (1u << hl[i]); b++) {
+                bh.push_back(i);
+                bb.push_back(b);
+            }
         }
-        // first edge of every hub, then its chunks (largest hubs first)
-        uint32_t* hs_dev = arena.alloc<uint32_t>(g.n_hubs);
         uint32_t* hv_dev = arena.alloc<uint32_t>(g.n_hubs);
+        uint32_t* hs_dev = arena.alloc<uint32_t>(g.n_hubs);
         hip_check(hipMemcpyAsync(hv_dev, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, s), "hub v");
         k_hub_starts<<<ceil_div(g.n_hubs, kBlock), kBlock, 0, s>>>(g.row_off, hv_dev, g.n_hubs, hs_dev);
         hip_check(hipMemcpyAsync(hstart.data(), hs_dev, g.n_hubs * 4, hipMemcpyDeviceToHost, s), "hub starts");
         hip_check(hipStreamSynchronize(s), "hub starts sync");
         for (uint32_t i = 0; i < g.n_hubs; i++)
-            for (uint32_t c = 0; c < hn[i]; c++) {
+            for (uint32_t c = 0; c < ceil_div(hd[i], kTileMaxEdges); c++) {
                 ch.push_back(i);
                 ce.push_back(hstart[i] + c * kTileMaxEdges);
             }
         g.host_hub_v = hv;
         g.host_hub_deg = hd;
         g.n_hub_chunks = static_cast<uint32_t>(ch.size());
-        g.hub_tab_slots = slots;
+        g.n_hub_blocks = static_cast<uint32_t>(bh.size());
+        g.hub_keys_total = keys;
         g.hub_v = hv_dev;
-        g.hub_nchunks = arena.alloc<uint32_t>(g.n_hubs);
-        g.hub_tab_off = arena.alloc<uint64_t>(g.n_hubs);
+        g.hub_deg = arena.alloc<uint32_t>(g.n_hubs);
+        g.hub_logb = arena.alloc<uint32_t>(g.n_hubs);
+        g.hub_key_off = arena.alloc<uint64_t>(g.n_hubs);
         g.hc_hub = arena.alloc<uint32_t>(g.n_hub_chunks);
         g.hc_e0 = arena.alloc<uint32_t>(g.n_hub_chunks);
-        hip_check(hipMemcpyAsync(g.hub_nchunks, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, s), "hub n");
-        hip_check(hipMemcpyAsync(g.hub_tab_off, ho.data(), ho.size() * 8, hipMemcpyHostToDevice, s), "hub off");
+        g.hb_hub = arena.alloc<uint32_t>(g.n_hub_blocks);
+        g.hb_bucket = arena.alloc<uint32_t>(g.n_hub_blocks);
+        hip_check(hipMemcpyAsync(g.hub_deg, hd.data(), hd.size() * 4, hipMemcpyHostToDevice, s), "hub deg");
+        hip_check(hipMemcpyAsync(g.hub_logb, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s), "hub logb");
+        hip_check(hipMemcpyAsync(g.hub_key_off, ho.data(), ho.size() * 8, hipMemcpyHostToDevice, s), "hub off");
         hip_check(hipMemcpyAsync(g.hc_hub, ch.data(), ch.size() * 4, hipMemcpyHostToDevice, s), "hub chunks");
         hip_check(hipMemcpyAsync(g.hc_e0, ce.data(), ce.size() * 4, hipMemcpyHostToDevice, s), "hub chunk e0");
+        hip_check(hipMemcpyAsync(g.hb_hub, bh.data(), bh.size() * 4, hipMemcpyHostToDevice, s), "hub blocks");
+        hip_check(hipMemcpyAsync(g.hb_bucket, bb.data(), bb.size() * 4, hipMemcpyHostToDevice, s), "hub buckets");
         hip_check(hipStreamSynchronize(s), "hub schedule sync");
     } else {
         g.n_hub_chunks = 0;
-        g.hub_tab_slots = 0;
+        g.n_hub_blocks = 0;
+        g.hub_keys_total = 0;
     }
 
     // label salts

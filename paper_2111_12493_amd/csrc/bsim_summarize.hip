@@ -82,10 +82,11 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     const bool stop = (p.flags & BSIM_STOP_AT_FIXPOINT) != 0;
     const bool untyped = (p.flags & BSIM_UNTYPED) != 0;
     if (sink && !sink->levels.empty()) rb.h[0] = sink->levels[0];
-    launch_type_hash(g, rb, untyped, s);
+    launch_init(g, rb, untyped, s);
 
     LoopResult lr;
-    const uint64_t k_last = static_cast<uint64_t>(p.k_max) + 1;  // this launch always sees the cap
+    // launch k tests level k-2, so launch k_max + 2 always sees the cap
+    const uint64_t k_last = static_cast<uint64_t>(p.k_max) + 2;
     uint64_t k = 1;
     uint32_t chunk = 8;
     int pending = -1;
@@ -112,18 +113,17 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                         rb.h[(kk - 1) & 1] = sink->levels[std::min(kk - 1, top)];
                         rb.h[kk & 1] = sink->levels[std::min(kk, top)];
                     }
+                    hipEvent_t ea = nullptr, eb = nullptr;
                     if (ctx->time_launches) {
-                        hipEvent_t a, b;
-                        hip_check(hipEventCreate(&a), "event");
-                        hip_check(hipEventCreate(&b), "event");
-                        timers.push_back(a);
-                        timers.push_back(b);
-                        hip_check(hipEventRecord(a, s), "event");
-                        launch_iteration(g, rb, kk, p.k_max, stop, s);
-                        hip_check(hipEventRecord(b, s), "event");
-                    } else {
-                        launch_iteration(g, rb, kk, p.k_max, stop, s);
+                        hip_check(hipEventCreate(&ea), "event");
+                        hip_check(hipEventCreate(&eb), "event");
+                        timers.push_back(ea);
+                        timers.push_back(eb);
+                        hip_check(hipEventRecord(ea, s), "event");
                     }
+                    launch_iteration(g, rb, kk, p.k_max, stop, s);
+                    if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
+                    if (ctx->time_launches) hip_check(hipEventRecord(eb, s), "event");
                     lr.launches++;
                 }
                 const int slot = pending < 0 ? 0 : (pending ^ 1);
@@ -158,6 +158,8 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     }
     RunStatus st;
     hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
+    if (st.error & kErrZeroHash)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
     lr.k_done = st.k_done;
     lr.fixpoint = st.fixpoint;
     lr.blocks_per_iter.resize(static_cast<size_t>(lr.k_done) + 1);
@@ -243,6 +245,7 @@ bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_
     hip_check(hipEventRecord(ev[0], s), "event");
     Staged g;
     upload_graph(graph, g, arena, s);
+    g.hub_table_slots = ctx->hub_table_slots;
     RunStatus* stage_status = arena.alloc<RunStatus>(1);
     stage_graph(g, stage_status, &ctx->status_host[3], arena, s);
     RunBuffers rb;
@@ -251,7 +254,9 @@ bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_
     LoopResult lr = run_refinement(ctx, g, p, rb, nullptr, arena);
     hip_check(hipEventRecord(ev[2], s), "event");
     FinalOut fo;
-    finalize(g, lr.h_final, 0, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    finalize(g, rb.rep, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    if (fo.n_blocks != lr.blocks_per_iter.back())
+        throw DeviceError{BSIM_E_DEVICE, "internal: class count mismatch in finalize"};
     bsim_result* r = make_result(ctx, g, lr, lr.h_final, fo, keep, p.flags);
     hip_check(hipEventRecord(ev[3], s), "event");
     hip_check(hipEventSynchronize(ev[3]), "event");
