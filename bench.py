@@ -73,6 +73,9 @@ def main() -> int:
     ap.add_argument("--workload", default="rmat22_chains")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of this many MiB, so that a "
+                         "rocprofv3 counter run can scale FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (see DESIGN.md for how "
@@ -90,6 +93,16 @@ def main() -> int:
     gen_s = time.perf_counter() - t_gen
     print("# workload %s: %d vertices, %d edges (generated in %.1f s)" % (args.workload, g.n, g.m, gen_s),
           file=sys.stderr, flush=True)
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# calibration copy: %d bytes read, %d bytes written" % (nbytes, nbytes), file=sys.stderr,
+              flush=True)
+        del src, dst
     dg = binding.DeviceGraph(g)
     ctx = binding.Context(0)
     ctx.set_option("time_launches", 1)

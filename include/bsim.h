@@ -168,8 +168,10 @@ const char* bsim_status_string(int status);
 /* Run-time options (see bsim_option_names()): "chunk_max" = refinement
  * launches queued per stop-flag check (1..4096); "time_launches" = 1 to
  * bracket every refinement launch with HIP events and report the summed
- * kernel time in bsim_result.ms_iter_kernels.  Values outside the range
- * give BSIM_E_RANGE, unknown names BSIM_E_INVALID. */
+ * kernel time in bsim_result.ms_iter_kernels; "hub_table_slots" = LDS hash
+ * slots of a hub-bucket block (power of two from 64 to the device limit,
+ * the default; smaller values force more hash buckets per hub).  Values
+ * outside the range give BSIM_E_RANGE, unknown names BSIM_E_INVALID. */
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value);
 int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value);
 const char* bsim_option_names(void);

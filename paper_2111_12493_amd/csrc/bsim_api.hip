@@ -63,7 +63,8 @@ const char* bsim_last_error(const bsim_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 const char* bsim_option_names(void) {
     return "chunk_max (refinement launches queued per stop-flag check, 1..4096); "
-           "time_launches (0/1: time every refinement launch with HIP events)";
+           "time_launches (0/1: time every refinement launch with HIP events); "
+           "hub_table_slots (LDS slots of a hub-bucket block: power of two, 64..device limit)";
 }
 
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
@@ -78,6 +79,13 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
         ctx->time_launches = static_cast<uint32_t>(value);
         return BSIM_OK;
     }
+    if (!strcmp(name, "hub_table_slots")) {
+        // power of two between 64 and what the device's LDS allows
+        if (value < 64 || value > query_hub_table_slots(ctx->device, true) || (value & (value - 1)))
+            return BSIM_E_RANGE;
+        ctx->hub_table_slots = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
     return BSIM_E_INVALID;
 }
 
@@ -89,6 +97,10 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     }
     if (!strcmp(name, "time_launches")) {
         *value = ctx->time_launches;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "hub_table_slots")) {
+        *value = ctx->hub_table_slots;
         return BSIM_OK;
     }
     return BSIM_E_INVALID;

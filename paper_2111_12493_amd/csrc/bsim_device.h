@@ -96,6 +96,24 @@ __device__ __forceinline__ uint32_t lds_insert(uint64_t* tab, uint32_t slot, uin
     }
 }
 
+// Insert a nonzero key into an LDS table of `slots` slots, probing at most
+// `slots` positions: 1 = inserted, 0 = already present, 2 = table full.
+__device__ __forceinline__ uint32_t lds_insert_bounded(uint64_t* tab, uint32_t slot, uint32_t slots,
+                                                       uint64_t f) {
+    for (uint32_t step = 0; step < slots; step++) {
+        uint64_t cur = *reinterpret_cast<volatile uint64_t*>(&tab[slot]);
+        if (cur == f) return 0u;
+        if (cur == 0) {
+            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot]), 0ull,
+                                               static_cast<unsigned long long>(f));
+            if (old == 0ull) return 1u;
+            if (old == f) return 0u;
+        }
+        if (++slot == slots) slot = 0;
+    }
+    return 2u;
+}
+
 __device__ __forceinline__ void add_block_count(uint32_t* stripes, uint32_t k, uint32_t c) {
     if (c) atomicAdd(&stripes[(k & (kStripeRing - 1)) * kStripes + (blockIdx.x & (kStripes - 1))], c);
 }

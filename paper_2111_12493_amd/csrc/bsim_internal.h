@@ -32,9 +32,9 @@ constexpr uint64_t kCE = mix64(4);  // per-pair domain
 //
 // The refinement kernel works on "tiles": runs of consecutive vertices whose
 // out-edges are contiguous in the CSR.  A tile holds at most kTileMaxVerts
-// vertices and fewer than 2 * kTileQuota edges, so its per-vertex
+// vertices and fewer than kTileMaxEdges edges, so its per-vertex
 // de-duplication tables (two slots per edge) fit one block's LDS.  Vertices
-// with more than kTileQuota out-edges ("hubs") are cut into chunks of
+// with kTileMaxEdges or more out-edges ("hubs") are cut into chunks of
 // kTileMaxEdges edges whose blocks write their mixed pair keys to a per-hub
 // scratch area; a second launch de-duplicates each hub's keys in LDS, split
 // by the top key bits into buckets that fit a large LDS table.
@@ -48,13 +48,15 @@ constexpr uint64_t kCE = mix64(4);  // per-pair domain
 // late iteration of a long chain run inserts a handful of keys.
 
 constexpr int kBlock = 256;              // threads per block (4 wave64s)
-constexpr int kTileQuota = 1024;         // tile boundaries every kTileQuota edges
-constexpr int kTileMaxEdges = 2 * kTileQuota;
+constexpr int kTileMaxEdges = 2048;      // a tile holds fewer edges than this
 constexpr int kTileMaxVerts = 256;
 constexpr int kEdgesPerThread = kTileMaxEdges / kBlock;  // 8
 constexpr int kTableSlots = 2 * kTileMaxEdges;           // 4096 x 8 B = 32 KiB
-constexpr uint32_t kHubMinDegree = kTileQuota + 1;
+constexpr uint32_t kHubMinDegree = kTileMaxEdges;  // a hub would not fit an empty tile
 constexpr int kHubBlock = 512;           // threads per hub-bucket block
+constexpr int kMaxHubLogB = 8;           // at most 256 hash buckets per hub
+constexpr uint32_t kHubTableDefault = 4096;  // LDS slots per hub-bucket block (32 KiB)
+constexpr int kHubOffStride = (1 << kMaxHubLogB) + 1;  // bucket offsets per hub chunk
 constexpr int kStripes = 64;             // striped per-level claim counters
 constexpr int kStripeRing = 4;
 constexpr int kListPerStripe = 4096;     // claimed split-table slots remembered per stripe
@@ -75,6 +77,8 @@ struct RunStatus {
 constexpr uint32_t kErrInvalid = 1u;
 constexpr uint32_t kErrRange = 2u;
 constexpr uint32_t kErrZeroHash = 4u;   // more than kZeroSlots classes hashed to 0 at one level
+constexpr uint32_t kErrHubSplit = 8u;   // a hub bucket could not be split small enough
+constexpr uint32_t kMaxHubExtraBits = 24;  // re-split depth of an overflowing hub bucket
 
 // One slot of the split table: key = h^k, owner = ((rep + 1) << 32) | member.
 struct SplitSlot {
@@ -106,8 +110,10 @@ struct IterArgs {
     const uint32_t* hc_hub;     // hub chunk block -> hub index
     const uint32_t* hc_e0;      // hub chunk block -> first edge
     const uint32_t* hub_v;
+    const uint32_t* hub_logb;
     const uint64_t* hub_key_off;  // first scratch key of the hub
     uint64_t* hub_keys;
+    uint32_t* hub_boff;           // per hub chunk: kHubOffStride bucket offsets
     SplitTable test_tab;    // receives the split-offs of level k-1
     SplitTable clr_tab;     // filled at level k-2, cleared here
     uint32_t* lcnt;         // [kStripeRing][kStripes] claims per level
@@ -125,6 +131,10 @@ struct HubArgs {
     const uint64_t* t;
     const uint64_t* hub_keys;
     const uint64_t* hub_key_off;
+    const uint32_t* hub_boff;
+    const uint32_t* hub_chunk0;
+    const uint32_t* hub_nchunks;
+    const uint32_t* hc_e0;
     const uint32_t* hub_v;
     const uint32_t* hub_deg;
     const uint32_t* hub_logb;
@@ -231,6 +241,8 @@ struct Staged {
     uint32_t* hub_v = nullptr;       // by degree, descending
     uint32_t* hub_deg = nullptr;
     uint32_t* hub_logb = nullptr;
+    uint32_t* hub_chunk0 = nullptr;   // first chunk block of the hub
+    uint32_t* hub_nchunks = nullptr;
     uint64_t* hub_key_off = nullptr;
     uint64_t hub_keys_total = 0;
     uint32_t* hc_hub = nullptr;
@@ -257,6 +269,7 @@ struct RunBuffers {
     uint32_t* totals = nullptr;    // [k_cap]
     uint32_t k_cap = 0;
     uint64_t* hub_keys = nullptr;
+    uint32_t* hub_boff = nullptr;
     uint64_t* hub_acc = nullptr;
     uint32_t* hub_done = nullptr;
     RunStatus* status = nullptr;
@@ -276,7 +289,8 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
 void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s);
 
 // LDS slots the hub-bucket launch can use on this device.
-uint32_t query_hub_table_slots(int device);
+// device_max: the largest table the device allows (else the default size).
+uint32_t query_hub_table_slots(int device, bool device_max = false);
 
 // Finalize (a8): block ids, block sizes, sorted distinct quotient edges.
 struct FinalOut {

@@ -181,15 +181,34 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
     const uint32_t tid = threadIdx.x;
     const uint32_t v0 = a.tile_v0[tile], v1 = a.tile_v1[tile];
     const uint32_t nv = v1 - v0;
+    const uint32_t v = v0 + tid;
+    const bool mine = tid < nv;
+    // issue every per-vertex load that depends only on the tile range at once
+    const uint32_t ebase = a.row_off[v0];
+    uint32_t ro0 = 0, ro1 = 0, rv = v;
+    uint64_t hv_own = 0, tv = 0;
+    bool live = false;
+    if (tid <= nv) ro0 = a.row_off[v];
+    if (tid + kBlock <= nv) ro1 = a.row_off[v + kBlock];
+    if (mine) {
+        live = !a.alive || a.alive[v];
+        if (test) {
+            rv = a.rep[v];
+            hv_own = a.h_prev[v];
+        }
+        if (hash) tv = a.t[v];
+    }
     if (test) {
+        // split test of level k-1: leave the class of rep[v] if h^{k-1} differs
         uint32_t founded = 0, slot = 0xFFFFFFFFu;
-        if (tid < nv) split_test(a, v0 + tid, &founded, &slot);
+        if (mine && live && rv != v && hv_own != a.h_prev[rv])
+            a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, rv, hv_own, v, &founded, &slot, a.status));
         record_founders(a.test_tab, a.lcnt, a.k - 1, founded, slot, S.red, &S.ctl[1]);
     }
     if (!hash) return;
-    const uint32_t ebase = a.row_off[v0];
-    for (uint32_t i = tid; i <= nv; i += kBlock) S.off[i] = a.row_off[v0 + i] - ebase;
-    for (uint32_t i = tid; i < nv; i += kBlock) S.acc[i] = 0;
+    if (tid <= nv) S.off[tid] = ro0 - ebase;
+    if (tid + kBlock <= nv) S.off[tid + kBlock] = ro1 - ebase;
+    if (mine) S.acc[tid] = 0;
     __syncthreads();
     const uint32_t ne = S.off[nv];
     for (uint32_t j = tid; j < 2 * ne; j += kBlock) S.tab[j] = 0;
@@ -231,10 +250,7 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
         }
     }
     __syncthreads();
-    if (tid < nv) {
-        const uint32_t v = v0 + tid;
-        a.h_next[v] = (!a.alive || a.alive[v]) ? mix64(a.t[v] ^ mix64(kCS + S.acc[tid])) : 0;
-    }
+    if (mine) a.h_next[v] = live ? mix64(tv ^ mix64(kCS + S.acc[tid])) : 0;
 }
 
 template <typename LabT>
@@ -270,10 +286,44 @@ __device__ void hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, 
         const uint32_t j = tid + r * kBlock;
         if (j < ne) hv[r] = a.h_prev[w[r]] ^ a.salt[l[r]];
     }
+    // group the chunk's nonzero keys by hash bucket (top logb bits) so each
+    // hub-bucket block reads only its own keys; order within a bucket is free
+    const uint32_t logb = a.hub_logb[hi];
+    const uint32_t nb = 1u << logb;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(S.tab);
+    for (uint32_t b = tid; b <= nb; b += kBlock) hist[b] = 0;
+    __syncthreads();
+    uint64_t f[kEdgesPerThread];
+    uint32_t rank[kEdgesPerThread];
 #pragma unroll
     for (int r = 0; r < kEdgesPerThread; r++) {
         const uint32_t j = tid + r * kBlock;
-        if (j < ne) out[j] = mix64(hv[r] ^ kCE);
+        f[r] = j < ne ? mix64(hv[r] ^ kCE) : 0;
+        rank[r] = 0;
+        if (f[r] != 0) {
+            const uint32_t b = logb ? static_cast<uint32_t>(f[r] >> (64 - logb)) : 0u;
+            rank[r] = atomicAdd(&hist[b], 1u);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {  // exclusive prefix over at most 256 buckets
+        uint32_t run = 0;
+        for (uint32_t b = 0; b < nb; b++) {
+            const uint32_t c = hist[b];
+            hist[b] = run;
+            run += c;
+        }
+        hist[nb] = run;
+    }
+    __syncthreads();
+    uint32_t* boff = a.hub_boff + static_cast<uint64_t>(blk) * kHubOffStride;
+    for (uint32_t b = tid; b <= nb; b += kBlock) boff[b] = hist[b];
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++) {
+        if (f[r] != 0) {
+            const uint32_t b = logb ? static_cast<uint32_t>(f[r] >> (64 - logb)) : 0u;
+            out[hist[b] + rank[r]] = f[r];
+        }
     }
 }
 
@@ -351,63 +401,110 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
 
 // ------------------------------------------------------------ hub buckets
 
+constexpr int kMaxHubRuns = 256;  // chunk runs staged in LDS at a time
+
+// Stage the runs of chunks [cb, cb+ncb) of this bucket: s_src[i] = scratch
+// offset of run i, s_run = exclusive prefix of run lengths (s_run[ncb] = total).
+__device__ void stage_runs(const HubArgs& a, uint32_t c0, uint32_t cb, uint32_t ncb, uint32_t bucket,
+                           uint32_t e_first, uint32_t* s_run, uint32_t* s_src) {
+    const uint32_t tid = threadIdx.x;
+    __syncthreads();
+    if (tid < ncb) {
+        const uint32_t blk = c0 + cb + tid;
+        const uint32_t* boff = a.hub_boff + static_cast<uint64_t>(blk) * kHubOffStride;
+        s_src[tid] = (a.hc_e0[blk] - e_first) + boff[bucket];
+        s_run[tid + 1] = boff[bucket + 1] - boff[bucket];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_run[0] = 0;
+        for (uint32_t i = 1; i <= ncb; i++) s_run[i] += s_run[i - 1];
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(kHubBlock) k_hub(HubArgs a) {
     extern __shared__ uint64_t s_tab[];
     __shared__ uint64_t s_red64[kHubBlock / 64];
     __shared__ uint32_t s_ctl[4];
+    __shared__ uint32_t s_run[kMaxHubRuns + 1];   // prefix of run lengths
+    __shared__ uint32_t s_src[kMaxHubRuns];       // scratch offset of each run
     const uint32_t tid = threadIdx.x;
     if (*reinterpret_cast<volatile uint32_t*>(&a.status->done)) return;
     const uint32_t hi = a.hb_hub[blockIdx.x];
     const uint32_t bucket = a.hb_bucket[blockIdx.x];
     const uint32_t logb = a.hub_logb[hi];
-    const uint32_t d = a.hub_deg[hi];
+    const uint32_t c0 = a.hub_chunk0[hi], nc = a.hub_nchunks[hi];
     const uint64_t* __restrict__ keys = a.hub_keys + a.hub_key_off[hi];
     const uint32_t mask = a.table_slots - 1;
     volatile uint32_t* ctl = s_ctl;
+    const uint32_t e_first = a.hc_e0[c0];
 
+    // The bucket's keys form one run per chunk of the hub.  They are inserted
+    // into one LDS table (runs staged kMaxHubRuns chunks at a time).  Only
+    // distinct keys occupy slots; a bucket with more distinct keys than the
+    // table limit is re-split by further hash bits and re-read, which ends
+    // because distinct keys differ in some bit (depth capped for safety).
     uint64_t sum = 0;
     for (uint32_t extra = 0;; extra++) {
+        if (extra > kMaxHubExtraBits) {
+            if (tid == 0) atomicOr(&a.status->error, kErrHubSplit);
+            break;
+        }
         sum = 0;
         bool overflow = false;
         const uint32_t bits = logb + extra;
         for (uint32_t sub = 0; sub < (1u << extra) && !overflow; sub++) {
             const uint64_t want = (static_cast<uint64_t>(bucket) << extra) | sub;
+            __syncthreads();
             for (uint32_t j = tid; j < a.table_slots; j += kHubBlock) s_tab[j] = 0;
             if (tid == 0) {
-                ctl[1] = 0;  // reserved slots
+                ctl[1] = 0;  // distinct keys inserted
                 ctl[2] = 0;  // overflow
             }
-            __syncthreads();
-            for (uint32_t j0 = 0; j0 < d; j0 += 4 * kHubBlock) {
-                if (ctl[2]) break;
-                uint64_t f[4];
+            for (uint32_t cb = 0; cb < nc && !overflow; cb += kMaxHubRuns) {
+                const uint32_t ncb = min(static_cast<uint32_t>(kMaxHubRuns), nc - cb);
+                stage_runs(a, c0, cb, ncb, bucket, e_first, s_run, s_src);
+                const uint32_t total = s_run[ncb];
+                for (uint32_t j0 = 0; j0 < total; j0 += 4 * kHubBlock) {
+                    if (ctl[2]) break;
+                    uint64_t f[4];
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const uint32_t j = j0 + r * kHubBlock + tid;
-                    f[r] = j < d ? keys[j] : 0;
-                }
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    if (f[r] == 0) continue;
-                    if (bits && (f[r] >> (64 - bits)) != want) continue;
-                    // reserve first so the table never fills up
-                    if (atomicAdd(const_cast<uint32_t*>(&ctl[1]), 1u) >= a.table_limit) {
-                        ctl[2] = 1;
-                        break;
+                    for (int r = 0; r < 4; r++) {
+                        const uint32_t j = j0 + r * kHubBlock + tid;
+                        f[r] = 0;
+                        if (j < total) {
+                            // run containing j: binary search over the run prefix
+                            uint32_t lo = 0, hi2 = ncb;
+                            while (hi2 - lo > 1) {
+                                const uint32_t mid = (lo + hi2) >> 1;
+                                if (s_run[mid] <= j) lo = mid; else hi2 = mid;
+                            }
+                            f[r] = keys[s_src[lo] + (j - s_run[lo])];
+                        }
                     }
-                    const uint32_t slot = static_cast<uint32_t>(f[r]) & mask;
-                    if (lds_insert(s_tab, slot, 0, a.table_slots, f[r]))
-                        sum += f[r];
-                    else
-                        atomicSub(const_cast<uint32_t*>(&ctl[1]), 1u);
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        if (f[r] == 0) continue;
+                        if (extra && (f[r] >> (64 - bits)) != want) continue;
+                        const uint32_t got =
+                            lds_insert_bounded(s_tab, static_cast<uint32_t>(f[r]) & mask, a.table_slots, f[r]);
+                        if (got == 1u) {
+                            sum += f[r];
+                            // count distinct keys only: duplicates never overflow
+                            if (atomicAdd(const_cast<uint32_t*>(&ctl[1]), 1u) + 1 >= a.table_limit) ctl[2] = 1;
+                        } else if (got == 2u) {
+                            ctl[2] = 1;
+                        }
+                    }
                 }
+                __syncthreads();
+                overflow = ctl[2] != 0;
             }
-            __syncthreads();
-            overflow = ctl[2] != 0;
-            __syncthreads();
         }
         if (!overflow) break;
     }
+    __syncthreads();
     // block sum
     uint64_t x = wave_sum_u64(sum);
     if (lane_id() == 0) s_red64[tid >> 6] = x;
@@ -430,13 +527,14 @@ __global__ void __launch_bounds__(kHubBlock) k_hub(HubArgs a) {
 
 }  // namespace
 
-uint32_t query_hub_table_slots(int device) {
+uint32_t query_hub_table_slots(int device, bool device_max) {
     int bytes = 0;
     if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
         bytes = 65536;
-    // keep room for the block's static LDS; at most 128 KiB of table
+    // keep room for the block's static LDS.  Keys arrive grouped by bucket,
+    // so small tables cost no extra reads and let several blocks share a CU.
     uint64_t avail = bytes > 4096 ? static_cast<uint64_t>(bytes) - 4096 : 4096;
-    uint64_t slots = std::min<uint64_t>(avail / 8, 16384);
+    uint64_t slots = std::min<uint64_t>(avail / 8, device_max ? 16384 : kHubTableDefault);
     uint32_t p = 1;
     while (2ull * p <= slots) p <<= 1;
     return p;
@@ -472,6 +570,7 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
     rb.k_cap = static_cast<uint32_t>(kc) + 3;
     rb.totals = arena.alloc<uint32_t>(rb.k_cap);
     rb.hub_keys = arena.alloc<uint64_t>(g.hub_keys_total + 1);
+    rb.hub_boff = arena.alloc<uint32_t>((static_cast<size_t>(g.n_hub_chunks) + 1) * kHubOffStride);
     rb.hub_acc = arena.alloc<uint64_t>(g.n_hubs + 1);
     rb.hub_done = arena.alloc<uint32_t>(g.n_hubs + 1);
     rb.status = arena.alloc<RunStatus>(1);
@@ -507,8 +606,10 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.hc_hub = g.hc_hub;
     a.hc_e0 = g.hc_e0;
     a.hub_v = g.hub_v;
+    a.hub_logb = g.hub_logb;
     a.hub_key_off = g.hub_key_off;
     a.hub_keys = rb.hub_keys;
+    a.hub_boff = rb.hub_boff;
     a.test_tab = rb.tab[(k - 1) & 1];
     a.clr_tab = rb.tab[k & 1];
     a.lcnt = rb.lcnt;
@@ -533,6 +634,10 @@ void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t 
     a.t = rb.t;
     a.hub_keys = rb.hub_keys;
     a.hub_key_off = g.hub_key_off;
+    a.hub_boff = rb.hub_boff;
+    a.hub_chunk0 = g.hub_chunk0;
+    a.hub_nchunks = g.hub_nchunks;
+    a.hc_e0 = g.hc_e0;
     a.hub_v = g.hub_v;
     a.hub_deg = g.hub_deg;
     a.hub_logb = g.hub_logb;

@@ -4,13 +4,12 @@
 // Staging validates the CSR (paper Sec. 3.1 Phase 0 co-locates every vertex
 // with its out-edges; here that is the out-edge CSR itself), computes the
 // label salts, and cuts the vertex range into tiles and hub buckets:
-//   * a vertex with more than kTileQuota out-edges is a hub;
+//   * a vertex with kHubMinDegree or more out-edges (too many for one tile)
+//     is a hub;
 //   * every other vertex belongs to exactly one tile, a run of consecutive
-//     non-hub vertices cut wherever a multiple of kTileQuota edges is
-//     crossed, every kTileMaxVerts vertices, and around hubs.  All vertex
-//     starts of a tile lie in one kTileQuota window of edges and its last
-//     vertex has at most kTileQuota edges, so a tile holds < 2 kTileQuota
-//     edges;
+//     non-hub vertices packed greedily (within windows of kPackWindow
+//     vertices, one thread per window) up to kTileMaxEdges - 1 edges and
+//     kTileMaxVerts vertices; a non-hub vertex always fits an empty tile;
 //   * a hub of degree d is cut into chunks of kTileMaxEdges edges that write
 //     its mixed pair keys to d scratch slots, and into 2^b hash buckets that
 //     each fit the LDS table of the hub-bucket launch.
@@ -140,8 +139,8 @@ namespace {
 
 __global__ void __launch_bounds__(kBlock) k_stage_vertices(
     const uint32_t* __restrict__ row_off, const uint32_t* __restrict__ type_off,
-    const uint8_t* __restrict__ alive, uint32_t n, uint64_t m, uint32_t* __restrict__ bnd,
-    uint32_t* __restrict__ hubf, RunStatus* status) {
+    const uint8_t* __restrict__ alive, uint32_t n, uint64_t m, uint32_t* __restrict__ hubf,
+    RunStatus* status) {
     uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     const bool in = v < n;
     if (!in) v = n - 1;  // inactive lanes mirror the last vertex and store nothing
@@ -165,16 +164,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_vertices(
         for (int i = 1; i < kBlock / 64; i++) wmax = max(wmax, s_max[i]);
         if (wmax) atomicMax(&status->max_types, wmax);
     }
-    bool hub = (b >= a) && d > static_cast<uint32_t>(kTileQuota);
-    bool prev_hub = false;
-    bool cross = false;
-    if (v > 0) {
-        uint32_t pa = row_off[v - 1];
-        prev_hub = (a >= pa) && (a - pa) > static_cast<uint32_t>(kTileQuota);
-        cross = (a / kTileQuota) != (pa / kTileQuota);
-    }
+    bool hub = (b >= a) && d >= kHubMinDegree;
     if (in) {
-        bnd[v] = (v == 0 || hub || prev_hub || cross || (v % kTileMaxVerts) == 0) ? 1u : 0u;
         hubf[v] = hub ? 1u : 0u;
         if (err) atomicOr(&status->error, err);
     }
@@ -221,25 +212,56 @@ __global__ void __launch_bounds__(kBlock) k_compact_flags(const uint32_t* __rest
     if (v < n && flag[v]) out[pos[v]] = v;
 }
 
-// Tile p spans boundaries B[p]..B[p+1]; tiles that start at a hub are dropped.
-__global__ void __launch_bounds__(kBlock) k_tile_flags(const uint32_t* __restrict__ B, uint32_t nb,
-                                                       const uint32_t* __restrict__ hubf,
-                                                       uint32_t* __restrict__ keep) {
-    uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    if (p < nb) keep[p] = hubf[B[p]] ? 0u : 1u;
+// Greedy tile packing within windows of kPackWindow consecutive vertices
+// (one thread per window): a tile grows until the next vertex would bring it
+// to kTileMaxEdges edges or kTileMaxVerts vertices; hubs end a tile and
+// belong to none.  With emit == false only the tile count per window is
+// written (to cnt[w]); with emit == true tiles are written from pos[w] on.
+constexpr uint32_t kPackWindow = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_pack_tiles(const uint32_t* __restrict__ row_off, uint32_t n,
+                                                       bool emit, uint32_t* __restrict__ cnt,
+                                                       const uint32_t* __restrict__ pos,
+                                                       uint32_t* __restrict__ v0,
+                                                       uint32_t* __restrict__ v1) {
+    const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t vb64 = static_cast<uint64_t>(w) * kPackWindow;
+    if (vb64 >= n) return;
+    const uint32_t vb = static_cast<uint32_t>(vb64);
+    const uint32_t ve = static_cast<uint32_t>(min<uint64_t>(n, vb64 + kPackWindow));
+    uint32_t out = emit ? pos[w] : 0, made = 0;
+    uint32_t start = vb, edges = 0, verts = 0;
+    uint32_t a = row_off[vb];
+    for (uint32_t v = vb; v < ve; v++) {
+        const uint32_t b = row_off[v + 1];
+        const uint32_t d = b - a;
+        a = b;
+        if (d >= kHubMinDegree) {  // hub: close the tile, skip the vertex
+            if (verts) {
+                if (emit) { v0[out] = start; v1[out] = v; out++; }
+                made++;
+            }
+            start = v + 1;
+            edges = verts = 0;
+            continue;
+        }
+        if (verts == static_cast<uint32_t>(kTileMaxVerts) || edges + d >= static_cast<uint32_t>(kTileMaxEdges)) {
+            if (emit) { v0[out] = start; v1[out] = v; out++; }
+            made++;
+            start = v;
+            edges = verts = 0;
+        }
+        edges += d;
+        verts++;
+    }
+    if (verts) {
+        if (emit) { v0[out] = start; v1[out] = ve; out++; }
+        made++;
+    }
+    if (!emit) cnt[w] = made;
 }
 
-__global__ void __launch_bounds__(kBlock) k_tile_emit(const uint32_t* __restrict__ B, uint32_t nb,
-                                                      uint32_t n, const uint32_t* __restrict__ keep,
-                                                      const uint32_t* __restrict__ pos,
-                                                      uint32_t* __restrict__ v0,
-                                                      uint32_t* __restrict__ v1) {
-    uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    if (p < nb && keep[p]) {
-        v0[pos[p]] = B[p];
-        v1[pos[p]] = (p + 1 < nb) ? B[p + 1] : n;
-    }
-}
+
 
 __global__ void __launch_bounds__(kBlock) k_hub_degrees(const uint32_t* __restrict__ row_off,
                                                          const uint32_t* __restrict__ hubs,
@@ -266,13 +288,11 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
                  hipStream_t s) {
     const uint32_t n = g.n;
     hip_check(hipMemsetAsync(status_dev, 0, sizeof(RunStatus), s), "stage status");
-    uint32_t* bnd = arena.alloc<uint32_t>(n + 1);
     uint32_t* hubf = arena.alloc<uint32_t>(n + 1);
-    uint32_t* pos = arena.alloc<uint32_t>(n + 1);
     uint32_t* counts = arena.alloc<uint32_t>(4);
     if (n > 0) {
         k_stage_vertices<<<ceil_div(n, kBlock), kBlock, 0, s>>>(g.row_off, g.type_off, g.alive, n,
-                                                                g.m, bnd, hubf, status_dev);
+                                                                g.m, hubf, status_dev);
         if (g.m > 0) {
             uint32_t nbk = std::min<uint64_t>(ceil_div(g.m, kBlock), 2048);
             if (g.label_bytes == 2)
@@ -284,10 +304,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         }
         hip_check(hipGetLastError(), "stage launch");
     }
-    // boundaries -> B[], hubs -> hub list
-    scan_exclusive(bnd, pos, n, counts + 0, arena, s);
-    uint32_t* B = arena.alloc<uint32_t>(n + 1);
-    if (n) k_compact_flags<<<ceil_div(n, kBlock), kBlock, 0, s>>>(bnd, pos, n, B);
+    // hubs -> hub list
     uint32_t* hpos = arena.alloc<uint32_t>(n + 1);
     scan_exclusive(hubf, hpos, n, counts + 1, arena, s);
     uint32_t* hubs = arena.alloc<uint32_t>(n + 1);
@@ -301,28 +318,29 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         throw DeviceError{BSIM_E_RANGE, "edge target out of range"};
     if (status_host->error & kErrInvalid)
         throw DeviceError{BSIM_E_INVALID, "malformed CSR or an edge touching a dead vertex"};
-    if (status_host->max_types > (1u << 16))
-        throw DeviceError{BSIM_E_UNSUPPORTED, "more than 65536 type ids on one vertex"};
+    if (status_host->max_types > 4096)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "more than 4096 type ids on one vertex"};
     if (status_host->max_label >= (1u << 24))
         throw DeviceError{BSIM_E_UNSUPPORTED, "edge labels must be < 2^24"};
     g.max_label = status_host->max_label;
-    const uint32_t nb = hc[0];
     g.n_hubs = hc[1];
 
-    // tiles
-    uint32_t* keep = arena.alloc<uint32_t>(nb + 1);
-    uint32_t* tpos = arena.alloc<uint32_t>(nb + 1);
-    if (nb) k_tile_flags<<<ceil_div(nb, kBlock), kBlock, 0, s>>>(B, nb, hubf, keep);
-    scan_exclusive(keep, tpos, nb, counts + 2, arena, s);
+    // tiles: greedy packing per window of vertices
+    const uint32_t nwin = ceil_div(n, kPackWindow);
+    uint32_t* wcnt = arena.alloc<uint32_t>(nwin + 1);
+    uint32_t* wpos = arena.alloc<uint32_t>(nwin + 1);
+    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, n, false, wcnt, nullptr,
+                                                                      nullptr, nullptr);
+    scan_exclusive(wcnt, wpos, nwin, counts + 2, arena, s);
     uint32_t ntiles = 0;
     hip_check(hipMemcpyAsync(&ntiles, counts + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "tiles");
     hip_check(hipStreamSynchronize(s), "tiles sync");
     g.n_tiles = ntiles;
     g.tile_v0 = arena.alloc<uint32_t>(ntiles + 1);
     g.tile_v1 = arena.alloc<uint32_t>(ntiles + 1);
-    if (nb)
-        k_tile_emit<<<ceil_div(nb, kBlock), kBlock, 0, s>>>(B, nb, n, keep, tpos, g.tile_v0,
-                                                            g.tile_v1);
+    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, n, true, nullptr, wpos,
+                                                                      g.tile_v0, g.tile_v1);
+    hip_check(hipGetLastError(), "tile packing");
 
     // hubs: schedule on the host (few), largest first so long buckets start early
     g.host_hub_v.assign(g.n_hubs, 0);
@@ -341,8 +359,8 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
             return g.host_hub_deg[a] > g.host_hub_deg[b];
         });
         // a hub of degree d: ceil(d / kTileMaxEdges) chunk blocks, and 2^b
-        // bucket blocks so that a bucket expects at most 3/8 of the LDS slots
-        const uint64_t per_bucket = std::max<uint64_t>(1, (uint64_t(g.hub_table_slots) * 3) / 8);
+        // bucket blocks so that a bucket expects at most half the LDS slots
+        const uint64_t per_bucket = std::max<uint64_t>(1, uint64_t(g.hub_table_slots) / 2);
         std::vector<uint32_t> hv(g.n_hubs), hd(g.n_hubs), hl(g.n_hubs);
         std::vector<uint64_t> ho(g.n_hubs);
         std::vector<uint32_t> ch, ce, bh, bb;
@@ -354,7 +372,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
             ho[i] = keys;
             keys += hd[i];
             const uint64_t want = (hd[i] + per_bucket - 1) / per_bucket;
-            hl[i] = static_cast<uint32_t>(bit_width(next_pow2(want)) - 1);
+            hl[i] = std::min<uint32_t>(static_cast<uint32_t>(bit_width(next_pow2(want)) - 1), kMaxHubLogB);
             for (uint32_t b = 0; b < (1u << hl[i]); b++) {
                 bh.push_back(i);
                 bb.push_back(b);
@@ -366,11 +384,15 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         k_hub_starts<<<ceil_div(g.n_hubs, kBlock), kBlock, 0, s>>>(g.row_off, hv_dev, g.n_hubs, hs_dev);
         hip_check(hipMemcpyAsync(hstart.data(), hs_dev, g.n_hubs * 4, hipMemcpyDeviceToHost, s), "hub starts");
         hip_check(hipStreamSynchronize(s), "hub starts sync");
-        for (uint32_t i = 0; i < g.n_hubs; i++)
-            for (uint32_t c = 0; c < ceil_div(hd[i], kTileMaxEdges); c++) {
+        std::vector<uint32_t> hc0(g.n_hubs), hnc(g.n_hubs);
+        for (uint32_t i = 0; i < g.n_hubs; i++) {
+            hc0[i] = static_cast<uint32_t>(ch.size());
+            hnc[i] = ceil_div(hd[i], kTileMaxEdges);
+            for (uint32_t c = 0; c < hnc[i]; c++) {
                 ch.push_back(i);
                 ce.push_back(hstart[i] + c * kTileMaxEdges);
             }
+        }
         g.host_hub_v = hv;
         g.host_hub_deg = hd;
         g.n_hub_chunks = static_cast<uint32_t>(ch.size());
@@ -380,6 +402,10 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         g.hub_deg = arena.alloc<uint32_t>(g.n_hubs);
         g.hub_logb = arena.alloc<uint32_t>(g.n_hubs);
         g.hub_key_off = arena.alloc<uint64_t>(g.n_hubs);
+        g.hub_chunk0 = arena.alloc<uint32_t>(g.n_hubs);
+        g.hub_nchunks = arena.alloc<uint32_t>(g.n_hubs);
+        hip_check(hipMemcpyAsync(g.hub_chunk0, hc0.data(), hc0.size() * 4, hipMemcpyHostToDevice, s), "hub c0");
+        hip_check(hipMemcpyAsync(g.hub_nchunks, hnc.data(), hnc.size() * 4, hipMemcpyHostToDevice, s), "hub nc");
         g.hc_hub = arena.alloc<uint32_t>(g.n_hub_chunks);
         g.hc_e0 = arena.alloc<uint32_t>(g.n_hub_chunks);
         g.hb_hub = arena.alloc<uint32_t>(g.n_hub_blocks);

@@ -160,6 +160,8 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
     if (st.error & kErrZeroHash)
         throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
+    if (st.error & kErrHubSplit)
+        throw DeviceError{BSIM_E_DEVICE, "a hub hash bucket could not be split to fit its table"};
     lr.k_done = st.k_done;
     lr.fixpoint = st.fixpoint;
     lr.blocks_per_iter.resize(static_cast<size_t>(lr.k_done) + 1);

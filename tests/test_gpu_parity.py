@@ -98,9 +98,27 @@ def _hub_graph(seed, degs, n_extra=3000, n_labels=7, dup_every=5):
 
 def test_hub_vertices():
     # degrees around the tile limit and well above it (several buckets)
-    g = _hub_graph(7, [1023, 1024, 1025, 1536, 1537, 3100, 5000, 20000, 70000])
+    g = _hub_graph(7, [1023, 1024, 1025, 2046, 2047, 2048, 2049, 3100, 5000, 20000, 70000])
     check(g, UNB, what="hubs")
     check(g, 3, stop=False, untyped=True, what="hubs untyped")
+
+
+def test_hub_with_more_than_256_chunks():
+    # one hub of 600,000 edges: its bucket keys span more than one batch of runs
+    g = _hub_graph(8, [600_000, 3000], n_extra=20000, n_labels=5, dup_every=3)
+    check(g, 4, stop=False, what="600k hub")
+
+
+def test_hub_bucket_resplit():
+    # a tiny hub table forces buckets to overflow and re-split by more bits
+    c = ctx()
+    old = c.get_option("hub_table_slots")
+    try:
+        c.set_option("hub_table_slots", 64)
+        g = _hub_graph(9, [30000, 4000, 1500], n_extra=4000, n_labels=9, dup_every=4)
+        check(g, UNB, what="resplit")
+    finally:
+        c.set_option("hub_table_slots", old)
 
 
 def test_hub_with_few_distinct_keys():
@@ -119,6 +137,7 @@ def test_ragged_tiles_and_u16_labels():
     degs = np.zeros(5000, dtype=np.int64)
     degs[rng.integers(0, 5000, 300)] = rng.integers(1, 1025, 300)
     degs[::997] = 1024
+    degs[5::1499] = 2047  # the largest degree that still fits one tile
     src = np.repeat(np.arange(5000), degs)
     dst = rng.integers(0, 5000, size=src.size)
     lab = rng.integers(0, 40000, size=src.size)
