@@ -130,9 +130,11 @@ typedef struct {
     float ms_iterate;
     float ms_finalize;
     float ms_total;
-    float ms_iter_kernels; /* summed durations of the refinement launches when the
-                              ctx option "time_launches" is 1, else 0 */
-    uint32_t reserved;
+    float ms_iter_kernels; /* when the ctx option "time_launches" is 1: summed
+                              durations of the refinement-kernel launches that did
+                              work (launches 1..k_done+1; later ones return at
+                              once), else 0 */
+    float ms_hub_kernels;  /* the same for the hub-vertex launches */
     void* priv;
 } bsim_result;
 
@@ -167,8 +169,8 @@ const char* bsim_last_error(const bsim_ctx* ctx);
 const char* bsim_status_string(int status);
 /* Run-time options (see bsim_option_names()): "chunk_max" = refinement
  * launches queued per stop-flag check (1..4096); "time_launches" = 1 to
- * bracket every refinement launch with HIP events and report the summed
- * kernel time in bsim_result.ms_iter_kernels; "hub_table_slots" = LDS hash
+ * bracket every refinement and hub launch with HIP events and report the
+ * summed kernel times in bsim_result.ms_iter_kernels / ms_hub_kernels; "hub_table_slots" = LDS hash
  * slots of a hub-bucket block (power of two from 64 to the device limit,
  * the default; smaller values force more hash buckets per hub).  Values
  * outside the range give BSIM_E_RANGE, unknown names BSIM_E_INVALID. */

@@ -47,7 +47,8 @@ class BsimResult(ctypes.Structure):
                 ("blocks_per_iter", ctypes.POINTER(_u32)), ("se_src", _p), ("se_label", _p),
                 ("se_dst", _p), ("ms_stage", ctypes.c_float), ("ms_iterate", ctypes.c_float),
                 ("ms_finalize", ctypes.c_float), ("ms_total", ctypes.c_float),
-                ("ms_iter_kernels", ctypes.c_float), ("reserved", _u32), ("priv", _p)]
+                ("ms_iter_kernels", ctypes.c_float), ("ms_hub_kernels", ctypes.c_float),
+                ("priv", _p)]
 
 
 class BsimUpdate(ctypes.Structure):
@@ -226,6 +227,7 @@ class Result:
         self.ms_stage, self.ms_iterate = r.ms_stage, r.ms_iterate
         self.ms_finalize, self.ms_total = r.ms_finalize, r.ms_total
         self.ms_iter_kernels = r.ms_iter_kernels
+        self.ms_hub_kernels = r.ms_hub_kernels
 
     def _len(self, field):
         if field in ("hashes", "block_ids"):

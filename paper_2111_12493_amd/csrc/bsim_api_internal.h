@@ -45,7 +45,8 @@ struct LoopResult {
     uint32_t k_done = 0;
     uint32_t fixpoint = 0;
     uint32_t launches = 0;
-    float ms_kernels = 0.f;
+    float ms_kernels = 0.f;      // refinement launches that did work
+    float ms_hub_kernels = 0.f;  // hub launches of those iterations
     std::vector<uint32_t> blocks_per_iter;
     const uint64_t* h_final = nullptr;
 };

@@ -94,7 +94,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming), "event");
     bool done = false;
-    std::vector<hipEvent_t> timers;  // (start, end) per launch when timing launches
+    std::vector<hipEvent_t> timers;  // (start, after refinement, after hubs) per launch
     struct TimerGuard {
         std::vector<hipEvent_t>& t;
         ~TimerGuard() {
@@ -113,17 +113,18 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                         rb.h[(kk - 1) & 1] = sink->levels[std::min(kk - 1, top)];
                         rb.h[kk & 1] = sink->levels[std::min(kk, top)];
                     }
-                    hipEvent_t ea = nullptr, eb = nullptr;
+                    hipEvent_t et[3] = {nullptr, nullptr, nullptr};
                     if (ctx->time_launches) {
-                        hip_check(hipEventCreate(&ea), "event");
-                        hip_check(hipEventCreate(&eb), "event");
-                        timers.push_back(ea);
-                        timers.push_back(eb);
-                        hip_check(hipEventRecord(ea, s), "event");
+                        for (hipEvent_t& e : et) {
+                            hip_check(hipEventCreate(&e), "event");
+                            timers.push_back(e);
+                        }
+                        hip_check(hipEventRecord(et[0], s), "event");
                     }
                     launch_iteration(g, rb, kk, p.k_max, stop, s);
+                    if (ctx->time_launches) hip_check(hipEventRecord(et[1], s), "event");
                     if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
-                    if (ctx->time_launches) hip_check(hipEventRecord(eb, s), "event");
+                    if (ctx->time_launches) hip_check(hipEventRecord(et[2], s), "event");
                     lr.launches++;
                 }
                 const int slot = pending < 0 ? 0 : (pending ^ 1);
@@ -151,13 +152,17 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipStreamSynchronize(s), "loop sync");
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
-    for (size_t i = 0; i + 1 < timers.size(); i += 2) {
-        float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, timers[i], timers[i + 1]), "launch timer");
-        lr.ms_kernels += ms;
-    }
     RunStatus st;
     hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
+    // launch j (1-based) did work iff j <= k_done + 1: launch k_done + 2 finds
+    // the stop at level k_done and returns at once, as do all later ones
+    for (size_t i = 0; i + 2 < timers.size() && i / 3 < static_cast<size_t>(st.k_done) + 1; i += 3) {
+        float a = 0.f, b = 0.f;
+        hip_check(hipEventElapsedTime(&a, timers[i], timers[i + 1]), "launch timer");
+        hip_check(hipEventElapsedTime(&b, timers[i + 1], timers[i + 2]), "launch timer");
+        lr.ms_kernels += a;
+        lr.ms_hub_kernels += b;
+    }
     if (st.error & kErrZeroHash)
         throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
     if (st.error & kErrHubSplit)
@@ -191,6 +196,7 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
     r->n_summary_edges = fo.n_se;
     r->n_iter_launches = lr.launches;
     r->ms_iter_kernels = lr.ms_kernels;
+    r->ms_hub_kernels = lr.ms_hub_kernels;
     r->blocks_per_iter = p->blocks_per_iter.data();
     uint64_t* hashes = keep.alloc<uint64_t>(g.n);
     if (g.n) hip_check(hipMemcpyAsync(hashes, h, static_cast<size_t>(g.n) * 8, hipMemcpyDeviceToDevice, s),
