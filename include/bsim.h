@@ -209,8 +209,14 @@ int bsim_result_copy(const bsim_result* result, const char* field, void* dst,
 int bsim_apply_updates(bsim_state* state, const bsim_update* ops, uint64_t n_ops,
                        bsim_result** out);
 /* Current graph of a state as host CSR arrays (for checking); the caller
- * frees them with bsim_host_free. */
+ * frees each array (row_off, targets, labels, type_off, type_ids, alive)
+ * with bsim_host_free.  Rows list surviving old edges first, in their old
+ * order, then the edges the batches added. */
 int bsim_state_graph(const bsim_state* state, bsim_graph* out_host_graph);
+/* The same graph as borrowed device pointers (mem_kind DEVICE), valid until
+ * the next bsim_apply_updates or bsim_state_free on this state; it can be
+ * passed to bsim_summarize (full recomputation of the updated graph). */
+int bsim_state_device_graph(const bsim_state* state, bsim_graph* out_device_graph);
 void bsim_host_free(void* p);
 void bsim_state_free(bsim_state* state);
 

@@ -1,0 +1,80 @@
+"""Sequential application of an update batch to a graph -- test
+infrastructure, like the rest of oracle/.
+
+The change classes of Sec. 3.2 (a summary or payload element added,
+modified or deleted) arise from these operations on the data graph:
+
+  ("add_v", types)          new vertex with id n and the given type set
+  ("mod_v", u, types)       replace the type set of u
+  ("del_v", u)              delete u: its types and every edge into or out of it
+  ("add_e", u, l, w)        add the triple (u, l, w) unless it already exists
+  ("del_e", u, l, w)        delete every copy of (u, l, w) (no-op when absent)
+  ("mod_e", u, l, w, l2)    ("del_e", u, l, w) then ("add_e", u, l2, w)
+
+Operations apply one after the other; one that names a vertex id not yet
+created raises IndexError, one that names a deleted vertex raises ValueError.
+Vertex ids are stable: a deleted vertex keeps its id and is marked dead.
+By Theorem 2 the incremental summary after the batch equals the batch
+summary of the graph this returns.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2111_12493_amd.graphgen import Graph
+
+
+def apply_ops(g: Graph, ops) -> Graph:
+    n = g.n
+    alive = [True] * n if g.alive is None else [bool(x) for x in g.alive]
+    types = [[int(x) for x in g.typ[g.typ_off[v]:g.typ_off[v + 1]]] for v in range(n)]
+    out = [[(int(l), int(w)) for l, w in zip(g.lab[g.row_off[v]:g.row_off[v + 1]],
+                                              g.tgt[g.row_off[v]:g.row_off[v + 1]])] for v in range(n)]
+
+    def live(v):
+        if v >= len(alive):
+            raise IndexError("vertex %d does not exist" % v)
+        if not alive[v]:
+            raise ValueError("vertex %d is deleted" % v)
+
+    for o in ops:
+        kind = o[0]
+        if kind == "add_v":
+            types.append([int(x) for x in o[1]])
+            alive.append(True)
+            out.append([])
+        elif kind == "mod_v":
+            live(o[1])
+            types[o[1]] = [int(x) for x in o[2]]
+        elif kind == "del_v":
+            u = o[1]
+            live(u)
+            alive[u] = False
+            types[u] = []
+            out[u] = []
+            for s in range(len(out)):
+                if out[s]:
+                    out[s] = [e for e in out[s] if e[1] != u]
+        elif kind in ("add_e", "del_e", "mod_e"):
+            u, l, w = o[1], o[2], o[3]
+            live(u)
+            live(w)
+            if kind != "add_e":
+                out[u] = [e for e in out[u] if e != (l, w)]
+            if kind != "del_e":
+                ln = o[4] if kind == "mod_e" else l
+                if (ln, w) not in out[u]:
+                    out[u].append((ln, w))
+        else:
+            raise ValueError("unknown op " + str(kind))
+    n = len(out)
+    row_off = np.zeros(n + 1, dtype=np.uint64)
+    row_off[1:] = np.cumsum([len(r) for r in out]) if n else []
+    tgt = np.array([w for r in out for (_, w) in r], dtype=np.uint32)
+    lab = np.array([l for r in out for (l, _) in r], dtype=g.lab.dtype)
+    typ_off = np.zeros(n + 1, dtype=np.uint64)
+    typ_off[1:] = np.cumsum([len(t) for t in types]) if n else []
+    typ = np.array([x for t in types for x in t], dtype=np.uint32)
+    return Graph(n=n, row_off=row_off, tgt=tgt, lab=lab, typ_off=typ_off, typ=typ,
+                 alive=np.array(alive, dtype=np.uint8), n_labels=g.n_labels, n_types=g.n_types)

@@ -71,6 +71,7 @@ EXPORTS = {
     "bsim_apply_updates": (ctypes.c_int, [_p, ctypes.POINTER(BsimUpdate), _u64,
                                           ctypes.POINTER(ctypes.POINTER(BsimResult))]),
     "bsim_state_graph": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph)]),
+    "bsim_state_device_graph": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph)]),
     "bsim_host_free": (None, [_p]),
     "bsim_state_free": (None, [_p]),
     "bsim_batch_summarize": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), _u32,
@@ -274,3 +275,150 @@ def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: b
     ctx.check(lib().bsim_summarize(ctx.handle, ctypes.byref(gs), ctypes.byref(params), None,
                                    ctypes.byref(out)))
     return Result(out)
+
+
+# ---------------------------------------------------------------- update batches
+
+UPDATE_DTYPE = np.dtype({"names": ["op", "u", "w", "label", "new_label", "n_types", "types"],
+                         "formats": [np.uint32] * 6 + [np.uint64],
+                         "offsets": [0, 4, 8, 12, 16, 20, 24], "itemsize": 32})
+assert UPDATE_DTYPE.itemsize == ctypes.sizeof(BsimUpdate)
+
+OP_CODES = {"add_v": OP_ADD_V, "mod_v": OP_MOD_V, "del_v": OP_DEL_V, "add_e": OP_ADD_E,
+            "mod_e": OP_MOD_E, "del_e": OP_DEL_E}
+
+
+class UpdateBatch:
+    """An ordered batch of update operations laid out as bsim_update[].
+
+    Built from tuples: ("add_v", types), ("mod_v", u, types), ("del_v", u),
+    ("add_e", u, label, w), ("mod_e", u, label, w, new_label), ("del_e", u, label, w).
+    """
+
+    def __init__(self, ops: Sequence[tuple]):
+        n = len(ops)
+        self.arr = np.zeros(max(n, 1), dtype=UPDATE_DTYPE)[:n]
+        lists = []
+        for i, o in enumerate(ops):
+            kind = o[0]
+            rec = self.arr[i]
+            rec["op"] = OP_CODES[kind]
+            if kind == "add_v":
+                lists.append((i, o[1]))
+            elif kind in ("mod_v", "del_v"):
+                rec["u"] = o[1]
+                if kind == "mod_v":
+                    lists.append((i, o[2]))
+            else:
+                rec["u"], rec["label"], rec["w"] = o[1], o[2], o[3]
+                if kind == "mod_e":
+                    rec["new_label"] = o[4]
+        sizes = [len(t) for _, t in lists]
+        self.types = np.zeros(max(sum(sizes), 1), dtype=np.uint32)
+        pos = 0
+        for (i, t), c in zip(lists, sizes):
+            self.types[pos:pos + c] = np.asarray(t, dtype=np.uint32)
+            self.arr[i]["n_types"] = c
+            self.arr[i]["types"] = self.types.ctypes.data + 4 * pos
+            pos += c
+
+    @classmethod
+    def from_op_arrays(cls, d: dict) -> "UpdateBatch":
+        """From the arrays of graphgen.update_ops (op, u, w, label, new_label, t_off, t_ids)."""
+        n = len(d["op"])
+        arr = np.zeros(max(n, 1), dtype=UPDATE_DTYPE)[:n]
+        for f in ("op", "u", "w", "label", "new_label"):
+            arr[f] = d[f]
+        types = np.ascontiguousarray(d["t_ids"], dtype=np.uint32)
+        if types.size == 0:
+            types = np.zeros(1, dtype=np.uint32)
+        t_off = np.asarray(d["t_off"], dtype=np.uint64)
+        arr["n_types"] = np.diff(t_off).astype(np.uint32)
+        arr["types"] = np.uint64(types.ctypes.data) + 4 * t_off[:-1]
+        return cls.from_arrays(arr, types)
+
+    @classmethod
+    def from_arrays(cls, arr: np.ndarray, types: np.ndarray) -> "UpdateBatch":
+        """Wrap a prepared UPDATE_DTYPE array whose type pointers index `types`."""
+        b = cls.__new__(cls)
+        b.arr, b.types = arr, types
+        return b
+
+    def __len__(self):
+        return len(self.arr)
+
+
+class State:
+    """A resident incremental state (bsim_summarize with state_out), with its
+    first result in ``self.result``."""
+
+    def __init__(self, ctx: Context, graph, k_max: int, stop_at_fixpoint: bool = False,
+                 untyped: bool = False, summary_edges: bool = True):
+        flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
+                (0 if summary_edges else NO_SUMMARY_EDGES)
+        self.ctx = ctx
+        gs = graph.struct()
+        params = BsimParams(int(k_max), flags)
+        out = ctypes.POINTER(BsimResult)()
+        h = _p()
+        ctx.check(lib().bsim_summarize(ctx.handle, ctypes.byref(gs), ctypes.byref(params), ctypes.byref(h),
+                                       ctypes.byref(out)))
+        self.handle = h
+        self.result = Result(out)
+
+    def apply(self, batch: UpdateBatch) -> Result:
+        out = ctypes.POINTER(BsimResult)()
+        ptr = batch.arr.ctypes.data_as(ctypes.POINTER(BsimUpdate)) if len(batch) else None
+        self.ctx.check(lib().bsim_apply_updates(self.handle, ptr, len(batch), ctypes.byref(out)))
+        return Result(out)
+
+    def graph(self):
+        """The state's current graph as a host graphgen.Graph."""
+        from . import graphgen as gg
+        g = BsimGraph()
+        self.ctx.check(lib().bsim_state_graph(self.handle, ctypes.byref(g)))
+        n, m = g.n_vertices, g.n_edges
+
+        def take(ptr, count, dt):
+            a = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(np.ctypeslib.as_ctypes_type(dt))),
+                                      shape=(max(count, 1),))[:count].copy()
+            return a
+
+        try:
+            row_off = take(g.row_off, n + 1, np.uint32).astype(np.uint64)
+            tgt = take(g.targets, m, np.uint32)
+            lab = take(g.labels, m, np.uint16 if g.label_bytes == 2 else np.uint32)
+            typ_off = take(g.type_off, n + 1, np.uint32).astype(np.uint64)
+            typ = take(g.type_ids, int(typ_off[-1]) if n + 1 else 0, np.uint32)
+            alive = take(g.alive, n, np.uint8)
+        finally:
+            for p in (g.row_off, g.targets, g.labels, g.type_off, g.type_ids, g.alive):
+                lib().bsim_host_free(p)
+        return gg.Graph(n=n, row_off=row_off, tgt=tgt, lab=lab, typ_off=typ_off, typ=typ, alive=alive)
+
+    def device_graph(self) -> BsimGraph:
+        g = BsimGraph()
+        self.ctx.check(lib().bsim_state_device_graph(self.handle, ctypes.byref(g)))
+        return g
+
+    def free(self):
+        if getattr(self, "handle", None):
+            self.result.free()
+            lib().bsim_state_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class _Borrowed:
+    """A bsim_graph struct passed through as is (e.g. a state's device view)."""
+
+    def __init__(self, gs: BsimGraph):
+        self.gs = gs
+
+    def struct(self) -> BsimGraph:
+        return self.gs

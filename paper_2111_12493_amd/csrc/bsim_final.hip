@@ -133,6 +133,19 @@ __global__ void __launch_bounds__(kBlock) k_edge_keys(
 constexpr int kSortItems = 4;
 constexpr int kSortTile = kBlock * kSortItems;
 
+// Edge keys from a COO source array (graphs without a tile schedule).
+template <typename LabT>
+__global__ void __launch_bounds__(kBlock) k_edge_keys_coo(const uint32_t* __restrict__ src,
+                                                          const uint32_t* __restrict__ tgt,
+                                                          const LabT* __restrict__ lab,
+                                                          const uint32_t* __restrict__ bid, uint32_t m,
+                                                          int lb, int bb, uint64_t* __restrict__ keys) {
+    const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= m) return;
+    keys[e] = (static_cast<uint64_t>(bid[src[e]]) << (lb + bb)) |
+              (static_cast<uint64_t>(lab[e]) << bb) | bid[tgt[e]];
+}
+
 __global__ void __launch_bounds__(kBlock) k_sort_hist(const uint64_t* __restrict__ in, uint32_t m,
                                                       int shift, uint32_t nblk,
                                                       uint32_t* __restrict__ hist) {
@@ -215,8 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_unpack(const uint64_t* __restrict__ 
 
 // Sort m keys ascending on bits [0, bits); returns the buffer holding the
 // result (a or b).
-static uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Arena& arena,
-                            hipStream_t s) {
+uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Arena& arena, hipStream_t s) {
     if (m <= 1) return a;
     const uint32_t nblk = ceil_div(m, kSortTile);
     uint32_t* hist = arena.alloc<uint32_t>(static_cast<size_t>(nblk) * 256);
@@ -270,7 +282,14 @@ void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& o
     uint64_t* ka = arena.alloc<uint64_t>(m);
     uint64_t* kb = arena.alloc<uint64_t>(m);
     const uint32_t grid = std::max<uint32_t>(g.n_hubs + g.n_tiles, 1);
-    if (g.label_bytes == 2)
+    if (g.src) {
+        if (g.label_bytes == 2)
+            k_edge_keys_coo<uint16_t><<<ceil_div(m, kBlock), kBlock, 0, s>>>(
+                g.src, g.tgt, static_cast<const uint16_t*>(g.lab), out.block_ids, m, lb, bb, ka);
+        else
+            k_edge_keys_coo<uint32_t><<<ceil_div(m, kBlock), kBlock, 0, s>>>(
+                g.src, g.tgt, static_cast<const uint32_t*>(g.lab), out.block_ids, m, lb, bb, ka);
+    } else if (g.label_bytes == 2)
         k_edge_keys<uint16_t><<<grid, kBlock, 0, s>>>(g.row_off, g.tgt,
                                                       static_cast<const uint16_t*>(g.lab), out.block_ids,
                                                       g.tile_v0, g.tile_v1, g.n_tiles, g.hub_v, g.n_hubs,

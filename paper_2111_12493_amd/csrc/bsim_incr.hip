@@ -1,26 +1,1444 @@
-// bsim_incr.hip -- incremental summarization (resident state, update batches).
+// bsim_incr.hip -- incremental summarization (a9): a resident state that keeps
+// the graph and every level h^0..h^K in HBM, and update batches that re-hash
+// only the vertices a change can reach (Sec. 3.2; Theorem 2 states that the
+// result then equals a batch run on the updated graph).
+//
+// State layout (device): the out-edges as CSR plus a per-edge source array
+// (COO order = CSR order), the type lists likewise, a reverse adjacency
+// (in-neighbour lists) that may hold stale extra entries, the alive mask and
+// the levels.  Vertex ids are stable: deleted vertices keep their id, with
+// no edges, no types, hash 0 and no block.
+//
+// An update batch:
+//   1. host: validate the ordered operations and resolve them into the net
+//      change of every touched (u, label, w) triple -- "deleted" (some
+//      deletion of the triple happened, so its old copies go) and
+//      "present" (the triple exists at the end) -- plus the final type set of
+//      every touched vertex;
+//   2. device: rebuild the CSR (edge-parallel: old edges that survive are
+//      moved by a prefix sum, new triples are appended to their row), the
+//      type lists and the reverse adjacency;
+//   3. device: level 0 recomputes t(v) for the vertices whose types changed;
+//      level j recomputes h^j on the frontier F_j = B u in(C_{j-1}), where B
+//      holds the vertices whose own inputs changed (types or out-edge set)
+//      and C_{j-1} the vertices whose h^{j-1} changed.  Every other vertex
+//      keeps h^j: all its inputs are unchanged;
+//   4. device: classes of levels 0..K from the stored levels, the fixpoint
+//      rule, and finalize (block ids, sizes, summary edges) as in batch.
+#include <algorithm>
+#include <cstring>
+#include <unordered_map>
+
 #include "bsim_api_internal.h"
+#include "bsim_device.h"
+
+using namespace bsim;
 
 namespace bsim {
+namespace {
 
-int summarize_with_state(bsim_ctx* ctx, const bsim_graph&, const bsim_params&, bsim_state**,
-                         bsim_result**) {
-    ctx->err = "incremental state not available in this build";
-    return BSIM_E_UNSUPPORTED;
+constexpr uint32_t kFlagRows = 1u;    // dflag: the out-edge row is rebuilt
+constexpr uint32_t kFlagTypes = 2u;   // dflag: the type list is replaced
+constexpr uint32_t kChgDeleted = 1u;  // change flags
+constexpr uint32_t kChgPresent = 2u;
+constexpr uint32_t kSmallDeg = 512;   // frontier vertices handled by one wave
+constexpr uint32_t kWaveSlots = 1024; // LDS de-dup slots per wave (>= 2 * kSmallDeg)
+constexpr uint32_t kChunkEdges = 4096;  // edges per block of a large frontier vertex
+constexpr uint32_t kFrontGrid = 2048;   // blocks of the frontier kernels (grid-stride)
+constexpr uint32_t kMaxStateTypes = 4096;
+
+// Device counters of one update batch.
+struct IncCounters {
+    uint32_t b_count;      // base frontier list
+    uint32_t f_count;      // frontier of the current level
+    uint32_t c_count[2];   // changed vertices of a level (by parity)
+    uint32_t big_count;    // large frontier vertices deferred to chunk blocks
+    uint32_t chunk_count;
+    uint64_t slot_top;     // scratch table slots handed out
+};
+
+struct BigEntry {
+    uint32_t v;
+    uint32_t chunk0;
+    uint32_t nchunks;
+    uint32_t slots;
+    uint64_t slot0;
+};
+
+__device__ __forceinline__ uint32_t next_pow2_dev(uint32_t x) {
+    return x <= 1 ? 1u : 1u << (32 - __clz(static_cast<int>(x - 1)));
+}
+
+__device__ __forceinline__ void wave_append(bool pred, uint32_t val, uint32_t* list, uint32_t* count) {
+    const uint64_t b = __ballot(pred);
+    if (!b) return;
+    const uint32_t lane = lane_id();
+    const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(b)) - 1);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, static_cast<uint32_t>(__popcll(b)));
+    base = static_cast<uint32_t>(__shfl(static_cast<int>(base), static_cast<int>(leader), 64));
+    if (pred) list[base + static_cast<uint32_t>(__popcll(b & ((1ull << lane) - 1)))] = val;
+}
+
+// Set mark[v] once; the first setter appends v to the list.
+__device__ __forceinline__ void mark_append(bool valid, uint32_t v, uint32_t* mark, uint32_t* list,
+                                            uint32_t* count) {
+    bool first = false;
+    if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) == 0) first = atomicOr(&mark[v], 1u) == 0;
+    wave_append(first, v, list, count);
+}
+
+// t(v) of one vertex from its type list (set semantics), as at level 0 of a run.
+__device__ uint64_t type_hash(const uint32_t* ids, uint32_t a, uint32_t b, bool untyped) {
+    uint64_t sum = 0;
+    if (!untyped) {
+        for (uint32_t i = a; i < b; i++) {
+            const uint32_t tau = ids[i];
+            bool dup = false;
+            for (uint32_t j = a; j < i && !dup; j++) dup = ids[j] == tau;
+            if (!dup) sum += mix64(kCT ^ static_cast<uint64_t>(tau));
+        }
+    }
+    return mix64(kCT + sum);
+}
+
+// ---------------------------------------------------------------- staging
+
+__global__ void k_coo_owner(const uint32_t* __restrict__ off, uint32_t n, uint64_t m,
+                            uint32_t* __restrict__ own) {
+    const uint64_t e = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= m) return;
+    uint32_t lo = 0, hi = n;  // largest v with off[v] <= e
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= e) lo = mid; else hi = mid;
+    }
+    own[e] = lo;
+}
+
+__global__ void k_salt_table(uint64_t* salt, uint32_t count) {
+    const uint32_t l = blockIdx.x * kBlock + threadIdx.x;
+    if (l < count) salt[l] = mix64(kCL + static_cast<uint64_t>(l));
+}
+
+__global__ void k_alive_all(uint8_t* alive, const uint8_t* src, uint32_t n) {
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v < n) alive[v] = src ? (src[v] ? 1 : 0) : 1;
+}
+
+// Reverse adjacency from keys (target << 32 | source) sorted ascending.
+__global__ void k_rev_split(const uint64_t* __restrict__ keys, uint32_t m, uint32_t* __restrict__ own,
+                            uint32_t* __restrict__ srcs) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    own[i] = static_cast<uint32_t>(keys[i] >> 32);
+    srcs[i] = static_cast<uint32_t>(keys[i]);
+}
+
+// rev_off[w] = first entry whose owner is >= w, for w = 0..n.
+__global__ void k_rev_offsets(const uint32_t* __restrict__ own, uint32_t m, uint32_t n,
+                              uint32_t* __restrict__ off) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i > m) return;
+    const uint32_t hi = i < m ? own[i] : n;
+    const int64_t lo = i > 0 ? static_cast<int64_t>(own[i - 1]) : -1;
+    for (int64_t w = lo + 1; w <= static_cast<int64_t>(hi); w++) off[w] = i;
+}
+
+__global__ void k_edge_keys_rev(const uint32_t* __restrict__ src, const uint32_t* __restrict__ tgt,
+                                uint32_t m, uint64_t* __restrict__ keys) {
+    const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e < m) keys[e] = (static_cast<uint64_t>(tgt[e]) << 32) | src[e];
+}
+
+// ---------------------------------------------------------------- marking
+
+__global__ void k_set_dead(const uint32_t* __restrict__ dead, uint32_t nd, uint8_t* alive) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < nd) alive[dead[i]] = 0;
+}
+
+// Explicit change groups: per source u its range of changes; u's row is rebuilt.
+__global__ void k_mark_groups(const uint32_t* __restrict__ gsrc, const uint32_t* __restrict__ gbeg,
+                              const uint32_t* __restrict__ gend, uint32_t ng, uint32_t* dflag,
+                              uint32_t* chg_lo, uint32_t* chg_hi, uint32_t* bmark, uint32_t* blist,
+                              IncCounters* cnt) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < ng;
+    uint32_t u = 0;
+    if (valid) {
+        u = gsrc[i];
+        atomicOr(&dflag[u], kFlagRows);
+        chg_lo[u] = gbeg[i];
+        chg_hi[u] = gend[i];
+    }
+    mark_append(valid, u, bmark, blist, &cnt->b_count);
+}
+
+__global__ void k_clear_groups(const uint32_t* __restrict__ gsrc, uint32_t ng, uint32_t* chg_lo,
+                               uint32_t* chg_hi) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < ng) {
+        chg_lo[gsrc[i]] = 0;
+        chg_hi[gsrc[i]] = 0;
+    }
+}
+
+// A deleted vertex d: its own row goes, and every in-neighbour's row is
+// rebuilt without the edges to d (one wave per deleted vertex).
+__global__ void k_mark_dead(const uint32_t* __restrict__ dead, uint32_t nd,
+                            const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
+                            uint32_t n_rev, uint32_t* dflag, uint32_t* bmark, uint32_t* blist,
+                            IncCounters* cnt) {
+    const uint32_t lane = lane_id();
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    if (wave >= nd) return;
+    const uint32_t d = dead[wave];
+    if (lane == 0) atomicOr(&dflag[d], kFlagRows);
+    if (d >= n_rev) return;
+    const uint32_t a = rev_off[d], b = rev_off[d + 1];
+    for (uint32_t j0 = a; j0 < b; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        const bool valid = j < b;
+        uint32_t s = 0;
+        if (valid) {
+            s = rev_src[j];
+            if ((*reinterpret_cast<volatile uint32_t*>(&dflag[s]) & kFlagRows) == 0)
+                atomicOr(&dflag[s], kFlagRows);
+        }
+        mark_append(valid, s, bmark, blist, &cnt->b_count);
+    }
+}
+
+// Vertices whose type set changes (new, modified, deleted).
+__global__ void k_mark_types(const uint32_t* __restrict__ tl, uint32_t nT, uint32_t* dflag,
+                             uint32_t* tidx, uint32_t* bmark, uint32_t* blist, IncCounters* cnt) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < nT;
+    uint32_t v = 0;
+    if (valid) {
+        v = tl[i];
+        atomicOr(&dflag[v], kFlagTypes);
+        tidx[v] = i + 1;
+    }
+    mark_append(valid, v, bmark, blist, &cnt->b_count);
+}
+
+__global__ void k_clear_tidx(const uint32_t* __restrict__ tl, uint32_t nT, uint32_t* tidx) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < nT) tidx[tl[i]] = 0;
+}
+
+// ---------------------------------------------------------------- out-edge merge
+
+// keep[e] (written to kpos before the scan): does old edge e survive?
+template <typename LabT>
+__global__ void k_fwd_keep(const uint32_t* __restrict__ src, const uint32_t* __restrict__ tgt,
+                           const LabT* __restrict__ lab, uint32_t m, const uint32_t* __restrict__ dflag,
+                           const uint8_t* __restrict__ alive, const uint32_t* __restrict__ chg_lo,
+                           const uint32_t* __restrict__ chg_hi, const uint32_t* __restrict__ cw,
+                           const uint32_t* __restrict__ cl, const uint32_t* __restrict__ cf,
+                           uint32_t* __restrict__ exist, uint32_t* __restrict__ keep) {
+    const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t v = src[e];
+    uint32_t k = 1;
+    if (dflag[v] & kFlagRows) {
+        const uint32_t w = tgt[e];
+        if (!alive[v] || !alive[w]) {
+            k = 0;
+        } else {
+            uint32_t lo = chg_lo[v], hi = chg_hi[v];
+            const uint32_t l = static_cast<uint32_t>(lab[e]);
+            // changes of v are sorted by (w, l)
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t mw = cw[mid], ml = cl[mid];
+                if (mw < w || (mw == w && ml < l)) lo = mid + 1; else hi = mid;
+            }
+            if (lo < chg_hi[v] && cw[lo] == w && cl[lo] == l) {
+                if (cf[lo] & kChgDeleted) k = 0;
+                else exist[lo] = 1;
+            }
+        }
+    }
+    keep[e] = k;
+}
+
+// Is change c appended as a new edge?
+__global__ void k_app_flags(const uint32_t* __restrict__ cf, const uint32_t* __restrict__ exist,
+                            uint32_t nc, uint32_t* __restrict__ app) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= nc) return;
+    const uint32_t f = cf[c];
+    app[c] = ((f & kChgPresent) && ((f & kChgDeleted) || !exist[c])) ? 1u : 0u;
+}
+
+__global__ void k_fwd_deg(uint32_t n_new, uint32_t n_old, const uint32_t* __restrict__ off_old,
+                          const uint32_t* __restrict__ kpos, const uint32_t* __restrict__ chg_lo,
+                          const uint32_t* __restrict__ chg_hi, const uint32_t* __restrict__ apos,
+                          uint32_t* __restrict__ kept, uint32_t* __restrict__ deg) {
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_new) return;
+    const uint32_t k = v < n_old ? kpos[off_old[v + 1]] - kpos[off_old[v]] : 0u;
+    const uint32_t a = apos[chg_hi[v]] - apos[chg_lo[v]];
+    kept[v] = k;
+    deg[v] = k + a;
+}
+
+template <typename LabT>
+__global__ void k_fwd_copy(const uint32_t* __restrict__ src, const uint32_t* __restrict__ tgt,
+                           const LabT* __restrict__ lab, uint32_t m, const uint32_t* __restrict__ off_old,
+                           const uint32_t* __restrict__ kpos, const uint32_t* __restrict__ off_new,
+                           uint32_t* __restrict__ src2, uint32_t* __restrict__ tgt2, LabT* __restrict__ lab2) {
+    const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t ke = kpos[e];
+    if (kpos[e + 1] == ke) return;
+    const uint32_t v = src[e];
+    const uint32_t p = off_new[v] + (ke - kpos[off_old[v]]);
+    src2[p] = v;
+    tgt2[p] = tgt[e];
+    lab2[p] = lab[e];
+}
+
+template <typename LabT>
+__global__ void k_fwd_append(const uint32_t* __restrict__ cu, const uint32_t* __restrict__ cw,
+                             const uint32_t* __restrict__ cl, uint32_t nc, const uint32_t* __restrict__ apos,
+                             const uint32_t* __restrict__ off_new, const uint32_t* __restrict__ kept,
+                             const uint32_t* __restrict__ chg_lo, uint32_t* __restrict__ src2,
+                             uint32_t* __restrict__ tgt2, LabT* __restrict__ lab2) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= nc || apos[c + 1] == apos[c]) return;
+    const uint32_t u = cu[c];
+    const uint32_t p = off_new[u] + kept[u] + (apos[c] - apos[chg_lo[u]]);
+    src2[p] = u;
+    tgt2[p] = cw[c];
+    lab2[p] = static_cast<LabT>(cl[c]);
+}
+
+// ---------------------------------------------------------------- type lists
+
+__global__ void k_typ_keep(const uint32_t* __restrict__ own, uint32_t nt, const uint32_t* __restrict__ dflag,
+                           uint32_t* __restrict__ keep) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < nt) keep[i] = (dflag[own[i]] & kFlagTypes) ? 0u : 1u;
+}
+
+__global__ void k_typ_deg(uint32_t n_new, uint32_t n_old, const uint32_t* __restrict__ off_old,
+                          const uint32_t* __restrict__ kpos, const uint32_t* __restrict__ tidx,
+                          const uint32_t* __restrict__ tl_off, uint32_t* __restrict__ deg) {
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_new) return;
+    const uint32_t ti = tidx[v];
+    if (ti) deg[v] = tl_off[ti] - tl_off[ti - 1];
+    else deg[v] = v < n_old ? kpos[off_old[v + 1]] - kpos[off_old[v]] : 0u;
+}
+
+__global__ void k_typ_copy(const uint32_t* __restrict__ own, const uint32_t* __restrict__ ids, uint32_t nt,
+                           const uint32_t* __restrict__ off_old, const uint32_t* __restrict__ kpos,
+                           const uint32_t* __restrict__ off_new, uint32_t* __restrict__ own2,
+                           uint32_t* __restrict__ ids2) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nt) return;
+    const uint32_t ki = kpos[i];
+    if (kpos[i + 1] == ki) return;
+    const uint32_t v = own[i];
+    const uint32_t p = off_new[v] + (ki - kpos[off_old[v]]);
+    own2[p] = v;
+    ids2[p] = ids[i];
+}
+
+__global__ void k_typ_write(const uint32_t* __restrict__ tl, uint32_t nT, const uint32_t* __restrict__ tl_off,
+                            const uint32_t* __restrict__ tl_ids, const uint32_t* __restrict__ off_new,
+                            uint32_t* __restrict__ own2, uint32_t* __restrict__ ids2) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nT) return;
+    const uint32_t v = tl[i];
+    const uint32_t p = off_new[v];
+    for (uint32_t j = tl_off[i]; j < tl_off[i + 1]; j++) {
+        own2[p + j - tl_off[i]] = v;
+        ids2[p + j - tl_off[i]] = tl_ids[j];
+    }
+}
+
+// Level 0 on the vertices whose types changed: C_0 = those whose t changed.
+__global__ void k_level0(const uint32_t* __restrict__ tl, uint32_t nT, const uint32_t* __restrict__ type_off,
+                         const uint32_t* __restrict__ type_ids, const uint8_t* __restrict__ alive,
+                         int untyped, uint64_t* __restrict__ t, uint32_t* clist, IncCounters* cnt) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    bool changed = false;
+    uint32_t v = 0;
+    if (i < nT) {
+        v = tl[i];
+        const uint64_t tv = alive[v] ? type_hash(type_ids, type_off[v], type_off[v + 1], untyped != 0) : 0;
+        if (tv != t[v]) {
+            t[v] = tv;
+            changed = true;
+        }
+    }
+    wave_append(changed, v, clist, &cnt->c_count[0]);
+}
+
+// ---------------------------------------------------------------- reverse lists
+
+__global__ void k_rev_deg(uint32_t n_new, uint32_t n_old, const uint32_t* __restrict__ off_old,
+                          const uint32_t* __restrict__ r_lo, const uint32_t* __restrict__ r_hi,
+                          uint32_t* __restrict__ deg) {
+    const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
+    if (w >= n_new) return;
+    deg[w] = (w < n_old ? off_old[w + 1] - off_old[w] : 0u) + (r_hi[w] - r_lo[w]);
+}
+
+__global__ void k_rev_copy(const uint32_t* __restrict__ own, const uint32_t* __restrict__ srcs, uint32_t rm,
+                           const uint32_t* __restrict__ off_old, const uint32_t* __restrict__ off_new,
+                           uint32_t* __restrict__ own2, uint32_t* __restrict__ srcs2) {
+    const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= rm) return;
+    const uint32_t w = own[e];
+    const uint32_t p = off_new[w] + (e - off_old[w]);
+    own2[p] = w;
+    srcs2[p] = srcs[e];
+}
+
+__global__ void k_rev_append(const uint32_t* __restrict__ rw, const uint32_t* __restrict__ ru, uint32_t nr,
+                             uint32_t n_old, const uint32_t* __restrict__ off_old,
+                             const uint32_t* __restrict__ off_new, const uint32_t* __restrict__ r_lo,
+                             uint32_t* __restrict__ own2, uint32_t* __restrict__ srcs2) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= nr) return;
+    const uint32_t w = rw[c];
+    const uint32_t od = w < n_old ? off_old[w + 1] - off_old[w] : 0u;
+    const uint32_t p = off_new[w] + od + (c - r_lo[w]);
+    own2[p] = w;
+    srcs2[p] = ru[c];
+}
+
+// ---------------------------------------------------------------- frontier levels
+
+__global__ void k_level_reset(IncCounters* cnt, uint32_t parity) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cnt->f_count = 0;
+        cnt->c_count[parity] = 0;
+        cnt->big_count = 0;
+        cnt->chunk_count = 0;
+        cnt->slot_top = 0;
+    }
+}
+
+// F_j starts as the base set B.
+__global__ void k_front_base(const uint32_t* __restrict__ blist, const IncCounters* cnt_in, uint32_t* fmark,
+                             uint32_t* flist, IncCounters* cnt) {
+    const uint32_t nb = cnt_in->b_count;
+    for (uint32_t i0 = blockIdx.x * kBlock; i0 < nb; i0 += gridDim.x * kBlock) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool valid = i < nb;
+        mark_append(valid, valid ? blist[i] : 0u, fmark, flist, &cnt->f_count);
+    }
+}
+
+// F_j grows by the in-neighbours of C_{j-1} (one wave per changed vertex).
+__global__ void k_front_innbrs(const uint32_t* __restrict__ clist, const IncCounters* cnt_in, uint32_t parity,
+                               const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
+                               uint32_t* fmark, uint32_t* flist, IncCounters* cnt) {
+    const uint32_t nc = cnt_in->c_count[parity];
+    const uint32_t lane = lane_id();
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < nc; i += waves) {
+        const uint32_t w = clist[i];
+        const uint32_t a = rev_off[w], b = rev_off[w + 1];
+        for (uint32_t j0 = a; j0 < b; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const bool valid = j < b;
+            mark_append(valid, valid ? rev_src[j] : 0u, fmark, flist, &cnt->f_count);
+        }
+    }
+}
+
+struct FrontArgs {
+    const uint32_t* row_off;
+    const uint32_t* tgt;
+    const void* lab;
+    const uint64_t* t;
+    const uint64_t* salt;
+    const uint64_t* h_prev;
+    uint64_t* h_cur;
+    const uint8_t* alive;
+    const uint32_t* flist;
+    uint32_t* clist;
+    IncCounters* cnt;
+    BigEntry* big;
+    uint32_t* chunk_owner;
+    uint64_t* big_acc;
+    uint32_t* big_done;
+    uint64_t* scratch;
+    uint32_t parity;
+};
+
+__device__ __forceinline__ void publish(const FrontArgs& a, uint32_t v, uint64_t h) {
+    if (a.h_cur[v] != h) {
+        a.h_cur[v] = h;
+        const uint32_t pos = atomicAdd(&a.cnt->c_count[a.parity], 1u);
+        a.clist[pos] = v;
+    }
+}
+
+// h^j of every frontier vertex: one wave per vertex of degree <= kSmallDeg,
+// de-duplicating its pair keys in a wave-private LDS region; larger vertices
+// are deferred to chunk blocks with a global table.
+template <typename LabT>
+__global__ void __launch_bounds__(kBlock) k_front_hash(FrontArgs a) {
+    __shared__ uint64_t s_tab[kBlock / 64][kWaveSlots];
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    volatile uint64_t* tab = s_tab[wid];
+    const uint32_t nf = a.cnt->f_count;
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
+    for (uint32_t i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < nf; i += waves) {
+        const uint32_t v = a.flist[i];
+        if (!a.alive[v]) {
+            if (lane == 0) publish(a, v, 0);
+            continue;
+        }
+        const uint32_t e0 = a.row_off[v], deg = a.row_off[v + 1] - e0;
+        if (deg > kSmallDeg) {
+            if (lane == 0) {
+                const uint32_t nch = (deg + kChunkEdges - 1) / kChunkEdges;
+                const uint32_t slots = next_pow2_dev(2 * deg);
+                const uint32_t bi = atomicAdd(&a.cnt->big_count, 1u);
+                const uint32_t c0 = atomicAdd(&a.cnt->chunk_count, nch);
+                const uint64_t s0 = atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt->slot_top),
+                                              static_cast<unsigned long long>(slots));
+                a.big[bi] = BigEntry{v, c0, nch, slots, s0};
+                a.big_acc[bi] = 0;
+                a.big_done[bi] = 0;
+                for (uint32_t c = 0; c < nch; c++) a.chunk_owner[c0 + c] = bi;
+            }
+            continue;
+        }
+        const uint32_t slots = max(64u, next_pow2_dev(2 * deg));
+        for (uint32_t j = lane; j < slots; j += 64) tab[j] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t acc = 0;
+        for (uint32_t j = lane; j < deg; j += 64) {
+            const uint32_t w = a.tgt[e0 + j];
+            const uint32_t l = static_cast<uint32_t>(lab[e0 + j]);
+            const uint64_t f = mix64((a.h_prev[w] ^ a.salt[l]) ^ kCE);
+            if (f != 0 && lds_insert(const_cast<uint64_t*>(tab), static_cast<uint32_t>(f) & (slots - 1), 0,
+                                     slots, f))
+                acc += f;
+        }
+        acc = wave_sum_u64(acc);
+        if (lane == 0) publish(a, v, mix64(a.t[v] ^ mix64(kCS + acc)));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+__global__ void k_big_clear(IncCounters* cnt, uint64_t* scratch) {
+    const uint64_t top = cnt->slot_top;
+    for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; j < top;
+         j += static_cast<uint64_t>(gridDim.x) * kBlock)
+        scratch[j] = 0;
+}
+
+template <typename LabT>
+__global__ void __launch_bounds__(kBlock) k_big_chunks(FrontArgs a) {
+    __shared__ uint64_t s_red[kBlock / 64];
+    __shared__ uint32_t s_last;
+    const uint32_t nch = a.cnt->chunk_count;
+    const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const uint32_t bi = a.chunk_owner[c];
+        const BigEntry be = a.big[bi];
+        const uint32_t v = be.v;
+        const uint32_t vb = a.row_off[v], ve = a.row_off[v + 1];
+        const uint32_t e0 = vb + (c - be.chunk0) * kChunkEdges;
+        const uint32_t e1 = min(ve, e0 + kChunkEdges);
+        uint64_t* tab = a.scratch + be.slot0;
+        const uint32_t mask = be.slots - 1;
+        uint64_t acc = 0;
+        for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+            const uint32_t w = a.tgt[e];
+            const uint32_t l = static_cast<uint32_t>(lab[e]);
+            const uint64_t f = mix64((a.h_prev[w] ^ a.salt[l]) ^ kCE);
+            if (f == 0) continue;
+            uint32_t slot = static_cast<uint32_t>(f) & mask;
+            for (;;) {
+                uint64_t cur = *reinterpret_cast<volatile uint64_t*>(&tab[slot]);
+                if (cur == f) break;
+                if (cur == 0) {
+                    cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot]), 0ull,
+                                    static_cast<unsigned long long>(f));
+                    if (cur == 0) {
+                        acc += f;
+                        break;
+                    }
+                    if (cur == f) break;
+                }
+                slot = (slot + 1) & mask;
+            }
+        }
+        const uint64_t sum = block_sum_u64(acc, s_red);
+        if (threadIdx.x == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.big_acc[bi]), static_cast<unsigned long long>(sum));
+            __threadfence();
+            s_last = atomicAdd(&a.big_done[bi], 1u) == be.nchunks - 1 ? 1u : 0u;
+            if (s_last) {
+                __threadfence();
+                const uint64_t total = atomicAdd(reinterpret_cast<unsigned long long*>(&a.big_acc[bi]), 0ull);
+                publish(a, v, mix64(a.t[v] ^ mix64(kCS + total)));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+}  // namespace bsim
+
+// ======================================================================== host
+
+namespace bsim {
+namespace {
+
+// A device array owned by a resident state; grows by copying.
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t cap = 0;
+    void ensure(size_t n, size_t keep, hipStream_t s) {
+        if (p && n <= cap) return;
+        const size_t nc = std::max<size_t>({n, cap + cap / 2, 64});
+        T* q = nullptr;
+        if (hipMallocAsync(reinterpret_cast<void**>(&q), nc * sizeof(T), s) != hipSuccess)
+            throw DeviceError{BSIM_E_NOMEM, "state allocation of " + std::to_string(nc * sizeof(T)) + " bytes failed"};
+        if (p && keep)
+            hip_check(hipMemcpyAsync(q, p, std::min(keep, cap) * sizeof(T), hipMemcpyDeviceToDevice, s), "state grow");
+        if (p) (void)hipFreeAsync(p, s);
+        p = q;
+        cap = nc;
+    }
+    void release(hipStream_t s) {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+template <typename T>
+T* upload(Arena& arena, const std::vector<T>& v, hipStream_t s) {
+    T* d = arena.alloc<T>(v.size() + 1);
+    if (!v.empty()) hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+    return d;
+}
+
+inline uint32_t grid_for(uint64_t n) { return std::max<uint32_t>(ceil_div(n, kBlock), 1); }
+
+// Net effect of one update batch, resolved on the host.
+struct HostBatch {
+    uint32_t n_new = 0;
+    std::vector<uint32_t> cu, cw, cl, cf;      // changed triples, sorted by (u, w, l)
+    std::vector<uint32_t> gsrc, gbeg, gend;    // change range of every source
+    std::vector<uint32_t> rw, ru;              // reverse-list additions, sorted by (w, u)
+    std::vector<uint32_t> rgw, rgbeg, rgend;
+    std::vector<uint32_t> tl, tl_off, tl_ids;  // vertices with a new type set (sorted) and the sets
+    std::vector<uint32_t> dead;                // vertices deleted by the batch
+    uint32_t max_label = 0;
+    uint64_t n_present = 0;                    // changes that end present (upper bound of appends)
+};
+
+}  // namespace
+}  // namespace bsim
+
+struct bsim_state {
+    bsim_ctx* ctx = nullptr;
+    hipStream_t s = nullptr;
+    uint32_t K = 0, flags = 0, label_bytes = 4;
+    bool untyped = false;
+    uint32_t n = 0, n_rev = 0;
+    uint64_t m = 0, nt = 0, rm = 0;
+    uint32_t max_label = 0;
+    int cur = 0, tcur = 0, rcur = 0;
+    DevBuf<uint32_t> row_off[2], src[2], tgt[2];
+    DevBuf<uint8_t> lab[2];
+    DevBuf<uint32_t> type_off[2], type_own[2], type_ids[2];
+    DevBuf<uint32_t> rev_off[2], rev_own[2], rev_src[2];
+    DevBuf<uint8_t> alive;
+    std::vector<DevBuf<uint64_t>> levels;
+    DevBuf<uint64_t> salt;
+    DevBuf<uint32_t> rep, dflag, bmark, fmark, chg_lo, chg_hi, tidx, kept, deg, blist, flist, clist[2];
+    SplitSlot* cls_slots = nullptr;
+    uint64_t* cls_zero = nullptr;
+    uint32_t* cls_list = nullptr;
+    uint32_t cls_cap = 0;  // power of two
+    DevBuf<uint32_t> cls_cnt, kpos, chunk_owner, big_done;
+    DevBuf<BigEntry> big;
+    DevBuf<uint64_t> big_acc, scratch;
+    DevBuf<IncCounters> cnt;
+    DevBuf<RunStatus> status;
+    std::vector<uint8_t> alive_host;
+    std::vector<uint32_t> blocks_per_iter;
+
+    void release() {
+        for (int i = 0; i < 2; i++) {
+            row_off[i].release(s), src[i].release(s), tgt[i].release(s), lab[i].release(s);
+            type_off[i].release(s), type_own[i].release(s), type_ids[i].release(s);
+            rev_off[i].release(s), rev_own[i].release(s), rev_src[i].release(s);
+            clist[i].release(s);
+        }
+        alive.release(s);
+        for (auto& l : levels) l.release(s);
+        salt.release(s), rep.release(s), dflag.release(s), bmark.release(s), fmark.release(s);
+        chg_lo.release(s), chg_hi.release(s), tidx.release(s), kept.release(s), deg.release(s);
+        blist.release(s), flist.release(s), cls_cnt.release(s), kpos.release(s), chunk_owner.release(s);
+        big_done.release(s), big.release(s), big_acc.release(s), scratch.release(s), cnt.release(s);
+        status.release(s);
+        if (cls_slots) (void)hipFreeAsync(cls_slots, s);
+        if (cls_zero) (void)hipFreeAsync(cls_zero, s);
+        if (cls_list) (void)hipFreeAsync(cls_list, s);
+        cls_slots = nullptr, cls_zero = nullptr, cls_list = nullptr;
+        (void)hipStreamSynchronize(s);
+    }
+};
+
+namespace bsim {
+namespace {
+
+// Vertex-indexed arrays for n vertices (kept contents: the first n_keep).
+void ensure_vertices(bsim_state* st, uint32_t n_new) {
+    hipStream_t s = st->s;
+    const size_t nv = static_cast<size_t>(n_new) + 1;
+    const size_t keep_v = st->n, keep_o = static_cast<size_t>(st->n) + 1;
+    st->row_off[st->cur].ensure(nv, keep_o, s);
+    st->row_off[st->cur ^ 1].ensure(nv, 0, s);
+    st->type_off[st->tcur].ensure(nv, keep_o, s);
+    st->type_off[st->tcur ^ 1].ensure(nv, 0, s);
+    st->rev_off[st->rcur].ensure(nv, static_cast<size_t>(st->n_rev) + 1, s);
+    st->rev_off[st->rcur ^ 1].ensure(nv, 0, s);
+    st->alive.ensure(nv, keep_v, s);
+    for (auto& l : st->levels) l.ensure(nv, keep_v, s);
+    // chg_lo / chg_hi / tidx are zero outside a batch: keep them
+    st->chg_lo.ensure(nv, keep_v, s);
+    st->chg_hi.ensure(nv, keep_v, s);
+    st->tidx.ensure(nv, keep_v, s);
+    for (DevBuf<uint32_t>* b : {&st->rep, &st->dflag, &st->bmark, &st->fmark, &st->kept, &st->deg,
+                                &st->blist, &st->flist, &st->clist[0], &st->clist[1], &st->big_done,
+                                &st->chunk_owner})
+        b->ensure(nv, 0, s);
+    st->big.ensure(nv, 0, s);
+    st->big_acc.ensure(nv, 0, s);
+    const uint32_t want = next_pow2(std::max<uint64_t>(2ull * n_new, 1024));
+    if (want > st->cls_cap) {
+        if (st->cls_slots) (void)hipFreeAsync(st->cls_slots, s);
+        if (st->cls_list) (void)hipFreeAsync(st->cls_list, s);
+        st->cls_slots = nullptr, st->cls_list = nullptr;
+        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_slots), sizeof(SplitSlot) * want, s), "class table");
+        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_list), 4ull * want, s), "class list");
+        hip_check(hipMemsetAsync(st->cls_slots, 0, sizeof(SplitSlot) * want, s), "class table clear");
+        st->cls_cap = want;
+    }
+    if (!st->cls_zero) {
+        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_zero), 8 * kZeroSlots, s), "zero slots");
+        hip_check(hipMemsetAsync(st->cls_zero, 0, 8 * kZeroSlots, s), "zero slots clear");
+    }
+}
+
+void ensure_salt(bsim_state* st, uint32_t max_label) {
+    if (st->salt.p && max_label < st->salt.cap) return;
+    const uint32_t count = next_pow2(static_cast<uint64_t>(max_label) + 1);
+    st->salt.ensure(count, 0, st->s);
+    k_salt_table<<<grid_for(st->salt.cap), kBlock, 0, st->s>>>(st->salt.p, static_cast<uint32_t>(st->salt.cap));
+    hip_check(hipGetLastError(), "salt launch");
+}
+
+uint32_t read_u32(const uint32_t* dev, hipStream_t s) {
+    uint32_t v = 0;
+    hip_check(hipMemcpyAsync(&v, dev, 4, hipMemcpyDeviceToHost, s), "read count");
+    hip_check(hipStreamSynchronize(s), "read count sync");
+    return v;
+}
+
+// Reverse lists from the current out-edges (sorted by target, then source).
+void rebuild_reverse(bsim_state* st, Arena& arena) {
+    hipStream_t s = st->s;
+    const uint32_t n = st->n, m = static_cast<uint32_t>(st->m);
+    const int r = st->rcur;
+    st->rev_own[r].ensure(std::max<uint64_t>(m, 1), 0, s);
+    st->rev_src[r].ensure(std::max<uint64_t>(m, 1), 0, s);
+    st->rev_own[r ^ 1].ensure(std::max<uint64_t>(m, 1), 0, s);
+    st->rev_src[r ^ 1].ensure(std::max<uint64_t>(m, 1), 0, s);
+    st->rev_off[r].ensure(static_cast<size_t>(n) + 1, 0, s);
+    if (m) {
+        uint64_t* ka = arena.alloc<uint64_t>(m);
+        uint64_t* kb = arena.alloc<uint64_t>(m);
+        k_edge_keys_rev<<<grid_for(m), kBlock, 0, s>>>(st->src[st->cur].p, st->tgt[st->cur].p, m, ka);
+        uint64_t* sorted = radix_sort(ka, kb, m, 32 + std::max(1, bit_width(n)), arena, s);
+        k_rev_split<<<grid_for(m), kBlock, 0, s>>>(sorted, m, st->rev_own[r].p, st->rev_src[r].p);
+    }
+    k_rev_offsets<<<grid_for(static_cast<uint64_t>(m) + 1), kBlock, 0, s>>>(st->rev_own[r].p, m, n,
+                                                                            st->rev_off[r].p);
+    hip_check(hipGetLastError(), "reverse build");
+    st->rm = m;
+    st->n_rev = n;
+}
+
+HostBatch resolve(const bsim_state* st, const bsim_update* ops, uint64_t n_ops) {
+    HostBatch hb;
+    uint32_t n_cur = st->n;
+    std::unordered_map<uint32_t, uint8_t> vstate;  // touched vertex -> alive after the batch
+    std::unordered_map<uint32_t, std::vector<uint32_t>> vtypes;
+    auto alive_now = [&](uint32_t v) -> bool {
+        auto it = vstate.find(v);
+        if (it != vstate.end()) return it->second != 0;
+        return st->alive_host[v] != 0;
+    };
+    struct Rec {
+        uint32_t u, w, l, seq, add;
+    };
+    std::vector<Rec> recs;
+    recs.reserve(n_ops);
+    const uint64_t lab_lim = st->label_bytes == 2 ? (1ull << 16) : (1ull << 24);
+    uint32_t seq = 0;
+    auto check_vertex = [&](uint32_t u) {
+        if (u >= n_cur) throw DeviceError{BSIM_E_RANGE, "vertex id out of range in update"};
+        if (!alive_now(u)) throw DeviceError{BSIM_E_INVALID, "update names a deleted vertex"};
+    };
+    auto check_types = [&](const bsim_update& o) {
+        if (o.n_types > kMaxStateTypes) throw DeviceError{BSIM_E_UNSUPPORTED, "more than 4096 types on a vertex"};
+        if (o.n_types && !o.types) throw DeviceError{BSIM_E_INVALID, "types pointer is NULL"};
+    };
+    for (uint64_t i = 0; i < n_ops; i++) {
+        const bsim_update& o = ops[i];
+        switch (o.op) {
+            case BSIM_OP_ADD_V: {
+                check_types(o);
+                if (n_cur >= 0xFFFFFFF0u) throw DeviceError{BSIM_E_UNSUPPORTED, "too many vertices"};
+                const uint32_t v = n_cur++;
+                vstate[v] = 1;
+                vtypes[v].assign(o.types, o.types + o.n_types);
+                break;
+            }
+            case BSIM_OP_MOD_V:
+                check_vertex(o.u);
+                check_types(o);
+                vstate[o.u] = 1;
+                vtypes[o.u].assign(o.types, o.types + o.n_types);
+                break;
+            case BSIM_OP_DEL_V:
+                check_vertex(o.u);
+                vstate[o.u] = 0;
+                vtypes[o.u].clear();
+                break;
+            case BSIM_OP_ADD_E:
+            case BSIM_OP_DEL_E:
+            case BSIM_OP_MOD_E:
+                if (o.u >= n_cur || o.w >= n_cur) throw DeviceError{BSIM_E_RANGE, "vertex id out of range in update"};
+                check_vertex(o.u);
+                check_vertex(o.w);
+                if (o.label >= lab_lim || (o.op == BSIM_OP_MOD_E && o.new_label >= lab_lim))
+                    throw DeviceError{BSIM_E_RANGE, "edge label out of range in update"};
+                if (o.op == BSIM_OP_ADD_E) {
+                    recs.push_back({o.u, o.w, o.label, seq++, 1});
+                } else {
+                    recs.push_back({o.u, o.w, o.label, seq++, 0});
+                    if (o.op == BSIM_OP_MOD_E) recs.push_back({o.u, o.w, o.new_label, seq++, 1});
+                }
+                break;
+            default:
+                throw DeviceError{BSIM_E_INVALID, "unknown update op code"};
+        }
+    }
+    hb.n_new = n_cur;
+    for (auto& kv : vstate) {
+        hb.tl.push_back(kv.first);
+        if (!kv.second) hb.dead.push_back(kv.first);
+    }
+    std::sort(hb.tl.begin(), hb.tl.end());
+    std::sort(hb.dead.begin(), hb.dead.end());
+    hb.tl_off.push_back(0);
+    for (uint32_t v : hb.tl) {
+        if (vstate[v]) {
+            const auto& ty = vtypes[v];
+            hb.tl_ids.insert(hb.tl_ids.end(), ty.begin(), ty.end());
+        }
+        hb.tl_off.push_back(static_cast<uint32_t>(hb.tl_ids.size()));
+    }
+    std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+        if (a.u != b.u) return a.u < b.u;
+        if (a.w != b.w) return a.w < b.w;
+        if (a.l != b.l) return a.l < b.l;
+        return a.seq < b.seq;
+    });
+    auto dead_at_end = [&](uint32_t v) {
+        auto it = vstate.find(v);
+        return it != vstate.end() && it->second == 0;
+    };
+    for (size_t i = 0; i < recs.size();) {
+        size_t j = i;
+        uint32_t deleted = 0;
+        while (j < recs.size() && recs[j].u == recs[i].u && recs[j].w == recs[i].w && recs[j].l == recs[i].l) {
+            if (!recs[j].add) deleted = 1;
+            j++;
+        }
+        const Rec& last = recs[j - 1];
+        if (!dead_at_end(last.u) && !dead_at_end(last.w)) {
+            const uint32_t f = (deleted ? kChgDeleted : 0u) | (last.add ? kChgPresent : 0u);
+            hb.cu.push_back(last.u);
+            hb.cw.push_back(last.w);
+            hb.cl.push_back(last.l);
+            hb.cf.push_back(f);
+            if (last.add) {
+                hb.n_present++;
+                hb.max_label = std::max(hb.max_label, last.l);
+                hb.rw.push_back(last.w);
+                hb.ru.push_back(last.u);
+            }
+        }
+        i = j;
+    }
+    for (size_t i = 0; i < hb.cu.size();) {
+        size_t j = i;
+        while (j < hb.cu.size() && hb.cu[j] == hb.cu[i]) j++;
+        hb.gsrc.push_back(hb.cu[i]);
+        hb.gbeg.push_back(static_cast<uint32_t>(i));
+        hb.gend.push_back(static_cast<uint32_t>(j));
+        i = j;
+    }
+    // reverse additions, grouped by target (duplicate pairs are harmless)
+    std::vector<uint64_t> rk(hb.rw.size());
+    for (size_t i = 0; i < rk.size(); i++) rk[i] = (static_cast<uint64_t>(hb.rw[i]) << 32) | hb.ru[i];
+    std::sort(rk.begin(), rk.end());
+    rk.erase(std::unique(rk.begin(), rk.end()), rk.end());
+    hb.rw.resize(rk.size());
+    hb.ru.resize(rk.size());
+    for (size_t i = 0; i < rk.size(); i++) {
+        hb.rw[i] = static_cast<uint32_t>(rk[i] >> 32);
+        hb.ru[i] = static_cast<uint32_t>(rk[i]);
+    }
+    for (size_t i = 0; i < hb.rw.size();) {
+        size_t j = i;
+        while (j < hb.rw.size() && hb.rw[j] == hb.rw[i]) j++;
+        hb.rgw.push_back(hb.rw[i]);
+        hb.rgbeg.push_back(static_cast<uint32_t>(i));
+        hb.rgend.push_back(static_cast<uint32_t>(j));
+        i = j;
+    }
+    return hb;
+}
+
+__global__ void k_set_ranges(const uint32_t* __restrict__ gk, const uint32_t* __restrict__ gb,
+                             const uint32_t* __restrict__ ge, uint32_t ng, uint32_t* lo, uint32_t* hi) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < ng) {
+        lo[gk[i]] = gb[i];
+        hi[gk[i]] = ge[i];
+    }
+}
+
+template <typename LabT>
+void merge_edges(bsim_state* st, const HostBatch& hb, uint32_t n_old, Arena& arena) {
+    hipStream_t s = st->s;
+    const uint32_t n_new = hb.n_new;
+    const uint32_t m_old = static_cast<uint32_t>(st->m);
+    const uint32_t nc = static_cast<uint32_t>(hb.cu.size());
+    const int c = st->cur;
+    const uint64_t m_cap = static_cast<uint64_t>(m_old) + hb.n_present;
+    if (m_cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "this build supports fewer than 2^32 edges"};
+    st->src[c ^ 1].ensure(m_cap + 1, 0, s);
+    st->tgt[c ^ 1].ensure(m_cap + 1, 0, s);
+    st->lab[c ^ 1].ensure((m_cap + 1) * sizeof(LabT), 0, s);
+    st->kpos.ensure(std::max<uint64_t>(m_old, st->nt) + 1, 0, s);
+    uint32_t* d_cu = upload(arena, hb.cu, s);
+    uint32_t* d_cw = upload(arena, hb.cw, s);
+    uint32_t* d_cl = upload(arena, hb.cl, s);
+    uint32_t* d_cf = upload(arena, hb.cf, s);
+    uint32_t* exist = arena.alloc<uint32_t>(nc + 1);
+    uint32_t* apos = arena.alloc<uint32_t>(nc + 1);
+    hip_check(hipMemsetAsync(exist, 0, (nc + 1) * 4ull, s), "exist");
+    hip_check(hipMemsetAsync(apos, 0, (nc + 1) * 4ull, s), "apos");
+    uint32_t* kpos = st->kpos.p;
+    const LabT* lab = reinterpret_cast<const LabT*>(st->lab[c].p);
+    hip_check(hipMemsetAsync(kpos, 0, (m_old + 1) * 4ull, s), "kpos");
+    if (m_old) {
+        k_fwd_keep<LabT><<<grid_for(m_old), kBlock, 0, s>>>(st->src[c].p, st->tgt[c].p, lab, m_old, st->dflag.p,
+                                                          st->alive.p, st->chg_lo.p, st->chg_hi.p, d_cw, d_cl,
+                                                          d_cf, exist, kpos);
+        scan_exclusive(kpos, kpos, m_old, kpos + m_old, arena, s);
+    }
+    if (nc) {
+        k_app_flags<<<grid_for(nc), kBlock, 0, s>>>(d_cf, exist, nc, apos);
+        scan_exclusive(apos, apos, nc, apos + nc, arena, s);
+    }
+    k_fwd_deg<<<grid_for(n_new), kBlock, 0, s>>>(n_new, n_old, st->row_off[c].p, kpos, st->chg_lo.p,
+                                                 st->chg_hi.p, apos, st->kept.p, st->deg.p);
+    uint32_t* off_new = st->row_off[c ^ 1].p;
+    scan_exclusive(st->deg.p, off_new, n_new, off_new + n_new, arena, s);
+    const uint32_t m_new = read_u32(off_new + n_new, s);
+    if (m_old)
+        k_fwd_copy<LabT><<<grid_for(m_old), kBlock, 0, s>>>(st->src[c].p, st->tgt[c].p, lab, m_old,
+                                                          st->row_off[c].p, kpos, off_new, st->src[c ^ 1].p,
+                                                          st->tgt[c ^ 1].p,
+                                                          reinterpret_cast<LabT*>(st->lab[c ^ 1].p));
+    if (nc)
+        k_fwd_append<LabT><<<grid_for(nc), kBlock, 0, s>>>(d_cu, d_cw, d_cl, nc, apos, off_new, st->kept.p,
+                                                         st->chg_lo.p, st->src[c ^ 1].p, st->tgt[c ^ 1].p,
+                                                         reinterpret_cast<LabT*>(st->lab[c ^ 1].p));
+    hip_check(hipGetLastError(), "edge merge");
+    st->cur ^= 1;
+    st->m = m_new;
+}
+
+void merge_types(bsim_state* st, const HostBatch& hb, uint32_t n_old, Arena& arena) {
+    hipStream_t s = st->s;
+    const uint32_t n_new = hb.n_new;
+    const uint32_t nt_old = static_cast<uint32_t>(st->nt);
+    const uint32_t nT = static_cast<uint32_t>(hb.tl.size());
+    const int c = st->tcur;
+    const uint64_t cap = static_cast<uint64_t>(nt_old) + hb.tl_ids.size();
+    if (cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "too many type entries"};
+    st->type_own[c ^ 1].ensure(cap + 1, 0, s);
+    st->type_ids[c ^ 1].ensure(cap + 1, 0, s);
+    st->kpos.ensure(std::max<uint64_t>(st->m, nt_old) + 1, 0, s);
+    uint32_t* kpos = st->kpos.p;
+    uint32_t* d_tl = upload(arena, hb.tl, s);
+    uint32_t* d_off = upload(arena, hb.tl_off, s);
+    uint32_t* d_ids = upload(arena, hb.tl_ids, s);
+    hip_check(hipMemsetAsync(kpos, 0, (nt_old + 1) * 4ull, s), "kpos");
+    if (nt_old) {
+        k_typ_keep<<<grid_for(nt_old), kBlock, 0, s>>>(st->type_own[c].p, nt_old, st->dflag.p, kpos);
+        scan_exclusive(kpos, kpos, nt_old, kpos + nt_old, arena, s);
+    }
+    k_typ_deg<<<grid_for(n_new), kBlock, 0, s>>>(n_new, n_old, st->type_off[c].p, kpos, st->tidx.p, d_off,
+                                                 st->deg.p);
+    uint32_t* off_new = st->type_off[c ^ 1].p;
+    scan_exclusive(st->deg.p, off_new, n_new, off_new + n_new, arena, s);
+    if (nt_old)
+        k_typ_copy<<<grid_for(nt_old), kBlock, 0, s>>>(st->type_own[c].p, st->type_ids[c].p, nt_old,
+                                                       st->type_off[c].p, kpos, off_new, st->type_own[c ^ 1].p,
+                                                       st->type_ids[c ^ 1].p);
+    if (nT)
+        k_typ_write<<<grid_for(nT), kBlock, 0, s>>>(d_tl, nT, d_off, d_ids, off_new, st->type_own[c ^ 1].p,
+                                                    st->type_ids[c ^ 1].p);
+    hip_check(hipGetLastError(), "type merge");
+    st->tcur ^= 1;
+    st->nt = read_u32(off_new + n_new, s);
+}
+
+void merge_reverse(bsim_state* st, const HostBatch& hb, Arena& arena) {
+    hipStream_t s = st->s;
+    const uint32_t n_new = hb.n_new, n_old = st->n_rev;
+    const uint32_t nr = static_cast<uint32_t>(hb.rw.size());
+    const uint32_t ng = static_cast<uint32_t>(hb.rgw.size());
+    const int c = st->rcur;
+    const uint64_t cap = st->rm + nr;
+    if (cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "reverse lists too long"};
+    st->rev_own[c ^ 1].ensure(cap + 1, 0, s);
+    st->rev_src[c ^ 1].ensure(cap + 1, 0, s);
+    uint32_t* d_rw = upload(arena, hb.rw, s);
+    uint32_t* d_ru = upload(arena, hb.ru, s);
+    uint32_t* d_gw = upload(arena, hb.rgw, s);
+    uint32_t* d_gb = upload(arena, hb.rgbeg, s);
+    uint32_t* d_ge = upload(arena, hb.rgend, s);
+    if (ng) k_set_ranges<<<grid_for(ng), kBlock, 0, s>>>(d_gw, d_gb, d_ge, ng, st->chg_lo.p, st->chg_hi.p);
+    k_rev_deg<<<grid_for(n_new), kBlock, 0, s>>>(n_new, n_old, st->rev_off[c].p, st->chg_lo.p, st->chg_hi.p,
+                                                 st->deg.p);
+    uint32_t* off_new = st->rev_off[c ^ 1].p;
+    scan_exclusive(st->deg.p, off_new, n_new, off_new + n_new, arena, s);
+    if (st->rm)
+        k_rev_copy<<<grid_for(st->rm), kBlock, 0, s>>>(st->rev_own[c].p, st->rev_src[c].p,
+                                                       static_cast<uint32_t>(st->rm), st->rev_off[c].p, off_new,
+                                                       st->rev_own[c ^ 1].p, st->rev_src[c ^ 1].p);
+    if (nr)
+        k_rev_append<<<grid_for(nr), kBlock, 0, s>>>(d_rw, d_ru, nr, n_old, st->rev_off[c].p, off_new,
+                                                     st->chg_lo.p, st->rev_own[c ^ 1].p, st->rev_src[c ^ 1].p);
+    if (ng) k_clear_groups<<<grid_for(ng), kBlock, 0, s>>>(d_gw, ng, st->chg_lo.p, st->chg_hi.p);
+    hip_check(hipGetLastError(), "reverse merge");
+    st->rcur ^= 1;
+    st->rm = cap;
+    st->n_rev = n_new;
+}
+
+// Re-hash levels 1..K on the frontiers of the batch (level 0 already done).
+void propagate(bsim_state* st) {
+    hipStream_t s = st->s;
+    const uint32_t n = st->n;
+    // every table slot of a deferred vertex: next_pow2(2 deg) <= 4 deg
+    st->scratch.ensure(4 * std::max<uint64_t>(st->m, 16), 0, s);
+    st->chunk_owner.ensure(static_cast<size_t>(n) + st->m / kChunkEdges + 2, 0, s);
+    const int lb = st->label_bytes;
+    for (uint32_t j = 1; j <= st->K; j++) {
+        const uint32_t par = j & 1;
+        k_level_reset<<<1, 64, 0, s>>>(st->cnt.p, par);
+        hip_check(hipMemsetAsync(st->fmark.p, 0, (static_cast<size_t>(n) + 1) * 4, s), "frontier marks");
+        k_front_base<<<256, kBlock, 0, s>>>(st->blist.p, st->cnt.p, st->fmark.p, st->flist.p, st->cnt.p);
+        k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(st->clist[par ^ 1].p, st->cnt.p, par ^ 1, st->rev_off[st->rcur].p,
+                                                     st->rev_src[st->rcur].p, st->fmark.p, st->flist.p, st->cnt.p);
+        FrontArgs a;
+        a.row_off = st->row_off[st->cur].p;
+        a.tgt = st->tgt[st->cur].p;
+        a.lab = st->lab[st->cur].p;
+        a.t = st->levels[0].p;
+        a.salt = st->salt.p;
+        a.h_prev = st->levels[j - 1].p;
+        a.h_cur = st->levels[j].p;
+        a.alive = st->alive.p;
+        a.flist = st->flist.p;
+        a.clist = st->clist[par].p;
+        a.cnt = st->cnt.p;
+        a.big = st->big.p;
+        a.chunk_owner = st->chunk_owner.p;
+        a.big_acc = st->big_acc.p;
+        a.big_done = st->big_done.p;
+        a.scratch = st->scratch.p;
+        a.parity = par;
+        if (lb == 2) k_front_hash<uint16_t><<<kFrontGrid, kBlock, 0, s>>>(a);
+        else k_front_hash<uint32_t><<<kFrontGrid, kBlock, 0, s>>>(a);
+        k_big_clear<<<1024, kBlock, 0, s>>>(st->cnt.p, st->scratch.p);
+        if (lb == 2) k_big_chunks<uint16_t><<<1024, kBlock, 0, s>>>(a);
+        else k_big_chunks<uint32_t><<<1024, kBlock, 0, s>>>(a);
+        hip_check(hipGetLastError(), "frontier launch");
+    }
+}
+
+// Classes of levels 0..upto into st->rep; returns the founded count per level.
+std::vector<uint32_t> level_classes(bsim_state* st, uint32_t upto) {
+    hipStream_t s = st->s;
+    SplitTable T;
+    T.slots = st->cls_slots;
+    T.zero = st->cls_zero;
+    T.list = st->cls_list;
+    T.mask = st->cls_cap - 1;
+    st->cls_cnt.ensure(2ull * (upto + 1), 0, s);
+    hip_check(hipMemsetAsync(st->cls_cnt.p, 0, 8ull * (upto + 1), s), "class counts");
+    for (uint32_t j = 0; j <= upto; j++) {
+        launch_level_classes(st->levels[j].p, st->rep.p, st->alive.p, st->n, j, T, st->cls_cnt.p + 2 * j,
+                             st->cls_cnt.p + 2 * j + 1, st->status.p, s);
+        launch_level_clear(T, st->cls_cnt.p + 2 * j + 1, s);
+    }
+    std::vector<uint32_t> c(2ull * (upto + 1));
+    hip_check(hipMemcpyAsync(c.data(), st->cls_cnt.p, c.size() * 4, hipMemcpyDeviceToHost, s), "class counts");
+    RunStatus rs;
+    hip_check(hipMemcpyAsync(&rs, st->status.p, sizeof(rs), hipMemcpyDeviceToHost, s), "status");
+    hip_check(hipStreamSynchronize(s), "class sync");
+    if (rs.error & kErrZeroHash)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
+    std::vector<uint32_t> founded(upto + 1);
+    for (uint32_t j = 0; j <= upto; j++) founded[j] = c[2 * j];
+    return founded;
+}
+
+// Classes, fixpoint rule and finalize on the current levels.
+bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls) {
+    hipStream_t s = st->s;
+    std::vector<uint32_t> f = level_classes(st, st->K);
+    std::vector<uint32_t> nk(st->K + 1);
+    uint32_t run = 0;
+    for (uint32_t j = 0; j <= st->K; j++) nk[j] = run += f[j];
+    const bool stop = (st->flags & BSIM_STOP_AT_FIXPOINT) != 0;
+    uint32_t k_done = st->K, fix = 0;
+    for (uint32_t j = 0; j <= st->K; j++) {
+        const uint32_t fx = (j >= 1 && nk[j] == nk[j - 1]) ? 1u : 0u;
+        if ((stop && fx) || j >= st->K) {
+            k_done = j;
+            fix = fx;
+            break;
+        }
+    }
+    if (k_done < st->K) level_classes(st, k_done);
+    (void)ms_cls;
+    Staged g;
+    g.n = st->n;
+    g.m = st->m;
+    g.label_bytes = st->label_bytes;
+    g.row_off = st->row_off[st->cur].p;
+    g.tgt = st->tgt[st->cur].p;
+    g.lab = st->lab[st->cur].p;
+    g.alive = st->alive.p;
+    g.src = st->src[st->cur].p;
+    g.max_label = st->max_label;
+    Arena keep(s);
+    FinalOut fo;
+    finalize(g, st->rep.p, !(st->flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    if (fo.n_blocks != nk[k_done]) throw DeviceError{BSIM_E_DEVICE, "internal: class count mismatch in finalize"};
+    LoopResult lr;
+    lr.k_done = k_done;
+    lr.fixpoint = fix;
+    lr.blocks_per_iter.assign(nk.begin(), nk.begin() + k_done + 1);
+    return make_result(st->ctx, g, lr, st->levels[k_done].p, fo, keep, st->flags);
+}
+
+struct PhaseTimer {
+    hipStream_t s;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    explicit PhaseTimer(hipStream_t st) : s(st) {
+        for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+    }
+    ~PhaseTimer() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void mark(int i) { hip_check(hipEventRecord(ev[i], s), "event"); }
+    void fill(bsim_result* r) {
+        hip_check(hipEventSynchronize(ev[3]), "event");
+        (void)hipEventElapsedTime(&r->ms_stage, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&r->ms_iterate, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&r->ms_finalize, ev[2], ev[3]);
+        (void)hipEventElapsedTime(&r->ms_total, ev[0], ev[3]);
+    }
+};
+
+bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
+    hipStream_t s = st->s;
+    PhaseTimer tm(s);
+    tm.mark(0);
+    Arena arena(s);
+    const uint32_t n_old = st->n, n_new = hb.n_new;
+    ensure_vertices(st, n_new);
+    const size_t grow = n_new - n_old;
+    if (grow) {
+        hip_check(hipMemsetAsync(st->alive.p + n_old, 1, grow, s), "new alive");
+        for (auto& l : st->levels) hip_check(hipMemsetAsync(l.p + n_old, 0, grow * 8, s), "new levels");
+        // a grown index array holds unset memory past the old vertices
+        for (DevBuf<uint32_t>* b : {&st->chg_lo, &st->chg_hi, &st->tidx})
+            hip_check(hipMemsetAsync(b->p + n_old, 0, (grow + 1) * 4, s), "index arrays");
+    }
+    hip_check(hipMemsetAsync(st->dflag.p, 0, (static_cast<size_t>(n_new) + 1) * 4, s), "dflag");
+    hip_check(hipMemsetAsync(st->bmark.p, 0, (static_cast<size_t>(n_new) + 1) * 4, s), "bmark");
+    hip_check(hipMemsetAsync(st->cnt.p, 0, sizeof(IncCounters), s), "counters");
+    uint32_t* d_dead = upload(arena, hb.dead, s);
+    uint32_t* d_tl = upload(arena, hb.tl, s);
+    uint32_t* d_gsrc = upload(arena, hb.gsrc, s);
+    uint32_t* d_gbeg = upload(arena, hb.gbeg, s);
+    uint32_t* d_gend = upload(arena, hb.gend, s);
+    const uint32_t nd = static_cast<uint32_t>(hb.dead.size());
+    const uint32_t nT = static_cast<uint32_t>(hb.tl.size());
+    const uint32_t ng = static_cast<uint32_t>(hb.gsrc.size());
+    if (nd) k_set_dead<<<grid_for(nd), kBlock, 0, s>>>(d_dead, nd, st->alive.p);
+    if (ng)
+        k_mark_groups<<<grid_for(ng), kBlock, 0, s>>>(d_gsrc, d_gbeg, d_gend, ng, st->dflag.p, st->chg_lo.p,
+                                                      st->chg_hi.p, st->bmark.p, st->blist.p, st->cnt.p);
+    if (nd)
+        k_mark_dead<<<grid_for(64ull * nd), kBlock, 0, s>>>(d_dead, nd, st->rev_off[st->rcur].p,
+                                                            st->rev_src[st->rcur].p, st->n_rev, st->dflag.p,
+                                                            st->bmark.p, st->blist.p, st->cnt.p);
+    if (nT) k_mark_types<<<grid_for(nT), kBlock, 0, s>>>(d_tl, nT, st->dflag.p, st->tidx.p, st->bmark.p,
+                                                          st->blist.p, st->cnt.p);
+    hip_check(hipGetLastError(), "batch marks");
+    if (ng || nd) {
+        if (st->label_bytes == 2) merge_edges<uint16_t>(st, hb, n_old, arena);
+        else merge_edges<uint32_t>(st, hb, n_old, arena);
+    } else if (grow) {
+        hip_check(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(st->row_off[st->cur].p + n_old + 1),
+                                    static_cast<int>(st->m), grow, s), "new rows");
+    }
+    if (ng) k_clear_groups<<<grid_for(ng), kBlock, 0, s>>>(d_gsrc, ng, st->chg_lo.p, st->chg_hi.p);
+    if (nT) {
+        merge_types(st, hb, n_old, arena);
+        k_clear_tidx<<<grid_for(nT), kBlock, 0, s>>>(d_tl, nT, st->tidx.p);
+    }
+    if (!hb.rw.empty() || n_new > st->n_rev) merge_reverse(st, hb, arena);
+    st->n = n_new;
+    st->max_label = std::max(st->max_label, hb.max_label);
+    ensure_salt(st, st->max_label);
+    if (st->rm > 2 * st->m + 65536) rebuild_reverse(st, arena);
+    tm.mark(1);
+    if (nT)
+        k_level0<<<grid_for(nT), kBlock, 0, s>>>(d_tl, nT, st->type_off[st->tcur].p, st->type_ids[st->tcur].p,
+                                                 st->alive.p, st->untyped ? 1 : 0, st->levels[0].p, st->clist[0].p,
+                                                 st->cnt.p);
+    hip_check(hipGetLastError(), "level 0");
+    propagate(st);
+    tm.mark(2);
+    bsim_result* r = finish(st, arena, nullptr);
+    tm.mark(3);
+    tm.fill(r);
+    st->alive_host.resize(n_new, 1);
+    for (uint32_t d : hb.dead) st->alive_host[d] = 0;
+    return r;
+}
+
+bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p, bsim_state* st) {
+    hipStream_t s = ctx->stream;
+    PhaseTimer tm(s);
+    tm.mark(0);
+    Arena arena(s);
+    Staged g;
+    upload_graph(graph, g, arena, s);
+    g.hub_table_slots = ctx->hub_table_slots;
+    RunStatus* stage_status = arena.alloc<RunStatus>(1);
+    stage_graph(g, stage_status, &ctx->status_host[3], arena, s);
+    st->ctx = ctx;
+    st->s = s;
+    st->K = p.k_max;
+    st->flags = p.flags & ~BSIM_KEEP_LEVELS;
+    st->untyped = (p.flags & BSIM_UNTYPED) != 0;
+    st->label_bytes = graph.label_bytes;
+    st->levels.resize(p.k_max + 1);
+    st->status.ensure(1, 0, s);
+    st->cnt.ensure(1, 0, s);
+    hip_check(hipMemsetAsync(st->status.p, 0, sizeof(RunStatus), s), "status");
+    ensure_vertices(st, g.n);
+    // chg_lo / chg_hi / tidx are index arrays that every batch reads for all
+    // vertices: they start at zero and batches restore the entries they set
+    for (DevBuf<uint32_t>* b : {&st->chg_lo, &st->chg_hi, &st->tidx})
+        hip_check(hipMemsetAsync(b->p, 0, b->cap * 4, s), "index arrays");
+    st->n = g.n;
+    st->m = g.m;
+    st->max_label = g.max_label;
+    const uint32_t n = g.n;
+    const uint32_t m = static_cast<uint32_t>(g.m);
+    const int c = st->cur;
+    st->src[c].ensure(m + 1ull, 0, s);
+    st->tgt[c].ensure(m + 1ull, 0, s);
+    st->lab[c].ensure((m + 1ull) * g.label_bytes, 0, s);
+    hip_check(hipMemcpyAsync(st->row_off[c].p, g.row_off, (n + 1ull) * 4, hipMemcpyDeviceToDevice, s), "row_off");
+    if (m) {
+        hip_check(hipMemcpyAsync(st->tgt[c].p, g.tgt, m * 4ull, hipMemcpyDeviceToDevice, s), "targets");
+        hip_check(hipMemcpyAsync(st->lab[c].p, g.lab, static_cast<size_t>(m) * g.label_bytes,
+                                 hipMemcpyDeviceToDevice, s), "labels");
+        k_coo_owner<<<grid_for(m), kBlock, 0, s>>>(g.row_off, n, m, st->src[c].p);
+    }
+    const uint32_t nt = read_u32(g.type_off + n, s);
+    st->nt = nt;
+    st->type_own[st->tcur].ensure(nt + 1ull, 0, s);
+    st->type_ids[st->tcur].ensure(nt + 1ull, 0, s);
+    hip_check(hipMemcpyAsync(st->type_off[st->tcur].p, g.type_off, (n + 1ull) * 4, hipMemcpyDeviceToDevice, s),
+              "type_off");
+    if (nt) {
+        hip_check(hipMemcpyAsync(st->type_ids[st->tcur].p, g.type_ids, nt * 4ull, hipMemcpyDeviceToDevice, s),
+                  "type ids");
+        k_coo_owner<<<grid_for(nt), kBlock, 0, s>>>(g.type_off, n, nt, st->type_own[st->tcur].p);
+    }
+    if (n) k_alive_all<<<grid_for(n), kBlock, 0, s>>>(st->alive.p, g.alive, n);
+    hip_check(hipGetLastError(), "state copy");
+    st->alive_host.resize(n);
+    if (n) hip_check(hipMemcpyAsync(st->alive_host.data(), st->alive.p, n, hipMemcpyDeviceToHost, s), "alive");
+    ensure_salt(st, st->max_label);
+    rebuild_reverse(st, arena);
+    tm.mark(1);
+    // every level h^0..h^K by the batch refinement (no early stop)
+    RunBuffers rb;
+    alloc_run_buffers(g, p.k_max, false, rb, arena, s);
+    LevelSink sink;
+    for (auto& l : st->levels) sink.levels.push_back(l.p);
+    bsim_params bp{p.k_max, p.flags & ~BSIM_STOP_AT_FIXPOINT};
+    run_refinement(ctx, g, bp, rb, &sink, arena);
+    tm.mark(2);
+    bsim_result* r = finish(st, arena, nullptr);
+    tm.mark(3);
+    tm.fill(r);
+    return r;
+}
+
+}  // namespace
+
+int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p, bsim_state** state_out,
+                         bsim_result** out) {
+    validate_params(graph, p);
+    if (p.k_max > 4096)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "a resident state needs k_max <= 4096 (it keeps every level)"};
+    bsim_state* st = new bsim_state();
+    try {
+        *out = create_state(ctx, graph, p, st);
+    } catch (...) {
+        st->s = ctx->stream;
+        st->release();
+        delete st;
+        throw;
+    }
+    *state_out = st;
+    return BSIM_OK;
 }
 
 }  // namespace bsim
 
 extern "C" {
 
-int bsim_apply_updates(bsim_state*, const bsim_update*, uint64_t, bsim_result** out) {
+int bsim_apply_updates(bsim_state* st, const bsim_update* ops, uint64_t n_ops, bsim_result** out) {
     if (out) *out = nullptr;
-    return BSIM_E_UNSUPPORTED;
+    if (!st || !out || (n_ops && !ops)) return BSIM_E_INVALID;
+    try {
+        hip_check(hipSetDevice(st->ctx->device), "set device");
+        HostBatch hb = resolve(st, ops, n_ops);
+        *out = apply_batch(st, hb);
+        return BSIM_OK;
+    } catch (const DeviceError& e) {
+        st->ctx->err = e.msg;
+        (void)hipStreamSynchronize(st->s);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        st->ctx->err = "host allocation failed";
+        return BSIM_E_NOMEM;
+    }
 }
 
-int bsim_state_graph(const bsim_state*, bsim_graph*) { return BSIM_E_UNSUPPORTED; }
+int bsim_state_graph(const bsim_state* st, bsim_graph* g) {
+    if (!st || !g) return BSIM_E_INVALID;
+    memset(g, 0, sizeof(*g));
+    try {
+        hip_check(hipSetDevice(st->ctx->device), "set device");
+        const size_t n = st->n, m = st->m, nt = st->nt;
+        void* a[6] = {malloc((n + 1) * 4), malloc(m * 4 + 4), malloc(m * st->label_bytes + 4),
+                      malloc((n + 1) * 4), malloc(nt * 4 + 4), malloc(n + 1)};
+        for (void* q : a)
+            if (!q) {
+                for (void* r : a) free(r);
+                return BSIM_E_NOMEM;
+            }
+        hipStream_t s = st->s;
+        hip_check(hipMemcpyAsync(a[0], st->row_off[st->cur].p, (n + 1) * 4, hipMemcpyDeviceToHost, s), "row_off");
+        if (m) {
+            hip_check(hipMemcpyAsync(a[1], st->tgt[st->cur].p, m * 4, hipMemcpyDeviceToHost, s), "targets");
+            hip_check(hipMemcpyAsync(a[2], st->lab[st->cur].p, m * st->label_bytes, hipMemcpyDeviceToHost, s),
+                      "labels");
+        }
+        hip_check(hipMemcpyAsync(a[3], st->type_off[st->tcur].p, (n + 1) * 4, hipMemcpyDeviceToHost, s), "type_off");
+        if (nt) hip_check(hipMemcpyAsync(a[4], st->type_ids[st->tcur].p, nt * 4, hipMemcpyDeviceToHost, s), "types");
+        if (n) hip_check(hipMemcpyAsync(a[5], st->alive.p, n, hipMemcpyDeviceToHost, s), "alive");
+        hip_check(hipStreamSynchronize(s), "state graph");
+        g->n_vertices = st->n;
+        g->label_bytes = st->label_bytes;
+        g->n_edges = st->m;
+        g->row_off = static_cast<uint32_t*>(a[0]);
+        g->targets = static_cast<uint32_t*>(a[1]);
+        g->labels = a[2];
+        g->type_off = static_cast<uint32_t*>(a[3]);
+        g->type_ids = static_cast<uint32_t*>(a[4]);
+        g->alive = static_cast<uint8_t*>(a[5]);
+        g->mem_kind = BSIM_MEM_HOST;
+        return BSIM_OK;
+    } catch (const DeviceError& e) {
+        st->ctx->err = e.msg;
+        return e.status;
+    }
+}
 
-void bsim_state_free(bsim_state*) {}
+int bsim_state_device_graph(const bsim_state* st, bsim_graph* g) {
+    if (!st || !g) return BSIM_E_INVALID;
+    memset(g, 0, sizeof(*g));
+    g->n_vertices = st->n;
+    g->label_bytes = st->label_bytes;
+    g->n_edges = st->m;
+    g->row_off = st->row_off[st->cur].p;
+    g->targets = st->tgt[st->cur].p;
+    g->labels = st->lab[st->cur].p;
+    g->type_off = st->type_off[st->tcur].p;
+    g->type_ids = st->type_ids[st->tcur].p;
+    g->alive = st->alive.p;
+    g->mem_kind = BSIM_MEM_DEVICE;
+    return BSIM_OK;
+}
+
+void bsim_state_free(bsim_state* st) {
+    if (!st) return;
+    (void)hipSetDevice(st->ctx->device);
+    st->release();
+    delete st;
+}
 
 int bsim_batch_summarize(bsim_ctx*, const bsim_graph*, uint32_t, const bsim_params*, bsim_result** outs) {
     (void)outs;

@@ -230,6 +230,7 @@ struct Staged {
     const uint32_t* type_off = nullptr;
     const uint32_t* type_ids = nullptr;
     const uint8_t* alive = nullptr;
+    const uint32_t* src = nullptr;   // per-edge source (COO), when there is no tile schedule
     uint32_t max_label = 0;
     uint64_t* salt = nullptr;
     uint32_t n_tiles = 0;
@@ -291,6 +292,20 @@ void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t 
 // LDS slots the hub-bucket launch can use on this device.
 // device_max: the largest table the device allows (else the default size).
 uint32_t query_hub_table_slots(int device, bool device_max = false);
+
+// Classes of one stored level: level 0 groups alive vertices by h (= t),
+// level j >= 1 splits the classes in rep[] by h = h^j.  T must be empty; its
+// `list` (mask + 1 entries) receives the founded slots, *slot_count their
+// number, *founded_total grows by the number of classes founded.
+void launch_level_classes(const uint64_t* h, uint32_t* rep, const uint8_t* alive, uint32_t n,
+                          uint32_t level, const SplitTable& T, uint32_t* founded_total,
+                          uint32_t* slot_count, RunStatus* status, hipStream_t s);
+// Empty T again after launch_level_classes (slots listed by it).
+void launch_level_clear(const SplitTable& T, const uint32_t* slot_count, hipStream_t s);
+
+// Sort m 64-bit keys ascending on bits [0, bits); returns a or b, whichever
+// holds the result.
+uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Arena& arena, hipStream_t s);
 
 // Finalize (a8): block ids, block sizes, sorted distinct quotient edges.
 struct FinalOut {

@@ -525,6 +525,54 @@ __global__ void __launch_bounds__(kHubBlock) k_hub(HubArgs a) {
     }
 }
 
+// ------------------------------------------------------------ level classes
+//
+// The classes of stored levels h^0..h^K, level by level (used by the
+// resident state, whose levels change under update batches): level 0 groups
+// alive vertices by t(v); level j >= 1 splits every class by h^j with the
+// same split test as launch j+1 of the refinement loop.
+
+__global__ void __launch_bounds__(kBlock) k_level_classes(const uint64_t* __restrict__ h,
+                                                          uint32_t* __restrict__ rep,
+                                                          const uint8_t* __restrict__ alive, uint32_t n,
+                                                          uint32_t level, SplitTable T,
+                                                          uint32_t* __restrict__ founded_total,
+                                                          uint32_t* __restrict__ slot_count,
+                                                          RunStatus* status) {
+    __shared__ uint32_t s_red[kBlock / 64];
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t founded = 0, slot = 0xFFFFFFFFu;
+    if (v < n) {
+        if (!alive[v]) {
+            if (level == 0) rep[v] = 0xFFFFFFFFu;
+        } else if (level == 0) {
+            rep[v] = static_cast<uint32_t>(split_join(T, kNoRep, h[v], v, &founded, &slot, status));
+        } else {
+            const uint32_t r = rep[v];
+            const uint64_t hv = h[v];
+            if (r != v && hv != h[r])
+                rep[v] = static_cast<uint32_t>(split_join(T, r, hv, v, &founded, &slot, status));
+        }
+    }
+    // founded slots are listed so that only they are cleared afterwards
+    if (founded && slot != 0xFFFFFFFFu) {
+        const uint32_t pos = atomicAdd(slot_count, 1u);
+        if (pos <= T.mask) T.list[pos] = slot;
+    }
+    const uint32_t c = block_sum_u32(founded, s_red);
+    if (threadIdx.x == 0 && c) atomicAdd(founded_total, c);
+}
+
+__global__ void __launch_bounds__(kBlock) k_level_clear(SplitTable T, const uint32_t* __restrict__ slot_count) {
+    const uint32_t cnt = min(*slot_count, T.mask + 1);
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+        SplitSlot* p = &T.slots[T.list[i]];
+        p->key = 0;
+        p->owner = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kZeroSlots) T.zero[threadIdx.x] = 0;
+}
+
 }  // namespace
 
 uint32_t query_hub_table_slots(int device, bool device_max) {
@@ -651,6 +699,20 @@ void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t 
     a.table_limit = (g.hub_table_slots / 8) * 7;
     k_hub<<<g.n_hub_blocks, kHubBlock, static_cast<size_t>(g.hub_table_slots) * 8, s>>>(a);
     hip_check(hipGetLastError(), "hub launch");
+}
+
+void launch_level_classes(const uint64_t* h, uint32_t* rep, const uint8_t* alive, uint32_t n,
+                          uint32_t level, const SplitTable& T, uint32_t* founded_total,
+                          uint32_t* slot_count, RunStatus* status, hipStream_t s) {
+    if (n == 0) return;
+    k_level_classes<<<ceil_div(n, kBlock), kBlock, 0, s>>>(h, rep, alive, n, level, T, founded_total,
+                                                           slot_count, status);
+    hip_check(hipGetLastError(), "level classes launch");
+}
+
+void launch_level_clear(const SplitTable& T, const uint32_t* slot_count, hipStream_t s) {
+    k_level_clear<<<1024, kBlock, 0, s>>>(T, slot_count);
+    hip_check(hipGetLastError(), "level clear launch");
 }
 
 }  // namespace bsim

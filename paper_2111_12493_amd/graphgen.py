@@ -390,3 +390,118 @@ def random_small_graph(rng: np.random.Generator, n: int, m: int, n_labels: int,
         types.append([int(x) for x in rng.integers(0, max(1, n_types), size=c)])
     return from_edges(n, src, dst, lab, types=types, alive=alive,
                       n_labels=max(1, n_labels), n_types=max(1, n_types))
+
+
+# ---------------------------------------------------------------------------
+# Update batches (ADD / MOD / DEL of vertices and edges)
+# ---------------------------------------------------------------------------
+
+OP_KINDS = ("add_v", "mod_v", "del_v", "add_e", "mod_e", "del_e")
+
+
+def update_ops(g: Graph, rng: np.random.Generator, n_ops: int, mix=(0.60, 0.25, 0.15),
+               vertex_frac: float = 0.10, n_labels: Optional[int] = None,
+               n_types: Optional[int] = None, rmat_scale: Optional[int] = None,
+               max_types: int = 4) -> dict:
+    """A seeded, valid ordered batch of update operations for graph g.
+
+    Kinds: ADD / MOD / DEL with probabilities `mix`; within each class a
+    `vertex_frac` share are vertex operations, the rest edge operations.
+    Vertices deleted by the batch are chosen first and no other operation of
+    the batch touches them; edge ops use vertices that exist when the batch
+    starts.  DEL_E / MOD_E pick existing edges uniformly; ADD_E endpoints are
+    uniform, or drawn by the R-MAT sampler when `rmat_scale` is given
+    (rejecting ids >= n).  Returns numpy arrays (op, u, w, label, new_label)
+    and the type lists of the vertex ops as a CSR (t_off, t_ids), with t_off
+    indexed by operation.
+    """
+    n, m = g.n, g.m
+    n_labels = n_labels or max(g.n_labels, 1)
+    n_types = n_types or max(g.n_types, 1)
+    alive = np.ones(n, dtype=bool) if g.alive is None else g.alive.astype(bool)
+    cls = rng.choice(3, size=n_ops, p=np.asarray(mix) / sum(mix))       # 0 add, 1 mod, 2 del
+    is_v = rng.random(n_ops) < vertex_frac
+    op = np.where(is_v, cls + 1, cls + 4).astype(np.uint32)            # 1..3 vertex, 4..6 edge
+    u = np.zeros(n_ops, dtype=np.uint32)
+    w = np.zeros(n_ops, dtype=np.uint32)
+    lab = np.zeros(n_ops, dtype=np.uint32)
+    nlab = np.zeros(n_ops, dtype=np.uint32)
+    live = np.flatnonzero(alive)
+    # deleted vertices: distinct alive vertices
+    n_del_v = int(np.sum(op == 3))
+    if n_del_v > live.size // 2:
+        op[np.flatnonzero(op == 3)[live.size // 2:]] = 2
+        n_del_v = int(np.sum(op == 3))
+    dead = rng.choice(live, size=n_del_v, replace=False) if n_del_v else np.zeros(0, dtype=np.int64)
+    u[op == 3] = dead
+    keep = np.ones(n, dtype=bool)
+    keep[dead] = False
+    keep &= alive
+    pool = np.flatnonzero(keep)
+    if pool.size == 0:
+        op[(op == 2) | (op >= 4)] = 1
+    else:
+        mv = op == 2
+        u[mv] = rng.choice(pool, size=int(mv.sum()))
+        # edges usable by DEL_E / MOD_E: both endpoints stay alive
+        src = g.src()
+        ok = keep[src] & keep[g.tgt] if m else np.zeros(0, dtype=bool)
+        eidx = np.flatnonzero(ok)
+        de = (op == 5) | (op == 6)
+        if eidx.size == 0:
+            op[de] = 4
+            de[:] = False
+        pick = eidx[rng.integers(0, eidx.size, size=int(de.sum()))] if de.any() else np.zeros(0, dtype=np.int64)
+        u[de] = src[pick]
+        w[de] = g.tgt[pick]
+        lab[de] = g.lab[pick]
+        nlab[op == 5] = rng.integers(0, n_labels, size=int(np.sum(op == 5)))
+        ae = op == 4
+        k = int(ae.sum())
+        if rmat_scale is not None and k:
+            got_u, got_w = [], []
+            need = k
+            while need > 0:
+                s_, d_ = rmat_edges(rng, rmat_scale, 2 * need + 16, 0.57, 0.19, 0.19)
+                okm = (s_ < n) & (d_ < n)
+                s_, d_ = s_[okm], d_[okm]
+                okm = keep[s_] & keep[d_]
+                got_u.append(s_[okm][:need])
+                got_w.append(d_[okm][:need])
+                need -= len(got_u[-1])
+            u[ae] = np.concatenate(got_u)[:k]
+            w[ae] = np.concatenate(got_w)[:k]
+        else:
+            u[ae] = rng.choice(pool, size=k)
+            w[ae] = rng.choice(pool, size=k)
+        lab[ae] = zipf_sample(rng, n_labels, 1.1, k) if k else lab[ae]
+    # type lists of ADD_V / MOD_V
+    tv = (op == 1) | (op == 2)
+    cnt = np.zeros(n_ops, dtype=np.int64)
+    cnt[tv] = rng.integers(0, max_types + 1, size=int(tv.sum()))
+    t_off = np.zeros(n_ops + 1, dtype=np.int64)
+    np.cumsum(cnt, out=t_off[1:])
+    t_ids = rng.integers(0, n_types, size=int(t_off[-1])).astype(np.uint32)
+    return dict(op=op, u=u, w=w, label=lab, new_label=nlab, t_off=t_off, t_ids=t_ids)
+
+
+def ops_as_tuples(d: dict) -> List[tuple]:
+    """The same batch as tuples ("add_v", types), ("mod_v", u, types),
+    ("del_v", u), ("add_e", u, l, w), ("mod_e", u, l, w, l2), ("del_e", u, l, w)."""
+    out = []
+    for i, o in enumerate(d["op"]):
+        ty = [int(x) for x in d["t_ids"][d["t_off"][i]:d["t_off"][i + 1]]]
+        u, w, l, l2 = int(d["u"][i]), int(d["w"][i]), int(d["label"][i]), int(d["new_label"][i])
+        if o == 1:
+            out.append(("add_v", ty))
+        elif o == 2:
+            out.append(("mod_v", u, ty))
+        elif o == 3:
+            out.append(("del_v", u))
+        elif o == 4:
+            out.append(("add_e", u, l, w))
+        elif o == 5:
+            out.append(("mod_e", u, l, w, l2))
+        else:
+            out.append(("del_e", u, l, w))
+    return out

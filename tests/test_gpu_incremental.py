@@ -1,0 +1,184 @@
+"""GPU parity of the incremental path (bsim_apply_updates): after every update
+batch the result must equal the oracle's batch summary of the updated graph
+bit for bit (Theorem 2: incremental equals batch), and the state's graph
+must equal the oracle's sequential application of the same operations."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from oracle.updates import apply_ops
+from paper_2111_12493_amd import binding
+from paper_2111_12493_amd import graphgen as gg
+
+from gpu_util import assert_same, ctx
+
+pytestmark = pytest.mark.gpu
+
+
+def result_dict(r):
+    d = r.to_dict()
+    r.free()
+    return d
+
+
+def rows(g):
+    out = []
+    for v in range(g.n):
+        if g.alive is not None and not g.alive[v]:
+            out.append(None)
+            continue
+        a, b = int(g.row_off[v]), int(g.row_off[v + 1])
+        out.append(sorted(zip(g.lab[a:b].tolist(), g.tgt[a:b].tolist())))
+    return out
+
+
+def types(g):
+    return [sorted(g.types_of(v)) for v in range(g.n)]
+
+
+class Session:
+    """A GPU state and the oracle's view of the same graph, kept in step."""
+
+    def __init__(self, g, k, stop=False, untyped=False, device_input=False):
+        self.g, self.k, self.stop, self.untyped = g, k, stop, untyped
+        graph = binding.DeviceGraph(g) if device_input else binding.HostGraph(g)
+        self.state = binding.State(ctx(), graph, k, stop_at_fixpoint=stop, untyped=untyped)
+        self.check(self.state.result, "initial")
+
+    def ref(self):
+        return orc.summarize(self.g, self.k, self.stop, self.untyped)
+
+    def check(self, r, what):
+        assert_same(result_dict(r) if not isinstance(r, dict) else r, self.ref(), what)
+
+    def apply(self, ops, what=""):
+        self.g = apply_ops(self.g, ops)
+        r = self.state.apply(binding.UpdateBatch(ops))
+        self.check(r, what)
+        sg = self.state.graph()
+        assert sg.n == self.g.n, what
+        assert list(sg.alive) == list(self.g.alive), what
+        assert rows(sg) == rows(self.g), what
+        assert types(sg) == types(self.g), what
+
+    def close(self):
+        self.state.free()
+
+
+def test_initial_state_matches_batch():
+    rng = np.random.default_rng(11)
+    for trial in range(12):
+        g = gg.random_small_graph(rng, int(rng.integers(1, 50)), int(rng.integers(0, 200)), 3, 3, 3,
+                                  p_alive=1.0 if trial % 2 else 0.8)
+        for k, stop in ((0, False), (1, False), (3, True), (6, True)):
+            s = Session(g, k, stop=stop, untyped=bool(trial % 3 == 0))
+            s.close()
+
+
+def test_each_operation_kind():
+    g = gg.from_edges(6, [0, 0, 0, 1, 2, 3, 4, 5], [1, 1, 2, 2, 0, 4, 5, 3], [0, 0, 1, 0, 0, 1, 1, 1],
+                      types=[[5], [6], [6], [7], [7], [7]])
+    cases = [
+        [("add_e", 0, 0, 1)],                          # existing triple: no-op
+        [("add_e", 3, 0, 0)],
+        [("del_e", 0, 0, 1)],                          # every copy
+        [("del_e", 0, 0, 1), ("add_e", 0, 0, 1)],      # back as one copy
+        [("mod_e", 4, 1, 5, 2)],
+        [("mod_e", 1, 9, 3, 4)],                       # absent: adds the new triple
+        [("mod_v", 2, [5])],
+        [("add_v", [6]), ("add_e", 6, 0, 2), ("add_e", 1, 3, 6)],
+        [("del_v", 2)],
+        [("add_v", []), ("del_v", 7)],                 # created and deleted in one batch
+        [],
+    ]
+    for stop in (False, True):
+        s = Session(g, 4, stop=stop)
+        for i, ops in enumerate(cases):
+            s.apply(ops, what=("case", i, stop))
+        s.close()
+
+
+@pytest.mark.parametrize("label_u16", [False, True])
+def test_random_batch_sequences(label_u16):
+    rng = np.random.default_rng(23)
+    g = gg.uniform_graph(2000, 10000, 8, 16, seed=5)
+    if label_u16:
+        g = gg.with_u16_labels(g)
+    s = Session(g, 4)
+    for i, size in enumerate([1, 3, 10, 30, 100, 300, 1000, 1, 3000]):
+        d = gg.update_ops(s.g, rng, size, n_labels=16, n_types=8)
+        s.apply(gg.ops_as_tuples(d), what=("batch", i, size))
+    s.close()
+
+
+def test_untyped_and_fixpoint_stop():
+    rng = np.random.default_rng(29)
+    g = gg.append_chains(gg.uniform_graph(300, 900, 4, 4, seed=2), 3, 12, type_id=4)
+    s = Session(g, 20, stop=True, untyped=True)
+    for i in range(6):
+        d = gg.update_ops(s.g, rng, 20, n_labels=4, n_types=4)
+        s.apply(gg.ops_as_tuples(d), what=("untyped", i))
+    # cutting a chain in the middle shortens the fixpoint
+    s.close()
+    c = gg.chain(15)
+    s = Session(c, 20, stop=True)
+    s.apply([("del_e", 7, 0, 8)], what="cut chain")
+    s.apply([("add_e", 7, 0, 8)], what="rejoin chain")
+    s.close()
+
+
+def test_frontier_through_large_vertices():
+    # vertices of degree above the wave limit take the chunked global-table path
+    rng = np.random.default_rng(31)
+    n = 3000
+    src = [np.full(d, v) for v, d in enumerate([600, 5000, 9000, 513, 512])]
+    dst = [rng.integers(0, n, size=len(x)) for x in src]
+    lab = [rng.integers(0, 6, size=len(x)) for x in src]
+    src.append(rng.integers(5, n, size=12000))
+    dst.append(rng.integers(0, n, size=12000))
+    lab.append(rng.integers(0, 6, size=12000))
+    g = gg.from_edges(n, np.concatenate(src), np.concatenate(dst), np.concatenate(lab),
+                      types=[[int(x)] for x in rng.integers(0, 3, n)], n_labels=6)
+    s = Session(g, 3)
+    # touch the targets of the large vertices so they re-hash at level 2
+    for i in range(4):
+        d = gg.update_ops(s.g, rng, 200, n_labels=6, n_types=3)
+        s.apply(gg.ops_as_tuples(d), what=("large", i))
+    s.apply([("add_e", 1, 5, 7), ("del_e", 2, int(s.g.lab[s.g.row_off[2]]), int(s.g.tgt[s.g.row_off[2]]))],
+            what="large rows")
+    s.close()
+
+
+def test_incremental_equals_gpu_batch_on_state_graph():
+    rng = np.random.default_rng(37)
+    g = gg.rmat_graph(12, 1 << 15, n_types=16, n_labels=8, seed=4)
+    s = Session(g, 4, device_input=True)
+    d = gg.update_ops(s.g, rng, 2000, n_labels=8, n_types=16, rmat_scale=12)
+    ops = gg.ops_as_tuples(d)
+    s.g = apply_ops(s.g, ops)
+    inc = result_dict(s.state.apply(binding.UpdateBatch.from_op_arrays(d)))
+    full = binding.summarize(ctx(), binding._Borrowed(s.state.device_graph()), k_max=4,
+                             stop_at_fixpoint=False)
+    assert_same(inc, full.to_dict(), "incremental vs GPU batch")
+    full.free()
+    s.check(inc, "incremental vs oracle")
+    s.close()
+
+
+def test_invalid_batches_leave_state_unchanged():
+    g = gg.from_edges(4, [0, 1, 2], [1, 2, 3], [0, 0, 0], types=[[0], [1], [1], [2]])
+    s = Session(g, 3)
+    bad = [
+        ([("del_v", 1), ("add_e", 0, 0, 1)], binding.E_INVALID),
+        ([("add_e", 0, 0, 9)], binding.E_RANGE),
+        ([("mod_v", 7, [1])], binding.E_RANGE),
+        ([("add_e", 0, 1 << 24, 1)], binding.E_RANGE),
+    ]
+    for ops, code in bad:
+        with pytest.raises(binding.BsimError) as e:
+            s.state.apply(binding.UpdateBatch(ops))
+        assert e.value.status == code
+        assert rows(s.state.graph()) == rows(s.g)
+    s.apply([("add_e", 3, 1, 0)], what="after errors")
+    s.close()
