@@ -422,3 +422,18 @@ class _Borrowed:
 
     def struct(self) -> BsimGraph:
         return self.gs
+
+
+def batch_summarize(ctx: Context, graphs: Sequence, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
+                    untyped: bool = False, summary_edges: bool = True,
+                    result_on_host: bool = False) -> List[Result]:
+    """bsim_batch_summarize: one refinement run over many graphs (all
+    DeviceGraph or all HostGraph, same label width); one Result per graph."""
+    flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
+            (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0)
+    G = len(graphs)
+    arr = (BsimGraph * max(G, 1))(*[g.struct() for g in graphs])
+    outs = (ctypes.POINTER(BsimResult) * max(G, 1))()
+    params = BsimParams(int(k_max), flags)
+    ctx.check(lib().bsim_batch_summarize(ctx.handle, arr, G, ctypes.byref(params), outs))
+    return [Result(outs[i]) for i in range(G)]

@@ -126,6 +126,17 @@ int bsim_summarize(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* pa
     }
 }
 
+namespace bsim {
+SharedArrays::~SharedArrays() {
+    if (!device_ptrs.empty()) {
+        (void)hipSetDevice(device);
+        for (void* q : device_ptrs) (void)hipFreeAsync(q, stream);
+        (void)hipStreamSynchronize(stream);
+    }
+    for (void* q : host_ptrs) free(q);
+}
+}  // namespace bsim
+
 void bsim_result_free(bsim_result* r) {
     if (!r) return;
     ResultPriv* p = static_cast<ResultPriv*>(r->priv);

@@ -1,6 +1,7 @@
 // bsim_api_internal.h -- host-side objects behind the opaque ABI handles.
 #pragma once
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,16 @@ struct bsim_ctx {
 
 namespace bsim {
 
+// Arrays shared by several results (the per-graph results of one batched
+// call are views into the batch's arrays); freed with the last holder.
+struct SharedArrays {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<void*> device_ptrs;
+    std::vector<void*> host_ptrs;
+    ~SharedArrays();
+};
+
 // Owner of a result's arrays.
 struct ResultPriv {
     int device = 0;
@@ -25,6 +36,7 @@ struct ResultPriv {
     std::vector<void*> device_ptrs;
     std::vector<void*> host_ptrs;
     std::vector<uint32_t> blocks_per_iter;
+    std::shared_ptr<SharedArrays> shared;
 };
 
 // Device copies of the caller's graph when it arrives in host memory, or
@@ -62,6 +74,10 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
 // Whole batch path for one graph.
 bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,
                              void* unused);
+
+// Many independent graphs in one refinement run (a disjoint union).
+void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t n_graphs, const bsim_params& p,
+                     bsim_result** outs);
 
 // Batch path that also returns a resident state for incremental updates.
 int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,

@@ -1440,9 +1440,4 @@ void bsim_state_free(bsim_state* st) {
     delete st;
 }
 
-int bsim_batch_summarize(bsim_ctx*, const bsim_graph*, uint32_t, const bsim_params*, bsim_result** outs) {
-    (void)outs;
-    return BSIM_E_UNSUPPORTED;
-}
-
 }  // extern "C"

@@ -94,6 +94,22 @@ struct SplitTable {
     uint32_t mask;        // cap - 1
 };
 
+// Per-graph control of a batched run: many independent graphs refined as one
+// disjoint union.  Level-0 classes are keyed by a virtual class per graph, so
+// no class spans two graphs; every graph has its own stop test, and once a
+// graph has stopped at level L its vertices keep rep (level L classes) and
+// the hash buffer of parity L untouched.  gid == nullptr: not batched.
+struct BatchCtl {
+    const uint32_t* gid = nullptr;  // vertex -> graph
+    uint32_t* done_level = nullptr; // per graph: level it stopped at, UINT32_MAX while running
+    uint32_t* fix = nullptr;        // per graph: 1 if it stopped at its fixpoint
+    uint32_t* hist = nullptr;       // [hist_cap][n_graphs] classes founded per level
+    uint32_t* n_done = nullptr;     // graphs stopped so far
+    uint32_t n_graphs = 0;
+    uint32_t hist_cap = 0;
+    uint32_t virt_base = 0;         // level-0 virtual class of graph g: virt_base + g
+};
+
 // Arguments of one refinement launch k: split test of level k-1, h^k.
 struct IterArgs {
     const uint32_t* row_off;
@@ -124,6 +140,7 @@ struct IterArgs {
     uint32_t k;
     uint32_t k_max;
     uint32_t stop;
+    BatchCtl bc;
 };
 
 // Arguments of the hub-bucket launch of iteration k.
@@ -146,6 +163,8 @@ struct HubArgs {
     RunStatus* status;
     uint32_t table_slots;   // LDS slots (power of two)
     uint32_t table_limit;   // re-split a bucket beyond this many keys
+    uint32_t k;
+    BatchCtl bc;
 };
 
 // ------------------------------------------------------------ host helpers
@@ -274,6 +293,7 @@ struct RunBuffers {
     uint64_t* hub_acc = nullptr;
     uint32_t* hub_done = nullptr;
     RunStatus* status = nullptr;
+    BatchCtl bc;                   // batched runs only
 };
 
 void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& rb, Arena& arena,
@@ -288,6 +308,9 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
 
 // Hub buckets of iteration k (only when the graph has hubs and k <= k_max).
 void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s);
+
+// Batched runs: per-graph stop test of level k-2, before launch k.
+void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool stop, hipStream_t s);
 
 // LDS slots the hub-bucket launch can use on this device.
 // device_max: the largest table the device allows (else the default size).

@@ -123,7 +123,8 @@ __global__ void __launch_bounds__(kBlock) k_init(const uint32_t* __restrict__ ty
                                                  const uint8_t* __restrict__ alive, uint32_t n,
                                                  int untyped, uint64_t* __restrict__ t,
                                                  uint64_t* __restrict__ h0, uint32_t* __restrict__ rep,
-                                                 SplitTable T, uint32_t* lcnt, RunStatus* status) {
+                                                 SplitTable T, uint32_t* lcnt, RunStatus* status,
+                                                 BatchCtl bc) {
     __shared__ uint32_t s_red[kBlock / 64];
     __shared__ uint32_t s_base;
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
@@ -143,7 +144,13 @@ __global__ void __launch_bounds__(kBlock) k_init(const uint32_t* __restrict__ ty
                 }
             }
             tv = mix64(kCT + sum);
-            r = static_cast<uint32_t>(split_join(T, kNoRep, tv, v, &founded, &slot, status));
+            if (bc.gid) {
+                const uint32_t gi = bc.gid[v];
+                r = static_cast<uint32_t>(split_join(T, bc.virt_base + gi, tv, v, &founded, &slot, status));
+                if (founded) atomicAdd(&bc.hist[gi], 1u);
+            } else {
+                r = static_cast<uint32_t>(split_join(T, kNoRep, tv, v, &founded, &slot, status));
+            }
         }
         t[v] = tv;
         h0[v] = tv;
@@ -169,11 +176,14 @@ __device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32
     *founded = 0;
     *slot = 0xFFFFFFFFu;
     if (a.alive && !a.alive[v]) return;
+    if (a.bc.gid && a.k - 1 > a.bc.done_level[a.bc.gid[v]]) return;
     const uint32_t r = a.rep[v];
     if (r == v) return;
     const uint64_t hv = a.h_prev[v];
     if (hv == a.h_prev[r]) return;
     a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, r, hv, v, founded, slot, a.status));
+    if (a.bc.gid && *founded)
+        atomicAdd(&a.bc.hist[static_cast<size_t>(a.k - 1) * a.bc.n_graphs + a.bc.gid[v]], 1u);
 }
 
 template <typename LabT>
@@ -188,10 +198,19 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
     uint32_t ro0 = 0, ro1 = 0, rv = v;
     uint64_t hv_own = 0, tv = 0;
     bool live = false;
+    // batched runs: a graph that stopped at level L keeps its level-L state
+    bool act_test = true, act_hash = true;
+    uint32_t gi = 0;
     if (tid <= nv) ro0 = a.row_off[v];
     if (tid + kBlock <= nv) ro1 = a.row_off[v + kBlock];
     if (mine) {
         live = !a.alive || a.alive[v];
+        if (a.bc.gid) {
+            gi = a.bc.gid[v];
+            const uint32_t dl = a.bc.done_level[gi];
+            act_test = a.k - 1 <= dl;
+            act_hash = a.k <= dl;
+        }
         if (test) {
             rv = a.rep[v];
             hv_own = a.h_prev[v];
@@ -201,8 +220,11 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
     if (test) {
         // split test of level k-1: leave the class of rep[v] if h^{k-1} differs
         uint32_t founded = 0, slot = 0xFFFFFFFFu;
-        if (mine && live && rv != v && hv_own != a.h_prev[rv])
+        if (mine && live && act_test && rv != v && hv_own != a.h_prev[rv]) {
             a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, rv, hv_own, v, &founded, &slot, a.status));
+            if (a.bc.gid && founded)
+                atomicAdd(&a.bc.hist[static_cast<size_t>(a.k - 1) * a.bc.n_graphs + gi], 1u);
+        }
         record_founders(a.test_tab, a.lcnt, a.k - 1, founded, slot, S.red, &S.ctl[1]);
     }
     if (!hash) return;
@@ -250,7 +272,7 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
         }
     }
     __syncthreads();
-    if (mine) a.h_next[v] = live ? mix64(tv ^ mix64(kCS + S.acc[tid])) : 0;
+    if (mine && act_hash) a.h_next[v] = live ? mix64(tv ^ mix64(kCS + S.acc[tid])) : 0;
 }
 
 template <typename LabT>
@@ -335,7 +357,8 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
     // ---- phase 0: stop test on level k-2
     if (tid < 64) {
         uint32_t ex = *reinterpret_cast<volatile uint32_t*>(&a.status->done);
-        if (!ex && k >= 2) {
+        // batched runs: the per-graph stop launch before this one sets done
+        if (!ex && k >= 2 && !a.bc.gid) {
             const uint32_t lv = k - 2;
             const uint32_t c = wave_sum_u32(a.lcnt[(lv & (kStripeRing - 1)) * kStripes + tid]);
             const uint32_t nl = lv == 0 ? c : a.totals[lv - 1] + c;
@@ -518,9 +541,31 @@ __global__ void __launch_bounds__(kHubBlock) k_hub(HubArgs a) {
         if (prev + 1 == (1u << logb)) {
             const uint64_t acc = __hip_atomic_load(&a.hub_acc[hi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t v = a.hub_v[hi];
-            a.h_next[v] = mix64(a.t[v] ^ mix64(kCS + acc));
+            if (!a.bc.gid || a.k <= a.bc.done_level[a.bc.gid[v]]) a.h_next[v] = mix64(a.t[v] ^ mix64(kCS + acc));
             a.hub_acc[hi] = 0;
             a.hub_done[hi] = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------ batched stop
+
+// Launch k of a batched run begins with this: graph g stops at level k-2
+// when its class count did not grow there (fixpoint) or k-2 reaches k_max.
+__global__ void __launch_bounds__(kBlock) k_graph_stop(BatchCtl bc, uint32_t k, uint32_t k_max, uint32_t stop,
+                                                       RunStatus* status) {
+    const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= bc.n_graphs || k < 2 || bc.done_level[g] != 0xFFFFFFFFu) return;
+    const uint32_t lv = k - 2;
+    const uint32_t c = bc.hist[static_cast<size_t>(lv) * bc.n_graphs + g];
+    const uint32_t fx = (lv >= 1 && c == 0) ? 1u : 0u;
+    if ((stop && fx) || lv >= k_max) {
+        bc.done_level[g] = lv;
+        bc.fix[g] = fx;
+        if (atomicAdd(bc.n_done, 1u) + 1 == bc.n_graphs) {
+            status->k_done = lv;
+            status->fixpoint = fx;
+            status->done = 1;
         }
     }
 }
@@ -633,7 +678,7 @@ void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_
     const uint32_t n = g.n;
     k_init<<<std::max<uint32_t>(ceil_div(n, kBlock), 1), kBlock, 0, s>>>(
         g.type_off, g.type_ids, g.alive, n, untyped ? 1 : 0, rb.t, rb.h[0], rb.rep, rb.tab[0], rb.lcnt,
-        rb.status);
+        rb.status, rb.bc);
     hip_check(hipGetLastError(), "init launch");
 }
 
@@ -668,6 +713,7 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.k = k;
     a.k_max = k_max;
     a.stop = stop ? 1u : 0u;
+    a.bc = rb.bc;
     const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_tiles, 1);
     if (g.label_bytes == 2)
         k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
@@ -697,8 +743,15 @@ void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t 
     a.status = rb.status;
     a.table_slots = g.hub_table_slots;
     a.table_limit = (g.hub_table_slots / 8) * 7;
+    a.k = k;
+    a.bc = rb.bc;
     k_hub<<<g.n_hub_blocks, kHubBlock, static_cast<size_t>(g.hub_table_slots) * 8, s>>>(a);
     hip_check(hipGetLastError(), "hub launch");
+}
+
+void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool stop, hipStream_t s) {
+    k_graph_stop<<<ceil_div(rb.bc.n_graphs, kBlock), kBlock, 0, s>>>(rb.bc, k, k_max, stop ? 1u : 0u, rb.status);
+    hip_check(hipGetLastError(), "graph stop launch");
 }
 
 void launch_level_classes(const uint64_t* h, uint32_t* rep, const uint8_t* alive, uint32_t n,

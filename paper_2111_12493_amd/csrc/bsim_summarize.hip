@@ -77,7 +77,6 @@ void upload_graph(const bsim_graph& in, Staged& g, Arena& arena, hipStream_t s) 
 
 LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
                           LevelSink* sink, Arena& arena) {
-    (void)arena;
     hipStream_t s = ctx->stream;
     const bool stop = (p.flags & BSIM_STOP_AT_FIXPOINT) != 0;
     const bool untyped = (p.flags & BSIM_UNTYPED) != 0;
@@ -105,6 +104,19 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
         while (!done) {
             if (k <= k_last) {
                 const uint32_t c = static_cast<uint32_t>(std::min<uint64_t>(chunk, k_last - k + 1));
+                if (rb.bc.gid && k + c > rb.bc.hist_cap) {
+                    // launch kk writes level kk-1 of the per-graph history: grow it
+                    // while no launch is in flight
+                    hip_check(hipStreamSynchronize(s), "history sync");
+                    const uint64_t cap = std::max<uint64_t>(2ull * rb.bc.hist_cap, k + c + 1);
+                    const size_t G = rb.bc.n_graphs;
+                    uint32_t* nh = arena.alloc<uint32_t>(cap * G);
+                    hip_check(hipMemsetAsync(nh, 0, cap * G * 4, s), "history clear");
+                    hip_check(hipMemcpyAsync(nh, rb.bc.hist, static_cast<size_t>(rb.bc.hist_cap) * G * 4,
+                                             hipMemcpyDeviceToDevice, s), "history copy");
+                    rb.bc.hist = nh;
+                    rb.bc.hist_cap = static_cast<uint32_t>(cap);
+                }
                 for (uint32_t i = 0; i < c; i++, k++) {
                     const uint32_t kk = static_cast<uint32_t>(k);
                     if (sink && !sink->levels.empty()) {
@@ -121,6 +133,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                         }
                         hip_check(hipEventRecord(et[0], s), "event");
                     }
+                    if (rb.bc.gid) launch_graph_stop(rb, kk, p.k_max, stop, s);
                     launch_iteration(g, rb, kk, p.k_max, stop, s);
                     if (ctx->time_launches) hip_check(hipEventRecord(et[1], s), "event");
                     if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
@@ -169,6 +182,10 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
         throw DeviceError{BSIM_E_DEVICE, "a hub hash bucket could not be split to fit its table"};
     lr.k_done = st.k_done;
     lr.fixpoint = st.fixpoint;
+    if (rb.bc.gid) {  // batched: counts and final buffers are per graph
+        lr.h_final = nullptr;
+        return lr;
+    }
     lr.blocks_per_iter.resize(static_cast<size_t>(lr.k_done) + 1);
     hip_check(hipMemcpy(lr.blocks_per_iter.data(), rb.totals, (lr.k_done + 1) * 4, hipMemcpyDeviceToHost),
               "block counts");
