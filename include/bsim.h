@@ -229,6 +229,58 @@ void bsim_state_free(bsim_state* state);
 int bsim_batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t n_graphs,
                          const bsim_params* params, bsim_result** outs);
 
+/* ---- serving: continuous batching of summarize and update requests ------ */
+
+/*
+ * A server runs requests on a pool of worker threads, each with its own
+ * context and HIP stream, so the kernels of concurrent requests overlap on
+ * the device.  Admission is by memory footprint: a request starts once its
+ * estimated device footprint fits the budget that running requests and
+ * server-owned states leave free; until then it waits (requests start in
+ * submission order among those that fit).  Updates of one state run one at
+ * a time in submission order.  Every result equals what the same call made
+ * alone would return.
+ */
+typedef struct bsim_server bsim_server;
+
+#define BSIM_REQ_SUMMARIZE 1u /* summarize `graph` (optionally keeping a state) */
+#define BSIM_REQ_UPDATE 2u    /* apply `ops` to `state` */
+
+typedef struct {
+    uint32_t kind;
+    uint32_t keep_state;      /* SUMMARIZE: also create a server-owned state */
+    const bsim_graph* graph;  /* SUMMARIZE: host arrays are copied at submit;
+                                 device arrays are borrowed until completion */
+    bsim_params params;       /* SUMMARIZE */
+    bsim_state* state;        /* UPDATE: a state from this server (keep_state) or
+                                 one the caller does not touch meanwhile */
+    const bsim_update* ops;   /* UPDATE: copied at submit (with their type lists) */
+    uint64_t n_ops;
+} bsim_request;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t bytes_in_use, bytes_budget;
+    double p50_ms[3], p99_ms[3]; /* index 0 all, 1 summarize, 2 update: submit-to-done */
+    double busy_ms;              /* wall time from first submit to last completion */
+} bsim_server_stats;
+
+/* n_workers concurrent requests (1..64); mem_budget_bytes 0 = 90 % of the
+ * device memory free at creation. */
+int bsim_server_create(int device, uint64_t mem_budget_bytes, uint32_t n_workers, bsim_server** out);
+/* Queue a request.  BSIM_E_BUSY: its footprint exceeds the whole budget;
+ * BSIM_E_INVALID / BSIM_E_RANGE: malformed request (nothing queued). */
+int bsim_server_submit(bsim_server* srv, const bsim_request* req, uint64_t* ticket);
+/* Result of a request: BSIM_OK with *out (and *state_out for keep_state)
+ * once done, the request's own error status if it failed, BSIM_E_BUSY if it
+ * is not done and wait == 0.  Each ticket is collected once. */
+int bsim_server_poll(bsim_server* srv, uint64_t ticket, int wait, bsim_result** out, bsim_state** state_out);
+int bsim_server_stats_get(bsim_server* srv, bsim_server_stats* out);
+/* Free a server-owned state and return its memory to the budget. */
+int bsim_server_release_state(bsim_server* srv, bsim_state* state);
+/* Waits for running requests, then frees everything the server owns. */
+void bsim_server_free(bsim_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,19 @@ class BsimUpdate(ctypes.Structure):
                 ("n_types", _u32), ("types", ctypes.POINTER(_u32))]
 
 
+class BsimRequest(ctypes.Structure):
+    _fields_ = [("kind", _u32), ("keep_state", _u32), ("graph", ctypes.POINTER(BsimGraph)),
+                ("params", BsimParams), ("state", _p), ("ops", ctypes.POINTER(BsimUpdate)), ("n_ops", _u64)]
+
+
+class BsimServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _u64), ("completed", _u64), ("failed", _u64), ("bytes_in_use", _u64),
+                ("bytes_budget", _u64), ("p50_ms", ctypes.c_double * 3), ("p99_ms", ctypes.c_double * 3),
+                ("busy_ms", ctypes.c_double)]
+
+
+REQ_SUMMARIZE, REQ_UPDATE = 1, 2
+
 EXPORTS = {
     "bsim_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "bsim_ctx_create": (ctypes.c_int, [ctypes.c_int, _p, ctypes.POINTER(_p)]),
@@ -74,6 +87,13 @@ EXPORTS = {
     "bsim_state_device_graph": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph)]),
     "bsim_host_free": (None, [_p]),
     "bsim_state_free": (None, [_p]),
+    "bsim_server_create": (ctypes.c_int, [ctypes.c_int, _u64, _u32, ctypes.POINTER(_p)]),
+    "bsim_server_submit": (ctypes.c_int, [_p, ctypes.POINTER(BsimRequest), ctypes.POINTER(_u64)]),
+    "bsim_server_poll": (ctypes.c_int, [_p, _u64, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(BsimResult)),
+                                        ctypes.POINTER(_p)]),
+    "bsim_server_stats_get": (ctypes.c_int, [_p, ctypes.POINTER(BsimServerStats)]),
+    "bsim_server_release_state": (ctypes.c_int, [_p, _p]),
+    "bsim_server_free": (None, [_p]),
     "bsim_batch_summarize": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), _u32,
                                             ctypes.POINTER(BsimParams),
                                             ctypes.POINTER(ctypes.POINTER(BsimResult))]),
@@ -437,3 +457,85 @@ def batch_summarize(ctx: Context, graphs: Sequence, k_max: int = K_UNBOUNDED, st
     params = BsimParams(int(k_max), flags)
     ctx.check(lib().bsim_batch_summarize(ctx.handle, arr, G, ctypes.byref(params), outs))
     return [Result(outs[i]) for i in range(G)]
+
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise BsimError(rc, what)
+
+
+class Server:
+    """bsim_server: continuous batching of summarize and update requests."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0, workers: int = 4):
+        h = _p()
+        _check(lib().bsim_server_create(device, int(mem_budget), int(workers), ctypes.byref(h)), "server create")
+        self.handle = h
+        self._keep = {}
+
+    def submit_summarize(self, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
+                         untyped: bool = False, summary_edges: bool = True, keep_state: bool = False) -> int:
+        flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
+                (0 if summary_edges else NO_SUMMARY_EDGES)
+        gs = graph.struct()
+        req = BsimRequest(REQ_SUMMARIZE, 1 if keep_state else 0, ctypes.pointer(gs), BsimParams(int(k_max), flags),
+                          None, None, 0)
+        t = _u64()
+        _check(lib().bsim_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "submit")
+        if graph.struct().mem_kind == MEM_DEVICE:
+            self._keep[t.value] = graph  # device arrays are borrowed until completion
+        return t.value
+
+    def submit_update(self, state, batch: "UpdateBatch") -> int:
+        ptr = batch.arr.ctypes.data_as(ctypes.POINTER(BsimUpdate)) if len(batch) else None
+        req = BsimRequest(REQ_UPDATE, 0, None, BsimParams(0, 0), state, ptr, len(batch))
+        t = _u64()
+        _check(lib().bsim_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "submit")
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """(Result, state handle or None); raises BsimError for a failed request."""
+        out = ctypes.POINTER(BsimResult)()
+        st = _p()
+        rc = lib().bsim_server_poll(self.handle, ticket, 1 if wait else 0, ctypes.byref(out), ctypes.byref(st))
+        self._keep.pop(ticket, None)
+        _check(rc, "request %d" % ticket)
+        return Result(out), (st.value or None)
+
+    def stats(self) -> dict:
+        s = BsimServerStats()
+        _check(lib().bsim_server_stats_get(self.handle, ctypes.byref(s)), "stats")
+        return dict(submitted=s.submitted, completed=s.completed, failed=s.failed,
+                    bytes_in_use=s.bytes_in_use, bytes_budget=s.bytes_budget,
+                    p50_ms=list(s.p50_ms), p99_ms=list(s.p99_ms), busy_ms=s.busy_ms)
+
+    def release_state(self, state):
+        _check(lib().bsim_server_release_state(self.handle, state), "release state")
+
+    def free(self):
+        if getattr(self, "handle", None):
+            lib().bsim_server_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def state_graph(state_handle):
+    """Host copy of any state's graph (as graphgen.Graph)."""
+    s = State.__new__(State)
+    s.handle = state_handle
+
+    class _C:
+        @staticmethod
+        def check(rc):
+            _check(rc, "state graph")
+
+    s.ctx = _C()
+    g = s.graph()
+    s.handle = None
+    return g

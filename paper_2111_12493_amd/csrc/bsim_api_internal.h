@@ -85,4 +85,9 @@ int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_para
 
 void validate_params(const bsim_graph& graph, const bsim_params& p);
 
+// Device bytes a resident state holds.
+uint64_t state_bytes(const bsim_state* st);
+// The context a state runs on.
+bsim_ctx* state_ctx(const bsim_state* st);
+
 }  // namespace bsim

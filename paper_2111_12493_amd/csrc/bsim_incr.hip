@@ -1354,6 +1354,26 @@ int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_para
     return BSIM_OK;
 }
 
+uint64_t state_bytes(const bsim_state* st) {
+    uint64_t b = 0;
+    auto add = [&](const auto& buf) { b += buf.cap * sizeof(*buf.p); };
+    for (int i = 0; i < 2; i++) {
+        add(st->row_off[i]), add(st->src[i]), add(st->tgt[i]), add(st->lab[i]);
+        add(st->type_off[i]), add(st->type_own[i]), add(st->type_ids[i]);
+        add(st->rev_off[i]), add(st->rev_own[i]), add(st->rev_src[i]), add(st->clist[i]);
+    }
+    add(st->alive);
+    for (const auto& l : st->levels) add(l);
+    add(st->salt), add(st->rep), add(st->dflag), add(st->bmark), add(st->fmark), add(st->chg_lo);
+    add(st->chg_hi), add(st->tidx), add(st->kept), add(st->deg), add(st->blist), add(st->flist);
+    add(st->cls_cnt), add(st->kpos), add(st->chunk_owner), add(st->big_done), add(st->big), add(st->big_acc);
+    add(st->scratch);
+    b += static_cast<uint64_t>(st->cls_cap) * (sizeof(SplitSlot) + 4);
+    return b;
+}
+
+bsim_ctx* state_ctx(const bsim_state* st) { return st->ctx; }
+
 }  // namespace bsim
 
 extern "C" {
