@@ -68,14 +68,131 @@ def cpu_baseline(g, iters: int):
                       "thread, %.1f s" % (iters, dt)}
 
 
+def percentile(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+
+
+def incremental_leg(args, binding, gg, torch):
+    """Update-batch latency on a resident graph (k = 4): the incremental form
+    (frontier re-hash, full levels once a frontier exceeds the limit) beside
+    the plain form (every level recomputed for all vertices) on the same
+    batches, each on its own copy of the state."""
+    import numpy as np
+
+    g = gg.make_config(args.inc_workload)
+    print("# incremental: %s, %d vertices, %d edges" % (args.inc_workload, g.n, g.m), file=sys.stderr, flush=True)
+    ctx_i, ctx_p = binding.Context(0), binding.Context(0)
+    ctx_p.set_option("frontier_limit_pct", 0)
+    dg = binding.DeviceGraph(g)
+    t0 = time.perf_counter()
+    st_i = binding.State(ctx_i, dg, 4, stop_at_fixpoint=False, summary_edges=False)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    st_p = binding.State(ctx_p, dg, 4, stop_at_fixpoint=False, summary_edges=False)
+    st_i.result.free()
+    st_p.result.free()
+    del dg
+    rng = np.random.default_rng(17)
+    dead = np.zeros(g.n + 4_000_000, dtype=bool)
+    if g.alive is not None:
+        dead[:g.n] = g.alive == 0
+    n = g.n
+    scale = int(np.ceil(np.log2(max(g.n, 2))))
+    lat_i, lat_p, ops_total = [], [], 0
+    for i in range(args.inc_batches):
+        size = int(round(10 ** rng.uniform(3, np.log10(args.inc_max_ops))))
+        d = gg.sample_update_ops(g.row_off, g.tgt, g.lab, n, dead, rng, size, max(g.n_labels, 1),
+                                 max(g.n_types, 1), rmat_scale=scale)
+        n = d["n_after"]
+        batch = binding.UpdateBatch.from_op_arrays(d)
+        nb = []
+        for st, lat in ((st_i, lat_i), (st_p, lat_p)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = st.apply(batch)
+            lat.append((time.perf_counter() - t) * 1e3)
+            nb.append(r.n_blocks)
+            r.free()
+        if nb[0] != nb[1]:
+            raise RuntimeError("incremental and full recomputation disagree on batch %d" % i)
+        ops_total += size
+        print("# update batch %d: %d ops, incremental %.2f ms, full recomputation %.2f ms"
+              % (i, size, lat_i[-1], lat_p[-1]), file=sys.stderr, flush=True)
+    st_i.free()
+    st_p.free()
+    ctx_i.close()
+    ctx_p.close()
+    p50, p99 = percentile(lat_i, 0.5), percentile(lat_i, 0.99)
+    q50, q99 = percentile(lat_p, 0.5), percentile(lat_p, 0.99)
+    return {"workload": "%s resident, k=4, update batches of log-uniform 10^3-%.0e ops (ADD/MOD/DEL 60/25/15, "
+                        "R-MAT endpoints for new edges)" % (args.inc_workload, args.inc_max_ops),
+            "batches": len(lat_i), "ops": ops_total, "p50_ms": p50, "p99_ms": p99,
+            "plain_p50_ms": q50, "plain_p99_ms": q99, "speedup_p50": q50 / p50, "speedup_p99": q99 / p99,
+            "state_create_s": create_s, "summary_edges": False,
+            "plain_form": "same update batch, every level recomputed for all vertices"}
+
+
+def batched_leg(args, binding, gg, torch):
+    """One batched run over many R-MAT graphs against one call per graph."""
+    import numpy as np
+
+    rng = np.random.default_rng(23)
+    graphs = []
+    for i in range(args.batch_graphs):
+        m = int(round(10 ** rng.uniform(2, np.log10(args.batch_max_edges))))
+        deg = rng.uniform(4, 16)
+        n = max(2, int(round(m / deg)))
+        scale = max(1, int(np.ceil(np.log2(n))))
+        graphs.append(gg.rmat_graph(scale, m, n_types=32, n_labels=32, types_lo=0, types_hi=3, s_types=1.0,
+                                    s_labels=1.0, seed=int(rng.integers(1, 1 << 30)), n=n))
+    dgs = [binding.DeviceGraph(g) for g in graphs]
+    ctx = binding.Context(0)
+    edges = sum(g.m for g in graphs)
+    print("# batched: %d graphs, %d edges" % (len(graphs), edges), file=sys.stderr, flush=True)
+    rs = binding.batch_summarize(ctx, dgs, summary_edges=True)  # warm-up
+    for r in rs:
+        r.free()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs = binding.batch_summarize(ctx, dgs, summary_edges=True)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    work = sum(r.k_done * g.m for r, g in zip(rs, graphs))
+    kmax = max(r.k_done for r in rs)
+    for r in rs:
+        r.free()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for dg in dgs:
+        binding.summarize(ctx, dg).free()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    ctx.close()
+    return {"workload": "%d R-MAT graphs, edges log-uniform 10^2-%.0e, degree U(4,16), 32 types / 32 labels "
+                        "(Zipf 1.0), each to its own fixpoint" % (len(graphs), args.batch_max_edges),
+            "graphs": len(graphs), "edges": edges, "max_k_done": kmax, "edge_iterations": work,
+            "batched_s": tb, "per_graph_s": tp, "value_batched": work / tb, "value_per_graph": work / tp,
+            "speedup": tp / tb}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22_chains")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--time-every", type=int, default=16,
+                    help="bracket every N-th refinement launch with HIP events")
+    ap.add_argument("--no-incremental", action="store_true")
+    ap.add_argument("--inc-workload", default="rmat24")
+    ap.add_argument("--inc-batches", type=int, default=16)
+    ap.add_argument("--inc-max-ops", type=float, default=1e6)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=1024)
+    ap.add_argument("--batch-max-edges", type=float, default=1e5)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one elementwise copy kernel over this many MiB, so that a "
                          "rocprofv3 counter run can scale FETCH_SIZE/WRITE_SIZE")
@@ -108,13 +225,14 @@ def main() -> int:
         del src, dst
     dg = binding.DeviceGraph(g)
     ctx = binding.Context(0)
-    ctx.set_option("time_launches", 1)
+    # time every 16th launch: events on every launch would add gaps to the timed run
+    ctx.set_option("time_launches", args.time_every)
     torch.cuda.synchronize()
 
     def step():
         r = binding.summarize(ctx, dg, k_max=binding.K_UNBOUNDED)
         rec = dict(k_done=r.k_done, launches=r.n_iter_launches, ms_kernels=r.ms_iter_kernels,
-                   ms_hub=r.ms_hub_kernels,
+                   ms_hub=r.ms_hub_kernels, timed=r.n_timed_launches,
                    ms_iterate=r.ms_iterate, ms_stage=r.ms_stage, ms_finalize=r.ms_finalize,
                    ms_total=r.ms_total, n_blocks=r.n_blocks, n_se=r.n_summary_edges)
         r.free()
@@ -141,13 +259,14 @@ def main() -> int:
     label_bytes = 2 if g.lab.dtype.itemsize == 2 else 4
     b_iter = iteration_bytes(g.n, g.m, label_bytes)
     # live kernel timing: HIP events on the library's stream around every
-    # refinement launch; launches 1..k_done+1 of a run do the work, the rest
-    # of the last queued chunk return at once and are not counted
+    # N-th refinement launch; launches 1..k_done+1 of a run do the work, the
+    # rest of the last queued chunk return at once and are not counted
     kern_ms = sum(r["ms_kernels"] for r in recs)
     hub_ms = sum(r["ms_hub"] for r in recs)
     launches = sum(r["launches"] for r in recs)
     working = sum(min(r["k_done"] + 1, r["launches"]) for r in recs)
-    avg_us = kern_ms * 1e3 / max(working, 1)
+    timed = sum(r["timed"] for r in recs)
+    avg_us = kern_ms * 1e3 / max(timed, 1)
     achieved = b_iter / (avg_us * 1e-6) / 1e9 if kern_ms > 0 else 0.0
     traffic = read_traffic(args.workload)
     out = {
@@ -170,12 +289,18 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_iterate", "algorithmic_bytes_per_launch": b_iter,
-                     "avg_launch_us": avg_us, "working_launches": working, "launches_issued": launches,
-                     "hub_kernel_avg_us": hub_ms * 1e3 / max(working, 1)},
+                     "avg_launch_us": avg_us, "timed_launches": timed, "working_launches": working,
+                     "launches_issued": launches, "hub_kernel_avg_us": hub_ms * 1e3 / max(timed, 1)},
     }
+    ctx.close()
+    del dg
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_iters)
-    ctx.close()
+    del g
+    if not args.no_incremental:
+        out["incremental"] = incremental_leg(args, binding, gg, torch)
+    if not args.no_batched:
+        out["batched"] = batched_leg(args, binding, gg, torch)
     print(json.dumps(out), flush=True)
     return 0
 

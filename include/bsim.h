@@ -130,11 +130,13 @@ typedef struct {
     float ms_iterate;
     float ms_finalize;
     float ms_total;
-    float ms_iter_kernels; /* when the ctx option "time_launches" is 1: summed
-                              durations of the refinement-kernel launches that did
-                              work (launches 1..k_done+1; later ones return at
-                              once), else 0 */
+    float ms_iter_kernels; /* when the ctx option "time_launches" is N > 0: summed
+                              durations of every N-th refinement-kernel launch
+                              among those that did work (launches 1..k_done+1;
+                              later ones return at once), else 0 */
     float ms_hub_kernels;  /* the same for the hub-vertex launches */
+    uint32_t n_timed_launches; /* launches those sums cover */
+    uint32_t reserved;
     void* priv;
 } bsim_result;
 
@@ -168,9 +170,11 @@ void bsim_ctx_free(bsim_ctx* ctx);
 const char* bsim_last_error(const bsim_ctx* ctx);
 const char* bsim_status_string(int status);
 /* Run-time options (see bsim_option_names()): "chunk_max" = refinement
- * launches queued per stop-flag check (1..4096); "time_launches" = 1 to
- * bracket every refinement and hub launch with HIP events and report the
- * summed kernel times in bsim_result.ms_iter_kernels / ms_hub_kernels; "hub_table_slots" = LDS hash
+ * launches queued per stop-flag check (1..4096); "time_launches" = N > 0
+ * to bracket every N-th refinement and hub launch (0..1 << 20) with HIP
+ * events and report the summed kernel times in bsim_result.ms_iter_kernels /
+ * ms_hub_kernels (events on every launch add gaps between launches, so
+ * sampling keeps the timed run close to an untimed one); "hub_table_slots" = LDS hash
  * slots of a hub-bucket block (power of two from 64 to the device limit,
  * the default; smaller values force more hash buckets per hub).  Values
  * outside the range give BSIM_E_RANGE, unknown names BSIM_E_INVALID. */

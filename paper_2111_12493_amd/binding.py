@@ -48,7 +48,7 @@ class BsimResult(ctypes.Structure):
                 ("se_dst", _p), ("ms_stage", ctypes.c_float), ("ms_iterate", ctypes.c_float),
                 ("ms_finalize", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_iter_kernels", ctypes.c_float), ("ms_hub_kernels", ctypes.c_float),
-                ("priv", _p)]
+                ("n_timed_launches", _u32), ("reserved", _u32), ("priv", _p)]
 
 
 class BsimUpdate(ctypes.Structure):
@@ -249,6 +249,7 @@ class Result:
         self.ms_finalize, self.ms_total = r.ms_finalize, r.ms_total
         self.ms_iter_kernels = r.ms_iter_kernels
         self.ms_hub_kernels = r.ms_hub_kernels
+        self.n_timed_launches = r.n_timed_launches
 
     def _len(self, field):
         if field in ("hashes", "block_ids"):

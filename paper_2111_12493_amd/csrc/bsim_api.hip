@@ -63,8 +63,10 @@ const char* bsim_last_error(const bsim_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 const char* bsim_option_names(void) {
     return "chunk_max (refinement launches queued per stop-flag check, 1..4096); "
-           "time_launches (0/1: time every refinement launch with HIP events); "
-           "hub_table_slots (LDS slots of a hub-bucket block: power of two, 64..device limit)";
+           "time_launches (N, 0..1048576: time every N-th refinement launch with HIP events, 0 = off); "
+           "hub_table_slots (LDS slots of a hub-bucket block: power of two, 64..device limit); "
+           "frontier_limit_pct (0..100: an update level whose frontier exceeds this share of the vertices is "
+           "recomputed for all vertices; 0 = always, the plain full recomputation)";
 }
 
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
@@ -75,8 +77,13 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
         return BSIM_OK;
     }
     if (!strcmp(name, "time_launches")) {
-        if (value < 0 || value > 1) return BSIM_E_RANGE;
+        if (value < 0 || value > (1 << 20)) return BSIM_E_RANGE;
         ctx->time_launches = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "frontier_limit_pct")) {
+        if (value < 0 || value > 100) return BSIM_E_RANGE;
+        ctx->frontier_limit_pct = static_cast<uint32_t>(value);
         return BSIM_OK;
     }
     if (!strcmp(name, "hub_table_slots")) {
@@ -101,6 +108,10 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     }
     if (!strcmp(name, "hub_table_slots")) {
         *value = ctx->hub_table_slots;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "frontier_limit_pct")) {
+        *value = ctx->frontier_limit_pct;
         return BSIM_OK;
     }
     return BSIM_E_INVALID;

@@ -15,6 +15,7 @@ struct bsim_ctx {
     uint32_t chunk_max = 256;
     uint32_t time_launches = 0;
     uint32_t hub_table_slots = 8192;  // LDS slots per hub-bucket block on this device
+    uint32_t frontier_limit_pct = 2;  // incremental: larger frontiers recompute the level for all vertices
 };
 
 namespace bsim {
@@ -59,6 +60,7 @@ struct LoopResult {
     uint32_t launches = 0;
     float ms_kernels = 0.f;      // refinement launches that did work
     float ms_hub_kernels = 0.f;  // hub launches of those iterations
+    uint32_t n_timed = 0;        // launches the two sums cover
     std::vector<uint32_t> blocks_per_iter;
     const uint64_t* h_final = nullptr;
 };

@@ -379,6 +379,7 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const 
         r->ms_total = ms[3];
         r->ms_iter_kernels = lr.ms_kernels;
         r->ms_hub_kernels = lr.ms_hub_kernels;
+        r->n_timed_launches = lr.n_timed;
         outs[g] = r;
         voff += graphs[g].n_vertices;
     }

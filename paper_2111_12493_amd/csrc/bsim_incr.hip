@@ -50,10 +50,10 @@ constexpr uint32_t kMaxStateTypes = 4096;
 // Device counters of one update batch.
 struct IncCounters {
     uint32_t b_count;      // base frontier list
-    uint32_t f_count;      // frontier of the current level
-    uint32_t c_count[2];   // changed vertices of a level (by parity)
+    uint32_t f_count[2];   // frontier of a level (by parity)
     uint32_t big_count;    // large frontier vertices deferred to chunk blocks
     uint32_t chunk_count;
+    uint32_t pad;
     uint64_t slot_top;     // scratch table slots handed out
 };
 
@@ -85,6 +85,15 @@ __device__ __forceinline__ void mark_append(bool valid, uint32_t v, uint32_t* ma
                                             uint32_t* count) {
     bool first = false;
     if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) == 0) first = atomicOr(&mark[v], 1u) == 0;
+    wave_append(first, v, list, count);
+}
+
+// The same with a tag instead of a flag: marks of earlier levels and
+// batches carry other tags, so the mark array is never cleared.
+__device__ __forceinline__ void tag_append(bool valid, uint32_t v, uint32_t tag, uint32_t* mark, uint32_t* list,
+                                           uint32_t* count) {
+    bool first = false;
+    if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) != tag) first = atomicExch(&mark[v], tag) != tag;
     wave_append(first, v, list, count);
 }
 
@@ -365,19 +374,15 @@ __global__ void k_typ_write(const uint32_t* __restrict__ tl, uint32_t nT, const 
 // Level 0 on the vertices whose types changed: C_0 = those whose t changed.
 __global__ void k_level0(const uint32_t* __restrict__ tl, uint32_t nT, const uint32_t* __restrict__ type_off,
                          const uint32_t* __restrict__ type_ids, const uint8_t* __restrict__ alive,
-                         int untyped, uint64_t* __restrict__ t, uint32_t* clist, IncCounters* cnt) {
+                         int untyped, uint64_t* __restrict__ t, uint32_t* cflag, uint32_t tag) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    bool changed = false;
-    uint32_t v = 0;
-    if (i < nT) {
-        v = tl[i];
-        const uint64_t tv = alive[v] ? type_hash(type_ids, type_off[v], type_off[v + 1], untyped != 0) : 0;
-        if (tv != t[v]) {
-            t[v] = tv;
-            changed = true;
-        }
+    if (i >= nT) return;
+    const uint32_t v = tl[i];
+    const uint64_t tv = alive[v] ? type_hash(type_ids, type_off[v], type_off[v + 1], untyped != 0) : 0;
+    if (tv != t[v]) {
+        t[v] = tv;
+        cflag[v] = tag;
     }
-    wave_append(changed, v, clist, &cnt->c_count[0]);
 }
 
 // ---------------------------------------------------------------- reverse lists
@@ -418,8 +423,7 @@ __global__ void k_rev_append(const uint32_t* __restrict__ rw, const uint32_t* __
 
 __global__ void k_level_reset(IncCounters* cnt, uint32_t parity) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        cnt->f_count = 0;
-        cnt->c_count[parity] = 0;
+        cnt->f_count[parity] = 0;
         cnt->big_count = 0;
         cnt->chunk_count = 0;
         cnt->slot_top = 0;
@@ -427,30 +431,33 @@ __global__ void k_level_reset(IncCounters* cnt, uint32_t parity) {
 }
 
 // F_j starts as the base set B.
-__global__ void k_front_base(const uint32_t* __restrict__ blist, const IncCounters* cnt_in, uint32_t* fmark,
-                             uint32_t* flist, IncCounters* cnt) {
-    const uint32_t nb = cnt_in->b_count;
+__global__ void k_front_base(const uint32_t* __restrict__ blist, IncCounters* cnt, uint32_t parity, uint32_t tag,
+                             uint32_t* fmark, uint32_t* flist) {
+    const uint32_t nb = cnt->b_count;
     for (uint32_t i0 = blockIdx.x * kBlock; i0 < nb; i0 += gridDim.x * kBlock) {
         const uint32_t i = i0 + threadIdx.x;
         const bool valid = i < nb;
-        mark_append(valid, valid ? blist[i] : 0u, fmark, flist, &cnt->f_count);
+        tag_append(valid, valid ? blist[i] : 0u, tag, fmark, flist, &cnt->f_count[parity]);
     }
 }
 
-// F_j grows by the in-neighbours of C_{j-1} (one wave per changed vertex).
-__global__ void k_front_innbrs(const uint32_t* __restrict__ clist, const IncCounters* cnt_in, uint32_t parity,
+// F_j grows by the in-neighbours of C_{j-1}: the vertices of the previous
+// list whose change tag is prev_tag (one wave per listed vertex).
+__global__ void k_front_innbrs(const uint32_t* __restrict__ prev, const uint32_t* prev_count, uint32_t prev_n,
+                               const uint32_t* __restrict__ cflag, uint32_t prev_tag,
                                const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
-                               uint32_t* fmark, uint32_t* flist, IncCounters* cnt) {
-    const uint32_t nc = cnt_in->c_count[parity];
+                               uint32_t tag, uint32_t* fmark, uint32_t* flist, IncCounters* cnt, uint32_t parity) {
+    const uint32_t np = prev_count ? *prev_count : prev_n;
     const uint32_t lane = lane_id();
     const uint32_t waves = gridDim.x * (kBlock / 64);
-    for (uint32_t i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < nc; i += waves) {
-        const uint32_t w = clist[i];
+    for (uint32_t i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < np; i += waves) {
+        const uint32_t w = prev[i];
+        if (cflag[w] != prev_tag) continue;
         const uint32_t a = rev_off[w], b = rev_off[w + 1];
         for (uint32_t j0 = a; j0 < b; j0 += 64) {
             const uint32_t j = j0 + lane;
             const bool valid = j < b;
-            mark_append(valid, valid ? rev_src[j] : 0u, fmark, flist, &cnt->f_count);
+            tag_append(valid, valid ? rev_src[j] : 0u, tag, fmark, flist, &cnt->f_count[parity]);
         }
     }
 }
@@ -465,21 +472,22 @@ struct FrontArgs {
     uint64_t* h_cur;
     const uint8_t* alive;
     const uint32_t* flist;
-    uint32_t* clist;
+    const uint32_t* f_count;
+    uint32_t* cflag;
+    uint32_t tag;
     IncCounters* cnt;
     BigEntry* big;
     uint32_t* chunk_owner;
     uint64_t* big_acc;
     uint32_t* big_done;
     uint64_t* scratch;
-    uint32_t parity;
 };
 
+// Store h^j(v); a changed value tags v for the next level's frontier.
 __device__ __forceinline__ void publish(const FrontArgs& a, uint32_t v, uint64_t h) {
     if (a.h_cur[v] != h) {
         a.h_cur[v] = h;
-        const uint32_t pos = atomicAdd(&a.cnt->c_count[a.parity], 1u);
-        a.clist[pos] = v;
+        a.cflag[v] = a.tag;
     }
 }
 
@@ -491,7 +499,7 @@ __global__ void __launch_bounds__(kBlock) k_front_hash(FrontArgs a) {
     __shared__ uint64_t s_tab[kBlock / 64][kWaveSlots];
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
     volatile uint64_t* tab = s_tab[wid];
-    const uint32_t nf = a.cnt->f_count;
+    const uint32_t nf = *a.f_count;
     const uint32_t waves = gridDim.x * (kBlock / 64);
     const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
     for (uint32_t i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < nf; i += waves) {
@@ -670,7 +678,8 @@ struct bsim_state {
     DevBuf<uint8_t> alive;
     std::vector<DevBuf<uint64_t>> levels;
     DevBuf<uint64_t> salt;
-    DevBuf<uint32_t> rep, dflag, bmark, fmark, chg_lo, chg_hi, tidx, kept, deg, blist, flist, clist[2];
+    DevBuf<uint32_t> rep, dflag, bmark, fmark, chg_lo, chg_hi, tidx, kept, deg, blist, flist[2], cflag;
+    uint32_t tag_base = 0;  // change / frontier tags of the next batch start above this
     SplitSlot* cls_slots = nullptr;
     uint64_t* cls_zero = nullptr;
     uint32_t* cls_list = nullptr;
@@ -688,13 +697,13 @@ struct bsim_state {
             row_off[i].release(s), src[i].release(s), tgt[i].release(s), lab[i].release(s);
             type_off[i].release(s), type_own[i].release(s), type_ids[i].release(s);
             rev_off[i].release(s), rev_own[i].release(s), rev_src[i].release(s);
-            clist[i].release(s);
+            flist[i].release(s);
         }
         alive.release(s);
         for (auto& l : levels) l.release(s);
-        salt.release(s), rep.release(s), dflag.release(s), bmark.release(s), fmark.release(s);
+        salt.release(s), rep.release(s), dflag.release(s), bmark.release(s), fmark.release(s), cflag.release(s);
         chg_lo.release(s), chg_hi.release(s), tidx.release(s), kept.release(s), deg.release(s);
-        blist.release(s), flist.release(s), cls_cnt.release(s), kpos.release(s), chunk_owner.release(s);
+        blist.release(s), cls_cnt.release(s), kpos.release(s), chunk_owner.release(s);
         big_done.release(s), big.release(s), big_acc.release(s), scratch.release(s), cnt.release(s);
         status.release(s);
         if (cls_slots) (void)hipFreeAsync(cls_slots, s);
@@ -721,13 +730,15 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
     st->rev_off[st->rcur ^ 1].ensure(nv, 0, s);
     st->alive.ensure(nv, keep_v, s);
     for (auto& l : st->levels) l.ensure(nv, keep_v, s);
-    // chg_lo / chg_hi / tidx are zero outside a batch: keep them
+    // chg_lo / chg_hi / tidx are zero outside a batch, fmark / cflag hold
+    // tags of earlier batches: keep them
     st->chg_lo.ensure(nv, keep_v, s);
     st->chg_hi.ensure(nv, keep_v, s);
     st->tidx.ensure(nv, keep_v, s);
-    for (DevBuf<uint32_t>* b : {&st->rep, &st->dflag, &st->bmark, &st->fmark, &st->kept, &st->deg,
-                                &st->blist, &st->flist, &st->clist[0], &st->clist[1], &st->big_done,
-                                &st->chunk_owner})
+    st->fmark.ensure(nv, keep_v, s);
+    st->cflag.ensure(nv, keep_v, s);
+    for (DevBuf<uint32_t>* b : {&st->rep, &st->dflag, &st->bmark, &st->kept, &st->deg, &st->blist,
+                                &st->flist[0], &st->flist[1], &st->big_done, &st->chunk_owner})
         b->ensure(nv, 0, s);
     st->big.ensure(nv, 0, s);
     st->big_acc.ensure(nv, 0, s);
@@ -1062,21 +1073,67 @@ void merge_reverse(bsim_state* st, const HostBatch& hb, Arena& arena) {
     st->n_rev = n_new;
 }
 
-// Re-hash levels 1..K on the frontiers of the batch (level 0 already done).
-void propagate(bsim_state* st) {
+// Levels j0..K for every vertex with the refinement kernels (hash-only
+// mode): used when a frontier covers a large share of the graph, and as the
+// plain form (full recomputation per update).
+void full_levels(bsim_state* st, uint32_t j0, Arena& arena) {
+    hipStream_t s = st->s;
+    Staged g;
+    g.n = st->n;
+    g.m = st->m;
+    g.label_bytes = st->label_bytes;
+    g.row_off = st->row_off[st->cur].p;
+    g.tgt = st->tgt[st->cur].p;
+    g.lab = st->lab[st->cur].p;
+    g.type_off = st->type_off[st->tcur].p;
+    g.type_ids = st->type_ids[st->tcur].p;
+    g.alive = st->alive.p;
+    g.hub_table_slots = st->ctx->hub_table_slots;
+    RunStatus* sd = arena.alloc<RunStatus>(1);
+    stage_graph(g, sd, &st->ctx->status_host[3], arena, s);
+    HashScratch hs;
+    alloc_hash_scratch(g, hs, arena, s);
+    for (uint32_t j = j0; j <= st->K; j++)
+        launch_hash_level(g, st->levels[0].p, st->levels[j - 1].p, st->levels[j].p, hs, j, s);
+}
+
+// Re-hash levels 1..K on the frontiers of the batch (level 0 already done:
+// the vertices of `tl` whose t changed carry tag `tag0` in cflag).  A level
+// whose frontier exceeds the ctx's frontier limit, and every level after
+// it, is recomputed for all vertices instead.
+void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0, Arena& arena) {
     hipStream_t s = st->s;
     const uint32_t n = st->n;
+    const uint64_t limit = static_cast<uint64_t>(n) * st->ctx->frontier_limit_pct / 100;
+    if (st->ctx->frontier_limit_pct == 0) {
+        if (st->K >= 1) full_levels(st, 1, arena);
+        return;
+    }
     // every table slot of a deferred vertex: next_pow2(2 deg) <= 4 deg
     st->scratch.ensure(4 * std::max<uint64_t>(st->m, 16), 0, s);
     st->chunk_owner.ensure(static_cast<size_t>(n) + st->m / kChunkEdges + 2, 0, s);
     const int lb = st->label_bytes;
+    uint32_t fcount = 0;
     for (uint32_t j = 1; j <= st->K; j++) {
         const uint32_t par = j & 1;
+        const uint32_t tag = tag0 + j;
         k_level_reset<<<1, 64, 0, s>>>(st->cnt.p, par);
-        hip_check(hipMemsetAsync(st->fmark.p, 0, (static_cast<size_t>(n) + 1) * 4, s), "frontier marks");
-        k_front_base<<<256, kBlock, 0, s>>>(st->blist.p, st->cnt.p, st->fmark.p, st->flist.p, st->cnt.p);
-        k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(st->clist[par ^ 1].p, st->cnt.p, par ^ 1, st->rev_off[st->rcur].p,
-                                                     st->rev_src[st->rcur].p, st->fmark.p, st->flist.p, st->cnt.p);
+        k_front_base<<<256, kBlock, 0, s>>>(st->blist.p, st->cnt.p, par, tag, st->fmark.p, st->flist[par].p);
+        if (j == 1)
+            k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(d_tl, nullptr, nT, st->cflag.p, tag0, st->rev_off[st->rcur].p,
+                                                         st->rev_src[st->rcur].p, tag, st->fmark.p, st->flist[par].p,
+                                                         st->cnt.p, par);
+        else
+            k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(st->flist[par ^ 1].p, &st->cnt.p->f_count[par ^ 1], 0,
+                                                         st->cflag.p, tag - 1, st->rev_off[st->rcur].p,
+                                                         st->rev_src[st->rcur].p, tag, st->fmark.p, st->flist[par].p,
+                                                         st->cnt.p, par);
+        hip_check(hipGetLastError(), "frontier marks");
+        fcount = read_u32(&st->cnt.p->f_count[par], s);
+        if (fcount > limit) {
+            full_levels(st, j, arena);
+            return;
+        }
         FrontArgs a;
         a.row_off = st->row_off[st->cur].p;
         a.tgt = st->tgt[st->cur].p;
@@ -1086,20 +1143,22 @@ void propagate(bsim_state* st) {
         a.h_prev = st->levels[j - 1].p;
         a.h_cur = st->levels[j].p;
         a.alive = st->alive.p;
-        a.flist = st->flist.p;
-        a.clist = st->clist[par].p;
+        a.flist = st->flist[par].p;
+        a.f_count = &st->cnt.p->f_count[par];
+        a.cflag = st->cflag.p;
+        a.tag = tag;
         a.cnt = st->cnt.p;
         a.big = st->big.p;
         a.chunk_owner = st->chunk_owner.p;
         a.big_acc = st->big_acc.p;
         a.big_done = st->big_done.p;
         a.scratch = st->scratch.p;
-        a.parity = par;
-        if (lb == 2) k_front_hash<uint16_t><<<kFrontGrid, kBlock, 0, s>>>(a);
-        else k_front_hash<uint32_t><<<kFrontGrid, kBlock, 0, s>>>(a);
-        k_big_clear<<<1024, kBlock, 0, s>>>(st->cnt.p, st->scratch.p);
-        if (lb == 2) k_big_chunks<uint16_t><<<1024, kBlock, 0, s>>>(a);
-        else k_big_chunks<uint32_t><<<1024, kBlock, 0, s>>>(a);
+        const uint32_t grid = std::max<uint32_t>(std::min<uint32_t>(ceil_div(fcount, kBlock / 64), kFrontGrid), 1);
+        if (lb == 2) k_front_hash<uint16_t><<<grid, kBlock, 0, s>>>(a);
+        else k_front_hash<uint32_t><<<grid, kBlock, 0, s>>>(a);
+        k_big_clear<<<256, kBlock, 0, s>>>(st->cnt.p, st->scratch.p);
+        if (lb == 2) k_big_chunks<uint16_t><<<512, kBlock, 0, s>>>(a);
+        else k_big_chunks<uint32_t><<<512, kBlock, 0, s>>>(a);
         hip_check(hipGetLastError(), "frontier launch");
     }
 }
@@ -1203,8 +1262,8 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
         hip_check(hipMemsetAsync(st->alive.p + n_old, 1, grow, s), "new alive");
         for (auto& l : st->levels) hip_check(hipMemsetAsync(l.p + n_old, 0, grow * 8, s), "new levels");
         // a grown index array holds unset memory past the old vertices
-        for (DevBuf<uint32_t>* b : {&st->chg_lo, &st->chg_hi, &st->tidx})
-            hip_check(hipMemsetAsync(b->p + n_old, 0, (grow + 1) * 4, s), "index arrays");
+        for (DevBuf<uint32_t>* b : {&st->chg_lo, &st->chg_hi, &st->tidx, &st->fmark, &st->cflag})
+            hip_check(hipMemsetAsync(b->p + n_old, 0, (grow + 1) * 4, s), "index and tag arrays");
     }
     hip_check(hipMemsetAsync(st->dflag.p, 0, (static_cast<size_t>(n_new) + 1) * 4, s), "dflag");
     hip_check(hipMemsetAsync(st->bmark.p, 0, (static_cast<size_t>(n_new) + 1) * 4, s), "bmark");
@@ -1246,12 +1305,20 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
     ensure_salt(st, st->max_label);
     if (st->rm > 2 * st->m + 65536) rebuild_reverse(st, arena);
     tm.mark(1);
+    // tags of this batch: tag0 for level 0, tag0 + j for level j
+    if (st->tag_base > 0xFFFFFFFFu - 2 * (st->K + 2)) {
+        hip_check(hipMemsetAsync(st->fmark.p, 0, st->fmark.cap * 4, s), "tags");
+        hip_check(hipMemsetAsync(st->cflag.p, 0, st->cflag.cap * 4, s), "tags");
+        st->tag_base = 0;
+    }
+    const uint32_t tag0 = st->tag_base + 1;
+    st->tag_base += st->K + 2;
     if (nT)
         k_level0<<<grid_for(nT), kBlock, 0, s>>>(d_tl, nT, st->type_off[st->tcur].p, st->type_ids[st->tcur].p,
-                                                 st->alive.p, st->untyped ? 1 : 0, st->levels[0].p, st->clist[0].p,
-                                                 st->cnt.p);
+                                                 st->alive.p, st->untyped ? 1 : 0, st->levels[0].p, st->cflag.p,
+                                                 tag0);
     hip_check(hipGetLastError(), "level 0");
-    propagate(st);
+    propagate(st, d_tl, nT, tag0, arena);
     tm.mark(2);
     bsim_result* r = finish(st, arena, nullptr);
     tm.mark(3);
@@ -1284,8 +1351,8 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     ensure_vertices(st, g.n);
     // chg_lo / chg_hi / tidx are index arrays that every batch reads for all
     // vertices: they start at zero and batches restore the entries they set
-    for (DevBuf<uint32_t>* b : {&st->chg_lo, &st->chg_hi, &st->tidx})
-        hip_check(hipMemsetAsync(b->p, 0, b->cap * 4, s), "index arrays");
+    for (DevBuf<uint32_t>* b : {&st->chg_lo, &st->chg_hi, &st->tidx, &st->fmark, &st->cflag})
+        hip_check(hipMemsetAsync(b->p, 0, b->cap * 4, s), "index and tag arrays");
     st->n = g.n;
     st->m = g.m;
     st->max_label = g.max_label;
@@ -1360,12 +1427,12 @@ uint64_t state_bytes(const bsim_state* st) {
     for (int i = 0; i < 2; i++) {
         add(st->row_off[i]), add(st->src[i]), add(st->tgt[i]), add(st->lab[i]);
         add(st->type_off[i]), add(st->type_own[i]), add(st->type_ids[i]);
-        add(st->rev_off[i]), add(st->rev_own[i]), add(st->rev_src[i]), add(st->clist[i]);
+        add(st->rev_off[i]), add(st->rev_own[i]), add(st->rev_src[i]), add(st->flist[i]);
     }
     add(st->alive);
     for (const auto& l : st->levels) add(l);
     add(st->salt), add(st->rep), add(st->dflag), add(st->bmark), add(st->fmark), add(st->chg_lo);
-    add(st->chg_hi), add(st->tidx), add(st->kept), add(st->deg), add(st->blist), add(st->flist);
+    add(st->chg_hi), add(st->tidx), add(st->kept), add(st->deg), add(st->blist), add(st->cflag);
     add(st->cls_cnt), add(st->kpos), add(st->chunk_owner), add(st->big_done), add(st->big), add(st->big_acc);
     add(st->scratch);
     b += static_cast<uint64_t>(st->cls_cap) * (sizeof(SplitSlot) + 4);

@@ -140,6 +140,7 @@ struct IterArgs {
     uint32_t k;
     uint32_t k_max;
     uint32_t stop;
+    uint32_t hash_only;     // h^k only: no stop test, split test or recycling
     BatchCtl bc;
 };
 
@@ -308,6 +309,20 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
 
 // Hub buckets of iteration k (only when the graph has hubs and k <= k_max).
 void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s);
+
+// Scratch of hash-only launches (hub keys and per-hub sums).
+struct HashScratch {
+    uint64_t* hub_keys = nullptr;
+    uint32_t* hub_boff = nullptr;
+    uint64_t* hub_acc = nullptr;   // zero, kept zero by the launches
+    uint32_t* hub_done = nullptr;  // zero, kept zero by the launches
+    RunStatus* status = nullptr;   // zero (never done)
+};
+void alloc_hash_scratch(const Staged& g, HashScratch& hs, Arena& arena, hipStream_t s);
+// h_next = h^level from h_prev = h^{level-1} for every vertex of a staged
+// graph, with the refinement kernels in hash-only mode.
+void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_prev, uint64_t* h_next,
+                       const HashScratch& hs, uint32_t level, hipStream_t s);
 
 // Batched runs: per-graph stop test of level k-2, before launch k.
 void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool stop, hipStream_t s);

@@ -186,21 +186,57 @@ __device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32
         atomicAdd(&a.bc.hist[static_cast<size_t>(a.k - 1) * a.bc.n_graphs + a.bc.gid[v]], 1u);
 }
 
+// Stop test of level k-2 (wave 0), from the values loaded at block start:
+// S.ctl[0] = 1 when the run is done; block 0 also records n_{k-2} and, on
+// stopping, the final status.  Visible to the block after its next barrier.
+__device__ __forceinline__ void stop_decision(const IterArgs& a, IterShared& S, uint32_t p_done,
+                                              uint32_t p_cnt, uint32_t p_tot) {
+    const uint32_t tid = threadIdx.x, k = a.k;
+    if (tid >= 64) return;
+    uint32_t ex = p_done;
+    // batched runs: the per-graph stop launch before this one sets done
+    if (!ex && k >= 2 && !a.bc.gid && !a.hash_only) {
+        const uint32_t lv = k - 2;
+        const uint32_t c = wave_sum_u32(p_cnt);
+        const uint32_t nl = lv == 0 ? c : p_tot + c;
+        if (tid == 0) {
+            if (blockIdx.x == 0) a.totals[lv] = nl;
+            const uint32_t fix = (lv >= 1 && c == 0) ? 1u : 0u;
+            if ((a.stop && fix) || lv >= a.k_max) {
+                ex = 1;
+                if (blockIdx.x == 0) {
+                    a.status->k_done = lv;
+                    a.status->fixpoint = fix;
+                    a.status->done = 1;
+                }
+            }
+        }
+    }
+    if (tid == 0) S.ctl[0] = ex;
+}
+
+// A tile block.  Its latency is a chain of dependent memory round trips, so
+// every load is issued before the first barrier: tile bounds -> offsets and
+// per-vertex state -> edge targets / labels and the representative's hash
+// -> neighbour hashes.  Nothing is written before the stop decision.
+// Returns false when the run is done.
 template <typename LabT>
-__device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool test, bool hash) {
-    const uint32_t tid = threadIdx.x;
+__device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint32_t p_done, uint32_t p_cnt,
+                           uint32_t p_tot) {
+    const uint32_t tid = threadIdx.x, k = a.k;
+    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
+    const bool hash = k <= a.k_max;
     const uint32_t v0 = a.tile_v0[tile], v1 = a.tile_v1[tile];
     const uint32_t nv = v1 - v0;
     const uint32_t v = v0 + tid;
     const bool mine = tid < nv;
-    // issue every per-vertex load that depends only on the tile range at once
     const uint32_t ebase = a.row_off[v0];
-    uint32_t ro0 = 0, ro1 = 0, rv = v;
+    const uint32_t ne = a.row_off[v1] - ebase;
+    uint32_t ro0 = 0, ro1 = 0, rv = v, gi = 0;
     uint64_t hv_own = 0, tv = 0;
     bool live = false;
     // batched runs: a graph that stopped at level L keeps its level-L state
     bool act_test = true, act_hash = true;
-    uint32_t gi = 0;
     if (tid <= nv) ro0 = a.row_off[v];
     if (tid + kBlock <= nv) ro1 = a.row_off[v + kBlock];
     if (mine) {
@@ -208,8 +244,8 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
         if (a.bc.gid) {
             gi = a.bc.gid[v];
             const uint32_t dl = a.bc.done_level[gi];
-            act_test = a.k - 1 <= dl;
-            act_hash = a.k <= dl;
+            act_test = k - 1 <= dl;
+            act_hash = k <= dl;
         }
         if (test) {
             rv = a.rep[v];
@@ -217,43 +253,50 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
         }
         if (hash) tv = a.t[v];
     }
-    if (test) {
-        // split test of level k-1: leave the class of rep[v] if h^{k-1} differs
-        uint32_t founded = 0, slot = 0xFFFFFFFFu;
-        if (mine && live && act_test && rv != v && hv_own != a.h_prev[rv]) {
-            a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, rv, hv_own, v, &founded, &slot, a.status));
-            if (a.bc.gid && founded)
-                atomicAdd(&a.bc.hist[static_cast<size_t>(a.k - 1) * a.bc.n_graphs + gi], 1u);
-        }
-        record_founders(a.test_tab, a.lcnt, a.k - 1, founded, slot, S.red, &S.ctl[1]);
-    }
-    if (!hash) return;
-    if (tid <= nv) S.off[tid] = ro0 - ebase;
-    if (tid + kBlock <= nv) S.off[tid + kBlock] = ro1 - ebase;
-    if (mine) S.acc[tid] = 0;
-    __syncthreads();
-    const uint32_t ne = S.off[nv];
-    for (uint32_t j = tid; j < 2 * ne; j += kBlock) S.tab[j] = 0;
-    tile_segments(nv, S.off, S.seg, S.red);
-
     const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
-    // stage all loads first so the gathers of one thread are in flight together
     uint32_t w[kEdgesPerThread];
     uint32_t l[kEdgesPerThread];
-#pragma unroll
-    for (int r = 0; r < kEdgesPerThread; r++) {
-        const uint32_t j = tid + r * kBlock;
-        if (j < ne) {
-            w[r] = a.tgt[ebase + j];
-            l[r] = static_cast<uint32_t>(lab[ebase + j]);
-        }
-    }
     uint64_t hv[kEdgesPerThread];
 #pragma unroll
     for (int r = 0; r < kEdgesPerThread; r++) {
         const uint32_t j = tid + r * kBlock;
-        if (j < ne) hv[r] = a.h_prev[w[r]] ^ a.salt[l[r]];
+        w[r] = 0;
+        l[r] = 0;
+        if (hash && j < ne) {
+            w[r] = a.tgt[ebase + j];
+            l[r] = static_cast<uint32_t>(lab[ebase + j]);
+        }
     }
+    // split test of level k-1: the representative's hash
+    const bool probe = test && mine && live && act_test && rv != v;
+    uint64_t hv_rep = 0;
+    if (probe) hv_rep = a.h_prev[rv];
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        hv[r] = (hash && j < ne) ? a.h_prev[w[r]] ^ a.salt[l[r]] : 0;
+    }
+    stop_decision(a, S, p_done, p_cnt, p_tot);
+    if (hash) {
+        if (tid <= nv) S.off[tid] = ro0 - ebase;
+        if (tid + kBlock <= nv) S.off[tid + kBlock] = ro1 - ebase;
+        if (mine) S.acc[tid] = 0;
+    }
+    __syncthreads();
+    if (S.ctl[0]) return false;
+    if (test) {
+        // leave the class of rep[v] if h^{k-1} differs
+        uint32_t founded = 0, slot = 0xFFFFFFFFu;
+        if (probe && hv_own != hv_rep) {
+            a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, rv, hv_own, v, &founded, &slot, a.status));
+            if (a.bc.gid && founded)
+                atomicAdd(&a.bc.hist[static_cast<size_t>(k - 1) * a.bc.n_graphs + gi], 1u);
+        }
+        record_founders(a.test_tab, a.lcnt, k - 1, founded, slot, S.red, &S.ctl[1]);
+    }
+    if (!hash) return true;
+    for (uint32_t j = tid; j < 2 * ne; j += kBlock) S.tab[j] = 0;
+    tile_segments(nv, S.off, S.seg, S.red);
 #pragma unroll
     for (int r = 0; r < kEdgesPerThread; r++) {
         const uint32_t j = tid + r * kBlock;
@@ -273,44 +316,55 @@ __device__ void tile_block(const IterArgs& a, uint32_t tile, IterShared& S, bool
     }
     __syncthreads();
     if (mine && act_hash) a.h_next[v] = live ? mix64(tv ^ mix64(kCS + S.acc[tid])) : 0;
+    return true;
 }
 
+// A hub chunk block: kTileMaxEdges edges of one hub.  Loads first, as in
+// tile_block; the hub's first chunk block owns the hub vertex's split test.
 template <typename LabT>
-__device__ void hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, bool test, bool hash) {
-    const uint32_t tid = threadIdx.x;
+__device__ bool hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32_t p_done, uint32_t p_cnt,
+                                uint32_t p_tot) {
+    const uint32_t tid = threadIdx.x, k = a.k;
+    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
+    const bool hash = k <= a.k_max;
     const uint32_t hi = a.hc_hub[blk];
     const uint32_t e0 = a.hc_e0[blk];
     const uint32_t v = a.hub_v[hi];
+    const uint32_t logb = a.hub_logb[hi];
+    const uint64_t koff = a.hub_key_off[hi];
     const uint32_t vbeg = a.row_off[v], vend = a.row_off[v + 1];
-    if (test) {
-        // the hub's first chunk block owns the hub vertex's split test
-        uint32_t founded = 0, slot = 0xFFFFFFFFu;
-        if (tid == 0 && e0 == vbeg) split_test(a, v, &founded, &slot);
-        record_founders(a.test_tab, a.lcnt, a.k - 1, founded, slot, S.red, &S.ctl[1]);
-    }
-    if (!hash) return;
     const uint32_t ne = min(static_cast<uint32_t>(kTileMaxEdges), vend - e0);
-    uint64_t* __restrict__ out = a.hub_keys + a.hub_key_off[hi] + (e0 - vbeg);
     const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
     uint32_t w[kEdgesPerThread];
     uint32_t l[kEdgesPerThread];
-#pragma unroll
-    for (int r = 0; r < kEdgesPerThread; r++) {
-        const uint32_t j = tid + r * kBlock;
-        if (j < ne) {
-            w[r] = a.tgt[e0 + j];
-            l[r] = static_cast<uint32_t>(lab[e0 + j]);
-        }
-    }
     uint64_t hv[kEdgesPerThread];
 #pragma unroll
     for (int r = 0; r < kEdgesPerThread; r++) {
         const uint32_t j = tid + r * kBlock;
-        if (j < ne) hv[r] = a.h_prev[w[r]] ^ a.salt[l[r]];
+        w[r] = 0;
+        l[r] = 0;
+        if (hash && j < ne) {
+            w[r] = a.tgt[e0 + j];
+            l[r] = static_cast<uint32_t>(lab[e0 + j]);
+        }
     }
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        hv[r] = (hash && j < ne) ? a.h_prev[w[r]] ^ a.salt[l[r]] : 0;
+    }
+    stop_decision(a, S, p_done, p_cnt, p_tot);
+    __syncthreads();
+    if (S.ctl[0]) return false;
+    if (test) {
+        uint32_t founded = 0, slot = 0xFFFFFFFFu;
+        if (tid == 0 && e0 == vbeg) split_test(a, v, &founded, &slot);
+        record_founders(a.test_tab, a.lcnt, k - 1, founded, slot, S.red, &S.ctl[1]);
+    }
+    if (!hash) return true;
+    uint64_t* __restrict__ out = a.hub_keys + koff + (e0 - vbeg);
     // group the chunk's nonzero keys by hash bucket (top logb bits) so each
     // hub-bucket block reads only its own keys; order within a bucket is free
-    const uint32_t logb = a.hub_logb[hi];
     const uint32_t nb = 1u << logb;
     uint32_t* hist = reinterpret_cast<uint32_t*>(S.tab);
     for (uint32_t b = tid; b <= nb; b += kBlock) hist[b] = 0;
@@ -347,6 +401,51 @@ __device__ void hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, 
             out[hist[b] + rank[r]] = f[r];
         }
     }
+    return true;
+}
+
+// A block with no tile (an empty graph still needs its stop test).
+__device__ bool null_block(const IterArgs& a, IterShared& S, uint32_t p_done, uint32_t p_cnt, uint32_t p_tot) {
+    stop_decision(a, S, p_done, p_cnt, p_tot);
+    __syncthreads();
+    return S.ctl[0] == 0;
+}
+
+// Recycling, after the block's own work: counters of level k-3 and the
+// split table that level k-2 filled (launch k+1 tests level k in it).
+__device__ void recycle(const IterArgs& a) {
+    const uint32_t tid = threadIdx.x, k = a.k;
+    if (blockIdx.x == 0 && tid < kStripes && k >= 3)
+        a.lcnt[((k - 3) & (kStripeRing - 1)) * kStripes + tid] = 0;
+    if (k < 2) return;
+    const uint32_t* cnt = a.lcnt + ((k - 2) & (kStripeRing - 1)) * kStripes;
+    bool overflow = false;
+    for (int st = 0; st < kStripes; st++) overflow |= cnt[st] > static_cast<uint32_t>(kListPerStripe);
+    if (blockIdx.x == 0 && tid < kZeroSlots) a.clr_tab.zero[tid] = 0;
+    if (overflow) {
+        const uint64_t cap = static_cast<uint64_t>(a.clr_tab.mask) + 1;
+        const uint64_t per = (cap + gridDim.x - 1) / gridDim.x;
+        const uint64_t lo = per * blockIdx.x, hi = min(cap, lo + per);
+        for (uint64_t j = lo + tid; j < hi; j += kBlock) {
+            a.clr_tab.slots[j].key = 0;
+            a.clr_tab.slots[j].owner = 0;
+        }
+    } else {
+        const uint64_t items = static_cast<uint64_t>(kStripes) * kListPerStripe;
+        for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + tid; i < items;
+             i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+            const uint32_t st = static_cast<uint32_t>(i / kListPerStripe);
+            const uint32_t e = static_cast<uint32_t>(i % kListPerStripe);
+            if (e < cnt[st]) {
+                const uint32_t idx = a.clr_tab.list[i];
+                if (idx <= a.clr_tab.mask) {
+                    SplitSlot* p = &a.clr_tab.slots[idx];
+                    p->key = 0;
+                    p->owner = 0;
+                }
+            }
+        }
+    }
 }
 
 template <typename LabT>
@@ -354,72 +453,24 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
     __shared__ IterShared S;
     const uint32_t tid = threadIdx.x;
     const uint32_t k = a.k;
-    // ---- phase 0: stop test on level k-2
+    // stop-test inputs (level k-2), loaded together with everything else
+    uint32_t p_done = 0, p_cnt = 0, p_tot = 0;
     if (tid < 64) {
-        uint32_t ex = *reinterpret_cast<volatile uint32_t*>(&a.status->done);
-        // batched runs: the per-graph stop launch before this one sets done
-        if (!ex && k >= 2 && !a.bc.gid) {
+        p_done = *reinterpret_cast<volatile uint32_t*>(&a.status->done);
+        if (k >= 2 && !a.bc.gid && !a.hash_only) {
             const uint32_t lv = k - 2;
-            const uint32_t c = wave_sum_u32(a.lcnt[(lv & (kStripeRing - 1)) * kStripes + tid]);
-            const uint32_t nl = lv == 0 ? c : a.totals[lv - 1] + c;
-            if (tid == 0) {
-                if (blockIdx.x == 0) a.totals[lv] = nl;
-                const uint32_t fix = (lv >= 1 && c == 0) ? 1u : 0u;
-                if ((a.stop && fix) || lv >= a.k_max) {
-                    ex = 1;
-                    if (blockIdx.x == 0) {
-                        a.status->k_done = lv;
-                        a.status->fixpoint = fix;
-                        a.status->done = 1;
-                    }
-                }
-            }
-        }
-        if (tid == 0) S.ctl[0] = ex;
-    }
-    __syncthreads();
-    if (S.ctl[0]) return;
-
-    // ---- recycling: counters of level k-3, split table of level k-2
-    if (blockIdx.x == 0 && tid < kStripes && k >= 3)
-        a.lcnt[((k - 3) & (kStripeRing - 1)) * kStripes + tid] = 0;
-    if (k >= 2) {
-        const uint32_t* cnt = a.lcnt + ((k - 2) & (kStripeRing - 1)) * kStripes;
-        bool overflow = false;
-        for (int st = 0; st < kStripes; st++) overflow |= cnt[st] > static_cast<uint32_t>(kListPerStripe);
-        if (blockIdx.x == 0 && tid < kZeroSlots) a.clr_tab.zero[tid] = 0;
-        if (overflow) {
-            const uint64_t cap = static_cast<uint64_t>(a.clr_tab.mask) + 1;
-            const uint64_t per = (cap + gridDim.x - 1) / gridDim.x;
-            const uint64_t lo = per * blockIdx.x, hi = min(cap, lo + per);
-            for (uint64_t j = lo + tid; j < hi; j += kBlock) {
-                a.clr_tab.slots[j].key = 0;
-                a.clr_tab.slots[j].owner = 0;
-            }
-        } else {
-            const uint64_t items = static_cast<uint64_t>(kStripes) * kListPerStripe;
-            for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + tid; i < items;
-                 i += static_cast<uint64_t>(gridDim.x) * kBlock) {
-                const uint32_t st = static_cast<uint32_t>(i / kListPerStripe);
-                const uint32_t e = static_cast<uint32_t>(i % kListPerStripe);
-                if (e < cnt[st]) {
-                    const uint32_t idx = a.clr_tab.list[i];
-                    if (idx <= a.clr_tab.mask) {
-                        SplitSlot* p = &a.clr_tab.slots[idx];
-                        p->key = 0;
-                        p->owner = 0;
-                    }
-                }
-            }
+            p_cnt = a.lcnt[(lv & (kStripeRing - 1)) * kStripes + tid];
+            p_tot = lv ? a.totals[lv - 1] : 0u;
         }
     }
-
-    const bool test = k >= 2 && k - 1 <= a.k_max;
-    const bool hash = k <= a.k_max;
+    bool go;
     if (blockIdx.x < a.n_hub_chunks)
-        hub_chunk_block<LabT>(a, blockIdx.x, S, test, hash);
+        go = hub_chunk_block<LabT>(a, blockIdx.x, S, p_done, p_cnt, p_tot);
     else if (blockIdx.x - a.n_hub_chunks < a.n_tiles)
-        tile_block<LabT>(a, blockIdx.x - a.n_hub_chunks, S, test, hash);
+        go = tile_block<LabT>(a, blockIdx.x - a.n_hub_chunks, S, p_done, p_cnt, p_tot);
+    else
+        go = null_block(a, S, p_done, p_cnt, p_tot);
+    if (go && !a.hash_only) recycle(a);
 }
 
 // ------------------------------------------------------------ hub buckets
@@ -684,7 +735,7 @@ void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_
 
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
                       bool stop, hipStream_t s) {
-    IterArgs a;
+    IterArgs a{};
     a.row_off = g.row_off;
     a.tgt = g.tgt;
     a.lab = g.lab;
@@ -724,7 +775,7 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
 
 void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s) {
     if (g.n_hub_blocks == 0) return;
-    HubArgs a;
+    HubArgs a{};
     a.t = rb.t;
     a.hub_keys = rb.hub_keys;
     a.hub_key_off = g.hub_key_off;
@@ -747,6 +798,74 @@ void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t 
     a.bc = rb.bc;
     k_hub<<<g.n_hub_blocks, kHubBlock, static_cast<size_t>(g.hub_table_slots) * 8, s>>>(a);
     hip_check(hipGetLastError(), "hub launch");
+}
+
+void alloc_hash_scratch(const Staged& g, HashScratch& hs, Arena& arena, hipStream_t s) {
+    hs.hub_keys = arena.alloc<uint64_t>(g.hub_keys_total + 1);
+    hs.hub_boff = arena.alloc<uint32_t>((static_cast<size_t>(g.n_hub_chunks) + 1) * kHubOffStride);
+    hs.hub_acc = arena.alloc<uint64_t>(g.n_hubs + 1);
+    hs.hub_done = arena.alloc<uint32_t>(g.n_hubs + 1);
+    hs.status = arena.alloc<RunStatus>(1);
+    hip_check(hipMemsetAsync(hs.hub_acc, 0, (g.n_hubs + 1) * 8ull, s), "hub acc");
+    hip_check(hipMemsetAsync(hs.hub_done, 0, (g.n_hubs + 1) * 4ull, s), "hub done");
+    hip_check(hipMemsetAsync(hs.status, 0, sizeof(RunStatus), s), "status");
+}
+
+void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_prev, uint64_t* h_next,
+                       const HashScratch& hs, uint32_t level, hipStream_t s) {
+    IterArgs a{};
+    a.row_off = g.row_off;
+    a.tgt = g.tgt;
+    a.lab = g.lab;
+    a.t = t;
+    a.salt = g.salt;
+    a.h_prev = h_prev;
+    a.h_next = h_next;
+    a.alive = g.alive;
+    a.tile_v0 = g.tile_v0;
+    a.tile_v1 = g.tile_v1;
+    a.hc_hub = g.hc_hub;
+    a.hc_e0 = g.hc_e0;
+    a.hub_v = g.hub_v;
+    a.hub_logb = g.hub_logb;
+    a.hub_key_off = g.hub_key_off;
+    a.hub_keys = hs.hub_keys;
+    a.hub_boff = hs.hub_boff;
+    a.status = hs.status;
+    a.n_tiles = g.n_tiles;
+    a.n_hub_chunks = g.n_hub_chunks;
+    a.k = level;
+    a.k_max = 0xFFFFFFFFu;
+    a.hash_only = 1;
+    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_tiles, 1);
+    if (g.label_bytes == 2)
+        k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
+    else
+        k_iterate<uint32_t><<<grid, kBlock, 0, s>>>(a);
+    hip_check(hipGetLastError(), "hash level launch");
+    if (g.n_hub_blocks == 0) return;
+    HubArgs h{};
+    h.t = t;
+    h.hub_keys = hs.hub_keys;
+    h.hub_key_off = g.hub_key_off;
+    h.hub_boff = hs.hub_boff;
+    h.hub_chunk0 = g.hub_chunk0;
+    h.hub_nchunks = g.hub_nchunks;
+    h.hc_e0 = g.hc_e0;
+    h.hub_v = g.hub_v;
+    h.hub_deg = g.hub_deg;
+    h.hub_logb = g.hub_logb;
+    h.hb_hub = g.hb_hub;
+    h.hb_bucket = g.hb_bucket;
+    h.hub_acc = hs.hub_acc;
+    h.hub_done = hs.hub_done;
+    h.h_next = h_next;
+    h.status = hs.status;
+    h.table_slots = g.hub_table_slots;
+    h.table_limit = (g.hub_table_slots / 8) * 7;
+    h.k = level;
+    k_hub<<<g.n_hub_blocks, kHubBlock, static_cast<size_t>(g.hub_table_slots) * 8, s>>>(h);
+    hip_check(hipGetLastError(), "hash level hub launch");
 }
 
 void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool stop, hipStream_t s) {

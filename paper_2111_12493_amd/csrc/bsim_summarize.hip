@@ -93,7 +93,8 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming), "event");
     bool done = false;
-    std::vector<hipEvent_t> timers;  // (start, after refinement, after hubs) per launch
+    std::vector<hipEvent_t> timers;  // (start, after refinement, after hubs) per timed launch
+    std::vector<uint32_t> timed_k;   // the launches timed
     struct TimerGuard {
         std::vector<hipEvent_t>& t;
         ~TimerGuard() {
@@ -126,7 +127,9 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                         rb.h[kk & 1] = sink->levels[std::min(kk, top)];
                     }
                     hipEvent_t et[3] = {nullptr, nullptr, nullptr};
-                    if (ctx->time_launches) {
+                    const bool timed = ctx->time_launches && kk % ctx->time_launches == 0;
+                    if (timed) {
+                        timed_k.push_back(kk);
                         for (hipEvent_t& e : et) {
                             hip_check(hipEventCreate(&e), "event");
                             timers.push_back(e);
@@ -135,9 +138,9 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                     }
                     if (rb.bc.gid) launch_graph_stop(rb, kk, p.k_max, stop, s);
                     launch_iteration(g, rb, kk, p.k_max, stop, s);
-                    if (ctx->time_launches) hip_check(hipEventRecord(et[1], s), "event");
+                    if (timed) hip_check(hipEventRecord(et[1], s), "event");
                     if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
-                    if (ctx->time_launches) hip_check(hipEventRecord(et[2], s), "event");
+                    if (timed) hip_check(hipEventRecord(et[2], s), "event");
                     lr.launches++;
                 }
                 const int slot = pending < 0 ? 0 : (pending ^ 1);
@@ -169,12 +172,14 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
     // launch j (1-based) did work iff j <= k_done + 1: launch k_done + 2 finds
     // the stop at level k_done and returns at once, as do all later ones
-    for (size_t i = 0; i + 2 < timers.size() && i / 3 < static_cast<size_t>(st.k_done) + 1; i += 3) {
+    for (size_t i = 0; i + 2 < timers.size(); i += 3) {
+        if (timed_k[i / 3] > st.k_done + 1) break;
         float a = 0.f, b = 0.f;
         hip_check(hipEventElapsedTime(&a, timers[i], timers[i + 1]), "launch timer");
         hip_check(hipEventElapsedTime(&b, timers[i + 1], timers[i + 2]), "launch timer");
         lr.ms_kernels += a;
         lr.ms_hub_kernels += b;
+        lr.n_timed++;
     }
     if (st.error & kErrZeroHash)
         throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
@@ -214,6 +219,7 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
     r->n_iter_launches = lr.launches;
     r->ms_iter_kernels = lr.ms_kernels;
     r->ms_hub_kernels = lr.ms_hub_kernels;
+    r->n_timed_launches = lr.n_timed;
     r->blocks_per_iter = p->blocks_per_iter.data();
     uint64_t* hashes = keep.alloc<uint64_t>(g.n);
     if (g.n) hip_check(hipMemcpyAsync(hashes, h, static_cast<size_t>(g.n) * 8, hipMemcpyDeviceToDevice, s),

@@ -505,3 +505,86 @@ def ops_as_tuples(d: dict) -> List[tuple]:
         else:
             out.append(("del_e", u, l, w))
     return out
+
+
+def sample_update_ops(row_off: np.ndarray, tgt: np.ndarray, lab: np.ndarray, n: int, dead: np.ndarray,
+                      rng: np.random.Generator, n_ops: int, n_labels: int, n_types: int,
+                      mix=(0.60, 0.25, 0.15), vertex_frac: float = 0.10,
+                      rmat_scale: Optional[int] = None, max_types: int = 4) -> dict:
+    """A valid update batch for a large resident graph, built by sampling.
+
+    Same operation mix as `update_ops`, but DEL_E / MOD_E sample edges of the
+    given CSR (the graph the state started from; an edge already deleted by
+    an earlier batch makes a valid no-op delete) and only vertices with
+    dead[v] == False are used.  `dead` has at least n entries and is updated
+    in place with the vertices this batch deletes; new vertices take ids
+    n, n+1, ...  Returns the arrays of `update_ops` plus "n_after".
+    """
+    m = int(tgt.size)
+    cls = rng.choice(3, size=n_ops, p=np.asarray(mix) / sum(mix))
+    is_v = rng.random(n_ops) < vertex_frac
+    op = np.where(is_v, cls + 1, cls + 4).astype(np.uint32)
+    u = np.zeros(n_ops, dtype=np.uint32)
+    w = np.zeros(n_ops, dtype=np.uint32)
+    lb = np.zeros(n_ops, dtype=np.uint32)
+    nl = np.zeros(n_ops, dtype=np.uint32)
+
+    def alive_vertices(k):
+        out = []
+        need = k
+        while need > 0:
+            c = rng.integers(0, n, size=2 * need + 8)
+            c = c[~dead[c]]
+            out.append(c[:need])
+            need -= len(out[-1])
+        return np.concatenate(out)[:k] if k else np.zeros(0, dtype=np.int64)
+
+    # vertices deleted by this batch: distinct, alive, and untouched by the rest
+    dv = op == 3
+    victims = np.unique(alive_vertices(int(dv.sum())))
+    op[np.flatnonzero(dv)[victims.size:]] = 2
+    u[np.flatnonzero(op == 3)] = victims
+    dead[victims] = True
+    mv = op == 2
+    u[mv] = alive_vertices(int(mv.sum()))
+    de = (op == 5) | (op == 6)
+    k = int(de.sum())
+    if k:
+        su, sw, sl = [], [], []
+        need = k
+        while need > 0:
+            e = rng.integers(0, m, size=2 * need + 8)
+            s_ = np.searchsorted(row_off, e, side="right") - 1
+            ok = ~dead[s_] & ~dead[tgt[e]]
+            su.append(s_[ok][:need])
+            sw.append(tgt[e][ok][:need])
+            sl.append(lab[e][ok][:need])
+            need -= len(su[-1])
+        u[de], w[de], lb[de] = np.concatenate(su)[:k], np.concatenate(sw)[:k], np.concatenate(sl)[:k]
+    nl[op == 5] = rng.integers(0, n_labels, size=int(np.sum(op == 5)))
+    ae = op == 4
+    k = int(ae.sum())
+    if k:
+        if rmat_scale is not None:
+            su, sw = [], []
+            need = k
+            while need > 0:
+                s_, d_ = rmat_edges(rng, rmat_scale, 2 * need + 16, 0.57, 0.19, 0.19)
+                ok = (s_ < n) & (d_ < n)
+                s_, d_ = s_[ok], d_[ok]
+                ok = ~dead[s_] & ~dead[d_]
+                su.append(s_[ok][:need])
+                sw.append(d_[ok][:need])
+                need -= len(su[-1])
+            u[ae], w[ae] = np.concatenate(su)[:k], np.concatenate(sw)[:k]
+        else:
+            u[ae], w[ae] = alive_vertices(k), alive_vertices(k)
+        lb[ae] = zipf_sample(rng, n_labels, 1.1, k)
+    tv = (op == 1) | (op == 2)
+    cnt = np.zeros(n_ops, dtype=np.int64)
+    cnt[tv] = rng.integers(0, max_types + 1, size=int(tv.sum()))
+    t_off = np.zeros(n_ops + 1, dtype=np.int64)
+    np.cumsum(cnt, out=t_off[1:])
+    t_ids = rng.integers(0, n_types, size=int(t_off[-1])).astype(np.uint32)
+    return dict(op=op, u=u, w=w, label=lb, new_label=nl, t_off=t_off, t_ids=t_ids,
+                n_after=n + int(np.sum(op == 1)))

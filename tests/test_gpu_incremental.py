@@ -99,17 +99,49 @@ def test_each_operation_kind():
         s.close()
 
 
+class FrontierLimit:
+    """Set the ctx option frontier_limit_pct for the duration of a test:
+    100 keeps every level on the frontier kernels, 0 recomputes every level
+    for all vertices (the plain form), values between switch mid-batch."""
+
+    def __init__(self, pct):
+        self.pct = pct
+
+    def __enter__(self):
+        self.old = ctx().get_option("frontier_limit_pct")
+        ctx().set_option("frontier_limit_pct", self.pct)
+
+    def __exit__(self, *exc):
+        ctx().set_option("frontier_limit_pct", self.old)
+
+
+@pytest.mark.parametrize("pct", [100, 10, 0])
 @pytest.mark.parametrize("label_u16", [False, True])
-def test_random_batch_sequences(label_u16):
+def test_random_batch_sequences(label_u16, pct):
     rng = np.random.default_rng(23)
     g = gg.uniform_graph(2000, 10000, 8, 16, seed=5)
     if label_u16:
         g = gg.with_u16_labels(g)
-    s = Session(g, 4)
-    for i, size in enumerate([1, 3, 10, 30, 100, 300, 1000, 1, 3000]):
-        d = gg.update_ops(s.g, rng, size, n_labels=16, n_types=8)
-        s.apply(gg.ops_as_tuples(d), what=("batch", i, size))
-    s.close()
+    with FrontierLimit(pct):
+        s = Session(g, 4)
+        for i, size in enumerate([1, 3, 10, 30, 100, 300, 1000, 1, 3000]):
+            d = gg.update_ops(s.g, rng, size, n_labels=16, n_types=8)
+            s.apply(gg.ops_as_tuples(d), what=("batch", i, size, pct))
+        s.close()
+
+
+def test_rmat_updates_switch_to_full_levels():
+    # R-MAT hubs spread a change to most vertices within a few levels: the
+    # frontier limit then hands the remaining levels to the full kernels
+    rng = np.random.default_rng(71)
+    g = gg.rmat_graph(13, 1 << 16, n_types=16, n_labels=8, seed=12)
+    for pct in (2, 30):
+        with FrontierLimit(pct):
+            s = Session(g, 4)
+            for i in range(4):
+                d = gg.update_ops(s.g, rng, int(rng.integers(5, 500)), n_labels=8, n_types=16, rmat_scale=13)
+                s.apply(gg.ops_as_tuples(d), what=("rmat", pct, i))
+            s.close()
 
 
 def test_untyped_and_fixpoint_stop():
@@ -128,7 +160,8 @@ def test_untyped_and_fixpoint_stop():
     s.close()
 
 
-def test_frontier_through_large_vertices():
+@pytest.mark.parametrize("pct", [100, 0])
+def test_frontier_through_large_vertices(pct):
     # vertices of degree above the wave limit take the chunked global-table path
     rng = np.random.default_rng(31)
     n = 3000
@@ -140,14 +173,15 @@ def test_frontier_through_large_vertices():
     lab.append(rng.integers(0, 6, size=12000))
     g = gg.from_edges(n, np.concatenate(src), np.concatenate(dst), np.concatenate(lab),
                       types=[[int(x)] for x in rng.integers(0, 3, n)], n_labels=6)
-    s = Session(g, 3)
-    # touch the targets of the large vertices so they re-hash at level 2
-    for i in range(4):
-        d = gg.update_ops(s.g, rng, 200, n_labels=6, n_types=3)
-        s.apply(gg.ops_as_tuples(d), what=("large", i))
-    s.apply([("add_e", 1, 5, 7), ("del_e", 2, int(s.g.lab[s.g.row_off[2]]), int(s.g.tgt[s.g.row_off[2]]))],
-            what="large rows")
-    s.close()
+    with FrontierLimit(pct):
+        s = Session(g, 3)
+        # touch the targets of the large vertices so they re-hash at level 2
+        for i in range(4):
+            d = gg.update_ops(s.g, rng, 200, n_labels=6, n_types=3)
+            s.apply(gg.ops_as_tuples(d), what=("large", i))
+        s.apply([("add_e", 1, 5, 7), ("del_e", 2, int(s.g.lab[s.g.row_off[2]]), int(s.g.tgt[s.g.row_off[2]]))],
+                what="large rows")
+        s.close()
 
 
 def test_incremental_equals_gpu_batch_on_state_graph():
