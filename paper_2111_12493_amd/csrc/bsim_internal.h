@@ -53,6 +53,11 @@ constexpr int kTileMaxVerts = 256;
 constexpr int kEdgesPerThread = kTileMaxEdges / kBlock;  // 8
 constexpr int kTableSlots = 2 * kTileMaxEdges;           // 4096 x 8 B = 32 KiB
 constexpr uint32_t kHubMinDegree = kTileMaxEdges;  // a hub would not fit an empty tile
+// A hub of at most kSoloMaxEdges edges is a "solo" block of the refinement
+// launch: one block gathers all its edges and de-duplicates them in the
+// whole LDS table (load <= 3/4); larger hubs take the chunk / bucket path.
+constexpr uint32_t kSoloMaxEdges = 3 * kTableSlots / 4;
+constexpr int kSoloPerThread = kSoloMaxEdges / kBlock;  // 12
 constexpr int kHubBlock = 512;           // threads per hub-bucket block
 constexpr int kMaxHubLogB = 8;           // at most 256 hash buckets per hub
 constexpr uint32_t kHubTableDefault = 4096;  // LDS slots per hub-bucket block (32 KiB)
@@ -135,8 +140,10 @@ struct IterArgs {
     uint32_t* lcnt;         // [kStripeRing][kStripes] claims per level
     uint32_t* totals;       // totals[j] = n_j
     RunStatus* status;
+    const uint32_t* solo_v;     // solo hub vertices
     uint32_t n_tiles;
     uint32_t n_hub_chunks;
+    uint32_t n_solo;
     uint32_t k;
     uint32_t k_max;
     uint32_t stop;
@@ -256,10 +263,11 @@ struct Staged {
     uint32_t n_tiles = 0;
     uint32_t* tile_v0 = nullptr;
     uint32_t* tile_v1 = nullptr;
-    uint32_t n_hubs = 0;
+    uint32_t n_hubs = 0;             // all hubs: n_hubs - n_solo chunked ones, then the solo ones
+    uint32_t n_solo = 0;
     uint32_t n_hub_chunks = 0;
     uint32_t n_hub_blocks = 0;       // hub-bucket blocks of the second launch
-    uint32_t* hub_v = nullptr;       // by degree, descending
+    uint32_t* hub_v = nullptr;       // by degree, descending (solo hubs last)
     uint32_t* hub_deg = nullptr;
     uint32_t* hub_logb = nullptr;
     uint32_t* hub_chunk0 = nullptr;   // first chunk block of the hub

@@ -404,6 +404,69 @@ __device__ bool hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, 
     return true;
 }
 
+// A solo hub block: one hub vertex of at most kSoloMaxEdges edges, all its
+// pair keys de-duplicated in the whole LDS table.
+template <typename LabT>
+__device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_t p_done, uint32_t p_cnt,
+                           uint32_t p_tot) {
+    const uint32_t tid = threadIdx.x, k = a.k;
+    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
+    const bool hash = k <= a.k_max;
+    const uint32_t e0 = a.row_off[v];
+    const uint32_t ne = a.row_off[v + 1] - e0;
+    bool act_hash = true;
+    if (a.bc.gid) act_hash = k <= a.bc.done_level[a.bc.gid[v]];
+    const uint64_t tv = hash ? a.t[v] : 0;
+    const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
+    uint32_t w[kSoloPerThread];
+    uint32_t l[kSoloPerThread];
+    uint64_t hv[kSoloPerThread];
+#pragma unroll
+    for (int r = 0; r < kSoloPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        w[r] = 0;
+        l[r] = 0;
+        if (hash && j < ne) {
+            w[r] = a.tgt[e0 + j];
+            l[r] = static_cast<uint32_t>(lab[e0 + j]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kSoloPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        hv[r] = (hash && j < ne) ? a.h_prev[w[r]] ^ a.salt[l[r]] : 0;
+    }
+    stop_decision(a, S, p_done, p_cnt, p_tot);
+    for (uint32_t j = tid; j < kTableSlots; j += kBlock) S.tab[j] = 0;
+    __syncthreads();
+    if (S.ctl[0]) return false;
+    if (test) {
+        uint32_t founded = 0, slot = 0xFFFFFFFFu;
+        if (tid == 0) split_test(a, v, &founded, &slot);
+        record_founders(a.test_tab, a.lcnt, k - 1, founded, slot, S.red, &S.ctl[1]);
+    }
+    if (!hash) return true;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kSoloPerThread; r++) {
+        const uint32_t j = tid + r * kBlock;
+        if (j < ne) {
+            const uint64_t f = mix64(hv[r] ^ kCE);
+            if (f != 0 && lds_insert(S.tab, static_cast<uint32_t>(f) & (kTableSlots - 1), 0, kTableSlots, f))
+                acc += f;
+        }
+    }
+    acc = wave_sum_u64(acc);
+    if (lane_id() == 0) S.acc[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0 && act_hash) {
+        uint64_t sum = 0;
+        for (int i = 0; i < kBlock / 64; i++) sum += S.acc[i];
+        a.h_next[v] = mix64(tv ^ mix64(kCS + sum));
+    }
+    return true;
+}
+
 // A block with no tile (an empty graph still needs its stop test).
 __device__ bool null_block(const IterArgs& a, IterShared& S, uint32_t p_done, uint32_t p_cnt, uint32_t p_tot) {
     stop_decision(a, S, p_done, p_cnt, p_tot);
@@ -464,10 +527,13 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
         }
     }
     bool go;
-    if (blockIdx.x < a.n_hub_chunks)
-        go = hub_chunk_block<LabT>(a, blockIdx.x, S, p_done, p_cnt, p_tot);
-    else if (blockIdx.x - a.n_hub_chunks < a.n_tiles)
-        go = tile_block<LabT>(a, blockIdx.x - a.n_hub_chunks, S, p_done, p_cnt, p_tot);
+    const uint32_t b = blockIdx.x;
+    if (b < a.n_hub_chunks)
+        go = hub_chunk_block<LabT>(a, b, S, p_done, p_cnt, p_tot);
+    else if (b - a.n_hub_chunks < a.n_solo)
+        go = solo_block<LabT>(a, a.solo_v[b - a.n_hub_chunks], S, p_done, p_cnt, p_tot);
+    else if (b - a.n_hub_chunks - a.n_solo < a.n_tiles)
+        go = tile_block<LabT>(a, b - a.n_hub_chunks - a.n_solo, S, p_done, p_cnt, p_tot);
     else
         go = null_block(a, S, p_done, p_cnt, p_tot);
     if (go && !a.hash_only) recycle(a);
@@ -761,11 +827,13 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.status = rb.status;
     a.n_tiles = g.n_tiles;
     a.n_hub_chunks = g.n_hub_chunks;
+    a.n_solo = g.n_solo;
+    a.solo_v = g.hub_v ? g.hub_v + (g.n_hubs - g.n_solo) : nullptr;
     a.k = k;
     a.k_max = k_max;
     a.stop = stop ? 1u : 0u;
     a.bc = rb.bc;
-    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_tiles, 1);
+    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_solo + g.n_tiles, 1);
     if (g.label_bytes == 2)
         k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
     else
@@ -834,10 +902,12 @@ void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_pre
     a.status = hs.status;
     a.n_tiles = g.n_tiles;
     a.n_hub_chunks = g.n_hub_chunks;
+    a.n_solo = g.n_solo;
+    a.solo_v = g.hub_v ? g.hub_v + (g.n_hubs - g.n_solo) : nullptr;
     a.k = level;
     a.k_max = 0xFFFFFFFFu;
     a.hash_only = 1;
-    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_tiles, 1);
+    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_solo + g.n_tiles, 1);
     if (g.label_bytes == 2)
         k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
     else

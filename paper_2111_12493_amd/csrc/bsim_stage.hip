@@ -358,18 +358,23 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
             return g.host_hub_deg[a] > g.host_hub_deg[b];
         });
-        // a hub of degree d: ceil(d / kTileMaxEdges) chunk blocks, and 2^b
-        // bucket blocks so that a bucket expects at most half the LDS slots
-        const uint64_t per_bucket = std::max<uint64_t>(1, uint64_t(g.hub_table_slots) / 2);
+        // a hub of degree d > kSoloMaxEdges: ceil(d / kTileMaxEdges) chunk
+        // blocks, and 2^b bucket blocks so that a bucket expects at most 3/4
+        // of the LDS slots; the others are solo blocks (no chunks, no buckets)
+        const uint64_t per_bucket = std::max<uint64_t>(1, uint64_t(g.hub_table_slots) * 3 / 4);
         std::vector<uint32_t> hv(g.n_hubs), hd(g.n_hubs), hl(g.n_hubs);
         std::vector<uint64_t> ho(g.n_hubs);
         std::vector<uint32_t> ch, ce, bh, bb;
         std::vector<uint32_t> hstart(g.n_hubs);
         uint64_t keys = 0;
+        uint32_t n_big = 0;
         for (uint32_t i = 0; i < g.n_hubs; i++) {
             hv[i] = g.host_hub_v[order[i]];
             hd[i] = g.host_hub_deg[order[i]];
             ho[i] = keys;
+            hl[i] = 0;
+            if (hd[i] <= kSoloMaxEdges) continue;
+            n_big = i + 1;
             keys += hd[i];
             const uint64_t want = (hd[i] + per_bucket - 1) / per_bucket;
             hl[i] = std::min<uint32_t>(static_cast<uint32_t>(bit_width(next_pow2(want)) - 1), kMaxHubLogB);
@@ -378,6 +383,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
                 bb.push_back(b);
             }
         }
+        g.n_solo = g.n_hubs - n_big;
         uint32_t* hv_dev = arena.alloc<uint32_t>(g.n_hubs);
         uint32_t* hs_dev = arena.alloc<uint32_t>(g.n_hubs);
         hip_check(hipMemcpyAsync(hv_dev, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, s), "hub v");
@@ -387,7 +393,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         std::vector<uint32_t> hc0(g.n_hubs), hnc(g.n_hubs);
         for (uint32_t i = 0; i < g.n_hubs; i++) {
             hc0[i] = static_cast<uint32_t>(ch.size());
-            hnc[i] = ceil_div(hd[i], kTileMaxEdges);
+            hnc[i] = i < n_big ? ceil_div(hd[i], kTileMaxEdges) : 0;
             for (uint32_t c = 0; c < hnc[i]; c++) {
                 ch.push_back(i);
                 ce.push_back(hstart[i] + c * kTileMaxEdges);
@@ -421,6 +427,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
     } else {
         g.n_hub_chunks = 0;
         g.n_hub_blocks = 0;
+        g.n_solo = 0;
         g.hub_keys_total = 0;
     }
 

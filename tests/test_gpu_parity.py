@@ -97,8 +97,9 @@ def _hub_graph(seed, degs, n_extra=3000, n_labels=7, dup_every=5):
 
 
 def test_hub_vertices():
-    # degrees around the tile limit and well above it (several buckets)
-    g = _hub_graph(7, [1023, 1024, 1025, 2046, 2047, 2048, 2049, 3100, 5000, 20000, 70000])
+    # degrees around the tile limit, the solo-hub limit (3072) and well above
+    # it (several buckets)
+    g = _hub_graph(7, [1023, 1024, 1025, 2046, 2047, 2048, 2049, 3071, 3072, 3073, 3100, 5000, 20000, 70000])
     check(g, UNB, what="hubs")
     check(g, 3, stop=False, untyped=True, what="hubs untyped")
 
