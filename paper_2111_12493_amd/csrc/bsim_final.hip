@@ -95,7 +95,9 @@ template <typename LabT>
 __global__ void __launch_bounds__(kBlock) k_edge_keys(
     const uint32_t* __restrict__ row_off, const uint32_t* __restrict__ tgt,
     const LabT* __restrict__ lab, const uint32_t* __restrict__ bid,
-    const uint32_t* __restrict__ tile_v0, const uint32_t* __restrict__ tile_v1, uint32_t n_tiles,
+    const uint32_t* __restrict__ tile_i0, const uint32_t* __restrict__ tile_i1,
+    const uint32_t* __restrict__ tile_e0, const uint32_t* __restrict__ tile_e1,
+    const uint32_t* __restrict__ act, uint32_t n_tiles,
     const uint32_t* __restrict__ hub_v, uint32_t n_hubs, int lb, int bb,
     uint64_t* __restrict__ keys) {
     __shared__ KeyShared S;
@@ -109,15 +111,16 @@ __global__ void __launch_bounds__(kBlock) k_edge_keys(
     }
     const uint32_t tile = blockIdx.x - n_hubs;
     if (tile >= n_tiles) return;
-    const uint32_t v0 = tile_v0[tile], v1 = tile_v1[tile], nv = v1 - v0;
-    const uint32_t ebase = row_off[v0];
-    for (uint32_t i = tid; i <= nv; i += kBlock) S.off[i] = row_off[v0 + i] - ebase;
+    const uint32_t i0 = tile_i0[tile], nv = tile_i1[tile] - i0;
+    const uint32_t ebase = tile_e0[tile];
+    const uint32_t ne = tile_e1[tile] - ebase;
+    for (uint32_t i = tid; i < nv; i += kBlock) S.off[i] = row_off[act[i0 + i]] - ebase;
+    if (tid == 0) S.off[nv] = ne;
     __syncthreads();
-    const uint32_t ne = S.off[nv];
     tile_segments(nv, S.off, S.seg, S.red);
     for (uint32_t j = tid; j < ne; j += kBlock) {
         const uint32_t e = ebase + j;
-        const uint32_t v = v0 + S.seg[j];
+        const uint32_t v = act[i0 + S.seg[j]];
         keys[e] = (static_cast<uint64_t>(bid[v]) << (lb + bb)) |
                   (static_cast<uint64_t>(lab[e]) << bb) | bid[tgt[e]];
     }
@@ -292,12 +295,14 @@ void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& o
     } else if (g.label_bytes == 2)
         k_edge_keys<uint16_t><<<grid, kBlock, 0, s>>>(g.row_off, g.tgt,
                                                       static_cast<const uint16_t*>(g.lab), out.block_ids,
-                                                      g.tile_v0, g.tile_v1, g.n_tiles, g.hub_v, g.n_hubs,
+                                                      g.tile_i0, g.tile_i1, g.tile_e0, g.tile_e1, g.act,
+                                                      g.n_tiles, g.hub_v, g.n_hubs,
                                                       lb, bb, ka);
     else
         k_edge_keys<uint32_t><<<grid, kBlock, 0, s>>>(g.row_off, g.tgt,
                                                       static_cast<const uint32_t*>(g.lab), out.block_ids,
-                                                      g.tile_v0, g.tile_v1, g.n_tiles, g.hub_v, g.n_hubs,
+                                                      g.tile_i0, g.tile_i1, g.tile_e0, g.tile_e1, g.act,
+                                                      g.n_tiles, g.hub_v, g.n_hubs,
                                                       lb, bb, ka);
     hip_check(hipGetLastError(), "edge key launch");
     uint64_t* sorted = radix_sort(ka, kb, m, 2 * bb + lb, arena, s);

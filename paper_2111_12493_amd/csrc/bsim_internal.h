@@ -58,6 +58,12 @@ constexpr uint32_t kHubMinDegree = kTileMaxEdges;  // a hub would not fit an emp
 // whole LDS table (load <= 3/4); larger hubs take the chunk / bucket path.
 constexpr uint32_t kSoloMaxEdges = 3 * kTableSlots / 4;
 constexpr int kSoloPerThread = kSoloMaxEdges / kBlock;  // 12
+// Vertices without out-edges: h^k = M(t ^ M(C_S)) for every k >= 1, so they
+// need no tile.  Light blocks of kIsoPerBlock of them run their split test
+// and write their hash while it can still change the buffers (levels 1 and 2
+// when two buffers alternate; every level when each level has its own array).
+constexpr int kIsoPerThread = 4;
+constexpr uint32_t kIsoPerBlock = kBlock * kIsoPerThread;
 constexpr int kHubBlock = 512;           // threads per hub-bucket block
 constexpr int kMaxHubLogB = 8;           // at most 256 hash buckets per hub
 constexpr uint32_t kHubTableDefault = 4096;  // LDS slots per hub-bucket block (32 KiB)
@@ -126,8 +132,12 @@ struct IterArgs {
     uint64_t* h_next;       // h^k
     const uint8_t* alive;   // nullable
     uint32_t* rep;
-    const uint32_t* tile_v0;
-    const uint32_t* tile_v1;
+    const uint32_t* tile_i0;    // tile = positions [i0, i1) of the tile-vertex list
+    const uint32_t* tile_i1;
+    const uint32_t* tile_e0;    // and its edges [e0, e1)
+    const uint32_t* tile_e1;
+    const uint32_t* act;        // tile vertices (out-degree 1..kHubMinDegree-1), ascending
+    const uint32_t* iso;        // vertices without out-edges, ascending
     const uint32_t* hc_hub;     // hub chunk block -> hub index
     const uint32_t* hc_e0;      // hub chunk block -> first edge
     const uint32_t* hub_v;
@@ -144,6 +154,9 @@ struct IterArgs {
     uint32_t n_tiles;
     uint32_t n_hub_chunks;
     uint32_t n_solo;
+    uint32_t n_iso;
+    uint32_t n_iso_blocks;
+    uint32_t all_levels;    // every level has its own hash array (else two alternate)
     uint32_t k;
     uint32_t k_max;
     uint32_t stop;
@@ -261,8 +274,14 @@ struct Staged {
     uint32_t max_label = 0;
     uint64_t* salt = nullptr;
     uint32_t n_tiles = 0;
-    uint32_t* tile_v0 = nullptr;
-    uint32_t* tile_v1 = nullptr;
+    uint32_t* tile_i0 = nullptr;     // tile: positions [i0, i1) of `act`, edges [e0, e1)
+    uint32_t* tile_i1 = nullptr;
+    uint32_t* tile_e0 = nullptr;
+    uint32_t* tile_e1 = nullptr;
+    uint32_t n_act = 0;
+    uint32_t* act = nullptr;         // vertices of out-degree 1..kHubMinDegree-1
+    uint32_t n_iso = 0;
+    uint32_t* iso = nullptr;         // vertices without out-edges (dead ones included)
     uint32_t n_hubs = 0;             // all hubs: n_hubs - n_solo chunked ones, then the solo ones
     uint32_t n_solo = 0;
     uint32_t n_hub_chunks = 0;
@@ -313,7 +332,7 @@ void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_
 
 // Launch k: stop test, split test of level k-1, h^k (tiles and hub chunks).
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
-                      bool stop, hipStream_t s);
+                      bool stop, bool all_levels, hipStream_t s);
 
 // Hub buckets of iteration k (only when the graph has hubs and k <= k_max).
 void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s);

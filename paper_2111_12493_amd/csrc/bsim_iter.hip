@@ -226,20 +226,18 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
     const uint32_t tid = threadIdx.x, k = a.k;
     const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
     const bool hash = k <= a.k_max;
-    const uint32_t v0 = a.tile_v0[tile], v1 = a.tile_v1[tile];
-    const uint32_t nv = v1 - v0;
-    const uint32_t v = v0 + tid;
+    const uint32_t i0 = a.tile_i0[tile], nv = a.tile_i1[tile] - i0;
+    const uint32_t ebase = a.tile_e0[tile];
+    const uint32_t ne = a.tile_e1[tile] - ebase;
     const bool mine = tid < nv;
-    const uint32_t ebase = a.row_off[v0];
-    const uint32_t ne = a.row_off[v1] - ebase;
-    uint32_t ro0 = 0, ro1 = 0, rv = v, gi = 0;
+    const uint32_t v = mine ? a.act[i0 + tid] : 0u;
+    uint32_t ro0 = 0, rv = v, gi = 0;
     uint64_t hv_own = 0, tv = 0;
     bool live = false;
     // batched runs: a graph that stopped at level L keeps its level-L state
     bool act_test = true, act_hash = true;
-    if (tid <= nv) ro0 = a.row_off[v];
-    if (tid + kBlock <= nv) ro1 = a.row_off[v + kBlock];
     if (mine) {
+        ro0 = a.row_off[v];
         live = !a.alive || a.alive[v];
         if (a.bc.gid) {
             gi = a.bc.gid[v];
@@ -278,9 +276,11 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
     }
     stop_decision(a, S, p_done, p_cnt, p_tot);
     if (hash) {
-        if (tid <= nv) S.off[tid] = ro0 - ebase;
-        if (tid + kBlock <= nv) S.off[tid + kBlock] = ro1 - ebase;
-        if (mine) S.acc[tid] = 0;
+        if (mine) {
+            S.off[tid] = ro0 - ebase;
+            S.acc[tid] = 0;
+        }
+        if (tid == 0) S.off[nv] = ne;
     }
     __syncthreads();
     if (S.ctl[0]) return false;
@@ -467,6 +467,69 @@ __device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_
     return true;
 }
 
+// kIsoPerBlock vertices without out-edges: split test, and h^k = M(t ^
+// M(C_S)) where the hash buffer still needs it.
+__device__ bool iso_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32_t p_done, uint32_t p_cnt,
+                          uint32_t p_tot) {
+    const uint32_t tid = threadIdx.x, k = a.k;
+    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
+    const bool hash = k <= a.k_max && (k <= 2 || a.all_levels);
+    uint32_t v[kIsoPerThread], rv[kIsoPerThread], gi[kIsoPerThread];
+    uint64_t hv_own[kIsoPerThread], hv_rep[kIsoPerThread], tv[kIsoPerThread];
+    bool mine[kIsoPerThread], live[kIsoPerThread], probe[kIsoPerThread], act_hash[kIsoPerThread];
+#pragma unroll
+    for (int r = 0; r < kIsoPerThread; r++) {
+        const uint32_t i = blk * kIsoPerBlock + r * kBlock + tid;
+        mine[r] = i < a.n_iso;
+        v[r] = mine[r] ? a.iso[i] : 0u;
+        rv[r] = v[r];
+        gi[r] = 0;
+        hv_own[r] = tv[r] = hv_rep[r] = 0;
+        live[r] = false;
+        act_hash[r] = true;
+        bool act_test = true;
+        if (mine[r]) {
+            live[r] = !a.alive || a.alive[v[r]];
+            if (a.bc.gid) {
+                gi[r] = a.bc.gid[v[r]];
+                const uint32_t dl = a.bc.done_level[gi[r]];
+                act_test = k - 1 <= dl;
+                act_hash[r] = k <= dl;
+            }
+            if (test) {
+                rv[r] = a.rep[v[r]];
+                hv_own[r] = a.h_prev[v[r]];
+            }
+            if (hash) tv[r] = a.t[v[r]];
+        }
+        probe[r] = test && mine[r] && live[r] && act_test && rv[r] != v[r];
+    }
+#pragma unroll
+    for (int r = 0; r < kIsoPerThread; r++)
+        if (probe[r]) hv_rep[r] = a.h_prev[rv[r]];
+    stop_decision(a, S, p_done, p_cnt, p_tot);
+    __syncthreads();
+    if (S.ctl[0]) return false;
+    if (test) {
+        for (int r = 0; r < kIsoPerThread; r++) {
+            uint32_t founded = 0, slot = 0xFFFFFFFFu;
+            if (probe[r] && hv_own[r] != hv_rep[r]) {
+                a.rep[v[r]] =
+                    static_cast<uint32_t>(split_join(a.test_tab, rv[r], hv_own[r], v[r], &founded, &slot, a.status));
+                if (a.bc.gid && founded)
+                    atomicAdd(&a.bc.hist[static_cast<size_t>(k - 1) * a.bc.n_graphs + gi[r]], 1u);
+            }
+            record_founders(a.test_tab, a.lcnt, k - 1, founded, slot, S.red, &S.ctl[1]);
+        }
+    }
+    if (hash) {
+#pragma unroll
+        for (int r = 0; r < kIsoPerThread; r++)
+            if (mine[r] && act_hash[r]) a.h_next[v[r]] = live[r] ? mix64(tv[r] ^ mix64(kCS)) : 0;
+    }
+    return true;
+}
+
 // A block with no tile (an empty graph still needs its stop test).
 __device__ bool null_block(const IterArgs& a, IterShared& S, uint32_t p_done, uint32_t p_cnt, uint32_t p_tot) {
     stop_decision(a, S, p_done, p_cnt, p_tot);
@@ -532,8 +595,10 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
         go = hub_chunk_block<LabT>(a, b, S, p_done, p_cnt, p_tot);
     else if (b - a.n_hub_chunks < a.n_solo)
         go = solo_block<LabT>(a, a.solo_v[b - a.n_hub_chunks], S, p_done, p_cnt, p_tot);
-    else if (b - a.n_hub_chunks - a.n_solo < a.n_tiles)
-        go = tile_block<LabT>(a, b - a.n_hub_chunks - a.n_solo, S, p_done, p_cnt, p_tot);
+    else if (b - a.n_hub_chunks - a.n_solo < a.n_iso_blocks)
+        go = iso_block(a, b - a.n_hub_chunks - a.n_solo, S, p_done, p_cnt, p_tot);
+    else if (b - a.n_hub_chunks - a.n_solo - a.n_iso_blocks < a.n_tiles)
+        go = tile_block<LabT>(a, b - a.n_hub_chunks - a.n_solo - a.n_iso_blocks, S, p_done, p_cnt, p_tot);
     else
         go = null_block(a, S, p_done, p_cnt, p_tot);
     if (go && !a.hash_only) recycle(a);
@@ -800,7 +865,7 @@ void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_
 }
 
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
-                      bool stop, hipStream_t s) {
+                      bool stop, bool all_levels, hipStream_t s) {
     IterArgs a{};
     a.row_off = g.row_off;
     a.tgt = g.tgt;
@@ -811,8 +876,14 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.h_next = rb.h[k & 1];
     a.alive = g.alive;
     a.rep = rb.rep;
-    a.tile_v0 = g.tile_v0;
-    a.tile_v1 = g.tile_v1;
+    a.tile_i0 = g.tile_i0;
+    a.tile_i1 = g.tile_i1;
+    a.tile_e0 = g.tile_e0;
+    a.tile_e1 = g.tile_e1;
+    a.act = g.act;
+    a.iso = g.iso;
+    a.n_iso = g.n_iso;
+    a.n_iso_blocks = ceil_div(g.n_iso, kIsoPerBlock);
     a.hc_hub = g.hc_hub;
     a.hc_e0 = g.hc_e0;
     a.hub_v = g.hub_v;
@@ -832,8 +903,9 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.k = k;
     a.k_max = k_max;
     a.stop = stop ? 1u : 0u;
+    a.all_levels = all_levels ? 1u : 0u;
     a.bc = rb.bc;
-    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_solo + g.n_tiles, 1);
+    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_solo + a.n_iso_blocks + g.n_tiles, 1);
     if (g.label_bytes == 2)
         k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
     else
@@ -890,8 +962,14 @@ void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_pre
     a.h_prev = h_prev;
     a.h_next = h_next;
     a.alive = g.alive;
-    a.tile_v0 = g.tile_v0;
-    a.tile_v1 = g.tile_v1;
+    a.tile_i0 = g.tile_i0;
+    a.tile_i1 = g.tile_i1;
+    a.tile_e0 = g.tile_e0;
+    a.tile_e1 = g.tile_e1;
+    a.act = g.act;
+    a.iso = g.iso;
+    a.n_iso = g.n_iso;
+    a.n_iso_blocks = ceil_div(g.n_iso, kIsoPerBlock);
     a.hc_hub = g.hc_hub;
     a.hc_e0 = g.hc_e0;
     a.hub_v = g.hub_v;
@@ -907,7 +985,8 @@ void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_pre
     a.k = level;
     a.k_max = 0xFFFFFFFFu;
     a.hash_only = 1;
-    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_solo + g.n_tiles, 1);
+    a.all_levels = 1;
+    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_solo + a.n_iso_blocks + g.n_tiles, 1);
     if (g.label_bytes == 2)
         k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
     else

@@ -140,7 +140,7 @@ namespace {
 __global__ void __launch_bounds__(kBlock) k_stage_vertices(
     const uint32_t* __restrict__ row_off, const uint32_t* __restrict__ type_off,
     const uint8_t* __restrict__ alive, uint32_t n, uint64_t m, uint32_t* __restrict__ hubf,
-    RunStatus* status) {
+    uint32_t* __restrict__ actf, uint32_t* __restrict__ isof, RunStatus* status) {
     uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     const bool in = v < n;
     if (!in) v = n - 1;  // inactive lanes mirror the last vertex and store nothing
@@ -167,6 +167,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_vertices(
     bool hub = (b >= a) && d >= kHubMinDegree;
     if (in) {
         hubf[v] = hub ? 1u : 0u;
+        actf[v] = (b > a && !hub) ? 1u : 0u;
+        isof[v] = (b <= a) ? 1u : 0u;
         if (err) atomicOr(&status->error, err);
     }
 }
@@ -212,56 +214,63 @@ __global__ void __launch_bounds__(kBlock) k_compact_flags(const uint32_t* __rest
     if (v < n && flag[v]) out[pos[v]] = v;
 }
 
-// Greedy tile packing within windows of kPackWindow consecutive vertices
-// (one thread per window): a tile grows until the next vertex would bring it
-// to kTileMaxEdges edges or kTileMaxVerts vertices; hubs end a tile and
-// belong to none.  With emit == false only the tile count per window is
-// written (to cnt[w]); with emit == true tiles are written from pos[w] on.
+// Greedy tile packing within windows of kPackWindow consecutive entries of
+// the tile-vertex list (one thread per window): a tile grows until the next
+// vertex would bring it to kTileMaxEdges edges or kTileMaxVerts vertices, or
+// its edges would not follow the tile's (a hub lies between).  With
+// emit == false only the tile count per window is written (to cnt[w]); with
+// emit == true tiles are written from pos[w] on.
 constexpr uint32_t kPackWindow = 1024;
 
-__global__ void __launch_bounds__(kBlock) k_pack_tiles(const uint32_t* __restrict__ row_off, uint32_t n,
+__global__ void __launch_bounds__(kBlock) k_pack_tiles(const uint32_t* __restrict__ row_off,
+                                                       const uint32_t* __restrict__ act, uint32_t n_act,
                                                        bool emit, uint32_t* __restrict__ cnt,
                                                        const uint32_t* __restrict__ pos,
-                                                       uint32_t* __restrict__ v0,
-                                                       uint32_t* __restrict__ v1) {
+                                                       uint32_t* __restrict__ i0, uint32_t* __restrict__ i1,
+                                                       uint32_t* __restrict__ e0, uint32_t* __restrict__ e1) {
     const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
-    const uint64_t vb64 = static_cast<uint64_t>(w) * kPackWindow;
-    if (vb64 >= n) return;
-    const uint32_t vb = static_cast<uint32_t>(vb64);
-    const uint32_t ve = static_cast<uint32_t>(min<uint64_t>(n, vb64 + kPackWindow));
+    const uint64_t ib64 = static_cast<uint64_t>(w) * kPackWindow;
+    if (ib64 >= n_act) return;
+    const uint32_t ib = static_cast<uint32_t>(ib64);
+    const uint32_t ie = static_cast<uint32_t>(min<uint64_t>(n_act, ib64 + kPackWindow));
     uint32_t out = emit ? pos[w] : 0, made = 0;
-    uint32_t start = vb, edges = 0, verts = 0;
-    uint32_t a = row_off[vb];
-    for (uint32_t v = vb; v < ve; v++) {
-        const uint32_t b = row_off[v + 1];
+    uint32_t start = ib, edges = 0, verts = 0, ebeg = 0, eend = 0;
+    for (uint32_t i = ib; i < ie; i++) {
+        const uint32_t v = act[i];
+        const uint32_t a = row_off[v], b = row_off[v + 1];
         const uint32_t d = b - a;
-        a = b;
-        if (d >= kHubMinDegree) {  // hub: close the tile, skip the vertex
-            if (verts) {
-                if (emit) { v0[out] = start; v1[out] = v; out++; }
-                made++;
+        if (verts && (a != eend || verts == static_cast<uint32_t>(kTileMaxVerts) ||
+                      edges + d >= static_cast<uint32_t>(kTileMaxEdges))) {
+            if (emit) {
+                i0[out] = start;
+                i1[out] = i;
+                e0[out] = ebeg;
+                e1[out] = eend;
+                out++;
             }
-            start = v + 1;
-            edges = verts = 0;
-            continue;
-        }
-        if (verts == static_cast<uint32_t>(kTileMaxVerts) || edges + d >= static_cast<uint32_t>(kTileMaxEdges)) {
-            if (emit) { v0[out] = start; v1[out] = v; out++; }
             made++;
-            start = v;
-            edges = verts = 0;
+            verts = edges = 0;
+        }
+        if (!verts) {
+            start = i;
+            ebeg = a;
         }
         edges += d;
         verts++;
+        eend = b;
     }
     if (verts) {
-        if (emit) { v0[out] = start; v1[out] = ve; out++; }
+        if (emit) {
+            i0[out] = start;
+            i1[out] = ie;
+            e0[out] = ebeg;
+            e1[out] = eend;
+            out++;
+        }
         made++;
     }
     if (!emit) cnt[w] = made;
 }
-
-
 
 __global__ void __launch_bounds__(kBlock) k_hub_degrees(const uint32_t* __restrict__ row_off,
                                                          const uint32_t* __restrict__ hubs,
@@ -289,10 +298,13 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
     const uint32_t n = g.n;
     hip_check(hipMemsetAsync(status_dev, 0, sizeof(RunStatus), s), "stage status");
     uint32_t* hubf = arena.alloc<uint32_t>(n + 1);
-    uint32_t* counts = arena.alloc<uint32_t>(4);
+    uint32_t* actf = arena.alloc<uint32_t>(n + 1);
+    uint32_t* isof = arena.alloc<uint32_t>(n + 1);
+    uint32_t* counts = arena.alloc<uint32_t>(8);
+    hip_check(hipMemsetAsync(counts, 0, 8 * 4, s), "stage counts");
     if (n > 0) {
         k_stage_vertices<<<ceil_div(n, kBlock), kBlock, 0, s>>>(g.row_off, g.type_off, g.alive, n,
-                                                                g.m, hubf, status_dev);
+                                                                g.m, hubf, actf, isof, status_dev);
         if (g.m > 0) {
             uint32_t nbk = std::min<uint64_t>(ceil_div(g.m, kBlock), 2048);
             if (g.label_bytes == 2)
@@ -309,10 +321,21 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
     scan_exclusive(hubf, hpos, n, counts + 1, arena, s);
     uint32_t* hubs = arena.alloc<uint32_t>(n + 1);
     if (n) k_compact_flags<<<ceil_div(n, kBlock), kBlock, 0, s>>>(hubf, hpos, n, hubs);
+    // tile vertices and vertices without out-edges -> lists
+    uint32_t* apos = arena.alloc<uint32_t>(n + 1);
+    uint32_t* ipos = arena.alloc<uint32_t>(n + 1);
+    scan_exclusive(actf, apos, n, counts + 4, arena, s);
+    scan_exclusive(isof, ipos, n, counts + 5, arena, s);
+    g.act = arena.alloc<uint32_t>(n + 1);
+    g.iso = arena.alloc<uint32_t>(n + 1);
+    if (n) {
+        k_compact_flags<<<ceil_div(n, kBlock), kBlock, 0, s>>>(actf, apos, n, g.act);
+        k_compact_flags<<<ceil_div(n, kBlock), kBlock, 0, s>>>(isof, ipos, n, g.iso);
+    }
     hip_check(hipMemcpyAsync(status_host, status_dev, sizeof(RunStatus), hipMemcpyDeviceToHost, s),
               "stage status");
-    uint32_t hc[2];
-    hip_check(hipMemcpyAsync(hc, counts, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "stage counts");
+    uint32_t hc[8];
+    hip_check(hipMemcpyAsync(hc, counts, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "stage counts");
     hip_check(hipStreamSynchronize(s), "stage sync");
     if (status_host->error & kErrRange)
         throw DeviceError{BSIM_E_RANGE, "edge target out of range"};
@@ -324,22 +347,28 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         throw DeviceError{BSIM_E_UNSUPPORTED, "edge labels must be < 2^24"};
     g.max_label = status_host->max_label;
     g.n_hubs = hc[1];
+    g.n_act = hc[4];
+    g.n_iso = hc[5];
 
-    // tiles: greedy packing per window of vertices
-    const uint32_t nwin = ceil_div(n, kPackWindow);
+    // tiles: greedy packing per window of the tile-vertex list
+    const uint32_t nwin = ceil_div(g.n_act, kPackWindow);
     uint32_t* wcnt = arena.alloc<uint32_t>(nwin + 1);
     uint32_t* wpos = arena.alloc<uint32_t>(nwin + 1);
-    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, n, false, wcnt, nullptr,
-                                                                      nullptr, nullptr);
+    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, g.act, g.n_act, false, wcnt,
+                                                                      nullptr, nullptr, nullptr, nullptr,
+                                                                      nullptr);
     scan_exclusive(wcnt, wpos, nwin, counts + 2, arena, s);
     uint32_t ntiles = 0;
     hip_check(hipMemcpyAsync(&ntiles, counts + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "tiles");
     hip_check(hipStreamSynchronize(s), "tiles sync");
     g.n_tiles = ntiles;
-    g.tile_v0 = arena.alloc<uint32_t>(ntiles + 1);
-    g.tile_v1 = arena.alloc<uint32_t>(ntiles + 1);
-    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, n, true, nullptr, wpos,
-                                                                      g.tile_v0, g.tile_v1);
+    g.tile_i0 = arena.alloc<uint32_t>(ntiles + 1);
+    g.tile_i1 = arena.alloc<uint32_t>(ntiles + 1);
+    g.tile_e0 = arena.alloc<uint32_t>(ntiles + 1);
+    g.tile_e1 = arena.alloc<uint32_t>(ntiles + 1);
+    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, g.act, g.n_act, true, nullptr,
+                                                                      wpos, g.tile_i0, g.tile_i1, g.tile_e0,
+                                                                      g.tile_e1);
     hip_check(hipGetLastError(), "tile packing");
 
     // hubs: schedule on the host (few), largest first so long buckets start early

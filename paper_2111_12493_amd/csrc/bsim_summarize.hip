@@ -137,7 +137,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                         hip_check(hipEventRecord(et[0], s), "event");
                     }
                     if (rb.bc.gid) launch_graph_stop(rb, kk, p.k_max, stop, s);
-                    launch_iteration(g, rb, kk, p.k_max, stop, s);
+                    launch_iteration(g, rb, kk, p.k_max, stop, sink && !sink->levels.empty(), s);
                     if (timed) hip_check(hipEventRecord(et[1], s), "event");
                     if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
                     if (timed) hip_check(hipEventRecord(et[2], s), "event");
