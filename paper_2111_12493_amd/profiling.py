@@ -3,6 +3,7 @@
     python -m paper_2111_12493_amd.profiling stats  <kernel_stats.csv>
     python -m paper_2111_12493_amd.profiling trace  <kernel_trace.csv> <k_done>
     python -m paper_2111_12493_amd.profiling counters <counter_collection.csv> [calib_bytes [k_done]]
+    python -m paper_2111_12493_amd.profiling summary <dir> <workload> <k_done> <algorithmic_bytes> <calib_bytes> <out_dir>
     python -m paper_2111_12493_amd.profiling report <workload> <k_done> <algorithmic_bytes>
         <kernel_trace.csv> <fetch_counters.csv> <write_counters.csv> <calib_bytes> <out.json>
 
@@ -146,7 +147,73 @@ def report(workload: str, k_done: int, algo_bytes: int, trace_csv: str, fetch_cs
     return res
 
 
+COMMANDS = """    rocprofv3 --kernel-trace --stats -d {d}/stats -o run --output-format csv -- \\
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --steps 2 --warmup 1
+    rocprofv3 --pmc FETCH_SIZE -d {d}/fetch -o run --output-format csv -- \\
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --steps 1 --warmup 0 --calibrate-copy 1024
+    rocprofv3 --pmc WRITE_SIZE -d {d}/write -o run --output-format csv -- \\
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --steps 1 --warmup 0 --calibrate-copy 1024
+    rocprofv3 --pmc SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_INSTS_VALU \\
+        SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT -d {d}/sq1 -o run --output-format csv -- \\
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --steps 1 --warmup 0
+    rocprofv3 --pmc SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS \\
+        SQ_ACTIVE_INST_VMEM SQ_INST_CYCLES_VMEM_RD GRBM_GUI_ACTIVE TCC_HIT -d {d}/sq2 -o run \\
+        --output-format csv -- python -u bench.py --no-cpu-baseline --no-incremental --no-batched --steps 1 --warmup 0
+"""
+
+
+def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: int, out_dir: str) -> str:
+    """Write <out_dir>/k_iterate_<workload>.md and _counters.json from the
+    five rocprofv3 runs under directory d (see COMMANDS)."""
+    j = os.path.join
+    rep = report(workload, k_done, algo_bytes, j(d, "stats", "run_kernel_trace.csv"),
+                 j(d, "fetch", "run_counter_collection.csv"), j(d, "write", "run_counter_collection.csv"),
+                 calib_bytes, j(out_dir, "k_iterate_%s_counters.json" % workload))
+    sq = []
+    derived = {}
+    for pas in ("sq1", "sq2"):
+        res, _ = counters(j(d, pas, "run_counter_collection.csv"), 0, k_done)
+        for k in ("k_iterate", "k_hub"):
+            if k in res:
+                avg = res[k]["avg"]
+                derived.setdefault(k, {}).update(avg)
+                sq.append("%s %s" % (k, " ".join("%s=%.4g" % kv for kv in sorted(avg.items()))))
+    lines = ["# k_iterate / k_hub on %s (%d iterations)" % (workload, k_done), "",
+             "Kernel source fingerprint (%s): %s" % (", ".join(KERNEL_SOURCES), rep["kernel_sources_sha256_16"]), "",
+             "## Commands (repository root, one MI355X)", "", COMMANDS.format(d=d), "Summaries:", "",
+             "    python -m paper_2111_12493_amd.profiling summary %s %s %d %d %d profiles"
+             % (d, workload, k_done, algo_bytes, calib_bytes), "",
+             "## Kernel stats (every dispatch of the profiled runs)", "", "```",
+             stats(j(d, "stats", "run_kernel_stats.csv")), "```", "",
+             "Launches past the stop test of a run return at once; over the working launches "
+             "(1..k_done+1 of every run):", "", "```", trace(j(d, "stats", "run_kernel_trace.csv"), k_done), "```", "",
+             "## HBM traffic per working k_iterate launch", "",
+             "Calibration kernel (torch bitwise_not over %d bytes: reads and writes that many): one FETCH_SIZE "
+             "unit = %.1f bytes, one WRITE_SIZE unit = %.1f bytes." % (calib_bytes, rep["fetch_scale_bytes_per_unit"],
+                                                                       rep["write_scale_bytes_per_unit"]), "",
+             "| | raw units | bytes |", "|---|---:|---:|",
+             "| FETCH_SIZE | %.0f | %.1f MB |" % (rep["raw_fetch_size_per_launch"], rep["fetch_bytes_per_launch"] / 1e6),
+             "| WRITE_SIZE | %.0f | %.1f MB |" % (rep["raw_write_size_per_launch"], rep["write_bytes_per_launch"] / 1e6),
+             "| total | | %.1f MB |" % (rep["bytes_per_launch"] / 1e6),
+             "| algorithmic | | %.1f MB |" % (algo_bytes / 1e6), "",
+             "Measured / algorithmic = %.2f." % (rep["bytes_per_launch"] / algo_bytes), "",
+             "## Issue counters per working launch", "", "```"] + sq + ["```", ""]
+    k = derived.get("k_iterate", {})
+    if k.get("GRBM_GUI_ACTIVE") and k.get("SQ_ACTIVE_INST_VALU"):
+        busy = k["SQ_ACTIVE_INST_VALU"] * 4 / 1024 / (k["GRBM_GUI_ACTIVE"] / 8)
+        wait = k.get("SQ_WAIT_ANY", 0) / max(k.get("SQ_WAVE_CYCLES", 1), 1)
+        lines.append("k_iterate: VALU busy = SQ_ACTIVE_INST_VALU x 4 / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8 XCDs) "
+                     "= %.0f %%; SQ_WAIT_ANY / SQ_WAVE_CYCLES = %.0f %%." % (100 * busy, 100 * wait))
+    path = j(out_dir, "k_iterate_%s.md" % workload)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return path
+
+
 def main(argv):
+    if argv[1] == "summary":
+        print(summary(argv[2], argv[3], int(argv[4]), int(argv[5]), int(argv[6]), argv[7]))
+        return
     if argv[1] == "stats":
         print(stats(argv[2]))
     elif argv[1] == "report":
