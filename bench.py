@@ -73,14 +73,81 @@ def percentile(v, q):
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
 
 
-def incremental_leg(args, binding, gg, torch):
+def serving_leg(args, binding, gg, torch, g):
+    """A burst of fresh summarize requests and update batches for a resident
+    state through the server (4 workers, admission by footprint) against the
+    plain form: the same requests one at a time through one worker."""
+    import numpy as np
+
+    rng = np.random.default_rng(29)
+    fresh = []
+    for i in range(args.serve_requests // 2):
+        m = int(round(10 ** rng.uniform(4, 6)))
+        n = max(2, m // 8)
+        fresh.append(gg.rmat_graph(int(np.ceil(np.log2(n))), m, n_types=128, n_labels=64, n=n,
+                                   seed=int(rng.integers(1, 1 << 30))))
+    dead = np.zeros(g.n + 1_000_000, dtype=bool)
+    n_v = g.n
+    scale = int(np.ceil(np.log2(max(g.n, 2))))
+    batches = []
+    for i in range(args.serve_requests // 2):
+        d = gg.sample_update_ops(g.row_off, g.tgt, g.lab, n_v, dead, rng, int(round(10 ** rng.uniform(3, 5))),
+                                 max(g.n_labels, 1), max(g.n_types, 1), rmat_scale=scale)
+        n_v = d["n_after"]
+        batches.append(binding.UpdateBatch.from_op_arrays(d))
+    hg = [binding.HostGraph(x) for x in fresh]
+    dbase = binding.DeviceGraph(g)
+
+    def run(workers):
+        srv = binding.Server(workers=workers)
+        try:
+            res, state = srv.poll(srv.submit_summarize(dbase, k_max=4, stop_at_fixpoint=False,
+                                                       summary_edges=False, keep_state=True))
+            res.free()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tickets = []
+            for i in range(max(len(hg), len(batches))):
+                if i < len(hg):
+                    tickets.append(srv.submit_summarize(hg[i], summary_edges=False))
+                if i < len(batches):
+                    tickets.append(srv.submit_update(state, batches[i]))
+            blocks = []
+            for t in tickets:
+                r, _ = srv.poll(t)
+                blocks.append(r.n_blocks)
+                r.free()
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+            srv.release_state(state)
+        finally:
+            srv.free()
+        return blocks, wall, st
+
+    b_mix, w_mix, s_mix = run(4)
+    b_one, w_one, s_one = run(1)
+    if b_mix != b_one:
+        raise RuntimeError("serving results differ between the mix and one-at-a-time runs")
+    req = len(b_mix)
+    return {"workload": "%s resident (k=4) + %d fresh R-MAT summaries (10^4-10^6 edges, to fixpoint) + %d update "
+                        "batches (10^3-10^5 ops), submitted as one burst" % (args.inc_workload, len(hg), len(batches)),
+            "requests": req, "workers": 4,
+            "p50_ms": s_mix["p50_ms"][0], "p99_ms": s_mix["p99_ms"][0],
+            "update_p50_ms": s_mix["p50_ms"][2], "update_p99_ms": s_mix["p99_ms"][2],
+            "summarize_p50_ms": s_mix["p50_ms"][1], "summarize_p99_ms": s_mix["p99_ms"][1],
+            "requests_per_s": req / w_mix,
+            "plain_p50_ms": s_one["p50_ms"][0], "plain_p99_ms": s_one["p99_ms"][0],
+            "plain_requests_per_s": req / w_one,
+            "plain_form": "same requests, one worker, one at a time (FIFO, no overlap)"}
+
+
+def incremental_leg(args, binding, gg, torch, g):
     """Update-batch latency on a resident graph (k = 4): the incremental form
     (frontier re-hash, full levels once a frontier exceeds the limit) beside
     the plain form (every level recomputed for all vertices) on the same
     batches, each on its own copy of the state."""
     import numpy as np
 
-    g = gg.make_config(args.inc_workload)
     print("# incremental: %s, %d vertices, %d edges" % (args.inc_workload, g.n, g.m), file=sys.stderr, flush=True)
     ctx_i, ctx_p = binding.Context(0), binding.Context(0)
     ctx_p.set_option("frontier_limit_pct", 0)
@@ -190,6 +257,8 @@ def main() -> int:
     ap.add_argument("--inc-workload", default="rmat24")
     ap.add_argument("--inc-batches", type=int, default=16)
     ap.add_argument("--inc-max-ops", type=float, default=1e6)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=1024)
     ap.add_argument("--batch-max-edges", type=float, default=1e5)
@@ -297,8 +366,13 @@ def main() -> int:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_iters)
     del g
-    if not args.no_incremental:
-        out["incremental"] = incremental_leg(args, binding, gg, torch)
+    if not (args.no_incremental and args.no_serving):
+        g24 = gg.make_config(args.inc_workload)
+        if not args.no_incremental:
+            out["incremental"] = incremental_leg(args, binding, gg, torch, g24)
+        if not args.no_serving:
+            out["serving"] = serving_leg(args, binding, gg, torch, g24)
+        del g24
     if not args.no_batched:
         out["batched"] = batched_leg(args, binding, gg, torch)
     print(json.dumps(out), flush=True)

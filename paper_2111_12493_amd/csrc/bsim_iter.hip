@@ -297,22 +297,42 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
     if (!hash) return true;
     for (uint32_t j = tid; j < 2 * ne; j += kBlock) S.tab[j] = 0;
     tile_segments(nv, S.off, S.seg, S.red);
+    // De-duplicate the mixed keys per vertex.  Most keys are distinct and
+    // most home slots empty, so every key first tries its home slot, with
+    // all of a thread's attempts in flight together; the few keys whose home
+    // slot holds another key probe on from there.
+    uint64_t f[kEdgesPerThread];
+    uint32_t seg[kEdgesPerThread], slot[kEdgesPerThread], lo[kEdgesPerThread], hi[kEdgesPerThread];
 #pragma unroll
     for (int r = 0; r < kEdgesPerThread; r++) {
         const uint32_t j = tid + r * kBlock;
+        f[r] = 0;  // a zero term adds nothing to the sum, repeated or not
         if (j < ne) {
-            const uint64_t f = mix64(hv[r] ^ kCE);
-            if (f != 0) {  // a zero term adds nothing to the sum, repeated or not
-                const uint32_t i = S.seg[j];
-                const uint32_t base = 2 * S.off[i];
-                const uint32_t span = 2 * (S.off[i + 1] - S.off[i]);
-                const uint32_t slot = base + static_cast<uint32_t>(
-                                                 (static_cast<uint64_t>(static_cast<uint32_t>(f)) * span) >> 32);
-                if (lds_insert(S.tab, slot, base, base + span, f))
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&S.acc[i]),
-                              static_cast<unsigned long long>(f));
-            }
+            f[r] = mix64(hv[r] ^ kCE);
+            const uint32_t i = S.seg[j];
+            seg[r] = i;
+            lo[r] = 2 * S.off[i];
+            hi[r] = 2 * S.off[i + 1];
+            slot[r] = lo[r] + static_cast<uint32_t>(
+                                  (static_cast<uint64_t>(static_cast<uint32_t>(f[r])) * (hi[r] - lo[r])) >> 32);
         }
+    }
+    uint64_t old[kEdgesPerThread];
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++)
+        if (f[r] != 0)
+            old[r] = atomicCAS(reinterpret_cast<unsigned long long*>(&S.tab[slot[r]]), 0ull,
+                               static_cast<unsigned long long>(f[r]));
+#pragma unroll
+    for (int r = 0; r < kEdgesPerThread; r++) {
+        if (f[r] == 0 || old[r] == f[r]) continue;
+        bool fresh = old[r] == 0;
+        if (!fresh) {
+            const uint32_t next = slot[r] + 1 == hi[r] ? lo[r] : slot[r] + 1;
+            fresh = lds_insert(S.tab, next, lo[r], hi[r], f[r]) != 0;
+        }
+        if (fresh)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&S.acc[seg[r]]), static_cast<unsigned long long>(f[r]));
     }
     __syncthreads();
     if (mine && act_hash) a.h_next[v] = live ? mix64(tv ^ mix64(kCS + S.acc[tid])) : 0;
@@ -446,15 +466,28 @@ __device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_
         record_founders(a.test_tab, a.lcnt, k - 1, founded, slot, S.red, &S.ctl[1]);
     }
     if (!hash) return true;
+    // home-slot attempts first, all in flight together (see tile_block)
     uint64_t acc = 0;
+    uint64_t f[kSoloPerThread], old[kSoloPerThread];
 #pragma unroll
     for (int r = 0; r < kSoloPerThread; r++) {
         const uint32_t j = tid + r * kBlock;
-        if (j < ne) {
-            const uint64_t f = mix64(hv[r] ^ kCE);
-            if (f != 0 && lds_insert(S.tab, static_cast<uint32_t>(f) & (kTableSlots - 1), 0, kTableSlots, f))
-                acc += f;
-        }
+        f[r] = j < ne ? mix64(hv[r] ^ kCE) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kSoloPerThread; r++)
+        if (f[r] != 0)
+            old[r] = atomicCAS(reinterpret_cast<unsigned long long*>(
+                                   &S.tab[static_cast<uint32_t>(f[r]) & (kTableSlots - 1)]),
+                               0ull, static_cast<unsigned long long>(f[r]));
+#pragma unroll
+    for (int r = 0; r < kSoloPerThread; r++) {
+        if (f[r] == 0 || old[r] == f[r]) continue;
+        bool fresh = old[r] == 0;
+        if (!fresh)
+            fresh = lds_insert(S.tab, (static_cast<uint32_t>(f[r]) + 1) & (kTableSlots - 1), 0, kTableSlots,
+                               f[r]) != 0;
+        if (fresh) acc += f[r];
     }
     acc = wave_sum_u64(acc);
     if (lane_id() == 0) S.acc[tid >> 6] = acc;
