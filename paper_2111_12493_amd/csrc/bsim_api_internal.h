@@ -12,7 +12,7 @@ struct bsim_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bsim::RunStatus* status_host = nullptr;  // pinned, 4 entries
-    uint32_t chunk_max = 256;
+    uint32_t chunk_max = 32;
     uint32_t time_launches = 0;
     uint32_t hub_table_slots = 8192;  // LDS slots per hub-bucket block on this device
     uint32_t frontier_limit_pct = 2;  // incremental: larger frontiers recompute the level for all vertices

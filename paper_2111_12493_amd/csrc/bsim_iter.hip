@@ -186,6 +186,11 @@ __device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32
         atomicAdd(&a.bc.hist[static_cast<size_t>(a.k - 1) * a.bc.n_graphs + a.bc.gid[v]], 1u);
 }
 
+// The sticky done flag as this wave sees it (only to skip loads; see tile_block).
+__device__ __forceinline__ bool early_done(const IterArgs& a) {
+    return !a.hash_only && *reinterpret_cast<volatile uint32_t*>(&a.status->done) != 0;
+}
+
 // Stop test of level k-2 (wave 0), from the values loaded at block start:
 // S.ctl[0] = 1 when the run is done; block 0 also records n_{k-2} and, on
 // stopping, the final status.  Visible to the block after its next barrier.
@@ -228,8 +233,12 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
     const bool hash = k <= a.k_max;
     const uint32_t i0 = a.tile_i0[tile], nv = a.tile_i1[tile] - i0;
     const uint32_t ebase = a.tile_e0[tile];
-    const uint32_t ne = a.tile_e1[tile] - ebase;
-    const bool mine = tid < nv;
+    // A launch queued after the stop finds the sticky done flag set; every
+    // block of it then takes the same stop decision, so its waves may skip
+    // their loads at once (the exit itself still follows stop_decision).
+    const bool skip = early_done(a);
+    const uint32_t ne = skip ? 0u : a.tile_e1[tile] - ebase;
+    const bool mine = !skip && tid < nv;
     const uint32_t v = mine ? a.act[i0 + tid] : 0u;
     uint32_t ro0 = 0, rv = v, gi = 0;
     uint64_t hv_own = 0, tv = 0;
@@ -353,7 +362,7 @@ __device__ bool hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, 
     const uint32_t logb = a.hub_logb[hi];
     const uint64_t koff = a.hub_key_off[hi];
     const uint32_t vbeg = a.row_off[v], vend = a.row_off[v + 1];
-    const uint32_t ne = min(static_cast<uint32_t>(kTileMaxEdges), vend - e0);
+    const uint32_t ne = early_done(a) ? 0u : min(static_cast<uint32_t>(kTileMaxEdges), vend - e0);
     const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
     uint32_t w[kEdgesPerThread];
     uint32_t l[kEdgesPerThread];
@@ -433,7 +442,7 @@ __device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_
     const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
     const bool hash = k <= a.k_max;
     const uint32_t e0 = a.row_off[v];
-    const uint32_t ne = a.row_off[v + 1] - e0;
+    const uint32_t ne = early_done(a) ? 0u : a.row_off[v + 1] - e0;
     bool act_hash = true;
     if (a.bc.gid) act_hash = k <= a.bc.done_level[a.bc.gid[v]];
     const uint64_t tv = hash ? a.t[v] : 0;

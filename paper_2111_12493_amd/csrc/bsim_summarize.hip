@@ -87,7 +87,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     // launch k tests level k-2, so launch k_max + 2 always sees the cap
     const uint64_t k_last = static_cast<uint64_t>(p.k_max) + 2;
     uint64_t k = 1;
-    uint32_t chunk = 8;
+    uint32_t chunk = 4;
     int pending = -1;
     hipEvent_t ev[2];
     hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
