@@ -89,6 +89,41 @@ __device__ uint64_t split_join(const SplitTable& T, uint32_t r, uint64_t key, ui
     }
 }
 
+// split_join for the participating lanes of a wave, one call per distinct
+// (r, key): lanes are grouped by ballots first, so a key shared by many
+// vertices (every vertex without out-edges of one type set joins one class)
+// reaches the table once per wave.  All lanes of the wave must call it.
+// Returns the owner word for participating lanes; *founded / *slot as
+// split_join for the group's leader, 0 / 0xFFFFFFFF for the others.
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, uint32_t src) {
+    const int lo = __shfl(static_cast<int>(static_cast<uint32_t>(x)), static_cast<int>(src), 64);
+    const int hi = __shfl(static_cast<int>(static_cast<uint32_t>(x >> 32)), static_cast<int>(src), 64);
+    return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+__device__ uint64_t wave_split_join(const SplitTable& T, bool participant, uint32_t r, uint64_t key, uint32_t v,
+                                    uint32_t* founded, uint32_t* slot_out, RunStatus* status) {
+    const uint32_t lane = lane_id();
+    uint32_t leader_of = lane;
+    bool pending = participant;
+    for (;;) {
+        const uint64_t ball = __ballot(pending);
+        if (!ball) break;
+        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
+        const uint64_t lk = shfl_u64(key, leader);
+        const uint32_t lr = static_cast<uint32_t>(__shfl(static_cast<int>(r), static_cast<int>(leader), 64));
+        if (pending && key == lk && r == lr) {
+            leader_of = leader;
+            pending = false;
+        }
+    }
+    *founded = 0;
+    *slot_out = 0xFFFFFFFFu;
+    uint64_t o = 0;
+    if (participant && leader_of == lane) o = split_join(T, r, key, v, founded, slot_out, status);
+    return shfl_u64(o, leader_of);
+}
+
 // Count the classes founded by this block at `level` (stripe counter) and
 // remember their slots so the table can be cleared selectively.
 __device__ void record_founders(const SplitTable& T, uint32_t* lcnt, uint32_t level,
@@ -129,9 +164,9 @@ __global__ void __launch_bounds__(kBlock) k_init(const uint32_t* __restrict__ ty
     __shared__ uint32_t s_base;
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     uint32_t founded = 0, slot = 0xFFFFFFFFu;
+    uint32_t r = 0xFFFFFFFFu;
     if (v < n) {
         uint64_t tv = 0;
-        uint32_t r = 0xFFFFFFFFu;
         if (!alive || alive[v]) {
             uint64_t sum = 0;
             if (!untyped) {
@@ -144,18 +179,23 @@ __global__ void __launch_bounds__(kBlock) k_init(const uint32_t* __restrict__ ty
                 }
             }
             tv = mix64(kCT + sum);
-            if (bc.gid) {
-                const uint32_t gi = bc.gid[v];
-                r = static_cast<uint32_t>(split_join(T, bc.virt_base + gi, tv, v, &founded, &slot, status));
-                if (founded) atomicAdd(&bc.hist[gi], 1u);
-            } else {
-                r = static_cast<uint32_t>(split_join(T, kNoRep, tv, v, &founded, &slot, status));
-            }
         }
         t[v] = tv;
         h0[v] = tv;
-        rep[v] = r;
     }
+    // level-0 classes: many vertices share a type set, so group each wave's
+    // lanes by key before they touch the table
+    const bool part = v < n && (!alive || alive[v]);
+    const uint32_t gi = (part && bc.gid) ? bc.gid[v] : 0u;
+    const uint32_t vr = bc.gid ? bc.virt_base + gi : kNoRep;
+    uint64_t key = 0;
+    if (part) key = t[v];
+    const uint64_t o = wave_split_join(T, part, vr, key, v, &founded, &slot, status);
+    if (part) {
+        r = static_cast<uint32_t>(o);
+        if (bc.gid && founded) atomicAdd(&bc.hist[gi], 1u);
+    }
+    if (v < n) rep[v] = r;
     record_founders(T, lcnt, 0, founded, slot, s_red, &s_base);
 }
 
@@ -554,10 +594,13 @@ __device__ bool iso_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32
     if (S.ctl[0]) return false;
     if (test) {
         for (int r = 0; r < kIsoPerThread; r++) {
+            // vertices without out-edges of one type set and one class all
+            // carry the same key: group them per wave before the table
             uint32_t founded = 0, slot = 0xFFFFFFFFu;
-            if (probe[r] && hv_own[r] != hv_rep[r]) {
-                a.rep[v[r]] =
-                    static_cast<uint32_t>(split_join(a.test_tab, rv[r], hv_own[r], v[r], &founded, &slot, a.status));
+            const bool part = probe[r] && hv_own[r] != hv_rep[r];
+            const uint64_t o = wave_split_join(a.test_tab, part, rv[r], hv_own[r], v[r], &founded, &slot, a.status);
+            if (part) {
+                a.rep[v[r]] = static_cast<uint32_t>(o);
                 if (a.bc.gid && founded)
                     atomicAdd(&a.bc.hist[static_cast<size_t>(k - 1) * a.bc.n_graphs + gi[r]], 1u);
             }
@@ -811,22 +854,36 @@ __global__ void __launch_bounds__(kBlock) k_level_classes(const uint64_t* __rest
     __shared__ uint32_t s_red[kBlock / 64];
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     uint32_t founded = 0, slot = 0xFFFFFFFFu;
+    bool part = false;
+    uint32_t r = kNoRep;
+    uint64_t hv = 0;
     if (v < n) {
         if (!alive[v]) {
             if (level == 0) rep[v] = 0xFFFFFFFFu;
-        } else if (level == 0) {
-            rep[v] = static_cast<uint32_t>(split_join(T, kNoRep, h[v], v, &founded, &slot, status));
         } else {
-            const uint32_t r = rep[v];
-            const uint64_t hv = h[v];
-            if (r != v && hv != h[r])
-                rep[v] = static_cast<uint32_t>(split_join(T, r, hv, v, &founded, &slot, status));
+            hv = h[v];
+            if (level == 0) {
+                part = true;
+            } else {
+                r = rep[v];
+                part = r != v && hv != h[r];
+            }
         }
     }
-    // founded slots are listed so that only they are cleared afterwards
-    if (founded && slot != 0xFFFFFFFFu) {
-        const uint32_t pos = atomicAdd(slot_count, 1u);
-        if (pos <= T.mask) T.list[pos] = slot;
+    const uint64_t o = wave_split_join(T, part, r, hv, v, &founded, &slot, status);
+    if (part) rep[v] = static_cast<uint32_t>(o);
+    // founded slots are listed so that only they are cleared afterwards (one
+    // counter atomic per wave: level 0 founds a class per distinct type set)
+    const bool listed = founded && slot != 0xFFFFFFFFu;
+    const uint64_t ball = __ballot(listed);
+    if (ball) {
+        const uint32_t lane = lane_id();
+        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(slot_count, static_cast<uint32_t>(__popcll(ball)));
+        base = static_cast<uint32_t>(__shfl(static_cast<int>(base), static_cast<int>(leader), 64));
+        const uint32_t pos = base + static_cast<uint32_t>(__popcll(ball & ((1ull << lane) - 1)));
+        if (listed && pos <= T.mask) T.list[pos] = slot;
     }
     const uint32_t c = block_sum_u32(founded, s_red);
     if (threadIdx.x == 0 && c) atomicAdd(founded_total, c);
