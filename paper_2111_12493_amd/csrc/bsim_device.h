@@ -81,10 +81,17 @@ __device__ __forceinline__ uint32_t count_insert(uint64_t* tab, uint32_t mask, u
 
 // Insert a nonzero key into an LDS open-addressing region; returns 1 if it
 // was not present.  Same read-before-CAS rule as count_insert.
+// Current value of an LDS table slot other lanes may be writing.  A relaxed
+// atomic load (a volatile one would keep the generic address space and
+// compile to a flat load, which also waits on every global load in flight).
+__device__ __forceinline__ uint64_t lds_peek(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ uint32_t lds_insert(uint64_t* tab, uint32_t slot, uint32_t base,
                                                uint32_t end, uint64_t f) {
     for (;;) {
-        uint64_t cur = *reinterpret_cast<volatile uint64_t*>(&tab[slot]);
+        uint64_t cur = lds_peek(&tab[slot]);
         if (cur == f) return 0u;
         if (cur == 0) {
             unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot]), 0ull,
@@ -96,12 +103,33 @@ __device__ __forceinline__ uint32_t lds_insert(uint64_t* tab, uint32_t slot, uin
     }
 }
 
+// Insert a nonzero key into an LDS table of `slots` slots by double hashing:
+// after `slot` (already tried), probe slot + step, slot + 2 step, ... mod
+// slots.  With slots prime and 0 < step < slots the sequence visits every
+// slot, so a table with a free slot always ends the loop: 1 = inserted,
+// 0 = already present.
+__device__ __forceinline__ uint32_t lds_insert_step(uint64_t* tab, uint32_t slot, uint32_t step, uint32_t slots,
+                                                    uint64_t f) {
+    for (;;) {
+        slot += step;
+        if (slot >= slots) slot -= slots;
+        uint64_t cur = lds_peek(&tab[slot]);
+        if (cur == f) return 0u;
+        if (cur == 0) {
+            unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot]), 0ull,
+                                               static_cast<unsigned long long>(f));
+            if (old == 0ull) return 1u;
+            if (old == f) return 0u;
+        }
+    }
+}
+
 // Insert a nonzero key into an LDS table of `slots` slots, probing at most
 // `slots` positions: 1 = inserted, 0 = already present, 2 = table full.
 __device__ __forceinline__ uint32_t lds_insert_bounded(uint64_t* tab, uint32_t slot, uint32_t slots,
                                                        uint64_t f) {
     for (uint32_t step = 0; step < slots; step++) {
-        uint64_t cur = *reinterpret_cast<volatile uint64_t*>(&tab[slot]);
+        uint64_t cur = lds_peek(&tab[slot]);
         if (cur == f) return 0u;
         if (cur == 0) {
             unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[slot]), 0ull,
@@ -124,17 +152,18 @@ __device__ __forceinline__ void add_block_count(uint32_t* stripes, uint32_t k, u
 // s_seg must be 8-byte aligned.  Ends with a barrier.
 __device__ inline void tile_segments(uint32_t nv, const uint32_t* s_off, uint8_t* s_seg,
                                      uint32_t* s_red) {
+    constexpr uint32_t kWords = kTileMaxEdges / 8;  // owner-map words, one per thread
     const uint32_t tid = threadIdx.x;
-    const uint32_t ne = s_off[nv];
+    uint64_t* seg64 = reinterpret_cast<uint64_t*>(s_seg);
     // zero the owner map, then mark each non-empty segment start
-    for (uint32_t j = tid; j < kTileMaxEdges / 8; j += kBlock)
-        reinterpret_cast<uint64_t*>(s_seg)[j] = 0;
+    if (tid < kWords) seg64[tid] = 0;
     __syncthreads();
     for (uint32_t i = tid; i < nv; i += kBlock)
         if (s_off[i + 1] > s_off[i]) s_seg[s_off[i]] = static_cast<uint8_t>(i);
     __syncthreads();
     // inclusive max-scan over the owner map: thread t owns bytes 8t..8t+7
-    uint64_t word = reinterpret_cast<uint64_t*>(s_seg)[tid];
+    // (threads past the map scan zeros, which leave a max unchanged)
+    const uint64_t word = tid < kWords ? seg64[tid] : 0;
     uint32_t run = 0;
 #pragma unroll
     for (int r = 0; r < 8; r++) run = max(run, static_cast<uint32_t>((word >> (8 * r)) & 0xFF));
@@ -157,12 +186,12 @@ __device__ inline void tile_segments(uint32_t nv, const uint32_t* s_off, uint8_t
         cur = max(cur, static_cast<uint32_t>((word >> (8 * r)) & 0xFF));
         out |= static_cast<uint64_t>(cur) << (8 * r);
     }
-    (void)ne;
-    reinterpret_cast<uint64_t*>(s_seg)[tid] = out;
+    if (tid < kWords) seg64[tid] = out;
     __syncthreads();
 }
 
-static_assert(kTileMaxEdges == 8 * kBlock, "tile_segments assumes 8 owner bytes per thread");
+static_assert(kTileMaxEdges % 8 == 0 && kTileMaxEdges / 8 <= kBlock,
+              "tile_segments keeps one 8-byte owner-map word per thread");
 static_assert(kTileMaxVerts <= 256, "owner map stores vertex indices in one byte");
 
 }  // namespace bsim

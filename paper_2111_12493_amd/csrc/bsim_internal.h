@@ -48,16 +48,21 @@ constexpr uint64_t kCE = mix64(4);  // per-pair domain
 // late iteration of a long chain run inserts a handful of keys.
 
 constexpr int kBlock = 256;              // threads per block (4 wave64s)
-constexpr int kTileMaxEdges = 2048;      // a tile holds fewer edges than this
+// The refinement kernel is latency bound: its speed follows the number of
+// blocks resident per CU, which its LDS sets (160 KiB per CU).  Tiles of
+// fewer than 1,536 edges keep a block under 32 KiB, five blocks per CU.
+constexpr int kTileMaxEdges = 1536;      // a tile holds fewer edges than this
 constexpr int kTileMaxVerts = 256;
-constexpr int kEdgesPerThread = kTileMaxEdges / kBlock;  // 8
-constexpr int kTableSlots = 2 * kTileMaxEdges;           // 4096 x 8 B = 32 KiB
+constexpr int kEdgesPerThread = kTileMaxEdges / kBlock;  // 6
+constexpr int kTableSlots = 2 * kTileMaxEdges;           // 3072 x 8 B = 24 KiB
 constexpr uint32_t kHubMinDegree = kTileMaxEdges;  // a hub would not fit an empty tile
 // A hub of at most kSoloMaxEdges edges is a "solo" block of the refinement
-// launch: one block gathers all its edges and de-duplicates them in the
-// whole LDS table (load <= 3/4); larger hubs take the chunk / bucket path.
-constexpr uint32_t kSoloMaxEdges = 3 * kTableSlots / 4;
-constexpr int kSoloPerThread = kSoloMaxEdges / kBlock;  // 12
+// launch: one block gathers all its edges and de-duplicates them in one
+// table over the block's tile arrays (kSoloSlots, a prime, with double
+// hashing, load <= 0.9); larger hubs take the chunk / bucket path.
+constexpr uint32_t kSoloMaxEdges = 2 * kTileMaxEdges;   // 3072
+constexpr uint32_t kSoloSlots = 3449;                   // prime, 27,592 B
+constexpr int kSoloPerThread = (kSoloMaxEdges + kBlock - 1) / kBlock;  // 12
 // Vertices without out-edges: h^k = M(t ^ M(C_S)) for every k >= 1, so they
 // need no tile.  Light blocks of kIsoPerBlock of them run their split test
 // and write their hash while it can still change the buffers (levels 1 and 2

@@ -210,6 +210,10 @@ struct IterShared {
     alignas(8) uint8_t seg[kTileMaxEdges];
 };
 
+static_assert(offsetof(IterShared, red) >= kSoloSlots * sizeof(uint64_t),
+              "a solo block's table must end before the block's control words");
+static_assert(kTileMaxEdges >= (kBlock / 64) * 8, "a solo block's wave sums live in seg");
+
 // Split test of level k-1 for one owned vertex (h_prev holds h^{k-1}).
 __device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32_t* founded,
                                            uint32_t* slot) {
@@ -228,7 +232,7 @@ __device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32
 
 // The sticky done flag as this wave sees it (only to skip loads; see tile_block).
 __device__ __forceinline__ bool early_done(const IterArgs& a) {
-    return !a.hash_only && *reinterpret_cast<volatile uint32_t*>(&a.status->done) != 0;
+    return !a.hash_only && __hip_atomic_load(&a.status->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
 // Stop test of level k-2 (wave 0), from the values loaded at block start:
@@ -505,8 +509,10 @@ __device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_
         const uint32_t j = tid + r * kBlock;
         hv[r] = (hash && j < ne) ? a.h_prev[w[r]] ^ a.salt[l[r]] : 0;
     }
+    // the table spans tab, acc and off (the arrays a tile block uses)
+    uint64_t* tab = S.tab;
     stop_decision(a, S, p_done, p_cnt, p_tot);
-    for (uint32_t j = tid; j < kTableSlots; j += kBlock) S.tab[j] = 0;
+    for (uint32_t j = tid; j < kSoloSlots; j += kBlock) tab[j] = 0;
     __syncthreads();
     if (S.ctl[0]) return false;
     if (test) {
@@ -523,27 +529,34 @@ __device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_
         const uint32_t j = tid + r * kBlock;
         f[r] = j < ne ? mix64(hv[r] ^ kCE) : 0;
     }
+    // double hashing: home slot from the low key bits, step from the high
+    // bits; the table size is prime, so every step visits every slot
+    uint32_t home[kSoloPerThread];
+#pragma unroll
+    for (int r = 0; r < kSoloPerThread; r++)
+        home[r] = static_cast<uint32_t>((static_cast<uint64_t>(static_cast<uint32_t>(f[r])) * kSoloSlots) >> 32);
 #pragma unroll
     for (int r = 0; r < kSoloPerThread; r++)
         if (f[r] != 0)
-            old[r] = atomicCAS(reinterpret_cast<unsigned long long*>(
-                                   &S.tab[static_cast<uint32_t>(f[r]) & (kTableSlots - 1)]),
-                               0ull, static_cast<unsigned long long>(f[r]));
+            old[r] = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[home[r]]), 0ull,
+                               static_cast<unsigned long long>(f[r]));
 #pragma unroll
     for (int r = 0; r < kSoloPerThread; r++) {
         if (f[r] == 0 || old[r] == f[r]) continue;
         bool fresh = old[r] == 0;
-        if (!fresh)
-            fresh = lds_insert(S.tab, (static_cast<uint32_t>(f[r]) + 1) & (kTableSlots - 1), 0, kTableSlots,
-                               f[r]) != 0;
+        if (!fresh) {
+            const uint32_t step = 1u + static_cast<uint32_t>(f[r] >> 32) % (kSoloSlots - 1);
+            fresh = lds_insert_step(tab, home[r], step, kSoloSlots, f[r]) != 0;
+        }
         if (fresh) acc += f[r];
     }
     acc = wave_sum_u64(acc);
-    if (lane_id() == 0) S.acc[tid >> 6] = acc;
+    uint64_t* wsum = reinterpret_cast<uint64_t*>(S.seg);  // outside the table
+    if (lane_id() == 0) wsum[tid >> 6] = acc;
     __syncthreads();
     if (tid == 0 && act_hash) {
         uint64_t sum = 0;
-        for (int i = 0; i < kBlock / 64; i++) sum += S.acc[i];
+        for (int i = 0; i < kBlock / 64; i++) sum += wsum[i];
         a.h_next[v] = mix64(tv ^ mix64(kCS + sum));
     }
     return true;
@@ -667,7 +680,7 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
     // stop-test inputs (level k-2), loaded together with everything else
     uint32_t p_done = 0, p_cnt = 0, p_tot = 0;
     if (tid < 64) {
-        p_done = *reinterpret_cast<volatile uint32_t*>(&a.status->done);
+        p_done = __hip_atomic_load(&a.status->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (k >= 2 && !a.bc.gid && !a.hash_only) {
             const uint32_t lv = k - 2;
             p_cnt = a.lcnt[(lv & (kStripeRing - 1)) * kStripes + tid];
