@@ -78,3 +78,75 @@ def apply_ops(g: Graph, ops) -> Graph:
     typ = np.array([x for t in types for x in t], dtype=np.uint32)
     return Graph(n=n, row_off=row_off, tgt=tgt, lab=lab, typ_off=typ_off, typ=typ,
                  alive=np.array(alive, dtype=np.uint8), n_labels=g.n_labels, n_types=g.n_types)
+
+
+def replay_rows(g: Graph, ops, vertices):
+    """Out-rows, type lists and liveness of the given vertices after the
+    operations, by the sequential semantics of apply_ops.
+
+    An operation changes the out-row of its source, the type list of its
+    vertex, or (a vertex deletion) every edge into the deleted vertex.  Once
+    deleted, a vertex can be named by no later operation, so no edge into it
+    can come back: removing those edges at the end, by the final liveness of
+    the targets, gives the same rows as removing them at the deletion.  So
+    only the asked-for rows are followed (as multisets of (label, target)),
+    while every operation is still validated against the liveness of all
+    vertices, as apply_ops does.  Returns {v: sorted [(label, target), ...]},
+    {v: sorted types}, {v: alive}.
+    """
+    want = set(int(v) for v in vertices)
+    alive = list(np.ones(g.n, dtype=bool) if g.alive is None else g.alive.astype(bool))
+    rows = {}
+    types = {}
+    for v in want:
+        if v < g.n:
+            a, b = int(g.row_off[v]), int(g.row_off[v + 1])
+            r = {}
+            for e in zip(g.lab[a:b].tolist(), g.tgt[a:b].tolist()):
+                r[e] = r.get(e, 0) + 1
+            rows[v] = r
+            types[v] = [int(x) for x in g.typ[int(g.typ_off[v]):int(g.typ_off[v + 1])]]
+
+    def live(v):
+        if v >= len(alive):
+            raise IndexError("vertex %d does not exist" % v)
+        if not alive[v]:
+            raise ValueError("vertex %d is deleted" % v)
+
+    for o in ops:
+        kind = o[0]
+        if kind == "add_v":
+            v = len(alive)
+            alive.append(True)
+            if v in want:
+                rows[v] = {}
+                types[v] = [int(x) for x in o[1]]
+        elif kind == "mod_v":
+            live(o[1])
+            if o[1] in want:
+                types[o[1]] = [int(x) for x in o[2]]
+        elif kind == "del_v":
+            u = o[1]
+            live(u)
+            alive[u] = False
+            if u in want:
+                rows[u] = {}
+                types[u] = []
+        elif kind in ("add_e", "del_e", "mod_e"):
+            u, l, w = o[1], o[2], o[3]
+            live(u)
+            live(w)
+            if u not in want:
+                continue
+            if kind != "add_e":
+                rows[u].pop((l, w), None)
+            if kind != "del_e":
+                ln = o[4] if kind == "mod_e" else l
+                if (ln, w) not in rows[u]:
+                    rows[u][(ln, w)] = 1
+        else:
+            raise ValueError("unknown op " + str(kind))
+    out = {}
+    for v, r in rows.items():
+        out[v] = sorted(e for e, c in r.items() for _ in range(c) if alive[e[1]])
+    return out, {v: sorted(t) for v, t in types.items()}, {v: bool(alive[v]) for v in want if v < len(alive)}

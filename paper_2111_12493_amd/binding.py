@@ -265,6 +265,18 @@ class Result:
             raise BsimError(rc, "result copy of " + field)
         return out[:self._len(field)]
 
+    def fetch_device(self, field: str):
+        """The field copied into a new torch tensor on the current GPU
+        (int64 / int32 views of the unsigned arrays)."""
+        torch = _torch()
+        dt = torch.int64 if self.FIELDS[field] == np.uint64 else torch.int32
+        out = torch.zeros(max(self._len(field), 1), dtype=dt, device="cuda")
+        rc = lib().bsim_result_copy(self.ptr, field.encode(), out.data_ptr(), MEM_DEVICE)
+        if rc != OK:
+            raise BsimError(rc, "result copy of " + field)
+        torch.cuda.synchronize()
+        return out[:self._len(field)]
+
     def to_dict(self) -> Dict:
         d = dict(k_done=self.k_done, fixpoint=self.fixpoint, n_blocks=self.n_blocks,
                  blocks_per_iter=self.blocks_per_iter)

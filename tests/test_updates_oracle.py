@@ -92,3 +92,22 @@ def test_generated_batches_are_valid_and_summaries_match_exact_refinement():
         levels, _, _ = exact_refinement(g2, 4, stop_at_fixpoint=False)
         want = [0xFFFFFFFF if x is None else x for x in levels[-1]]
         assert r["block_ids"].tolist() == want
+
+
+def test_replay_rows_equals_whole_graph_application():
+    # the per-vertex replay used at full size agrees with apply_ops on every
+    # vertex of random graphs and batches (including deletions of targets)
+    from oracle.updates import replay_rows
+
+    rng = np.random.default_rng(41)
+    for trial in range(6):
+        g = gg.uniform_graph(150, 700, 5, 6, seed=trial + 3)
+        d = gg.update_ops(g, rng, 120, n_labels=6, n_types=5)
+        ops = gg.ops_as_tuples(d)
+        full = apply_ops(g, ops)
+        rows, types, alive = replay_rows(g, ops, range(full.n))
+        for v in range(full.n):
+            a, b = int(full.row_off[v]), int(full.row_off[v + 1])
+            assert rows[v] == sorted(zip(full.lab[a:b].tolist(), full.tgt[a:b].tolist())), (trial, v)
+            assert types[v] == sorted(full.types_of(v)), (trial, v)
+            assert alive[v] == bool(full.alive[v]), (trial, v)
