@@ -73,19 +73,21 @@ def percentile(v, q):
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
 
 
-def serving_leg(args, binding, gg, torch, g):
+def serving_leg(args, binding, gg, torch, g, dbase):
     """A burst of fresh summarize requests and update batches for a resident
     state through the server (4 workers, admission by footprint) against the
     plain form: the same requests one at a time through one worker."""
     import numpy as np
 
+    from paper_2111_12493_amd import devgen
+
     rng = np.random.default_rng(29)
     fresh = []
     for i in range(args.serve_requests // 2):
-        m = int(round(10 ** rng.uniform(4, 6)))
+        m = int(round(10 ** rng.uniform(4, np.log10(args.serve_max_edges))))
         n = max(2, m // 8)
-        fresh.append(gg.rmat_graph(int(np.ceil(np.log2(n))), m, n_types=128, n_labels=64, n=n,
-                                   seed=int(rng.integers(1, 1 << 30))))
+        fresh.append(devgen.rmat_device(int(np.ceil(np.log2(n))), m, n_types=128, n_labels=64, n=n,
+                                        seed=int(rng.integers(1, 1 << 30))))
     dead = np.zeros(g.n + 1_000_000, dtype=bool)
     n_v = g.n
     scale = int(np.ceil(np.log2(max(g.n, 2))))
@@ -95,8 +97,7 @@ def serving_leg(args, binding, gg, torch, g):
                                  max(g.n_labels, 1), max(g.n_types, 1), rmat_scale=scale)
         n_v = d["n_after"]
         batches.append(binding.UpdateBatch.from_op_arrays(d))
-    hg = [binding.HostGraph(x) for x in fresh]
-    dbase = binding.DeviceGraph(g)
+    hg = fresh
 
     def run(workers):
         srv = binding.Server(workers=workers)
@@ -129,8 +130,10 @@ def serving_leg(args, binding, gg, torch, g):
     if b_mix != b_one:
         raise RuntimeError("serving results differ between the mix and one-at-a-time runs")
     req = len(b_mix)
-    return {"workload": "%s resident (k=4) + %d fresh R-MAT summaries (10^4-10^6 edges, to fixpoint) + %d update "
-                        "batches (10^3-10^5 ops), submitted as one burst" % (args.inc_workload, len(hg), len(batches)),
+    return {"workload": "%s resident (k=4) + %d fresh R-MAT summaries (10^4-%.0e edges, device-resident, to "
+                        "fixpoint) + %d update batches (10^3-10^5 ops), submitted as one burst"
+                        % (args.inc_workload, len(hg), args.serve_max_edges, len(batches)),
+            "fresh_edges": int(sum(x.m for x in fresh)),
             "requests": req, "workers": 4,
             "p50_ms": s_mix["p50_ms"][0], "p99_ms": s_mix["p99_ms"][0],
             "update_p50_ms": s_mix["p50_ms"][2], "update_p99_ms": s_mix["p99_ms"][2],
@@ -141,7 +144,7 @@ def serving_leg(args, binding, gg, torch, g):
             "plain_form": "same requests, one worker, one at a time (FIFO, no overlap)"}
 
 
-def incremental_leg(args, binding, gg, torch, g):
+def incremental_leg(args, binding, gg, torch, g, dg):
     """Update-batch latency on a resident graph (k = 4): the incremental form
     (frontier re-hash, full levels once a frontier exceeds the limit) beside
     the plain form (every level recomputed for all vertices) on the same
@@ -151,7 +154,6 @@ def incremental_leg(args, binding, gg, torch, g):
     print("# incremental: %s, %d vertices, %d edges" % (args.inc_workload, g.n, g.m), file=sys.stderr, flush=True)
     ctx_i, ctx_p = binding.Context(0), binding.Context(0)
     ctx_p.set_option("frontier_limit_pct", 0)
-    dg = binding.DeviceGraph(g)
     t0 = time.perf_counter()
     st_i = binding.State(ctx_i, dg, 4, stop_at_fixpoint=False, summary_edges=False)
     torch.cuda.synchronize()
@@ -159,7 +161,6 @@ def incremental_leg(args, binding, gg, torch, g):
     st_p = binding.State(ctx_p, dg, 4, stop_at_fixpoint=False, summary_edges=False)
     st_i.result.free()
     st_p.result.free()
-    del dg
     rng = np.random.default_rng(17)
     dead = np.zeros(g.n + 4_000_000, dtype=bool)
     if g.alive is not None:
@@ -202,18 +203,10 @@ def incremental_leg(args, binding, gg, torch, g):
 
 def batched_leg(args, binding, gg, torch):
     """One batched run over many R-MAT graphs against one call per graph."""
-    import numpy as np
+    from paper_2111_12493_amd import devgen
 
-    rng = np.random.default_rng(23)
-    graphs = []
-    for i in range(args.batch_graphs):
-        m = int(round(10 ** rng.uniform(2, np.log10(args.batch_max_edges))))
-        deg = rng.uniform(4, 16)
-        n = max(2, int(round(m / deg)))
-        scale = max(1, int(np.ceil(np.log2(n))))
-        graphs.append(gg.rmat_graph(scale, m, n_types=32, n_labels=32, types_lo=0, types_hi=3, s_types=1.0,
-                                    s_labels=1.0, seed=int(rng.integers(1, 1 << 30)), n=n))
-    dgs = [binding.DeviceGraph(g) for g in graphs]
+    graphs = devgen.batched_device(args.batch_graphs, args.batch_max_edges, seed=23)
+    dgs = graphs
     ctx = binding.Context(0)
     edges = sum(g.m for g in graphs)
     print("# batched: %d graphs, %d edges" % (len(graphs), edges), file=sys.stderr, flush=True)
@@ -259,9 +252,10 @@ def main() -> int:
     ap.add_argument("--inc-max-ops", type=float, default=1e6)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-max-edges", type=float, default=1e7)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batch-graphs", type=int, default=1024)
-    ap.add_argument("--batch-max-edges", type=float, default=1e5)
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-max-edges", type=float, default=1e6)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one elementwise copy kernel over this many MiB, so that a "
                          "rocprofv3 counter run can scale FETCH_SIZE/WRITE_SIZE")
@@ -367,12 +361,20 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_iters)
     del g
     if not (args.no_incremental and args.no_serving):
-        g24 = gg.make_config(args.inc_workload)
+        from paper_2111_12493_amd import devgen
+
+        # the resident graph is drawn on the GPU; the update sampler reads a host copy
+        if args.inc_workload in devgen.DEVICE_CONFIGS:
+            dg24 = devgen.make_device_config(args.inc_workload)
+            g24 = dg24.to_host()
+        else:
+            g24 = gg.make_config(args.inc_workload)
+            dg24 = binding.DeviceGraph(g24)
         if not args.no_incremental:
-            out["incremental"] = incremental_leg(args, binding, gg, torch, g24)
+            out["incremental"] = incremental_leg(args, binding, gg, torch, g24, dg24)
         if not args.no_serving:
-            out["serving"] = serving_leg(args, binding, gg, torch, g24)
-        del g24
+            out["serving"] = serving_leg(args, binding, gg, torch, g24, dg24)
+        del g24, dg24
     if not args.no_batched:
         out["batched"] = batched_leg(args, binding, gg, torch)
     print(json.dumps(out), flush=True)
