@@ -48,6 +48,8 @@ constexpr uint32_t kFrontGrid = 2048;   // blocks of the frontier kernels (grid-
 constexpr uint32_t kMaxStateTypes = 4096;
 
 // Device counters of one update batch.
+constexpr uint32_t kInStripes = 64;     // striped in-degree sums of a level's changed vertices
+
 struct IncCounters {
     uint32_t b_count;      // base frontier list
     uint32_t f_count[2];   // frontier of a level (by parity)
@@ -55,6 +57,12 @@ struct IncCounters {
     uint32_t chunk_count;
     uint32_t pad;
     uint64_t slot_top;     // scratch table slots handed out
+    // sum of the in-degrees of the vertices whose hash changed at a level
+    // (by parity, striped by vertex id): bounds the next level's frontier
+    uint64_t in_sum[2][kInStripes];
+    // sum of the out-degrees of a level's frontier (striped by block): the
+    // edges its re-hash reads
+    uint64_t out_sum[2][kInStripes];
 };
 
 struct BigEntry {
@@ -95,6 +103,20 @@ __device__ __forceinline__ void tag_append(bool valid, uint32_t v, uint32_t tag,
     bool first = false;
     if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) != tag) first = atomicExch(&mark[v], tag) != tag;
     wave_append(first, v, list, count);
+}
+
+// tag_append that also adds the out-degrees of the vertices it lists to a
+// striped counter (one atomic per wave).  All lanes of the wave must call it.
+__device__ __forceinline__ void tag_append_deg(bool valid, uint32_t v, uint32_t tag, uint32_t* mark, uint32_t* list,
+                                               uint32_t* count, const uint32_t* __restrict__ row_off,
+                                               uint64_t* out_sum) {
+    bool first = false;
+    if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) != tag) first = atomicExch(&mark[v], tag) != tag;
+    wave_append(first, v, list, count);
+    const uint64_t d = wave_sum_u64(first ? static_cast<uint64_t>(row_off[v + 1] - row_off[v]) : 0ull);
+    if (lane_id() == 0 && d)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&out_sum[blockIdx.x & (kInStripes - 1)]),
+                  static_cast<unsigned long long>(d));
 }
 
 // t(v) of one vertex from its type list (set semantics), as at level 0 of a run.
@@ -428,16 +450,21 @@ __global__ void k_level_reset(IncCounters* cnt, uint32_t parity) {
         cnt->chunk_count = 0;
         cnt->slot_top = 0;
     }
+    for (uint32_t i = threadIdx.x; i < kInStripes; i += blockDim.x) {
+        cnt->in_sum[parity][i] = 0;
+        cnt->out_sum[parity][i] = 0;
+    }
 }
 
 // F_j starts as the base set B.
 __global__ void k_front_base(const uint32_t* __restrict__ blist, IncCounters* cnt, uint32_t parity, uint32_t tag,
-                             uint32_t* fmark, uint32_t* flist) {
+                             uint32_t* fmark, uint32_t* flist, const uint32_t* __restrict__ row_off) {
     const uint32_t nb = cnt->b_count;
     for (uint32_t i0 = blockIdx.x * kBlock; i0 < nb; i0 += gridDim.x * kBlock) {
         const uint32_t i = i0 + threadIdx.x;
         const bool valid = i < nb;
-        tag_append(valid, valid ? blist[i] : 0u, tag, fmark, flist, &cnt->f_count[parity]);
+        tag_append_deg(valid, valid ? blist[i] : 0u, tag, fmark, flist, &cnt->f_count[parity], row_off,
+                       cnt->out_sum[parity]);
     }
 }
 
@@ -446,7 +473,8 @@ __global__ void k_front_base(const uint32_t* __restrict__ blist, IncCounters* cn
 __global__ void k_front_innbrs(const uint32_t* __restrict__ prev, const uint32_t* prev_count, uint32_t prev_n,
                                const uint32_t* __restrict__ cflag, uint32_t prev_tag,
                                const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
-                               uint32_t tag, uint32_t* fmark, uint32_t* flist, IncCounters* cnt, uint32_t parity) {
+                               uint32_t tag, uint32_t* fmark, uint32_t* flist, IncCounters* cnt, uint32_t parity,
+                               const uint32_t* __restrict__ row_off) {
     const uint32_t np = prev_count ? *prev_count : prev_n;
     const uint32_t lane = lane_id();
     const uint32_t waves = gridDim.x * (kBlock / 64);
@@ -457,7 +485,8 @@ __global__ void k_front_innbrs(const uint32_t* __restrict__ prev, const uint32_t
         for (uint32_t j0 = a; j0 < b; j0 += 64) {
             const uint32_t j = j0 + lane;
             const bool valid = j < b;
-            tag_append(valid, valid ? rev_src[j] : 0u, tag, fmark, flist, &cnt->f_count[parity]);
+            tag_append_deg(valid, valid ? rev_src[j] : 0u, tag, fmark, flist, &cnt->f_count[parity], row_off,
+                           cnt->out_sum[parity]);
         }
     }
 }
@@ -481,13 +510,20 @@ struct FrontArgs {
     uint64_t* big_acc;
     uint32_t* big_done;
     uint64_t* scratch;
+    const uint32_t* rev_off;  // in-neighbour list offsets
+    uint32_t n_rev;
+    uint64_t* in_sum;         // kInStripes counters of this level
 };
 
-// Store h^j(v); a changed value tags v for the next level's frontier.
+// Store h^j(v); a changed value tags v for the next level's frontier and
+// adds its in-degree to the bound on that frontier.
 __device__ __forceinline__ void publish(const FrontArgs& a, uint32_t v, uint64_t h) {
     if (a.h_cur[v] != h) {
         a.h_cur[v] = h;
         a.cflag[v] = a.tag;
+        if (v < a.n_rev)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.in_sum[v & (kInStripes - 1)]),
+                      static_cast<unsigned long long>(a.rev_off[v + 1] - a.rev_off[v]));
     }
 }
 
@@ -691,6 +727,11 @@ struct bsim_state {
     DevBuf<RunStatus> status;
     std::vector<uint8_t> alive_host;
     std::vector<uint32_t> blocks_per_iter;
+    // host scratch of the op resolution, all zero between batches: a
+    // touched vertex's state after the batch so far (1 alive, 2 deleted) and
+    // 1 + the index of its latest type list
+    std::vector<uint8_t> vmark;
+    std::vector<uint32_t> vtype;
 
     void release() {
         for (int i = 0; i < 2; i++) {
@@ -797,120 +838,206 @@ void rebuild_reverse(bsim_state* st, Arena& arena) {
     st->n_rev = n;
 }
 
-HostBatch resolve(const bsim_state* st, const bsim_update* ops, uint64_t n_ops) {
+// Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
+void host_radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int bits) {
+    constexpr int kDigit = 11;
+    constexpr uint32_t kBuckets = 1u << kDigit;
+    const size_t n = key.size();
+    std::vector<uint64_t> k2(n);
+    std::vector<uint32_t> v2(n);
+    std::vector<uint32_t> cnt(kBuckets);
+    for (int sh = 0; sh < bits; sh += kDigit) {
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (size_t i = 0; i < n; i++) cnt[(key[i] >> sh) & (kBuckets - 1)]++;
+        uint32_t run = 0;
+        for (uint32_t& c : cnt) {
+            const uint32_t t = c;
+            c = run;
+            run += t;
+        }
+        for (size_t i = 0; i < n; i++) {
+            const uint32_t p = cnt[(key[i] >> sh) & (kBuckets - 1)]++;
+            k2[p] = key[i];
+            v2[p] = val[i];
+        }
+        key.swap(k2);
+        val.swap(v2);
+    }
+}
+
+// The batch's net effect, by the sequential semantics of the operations:
+// every (u, l, w) the batch touches ends deleted and/or present, every
+// touched vertex ends alive with a type set or deleted.  Per-vertex state
+// lives in flat host arrays of the state (reset for the touched vertices at
+// the end), and the edge records are radix sorted, so a batch of 10^6
+// operations resolves in tens of milliseconds.
+HostBatch resolve(bsim_state* st, const bsim_update* ops, uint64_t n_ops) {
     HostBatch hb;
     uint32_t n_cur = st->n;
-    std::unordered_map<uint32_t, uint8_t> vstate;  // touched vertex -> alive after the batch
-    std::unordered_map<uint32_t, std::vector<uint32_t>> vtypes;
+    std::vector<uint8_t>& vmark = st->vmark;
+    std::vector<uint32_t>& vtype = st->vtype;
+    std::vector<uint32_t> touched;   // vertices with a vertex op, first touch order
+    std::vector<uint32_t> ty_pool;   // type lists of the vertex ops
+    std::vector<std::pair<uint32_t, uint32_t>> ty_rec;  // (offset, count) in ty_pool
+    auto grow = [&](uint32_t need) {
+        if (vmark.size() < need) {
+            vmark.resize(std::max<size_t>(need, vmark.size() + vmark.size() / 4), 0);
+            vtype.resize(vmark.size(), 0);
+        }
+    };
+    grow(n_cur);
     auto alive_now = [&](uint32_t v) -> bool {
-        auto it = vstate.find(v);
-        if (it != vstate.end()) return it->second != 0;
-        return st->alive_host[v] != 0;
+        const uint8_t m = vmark[v];
+        return m ? m == 1 : st->alive_host[v] != 0;
     };
     struct Rec {
-        uint32_t u, w, l, seq, add;
+        uint32_t u, w, l, add;
     };
     std::vector<Rec> recs;
-    recs.reserve(n_ops);
+    recs.reserve(n_ops + n_ops / 8);
     const uint64_t lab_lim = st->label_bytes == 2 ? (1ull << 16) : (1ull << 24);
-    uint32_t seq = 0;
-    auto check_vertex = [&](uint32_t u) {
-        if (u >= n_cur) throw DeviceError{BSIM_E_RANGE, "vertex id out of range in update"};
-        if (!alive_now(u)) throw DeviceError{BSIM_E_INVALID, "update names a deleted vertex"};
+    uint32_t max_l = 0;
+    auto touch = [&](uint32_t v, uint8_t state) {
+        if (!vmark[v]) touched.push_back(v);
+        vmark[v] = state;
     };
-    auto check_types = [&](const bsim_update& o) {
-        if (o.n_types > kMaxStateTypes) throw DeviceError{BSIM_E_UNSUPPORTED, "more than 4096 types on a vertex"};
-        if (o.n_types && !o.types) throw DeviceError{BSIM_E_INVALID, "types pointer is NULL"};
+    auto set_types = [&](uint32_t v, const bsim_update& o) {
+        ty_rec.emplace_back(static_cast<uint32_t>(ty_pool.size()), o.n_types);
+        ty_pool.insert(ty_pool.end(), o.types, o.types + o.n_types);
+        vtype[v] = static_cast<uint32_t>(ty_rec.size());
     };
-    for (uint64_t i = 0; i < n_ops; i++) {
-        const bsim_update& o = ops[i];
-        switch (o.op) {
-            case BSIM_OP_ADD_V: {
-                check_types(o);
-                if (n_cur >= 0xFFFFFFF0u) throw DeviceError{BSIM_E_UNSUPPORTED, "too many vertices"};
-                const uint32_t v = n_cur++;
-                vstate[v] = 1;
-                vtypes[v].assign(o.types, o.types + o.n_types);
-                break;
+    try {
+        for (uint64_t i = 0; i < n_ops; i++) {
+            const bsim_update& o = ops[i];
+            const bool edge = o.op == BSIM_OP_ADD_E || o.op == BSIM_OP_DEL_E || o.op == BSIM_OP_MOD_E;
+            // checks in the order: ids in range, ids alive, types, labels
+            if (o.op == BSIM_OP_MOD_V || o.op == BSIM_OP_DEL_V || edge) {
+                if (o.u >= n_cur || (edge && o.w >= n_cur))
+                    throw DeviceError{BSIM_E_RANGE, "vertex id out of range in update"};
+                if (!alive_now(o.u) || (edge && !alive_now(o.w)))
+                    throw DeviceError{BSIM_E_INVALID, "update names a deleted vertex"};
             }
-            case BSIM_OP_MOD_V:
-                check_vertex(o.u);
-                check_types(o);
-                vstate[o.u] = 1;
-                vtypes[o.u].assign(o.types, o.types + o.n_types);
-                break;
-            case BSIM_OP_DEL_V:
-                check_vertex(o.u);
-                vstate[o.u] = 0;
-                vtypes[o.u].clear();
-                break;
-            case BSIM_OP_ADD_E:
-            case BSIM_OP_DEL_E:
-            case BSIM_OP_MOD_E:
-                if (o.u >= n_cur || o.w >= n_cur) throw DeviceError{BSIM_E_RANGE, "vertex id out of range in update"};
-                check_vertex(o.u);
-                check_vertex(o.w);
-                if (o.label >= lab_lim || (o.op == BSIM_OP_MOD_E && o.new_label >= lab_lim))
-                    throw DeviceError{BSIM_E_RANGE, "edge label out of range in update"};
-                if (o.op == BSIM_OP_ADD_E) {
-                    recs.push_back({o.u, o.w, o.label, seq++, 1});
-                } else {
-                    recs.push_back({o.u, o.w, o.label, seq++, 0});
-                    if (o.op == BSIM_OP_MOD_E) recs.push_back({o.u, o.w, o.new_label, seq++, 1});
+            if (o.op == BSIM_OP_ADD_V || o.op == BSIM_OP_MOD_V) {
+                if (o.n_types > kMaxStateTypes) throw DeviceError{BSIM_E_UNSUPPORTED, "more than 4096 types on a vertex"};
+                if (o.n_types && !o.types) throw DeviceError{BSIM_E_INVALID, "types pointer is NULL"};
+            }
+            switch (o.op) {
+                case BSIM_OP_ADD_V: {
+                    if (n_cur >= 0xFFFFFFF0u) throw DeviceError{BSIM_E_UNSUPPORTED, "too many vertices"};
+                    const uint32_t v = n_cur++;
+                    grow(n_cur);
+                    touch(v, 1);
+                    set_types(v, o);
+                    break;
                 }
-                break;
-            default:
-                throw DeviceError{BSIM_E_INVALID, "unknown update op code"};
+                case BSIM_OP_MOD_V:
+                    touch(o.u, 1);
+                    set_types(o.u, o);
+                    break;
+                case BSIM_OP_DEL_V:
+                    touch(o.u, 2);
+                    vtype[o.u] = 0;
+                    break;
+                case BSIM_OP_ADD_E:
+                case BSIM_OP_DEL_E:
+                case BSIM_OP_MOD_E:
+                    if (o.label >= lab_lim || (o.op == BSIM_OP_MOD_E && o.new_label >= lab_lim))
+                        throw DeviceError{BSIM_E_RANGE, "edge label out of range in update"};
+                    if (o.op == BSIM_OP_ADD_E) {
+                        recs.push_back({o.u, o.w, o.label, 1});
+                        max_l = std::max(max_l, o.label);
+                    } else {
+                        recs.push_back({o.u, o.w, o.label, 0});
+                        max_l = std::max(max_l, o.label);
+                        if (o.op == BSIM_OP_MOD_E) {
+                            recs.push_back({o.u, o.w, o.new_label, 1});
+                            max_l = std::max(max_l, o.new_label);
+                        }
+                    }
+                    break;
+                default:
+                    throw DeviceError{BSIM_E_INVALID, "unknown update op code"};
+            }
         }
+    } catch (...) {
+        for (uint32_t v : touched) vmark[v] = 0, vtype[v] = 0;
+        throw;
     }
     hb.n_new = n_cur;
-    for (auto& kv : vstate) {
-        hb.tl.push_back(kv.first);
-        if (!kv.second) hb.dead.push_back(kv.first);
-    }
+    hb.tl = touched;
     std::sort(hb.tl.begin(), hb.tl.end());
-    std::sort(hb.dead.begin(), hb.dead.end());
+    hb.tl_off.reserve(hb.tl.size() + 1);
     hb.tl_off.push_back(0);
     for (uint32_t v : hb.tl) {
-        if (vstate[v]) {
-            const auto& ty = vtypes[v];
-            hb.tl_ids.insert(hb.tl_ids.end(), ty.begin(), ty.end());
+        if (vmark[v] == 2) {
+            hb.dead.push_back(v);
+        } else if (vtype[v]) {
+            const auto& r = ty_rec[vtype[v] - 1];
+            hb.tl_ids.insert(hb.tl_ids.end(), ty_pool.begin() + r.first, ty_pool.begin() + r.first + r.second);
         }
         hb.tl_off.push_back(static_cast<uint32_t>(hb.tl_ids.size()));
     }
-    std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
-        if (a.u != b.u) return a.u < b.u;
-        if (a.w != b.w) return a.w < b.w;
-        if (a.l != b.l) return a.l < b.l;
-        return a.seq < b.seq;
-    });
-    auto dead_at_end = [&](uint32_t v) {
-        auto it = vstate.find(v);
-        return it != vstate.end() && it->second == 0;
+    auto dead_at_end = [&](uint32_t v) { return vmark[v] == 2; };
+    // edge records in (u, w, l) order, input order within equal triples:
+    // the triple packed in one key when it fits 64 bits (the add flag rides
+    // in the value), else a comparison sort
+    const int bv = std::max(1, bit_width(n_cur)), bl = std::max(1, bit_width(max_l + 1));
+    const size_t nr = recs.size();
+    std::vector<uint64_t> key;
+    std::vector<uint32_t> val(nr);
+    auto emit = [&](uint32_t u, uint32_t w, uint32_t l, bool deleted, bool add) {
+        if (dead_at_end(u) || dead_at_end(w)) return;
+        hb.cu.push_back(u);
+        hb.cw.push_back(w);
+        hb.cl.push_back(l);
+        hb.cf.push_back((deleted ? kChgDeleted : 0u) | (add ? kChgPresent : 0u));
+        if (add) {
+            hb.n_present++;
+            hb.max_label = std::max(hb.max_label, l);
+            hb.rw.push_back(w);
+            hb.ru.push_back(u);
+        }
     };
-    for (size_t i = 0; i < recs.size();) {
-        size_t j = i;
-        uint32_t deleted = 0;
-        while (j < recs.size() && recs[j].u == recs[i].u && recs[j].w == recs[i].w && recs[j].l == recs[i].l) {
-            if (!recs[j].add) deleted = 1;
-            j++;
+    hb.cu.reserve(nr);
+    hb.cw.reserve(nr);
+    hb.cl.reserve(nr);
+    hb.cf.reserve(nr);
+    if (2 * bv + bl <= 64) {
+        key.resize(nr);
+        for (size_t i = 0; i < nr; i++) {
+            key[i] = (static_cast<uint64_t>(recs[i].u) << (bv + bl)) | (static_cast<uint64_t>(recs[i].w) << bl) |
+                     recs[i].l;
+            val[i] = recs[i].add;
         }
-        const Rec& last = recs[j - 1];
-        if (!dead_at_end(last.u) && !dead_at_end(last.w)) {
-            const uint32_t f = (deleted ? kChgDeleted : 0u) | (last.add ? kChgPresent : 0u);
-            hb.cu.push_back(last.u);
-            hb.cw.push_back(last.w);
-            hb.cl.push_back(last.l);
-            hb.cf.push_back(f);
-            if (last.add) {
-                hb.n_present++;
-                hb.max_label = std::max(hb.max_label, last.l);
-                hb.rw.push_back(last.w);
-                hb.ru.push_back(last.u);
-            }
+        host_radix_sort(key, val, 2 * bv + bl);
+        const uint64_t lmask = (1ull << bl) - 1, wmask = (1ull << bv) - 1;
+        for (size_t i = 0; i < nr;) {
+            size_t j = i;
+            bool deleted = false;
+            while (j < nr && key[j] == key[i]) deleted |= val[j++] == 0;
+            emit(static_cast<uint32_t>(key[i] >> (bv + bl)), static_cast<uint32_t>((key[i] >> bl) & wmask),
+                 static_cast<uint32_t>(key[i] & lmask), deleted, val[j - 1] != 0);
+            i = j;
         }
-        i = j;
+    } else {
+        for (size_t i = 0; i < nr; i++) val[i] = static_cast<uint32_t>(i);
+        std::stable_sort(val.begin(), val.end(), [&](uint32_t a, uint32_t b) {
+            const Rec &x = recs[a], &y = recs[b];
+            if (x.u != y.u) return x.u < y.u;
+            if (x.w != y.w) return x.w < y.w;
+            return x.l < y.l;
+        });
+        for (size_t i = 0; i < nr;) {
+            const Rec& first = recs[val[i]];
+            size_t j = i;
+            bool deleted = false;
+            while (j < nr && recs[val[j]].u == first.u && recs[val[j]].w == first.w && recs[val[j]].l == first.l)
+                deleted |= recs[val[j++]].add == 0;
+            emit(first.u, first.w, first.l, deleted, recs[val[j - 1]].add != 0);
+            i = j;
+        }
     }
+    for (uint32_t v : touched) vmark[v] = 0, vtype[v] = 0;
     for (size_t i = 0; i < hb.cu.size();) {
         size_t j = i;
         while (j < hb.cu.size() && hb.cu[j] == hb.cu[i]) j++;
@@ -921,14 +1048,16 @@ HostBatch resolve(const bsim_state* st, const bsim_update* ops, uint64_t n_ops) 
     }
     // reverse additions, grouped by target (duplicate pairs are harmless)
     std::vector<uint64_t> rk(hb.rw.size());
-    for (size_t i = 0; i < rk.size(); i++) rk[i] = (static_cast<uint64_t>(hb.rw[i]) << 32) | hb.ru[i];
-    std::sort(rk.begin(), rk.end());
+    std::vector<uint32_t> rdummy(hb.rw.size(), 0);
+    for (size_t i = 0; i < rk.size(); i++) rk[i] = (static_cast<uint64_t>(hb.rw[i]) << bv) | hb.ru[i];
+    host_radix_sort(rk, rdummy, 2 * bv);
     rk.erase(std::unique(rk.begin(), rk.end()), rk.end());
     hb.rw.resize(rk.size());
     hb.ru.resize(rk.size());
+    const uint64_t umask = (1ull << bv) - 1;
     for (size_t i = 0; i < rk.size(); i++) {
-        hb.rw[i] = static_cast<uint32_t>(rk[i] >> 32);
-        hb.ru[i] = static_cast<uint32_t>(rk[i]);
+        hb.rw[i] = static_cast<uint32_t>(rk[i] >> bv);
+        hb.ru[i] = static_cast<uint32_t>(rk[i] & umask);
     }
     for (size_t i = 0; i < hb.rw.size();) {
         size_t j = i;
@@ -1105,6 +1234,7 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
     hipStream_t s = st->s;
     const uint32_t n = st->n;
     const uint64_t limit = static_cast<uint64_t>(n) * st->ctx->frontier_limit_pct / 100;
+    const uint64_t edge_limit = static_cast<uint64_t>(st->m) * 3 * st->ctx->frontier_limit_pct / 100 + 4096;
     if (st->ctx->frontier_limit_pct == 0) {
         if (st->K >= 1) full_levels(st, 1, arena);
         return;
@@ -1117,20 +1247,47 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
     for (uint32_t j = 1; j <= st->K; j++) {
         const uint32_t par = j & 1;
         const uint32_t tag = tag0 + j;
+        if (j >= 2 && st->ctx->frontier_limit_pct < 100) {
+            // F_j holds at most B plus the in-neighbours of C_{j-1}: when that
+            // bound is far past the limit (a changed hub), the expansion would
+            // only confirm that the level goes to the full kernels
+            uint64_t in_sum[kInStripes];
+            uint32_t nb = 0;
+            hip_check(hipMemcpyAsync(in_sum, st->cnt.p->in_sum[par ^ 1], sizeof(in_sum), hipMemcpyDeviceToHost, s),
+                      "frontier bound");
+            hip_check(hipMemcpyAsync(&nb, &st->cnt.p->b_count, 4, hipMemcpyDeviceToHost, s), "base count");
+            hip_check(hipStreamSynchronize(s), "frontier bound sync");
+            uint64_t bound = nb;
+            for (uint32_t i = 0; i < kInStripes; i++) bound += in_sum[i];
+            if (bound > 4 * limit + 1024) {
+                full_levels(st, j, arena);
+                return;
+            }
+        }
         k_level_reset<<<1, 64, 0, s>>>(st->cnt.p, par);
-        k_front_base<<<256, kBlock, 0, s>>>(st->blist.p, st->cnt.p, par, tag, st->fmark.p, st->flist[par].p);
+        const uint32_t* row_off = st->row_off[st->cur].p;
+        k_front_base<<<256, kBlock, 0, s>>>(st->blist.p, st->cnt.p, par, tag, st->fmark.p, st->flist[par].p,
+                                            row_off);
         if (j == 1)
             k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(d_tl, nullptr, nT, st->cflag.p, tag0, st->rev_off[st->rcur].p,
                                                          st->rev_src[st->rcur].p, tag, st->fmark.p, st->flist[par].p,
-                                                         st->cnt.p, par);
+                                                         st->cnt.p, par, row_off);
         else
             k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(st->flist[par ^ 1].p, &st->cnt.p->f_count[par ^ 1], 0,
                                                          st->cflag.p, tag - 1, st->rev_off[st->rcur].p,
                                                          st->rev_src[st->rcur].p, tag, st->fmark.p, st->flist[par].p,
-                                                         st->cnt.p, par);
+                                                         st->cnt.p, par, row_off);
         hip_check(hipGetLastError(), "frontier marks");
-        fcount = read_u32(&st->cnt.p->f_count[par], s);
-        if (fcount > limit) {
+        uint64_t out_sum[kInStripes];
+        hip_check(hipMemcpyAsync(&fcount, &st->cnt.p->f_count[par], 4, hipMemcpyDeviceToHost, s), "frontier count");
+        hip_check(hipMemcpyAsync(out_sum, st->cnt.p->out_sum[par], sizeof(out_sum), hipMemcpyDeviceToHost, s),
+                  "frontier edges");
+        hip_check(hipStreamSynchronize(s), "frontier sync");
+        uint64_t fedges = 0;
+        for (uint32_t i = 0; i < kInStripes; i++) fedges += out_sum[i];
+        // the frontier kernels read an edge several times slower than the
+        // full-level kernels: past 3 x pct % of the edges, a full level is cheaper
+        if (fcount > limit || fedges > edge_limit) {
             full_levels(st, j, arena);
             return;
         }
@@ -1153,6 +1310,9 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
         a.big_acc = st->big_acc.p;
         a.big_done = st->big_done.p;
         a.scratch = st->scratch.p;
+        a.rev_off = st->rev_off[st->rcur].p;
+        a.n_rev = st->n_rev;
+        a.in_sum = st->cnt.p->in_sum[par];
         const uint32_t grid = std::max<uint32_t>(std::min<uint32_t>(ceil_div(fcount, kBlock / 64), kFrontGrid), 1);
         if (lb == 2) k_front_hash<uint16_t><<<grid, kBlock, 0, s>>>(a);
         else k_front_hash<uint32_t><<<grid, kBlock, 0, s>>>(a);
@@ -1384,6 +1544,10 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     hip_check(hipGetLastError(), "state copy");
     st->alive_host.resize(n);
     if (n) hip_check(hipMemcpyAsync(st->alive_host.data(), st->alive.p, n, hipMemcpyDeviceToHost, s), "alive");
+    // the op resolution's per-vertex scratch, sized once here (not in the
+    // first batch's latency)
+    st->vmark.assign(static_cast<size_t>(n) + n / 8 + 1024, 0);
+    st->vtype.assign(st->vmark.size(), 0);
     ensure_salt(st, st->max_label);
     rebuild_reverse(st, arena);
     tm.mark(1);
