@@ -61,7 +61,11 @@ __device__ uint64_t split_join(const SplitTable& T, uint32_t r, uint64_t key, ui
         *slot_out = 0xFFFFFFFFu;
         return mine;
     }
-    uint32_t slot = static_cast<uint32_t>(key) & T.mask;
+    // the home slot depends on the class r as well as the key: isomorphic
+    // vertices of different classes (every batched graph has vertices with
+    // the same type set) share keys, and must not share one probe chain
+    uint32_t slot = (static_cast<uint32_t>(key) ^
+                     static_cast<uint32_t>((static_cast<uint64_t>(r) * 0x9E3779B97F4A7C15ull) >> 32)) & T.mask;
     for (;;) {
         SplitSlot* p = &T.slots[slot];
         uint64_t cur = p->key;
