@@ -1239,8 +1239,6 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
         if (st->K >= 1) full_levels(st, 1, arena);
         return;
     }
-    // every table slot of a deferred vertex: next_pow2(2 deg) <= 4 deg
-    st->scratch.ensure(4 * std::max<uint64_t>(st->m, 16), 0, s);
     st->chunk_owner.ensure(static_cast<size_t>(n) + st->m / kChunkEdges + 2, 0, s);
     const int lb = st->label_bytes;
     uint32_t fcount = 0;
@@ -1291,6 +1289,9 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
             full_levels(st, j, arena);
             return;
         }
+        // the table slots of the deferred (large) frontier vertices:
+        // next_pow2(2 deg) <= 4 deg each, so 4 x the frontier's edges
+        st->scratch.ensure(4 * fedges + 1024, 0, s);
         FrontArgs a;
         a.row_off = st->row_off[st->cur].p;
         a.tgt = st->tgt[st->cur].p;
@@ -1548,6 +1549,9 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     // first batch's latency)
     st->vmark.assign(static_cast<size_t>(n) + n / 8 + 1024, 0);
     st->vtype.assign(st->vmark.size(), 0);
+    // the frontier scratch up to the frontier edge limit (4 slots per edge),
+    // allocated here rather than in an update's latency
+    st->scratch.ensure(4 * (static_cast<uint64_t>(st->m) * 3 * ctx->frontier_limit_pct / 100 + 4096) + 1024, 0, s);
     ensure_salt(st, st->max_label);
     rebuild_reverse(st, arena);
     tm.mark(1);

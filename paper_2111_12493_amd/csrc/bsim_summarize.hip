@@ -87,7 +87,9 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     // launch k tests level k-2, so launch k_max + 2 always sees the cap
     const uint64_t k_last = static_cast<uint64_t>(p.k_max) + 2;
     uint64_t k = 1;
-    uint32_t chunk = 4;
+    // a batched run covers many small graphs that stop within a few levels,
+    // and its launches are large: start with shorter chunks
+    uint32_t chunk = rb.bc.gid ? 2u : 4u;
     int pending = -1;
     hipEvent_t ev[2];
     hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
