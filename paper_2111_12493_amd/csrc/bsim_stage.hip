@@ -215,12 +215,14 @@ __global__ void __launch_bounds__(kBlock) k_compact_flags(const uint32_t* __rest
 }
 
 // Greedy tile packing within windows of kPackWindow consecutive entries of
-// the tile-vertex list (one thread per window): a tile grows until the next
+// the tile-vertex list (one wave per window): a tile grows until the next
 // vertex would bring it to kTileMaxEdges edges or kTileMaxVerts vertices, or
-// its edges would not follow the tile's (a hub lies between).  With
-// emit == false only the tile count per window is written (to cnt[w]); with
-// emit == true tiles are written from pos[w] on.
+// its edges would not follow the tile's (a hub lies between).  The wave
+// loads the window's edge ranges together into LDS, then one lane runs the
+// greedy scan over them.  With emit == false only the tile count per window
+// is written (to cnt[w]); with emit == true tiles are written from pos[w] on.
 constexpr uint32_t kPackWindow = 1024;
+constexpr uint32_t kPackWaves = kBlock / 64;
 
 __global__ void __launch_bounds__(kBlock) k_pack_tiles(const uint32_t* __restrict__ row_off,
                                                        const uint32_t* __restrict__ act, uint32_t n_act,
@@ -228,16 +230,29 @@ __global__ void __launch_bounds__(kBlock) k_pack_tiles(const uint32_t* __restric
                                                        const uint32_t* __restrict__ pos,
                                                        uint32_t* __restrict__ i0, uint32_t* __restrict__ i1,
                                                        uint32_t* __restrict__ e0, uint32_t* __restrict__ e1) {
-    const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ uint32_t s_a[kPackWaves][kPackWindow];
+    __shared__ uint32_t s_b[kPackWaves][kPackWindow];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t w = blockIdx.x * kPackWaves + wv;
     const uint64_t ib64 = static_cast<uint64_t>(w) * kPackWindow;
-    if (ib64 >= n_act) return;
+    if (ib64 >= n_act) return;  // whole waves only: no block barrier below
     const uint32_t ib = static_cast<uint32_t>(ib64);
     const uint32_t ie = static_cast<uint32_t>(min<uint64_t>(n_act, ib64 + kPackWindow));
+    for (uint32_t i = ib + lane; i < ie; i += 64) {
+        const uint32_t v = act[i];
+        s_a[wv][i - ib] = row_off[v];
+        s_b[wv][i - ib] = row_off[v + 1];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane != 0) return;
+    const uint32_t* A = s_a[wv];
+    const uint32_t* B = s_b[wv];
     uint32_t out = emit ? pos[w] : 0, made = 0;
     uint32_t start = ib, edges = 0, verts = 0, ebeg = 0, eend = 0;
     for (uint32_t i = ib; i < ie; i++) {
-        const uint32_t v = act[i];
-        const uint32_t a = row_off[v], b = row_off[v + 1];
+        const uint32_t a = A[i - ib], b = B[i - ib];
         const uint32_t d = b - a;
         if (verts && (a != eend || verts == static_cast<uint32_t>(kTileMaxVerts) ||
                       edges + d >= static_cast<uint32_t>(kTileMaxEdges))) {
@@ -354,7 +369,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
     const uint32_t nwin = ceil_div(g.n_act, kPackWindow);
     uint32_t* wcnt = arena.alloc<uint32_t>(nwin + 1);
     uint32_t* wpos = arena.alloc<uint32_t>(nwin + 1);
-    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, g.act, g.n_act, false, wcnt,
+    if (nwin) k_pack_tiles<<<ceil_div(nwin, kPackWaves), kBlock, 0, s>>>(g.row_off, g.act, g.n_act, false, wcnt,
                                                                       nullptr, nullptr, nullptr, nullptr,
                                                                       nullptr);
     scan_exclusive(wcnt, wpos, nwin, counts + 2, arena, s);
@@ -366,7 +381,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
     g.tile_i1 = arena.alloc<uint32_t>(ntiles + 1);
     g.tile_e0 = arena.alloc<uint32_t>(ntiles + 1);
     g.tile_e1 = arena.alloc<uint32_t>(ntiles + 1);
-    if (nwin) k_pack_tiles<<<ceil_div(nwin, kBlock), kBlock, 0, s>>>(g.row_off, g.act, g.n_act, true, nullptr,
+    if (nwin) k_pack_tiles<<<ceil_div(nwin, kPackWaves), kBlock, 0, s>>>(g.row_off, g.act, g.n_act, true, nullptr,
                                                                       wpos, g.tile_i0, g.tile_i1, g.tile_e0,
                                                                       g.tile_e1);
     hip_check(hipGetLastError(), "tile packing");
