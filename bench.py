@@ -144,14 +144,15 @@ def serving_leg(args, binding, gg, torch, g, dbase):
             "plain_form": "same requests, one worker, one at a time (FIFO, no overlap)"}
 
 
-def incremental_leg(args, binding, gg, torch, g, dg):
+def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoints=True):
     """Update-batch latency on a resident graph (k = 4): the incremental form
     (frontier re-hash, full levels once a frontier exceeds the limit) beside
     the plain form (every level recomputed for all vertices) on the same
     batches, each on its own copy of the state."""
     import numpy as np
 
-    print("# incremental: %s, %d vertices, %d edges" % (args.inc_workload, g.n, g.m), file=sys.stderr, flush=True)
+    workload = workload or args.inc_workload
+    print("# incremental: %s, %d vertices, %d edges" % (workload, g.n, g.m), file=sys.stderr, flush=True)
     ctx_i, ctx_p = binding.Context(0), binding.Context(0)
     ctx_p.set_option("frontier_limit_pct", 0)
     t0 = time.perf_counter()
@@ -171,7 +172,7 @@ def incremental_leg(args, binding, gg, torch, g, dg):
     for i in range(args.inc_batches):
         size = int(round(10 ** rng.uniform(3, np.log10(args.inc_max_ops))))
         d = gg.sample_update_ops(g.row_off, g.tgt, g.lab, n, dead, rng, size, max(g.n_labels, 1),
-                                 max(g.n_types, 1), rmat_scale=scale)
+                                 max(g.n_types, 1), rmat_scale=scale if rmat_endpoints else None)
         n = d["n_after"]
         batch = binding.UpdateBatch.from_op_arrays(d)
         nb = []
@@ -194,7 +195,8 @@ def incremental_leg(args, binding, gg, torch, g, dg):
     p50, p99 = percentile(lat_i, 0.5), percentile(lat_i, 0.99)
     q50, q99 = percentile(lat_p, 0.5), percentile(lat_p, 0.99)
     return {"workload": "%s resident, k=4, update batches of log-uniform 10^3-%.0e ops (ADD/MOD/DEL 60/25/15, "
-                        "R-MAT endpoints for new edges)" % (args.inc_workload, args.inc_max_ops),
+                        "%s endpoints for new edges)" % (workload, args.inc_max_ops,
+                                                         "R-MAT" if rmat_endpoints else "uniform"),
             "batches": len(lat_i), "ops": ops_total, "p50_ms": p50, "p99_ms": p99,
             "plain_p50_ms": q50, "plain_p99_ms": q99, "speedup_p50": q50 / p50, "speedup_p99": q99 / p99,
             "state_create_s": create_s, "summary_edges": False,
@@ -249,6 +251,8 @@ def main() -> int:
     ap.add_argument("--no-incremental", action="store_true")
     ap.add_argument("--inc-workload", default="rmat24")
     ap.add_argument("--inc-batches", type=int, default=16)
+    ap.add_argument("--inc-uniform", default="uniform24",
+                    help="second incremental workload (a uniform graph); empty to skip")
     ap.add_argument("--inc-max-ops", type=float, default=1e6)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=32)
@@ -375,6 +379,15 @@ def main() -> int:
         if not args.no_serving:
             out["serving"] = serving_leg(args, binding, gg, torch, g24, dg24)
         del g24, dg24
+    if not args.no_incremental and args.inc_uniform:
+        from paper_2111_12493_amd import devgen
+
+        # the same batches on a graph without hubs, where a change stays local
+        dgu = devgen.make_device_config(args.inc_uniform)
+        gu = dgu.to_host()
+        out["incremental_uniform"] = incremental_leg(args, binding, gg, torch, gu, dgu, workload=args.inc_uniform,
+                                                     rmat_endpoints=False)
+        del gu, dgu
     if not args.no_batched:
         out["batched"] = batched_leg(args, binding, gg, torch)
     print(json.dumps(out), flush=True)

@@ -1552,6 +1552,15 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     // the frontier scratch up to the frontier edge limit (4 slots per edge),
     // allocated here rather than in an update's latency
     st->scratch.ensure(4 * (static_cast<uint64_t>(st->m) * 3 * ctx->frontier_limit_pct / 100 + 4096) + 1024, 0, s);
+    // reserve the stream-ordered pool for an update's temporary arrays
+    // (the full-level staging takes about 32 B per edge and 64 B per
+    // vertex): allocated and freed once here, the memory stays cached, so a
+    // later update rarely maps new memory inside its latency
+    {
+        void* warm = nullptr;
+        const size_t bytes = 32 * static_cast<size_t>(st->m) + 64 * static_cast<size_t>(n) + (64u << 20);
+        if (hipMallocAsync(&warm, bytes, s) == hipSuccess) (void)hipFreeAsync(warm, s);
+    }
     ensure_salt(st, st->max_label);
     rebuild_reverse(st, arena);
     tm.mark(1);

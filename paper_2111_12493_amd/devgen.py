@@ -217,6 +217,34 @@ def rmat_device(scale: int, m: int, n_types: int, n_labels: int, types_lo: int =
 
 
 # Full-size named recipes (the host ``graphgen.CONFIGS`` hold the others).
+def uniform_device(n: int, m: int, n_types: int, n_labels: int, types_lo: int = 1, types_hi: int = 3,
+                   s_types: float = 1.0, s_labels: float = 1.0, seed: int = 1, label_u16: bool = False,
+                   device: str = "cuda") -> DeviceCSR:
+    """Uniform random directed graph built on the GPU: endpoints i.i.d.
+    uniform, a self loop's target moved to the next vertex."""
+    torch = _torch()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    if m >= 1 << 31 or n >= 1 << 31 or n < 2:
+        raise ValueError("int32 offsets: at most 2^31 - 1 edges and vertices, at least 2 vertices")
+    src = torch.randint(0, n, (m,), generator=gen, device=device, dtype=torch.int64)
+    dst = torch.randint(0, n, (m,), generator=gen, device=device, dtype=torch.int64)
+    dst = torch.where(dst == src, (dst + 1) % n, dst)
+    order = torch.sort(src, stable=True).indices
+    tgt = dst[order].to(torch.int32)
+    del dst
+    counts = torch.bincount(src, minlength=n)
+    del src, order
+    row_off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(counts, 0, out=row_off[1:])
+    lab = _zipf(gen, n_labels, s_labels, max(m, 1), device)
+    lab = lab.to(torch.int16) if label_u16 else lab
+    toff, typ = _type_lists(gen, n, n_types, s_types, types_lo, types_hi, device)
+    return DeviceCSR(n=n, m=m, row_off=row_off.to(torch.int32), tgt=tgt, lab=lab,
+                     type_off=toff.to(torch.int32), typ=typ, label_bytes=2 if label_u16 else 4,
+                     n_labels=n_labels, n_types=n_types)
+
+
 def batched_recipe(count: int, max_edges: float, seed: int):
     """(m, n, scale, seed) of each graph of the batched workload: edges
     log-uniform in [10^2, max_edges], average degree uniform in [4, 16]."""
@@ -245,6 +273,11 @@ DEVICE_CONFIGS = {
     # base graph of the incremental / serving workload).
     "rmat24": dict(scale=24, m=1 << 27, n_types=128, n_labels=64, types_lo=0, types_hi=4,
                    s_types=1.1, s_labels=1.1, seed=5),
+    # Uniform random graph of the same size (2^24 vertices, 2^27 edges, 128
+    # types, 64 labels): without hubs, an update's change reaches few
+    # vertices per level, the case incremental maintenance is made for.
+    "uniform24": dict(kind="uniform", n=1 << 24, m=1 << 27, n_types=128, n_labels=64, types_lo=0, types_hi=4,
+                      s_types=1.1, s_labels=1.1, seed=6),
 }
 
 
@@ -252,4 +285,6 @@ def make_device_config(name: str, seed: Optional[int] = None, device: str = "cud
     cfg = dict(DEVICE_CONFIGS[name])
     if seed is not None:
         cfg["seed"] = seed
+    if cfg.pop("kind", "rmat") == "uniform":
+        return uniform_device(device=device, **cfg)
     return rmat_device(device=device, **cfg)
