@@ -265,8 +265,8 @@ def main() -> int:
                          "rocprofv3 counter run can scale FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (see DESIGN.md for how "
-              "the refinement would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         return 2
 
     import torch

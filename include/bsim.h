@@ -48,7 +48,7 @@ extern "C" {
 #define BSIM_E_RANGE (-2)       /* an id or label out of its range */
 #define BSIM_E_NOMEM (-3)       /* device or host allocation failed */
 #define BSIM_E_DEVICE (-4)      /* a HIP runtime error; text in bsim_last_error */
-#define BSIM_E_UNSUPPORTED (-5) /* valid input outside this build's limits */
+#define BSIM_E_UNSUPPORTED (-5) /* valid input outside this library's limits */
 #define BSIM_E_BUSY (-6)        /* server: request does not fit the memory budget now */
 
 /* ---- where an array lives ---------------------------------------------- */
@@ -69,7 +69,7 @@ typedef struct bsim_state bsim_state;
  * A labeled directed graph in CSR form (Sec. 2.2 labeled property graphs:
  * each vertex has a set of type ids, each edge one label).
  *   row_off[n_vertices+1]  out-edge offsets, row_off[0] = 0, monotone,
- *                          row_off[n] = n_edges (< 2^32 in this build)
+ *                          row_off[n] = n_edges (< 2^32 in this library)
  *   targets[n_edges]       edge target vertex, < n_vertices
  *   labels[n_edges]        edge label, uint16 (label_bytes 2) or uint32 (4)
  *   type_off[n_vertices+1] offsets into type_ids (monotone)

@@ -1087,7 +1087,7 @@ void merge_edges(bsim_state* st, const HostBatch& hb, uint32_t n_old, Arena& are
     const uint32_t nc = static_cast<uint32_t>(hb.cu.size());
     const int c = st->cur;
     const uint64_t m_cap = static_cast<uint64_t>(m_old) + hb.n_present;
-    if (m_cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "this build supports fewer than 2^32 edges"};
+    if (m_cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "this library supports fewer than 2^32 edges"};
     st->src[c ^ 1].ensure(m_cap + 1, 0, s);
     st->tgt[c ^ 1].ensure(m_cap + 1, 0, s);
     st->lab[c ^ 1].ensure((m_cap + 1) * sizeof(LabT), 0, s);

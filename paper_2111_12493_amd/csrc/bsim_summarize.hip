@@ -20,7 +20,7 @@ void validate_params(const bsim_graph& graph, const bsim_params& p) {
     if (graph.mem_kind != BSIM_MEM_HOST && graph.mem_kind != BSIM_MEM_DEVICE)
         throw DeviceError{BSIM_E_INVALID, "unknown mem_kind"};
     if (graph.n_edges >= (1ull << 32))
-        throw DeviceError{BSIM_E_UNSUPPORTED, "this build supports fewer than 2^32 edges"};
+        throw DeviceError{BSIM_E_UNSUPPORTED, "this library supports fewer than 2^32 edges"};
     if (graph.n_vertices >= 0xFFFFFFFFu)
         throw DeviceError{BSIM_E_UNSUPPORTED, "too many vertices"};
     if (!graph.row_off || !graph.type_off)
