@@ -656,7 +656,8 @@ struct DevBuf {
     size_t cap = 0;
     void ensure(size_t n, size_t keep, hipStream_t s) {
         if (p && n <= cap) return;
-        const size_t nc = std::max<size_t>({n, cap + cap / 2, 64});
+        // headroom, so that the small growth of most batches allocates nothing
+        const size_t nc = std::max<size_t>({n + n / 8, cap + cap / 2, 64});
         T* q = nullptr;
         if (hipMallocAsync(reinterpret_cast<void**>(&q), nc * sizeof(T), s) != hipSuccess)
             throw DeviceError{BSIM_E_NOMEM, "state allocation of " + std::to_string(nc * sizeof(T)) + " bytes failed"};
@@ -732,8 +733,20 @@ struct bsim_state {
     // 1 + the index of its latest type list
     std::vector<uint8_t> vmark;
     std::vector<uint32_t> vtype;
+    // the class passes of the stored levels run on a second stream, each
+    // after an event that follows the launches writing its level
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_level = nullptr, ev_classes = nullptr;
+    uint32_t cls_next = 0;  // the next level whose class pass is due
+    // backing of an update's temporary arrays, grown to the largest demand
+    // seen: large temporaries then never pass through the stream-ordered
+    // pool, which can return freed memory to the driver (tens of ms) and map
+    // it again in a later update
+    DevBuf<uint8_t> work;
+    size_t work_want = 0;
 
     void release() {
+        if (s2) (void)hipStreamSynchronize(s2);
         for (int i = 0; i < 2; i++) {
             row_off[i].release(s), src[i].release(s), tgt[i].release(s), lab[i].release(s);
             type_off[i].release(s), type_own[i].release(s), type_ids[i].release(s);
@@ -746,12 +759,16 @@ struct bsim_state {
         chg_lo.release(s), chg_hi.release(s), tidx.release(s), kept.release(s), deg.release(s);
         blist.release(s), cls_cnt.release(s), kpos.release(s), chunk_owner.release(s);
         big_done.release(s), big.release(s), big_acc.release(s), scratch.release(s), cnt.release(s);
-        status.release(s);
+        status.release(s), work.release(s);
         if (cls_slots) (void)hipFreeAsync(cls_slots, s);
         if (cls_zero) (void)hipFreeAsync(cls_zero, s);
         if (cls_list) (void)hipFreeAsync(cls_list, s);
         cls_slots = nullptr, cls_zero = nullptr, cls_list = nullptr;
         (void)hipStreamSynchronize(s);
+        if (ev_level) (void)hipEventDestroy(ev_level);
+        if (ev_classes) (void)hipEventDestroy(ev_classes);
+        if (s2) (void)hipStreamDestroy(s2);
+        ev_level = nullptr, ev_classes = nullptr, s2 = nullptr;
     }
 };
 
@@ -1202,6 +1219,59 @@ void merge_reverse(bsim_state* st, const HostBatch& hb, Arena& arena) {
     st->n_rev = n_new;
 }
 
+// The class passes of an update, level by level as the levels become final.
+// Level j's pass (its split of the level j-1 classes by h^j, into st->rep)
+// runs on the second stream once the launches that write h^j, enqueued on
+// the state's stream before the call, are done; so it overlaps the launches
+// of the levels after it.  classes_end joins the streams and returns the
+// founded count per level.
+void classes_begin(bsim_state* st) {
+    st->cls_cnt.ensure(2ull * (st->K + 1), 0, st->s);
+    hip_check(hipMemsetAsync(st->cls_cnt.p, 0, 8ull * (st->K + 1), st->s), "class counts");
+    st->cls_next = 0;
+}
+
+SplitTable class_table(const bsim_state* st) {
+    SplitTable T;
+    T.slots = st->cls_slots;
+    T.zero = st->cls_zero;
+    T.list = st->cls_list;
+    T.mask = st->cls_cap - 1;
+    return T;
+}
+
+void classes_level(bsim_state* st, uint32_t j) {
+    if (j != st->cls_next || j > st->K) throw DeviceError{BSIM_E_DEVICE, "internal: class passes out of order"};
+    hip_check(hipEventRecord(st->ev_level, st->s), "level event");
+    hip_check(hipStreamWaitEvent(st->s2, st->ev_level, 0), "level wait");
+    const SplitTable T = class_table(st);
+    launch_level_classes(st->levels[j].p, st->rep.p, st->alive.p, st->n, j, T, st->cls_cnt.p + 2 * j,
+                         st->cls_cnt.p + 2 * j + 1, st->status.p, st->s2);
+    launch_level_clear(T, st->cls_cnt.p + 2 * j + 1, st->s2);
+    st->cls_next = j + 1;
+}
+
+std::vector<uint32_t> read_class_counts(bsim_state* st, uint32_t upto) {
+    hipStream_t s = st->s;
+    std::vector<uint32_t> c(2ull * (upto + 1));
+    hip_check(hipMemcpyAsync(c.data(), st->cls_cnt.p, c.size() * 4, hipMemcpyDeviceToHost, s), "class counts");
+    RunStatus rs;
+    hip_check(hipMemcpyAsync(&rs, st->status.p, sizeof(rs), hipMemcpyDeviceToHost, s), "status");
+    hip_check(hipStreamSynchronize(s), "class sync");
+    if (rs.error & kErrZeroHash)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
+    std::vector<uint32_t> founded(upto + 1);
+    for (uint32_t j = 0; j <= upto; j++) founded[j] = c[2 * j];
+    return founded;
+}
+
+std::vector<uint32_t> classes_end(bsim_state* st) {
+    if (st->cls_next != st->K + 1) throw DeviceError{BSIM_E_DEVICE, "internal: a level's class pass is missing"};
+    hip_check(hipEventRecord(st->ev_classes, st->s2), "classes event");
+    hip_check(hipStreamWaitEvent(st->s, st->ev_classes, 0), "classes wait");
+    return read_class_counts(st, st->K);
+}
+
 // Levels j0..K for every vertex with the refinement kernels (hash-only
 // mode): used when a frontier covers a large share of the graph, and as the
 // plain form (full recomputation per update).
@@ -1222,8 +1292,10 @@ void full_levels(bsim_state* st, uint32_t j0, Arena& arena) {
     stage_graph(g, sd, &st->ctx->status_host[3], arena, s);
     HashScratch hs;
     alloc_hash_scratch(g, hs, arena, s);
-    for (uint32_t j = j0; j <= st->K; j++)
+    for (uint32_t j = j0; j <= st->K; j++) {
         launch_hash_level(g, st->levels[0].p, st->levels[j - 1].p, st->levels[j].p, hs, j, s);
+        classes_level(st, j);
+    }
 }
 
 // Re-hash levels 1..K on the frontiers of the batch (level 0 already done:
@@ -1321,17 +1393,15 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
         if (lb == 2) k_big_chunks<uint16_t><<<512, kBlock, 0, s>>>(a);
         else k_big_chunks<uint32_t><<<512, kBlock, 0, s>>>(a);
         hip_check(hipGetLastError(), "frontier launch");
+        classes_level(st, j);
     }
 }
 
-// Classes of levels 0..upto into st->rep; returns the founded count per level.
+// Classes of levels 0..upto into st->rep on the state's stream; returns the
+// founded count per level.
 std::vector<uint32_t> level_classes(bsim_state* st, uint32_t upto) {
     hipStream_t s = st->s;
-    SplitTable T;
-    T.slots = st->cls_slots;
-    T.zero = st->cls_zero;
-    T.list = st->cls_list;
-    T.mask = st->cls_cap - 1;
+    const SplitTable T = class_table(st);
     st->cls_cnt.ensure(2ull * (upto + 1), 0, s);
     hip_check(hipMemsetAsync(st->cls_cnt.p, 0, 8ull * (upto + 1), s), "class counts");
     for (uint32_t j = 0; j <= upto; j++) {
@@ -1339,22 +1409,13 @@ std::vector<uint32_t> level_classes(bsim_state* st, uint32_t upto) {
                              st->cls_cnt.p + 2 * j + 1, st->status.p, s);
         launch_level_clear(T, st->cls_cnt.p + 2 * j + 1, s);
     }
-    std::vector<uint32_t> c(2ull * (upto + 1));
-    hip_check(hipMemcpyAsync(c.data(), st->cls_cnt.p, c.size() * 4, hipMemcpyDeviceToHost, s), "class counts");
-    RunStatus rs;
-    hip_check(hipMemcpyAsync(&rs, st->status.p, sizeof(rs), hipMemcpyDeviceToHost, s), "status");
-    hip_check(hipStreamSynchronize(s), "class sync");
-    if (rs.error & kErrZeroHash)
-        throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
-    std::vector<uint32_t> founded(upto + 1);
-    for (uint32_t j = 0; j <= upto; j++) founded[j] = c[2 * j];
-    return founded;
+    return read_class_counts(st, upto);
 }
 
 // Classes, fixpoint rule and finalize on the current levels.
 bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls) {
     hipStream_t s = st->s;
-    std::vector<uint32_t> f = level_classes(st, st->K);
+    std::vector<uint32_t> f = classes_end(st);
     std::vector<uint32_t> nk(st->K + 1);
     uint32_t run = 0;
     for (uint32_t j = 0; j <= st->K; j++) nk[j] = run += f[j];
@@ -1416,6 +1477,8 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
     PhaseTimer tm(s);
     tm.mark(0);
     Arena arena(s);
+    st->work.ensure(st->work_want, 0, s);
+    arena.back(st->work.p, st->work.cap);
     const uint32_t n_old = st->n, n_new = hb.n_new;
     ensure_vertices(st, n_new);
     const size_t grow = n_new - n_old;
@@ -1479,11 +1542,14 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
                                                  st->alive.p, st->untyped ? 1 : 0, st->levels[0].p, st->cflag.p,
                                                  tag0);
     hip_check(hipGetLastError(), "level 0");
+    classes_begin(st);
+    classes_level(st, 0);
     propagate(st, d_tl, nT, tag0, arena);
     tm.mark(2);
     bsim_result* r = finish(st, arena, nullptr);
     tm.mark(3);
     tm.fill(r);
+    st->work_want = std::max(st->work_want, arena.demand());
     st->alive_host.resize(n_new, 1);
     for (uint32_t d : hb.dead) st->alive_host[d] = 0;
     return r;
@@ -1501,6 +1567,9 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     stage_graph(g, stage_status, &ctx->status_host[3], arena, s);
     st->ctx = ctx;
     st->s = s;
+    hip_check(hipStreamCreateWithFlags(&st->s2, hipStreamNonBlocking), "class stream");
+    hip_check(hipEventCreateWithFlags(&st->ev_level, hipEventDisableTiming), "level event");
+    hip_check(hipEventCreateWithFlags(&st->ev_classes, hipEventDisableTiming), "classes event");
     st->K = p.k_max;
     st->flags = p.flags & ~BSIM_KEEP_LEVELS;
     st->untyped = (p.flags & BSIM_UNTYPED) != 0;
@@ -1552,15 +1621,19 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     // the frontier scratch up to the frontier edge limit (4 slots per edge),
     // allocated here rather than in an update's latency
     st->scratch.ensure(4 * (static_cast<uint64_t>(st->m) * 3 * ctx->frontier_limit_pct / 100 + 4096) + 1024, 0, s);
-    // reserve the stream-ordered pool for an update's temporary arrays
-    // (the full-level staging takes about 32 B per edge and 64 B per
-    // vertex): allocated and freed once here, the memory stays cached, so a
-    // later update rarely maps new memory inside its latency
-    {
-        void* warm = nullptr;
-        const size_t bytes = 32 * static_cast<size_t>(st->m) + 64 * static_cast<size_t>(n) + (64u << 20);
-        if (hipMallocAsync(&warm, bytes, s) == hipSuccess) (void)hipFreeAsync(warm, s);
-    }
+    // the workspace of an update's temporary arrays (the full-level staging
+    // and the merges take about 8 B per edge and 8 B per vertex), and the
+    // second copies of the CSR and type arrays that the first merges write,
+    // allocated here rather than inside an update's latency
+    st->work_want = 12 * static_cast<size_t>(st->m) + 16 * static_cast<size_t>(n) + (64u << 20);
+    st->work.ensure(st->work_want, 0, s);
+    st->src[c ^ 1].ensure(m + 1ull, 0, s);
+    st->tgt[c ^ 1].ensure(m + 1ull, 0, s);
+    st->lab[c ^ 1].ensure((m + 1ull) * g.label_bytes, 0, s);
+    st->kpos.ensure(std::max<uint64_t>(m, nt) + 1, 0, s);
+    st->type_own[st->tcur ^ 1].ensure(nt + 1ull, 0, s);
+    st->type_ids[st->tcur ^ 1].ensure(nt + 1ull, 0, s);
+    st->chunk_owner.ensure(static_cast<size_t>(n) + st->m / kChunkEdges + 2, 0, s);
     ensure_salt(st, st->max_label);
     rebuild_reverse(st, arena);
     tm.mark(1);
@@ -1572,6 +1645,8 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     bsim_params bp{p.k_max, p.flags & ~BSIM_STOP_AT_FIXPOINT};
     run_refinement(ctx, g, bp, rb, &sink, arena);
     tm.mark(2);
+    classes_begin(st);
+    for (uint32_t j = 0; j <= st->K; j++) classes_level(st, j);
     bsim_result* r = finish(st, arena, nullptr);
     tm.mark(3);
     tm.fill(r);
@@ -1611,7 +1686,7 @@ uint64_t state_bytes(const bsim_state* st) {
     add(st->salt), add(st->rep), add(st->dflag), add(st->bmark), add(st->fmark), add(st->chg_lo);
     add(st->chg_hi), add(st->tidx), add(st->kept), add(st->deg), add(st->blist), add(st->cflag);
     add(st->cls_cnt), add(st->kpos), add(st->chunk_owner), add(st->big_done), add(st->big), add(st->big_acc);
-    add(st->scratch);
+    add(st->scratch), add(st->work);
     b += static_cast<uint64_t>(st->cls_cap) * (sizeof(SplitSlot) + 4);
     return b;
 }

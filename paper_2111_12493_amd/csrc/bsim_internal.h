@@ -184,7 +184,6 @@ struct HubArgs {
     const uint32_t* hb_hub;
     const uint32_t* hb_bucket;
     uint64_t* hub_acc;
-    uint32_t* hub_done;
     uint64_t* h_next;
     RunStatus* status;
     uint32_t table_slots;   // LDS slots (power of two)
@@ -207,19 +206,35 @@ class Arena {
     ~Arena() { release(); }
     Arena(const Arena&) = delete;
     Arena& operator=(const Arena&) = delete;
+    // Serve allocations from [base, base + cap) first, by bumping an offset:
+    // memory the caller owns, idle on the arena's stream, that outlives the
+    // arena.  What does not fit comes from the stream-ordered pool.
+    void back(void* base, size_t cap) {
+        base_ = static_cast<char*>(base);
+        cap_ = base ? cap : 0;
+        used_ = 0;
+    }
     template <typename T>
     T* alloc(size_t count) {
         void* p = nullptr;
         size_t bytes = count * sizeof(T);
         if (bytes == 0) bytes = 16;
         bytes = (bytes + 255) & ~size_t(255);
+        demand_ += bytes;
+        if (used_ + bytes <= cap_) {
+            p = base_ + used_;
+            used_ += bytes;
+            return static_cast<T*>(p);
+        }
         if (hipMallocAsync(&p, bytes, stream_) != hipSuccess)
             throw DeviceError{BSIM_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
         ptrs_.push_back(p);
         return static_cast<T*>(p);
     }
-    // Hand an allocation over to the caller (it leaves the arena).
+    // Hand a pool allocation over to the caller (it leaves the arena).
     void detach(void* p) {
+        if (cap_ && static_cast<char*>(p) >= base_ && static_cast<char*>(p) < base_ + cap_)
+            throw DeviceError{BSIM_E_DEVICE, "internal: backed arena memory cannot leave the arena"};
         for (auto& q : ptrs_)
             if (q == p) q = nullptr;
     }
@@ -227,11 +242,16 @@ class Arena {
         for (void* p : ptrs_)
             if (p) (void)hipFreeAsync(p, stream_);
         ptrs_.clear();
+        used_ = 0;
     }
+    // Bytes asked for so far, backed or not.
+    size_t demand() const { return demand_; }
 
   private:
     hipStream_t stream_;
     std::vector<void*> ptrs_;
+    char* base_ = nullptr;
+    size_t cap_ = 0, used_ = 0, demand_ = 0;
 };
 
 inline void hip_check(hipError_t e, const char* what) {
@@ -324,7 +344,6 @@ struct RunBuffers {
     uint64_t* hub_keys = nullptr;
     uint32_t* hub_boff = nullptr;
     uint64_t* hub_acc = nullptr;
-    uint32_t* hub_done = nullptr;
     RunStatus* status = nullptr;
     BatchCtl bc;                   // batched runs only
 };
@@ -347,7 +366,6 @@ struct HashScratch {
     uint64_t* hub_keys = nullptr;
     uint32_t* hub_boff = nullptr;
     uint64_t* hub_acc = nullptr;   // zero, kept zero by the launches
-    uint32_t* hub_done = nullptr;  // zero, kept zero by the launches
     RunStatus* status = nullptr;   // zero (never done)
 };
 void alloc_hash_scratch(const Staged& g, HashScratch& hs, Arena& arena, hipStream_t s);

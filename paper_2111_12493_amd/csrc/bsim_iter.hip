@@ -820,16 +820,23 @@ __global__ void __launch_bounds__(kHubBlock) k_hub(HubArgs a) {
         uint64_t bsum = 0;
         for (int i = 0; i < kHubBlock / 64; i++) bsum += s_red64[i];
         __hip_atomic_fetch_add(&a.hub_acc[hi], bsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t prev =
-            __hip_atomic_fetch_add(&a.hub_done[hi], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev + 1 == (1u << logb)) {
-            const uint64_t acc = __hip_atomic_load(&a.hub_acc[hi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t v = a.hub_v[hi];
-            if (!a.bc.gid || a.k <= a.bc.done_level[a.bc.gid[v]]) a.h_next[v] = mix64(a.t[v] ^ mix64(kCS + acc));
-            a.hub_acc[hi] = 0;
-            a.hub_done[hi] = 0;
-        }
     }
+}
+
+// h^k of each chunked hub from the sum of its buckets' distinct keys.  The
+// sums are read here, one launch after the bucket blocks added them, so the
+// bucket blocks need no fence or completion count (an agent-scope fence on
+// this chip writes back or invalidates the whole L2 of the block's XCD);
+// each sum is cleared for the next level.
+__global__ void __launch_bounds__(kBlock) k_hub_finish(const uint64_t* t, const uint32_t* hub_v, uint64_t* hub_acc,
+                                                       uint32_t n_big, uint64_t* h_next, const RunStatus* status,
+                                                       uint32_t k, BatchCtl bc) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_big || status->done) return;  // a done run added nothing
+    const uint64_t acc = hub_acc[i];
+    hub_acc[i] = 0;
+    const uint32_t v = hub_v[i];
+    if (!bc.gid || k <= bc.done_level[bc.gid[v]]) h_next[v] = mix64(t[v] ^ mix64(kCS + acc));
 }
 
 // ------------------------------------------------------------ batched stop
@@ -963,12 +970,10 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
     rb.hub_keys = arena.alloc<uint64_t>(g.hub_keys_total + 1);
     rb.hub_boff = arena.alloc<uint32_t>((static_cast<size_t>(g.n_hub_chunks) + 1) * kHubOffStride);
     rb.hub_acc = arena.alloc<uint64_t>(g.n_hubs + 1);
-    rb.hub_done = arena.alloc<uint32_t>(g.n_hubs + 1);
     rb.status = arena.alloc<RunStatus>(1);
     hip_check(hipMemsetAsync(rb.lcnt, 0, kStripeRing * kStripes * 4, s), "clear counters");
     hip_check(hipMemsetAsync(rb.totals, 0, rb.k_cap * 4, s), "clear totals");
     hip_check(hipMemsetAsync(rb.hub_acc, 0, (g.n_hubs + 1) * 8, s), "clear hub acc");
-    hip_check(hipMemsetAsync(rb.hub_done, 0, (g.n_hubs + 1) * 4, s), "clear hub done");
     hip_check(hipMemsetAsync(rb.status, 0, sizeof(RunStatus), s), "clear status");
 }
 
@@ -1045,7 +1050,6 @@ void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t 
     a.hb_hub = g.hb_hub;
     a.hb_bucket = g.hb_bucket;
     a.hub_acc = rb.hub_acc;
-    a.hub_done = rb.hub_done;
     a.h_next = rb.h[k & 1];
     a.status = rb.status;
     a.table_slots = g.hub_table_slots;
@@ -1054,16 +1058,18 @@ void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t 
     a.bc = rb.bc;
     k_hub<<<g.n_hub_blocks, kHubBlock, static_cast<size_t>(g.hub_table_slots) * 8, s>>>(a);
     hip_check(hipGetLastError(), "hub launch");
+    const uint32_t n_big = g.n_hubs - g.n_solo;
+    k_hub_finish<<<ceil_div(n_big, kBlock), kBlock, 0, s>>>(rb.t, g.hub_v, rb.hub_acc, n_big, rb.h[k & 1],
+                                                              rb.status, k, rb.bc);
+    hip_check(hipGetLastError(), "hub finish launch");
 }
 
 void alloc_hash_scratch(const Staged& g, HashScratch& hs, Arena& arena, hipStream_t s) {
     hs.hub_keys = arena.alloc<uint64_t>(g.hub_keys_total + 1);
     hs.hub_boff = arena.alloc<uint32_t>((static_cast<size_t>(g.n_hub_chunks) + 1) * kHubOffStride);
     hs.hub_acc = arena.alloc<uint64_t>(g.n_hubs + 1);
-    hs.hub_done = arena.alloc<uint32_t>(g.n_hubs + 1);
     hs.status = arena.alloc<RunStatus>(1);
     hip_check(hipMemsetAsync(hs.hub_acc, 0, (g.n_hubs + 1) * 8ull, s), "hub acc");
-    hip_check(hipMemsetAsync(hs.hub_done, 0, (g.n_hubs + 1) * 4ull, s), "hub done");
     hip_check(hipMemsetAsync(hs.status, 0, sizeof(RunStatus), s), "status");
 }
 
@@ -1123,7 +1129,6 @@ void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_pre
     h.hb_hub = g.hb_hub;
     h.hb_bucket = g.hb_bucket;
     h.hub_acc = hs.hub_acc;
-    h.hub_done = hs.hub_done;
     h.h_next = h_next;
     h.status = hs.status;
     h.table_slots = g.hub_table_slots;
@@ -1131,6 +1136,10 @@ void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_pre
     h.k = level;
     k_hub<<<g.n_hub_blocks, kHubBlock, static_cast<size_t>(g.hub_table_slots) * 8, s>>>(h);
     hip_check(hipGetLastError(), "hash level hub launch");
+    const uint32_t n_big = g.n_hubs - g.n_solo;
+    k_hub_finish<<<ceil_div(n_big, kBlock), kBlock, 0, s>>>(t, g.hub_v, hs.hub_acc, n_big, h_next, hs.status,
+                                                              level, BatchCtl{});
+    hip_check(hipGetLastError(), "hash level hub finish launch");
 }
 
 void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool stop, hipStream_t s) {
