@@ -717,8 +717,7 @@ struct bsim_state {
     DevBuf<uint64_t> salt;
     DevBuf<uint32_t> rep, dflag, bmark, fmark, chg_lo, chg_hi, tidx, kept, deg, blist, flist[2], cflag;
     uint32_t tag_base = 0;  // change / frontier tags of the next batch start above this
-    SplitSlot* cls_slots = nullptr;
-    uint64_t* cls_zero = nullptr;
+    uint64_t* cls_slots = nullptr;
     uint32_t* cls_list = nullptr;
     uint32_t cls_cap = 0;  // power of two
     DevBuf<uint32_t> cls_cnt, kpos, chunk_owner, big_done;
@@ -761,9 +760,8 @@ struct bsim_state {
         big_done.release(s), big.release(s), big_acc.release(s), scratch.release(s), cnt.release(s);
         status.release(s), work.release(s);
         if (cls_slots) (void)hipFreeAsync(cls_slots, s);
-        if (cls_zero) (void)hipFreeAsync(cls_zero, s);
         if (cls_list) (void)hipFreeAsync(cls_list, s);
-        cls_slots = nullptr, cls_zero = nullptr, cls_list = nullptr;
+        cls_slots = nullptr, cls_list = nullptr;
         (void)hipStreamSynchronize(s);
         if (ev_level) (void)hipEventDestroy(ev_level);
         if (ev_classes) (void)hipEventDestroy(ev_classes);
@@ -805,14 +803,10 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
         if (st->cls_slots) (void)hipFreeAsync(st->cls_slots, s);
         if (st->cls_list) (void)hipFreeAsync(st->cls_list, s);
         st->cls_slots = nullptr, st->cls_list = nullptr;
-        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_slots), sizeof(SplitSlot) * want, s), "class table");
+        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_slots), sizeof(uint64_t) * want, s), "class table");
         hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_list), 4ull * want, s), "class list");
-        hip_check(hipMemsetAsync(st->cls_slots, 0, sizeof(SplitSlot) * want, s), "class table clear");
+        hip_check(hipMemsetAsync(st->cls_slots, 0, sizeof(uint64_t) * want, s), "class table clear");
         st->cls_cap = want;
-    }
-    if (!st->cls_zero) {
-        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_zero), 8 * kZeroSlots, s), "zero slots");
-        hip_check(hipMemsetAsync(st->cls_zero, 0, 8 * kZeroSlots, s), "zero slots clear");
     }
 }
 
@@ -1234,7 +1228,6 @@ void classes_begin(bsim_state* st) {
 SplitTable class_table(const bsim_state* st) {
     SplitTable T;
     T.slots = st->cls_slots;
-    T.zero = st->cls_zero;
     T.list = st->cls_list;
     T.mask = st->cls_cap - 1;
     return T;
@@ -1246,7 +1239,7 @@ void classes_level(bsim_state* st, uint32_t j) {
     hip_check(hipStreamWaitEvent(st->s2, st->ev_level, 0), "level wait");
     const SplitTable T = class_table(st);
     launch_level_classes(st->levels[j].p, st->rep.p, st->alive.p, st->n, j, T, st->cls_cnt.p + 2 * j,
-                         st->cls_cnt.p + 2 * j + 1, st->status.p, st->s2);
+                         st->cls_cnt.p + 2 * j + 1, st->s2);
     launch_level_clear(T, st->cls_cnt.p + 2 * j + 1, st->s2);
     st->cls_next = j + 1;
 }
@@ -1255,11 +1248,7 @@ std::vector<uint32_t> read_class_counts(bsim_state* st, uint32_t upto) {
     hipStream_t s = st->s;
     std::vector<uint32_t> c(2ull * (upto + 1));
     hip_check(hipMemcpyAsync(c.data(), st->cls_cnt.p, c.size() * 4, hipMemcpyDeviceToHost, s), "class counts");
-    RunStatus rs;
-    hip_check(hipMemcpyAsync(&rs, st->status.p, sizeof(rs), hipMemcpyDeviceToHost, s), "status");
     hip_check(hipStreamSynchronize(s), "class sync");
-    if (rs.error & kErrZeroHash)
-        throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
     std::vector<uint32_t> founded(upto + 1);
     for (uint32_t j = 0; j <= upto; j++) founded[j] = c[2 * j];
     return founded;
@@ -1288,6 +1277,8 @@ void full_levels(bsim_state* st, uint32_t j0, Arena& arena) {
     g.type_ids = st->type_ids[st->tcur].p;
     g.alive = st->alive.p;
     g.hub_table_slots = st->ctx->hub_table_slots;
+    g.max_label = st->max_label;
+    g.trusted = true;
     RunStatus* sd = arena.alloc<RunStatus>(1);
     stage_graph(g, sd, &st->ctx->status_host[3], arena, s);
     HashScratch hs;
@@ -1406,7 +1397,7 @@ std::vector<uint32_t> level_classes(bsim_state* st, uint32_t upto) {
     hip_check(hipMemsetAsync(st->cls_cnt.p, 0, 8ull * (upto + 1), s), "class counts");
     for (uint32_t j = 0; j <= upto; j++) {
         launch_level_classes(st->levels[j].p, st->rep.p, st->alive.p, st->n, j, T, st->cls_cnt.p + 2 * j,
-                             st->cls_cnt.p + 2 * j + 1, st->status.p, s);
+                             st->cls_cnt.p + 2 * j + 1, s);
         launch_level_clear(T, st->cls_cnt.p + 2 * j + 1, s);
     }
     return read_class_counts(st, upto);
@@ -1687,7 +1678,7 @@ uint64_t state_bytes(const bsim_state* st) {
     add(st->chg_hi), add(st->tidx), add(st->kept), add(st->deg), add(st->blist), add(st->cflag);
     add(st->cls_cnt), add(st->kpos), add(st->chunk_owner), add(st->big_done), add(st->big), add(st->big_acc);
     add(st->scratch), add(st->work);
-    b += static_cast<uint64_t>(st->cls_cap) * (sizeof(SplitSlot) + 4);
+    b += static_cast<uint64_t>(st->cls_cap) * (sizeof(uint64_t) + 4);
     return b;
 }
 

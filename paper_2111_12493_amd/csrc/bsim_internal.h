@@ -77,7 +77,6 @@ constexpr int kStripes = 64;             // striped per-level claim counters
 constexpr int kStripeRing = 4;
 constexpr int kListPerStripe = 4096;     // claimed split-table slots remembered per stripe
 constexpr uint32_t kNoRep = 0xFFFFFFFEu; // virtual class of every vertex before level 0
-constexpr int kZeroSlots = 64;           // classes whose hash is 0, per table
 
 // Device-side status of a refinement run.
 struct RunStatus {
@@ -92,20 +91,14 @@ struct RunStatus {
 
 constexpr uint32_t kErrInvalid = 1u;
 constexpr uint32_t kErrRange = 2u;
-constexpr uint32_t kErrZeroHash = 4u;   // more than kZeroSlots classes hashed to 0 at one level
 constexpr uint32_t kErrHubSplit = 8u;   // a hub bucket could not be split small enough
 constexpr uint32_t kMaxHubExtraBits = 24;  // re-split depth of an overflowing hub bucket
 
-// One slot of the split table: key = h^k, owner = ((rep + 1) << 32) | member.
-struct SplitSlot {
-    uint64_t key;
-    uint64_t owner;
-};
-
-// The split table of one level (two alternate by level parity).
+// The split table of one level (two alternate by level parity).  A slot is
+// one class's owner word ((rep + 1) << 32) | owner, 0 when empty; the class
+// key is the owner's hash at that level.
 struct SplitTable {
-    SplitSlot* slots;     // cap slots, all zero between uses
-    uint64_t* zero;       // kZeroSlots owner words for the key 0
+    uint64_t* slots;      // cap slots, all zero between uses
     uint32_t* list;       // kStripes * kListPerStripe claimed slot indices
     uint32_t mask;        // cap - 1
 };
@@ -297,6 +290,9 @@ struct Staged {
     const uint8_t* alive = nullptr;
     const uint32_t* src = nullptr;   // per-edge source (COO), when there is no tile schedule
     uint32_t max_label = 0;
+    // the edges were checked when they entered a resident state: staging
+    // skips the per-edge pass and keeps max_label (an upper bound) as given
+    bool trusted = false;
     uint64_t* salt = nullptr;
     uint32_t n_tiles = 0;
     uint32_t* tile_i0 = nullptr;     // tile: positions [i0, i1) of `act`, edges [e0, e1)
@@ -387,7 +383,7 @@ uint32_t query_hub_table_slots(int device, bool device_max = false);
 // number, *founded_total grows by the number of classes founded.
 void launch_level_classes(const uint64_t* h, uint32_t* rep, const uint8_t* alive, uint32_t n,
                           uint32_t level, const SplitTable& T, uint32_t* founded_total,
-                          uint32_t* slot_count, RunStatus* status, hipStream_t s);
+                          uint32_t* slot_count, hipStream_t s);
 // Empty T again after launch_level_classes (slots listed by it).
 void launch_level_clear(const SplitTable& T, const uint32_t* slot_count, hipStream_t s);
 

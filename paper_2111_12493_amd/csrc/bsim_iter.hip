@@ -32,62 +32,36 @@ namespace {
 // ------------------------------------------------------------ split table
 
 // Join the class (r, key) of the level's split table, founding it if needed.
-// Returns the owner word ((r + 1) << 32 | member) and sets *founded when this
-// call created the class.  Slots only ever go from empty to filled during a
-// launch, so every caller with the same (r, key) walks the same probe
-// sequence and stops at the same slot.
-__device__ uint64_t split_join(const SplitTable& T, uint32_t r, uint64_t key, uint32_t v,
-                               uint32_t* founded, uint32_t* slot_out, RunStatus* status) {
-    const uint64_t mine = (static_cast<uint64_t>(r + 1) << 32) | v;
+// A slot holds the owner word ((r + 1) << 32 | owner) of one class; the
+// class key is the owner's own key, keys[owner], read back from the level's
+// hash array (written by an earlier launch, read-only here).  Returns the
+// owner word and sets *founded when this call created the class.  Slots
+// only ever go from empty to filled during a launch, so every caller with
+// the same (r, key) walks the same probe sequence and stops at the same
+// slot; founding a class is one CAS.
+__device__ uint64_t split_join(const SplitTable& T, const uint64_t* __restrict__ keys, uint32_t r, uint64_t key,
+                               uint32_t v, uint32_t* founded, uint32_t* slot_out) {
+    const uint64_t mine = (static_cast<uint64_t>(r + 1) << 32) | v;  // never 0: r + 1 >= 1
     *founded = 0;
-    if (key == 0) {
-        // the key 0 marks empty slots: its classes live in a short side array
-        for (uint32_t i = 0; i < kZeroSlots; i++) {
-            uint64_t o = T.zero[i];
-            if (o == 0) {
-                o = atomicCAS(reinterpret_cast<unsigned long long*>(&T.zero[i]), 0ull,
-                              static_cast<unsigned long long>(mine));
-                if (o == 0) {
-                    *founded = 1;
-                    o = mine;
-                }
-            }
-            if ((o >> 32) == static_cast<uint64_t>(r + 1)) {
-                *slot_out = 0xFFFFFFFFu;
-                return o;
-            }
-        }
-        atomicOr(&status->error, kErrZeroHash);
-        *slot_out = 0xFFFFFFFFu;
-        return mine;
-    }
     // the home slot depends on the class r as well as the key: isomorphic
     // vertices of different classes (every batched graph has vertices with
     // the same type set) share keys, and must not share one probe chain
     uint32_t slot = (static_cast<uint32_t>(key) ^
                      static_cast<uint32_t>((static_cast<uint64_t>(r) * 0x9E3779B97F4A7C15ull) >> 32)) & T.mask;
     for (;;) {
-        SplitSlot* p = &T.slots[slot];
-        uint64_t cur = p->key;
+        uint64_t* p = &T.slots[slot];
+        uint64_t cur = *p;  // a stale 0 only costs the CAS below
         if (cur == 0) {
-            cur = atomicCAS(reinterpret_cast<unsigned long long*>(&p->key), 0ull,
-                            static_cast<unsigned long long>(key));
-            if (cur == 0) cur = key;
-        }
-        if (cur == key) {
-            uint64_t o = p->owner;
-            if (o == 0) {
-                o = atomicCAS(reinterpret_cast<unsigned long long*>(&p->owner), 0ull,
-                              static_cast<unsigned long long>(mine));
-                if (o == 0) {
-                    *founded = 1;
-                    o = mine;
-                }
-            }
-            if ((o >> 32) == static_cast<uint64_t>(r + 1)) {
+            cur = atomicCAS(reinterpret_cast<unsigned long long*>(p), 0ull, static_cast<unsigned long long>(mine));
+            if (cur == 0) {
+                *founded = 1;
                 *slot_out = slot;
-                return o;
+                return mine;
             }
+        }
+        if ((cur >> 32) == static_cast<uint64_t>(r + 1) && keys[static_cast<uint32_t>(cur)] == key) {
+            *slot_out = slot;
+            return cur;
         }
         slot = (slot + 1) & T.mask;
     }
@@ -105,8 +79,8 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t x, uint32_t src) {
     return (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
 }
 
-__device__ uint64_t wave_split_join(const SplitTable& T, bool participant, uint32_t r, uint64_t key, uint32_t v,
-                                    uint32_t* founded, uint32_t* slot_out, RunStatus* status) {
+__device__ uint64_t wave_split_join(const SplitTable& T, const uint64_t* __restrict__ keys, bool participant,
+                                    uint32_t r, uint64_t key, uint32_t v, uint32_t* founded, uint32_t* slot_out) {
     const uint32_t lane = lane_id();
     uint32_t leader_of = lane;
     bool pending = participant;
@@ -124,7 +98,7 @@ __device__ uint64_t wave_split_join(const SplitTable& T, bool participant, uint3
     *founded = 0;
     *slot_out = 0xFFFFFFFFu;
     uint64_t o = 0;
-    if (participant && leader_of == lane) o = split_join(T, r, key, v, founded, slot_out, status);
+    if (participant && leader_of == lane) o = split_join(T, keys, r, key, v, founded, slot_out);
     return shfl_u64(o, leader_of);
 }
 
@@ -148,7 +122,7 @@ __device__ void record_founders(const SplitTable& T, uint32_t* lcnt, uint32_t le
         *s_base = tot ? atomicAdd(&lcnt[(level & (kStripeRing - 1)) * kStripes + stripe], tot) : 0;
     __syncthreads();
     if (founded) {
-        // every counted position is written (0xFFFFFFFF for the key-0 side array)
+        // every counted position is written
         const uint32_t pos = *s_base + off + wrank;
         if (pos < static_cast<uint32_t>(kListPerStripe)) T.list[stripe * kListPerStripe + pos] = slot;
     }
@@ -157,18 +131,12 @@ __device__ void record_founders(const SplitTable& T, uint32_t* lcnt, uint32_t le
 
 // ------------------------------------------------------------ level 0
 
-__global__ void __launch_bounds__(kBlock) k_init(const uint32_t* __restrict__ type_off,
-                                                 const uint32_t* __restrict__ type_ids,
-                                                 const uint8_t* __restrict__ alive, uint32_t n,
-                                                 int untyped, uint64_t* __restrict__ t,
-                                                 uint64_t* __restrict__ h0, uint32_t* __restrict__ rep,
-                                                 SplitTable T, uint32_t* lcnt, RunStatus* status,
-                                                 BatchCtl bc) {
-    __shared__ uint32_t s_red[kBlock / 64];
-    __shared__ uint32_t s_base;
+// t(v) and h^0 = t for every vertex (0 for a dead one).
+__global__ void __launch_bounds__(kBlock) k_types(const uint32_t* __restrict__ type_off,
+                                                  const uint32_t* __restrict__ type_ids,
+                                                  const uint8_t* __restrict__ alive, uint32_t n, int untyped,
+                                                  uint64_t* __restrict__ t, uint64_t* __restrict__ h0) {
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
-    uint32_t founded = 0, slot = 0xFFFFFFFFu;
-    uint32_t r = 0xFFFFFFFFu;
     if (v < n) {
         uint64_t tv = 0;
         if (!alive || alive[v]) {
@@ -187,14 +155,25 @@ __global__ void __launch_bounds__(kBlock) k_init(const uint32_t* __restrict__ ty
         t[v] = tv;
         h0[v] = tv;
     }
-    // level-0 classes: many vertices share a type set, so group each wave's
-    // lanes by key before they touch the table
+}
+
+// Level-0 classes by t (written by k_types, the launch before): many
+// vertices share a type set, so each wave's lanes are grouped by key before
+// they touch the table.
+__global__ void __launch_bounds__(kBlock) k_init(const uint64_t* __restrict__ t, const uint8_t* __restrict__ alive,
+                                                 uint32_t n, uint32_t* __restrict__ rep, SplitTable T,
+                                                 uint32_t* lcnt, BatchCtl bc) {
+    __shared__ uint32_t s_red[kBlock / 64];
+    __shared__ uint32_t s_base;
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t founded = 0, slot = 0xFFFFFFFFu;
+    uint32_t r = 0xFFFFFFFFu;
     const bool part = v < n && (!alive || alive[v]);
     const uint32_t gi = (part && bc.gid) ? bc.gid[v] : 0u;
     const uint32_t vr = bc.gid ? bc.virt_base + gi : kNoRep;
     uint64_t key = 0;
     if (part) key = t[v];
-    const uint64_t o = wave_split_join(T, part, vr, key, v, &founded, &slot, status);
+    const uint64_t o = wave_split_join(T, t, part, vr, key, v, &founded, &slot);
     if (part) {
         r = static_cast<uint32_t>(o);
         if (bc.gid && founded) atomicAdd(&bc.hist[gi], 1u);
@@ -229,7 +208,7 @@ __device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32
     if (r == v) return;
     const uint64_t hv = a.h_prev[v];
     if (hv == a.h_prev[r]) return;
-    a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, r, hv, v, founded, slot, a.status));
+    a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, a.h_prev, r, hv, v, founded, slot));
     if (a.bc.gid && *founded)
         atomicAdd(&a.bc.hist[static_cast<size_t>(a.k - 1) * a.bc.n_graphs + a.bc.gid[v]], 1u);
 }
@@ -345,7 +324,7 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
         // leave the class of rep[v] if h^{k-1} differs
         uint32_t founded = 0, slot = 0xFFFFFFFFu;
         if (probe && hv_own != hv_rep) {
-            a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, rv, hv_own, v, &founded, &slot, a.status));
+            a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, a.h_prev, rv, hv_own, v, &founded, &slot));
             if (a.bc.gid && founded)
                 atomicAdd(&a.bc.hist[static_cast<size_t>(k - 1) * a.bc.n_graphs + gi], 1u);
         }
@@ -615,7 +594,7 @@ __device__ bool iso_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32
             // carry the same key: group them per wave before the table
             uint32_t founded = 0, slot = 0xFFFFFFFFu;
             const bool part = probe[r] && hv_own[r] != hv_rep[r];
-            const uint64_t o = wave_split_join(a.test_tab, part, rv[r], hv_own[r], v[r], &founded, &slot, a.status);
+            const uint64_t o = wave_split_join(a.test_tab, a.h_prev, part, rv[r], hv_own[r], v[r], &founded, &slot);
             if (part) {
                 a.rep[v[r]] = static_cast<uint32_t>(o);
                 if (a.bc.gid && founded)
@@ -649,15 +628,11 @@ __device__ void recycle(const IterArgs& a) {
     const uint32_t* cnt = a.lcnt + ((k - 2) & (kStripeRing - 1)) * kStripes;
     bool overflow = false;
     for (int st = 0; st < kStripes; st++) overflow |= cnt[st] > static_cast<uint32_t>(kListPerStripe);
-    if (blockIdx.x == 0 && tid < kZeroSlots) a.clr_tab.zero[tid] = 0;
     if (overflow) {
         const uint64_t cap = static_cast<uint64_t>(a.clr_tab.mask) + 1;
         const uint64_t per = (cap + gridDim.x - 1) / gridDim.x;
         const uint64_t lo = per * blockIdx.x, hi = min(cap, lo + per);
-        for (uint64_t j = lo + tid; j < hi; j += kBlock) {
-            a.clr_tab.slots[j].key = 0;
-            a.clr_tab.slots[j].owner = 0;
-        }
+        for (uint64_t j = lo + tid; j < hi; j += kBlock) a.clr_tab.slots[j] = 0;
     } else {
         const uint64_t items = static_cast<uint64_t>(kStripes) * kListPerStripe;
         for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + tid; i < items;
@@ -666,11 +641,7 @@ __device__ void recycle(const IterArgs& a) {
             const uint32_t e = static_cast<uint32_t>(i % kListPerStripe);
             if (e < cnt[st]) {
                 const uint32_t idx = a.clr_tab.list[i];
-                if (idx <= a.clr_tab.mask) {
-                    SplitSlot* p = &a.clr_tab.slots[idx];
-                    p->key = 0;
-                    p->owner = 0;
-                }
+                if (idx <= a.clr_tab.mask) a.clr_tab.slots[idx] = 0;
             }
         }
     }
@@ -873,8 +844,7 @@ __global__ void __launch_bounds__(kBlock) k_level_classes(const uint64_t* __rest
                                                           const uint8_t* __restrict__ alive, uint32_t n,
                                                           uint32_t level, SplitTable T,
                                                           uint32_t* __restrict__ founded_total,
-                                                          uint32_t* __restrict__ slot_count,
-                                                          RunStatus* status) {
+                                                          uint32_t* __restrict__ slot_count) {
     __shared__ uint32_t s_red[kBlock / 64];
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     uint32_t founded = 0, slot = 0xFFFFFFFFu;
@@ -894,7 +864,7 @@ __global__ void __launch_bounds__(kBlock) k_level_classes(const uint64_t* __rest
             }
         }
     }
-    const uint64_t o = wave_split_join(T, part, r, hv, v, &founded, &slot, status);
+    const uint64_t o = wave_split_join(T, h, part, r, hv, v, &founded, &slot);
     if (part) rep[v] = static_cast<uint32_t>(o);
     // founded slots are listed so that only they are cleared afterwards (one
     // counter atomic per wave: level 0 founds a class per distinct type set)
@@ -915,12 +885,7 @@ __global__ void __launch_bounds__(kBlock) k_level_classes(const uint64_t* __rest
 
 __global__ void __launch_bounds__(kBlock) k_level_clear(SplitTable T, const uint32_t* __restrict__ slot_count) {
     const uint32_t cnt = min(*slot_count, T.mask + 1);
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
-        SplitSlot* p = &T.slots[T.list[i]];
-        p->key = 0;
-        p->owner = 0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < kZeroSlots) T.zero[threadIdx.x] = 0;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) T.slots[T.list[i]] = 0;
 }
 
 }  // namespace
@@ -940,8 +905,7 @@ uint32_t query_hub_table_slots(int device, bool device_max) {
 
 static SplitTable make_table(Arena& arena, uint32_t cap) {
     SplitTable T;
-    T.slots = arena.alloc<SplitSlot>(cap);
-    T.zero = arena.alloc<uint64_t>(kZeroSlots);
+    T.slots = arena.alloc<uint64_t>(cap);
     T.list = arena.alloc<uint32_t>(static_cast<size_t>(kStripes) * kListPerStripe);
     T.mask = cap - 1;
     return T;
@@ -957,9 +921,8 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
     const uint32_t cap = std::max<uint32_t>(next_pow2(static_cast<uint64_t>(n) + n / 2 + 1), 64);
     for (int i = 0; i < 2; i++) {
         rb.tab[i] = make_table(arena, cap);
-        hip_check(hipMemsetAsync(rb.tab[i].slots, 0, static_cast<size_t>(cap) * sizeof(SplitSlot), s),
+        hip_check(hipMemsetAsync(rb.tab[i].slots, 0, static_cast<size_t>(cap) * sizeof(uint64_t), s),
                   "clear split table");
-        hip_check(hipMemsetAsync(rb.tab[i].zero, 0, kZeroSlots * 8, s), "clear zero slots");
     }
     rb.lcnt = arena.alloc<uint32_t>(kStripeRing * kStripes);
     // level j's count is written by launch j+2 <= k_done+2; k_done <= max(n, 1)
@@ -979,9 +942,9 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
 
 void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s) {
     const uint32_t n = g.n;
-    k_init<<<std::max<uint32_t>(ceil_div(n, kBlock), 1), kBlock, 0, s>>>(
-        g.type_off, g.type_ids, g.alive, n, untyped ? 1 : 0, rb.t, rb.h[0], rb.rep, rb.tab[0], rb.lcnt,
-        rb.status, rb.bc);
+    const uint32_t grid = std::max<uint32_t>(ceil_div(n, kBlock), 1);
+    k_types<<<grid, kBlock, 0, s>>>(g.type_off, g.type_ids, g.alive, n, untyped ? 1 : 0, rb.t, rb.h[0]);
+    k_init<<<grid, kBlock, 0, s>>>(rb.t, g.alive, n, rb.rep, rb.tab[0], rb.lcnt, rb.bc);
     hip_check(hipGetLastError(), "init launch");
 }
 
@@ -1149,10 +1112,10 @@ void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool st
 
 void launch_level_classes(const uint64_t* h, uint32_t* rep, const uint8_t* alive, uint32_t n,
                           uint32_t level, const SplitTable& T, uint32_t* founded_total,
-                          uint32_t* slot_count, RunStatus* status, hipStream_t s) {
+                          uint32_t* slot_count, hipStream_t s) {
     if (n == 0) return;
     k_level_classes<<<ceil_div(n, kBlock), kBlock, 0, s>>>(h, rep, alive, n, level, T, founded_total,
-                                                           slot_count, status);
+                                                           slot_count);
     hip_check(hipGetLastError(), "level classes launch");
 }
 

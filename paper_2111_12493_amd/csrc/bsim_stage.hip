@@ -320,7 +320,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
     if (n > 0) {
         k_stage_vertices<<<ceil_div(n, kBlock), kBlock, 0, s>>>(g.row_off, g.type_off, g.alive, n,
                                                                 g.m, hubf, actf, isof, status_dev);
-        if (g.m > 0) {
+        if (g.m > 0 && !g.trusted) {
             uint32_t nbk = std::min<uint64_t>(ceil_div(g.m, kBlock), 2048);
             if (g.label_bytes == 2)
                 k_stage_edges<uint16_t><<<nbk, kBlock, 0, s>>>(
@@ -360,7 +360,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         throw DeviceError{BSIM_E_UNSUPPORTED, "more than 4096 type ids on one vertex"};
     if (status_host->max_label >= (1u << 24))
         throw DeviceError{BSIM_E_UNSUPPORTED, "edge labels must be < 2^24"};
-    g.max_label = status_host->max_label;
+    if (!g.trusted) g.max_label = status_host->max_label;
     g.n_hubs = hc[1];
     g.n_act = hc[4];
     g.n_iso = hc[5];

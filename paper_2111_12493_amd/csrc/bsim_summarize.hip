@@ -183,8 +183,6 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
         lr.ms_hub_kernels += b;
         lr.n_timed++;
     }
-    if (st.error & kErrZeroHash)
-        throw DeviceError{BSIM_E_UNSUPPORTED, "too many classes hashed to the value 0 at one level"};
     if (st.error & kErrHubSplit)
         throw DeviceError{BSIM_E_DEVICE, "a hub hash bucket could not be split to fit its table"};
     lr.k_done = st.k_done;
