@@ -345,3 +345,162 @@ int bo_iterate(uint32_t n, const uint64_t* row_off, const uint32_t* tgt, const u
     free(t); free(cur); free(nxt); free(cls); free(ncls); free(keys);
     return BO_OK;
 }
+
+/*
+ * Direction and label parameterizations (Sec. 2.4: the label
+ * parameterization keeps only the edges whose label is in a set P_l; the
+ * direction parameterization takes outgoing edges, incoming edges or both;
+ * Sec. 2.5: backward bisimulation is forward bisimulation with incoming
+ * edges).  TEST INFRASTRUCTURE ONLY, like everything in this file.
+ *
+ *   kept edges   E' = { (v, l, w) in E : P_l absent or l in P_l }
+ *   forward      the (partner, salt) pairs of v are (w, salt(l))    for (v, l, w) in E'
+ *   backward     the pairs of w are (v, salt(l))                    for (v, l, w) in E'
+ *   both         the forward pairs of v and the backward pairs of v, the
+ *                backward ones salted by salt_in(l) = M(C_L + 2^31 + l): an
+ *                incoming l-edge counts as an outgoing edge whose label is
+ *                l + 2^31, a range no input label reaches (labels < 2^24),
+ *                so incoming and outgoing edges never make the same pair
+ *   key          h^{k-1}(partner) ^ salt
+ *   h^k(v)       M(t(v) ^ M(C_S + sum over the distinct keys q of v of M(q ^ C_E)))
+ *
+ * The refinement, the stop rule and the block numbering are those of
+ * bo_summarize; the summary edges are the distinct (block(v), l, block(w))
+ * over the kept edges E', in their own direction.  With forward, no P_l the
+ * result equals bo_summarize.
+ */
+#define BO_BACKWARD 32u
+#define BO_BOTH_DIRECTIONS 64u
+
+uint64_t bo_label_salt_in(uint32_t label) { return bo_mix(bo_const_l() + 0x80000000ull + (uint64_t)label); }
+
+/* keep_label[l] != 0 for l in P_l, for l < n_keep; NULL keeps every edge */
+static int kept(const uint8_t* keep_label, uint32_t n_keep, uint32_t l) {
+    return !keep_label || (l < n_keep && keep_label[l]);
+}
+
+int bo_summarize_ext(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t* tgt,
+                     const uint32_t* lab, const uint64_t* typ_off, const uint32_t* typ,
+                     const uint8_t* alive, uint32_t k_max, uint32_t flags,
+                     const uint8_t* keep_label, uint32_t n_keep,
+                     uint64_t* hashes, uint32_t* block_ids, uint32_t* blocks_per_iter,
+                     uint32_t* k_done_out, uint32_t* fixpoint_out, uint32_t* n_blocks_out,
+                     uint32_t* block_sizes, uint64_t* n_se_out,
+                     uint32_t* se_src, uint32_t* se_lab, uint32_t* se_dst) {
+    if ((flags & BO_BACKWARD) && (flags & BO_BOTH_DIRECTIONS)) return BO_E_INVALID;
+    if (row_off[0] != 0 || row_off[n] != m) return BO_E_INVALID;
+    for (uint32_t v = 0; v < n; v++) {
+        if (row_off[v + 1] < row_off[v] || typ_off[v + 1] < typ_off[v]) return BO_E_INVALID;
+        for (uint64_t e = row_off[v]; e < row_off[v + 1]; e++) {
+            if (tgt[e] >= n) return BO_E_INVALID;
+            if (alive && (!alive[v] || !alive[tgt[e]])) return BO_E_INVALID;
+        }
+    }
+    const int fwd = !(flags & BO_BACKWARD);
+    const int bwd = (flags & BO_BACKWARD) || (flags & BO_BOTH_DIRECTIONS);
+    /* pair lists: pcount[v] pairs of v at pair_off[v] */
+    uint64_t* pair_off = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
+    if (!pair_off) return BO_E_NOMEM;
+    for (uint32_t v = 0; v < n; v++)
+        for (uint64_t e = row_off[v]; e < row_off[v + 1]; e++) {
+            if (!kept(keep_label, n_keep, lab[e])) continue;
+            if (fwd) pair_off[v + 1]++;
+            if (bwd) pair_off[tgt[e] + 1]++;
+        }
+    for (uint32_t v = 0; v < n; v++) pair_off[v + 1] += pair_off[v];
+    const uint64_t np = pair_off[n];
+    uint32_t* partner = (uint32_t*)malloc(sizeof(uint32_t) * (np ? np : 1));
+    uint64_t* salt = (uint64_t*)malloc(sizeof(uint64_t) * (np ? np : 1));
+    uint64_t* fill = (uint64_t*)malloc(sizeof(uint64_t) * ((size_t)n + 1));
+    if (!partner || !salt || !fill) return BO_E_NOMEM;
+    memcpy(fill, pair_off, sizeof(uint64_t) * ((size_t)n + 1));
+    for (uint32_t v = 0; v < n; v++)
+        for (uint64_t e = row_off[v]; e < row_off[v + 1]; e++) {
+            if (!kept(keep_label, n_keep, lab[e])) continue;
+            const uint32_t w = tgt[e];
+            if (fwd) {
+                partner[fill[v]] = w;
+                salt[fill[v]++] = bo_label_salt(lab[e]);
+            }
+            if (bwd) {
+                partner[fill[w]] = v;
+                salt[fill[w]++] = (flags & BO_BOTH_DIRECTIONS) ? bo_label_salt_in(lab[e]) : bo_label_salt(lab[e]);
+            }
+        }
+    uint64_t maxp = 1;
+    for (uint32_t v = 0; v < n; v++)
+        if (pair_off[v + 1] - pair_off[v] > maxp) maxp = pair_off[v + 1] - pair_off[v];
+    uint64_t* t = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint64_t* cur = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint64_t* nxt = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1));
+    uint32_t* cls = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t* ncls = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * maxp);
+    if (!t || !cur || !nxt || !cls || !ncls || !keys) return BO_E_NOMEM;
+    const uint64_t cs = bo_const_s(), ce = bo_const_e();
+
+    for (uint32_t v = 0; v < n; v++) {
+        int a = !alive || alive[v];
+        t[v] = a ? bo_type_hash(typ + typ_off[v], (uint32_t)(typ_off[v + 1] - typ_off[v]),
+                                flags & BO_UNTYPED)
+                 : 0;
+        cur[v] = t[v];
+    }
+    blocks_per_iter[0] = refine_classes(NULL, cur, alive, n, cls);
+    uint32_t k_done = 0, fixpoint = 0;
+    for (uint32_t k = 1; k <= k_max; k++) {
+        for (uint32_t v = 0; v < n; v++) {
+            if (alive && !alive[v]) { nxt[v] = 0; continue; }
+            const uint64_t d = pair_off[v + 1] - pair_off[v];
+            for (uint64_t i = 0; i < d; i++) keys[i] = cur[partner[pair_off[v] + i]] ^ salt[pair_off[v] + i];
+            size_t u = unique_u64(keys, (size_t)d);
+            uint64_t sum = 0;
+            for (size_t i = 0; i < u; i++) sum += bo_mix(keys[i] ^ ce);
+            nxt[v] = bo_mix(t[v] ^ bo_mix(cs + sum));
+        }
+        blocks_per_iter[k] = refine_classes(cls, nxt, alive, n, ncls);
+        uint32_t* sc = cls; cls = ncls; ncls = sc;
+        uint64_t* sw = cur; cur = nxt; nxt = sw;
+        k_done = k;
+        if (blocks_per_iter[k] == blocks_per_iter[k - 1]) {
+            fixpoint = 1;
+            if (flags & BO_STOP_AT_FIXPOINT) break;
+        } else {
+            fixpoint = 0;
+        }
+    }
+    memcpy(hashes, cur, sizeof(uint64_t) * n);
+    uint32_t nb = blocks_per_iter[k_done];
+    memcpy(block_ids, cls, sizeof(uint32_t) * n);
+    memset(block_sizes, 0, sizeof(uint32_t) * (nb ? nb : 0));
+    for (uint32_t v = 0; v < n; v++)
+        if (block_ids[v] != 0xFFFFFFFFu) block_sizes[block_ids[v]]++;
+
+    triple* tr = (triple*)malloc(sizeof(triple) * (m ? m : 1));
+    if (!tr) return BO_E_NOMEM;
+    uint64_t ne = 0;
+    for (uint32_t v = 0; v < n; v++)
+        for (uint64_t e = row_off[v]; e < row_off[v + 1]; e++) {
+            if (!kept(keep_label, n_keep, lab[e])) continue;
+            tr[ne].s = block_ids[v];
+            tr[ne].l = lab[e];
+            tr[ne].d = block_ids[tgt[e]];
+            ne++;
+        }
+    qsort(tr, (size_t)ne, sizeof(triple), cmp_triple);
+    uint64_t u = 0;
+    for (uint64_t i = 0; i < ne; i++) {
+        if (u > 0 && tr[i].s == se_src[u - 1] && tr[i].l == se_lab[u - 1] &&
+            tr[i].d == se_dst[u - 1])
+            continue;
+        se_src[u] = tr[i].s; se_lab[u] = tr[i].l; se_dst[u] = tr[i].d;
+        u++;
+    }
+    *n_se_out = u;
+    *k_done_out = k_done;
+    *fixpoint_out = fixpoint;
+    *n_blocks_out = nb;
+    free(tr); free(t); free(cur); free(nxt); free(cls); free(ncls); free(keys);
+    free(pair_off); free(partner); free(salt); free(fill);
+    return BO_OK;
+}

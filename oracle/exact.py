@@ -15,6 +15,11 @@ brute_force_classes -- the definition evaluated pairwise: relation R_k is
                      is matched by an l-edge of v into R_{k-1}, and vice
                      versa (the symmetric reading, as in the complex schema
                      element of Sec. 2.4).
+
+Both take the direction parameterization (outgoing edges, incoming edges as
+in backward bisimulation, or both, told apart by a direction tag) and the
+label parameterization (only edges whose label is in a given set) of
+Sec. 2.4 through ``signature_edges``.
 """
 
 from __future__ import annotations
@@ -40,13 +45,32 @@ def _intern(keys: Sequence) -> Tuple[List[int], int]:
     return out, len(ids)
 
 
+def signature_edges(g, direction: str = "out", labels=None) -> List[List[Tuple]]:
+    """Per vertex, the edges its signature looks at, as (direction tag, label,
+    partner): outgoing edges (tag "o", partner = target), incoming edges
+    (tag "i", partner = source) or both (Sec. 2.4 direction
+    parameterization; Sec. 2.5 backward bisimulation), keeping only labels
+    in ``labels`` when it is given (label parameterization)."""
+    keep = None if labels is None else set(int(x) for x in labels)
+    sig: List[List[Tuple]] = [[] for _ in range(g.n)]
+    for v in range(g.n):
+        for (l, w) in g.out_edges(v):
+            if keep is not None and l not in keep:
+                continue
+            if direction in ("out", "both"):
+                sig[v].append(("o", l, w))
+            if direction in ("in", "both"):
+                sig[w].append(("i", l, v))
+    return sig
+
+
 def exact_refinement(g, k_max: int, stop_at_fixpoint: bool = True,
-                     untyped: bool = False):
+                     untyped: bool = False, direction: str = "out", labels=None):
     """Returns (levels, counts, k_done): levels[k][v] is v's first-occurrence
     block id in the k-partition (None for dead vertices)."""
     n = g.n
     types = [frozenset(g.types_of(v)) if not untyped else frozenset() for v in range(n)]
-    edges = [g.out_edges(v) for v in range(n)]
+    edges = [[((d, l), w) for (d, l, w) in es] for es in signature_edges(g, direction, labels)]
     cls, cnt = _intern([types[v] if _alive(g, v) else None for v in range(n)])
     levels = [cls]
     counts = [cnt]
@@ -68,13 +92,16 @@ def exact_refinement(g, k_max: int, stop_at_fixpoint: bool = True,
     return levels, counts, k_done
 
 
-def brute_force_classes(g, k: int, untyped: bool = False) -> List[Optional[int]]:
+def brute_force_classes(g, k: int, untyped: bool = False, direction: str = "out",
+                        labels=None) -> List[Optional[int]]:
     """First-occurrence class ids of the k-bisimulation, from the pairwise
-    definition (quadratic in n; tiny graphs only)."""
+    definition (quadratic in n; tiny graphs only).  A (direction, label) pair
+    plays the role of the label."""
     n = g.n
     alive = [v for v in range(n) if _alive(g, v)]
     types = {v: (frozenset() if untyped else frozenset(g.types_of(v))) for v in alive}
-    out = {v: g.out_edges(v) for v in alive}
+    sig = signature_edges(g, direction, labels)
+    out = {v: [((d, l), w) for (d, l, w) in sig[v]] for v in alive}
     rel = {(u, v) for u in alive for v in alive if types[u] == types[v]}
     for _ in range(k):
         nxt = set()
@@ -101,10 +128,13 @@ def brute_force_classes(g, k: int, untyped: bool = False) -> List[Optional[int]]
     return res
 
 
-def quotient_edges(g, block_ids) -> List[Tuple[int, int, int]]:
-    """Distinct (block(v), label, block(w)) over all edges, sorted."""
+def quotient_edges(g, block_ids, labels=None) -> List[Tuple[int, int, int]]:
+    """Distinct (block(v), label, block(w)) over all edges (over the edges
+    whose label is in ``labels`` when it is given), sorted."""
+    keep = None if labels is None else set(int(x) for x in labels)
     s = set()
     for v in range(g.n):
         for (l, w) in g.out_edges(v):
-            s.add((int(block_ids[v]), int(l), int(block_ids[w])))
+            if keep is None or l in keep:
+                s.add((int(block_ids[v]), int(l), int(block_ids[w])))
     return sorted(s)

@@ -19,6 +19,8 @@ LIB = os.path.join(HERE, "libbsim_oracle.so")
 
 STOP_AT_FIXPOINT = 1
 UNTYPED = 4
+BACKWARD = 32
+BOTH_DIRECTIONS = 64
 
 
 def build(force: bool = True) -> str:
@@ -58,6 +60,11 @@ def load(path: str) -> ctypes.CDLL:
                                p, p, p, p, p, p, p, p, p, p, p, p]
     L.bo_iterate.restype = ctypes.c_int
     L.bo_iterate.argtypes = [u32, p, p, p, p, p, u32, u32, p, p]
+    L.bo_label_salt_in.restype = u64
+    L.bo_label_salt_in.argtypes = [u32]
+    L.bo_summarize_ext.restype = ctypes.c_int
+    L.bo_summarize_ext.argtypes = [u32, u64, p, p, p, p, p, p, u32, u32, p, u32,
+                                   p, p, p, p, p, p, p, p, p, p, p]
     return L
 
 
@@ -155,6 +162,48 @@ def summarize(g, k_max: int, stop_at_fixpoint: bool = True, untyped: bool = Fals
     kd, nbv, ns = k_done.value, nb.value, nse.value
     return dict(k_done=kd, fixpoint=fix.value, n_blocks=nbv, hashes=hashes[:n],
                 prev_hashes=prev[:n], block_ids=bids[:n], blocks_per_iter=bpi[:kd + 1],
+                block_sizes=bsz[:nbv], se_src=se_s[:ns], se_label=se_l[:ns], se_dst=se_d[:ns])
+
+
+def summarize_ext(g, k_max: int, stop_at_fixpoint: bool = True, untyped: bool = False,
+                  direction: str = "out", labels=None) -> Dict:
+    """Summarization under the direction parameterization ("out", "in" or
+    "both") and the label parameterization (``labels``: the kept label set
+    P_l, None for every label); see ``bo_summarize_ext`` in the C file."""
+    n, m = g.n, g.m
+    row_off, tgt, lab, typ_off, typ, alive = _csr(g)
+    if tgt.size == 0:
+        tgt = np.zeros(1, dtype=np.uint32)
+        lab = np.zeros(1, dtype=np.uint32)
+    flags = ((STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0)
+             | {"out": 0, "in": BACKWARD, "both": BOTH_DIRECTIONS}[direction])
+    keep = None
+    if labels is not None:
+        ls = np.asarray(list(labels), dtype=np.int64)
+        keep = np.zeros(int(ls.max()) + 1 if ls.size else 1, dtype=np.uint8)
+        keep[ls] = 1
+    hashes = np.zeros(max(n, 1), dtype=np.uint64)
+    bids = np.zeros(max(n, 1), dtype=np.uint32)
+    bpi = np.zeros(k_max + 1, dtype=np.uint32)
+    bsz = np.zeros(max(n, 1), dtype=np.uint32)
+    se_s = np.zeros(max(m, 1), dtype=np.uint32)
+    se_l = np.zeros(max(m, 1), dtype=np.uint32)
+    se_d = np.zeros(max(m, 1), dtype=np.uint32)
+    k_done = ctypes.c_uint32()
+    fix = ctypes.c_uint32()
+    nb = ctypes.c_uint32()
+    nse = ctypes.c_uint64()
+    rc = lib().bo_summarize_ext(n, m, _ptr(row_off), _ptr(tgt), _ptr(lab), _ptr(typ_off),
+                                _ptr(typ), _ptr(alive), k_max, flags, _ptr(keep),
+                                0 if keep is None else keep.size, _ptr(hashes), _ptr(bids),
+                                _ptr(bpi), ctypes.byref(k_done), ctypes.byref(fix),
+                                ctypes.byref(nb), _ptr(bsz), ctypes.byref(nse), _ptr(se_s),
+                                _ptr(se_l), _ptr(se_d))
+    if rc != 0:
+        raise ValueError("oracle rejected the graph (status %d)" % rc)
+    kd, nbv, ns = k_done.value, nb.value, nse.value
+    return dict(k_done=kd, fixpoint=fix.value, n_blocks=nbv, hashes=hashes[:n],
+                block_ids=bids[:n], blocks_per_iter=bpi[:kd + 1],
                 block_sizes=bsz[:nbv], se_src=se_s[:ns], se_label=se_l[:ns], se_dst=se_d[:ns])
 
 
