@@ -61,6 +61,16 @@ extern "C" {
 #define BSIM_UNTYPED 4u            /* ignore vertex types: t(v) = M(C_T) for all v */
 #define BSIM_RESULT_ON_HOST 8u     /* copy result arrays to host memory */
 #define BSIM_NO_SUMMARY_EDGES 16u  /* skip the quotient-edge output */
+/* Direction parameterization (Sec. 2.4; backward bisimulation, Sec. 2.5).
+ * Default: a signature reads the outgoing edges (v, l, w).  BSIM_BACKWARD:
+ * it reads the incoming edges (v, l, w) of w, partner v, salt(l).
+ * BSIM_BOTH_DIRECTIONS: both kinds in one set, an incoming l-edge salted as
+ * an outgoing edge of label l + 2^31 would be, M(C_L + 2^31 + l).  The two
+ * flags exclude each other; summary edges keep the edges' own direction.
+ * bsim_summarize / bsim_summarize_labels without a state only (a batch, a
+ * state or a server request with them gives BSIM_E_UNSUPPORTED). */
+#define BSIM_BACKWARD 32u
+#define BSIM_BOTH_DIRECTIONS 64u
 
 typedef struct bsim_ctx bsim_ctx;
 typedef struct bsim_state bsim_state;
@@ -193,6 +203,18 @@ const char* bsim_option_names(void);
  */
 int bsim_summarize(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* params,
                    bsim_state** state_out, bsim_result** out);
+
+/*
+ * Summarize under the label parameterization (Sec. 2.4): only the edges whose
+ * label is in labels[0..n_labels) count, for the signatures and for the
+ * summary edges; the others are ignored as if absent.  labels is a host
+ * array owned by the caller (read during the call); repeats and labels the
+ * graph never uses are allowed, and n_labels = 0 keeps no edge.  Otherwise
+ * as bsim_summarize without a state, the direction flags included.  Errors
+ * as bsim_summarize; labels == NULL with n_labels > 0 gives BSIM_E_INVALID.
+ */
+int bsim_summarize_labels(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* params,
+                          const uint32_t* labels, uint32_t n_labels, bsim_result** out);
 void bsim_result_free(bsim_result* result);
 
 /* Copy one result array to caller memory (host or device pointer, as

@@ -22,6 +22,8 @@ OK = 0
 E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY = -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
 STOP_AT_FIXPOINT, KEEP_LEVELS, UNTYPED, RESULT_ON_HOST, NO_SUMMARY_EDGES = 1, 2, 4, 8, 16
+BACKWARD, BOTH_DIRECTIONS = 32, 64
+DIRECTION_FLAGS = {"out": 0, "in": BACKWARD, "both": BOTH_DIRECTIONS}
 K_UNBOUNDED = 0xFFFFFFFF
 OP_ADD_V, OP_MOD_V, OP_DEL_V, OP_ADD_E, OP_MOD_E, OP_DEL_E = 1, 2, 3, 4, 5, 6
 
@@ -79,6 +81,8 @@ EXPORTS = {
     "bsim_option_names": (ctypes.c_char_p, []),
     "bsim_summarize": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), ctypes.POINTER(BsimParams),
                                       ctypes.POINTER(_p), ctypes.POINTER(ctypes.POINTER(BsimResult))]),
+    "bsim_summarize_labels": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), ctypes.POINTER(BsimParams),
+                                             _p, _u32, ctypes.POINTER(ctypes.POINTER(BsimResult))]),
     "bsim_result_free": (None, [ctypes.POINTER(BsimResult)]),
     "bsim_result_copy": (ctypes.c_int, [ctypes.POINTER(BsimResult), ctypes.c_char_p, _p, _u32]),
     "bsim_apply_updates": (ctypes.c_int, [_p, ctypes.POINTER(BsimUpdate), _u64,
@@ -298,15 +302,25 @@ class Result:
 
 
 def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
-              untyped: bool = False, summary_edges: bool = True, result_on_host: bool = False) -> Result:
-    """bsim_summarize on a DeviceGraph or HostGraph."""
+              untyped: bool = False, summary_edges: bool = True, result_on_host: bool = False,
+              direction: str = "out", labels=None) -> Result:
+    """bsim_summarize on a DeviceGraph or HostGraph; with ``labels`` (the
+    kept label set) bsim_summarize_labels.  ``direction`` is "out", "in"
+    (BSIM_BACKWARD) or "both" (BSIM_BOTH_DIRECTIONS)."""
     flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
-            (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0)
+            (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0) | \
+            DIRECTION_FLAGS[direction]
     gs = graph.struct()
     params = BsimParams(int(k_max), flags)
     out = ctypes.POINTER(BsimResult)()
-    ctx.check(lib().bsim_summarize(ctx.handle, ctypes.byref(gs), ctypes.byref(params), None,
-                                   ctypes.byref(out)))
+    if labels is None:
+        ctx.check(lib().bsim_summarize(ctx.handle, ctypes.byref(gs), ctypes.byref(params), None,
+                                       ctypes.byref(out)))
+    else:
+        ids = np.ascontiguousarray(np.asarray(list(labels), dtype=np.uint32).reshape(-1))
+        ctx.check(lib().bsim_summarize_labels(ctx.handle, ctypes.byref(gs), ctypes.byref(params),
+                                              ids.ctypes.data_as(_p) if ids.size else None, ids.size,
+                                              ctypes.byref(out)))
     return Result(out)
 
 

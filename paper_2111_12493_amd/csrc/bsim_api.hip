@@ -137,6 +137,25 @@ int bsim_summarize(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* pa
     }
 }
 
+int bsim_summarize_labels(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* params,
+                          const uint32_t* labels, uint32_t n_labels, bsim_result** out) {
+    if (out) *out = nullptr;
+    if (!ctx || !graph || !params || !out || (n_labels && !labels)) return BSIM_E_INVALID;
+    try {
+        hip_check(hipSetDevice(ctx->device), "set device");
+        const std::vector<uint32_t> keep(labels, labels + n_labels);
+        *out = summarize_graph(ctx, *graph, *params, &keep);
+        return BSIM_OK;
+    } catch (const DeviceError& e) {
+        ctx->err = e.msg;
+        (void)hipStreamSynchronize(ctx->stream);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        return BSIM_E_NOMEM;
+    }
+}
+
 namespace bsim {
 SharedArrays::~SharedArrays() {
     if (!device_ptrs.empty()) {

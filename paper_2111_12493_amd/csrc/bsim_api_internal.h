@@ -73,9 +73,10 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
 bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, const uint64_t* h,
                          FinalOut& fo, Arena& keep, uint32_t flags);
 
-// Whole batch path for one graph.
+// Whole batch path for one graph; labels = the kept label set of the label
+// parameterization (nullptr: every edge).
 bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,
-                             void* unused);
+                             const std::vector<uint32_t>* labels);
 
 // Many independent graphs in one refinement run (a disjoint union).
 void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t n_graphs, const bsim_params& p,
@@ -85,7 +86,9 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t n_graphs,
 int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,
                          bsim_state** state_out, bsim_result** out);
 
-void validate_params(const bsim_graph& graph, const bsim_params& p);
+// directions: whether the caller takes BSIM_BACKWARD / BSIM_BOTH_DIRECTIONS
+// (only the single-graph summarization does).
+void validate_params(const bsim_graph& graph, const bsim_params& p, bool directions = false);
 
 // Device bytes a resident state holds.
 uint64_t state_bytes(const bsim_state* st);

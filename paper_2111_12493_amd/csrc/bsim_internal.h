@@ -290,9 +290,13 @@ struct Staged {
     const uint8_t* alive = nullptr;
     const uint32_t* src = nullptr;   // per-edge source (COO), when there is no tile schedule
     uint32_t max_label = 0;
-    // the edges were checked when they entered a resident state: staging
-    // skips the per-edge pass and keeps max_label (an upper bound) as given
+    // the edges were checked before (a resident state's own CSR, or a view
+    // built from a staged graph): staging skips the per-edge pass and keeps
+    // max_label (an upper bound) as given
     bool trusted = false;
+    // labels >= in_label_base (when nonzero) stand for incoming edges of
+    // label l - in_label_base: salted as label l - in_label_base + 2^31
+    uint32_t in_label_base = 0;
     uint64_t* salt = nullptr;
     uint32_t n_tiles = 0;
     uint32_t* tile_i0 = nullptr;     // tile: positions [i0, i1) of `act`, edges [e0, e1)
@@ -327,6 +331,19 @@ struct Staged {
 // DeviceError with BSIM_E_INVALID / BSIM_E_RANGE on malformed input.
 void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena& arena,
                  hipStream_t s);
+
+// The graphs of the direction and label parameterizations (Sec. 2.4), built
+// on the device from a staged graph g: f = the edges whose label is in
+// *labels (all edges for labels == nullptr), with per-edge sources, for the
+// summary edges; h = the graph the signatures read (f, f reversed for
+// BSIM_BACKWARD, f plus f reversed on labels max_label + 1 + l for
+// BSIM_BOTH_DIRECTIONS), to be staged and refined.  Arrays live in arena.
+struct DirectedView {
+    Staged f;
+    Staged h;
+};
+void direction_view(const Staged& g, uint32_t flags, const std::vector<uint32_t>* labels, DirectedView& out,
+                    Arena& arena, hipStream_t s);
 
 // Per-run buffers of the refinement loop.
 struct RunBuffers {

@@ -301,9 +301,13 @@ __global__ void __launch_bounds__(kBlock) k_hub_starts(const uint32_t* __restric
     if (i < nh) start[i] = row_off[hubs[i]];
 }
 
-__global__ void __launch_bounds__(kBlock) k_salt(uint64_t* salt, uint32_t count) {
+// salt(l) = M(C_L + l); at and past in_base (when nonzero) the salts of
+// incoming edges: label in_base + l is salted as label l + 2^31
+__global__ void __launch_bounds__(kBlock) k_salt(uint64_t* salt, uint32_t count, uint32_t in_base) {
     uint32_t l = blockIdx.x * kBlock + threadIdx.x;
-    if (l < count) salt[l] = mix64(kCL + static_cast<uint64_t>(l));
+    if (l >= count) return;
+    const uint64_t x = (in_base && l >= in_base) ? 0x80000000ull + (l - in_base) : static_cast<uint64_t>(l);
+    salt[l] = mix64(kCL + x);
 }
 
 }  // namespace
@@ -478,7 +482,7 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
     // label salts
     uint32_t nsalt = g.max_label + 1;
     g.salt = arena.alloc<uint64_t>(nsalt);
-    k_salt<<<ceil_div(nsalt, kBlock), kBlock, 0, s>>>(g.salt, nsalt);
+    k_salt<<<ceil_div(nsalt, kBlock), kBlock, 0, s>>>(g.salt, nsalt, g.in_label_base);
     hip_check(hipGetLastError(), "salt launch");
 }
 

@@ -14,7 +14,7 @@
 
 namespace bsim {
 
-void validate_params(const bsim_graph& graph, const bsim_params& p) {
+void validate_params(const bsim_graph& graph, const bsim_params& p, bool directions) {
     if (graph.label_bytes != 2 && graph.label_bytes != 4)
         throw DeviceError{BSIM_E_INVALID, "label_bytes must be 2 or 4"};
     if (graph.mem_kind != BSIM_MEM_HOST && graph.mem_kind != BSIM_MEM_DEVICE)
@@ -30,8 +30,13 @@ void validate_params(const bsim_graph& graph, const bsim_params& p) {
     if (!(p.flags & BSIM_STOP_AT_FIXPOINT) && p.k_max > (1u << 24))
         throw DeviceError{BSIM_E_INVALID, "without a fixpoint test k_max must be finite (< 2^24)"};
     if (p.flags & ~(BSIM_STOP_AT_FIXPOINT | BSIM_KEEP_LEVELS | BSIM_UNTYPED | BSIM_RESULT_ON_HOST |
-                    BSIM_NO_SUMMARY_EDGES))
+                    BSIM_NO_SUMMARY_EDGES | BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS))
         throw DeviceError{BSIM_E_INVALID, "unknown flag bits"};
+    if ((p.flags & BSIM_BACKWARD) && (p.flags & BSIM_BOTH_DIRECTIONS))
+        throw DeviceError{BSIM_E_INVALID, "BSIM_BACKWARD and BSIM_BOTH_DIRECTIONS exclude each other"};
+    if (!directions && (p.flags & (BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS)))
+        throw DeviceError{BSIM_E_UNSUPPORTED, "edge directions other than outgoing are supported by "
+                                              "bsim_summarize without a state only"};
 }
 
 void upload_graph(const bsim_graph& in, Staged& g, Arena& arena, hipStream_t s) {
@@ -261,8 +266,9 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
     return r;
 }
 
-bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p, void*) {
-    validate_params(graph, p);
+bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,
+                             const std::vector<uint32_t>* labels) {
+    validate_params(graph, p, true);
     hipStream_t s = ctx->stream;
     Arena arena(s), keep(s);
     hipEvent_t ev[4];
@@ -279,13 +285,23 @@ bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_
     g.hub_table_slots = ctx->hub_table_slots;
     RunStatus* stage_status = arena.alloc<RunStatus>(1);
     stage_graph(g, stage_status, &ctx->status_host[3], arena, s);
+    // direction / label parameterizations: refine the view h, take the
+    // summary edges from the kept edges f
+    const bool view = labels || (p.flags & (BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS));
+    DirectedView dv;
+    if (view) {
+        direction_view(g, p.flags, labels, dv, arena, s);
+        stage_graph(dv.h, stage_status, &ctx->status_host[3], arena, s);
+    }
+    const Staged& gr = view ? dv.h : g;
+    const Staged& gf = view ? dv.f : g;
     RunBuffers rb;
-    alloc_run_buffers(g, p.k_max, (p.flags & BSIM_STOP_AT_FIXPOINT) != 0, rb, arena, s);
+    alloc_run_buffers(gr, p.k_max, (p.flags & BSIM_STOP_AT_FIXPOINT) != 0, rb, arena, s);
     hip_check(hipEventRecord(ev[1], s), "event");
-    LoopResult lr = run_refinement(ctx, g, p, rb, nullptr, arena);
+    LoopResult lr = run_refinement(ctx, gr, p, rb, nullptr, arena);
     hip_check(hipEventRecord(ev[2], s), "event");
     FinalOut fo;
-    finalize(g, rb.rep, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    finalize(gf, rb.rep, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
     if (fo.n_blocks != lr.blocks_per_iter.back())
         throw DeviceError{BSIM_E_DEVICE, "internal: class count mismatch in finalize"};
     bsim_result* r = make_result(ctx, g, lr, lr.h_final, fo, keep, p.flags);

@@ -1,0 +1,122 @@
+"""GPU parity for the direction and label parameterizations (Sec. 2.4;
+backward bisimulation, Sec. 2.5): bsim_summarize with BSIM_BACKWARD /
+BSIM_BOTH_DIRECTIONS and bsim_summarize_labels, through the C ABI, against
+the oracle's ``summarize_ext``, bit-exact on every output."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2111_12493_amd import binding
+from paper_2111_12493_amd import graphgen as gg
+
+from gpu_util import assert_same, ctx
+
+pytestmark = pytest.mark.gpu
+UNB = binding.K_UNBOUNDED
+
+
+def check_dir(g, k_max, stop=True, untyped=False, direction="out", labels=None, host_input=False,
+              u16=False, what=""):
+    ref = orc.summarize_ext(g, k_max if k_max != UNB else g.n + 2, stop, untyped, direction, labels)
+    src = gg.with_u16_labels(g) if u16 else g
+    graph = binding.HostGraph(src) if host_input else binding.DeviceGraph(src)
+    r = binding.summarize(ctx(), graph, k_max=k_max, stop_at_fixpoint=stop, untyped=untyped,
+                          direction=direction, labels=labels)
+    gpu = r.to_dict()
+    r.free()
+    assert_same(gpu, ref, (what, direction, labels))
+    return gpu, ref
+
+
+@pytest.mark.parametrize("direction", ["in", "both", "out"])
+def test_small_closed_forms(direction):
+    for L in (1, 7, 40):
+        gpu, _ = check_dir(gg.chain(L), UNB, untyped=True, direction=direction)
+        if direction == "in":
+            assert gpu["k_done"] == L + 1
+    for n in (1, 2, 9):
+        check_dir(gg.cycle(n), UNB, direction=direction)
+        check_dir(gg.cycle(n, marked=True), n + 3, stop=False, direction=direction)
+    check_dir(gg.out_star(9), UNB, untyped=True, direction=direction)
+    for D in (1, 4):
+        check_dir(gg.binary_tree(D), UNB, untyped=True, direction=direction)
+    for k in (0, 1, 2, 5):
+        check_dir(gg.paper_example(), k, stop=False, direction=direction, labels=[0, 2])
+
+
+def test_star_with_a_label_set_matches_the_closed_form():
+    g = gg.from_edges(9, [0] * 8, list(range(1, 9)), [0] * 4 + [1] * 4)
+    gpu, _ = check_dir(g, 3, stop=False, untyped=True, direction="both", labels=[0])
+    assert list(gpu["block_ids"]) == [0, 1, 1, 1, 1, 2, 2, 2, 2]
+
+
+def test_empty_edgeless_and_everything_filtered():
+    for direction in ("in", "both", "out"):
+        check_dir(gg.from_edges(0, [], [], []), UNB, direction=direction)
+        check_dir(gg.from_edges(5, [], [], [], types=[[i % 2] for i in range(5)]), UNB, direction=direction)
+        g = gg.from_edges(6, [0, 1, 2, 3], [1, 2, 3, 4], [1, 1, 2, 2])
+        for labels in ([], [7], [2], [1, 2, 2, 99]):
+            check_dir(g, UNB, direction=direction, labels=labels, what="filter")
+
+
+@pytest.mark.parametrize("direction", ["in", "both", "out"])
+def test_random_small_graphs(direction):
+    rng = np.random.default_rng(301 + len(direction))
+    for trial in range(60):
+        n = int(rng.integers(1, 60))
+        g = gg.random_small_graph(rng, n, int(rng.integers(0, 5 * n + 1)), int(rng.integers(1, 5)),
+                                  int(rng.integers(1, 5)), 3, p_alive=1.0 if trial % 3 else 0.75)
+        stop = trial % 4 != 0
+        k = UNB if stop else int(rng.integers(0, 6))
+        labels = [None, [0], [1, 3], [0, 1, 2, 3]][trial % 4]
+        if direction == "out" and labels is None:
+            labels = [2]
+        check_dir(g, k, stop=stop, untyped=bool(trial % 5 == 0), direction=direction, labels=labels,
+                  host_input=trial % 7 == 0, u16=trial % 6 == 0, what=("random", trial))
+
+
+def test_hubs_in_either_direction():
+    # vertex 0: 20,000 out-edges; vertex 1: 15,000 in-edges (a hub once the
+    # edges are reversed); vertex 2: 4,000 each way
+    rng = np.random.default_rng(7)
+    n = 30000
+    src = [0] * 20000 + list(range(2, 15002)) + [2] * 4000 + list(range(5000, 9000))
+    dst = list(range(1, 20001)) + [1] * 15000 + list(range(10000, 14000)) + [2] * 4000
+    lab = rng.integers(0, 6, len(src)).tolist()
+    types = [[int(x)] for x in rng.integers(0, 4, n)]
+    g = gg.from_edges(n, src, dst, lab, types=types)
+    for direction in ("in", "both"):
+        check_dir(g, UNB, direction=direction, what="hubs")
+        check_dir(g, 3, stop=False, direction=direction, labels=[0, 1, 5], u16=True, what="hubs filtered")
+
+
+@pytest.mark.parametrize("direction", ["in", "both"])
+def test_rmat_graph(direction):
+    g = gg.rmat_graph(15, 1 << 18, n_types=32, n_labels=16, seed=9)
+    check_dir(g, UNB, direction=direction, u16=True, what="rmat15")
+    check_dir(g, 4, stop=False, direction=direction, labels=list(range(0, 16, 3)), what="rmat15 filtered")
+
+
+def test_invalid_and_unsupported_combinations():
+    g = binding.DeviceGraph(gg.from_edges(3, [0, 1], [1, 2], [0, 0]))
+    gs = g.struct()
+    out = ctypes.POINTER(binding.BsimResult)()
+    both = binding.BsimParams(3, binding.BACKWARD | binding.BOTH_DIRECTIONS)
+    rc = binding.lib().bsim_summarize(ctx().handle, ctypes.byref(gs), ctypes.byref(both), None, ctypes.byref(out))
+    assert rc == binding.E_INVALID
+    rc = binding.lib().bsim_summarize_labels(ctx().handle, ctypes.byref(gs),
+                                             ctypes.byref(binding.BsimParams(3, 0)), None, 2, ctypes.byref(out))
+    assert rc == binding.E_INVALID
+    st = ctypes.c_void_p()
+    back = binding.BsimParams(3, binding.BACKWARD)
+    rc = binding.lib().bsim_summarize(ctx().handle, ctypes.byref(gs), ctypes.byref(back), ctypes.byref(st),
+                                      ctypes.byref(out))
+    assert rc == binding.E_UNSUPPORTED
+    # an edge into a dead vertex is rejected before any view is built
+    bad = gg.from_edges(3, [0], [1], [0], alive=np.array([1, 0, 1], dtype=np.uint8))
+    with pytest.raises(binding.BsimError) as err:
+        binding.summarize(ctx(), binding.DeviceGraph(bad), direction="both")
+    assert err.value.status == binding.E_INVALID
