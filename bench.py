@@ -203,6 +203,33 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
             "plain_form": "same update batch, every level recomputed for all vertices"}
 
 
+def directions_leg(binding, torch, ctx, dg, g):
+    """The direction and label parameterizations (Sec. 2.4) on the headline
+    graph, each to its fixpoint after one untimed run: backward (incoming
+    edges), both directions, and forward over the even labels.  The rate
+    counts the edges each signature reads (2|E| for both directions)."""
+    import numpy as np
+
+    even = list(range(0, max(int(g.n_labels), 1), 2))
+    kept = int(np.isin(g.lab, np.asarray(even, dtype=g.lab.dtype)).sum())
+    out = {}
+    for name, kw, edges in (("backward", dict(direction="in"), g.m), ("both", dict(direction="both"), 2 * g.m),
+                            ("even_labels", dict(labels=even), kept)):
+        binding.summarize(ctx, dg, k_max=binding.K_UNBOUNDED, **kw).free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = binding.summarize(ctx, dg, k_max=binding.K_UNBOUNDED, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"k_done": r.k_done, "blocks": r.n_blocks, "edges_read": edges, "s": wall,
+                     "edge_iterations_per_s": r.k_done * edges / wall,
+                     "ms_stage": r.ms_stage, "ms_iterate": r.ms_iterate}
+        r.free()
+        print("# %s: k_done=%d blocks=%d %.3f s" % (name, out[name]["k_done"], out[name]["blocks"], wall),
+              file=sys.stderr, flush=True)
+    return out
+
+
 def batched_leg(args, binding, gg, torch):
     """One batched run over many R-MAT graphs against one call per graph."""
     from paper_2111_12493_amd import devgen
@@ -258,6 +285,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-edges", type=float, default=1e7)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-directions", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-max-edges", type=float, default=1e6)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -359,6 +387,8 @@ def main() -> int:
                      "avg_launch_us": avg_us, "timed_launches": timed, "working_launches": working,
                      "launches_issued": launches, "hub_kernel_avg_us": hub_ms * 1e3 / max(timed, 1)},
     }
+    if not args.no_directions:
+        out["directions"] = directions_leg(binding, torch, ctx, dg, g)
     ctx.close()
     del dg
     if not args.no_cpu_baseline:

@@ -324,6 +324,25 @@ def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: b
     return Result(out)
 
 
+# The summary models of the paper's experiments as parameters of the same
+# refinement (no stop test, exact k):
+#   class collection      vertices with the same type set (k = 0);
+#   attribute collection  vertices with the same set of outgoing edge labels
+#                         (untyped, k = 1);
+#   SchemEX               the same type set and the same (edge label,
+#                         neighbour type set) pairs (typed, k = 1).
+SUMMARY_MODELS = {
+    "class_collection": dict(k_max=0, untyped=False),
+    "attribute_collection": dict(k_max=1, untyped=True),
+    "schemex": dict(k_max=1, untyped=False),
+}
+
+
+def summarize_model(ctx: Context, graph, model: str, **kw) -> Result:
+    """bsim_summarize with the parameters of one of SUMMARY_MODELS."""
+    return summarize(ctx, graph, stop_at_fixpoint=False, **SUMMARY_MODELS[model], **kw)
+
+
 # ---------------------------------------------------------------- update batches
 
 UPDATE_DTYPE = np.dtype({"names": ["op", "u", "w", "label", "new_label", "n_types", "types"],

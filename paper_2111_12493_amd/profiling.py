@@ -148,17 +148,17 @@ def report(workload: str, k_done: int, algo_bytes: int, trace_csv: str, fetch_cs
 
 
 COMMANDS = """    rocprofv3 --kernel-trace --stats -d {d}/stats -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --steps 2 --warmup 1
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 2 --warmup 1
     rocprofv3 --pmc FETCH_SIZE -d {d}/fetch -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --steps 1 --warmup 0 --calibrate-copy 1024
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0 --calibrate-copy 1024
     rocprofv3 --pmc WRITE_SIZE -d {d}/write -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --steps 1 --warmup 0 --calibrate-copy 1024
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0 --calibrate-copy 1024
     rocprofv3 --pmc SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_INSTS_VALU \\
         SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT -d {d}/sq1 -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --steps 1 --warmup 0
+        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0
     rocprofv3 --pmc SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS \\
         SQ_ACTIVE_INST_VMEM SQ_INST_CYCLES_VMEM_RD GRBM_GUI_ACTIVE TCC_HIT -d {d}/sq2 -o run \\
-        --output-format csv -- python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --steps 1 --warmup 0
+        --output-format csv -- python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0
 """
 
 
