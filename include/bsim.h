@@ -217,6 +217,21 @@ int bsim_summarize_labels(bsim_ctx* ctx, const bsim_graph* graph, const bsim_par
                           const uint32_t* labels, uint32_t n_labels, bsim_result** out);
 void bsim_result_free(bsim_result* result);
 
+/*
+ * Source-label payload (Sec. 3.3: a payload function may memorize the source
+ * label of a vertex; merging vertices into one block joins their source
+ * lists).  For result's block ids and source_labels[n_vertices] (one label
+ * per vertex, any uint32 value), writes the distinct (block, source label)
+ * pairs over the alive vertices, sorted by (block, label), to
+ * out_block[] / out_label[] and their number to *n_pairs.  source_labels and
+ * the two outputs are host or device pointers as mem_kind says; the outputs
+ * must hold result->n_vertices entries (an upper bound).  Caller-owned
+ * memory throughout.  BSIM_E_INVALID for a NULL pointer or an unknown
+ * mem_kind.
+ */
+int bsim_source_payload(bsim_ctx* ctx, const bsim_result* result, const uint32_t* source_labels,
+                        uint32_t mem_kind, uint32_t* out_block, uint32_t* out_label, uint64_t* n_pairs);
+
 /* Copy one result array to caller memory (host or device pointer, as
  * dst_mem_kind says).  `field` is one of "hashes", "block_ids",
  * "block_sizes", "se_src", "se_label", "se_dst". */

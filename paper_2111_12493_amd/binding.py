@@ -83,6 +83,8 @@ EXPORTS = {
                                       ctypes.POINTER(_p), ctypes.POINTER(ctypes.POINTER(BsimResult))]),
     "bsim_summarize_labels": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), ctypes.POINTER(BsimParams),
                                              _p, _u32, ctypes.POINTER(ctypes.POINTER(BsimResult))]),
+    "bsim_source_payload": (ctypes.c_int, [_p, ctypes.POINTER(BsimResult), _p, _u32, _p, _p,
+                                           ctypes.POINTER(_u64)]),
     "bsim_result_free": (None, [ctypes.POINTER(BsimResult)]),
     "bsim_result_copy": (ctypes.c_int, [ctypes.POINTER(BsimResult), ctypes.c_char_p, _p, _u32]),
     "bsim_apply_updates": (ctypes.c_int, [_p, ctypes.POINTER(BsimUpdate), _u64,
@@ -322,6 +324,21 @@ def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: b
                                               ids.ctypes.data_as(_p) if ids.size else None, ids.size,
                                               ctypes.byref(out)))
     return Result(out)
+
+
+def source_payload(ctx: Context, result: "Result", source_labels):
+    """bsim_source_payload with host arrays: the distinct (block, source
+    label) pairs of a result, sorted, as two numpy uint32 arrays."""
+    n = result.n_vertices
+    lab = np.ascontiguousarray(np.asarray(source_labels, dtype=np.uint32).reshape(-1))
+    if lab.size != n:
+        raise ValueError("one source label per vertex")
+    ob = np.zeros(max(n, 1), dtype=np.uint32)
+    ol = np.zeros(max(n, 1), dtype=np.uint32)
+    cnt = _u64()
+    ctx.check(lib().bsim_source_payload(ctx.handle, result.ptr, lab.ctypes.data_as(_p), MEM_HOST,
+                                        ob.ctypes.data_as(_p), ol.ctypes.data_as(_p), ctypes.byref(cnt)))
+    return ob[:cnt.value].copy(), ol[:cnt.value].copy()
 
 
 # The summary models of the paper's experiments as parameters of the same
