@@ -150,3 +150,62 @@ def replay_rows(g: Graph, ops, vertices):
     for v, r in rows.items():
         out[v] = sorted(e for e, c in r.items() for _ in range(c) if alive[e[1]])
     return out, {v: sorted(t) for v, t in types.items()}, {v: bool(alive[v]) for v in want if v < len(alive)}
+
+
+def diff_snapshots(before: Graph, after: Graph):
+    """Change detection from two snapshots without a change log: the ordered
+    batch that turns ``before`` into ``after`` (equal alive flags, type sets
+    and sets of edge triples).  Vertex ids are shared; ids before.n ..
+    after.n - 1 are new vertices.  The batch, in this order:
+
+      add_v  for every new id, ascending, with after's stored type list;
+      mod_v  for every vertex alive in both whose type *set* changed, with
+             after's stored type list;
+      del_e  for every distinct triple of before absent from after whose two
+             endpoints stay alive, in order of its first copy in before;
+      add_e  for every distinct triple of after absent from before, in order
+             of its first copy in after;
+      del_v  for every vertex alive in before (or new) and dead in after.
+
+    Edges of a deleted vertex go with its del_v.  A vertex dead in before
+    and alive in after cannot arise from updates (ids are never reused):
+    ValueError, as for after.n < before.n."""
+    n0, n1 = before.n, after.n
+    if n1 < n0:
+        raise ValueError("the later snapshot has fewer vertex ids")
+
+    def alive(g, v):
+        return g.alive is None or bool(g.alive[v])
+
+    def types(g, v):
+        return [int(x) for x in g.typ[int(g.typ_off[v]):int(g.typ_off[v + 1])]]
+
+    def triples(g):
+        seen, order = set(), []
+        for u in range(g.n):
+            for e in range(int(g.row_off[u]), int(g.row_off[u + 1])):
+                t = (u, int(g.lab[e]), int(g.tgt[e]))
+                if t not in seen:
+                    seen.add(t)
+                    order.append(t)
+        return seen, order
+
+    for v in range(n0):
+        if not alive(before, v) and alive(after, v):
+            raise ValueError("vertex %d is dead before and alive after" % v)
+    ops = [("add_v", types(after, v)) for v in range(n0, n1)]
+    for v in range(n0):
+        if alive(before, v) and alive(after, v) and set(types(before, v)) != set(types(after, v)):
+            ops.append(("mod_v", v, types(after, v)))
+    sb, ob = triples(before)
+    sa, oa = triples(after)
+    for (u, l, w) in ob:
+        if (u, l, w) not in sa and alive(after, u) and alive(after, w):
+            ops.append(("del_e", u, l, w))
+    for (u, l, w) in oa:
+        if (u, l, w) not in sb:
+            ops.append(("add_e", u, l, w))
+    for v in range(n1):
+        if (v >= n0 or alive(before, v)) and not alive(after, v):
+            ops.append(("del_v", v))
+    return ops
