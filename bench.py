@@ -188,6 +188,15 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
         ops_total += size
         print("# update batch %d: %d ops, incremental %.2f ms, full recomputation %.2f ms"
               % (i, size, lat_i[-1], lat_p[-1]), file=sys.stderr, flush=True)
+
+    # change detection: the ordered batch between the first snapshot and
+    # the state's graph after all batches, from the two device CSRs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_diff = binding.diff_snapshots(ctx_i, dg, st_i.device_graph(), as_tuples=False)
+    torch.cuda.synchronize()
+    diff_ms = (time.perf_counter() - t0) * 1e3
+    print("# snapshot diff: %d ops in %.1f ms" % (n_diff, diff_ms), file=sys.stderr, flush=True)
     st_i.free()
     st_p.free()
     ctx_i.close()
@@ -200,6 +209,9 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
             "batches": len(lat_i), "ops": ops_total, "p50_ms": p50, "p99_ms": p99,
             "plain_p50_ms": q50, "plain_p99_ms": q99, "speedup_p50": q50 / p50, "speedup_p99": q99 / p99,
             "state_create_s": create_s, "summary_edges": False,
+            "snapshot_diff": {"ops": n_diff, "ms": diff_ms,
+                              "what": "bsim_diff_snapshots between the first snapshot and the graph after "
+                                      "all batches"},
             "plain_form": "same update batch, every level recomputed for all vertices"}
 
 

@@ -261,6 +261,30 @@ int bsim_state_device_graph(const bsim_state* state, bsim_graph* out_device_grap
 void bsim_host_free(void* p);
 void bsim_state_free(bsim_state* state);
 
+/*
+ * Change detection from two snapshots without a change log (Sec. 3.2's
+ * change classes between the graph at time t and at t+1).  The snapshots
+ * share vertex ids: after has at least before's n_vertices, and the ids past
+ * them are new vertices.  *ops receives the ordered batch that turns before
+ * into after under bsim_apply_updates' semantics (equal alive masks, type
+ * sets and sets of edge triples), *n_ops its length:
+ *   ADD_V  each new id in ascending order, with after's type list;
+ *   MOD_V  each vertex alive in both whose type set changed (after's list);
+ *   DEL_E  each distinct triple of before that after lacks, both endpoints
+ *          alive in after, in order of its first copy in before;
+ *   ADD_E  each distinct triple of after that before lacks, in order of its
+ *          first copy in after;
+ *   DEL_V  each vertex alive in before (or new) and dead in after.
+ * Edges of a vertex that dies go with its DEL_V.  The batch is host memory
+ * the library allocates (the type lists live in the same block); free it
+ * with bsim_updates_free.  Inputs are host or device graphs (mem_kind).
+ * BSIM_E_INVALID: a malformed snapshot, fewer ids after, or a vertex dead
+ * before and alive after (ids are never reused).
+ */
+int bsim_diff_snapshots(bsim_ctx* ctx, const bsim_graph* before, const bsim_graph* after, bsim_update** ops,
+                        uint64_t* n_ops);
+void bsim_updates_free(bsim_update* ops);
+
 /* ---- batched summarization (many independent graphs, one launch stream) -- */
 
 /*

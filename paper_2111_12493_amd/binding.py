@@ -85,6 +85,9 @@ EXPORTS = {
                                              _p, _u32, ctypes.POINTER(ctypes.POINTER(BsimResult))]),
     "bsim_source_payload": (ctypes.c_int, [_p, ctypes.POINTER(BsimResult), _p, _u32, _p, _p,
                                            ctypes.POINTER(_u64)]),
+    "bsim_diff_snapshots": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), ctypes.POINTER(BsimGraph),
+                                           ctypes.POINTER(ctypes.POINTER(BsimUpdate)), ctypes.POINTER(_u64)]),
+    "bsim_updates_free": (None, [ctypes.POINTER(BsimUpdate)]),
     "bsim_result_free": (None, [ctypes.POINTER(BsimResult)]),
     "bsim_result_copy": (ctypes.c_int, [ctypes.POINTER(BsimResult), ctypes.c_char_p, _p, _u32]),
     "bsim_apply_updates": (ctypes.c_int, [_p, ctypes.POINTER(BsimUpdate), _u64,
@@ -324,6 +327,41 @@ def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: b
                                               ids.ctypes.data_as(_p) if ids.size else None, ids.size,
                                               ctypes.byref(out)))
     return Result(out)
+
+
+def diff_snapshots(ctx: Context, before, after, as_tuples: bool = True):
+    """bsim_diff_snapshots on two snapshots (DeviceGraph, HostGraph or a
+    BsimGraph such as State.device_graph()): the
+    ordered batch as tuples, ("add_v", types), ("mod_v", u, types),
+    ("del_e", u, l, w), ("add_e", u, l, w), ("del_v", u); with as_tuples
+    False only the number of operations."""
+    gb = before if isinstance(before, BsimGraph) else before.struct()
+    ga = after if isinstance(after, BsimGraph) else after.struct()
+    ops = ctypes.POINTER(BsimUpdate)()
+    n = _u64()
+    ctx.check(lib().bsim_diff_snapshots(ctx.handle, ctypes.byref(gb), ctypes.byref(ga), ctypes.byref(ops),
+                                        ctypes.byref(n)))
+    out = []
+    try:
+        if not as_tuples:
+            return n.value
+        for i in range(n.value):
+            o = ops[i]
+            types = [int(o.types[j]) for j in range(o.n_types)]
+            if o.op == OP_ADD_V:
+                out.append(("add_v", types))
+            elif o.op == OP_MOD_V:
+                out.append(("mod_v", int(o.u), types))
+            elif o.op == OP_DEL_V:
+                out.append(("del_v", int(o.u)))
+            elif o.op == OP_DEL_E:
+                out.append(("del_e", int(o.u), int(o.label), int(o.w)))
+            else:
+                out.append(("add_e", int(o.u), int(o.label), int(o.w)))
+    finally:
+        if ops:
+            lib().bsim_updates_free(ops)
+    return out
 
 
 def source_payload(ctx: Context, result: "Result", source_labels):
