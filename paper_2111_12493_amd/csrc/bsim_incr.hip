@@ -798,7 +798,9 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
         b->ensure(nv, 0, s);
     st->big.ensure(nv, 0, s);
     st->big_acc.ensure(nv, 0, s);
-    const uint32_t want = next_pow2(std::max<uint64_t>(2ull * n_new, 1024));
+    // at most n joins per level: load <= 2/3, and a table small enough to
+    // stay mostly in the last-level cache for the class passes' random CAS
+    const uint32_t want = next_pow2(std::max<uint64_t>(static_cast<uint64_t>(n_new) + n_new / 2 + 1, 1024));
     if (want > st->cls_cap) {
         if (st->cls_slots) (void)hipFreeAsync(st->cls_slots, s);
         if (st->cls_list) (void)hipFreeAsync(st->cls_list, s);
