@@ -67,8 +67,9 @@ extern "C" {
  * BSIM_BOTH_DIRECTIONS: both kinds in one set, an incoming l-edge salted as
  * an outgoing edge of label l + 2^31 would be, M(C_L + 2^31 + l).  The two
  * flags exclude each other; summary edges keep the edges' own direction.
- * bsim_summarize / bsim_summarize_labels without a state only (a batch, a
- * state or a server request with them gives BSIM_E_UNSUPPORTED). */
+ * bsim_summarize / bsim_summarize_labels, bsim_batch_summarize and server
+ * summarize requests, without a state only (a state or a keep_state request
+ * with them gives BSIM_E_UNSUPPORTED). */
 #define BSIM_BACKWARD 32u
 #define BSIM_BOTH_DIRECTIONS 64u
 

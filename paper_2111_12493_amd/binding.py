@@ -547,11 +547,12 @@ class _Borrowed:
 
 def batch_summarize(ctx: Context, graphs: Sequence, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
                     untyped: bool = False, summary_edges: bool = True,
-                    result_on_host: bool = False) -> List[Result]:
+                    result_on_host: bool = False, direction: str = "out") -> List[Result]:
     """bsim_batch_summarize: one refinement run over many graphs (all
     DeviceGraph or all HostGraph, same label width); one Result per graph."""
     flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
-            (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0)
+            (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0) | \
+            DIRECTION_FLAGS[direction]
     G = len(graphs)
     arr = (BsimGraph * max(G, 1))(*[g.struct() for g in graphs])
     outs = (ctypes.POINTER(BsimResult) * max(G, 1))()
@@ -576,9 +577,10 @@ class Server:
         self._keep = {}
 
     def submit_summarize(self, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
-                         untyped: bool = False, summary_edges: bool = True, keep_state: bool = False) -> int:
+                         untyped: bool = False, summary_edges: bool = True, keep_state: bool = False,
+                         direction: str = "out") -> int:
         flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
-                (0 if summary_edges else NO_SUMMARY_EDGES)
+                (0 if summary_edges else NO_SUMMARY_EDGES) | DIRECTION_FLAGS[direction]
         gs = graph.struct()
         req = BsimRequest(REQ_SUMMARIZE, 1 if keep_state else 0, ctypes.pointer(gs), BsimParams(int(k_max), flags),
                           None, None, 0)

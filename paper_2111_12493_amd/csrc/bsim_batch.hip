@@ -244,7 +244,7 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const 
                      bsim_result** outs) {
     hipStream_t s = ctx->stream;
     for (uint32_t g = 0; g < G; g++) {
-        validate_params(graphs[g], p);
+        validate_params(graphs[g], p, true);
         if (graphs[g].label_bytes != graphs[0].label_bytes || graphs[g].mem_kind != graphs[0].mem_kind)
             throw DeviceError{BSIM_E_INVALID, "all graphs of a batch need the same label_bytes and mem_kind"};
     }
@@ -264,9 +264,19 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const 
     build_union(graphs, G, u, gid, ustat, &ctx->status_host[3], arena, s);
     u.hub_table_slots = ctx->hub_table_slots;
     stage_graph(u, ustat, &ctx->status_host[3], arena, s);
+    // direction parameterization: the view of a disjoint union is the
+    // disjoint union of the graphs' views
+    const bool view = (p.flags & (BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS)) != 0;
+    DirectedView dv;
+    if (view) {
+        direction_view(u, p.flags, nullptr, dv, arena, s);
+        stage_graph(dv.h, ustat, &ctx->status_host[3], arena, s);
+    }
+    const Staged& ur = view ? dv.h : u;
+    const Staged& uf = view ? dv.f : u;
     const bool stop = (p.flags & BSIM_STOP_AT_FIXPOINT) != 0;
     RunBuffers rb;
-    alloc_run_buffers(u, p.k_max, stop, rb, arena, s);
+    alloc_run_buffers(ur, p.k_max, stop, rb, arena, s);
     rb.bc.gid = gid;
     rb.bc.n_graphs = G;
     rb.bc.virt_base = u.n;
@@ -280,7 +290,7 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const 
     hip_check(hipMemsetAsync(rb.bc.n_done, 0, 4, s), "done count");
     hip_check(hipMemsetAsync(rb.bc.hist, 0, static_cast<size_t>(rb.bc.hist_cap) * G * 4, s), "history");
     hip_check(hipEventRecord(ev[1], s), "event");
-    LoopResult lr = run_refinement(ctx, u, p, rb, nullptr, arena);
+    LoopResult lr = run_refinement(ctx, ur, p, rb, nullptr, arena);
     hip_check(hipEventRecord(ev[2], s), "event");
 
     // per-graph stop levels and class counts
@@ -303,7 +313,7 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const 
 
     Arena keep(s);
     FinalOut fo;
-    finalize(u, rb.rep, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    finalize(uf, rb.rep, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
     if (fo.n_blocks != bbase[G]) throw DeviceError{BSIM_E_DEVICE, "internal: class count mismatch in batch finalize"};
     uint64_t* d_bbase = upload_vec(arena, bbase, s);
     uint64_t* hashes = keep.alloc<uint64_t>(u.n + 1ull);

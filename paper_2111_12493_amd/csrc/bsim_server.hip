@@ -64,6 +64,10 @@ uint64_t summarize_footprint(const bsim_graph& g, const bsim_params& p, bool kee
     uint64_t b = m * (4 + lb + 8) + n * 160 + (1u << 20);
     if (g.mem_kind == BSIM_MEM_HOST) b += m * (4 + lb) + n * 16;
     if (edges) b += m * 36;
+    // the direction view: kept edges with sources, and the view itself (2m
+    // edges for both directions) staged a second time
+    if (p.flags & (BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS))
+        b += m * (12 + lb) + ((p.flags & BSIM_BOTH_DIRECTIONS) ? 2 : 1) * m * (4 + 4 + 8) + n * 48;
     if (keep) {
         const uint64_t K = std::min<uint64_t>(p.k_max, 4096);
         b += m * (2 * (8 + lb) + 16 + 36) + n * (8 * (K + 1) + 140);
@@ -216,7 +220,8 @@ int bsim_server_submit(bsim_server* s, const bsim_request* req, uint64_t* ticket
         if (req->kind == BSIM_REQ_SUMMARIZE) {
             if (!req->graph) return BSIM_E_INVALID;
             const bsim_graph& g = *req->graph;
-            validate_params(g, req->params);
+            // a direction flag takes a view of the graph: no resident state
+            validate_params(g, req->params, !req->keep_state);
             r.keep_state = req->keep_state ? 1 : 0;
             r.params = req->params;
             r.graph = g;

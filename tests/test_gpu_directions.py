@@ -120,3 +120,18 @@ def test_invalid_and_unsupported_combinations():
     with pytest.raises(binding.BsimError) as err:
         binding.summarize(ctx(), binding.DeviceGraph(bad), direction="both")
     assert err.value.status == binding.E_INVALID
+
+
+@pytest.mark.parametrize("direction", ["in", "both"])
+def test_batched_graphs_in_either_direction(direction):
+    # one batched run; each graph's result equals the oracle on that graph
+    rng = np.random.default_rng(401 + len(direction))
+    graphs = [gg.random_small_graph(rng, int(rng.integers(1, 60)), int(rng.integers(0, 200)), 3, 3, 2,
+                                    p_alive=1.0 if i % 3 else 0.8) for i in range(30)]
+    graphs.append(gg.rmat_graph(12, 1 << 15, n_types=8, n_labels=6, seed=4))
+    graphs.append(gg.chain(60))
+    rs = binding.batch_summarize(ctx(), [binding.DeviceGraph(g) for g in graphs], direction=direction)
+    for i, (g, r) in enumerate(zip(graphs, rs)):
+        got = r.to_dict()
+        r.free()
+        assert_same(got, orc.summarize_ext(g, g.n + 2, True, False, direction), ("batched", direction, i))

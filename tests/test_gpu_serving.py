@@ -120,3 +120,23 @@ def test_failed_request_reports_its_error():
         assert_same(fetch(srv.poll(t2)[0]), orc.summarize(good, good.n + 2, True))
     finally:
         srv.free()
+
+
+def test_direction_requests_in_the_mix():
+    # summarize requests with the direction parameterization, served together,
+    # each equal to the oracle; a state cannot take a direction flag
+    rng = np.random.default_rng(61)
+    graphs = [gg.rmat_graph(int(rng.integers(8, 12)), int(rng.integers(1000, 20000)), n_types=8, n_labels=6,
+                            seed=int(rng.integers(1, 1 << 30))) for _ in range(9)]
+    dirs = ["in", "both", "out"] * 3
+    srv = binding.Server(workers=4)
+    try:
+        tickets = [srv.submit_summarize(binding.HostGraph(g), k_max=UNB, direction=d) for g, d in zip(graphs, dirs)]
+        for g, d, t in zip(graphs, dirs, tickets):
+            got = fetch(srv.poll(t)[0])
+            assert_same(got, orc.summarize_ext(g, g.n + 2, True, False, d), ("serving", d))
+        with pytest.raises(binding.BsimError):
+            srv.submit_summarize(binding.HostGraph(graphs[0]), k_max=3, stop_at_fixpoint=False, keep_state=True,
+                                 direction="in")
+    finally:
+        srv.free()
