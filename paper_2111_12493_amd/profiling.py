@@ -6,6 +6,13 @@
     python -m paper_2111_12493_amd.profiling summary <dir> <workload> <k_done> <algorithmic_bytes> <calib_bytes> <out_dir>
     python -m paper_2111_12493_amd.profiling report <workload> <k_done> <algorithmic_bytes>
         <kernel_trace.csv> <fetch_counters.csv> <write_counters.csv> <calib_bytes> <out.json>
+    python -m paper_2111_12493_amd.profiling updates <incremental|plain> <batches>
+    python -m paper_2111_12493_amd.profiling summary-updates <dir> <batches> <out_dir>
+
+`updates` runs the update workload (the resident rmat24 state, k = 4, the
+bench's seeded batches of 10^3-10^6 operations) in one form, for a profiler
+to wrap; `summary-updates` turns the two kernel-stat tables
+(<dir>/incremental, <dir>/plain) into profiles/updates_rmat24.md.
 
 `trace` splits the dispatch sequence into summarization runs (one k_init
 dispatch starts each run) and averages each kernel over the launches that
@@ -210,7 +217,84 @@ def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: in
     return path
 
 
+UPDATE_COMMAND = """    rocprofv3 --kernel-trace --stats -d {d}/{form} -o run --output-format csv -- \\
+        python -u -m paper_2111_12493_amd.profiling updates {form} {batches}"""
+
+
+def run_updates(form: str, batches: int) -> None:
+    """The update workload of the bench's incremental leg, one form only."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import binding, devgen
+    from . import graphgen as gg
+
+    dg = devgen.make_device_config("rmat24")
+    g = dg.to_host()
+    ctx = binding.Context(0)
+    if form == "plain":
+        ctx.set_option("frontier_limit_pct", 0)
+    st = binding.State(ctx, dg, 4, stop_at_fixpoint=False, summary_edges=False)
+    st.result.free()
+    rng = np.random.default_rng(17)
+    dead = np.zeros(g.n + 4_000_000, dtype=bool)
+    n = g.n
+    for i in range(batches):
+        size = int(round(10 ** rng.uniform(3, 6)))
+        d = gg.sample_update_ops(g.row_off, g.tgt, g.lab, n, dead, rng, size, max(g.n_labels, 1),
+                                 max(g.n_types, 1), rmat_scale=24)
+        n = d["n_after"]
+        batch = binding.UpdateBatch.from_op_arrays(d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = st.apply(batch)
+        wall = (time.perf_counter() - t0) * 1e3
+        print("%s batch %d (%d ops): %.2f ms | merge %.2f, levels %.2f, classes+final %.2f"
+              % (form, i, size, wall, r.ms_stage, r.ms_iterate, r.ms_finalize), file=sys.stderr, flush=True)
+        r.free()
+    st.free()
+    ctx.close()
+
+
+def summary_updates(d: str, batches: int, out_dir: str) -> str:
+    lines = ["# Update batches on the resident rmat24 state (k = 4)", "",
+             "2^24 vertices, 2^27 edges (R-MAT, drawn on the GPU), the bench's seeded batches of "
+             "log-uniform 10^3-10^6 operations; one process per form.  The tables cover the whole "
+             "process: graph generation (torch kernels, not listed), the state's creation (one "
+             "refinement of levels 1-4 and its class passes) and %d update batches." % batches, "",
+             "## Commands (repository root, one MI355X)", ""]
+    for form in ("incremental", "plain"):
+        lines.append(UPDATE_COMMAND.format(d=d, form=form, batches=batches))
+    lines.append("")
+    for form in ("incremental", "plain"):
+        path = os.path.join(d, form, "run_kernel_stats.csv")
+        rows = [r for r in csv.DictReader(open(path)) if short(r["Name"]).startswith("k_")]
+        total = sum(int(r["TotalDurationNs"]) for r in rows)
+        lines += ["## %s form: library kernels" % form, "",
+                  "```", "%-28s %7s %11s %10s %13s" % ("kernel", "calls", "total_ms", "avg_us", "ms/update"),
+                  "%-28s %7s %11.2f" % ("(all library kernels)", "", total / 1e6)]
+        for r in rows[:16]:
+            t = int(r["TotalDurationNs"])
+            lines.append("%-28s %7s %11.2f %10.1f %13.2f" % (short(r["Name"]), r["Calls"], t / 1e6,
+                                                            float(r["AverageNs"]) / 1e3, t / 1e6 / (batches + 1)))
+        lines += ["```", ""]
+    lines.append("ms/update divides by the batches plus the creation, which does the same kinds of work once.")
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "updates_rmat24.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
+
+
 def main(argv):
+    if argv[1] == "updates":
+        run_updates(argv[2], int(argv[3]))
+        return
+    if argv[1] == "summary-updates":
+        print(summary_updates(argv[2], int(argv[3]), argv[4]))
+        return
     if argv[1] == "summary":
         print(summary(argv[2], argv[3], int(argv[4]), int(argv[5]), int(argv[6]), argv[7]))
         return
