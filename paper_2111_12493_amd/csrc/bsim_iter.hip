@@ -297,8 +297,10 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
         w[r] = 0;
         l[r] = 0;
         if (hash && j < ne) {
-            w[r] = a.tgt[ebase + j];
-            l[r] = static_cast<uint32_t>(lab[ebase + j]);
+            // targets and labels are read once per launch: non-temporal, so
+            // they do not push the gathered hashes out of L2
+            w[r] = __builtin_nontemporal_load(&a.tgt[ebase + j]);
+            l[r] = static_cast<uint32_t>(__builtin_nontemporal_load(&lab[ebase + j]));
         }
     }
     // split test of level k-1: the representative's hash
