@@ -50,6 +50,7 @@ extern "C" {
 #define BSIM_E_DEVICE (-4)      /* a HIP runtime error; text in bsim_last_error */
 #define BSIM_E_UNSUPPORTED (-5) /* valid input outside this library's limits */
 #define BSIM_E_BUSY (-6)        /* server: request does not fit the memory budget now */
+#define BSIM_E_IO (-7)          /* a file could not be opened, read or written */
 
 /* ---- where an array lives ---------------------------------------------- */
 #define BSIM_MEM_HOST 0u
@@ -261,6 +262,34 @@ int bsim_state_graph(const bsim_state* state, bsim_graph* out_host_graph);
 int bsim_state_device_graph(const bsim_state* state, bsim_graph* out_device_graph);
 void bsim_host_free(void* p);
 void bsim_state_free(bsim_state* state);
+
+/*
+ * Checkpoint and resume of a resident state (the incremental run of Sec. 3.2
+ * starts from the summary of the previous snapshot; these keep that summary
+ * across processes).
+ *
+ * bsim_state_save writes the state's graph (CSR, labels, type lists, alive
+ * mask), its parameters (k_max, flags, label width) and every level
+ * h^0..h^K to the host file `path`: first to `path`.tmp, renamed over
+ * `path` once complete.  The file is in host byte order with a 64-byte
+ * header and a checksum over the arrays.  It takes about
+ * 8(n+1) + m(4 + label_bytes) + 4 nt + n + 8 n (k_max+1) bytes.  Errors:
+ * BSIM_E_INVALID for null arguments, BSIM_E_IO when the file cannot be
+ * written (no partial file is left under `path`).
+ *
+ * bsim_state_load reads such a file into a new state owned by ctx and
+ * returns that state's summary in *out (every array of the result of the
+ * state's last summarize or update call).  The graph passes the checks of
+ * bsim_summarize; the levels are uploaded, not recomputed, and the classes
+ * are formed from them.  Later bsim_apply_updates calls on the loaded state
+ * return what they would return on the state that was saved.  Errors:
+ * BSIM_E_IO (cannot open or read), BSIM_E_INVALID (not a state file, a size
+ * or checksum that does not match, a hash on a deleted vertex, a malformed
+ * graph), BSIM_E_UNSUPPORTED (another format version), BSIM_E_NOMEM; on
+ * error *state_out and *out are null.
+ */
+int bsim_state_save(const bsim_state* state, const char* path);
+int bsim_state_load(bsim_ctx* ctx, const char* path, bsim_state** state_out, bsim_result** out);
 
 /*
  * Change detection from two snapshots without a change log (Sec. 3.2's

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libbsim.so")
 
 # bsim.h constants
 OK = 0
-E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY = -1, -2, -3, -4, -5, -6
+E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_IO = -1, -2, -3, -4, -5, -6, -7
 MEM_HOST, MEM_DEVICE = 0, 1
 STOP_AT_FIXPOINT, KEEP_LEVELS, UNTYPED, RESULT_ON_HOST, NO_SUMMARY_EDGES = 1, 2, 4, 8, 16
 BACKWARD, BOTH_DIRECTIONS = 32, 64
@@ -96,6 +96,9 @@ EXPORTS = {
     "bsim_state_device_graph": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph)]),
     "bsim_host_free": (None, [_p]),
     "bsim_state_free": (None, [_p]),
+    "bsim_state_save": (ctypes.c_int, [_p, ctypes.c_char_p]),
+    "bsim_state_load": (ctypes.c_int, [_p, ctypes.c_char_p, ctypes.POINTER(_p),
+                                       ctypes.POINTER(ctypes.POINTER(BsimResult))]),
     "bsim_server_create": (ctypes.c_int, [ctypes.c_int, _u64, _u32, ctypes.POINTER(_p)]),
     "bsim_server_submit": (ctypes.c_int, [_p, ctypes.POINTER(BsimRequest), ctypes.POINTER(_u64)]),
     "bsim_server_poll": (ctypes.c_int, [_p, _u64, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(BsimResult)),
@@ -516,6 +519,21 @@ class State:
             for p in (g.row_off, g.targets, g.labels, g.type_off, g.type_ids, g.alive):
                 lib().bsim_host_free(p)
         return gg.Graph(n=n, row_off=row_off, tgt=tgt, lab=lab, typ_off=typ_off, typ=typ, alive=alive)
+
+    def save(self, path) -> None:
+        """bsim_state_save: the state's graph, parameters and levels to a host file."""
+        self.ctx.check(lib().bsim_state_save(self.handle, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, ctx: Context, path) -> "State":
+        """bsim_state_load: a state read back from a file written by save();
+        its summary is in ``result``."""
+        out = ctypes.POINTER(BsimResult)()
+        h = _p()
+        ctx.check(lib().bsim_state_load(ctx.handle, os.fsencode(path), ctypes.byref(h), ctypes.byref(out)))
+        st = cls.__new__(cls)
+        st.ctx, st.handle, st.result = ctx, h, Result(out)
+        return st
 
     def device_graph(self) -> BsimGraph:
         g = BsimGraph()

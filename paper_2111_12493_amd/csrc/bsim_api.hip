@@ -21,6 +21,7 @@ const char* bsim_status_string(int status) {
         case BSIM_E_DEVICE: return "HIP runtime error";
         case BSIM_E_UNSUPPORTED: return "unsupported input";
         case BSIM_E_BUSY: return "busy";
+        case BSIM_E_IO: return "file I/O error";
         default: return "unknown status";
     }
 }

@@ -26,7 +26,9 @@
 //   4. device: classes of levels 0..K from the stored levels, the fixpoint
 //      rule, and finalize (block ids, sizes, summary edges) as in batch.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 
 #include "bsim_api_internal.h"
@@ -1548,7 +1550,11 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
     return r;
 }
 
-bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p, bsim_state* st) {
+// A new state from a graph.  Its levels come from the batch refinement, or,
+// for a state read back from a checkpoint, from `stored_levels`, which fills
+// st->levels[0..K] on the state's stream.
+bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p, bsim_state* st,
+                          const std::function<void(bsim_state*)>* stored_levels = nullptr) {
     hipStream_t s = ctx->stream;
     PhaseTimer tm(s);
     tm.mark(0);
@@ -1630,13 +1636,17 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     ensure_salt(st, st->max_label);
     rebuild_reverse(st, arena);
     tm.mark(1);
-    // every level h^0..h^K by the batch refinement (no early stop)
-    RunBuffers rb;
-    alloc_run_buffers(g, p.k_max, false, rb, arena, s);
-    LevelSink sink;
-    for (auto& l : st->levels) sink.levels.push_back(l.p);
-    bsim_params bp{p.k_max, p.flags & ~BSIM_STOP_AT_FIXPOINT};
-    run_refinement(ctx, g, bp, rb, &sink, arena);
+    if (stored_levels) {
+        (*stored_levels)(st);
+    } else {
+        // every level h^0..h^K by the batch refinement (no early stop)
+        RunBuffers rb;
+        alloc_run_buffers(g, p.k_max, false, rb, arena, s);
+        LevelSink sink;
+        for (auto& l : st->levels) sink.levels.push_back(l.p);
+        bsim_params bp{p.k_max, p.flags & ~BSIM_STOP_AT_FIXPOINT};
+        run_refinement(ctx, g, bp, rb, &sink, arena);
+    }
     tm.mark(2);
     classes_begin(st);
     for (uint32_t j = 0; j <= st->K; j++) classes_level(st, j);
@@ -1685,6 +1695,189 @@ uint64_t state_bytes(const bsim_state* st) {
 }
 
 bsim_ctx* state_ctx(const bsim_state* st) { return st->ctx; }
+
+// ---------------------------------------------------------------- checkpoint
+// A state on file (host byte order, little-endian on this platform): a
+// 64-byte header, then row_off (n+1 u32), targets (m u32), labels (m entries
+// of label_bytes), type_off (n+1 u32), type ids (nt u32), alive (n bytes) and
+// the levels h^0..h^K (n u64 each), back to back.  The header's checksum
+// folds every section in that order.  Loading rebuilds the state from the
+// graph, with the graph checks of a summarize call, and takes the levels from
+// the file instead of refining them again.
+namespace {
+
+constexpr char kCkptMagic[8] = {'B', 'S', 'I', 'M', 'S', 'T', 'A', 'T'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, k_max, flags, label_bytes, n, reserved0;
+    uint64_t m, nt, checksum, reserved1;
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
+
+// Fold of 8-byte words, acc <- (acc ^ w) * P, a section's last word padded
+// with zero bytes.  For a fixed word each step permutes acc, and for a fixed
+// acc it permutes the word, so a change confined to one word always changes
+// the result.
+struct Fold {
+    uint64_t acc = 0x243F6A8885A308D3ull;
+    void add(const void* data, size_t bytes) {
+        const uint8_t* b = static_cast<const uint8_t*>(data);
+        size_t i = 0;
+        for (; i + 8 <= bytes; i += 8) {
+            uint64_t w;
+            memcpy(&w, b + i, 8);
+            acc = (acc ^ w) * 0x100000001B3ull;
+        }
+        if (i < bytes) {
+            uint64_t w = 0;
+            memcpy(&w, b + i, bytes - i);
+            acc = (acc ^ w) * 0x100000001B3ull;
+        }
+    }
+};
+
+struct File {
+    FILE* f = nullptr;
+    ~File() {
+        if (f) fclose(f);
+    }
+};
+
+template <typename T>
+std::vector<T> to_host(const T* dev, size_t count, hipStream_t s) {
+    std::vector<T> h(count);
+    if (count) {
+        hip_check(hipMemcpyAsync(h.data(), dev, count * sizeof(T), hipMemcpyDeviceToHost, s), "checkpoint read");
+        hip_check(hipStreamSynchronize(s), "checkpoint read");
+    }
+    return h;
+}
+
+void save_state(const bsim_state* st, const char* path) {
+    hipStream_t s = st->s;
+    const size_t n = st->n, m = st->m, nt = st->nt;
+    CkptHeader hd{};
+    memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = kCkptVersion;
+    hd.k_max = st->K;
+    hd.flags = st->flags;
+    hd.label_bytes = st->label_bytes;
+    hd.n = st->n;
+    hd.m = m;
+    hd.nt = nt;
+    const std::string tmp = std::string(path) + ".tmp";
+    File out;
+    out.f = fopen(tmp.c_str(), "wb");
+    if (!out.f) throw DeviceError{BSIM_E_IO, "cannot open " + tmp + " for writing"};
+    bool ok = fwrite(&hd, sizeof(hd), 1, out.f) == 1;
+    Fold fold;
+    auto put = [&](const void* data, size_t bytes) {
+        fold.add(data, bytes);
+        if (bytes && ok) ok = fwrite(data, 1, bytes, out.f) == bytes;
+    };
+    {
+        auto v = to_host(st->row_off[st->cur].p, n + 1, s);
+        put(v.data(), v.size() * 4);
+    }
+    {
+        auto v = to_host(st->tgt[st->cur].p, m, s);
+        put(v.data(), v.size() * 4);
+    }
+    {
+        auto v = to_host(st->lab[st->cur].p, m * st->label_bytes, s);
+        put(v.data(), v.size());
+    }
+    {
+        auto v = to_host(st->type_off[st->tcur].p, n + 1, s);
+        put(v.data(), v.size() * 4);
+    }
+    {
+        auto v = to_host(st->type_ids[st->tcur].p, nt, s);
+        put(v.data(), v.size() * 4);
+    }
+    {
+        auto v = to_host(st->alive.p, n, s);
+        put(v.data(), v.size());
+    }
+    for (const auto& l : st->levels) {
+        auto v = to_host(l.p, n, s);
+        put(v.data(), v.size() * 8);
+    }
+    hd.checksum = fold.acc;
+    if (ok) ok = fseek(out.f, 0, SEEK_SET) == 0 && fwrite(&hd, sizeof(hd), 1, out.f) == 1;
+    ok = (fclose(out.f) == 0) && ok;
+    out.f = nullptr;
+    if (!ok || rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        throw DeviceError{BSIM_E_IO, std::string("writing the state to ") + path + " failed"};
+    }
+}
+
+bsim_result* load_state(bsim_ctx* ctx, const char* path, bsim_state* st) {
+    File in;
+    in.f = fopen(path, "rb");
+    if (!in.f) throw DeviceError{BSIM_E_IO, std::string("cannot open ") + path};
+    const DeviceError bad{BSIM_E_INVALID, std::string(path) + " is not a complete state file of this library"};
+    CkptHeader hd{};
+    if (fread(&hd, sizeof(hd), 1, in.f) != 1 || memcmp(hd.magic, kCkptMagic, 8) != 0) throw bad;
+    if (hd.version != kCkptVersion)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "state file version " + std::to_string(hd.version)};
+    if ((hd.label_bytes != 2 && hd.label_bytes != 4) || hd.n == 0xFFFFFFFFu || hd.m >= (1ull << 32) ||
+        hd.nt >= (1ull << 32) || hd.k_max > 4096)
+        throw bad;
+    const uint64_t n = hd.n, m = hd.m, nt = hd.nt;
+    const uint64_t total = sizeof(hd) + 8 * (n + 1) + m * (4 + hd.label_bytes) + 4 * nt + n +
+                           8 * n * (hd.k_max + 1ull);
+    if (fseeko(in.f, 0, SEEK_END) != 0 || static_cast<uint64_t>(ftello(in.f)) != total ||
+        fseeko(in.f, sizeof(hd), SEEK_SET) != 0)
+        throw bad;
+    Fold fold;
+    auto get = [&](void* data, size_t bytes) {
+        if (bytes && fread(data, 1, bytes, in.f) != bytes) throw DeviceError{BSIM_E_IO, std::string("reading ") + path};
+        fold.add(data, bytes);
+    };
+    std::vector<uint32_t> row_off(n + 1), tgt(m + 1), type_off(n + 1), type_ids(nt + 1);
+    std::vector<uint8_t> lab(m * hd.label_bytes + 4), alive(n + 1);
+    get(row_off.data(), (n + 1) * 4);
+    get(tgt.data(), m * 4);
+    get(lab.data(), m * hd.label_bytes);
+    get(type_off.data(), (n + 1) * 4);
+    get(type_ids.data(), nt * 4);
+    get(alive.data(), n);
+    // the staging checks the CSR on the device; the sizes it takes from the
+    // last offsets must agree with the arrays read here
+    if (row_off[n] != m || type_off[n] != nt) throw bad;
+    bsim_graph g{};
+    g.n_vertices = hd.n;
+    g.label_bytes = hd.label_bytes;
+    g.n_edges = m;
+    g.row_off = row_off.data();
+    g.targets = tgt.data();
+    g.labels = lab.data();
+    g.type_off = type_off.data();
+    g.type_ids = type_ids.data();
+    g.alive = alive.data();
+    g.mem_kind = BSIM_MEM_HOST;
+    const bsim_params p{hd.k_max, hd.flags};
+    validate_params(g, p, false);
+    const std::function<void(bsim_state*)> fill = [&](bsim_state* fresh) {
+        std::vector<uint64_t> h(n + 1);
+        for (auto& l : fresh->levels) {
+            get(h.data(), n * 8);
+            for (uint64_t v = 0; v < n; v++)
+                if (!alive[v] && h[v]) throw bad;  // a deleted vertex has hash 0
+            if (n) hip_check(hipMemcpyAsync(l.p, h.data(), n * 8, hipMemcpyHostToDevice, fresh->s), "level upload");
+            hip_check(hipStreamSynchronize(fresh->s), "level upload");
+        }
+        if (fold.acc != hd.checksum)
+            throw DeviceError{BSIM_E_INVALID, std::string(path) + ": checksum mismatch"};
+    };
+    return create_state(ctx, g, p, st, &fill);
+}
+
+}  // namespace
 
 }  // namespace bsim
 
@@ -1763,6 +1956,52 @@ int bsim_state_device_graph(const bsim_state* st, bsim_graph* g) {
     g->alive = st->alive.p;
     g->mem_kind = BSIM_MEM_DEVICE;
     return BSIM_OK;
+}
+
+int bsim_state_save(const bsim_state* st, const char* path) {
+    if (!st || !path) return BSIM_E_INVALID;
+    try {
+        hip_check(hipSetDevice(st->ctx->device), "set device");
+        save_state(st, path);
+        return BSIM_OK;
+    } catch (const DeviceError& e) {
+        st->ctx->err = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        st->ctx->err = "host allocation failed";
+        return BSIM_E_NOMEM;
+    }
+}
+
+int bsim_state_load(bsim_ctx* ctx, const char* path, bsim_state** state_out, bsim_result** out) {
+    if (state_out) *state_out = nullptr;
+    if (out) *out = nullptr;
+    if (!ctx || !path || !state_out || !out) return BSIM_E_INVALID;
+    bsim_state* st = nullptr;
+    try {
+        hip_check(hipSetDevice(ctx->device), "set device");
+        st = new bsim_state();
+        *out = load_state(ctx, path, st);
+        *state_out = st;
+        return BSIM_OK;
+    } catch (const DeviceError& e) {
+        ctx->err = e.msg;
+        if (st) {
+            st->s = ctx->stream;
+            st->release();
+            delete st;
+        }
+        (void)hipStreamSynchronize(ctx->stream);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        if (st) {
+            st->s = ctx->stream;
+            st->release();
+            delete st;
+        }
+        return BSIM_E_NOMEM;
+    }
 }
 
 void bsim_state_free(bsim_state* st) {

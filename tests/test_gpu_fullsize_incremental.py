@@ -13,6 +13,8 @@ as in the incremental measurement.  The graph is drawn on the GPU (devgen).
   (oracle.updates.replay_rows).
 """
 
+import time
+
 import numpy as np
 import pytest
 
@@ -69,3 +71,37 @@ def test_rmat24_batches_equal_batch_summary(pct):
         st.free()
     finally:
         c.set_option("frontier_limit_pct", old)
+
+
+def test_rmat24_state_checkpoint(tmp_path):
+    # a state saved after a batch of 10^5 operations and loaded again gives
+    # the same summary, and the next batch gives the same result on both
+    dg = devgen.make_device_config("rmat24")
+    host = dg.to_host()
+    c = ctx()
+    st = binding.State(c, dg, 4, stop_at_fixpoint=False)
+    dead = np.zeros(host.n + 2_000_000, dtype=bool)
+    rng = np.random.default_rng(77)
+    n = host.n
+    d = gg.sample_update_ops(host.row_off, host.tgt, host.lab, n, dead, rng, 100000, 64, 128, rmat_scale=24)
+    n = int(d["n_after"])
+    last = st.apply(binding.UpdateBatch.from_op_arrays(d))
+    path = tmp_path / "rmat24.bsim"
+    t0 = time.perf_counter()
+    st.save(path)
+    t1 = time.perf_counter()
+    ld = binding.State.load(c, path)
+    t2 = time.perf_counter()
+    print("rmat24 state file: %.2f GB, save %.2f s, load %.2f s" % (path.stat().st_size / 1e9, t1 - t0, t2 - t1),
+          flush=True)
+    path.unlink()
+    assert_same(ld.result.to_dict(), last.to_dict(), "loaded summary")
+    last.free()
+    d = gg.sample_update_ops(host.row_off, host.tgt, host.lab, n, dead, rng, 100000, 64, 128, rmat_scale=24)
+    batch = binding.UpdateBatch.from_op_arrays(d)
+    ra, rb = st.apply(batch), ld.apply(batch)
+    assert_same(ra.to_dict(), rb.to_dict(), "next batch")
+    ra.free()
+    rb.free()
+    st.free()
+    ld.free()
