@@ -50,6 +50,15 @@
  * over all edges, i.e. the quotient of the graph by the final partition
  * (Sec. 2.6, edges between vertex summaries), sorted by (src, label, dst).
  *
+ * With BO_PREV_LEVEL_EDGES the edges are instead those of the vertex
+ * summaries' top layer in Sec. 2.6's inductive definition: for a CSE whose
+ * object relation is the (k-1)-bisimulation, the primary vertex of v (its
+ * k_done-class) has an l-edge to the primary vertex of each neighbour's
+ * (k_done-1)-class.  So the triples are (block(v), l, prev_block(w)), where
+ * prev_block numbers the (k_done-1)-classes by first occurrence; at
+ * k_done = 0 the 0-classes stand in for both ends.  At a fixpoint the two
+ * partitions agree and so do the two edge sets.
+ *
  * Dead vertices (alive[v] == 0, deletions of Algorithm 3) have hash 0, block
  * 0xFFFFFFFF and are not counted; an edge touching a dead vertex is an error.
  */
@@ -59,6 +68,7 @@
 
 #define BO_STOP_AT_FIXPOINT 1u
 #define BO_UNTYPED 4u
+#define BO_PREV_LEVEL_EDGES 128u
 
 #define BO_OK 0
 #define BO_E_INVALID (-1)
@@ -284,6 +294,8 @@ int bo_summarize(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t
     for (uint32_t v = 0; v < n; v++)
         if (block_ids[v] != 0xFFFFFFFFu) block_sizes[block_ids[v]]++;
 
+    /* after the loop ncls holds the (k_done-1)-classes when k_done >= 1 */
+    const uint32_t* dst_ids = ((flags & BO_PREV_LEVEL_EDGES) && k_done >= 1) ? ncls : block_ids;
     triple* tr = (triple*)malloc(sizeof(triple) * (m ? m : 1));
     if (!tr) return BO_E_NOMEM;
     uint64_t ne = 0;
@@ -291,7 +303,7 @@ int bo_summarize(uint32_t n, uint64_t m, const uint64_t* row_off, const uint32_t
         for (uint64_t e = row_off[v]; e < row_off[v + 1]; e++) {
             tr[ne].s = block_ids[v];
             tr[ne].l = lab[e];
-            tr[ne].d = block_ids[tgt[e]];
+            tr[ne].d = dst_ids[tgt[e]];
             ne++;
         }
     qsort(tr, (size_t)ne, sizeof(triple), cmp_triple);
@@ -388,6 +400,8 @@ int bo_summarize_ext(uint32_t n, uint64_t m, const uint64_t* row_off, const uint
                      uint32_t* block_sizes, uint64_t* n_se_out,
                      uint32_t* se_src, uint32_t* se_lab, uint32_t* se_dst) {
     if ((flags & BO_BACKWARD) && (flags & BO_BOTH_DIRECTIONS)) return BO_E_INVALID;
+    /* previous-level edges are defined for the forward direction only */
+    if ((flags & BO_PREV_LEVEL_EDGES) && (flags & (BO_BACKWARD | BO_BOTH_DIRECTIONS))) return BO_E_INVALID;
     if (row_off[0] != 0 || row_off[n] != m) return BO_E_INVALID;
     for (uint32_t v = 0; v < n; v++) {
         if (row_off[v + 1] < row_off[v] || typ_off[v + 1] < typ_off[v]) return BO_E_INVALID;
@@ -476,6 +490,7 @@ int bo_summarize_ext(uint32_t n, uint64_t m, const uint64_t* row_off, const uint
     for (uint32_t v = 0; v < n; v++)
         if (block_ids[v] != 0xFFFFFFFFu) block_sizes[block_ids[v]]++;
 
+    const uint32_t* dst_ids = ((flags & BO_PREV_LEVEL_EDGES) && k_done >= 1) ? ncls : block_ids;
     triple* tr = (triple*)malloc(sizeof(triple) * (m ? m : 1));
     if (!tr) return BO_E_NOMEM;
     uint64_t ne = 0;
@@ -484,7 +499,7 @@ int bo_summarize_ext(uint32_t n, uint64_t m, const uint64_t* row_off, const uint
             if (!kept(keep_label, n_keep, lab[e])) continue;
             tr[ne].s = block_ids[v];
             tr[ne].l = lab[e];
-            tr[ne].d = block_ids[tgt[e]];
+            tr[ne].d = dst_ids[tgt[e]];
             ne++;
         }
     qsort(tr, (size_t)ne, sizeof(triple), cmp_triple);

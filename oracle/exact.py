@@ -128,13 +128,16 @@ def brute_force_classes(g, k: int, untyped: bool = False, direction: str = "out"
     return res
 
 
-def quotient_edges(g, block_ids, labels=None) -> List[Tuple[int, int, int]]:
+def quotient_edges(g, block_ids, labels=None, dst_ids=None) -> List[Tuple[int, int, int]]:
     """Distinct (block(v), label, block(w)) over all edges (over the edges
-    whose label is in ``labels`` when it is given), sorted."""
+    whose label is in ``labels`` when it is given), sorted.  With ``dst_ids``
+    the target end takes its id from there instead (the vertex-summary
+    edges of Sec. 2.6 into the neighbours' classes of the previous level)."""
     keep = None if labels is None else set(int(x) for x in labels)
+    dst = block_ids if dst_ids is None else dst_ids
     s = set()
     for v in range(g.n):
         for (l, w) in g.out_edges(v):
             if keep is None or l in keep:
-                s.add((int(block_ids[v]), int(l), int(block_ids[w])))
+                s.add((int(block_ids[v]), int(l), int(dst[w])))
     return sorted(s)

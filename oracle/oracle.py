@@ -19,6 +19,7 @@ LIB = os.path.join(HERE, "libbsim_oracle.so")
 
 STOP_AT_FIXPOINT = 1
 UNTYPED = 4
+PREV_LEVEL_EDGES = 128
 BACKWARD = 32
 BOTH_DIRECTIONS = 64
 
@@ -71,7 +72,7 @@ def load(path: str) -> ctypes.CDLL:
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
         _lib = load(LIB)
     return _lib
@@ -131,15 +132,18 @@ def _csr(g):
     return row_off, tgt, lab, typ_off, typ, alive
 
 
-def summarize(g, k_max: int, stop_at_fixpoint: bool = True, untyped: bool = False) -> Dict:
+def summarize(g, k_max: int, stop_at_fixpoint: bool = True, untyped: bool = False,
+              prev_level_edges: bool = False) -> Dict:
     """Batch summarization of graph ``g``; returns a dict of numpy arrays and
-    scalars (see ``bo_summarize`` in the C file)."""
+    scalars (see ``bo_summarize`` in the C file).  ``prev_level_edges``: the
+    summary edges lead to the targets' (k_done-1)-classes."""
     n, m = g.n, g.m
     row_off, tgt, lab, typ_off, typ, alive = _csr(g)
     if tgt.size == 0:
         tgt = np.zeros(1, dtype=np.uint32)
         lab = np.zeros(1, dtype=np.uint32)
-    flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0)
+    flags = ((STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0)
+             | (PREV_LEVEL_EDGES if prev_level_edges else 0))
     hashes = np.zeros(max(n, 1), dtype=np.uint64)
     prev = np.zeros(max(n, 1), dtype=np.uint64)
     bids = np.zeros(max(n, 1), dtype=np.uint32)
@@ -166,7 +170,7 @@ def summarize(g, k_max: int, stop_at_fixpoint: bool = True, untyped: bool = Fals
 
 
 def summarize_ext(g, k_max: int, stop_at_fixpoint: bool = True, untyped: bool = False,
-                  direction: str = "out", labels=None) -> Dict:
+                  direction: str = "out", labels=None, prev_level_edges: bool = False) -> Dict:
     """Summarization under the direction parameterization ("out", "in" or
     "both") and the label parameterization (``labels``: the kept label set
     P_l, None for every label); see ``bo_summarize_ext`` in the C file."""
@@ -176,7 +180,8 @@ def summarize_ext(g, k_max: int, stop_at_fixpoint: bool = True, untyped: bool = 
         tgt = np.zeros(1, dtype=np.uint32)
         lab = np.zeros(1, dtype=np.uint32)
     flags = ((STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0)
-             | {"out": 0, "in": BACKWARD, "both": BOTH_DIRECTIONS}[direction])
+             | {"out": 0, "in": BACKWARD, "both": BOTH_DIRECTIONS}[direction]
+             | (PREV_LEVEL_EDGES if prev_level_edges else 0))
     keep = None
     if labels is not None:
         ls = np.asarray(list(labels), dtype=np.int64)

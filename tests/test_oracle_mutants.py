@@ -32,8 +32,11 @@ MUTANTS = {
                                "int same = i > 0 && p[i].h == p[i - 1].h;"),
     "blocks_numbered_by_largest_vertex": ("for (uint32_t v = 0; v < n; v++)\n        if (is_min[v]) rank[v] = nb++;",
                                           "for (uint32_t v = n; v-- > 0;)\n        if (is_min[v]) rank[v] = nb++;"),
-    "summary_edge_transposed": ("tr[ne].d = block_ids[tgt[e]];",
-                                "tr[ne].d = block_ids[v]; tr[ne].s = block_ids[tgt[e]];"),
+    "summary_edge_transposed": ("tr[ne].d = dst_ids[tgt[e]];",
+                                "tr[ne].d = dst_ids[v]; tr[ne].s = block_ids[tgt[e]];"),
+    "prev_level_edges_use_final_classes": (
+        "const uint32_t* dst_ids = ((flags & BO_PREV_LEVEL_EDGES) && k_done >= 1) ? ncls : block_ids;",
+        "const uint32_t* dst_ids = block_ids;"),
 }
 
 # Mutations that keep a valid *set* hash change hash values but no partition.
@@ -64,6 +67,15 @@ def _pins_hold() -> bool:
             r = orc.summarize(gg.chain(L), L + 5, True, True)
             if r["k_done"] != L + 1:
                 return False
+        # previous-level edges of a chain of 6 edges at k = 3 (closed form:
+        # (j, 0, j) for j < k), and at k = 0 the quotient edges
+        r = orc.summarize(gg.chain(6), 3, False, True, prev_level_edges=True)
+        if list(zip(r["se_src"].tolist(), r["se_label"].tolist(), r["se_dst"].tolist())) != \
+                [(0, 0, 0), (1, 0, 1), (2, 0, 2)]:
+            return False
+        r = orc.summarize(gg.chain(6), 0, False, True, prev_level_edges=True)
+        if list(zip(r["se_src"].tolist(), r["se_label"].tolist(), r["se_dst"].tolist())) != [(0, 0, 0)]:
+            return False
         rng = np.random.default_rng(21)
         for trial in range(60):
             n = int(rng.integers(2, 30))
