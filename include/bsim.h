@@ -73,6 +73,19 @@ extern "C" {
  * with them gives BSIM_E_UNSUPPORTED). */
 #define BSIM_BACKWARD 32u
 #define BSIM_BOTH_DIRECTIONS 64u
+/* Previous-level summary edges (Sec. 2.6, inductive definition of vertex
+ * summaries: the primary vertex of v links to the class, under the object
+ * relation, of each neighbour; for the k-bisimulation that relation is the
+ * (k-1)-bisimulation).  The summary edges become the distinct
+ * (block(v), l, prev_block(w)), where prev_block numbers the
+ * (k_done-1)-classes by first occurrence -- the block ids that a run with
+ * k_max = k_done - 1 returns; at k_done = 0 both ends use the 0-classes.
+ * At a fixpoint the two partitions agree and so do the two edge sets.
+ * Forward direction only (with BSIM_BACKWARD or BSIM_BOTH_DIRECTIONS:
+ * BSIM_E_INVALID); bsim_summarize / bsim_summarize_labels and server
+ * summarize requests without a state (a state, a keep_state request or
+ * bsim_batch_summarize: BSIM_E_UNSUPPORTED). */
+#define BSIM_PREV_LEVEL_EDGES 128u
 
 typedef struct bsim_ctx bsim_ctx;
 typedef struct bsim_state bsim_state;

@@ -23,6 +23,7 @@ E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_IO = -1, -2, -3,
 MEM_HOST, MEM_DEVICE = 0, 1
 STOP_AT_FIXPOINT, KEEP_LEVELS, UNTYPED, RESULT_ON_HOST, NO_SUMMARY_EDGES = 1, 2, 4, 8, 16
 BACKWARD, BOTH_DIRECTIONS = 32, 64
+PREV_LEVEL_EDGES = 128
 DIRECTION_FLAGS = {"out": 0, "in": BACKWARD, "both": BOTH_DIRECTIONS}
 K_UNBOUNDED = 0xFFFFFFFF
 OP_ADD_V, OP_MOD_V, OP_DEL_V, OP_ADD_E, OP_MOD_E, OP_DEL_E = 1, 2, 3, 4, 5, 6
@@ -311,13 +312,15 @@ class Result:
 
 def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
               untyped: bool = False, summary_edges: bool = True, result_on_host: bool = False,
-              direction: str = "out", labels=None) -> Result:
+              direction: str = "out", labels=None, prev_level_edges: bool = False) -> Result:
     """bsim_summarize on a DeviceGraph or HostGraph; with ``labels`` (the
     kept label set) bsim_summarize_labels.  ``direction`` is "out", "in"
-    (BSIM_BACKWARD) or "both" (BSIM_BOTH_DIRECTIONS)."""
+    (BSIM_BACKWARD) or "both" (BSIM_BOTH_DIRECTIONS); ``prev_level_edges``
+    sets BSIM_PREV_LEVEL_EDGES (summary edges into the targets'
+    (k_done-1)-classes)."""
     flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
             (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0) | \
-            DIRECTION_FLAGS[direction]
+            DIRECTION_FLAGS[direction] | (PREV_LEVEL_EDGES if prev_level_edges else 0)
     gs = graph.struct()
     params = BsimParams(int(k_max), flags)
     out = ctypes.POINTER(BsimResult)()

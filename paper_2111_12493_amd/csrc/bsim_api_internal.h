@@ -65,9 +65,16 @@ struct LoopResult {
     const uint64_t* h_final = nullptr;
 };
 
-// Iterations 0..k_done on a staged graph.
+// Iterations 0..k_done on a staged graph.  rep_prev (nullable, n entries)
+// receives the class representatives of level k_done - 1 (of level 0 when
+// k_done = 0; at a fixpoint those of level k_done, the same partition).
 LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
-                          LevelSink* sink, Arena& arena);
+                          LevelSink* sink, Arena& arena, uint32_t* rep_prev = nullptr);
+
+// finalize with summary edges into the classes named by rep_prev (their
+// first-occurrence block ids) instead of the final blocks.
+void finalize_prev_level(const Staged& g, const uint32_t* rep, const uint32_t* rep_prev, bool want_edges,
+                         FinalOut& out, Arena& arena, Arena& keep, hipStream_t s);
 
 // Assemble a bsim_result from finalize output (takes ownership of `keep`).
 bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, const uint64_t* h,

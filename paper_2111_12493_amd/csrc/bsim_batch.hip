@@ -243,6 +243,8 @@ void build_union(const bsim_graph* graphs, uint32_t G, Staged& u, uint32_t*& gid
 void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const bsim_params& p,
                      bsim_result** outs) {
     hipStream_t s = ctx->stream;
+    if (p.flags & BSIM_PREV_LEVEL_EDGES)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "BSIM_PREV_LEVEL_EDGES is supported by single-graph calls only"};
     for (uint32_t g = 0; g < G; g++) {
         validate_params(graphs[g], p, true);
         if (graphs[g].label_bytes != graphs[0].label_bytes || graphs[g].mem_kind != graphs[0].mem_kind)

@@ -94,7 +94,7 @@ struct KeyShared {
 template <typename LabT>
 __global__ void __launch_bounds__(kBlock) k_edge_keys(
     const uint32_t* __restrict__ row_off, const uint32_t* __restrict__ tgt,
-    const LabT* __restrict__ lab, const uint32_t* __restrict__ bid,
+    const LabT* __restrict__ lab, const uint32_t* __restrict__ bid, const uint32_t* __restrict__ bid_dst,
     const uint32_t* __restrict__ tile_i0, const uint32_t* __restrict__ tile_i1,
     const uint32_t* __restrict__ tile_e0, const uint32_t* __restrict__ tile_e1,
     const uint32_t* __restrict__ act, uint32_t n_tiles,
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_edge_keys(
         const uint32_t v = hub_v[blockIdx.x];
         const uint64_t src = static_cast<uint64_t>(bid[v]) << (lb + bb);
         for (uint32_t e = row_off[v] + tid; e < row_off[v + 1]; e += kBlock)
-            keys[e] = src | (static_cast<uint64_t>(lab[e]) << bb) | bid[tgt[e]];
+            keys[e] = src | (static_cast<uint64_t>(lab[e]) << bb) | bid_dst[tgt[e]];
         return;
     }
     const uint32_t tile = blockIdx.x - n_hubs;
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(kBlock) k_edge_keys(
         const uint32_t e = ebase + j;
         const uint32_t v = act[i0 + S.seg[j]];
         keys[e] = (static_cast<uint64_t>(bid[v]) << (lb + bb)) |
-                  (static_cast<uint64_t>(lab[e]) << bb) | bid[tgt[e]];
+                  (static_cast<uint64_t>(lab[e]) << bb) | bid_dst[tgt[e]];
     }
 }
 
@@ -141,12 +141,13 @@ template <typename LabT>
 __global__ void __launch_bounds__(kBlock) k_edge_keys_coo(const uint32_t* __restrict__ src,
                                                           const uint32_t* __restrict__ tgt,
                                                           const LabT* __restrict__ lab,
-                                                          const uint32_t* __restrict__ bid, uint32_t m,
+                                                          const uint32_t* __restrict__ bid,
+                                                          const uint32_t* __restrict__ bid_dst, uint32_t m,
                                                           int lb, int bb, uint64_t* __restrict__ keys) {
     const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= m) return;
     keys[e] = (static_cast<uint64_t>(bid[src[e]]) << (lb + bb)) |
-              (static_cast<uint64_t>(lab[e]) << bb) | bid[tgt[e]];
+              (static_cast<uint64_t>(lab[e]) << bb) | bid_dst[tgt[e]];
 }
 
 __global__ void __launch_bounds__(kBlock) k_sort_hist(const uint64_t* __restrict__ in, uint32_t m,
@@ -245,14 +246,17 @@ uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Arena& aren
     return a;
 }
 
-void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& out, Arena& arena,
-              Arena& keep, hipStream_t s) {
+namespace {
+
+// First-occurrence block ids of the classes named by `rep` into ids[n], the
+// block sizes into a new array of `sizes_arena`; returns the block count.
+uint32_t number_blocks(const Staged& g, const uint32_t* rep, uint32_t* ids, uint32_t** sizes_out, Arena& arena,
+                       Arena& sizes_arena, hipStream_t s) {
     const uint32_t n = g.n;
     uint32_t* cmin = arena.alloc<uint32_t>(n + 1);
     uint32_t* isrep = arena.alloc<uint32_t>(n);
     uint32_t* rank = arena.alloc<uint32_t>(n);
     uint32_t* total = arena.alloc<uint32_t>(1);
-    out.block_ids = keep.alloc<uint32_t>(n);
     const uint32_t gb = std::max<uint32_t>(ceil_div(n, kBlock), 1);
     hip_check(hipMemsetAsync(cmin, 0xFF, (static_cast<size_t>(n) + 1) * 4, s), "class minima");
     if (n) {
@@ -263,13 +267,31 @@ void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& o
     uint32_t nb = 0;
     hip_check(hipMemcpyAsync(&nb, total, 4, hipMemcpyDeviceToHost, s), "block count");
     hip_check(hipStreamSynchronize(s), "block count sync");
-    out.n_blocks = nb;
-    out.block_sizes = keep.alloc<uint32_t>(nb + 1);
-    hip_check(hipMemsetAsync(out.block_sizes, 0, (static_cast<size_t>(nb) + 1) * 4, s), "sizes");
-    if (n)
-        k_fin_ids<<<ceil_div(n, kIdsPerBlock), kBlock, 0, s>>>(g.alive, n, rep, cmin, rank, out.block_ids,
-                                                              out.block_sizes);
+    uint32_t* sizes = sizes_arena.alloc<uint32_t>(nb + 1);
+    hip_check(hipMemsetAsync(sizes, 0, (static_cast<size_t>(nb) + 1) * 4, s), "sizes");
+    if (n) k_fin_ids<<<ceil_div(n, kIdsPerBlock), kBlock, 0, s>>>(g.alive, n, rep, cmin, rank, ids, sizes);
     hip_check(hipGetLastError(), "finalize launch");
+    *sizes_out = sizes;
+    return nb;
+}
+
+void finalize_impl(const Staged& g, const uint32_t* rep, const uint32_t* rep_prev, bool want_edges,
+                   FinalOut& out, Arena& arena, Arena& keep, hipStream_t s) {
+    const uint32_t n = g.n;
+    out.block_ids = keep.alloc<uint32_t>(n);
+    const uint32_t nb = number_blocks(g, rep, out.block_ids, &out.block_sizes, arena, keep, s);
+    out.n_blocks = nb;
+    // the target end of a summary edge: the final blocks, or the blocks of
+    // the previous level's classes
+    const uint32_t* dst_ids = out.block_ids;
+    uint32_t nb_dst = nb;
+    if (rep_prev && want_edges && g.m) {
+        uint32_t* ids = arena.alloc<uint32_t>(n);
+        uint32_t* sizes = nullptr;
+        nb_dst = number_blocks(g, rep_prev, ids, &sizes, arena, arena, s);
+        dst_ids = ids;
+    }
+    uint32_t* total = arena.alloc<uint32_t>(1);
     out.n_se = 0;
     if (!want_edges || g.m == 0) {
         out.se_src = keep.alloc<uint32_t>(1);
@@ -277,7 +299,8 @@ void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& o
         out.se_dst = keep.alloc<uint32_t>(1);
         return;
     }
-    const int bb = std::max(1, bit_width(nb ? nb - 1 : 0));
+    const uint32_t nb_max = std::max(nb, nb_dst);
+    const int bb = std::max(1, bit_width(nb_max ? nb_max - 1 : 0));
     const int lb = std::max(1, bit_width(g.max_label));
     if (2 * bb + lb > 64)
         throw DeviceError{BSIM_E_UNSUPPORTED, "summary-edge triple does not fit 64 bits"};
@@ -288,19 +311,19 @@ void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& o
     if (g.src) {
         if (g.label_bytes == 2)
             k_edge_keys_coo<uint16_t><<<ceil_div(m, kBlock), kBlock, 0, s>>>(
-                g.src, g.tgt, static_cast<const uint16_t*>(g.lab), out.block_ids, m, lb, bb, ka);
+                g.src, g.tgt, static_cast<const uint16_t*>(g.lab), out.block_ids, dst_ids, m, lb, bb, ka);
         else
             k_edge_keys_coo<uint32_t><<<ceil_div(m, kBlock), kBlock, 0, s>>>(
-                g.src, g.tgt, static_cast<const uint32_t*>(g.lab), out.block_ids, m, lb, bb, ka);
+                g.src, g.tgt, static_cast<const uint32_t*>(g.lab), out.block_ids, dst_ids, m, lb, bb, ka);
     } else if (g.label_bytes == 2)
         k_edge_keys<uint16_t><<<grid, kBlock, 0, s>>>(g.row_off, g.tgt,
-                                                      static_cast<const uint16_t*>(g.lab), out.block_ids,
+                                                      static_cast<const uint16_t*>(g.lab), out.block_ids, dst_ids,
                                                       g.tile_i0, g.tile_i1, g.tile_e0, g.tile_e1, g.act,
                                                       g.n_tiles, g.hub_v, g.n_hubs,
                                                       lb, bb, ka);
     else
         k_edge_keys<uint32_t><<<grid, kBlock, 0, s>>>(g.row_off, g.tgt,
-                                                      static_cast<const uint32_t*>(g.lab), out.block_ids,
+                                                      static_cast<const uint32_t*>(g.lab), out.block_ids, dst_ids,
                                                       g.tile_i0, g.tile_i1, g.tile_e0, g.tile_e1, g.act,
                                                       g.n_tiles, g.hub_v, g.n_hubs,
                                                       lb, bb, ka);
@@ -320,6 +343,18 @@ void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& o
     k_unpack<<<ceil_div(m, kBlock), kBlock, 0, s>>>(sorted, m, flag, pos, lb, bb, out.se_src,
                                                     out.se_label, out.se_dst);
     hip_check(hipGetLastError(), "unpack launch");
+}
+
+}  // namespace
+
+void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& out, Arena& arena,
+              Arena& keep, hipStream_t s) {
+    finalize_impl(g, rep, nullptr, want_edges, out, arena, keep, s);
+}
+
+void finalize_prev_level(const Staged& g, const uint32_t* rep, const uint32_t* rep_prev, bool want_edges,
+                         FinalOut& out, Arena& arena, Arena& keep, hipStream_t s) {
+    finalize_impl(g, rep, rep_prev, want_edges, out, arena, keep, s);
 }
 
 }  // namespace bsim

@@ -1555,6 +1555,8 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
 // st->levels[0..K] on the state's stream.
 bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p, bsim_state* st,
                           const std::function<void(bsim_state*)>* stored_levels = nullptr) {
+    if (p.flags & BSIM_PREV_LEVEL_EDGES)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "BSIM_PREV_LEVEL_EDGES is supported without a state only"};
     hipStream_t s = ctx->stream;
     PhaseTimer tm(s);
     tm.mark(0);

@@ -30,10 +30,12 @@ void validate_params(const bsim_graph& graph, const bsim_params& p, bool directi
     if (!(p.flags & BSIM_STOP_AT_FIXPOINT) && p.k_max > (1u << 24))
         throw DeviceError{BSIM_E_INVALID, "without a fixpoint test k_max must be finite (< 2^24)"};
     if (p.flags & ~(BSIM_STOP_AT_FIXPOINT | BSIM_KEEP_LEVELS | BSIM_UNTYPED | BSIM_RESULT_ON_HOST |
-                    BSIM_NO_SUMMARY_EDGES | BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS))
+                    BSIM_NO_SUMMARY_EDGES | BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS | BSIM_PREV_LEVEL_EDGES))
         throw DeviceError{BSIM_E_INVALID, "unknown flag bits"};
     if ((p.flags & BSIM_BACKWARD) && (p.flags & BSIM_BOTH_DIRECTIONS))
         throw DeviceError{BSIM_E_INVALID, "BSIM_BACKWARD and BSIM_BOTH_DIRECTIONS exclude each other"};
+    if ((p.flags & BSIM_PREV_LEVEL_EDGES) && (p.flags & (BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS)))
+        throw DeviceError{BSIM_E_INVALID, "BSIM_PREV_LEVEL_EDGES is defined for the forward direction only"};
     if (!directions && (p.flags & (BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS)))
         throw DeviceError{BSIM_E_UNSUPPORTED, "edge directions other than outgoing are supported by "
                                               "bsim_summarize without a state only"};
@@ -81,7 +83,7 @@ void upload_graph(const bsim_graph& in, Staged& g, Arena& arena, hipStream_t s) 
 }
 
 LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
-                          LevelSink* sink, Arena& arena) {
+                          LevelSink* sink, Arena& arena, uint32_t* rep_prev) {
     hipStream_t s = ctx->stream;
     const bool stop = (p.flags & BSIM_STOP_AT_FIXPOINT) != 0;
     const bool untyped = (p.flags & BSIM_UNTYPED) != 0;
@@ -100,6 +102,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
     hip_check(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming), "event");
     bool done = false;
+    bool prev_taken = false;
     std::vector<hipEvent_t> timers;  // (start, after refinement, after hubs) per timed launch
     std::vector<uint32_t> timed_k;   // the launches timed
     struct TimerGuard {
@@ -145,6 +148,15 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                     }
                     if (rb.bc.gid) launch_graph_stop(rb, kk, p.k_max, stop, s);
                     launch_iteration(g, rb, kk, p.k_max, stop, sink && !sink->levels.empty(), s);
+                    if (rep_prev && kk == p.k_max && g.n) {
+                        // launch k splits level k-1 and nothing after it in
+                        // the launch changes the classes: rep now names the
+                        // (k_max-1)-classes, or the final ones of a run that
+                        // stopped earlier at a fixpoint
+                        hip_check(hipMemcpyAsync(rep_prev, rb.rep, static_cast<size_t>(g.n) * 4,
+                                                 hipMemcpyDeviceToDevice, s), "previous classes");
+                        prev_taken = true;
+                    }
                     if (timed) hip_check(hipEventRecord(et[1], s), "event");
                     if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
                     if (timed) hip_check(hipEventRecord(et[2], s), "event");
@@ -190,6 +202,11 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     }
     if (st.error & kErrHubSplit)
         throw DeviceError{BSIM_E_DEVICE, "a hub hash bucket could not be split to fit its table"};
+    // k_max = 0, or a run whose stop was seen before launch k_max: the final
+    // classes (level 0, or a fixpoint's)
+    if (rep_prev && !prev_taken && g.n)
+        hip_check(hipMemcpyAsync(rep_prev, rb.rep, static_cast<size_t>(g.n) * 4, hipMemcpyDeviceToDevice, s),
+                  "previous classes");
     lr.k_done = st.k_done;
     lr.fixpoint = st.fixpoint;
     if (rb.bc.gid) {  // batched: counts and final buffers are per graph
@@ -298,10 +315,15 @@ bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_
     RunBuffers rb;
     alloc_run_buffers(gr, p.k_max, (p.flags & BSIM_STOP_AT_FIXPOINT) != 0, rb, arena, s);
     hip_check(hipEventRecord(ev[1], s), "event");
-    LoopResult lr = run_refinement(ctx, gr, p, rb, nullptr, arena);
+    const bool prev_edges = (p.flags & BSIM_PREV_LEVEL_EDGES) != 0;
+    uint32_t* rep_prev = prev_edges ? arena.alloc<uint32_t>(gr.n + 1) : nullptr;
+    LoopResult lr = run_refinement(ctx, gr, p, rb, nullptr, arena, rep_prev);
     hip_check(hipEventRecord(ev[2], s), "event");
     FinalOut fo;
-    finalize(gf, rb.rep, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    if (prev_edges)
+        finalize_prev_level(gf, rb.rep, rep_prev, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    else
+        finalize(gf, rb.rep, !(p.flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
     if (fo.n_blocks != lr.blocks_per_iter.back())
         throw DeviceError{BSIM_E_DEVICE, "internal: class count mismatch in finalize"};
     bsim_result* r = make_result(ctx, g, lr, lr.h_final, fo, keep, p.flags);
