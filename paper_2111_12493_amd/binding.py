@@ -599,9 +599,10 @@ class Server:
 
     def submit_summarize(self, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
                          untyped: bool = False, summary_edges: bool = True, keep_state: bool = False,
-                         direction: str = "out") -> int:
+                         direction: str = "out", prev_level_edges: bool = False) -> int:
         flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
-                (0 if summary_edges else NO_SUMMARY_EDGES) | DIRECTION_FLAGS[direction]
+                (0 if summary_edges else NO_SUMMARY_EDGES) | DIRECTION_FLAGS[direction] | \
+                (PREV_LEVEL_EDGES if prev_level_edges else 0)
         gs = graph.struct()
         req = BsimRequest(REQ_SUMMARIZE, 1 if keep_state else 0, ctypes.pointer(gs), BsimParams(int(k_max), flags),
                           None, None, 0)

@@ -64,6 +64,8 @@ uint64_t summarize_footprint(const bsim_graph& g, const bsim_params& p, bool kee
     uint64_t b = m * (4 + lb + 8) + n * 160 + (1u << 20);
     if (g.mem_kind == BSIM_MEM_HOST) b += m * (4 + lb) + n * 16;
     if (edges) b += m * 36;
+    // previous-level classes and their block ids
+    if (p.flags & BSIM_PREV_LEVEL_EDGES) b += n * 24;
     // the direction view: kept edges with sources, and the view itself (2m
     // edges for both directions) staged a second time
     if (p.flags & (BSIM_BACKWARD | BSIM_BOTH_DIRECTIONS))
@@ -222,6 +224,8 @@ int bsim_server_submit(bsim_server* s, const bsim_request* req, uint64_t* ticket
             const bsim_graph& g = *req->graph;
             // a direction flag takes a view of the graph: no resident state
             validate_params(g, req->params, !req->keep_state);
+            if (req->keep_state && (req->params.flags & BSIM_PREV_LEVEL_EDGES))
+                throw DeviceError{BSIM_E_UNSUPPORTED, "BSIM_PREV_LEVEL_EDGES is supported without a state only"};
             r.keep_state = req->keep_state ? 1 : 0;
             r.params = req->params;
             r.graph = g;

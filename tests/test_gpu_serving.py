@@ -140,3 +140,25 @@ def test_direction_requests_in_the_mix():
                                  direction="in")
     finally:
         srv.free()
+
+
+def test_previous_level_edge_requests():
+    # summarize requests with BSIM_PREV_LEVEL_EDGES at a cap, served
+    # together with plain ones, each equal to the oracle; a state refuses it
+    rng = np.random.default_rng(62)
+    graphs = [gg.rmat_graph(int(rng.integers(8, 12)), int(rng.integers(1000, 20000)), n_types=8, n_labels=6,
+                            seed=int(rng.integers(1, 1 << 30))) for _ in range(6)]
+    prev = [True, False] * 3
+    srv = binding.Server(workers=4)
+    try:
+        tickets = [srv.submit_summarize(binding.HostGraph(g), k_max=3, stop_at_fixpoint=False, prev_level_edges=p)
+                   for g, p in zip(graphs, prev)]
+        for g, p, t in zip(graphs, prev, tickets):
+            got = fetch(srv.poll(t)[0])
+            assert_same(got, orc.summarize(g, 3, False, False, prev_level_edges=p), ("serving prev", p))
+        with pytest.raises(binding.BsimError) as e:
+            srv.submit_summarize(binding.HostGraph(graphs[0]), k_max=3, stop_at_fixpoint=False, keep_state=True,
+                                 prev_level_edges=True)
+        assert e.value.status == binding.E_UNSUPPORTED
+    finally:
+        srv.free()
