@@ -288,7 +288,67 @@ def summary_updates(d: str, batches: int, out_dir: str) -> str:
     return out
 
 
+BATCHED_COMMAND = """    rocprofv3 --kernel-trace --stats -d {d} -o run --output-format csv -- \\
+        python -u -m paper_2111_12493_amd.profiling batched {runs}"""
+
+
+def run_batched(runs: int) -> None:
+    """The batched workload of the bench's batched leg: 4,096 R-MAT graphs
+    drawn on the GPU, summarized by `runs` batched calls (the first one a
+    warm-up, like the bench's)."""
+    import time
+
+    import torch
+
+    from . import binding, devgen
+
+    graphs = devgen.batched_device(4096, 1e6, seed=23)
+    ctx = binding.Context(0)
+    print("batched: %d graphs, %d edges" % (len(graphs), sum(g.m for g in graphs)), flush=True)
+    for i in range(runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = binding.batch_summarize(ctx, graphs, summary_edges=True)
+        torch.cuda.synchronize()
+        print("run %d: %.1f ms, max k_done %d" % (i, (time.perf_counter() - t0) * 1e3, max(r.k_done for r in rs)),
+              flush=True)
+        for r in rs:
+            r.free()
+    ctx.close()
+
+
+def summary_batched(d: str, runs: int, out_dir: str) -> str:
+    path = os.path.join(d, "run_kernel_stats.csv")
+    rows = [r for r in csv.DictReader(open(path)) if short(r["Name"]).startswith("k_")]
+    total = sum(int(r["TotalDurationNs"]) for r in rows)
+    lines = ["# Batched summarization of 4,096 R-MAT graphs", "",
+             "4,096 graphs with edge counts log-uniform in 10^2-10^6 (4.28e8 edges in all), degree U(4, 16), "
+             "32 types and 32 labels (Zipf 1.0), drawn on the GPU; %d batched calls (each graph to its own "
+             "fixpoint), the first a warm-up." % runs, "",
+             "## Command (repository root, one MI355X)", "",
+             BATCHED_COMMAND.format(d=d, runs=runs), "",
+             "## Library kernels (all calls)", "", "```",
+             "%-28s %7s %11s %10s %11s" % ("kernel", "calls", "total_ms", "avg_us", "ms/call"),
+             "%-28s %7s %11.2f %10s %11.2f" % ("(all library kernels)", "", total / 1e6, "", total / 1e6 / runs)]
+    for r in rows[:16]:
+        t = int(r["TotalDurationNs"])
+        lines.append("%-28s %7s %11.2f %10.1f %11.2f" % (short(r["Name"]), r["Calls"], t / 1e6,
+                                                        float(r["AverageNs"]) / 1e3, t / 1e6 / runs))
+    lines += ["```", ""]
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "batched_4096_rmat.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
+
+
 def main(argv):
+    if argv[1] == "batched":
+        run_batched(int(argv[2]))
+        return
+    if argv[1] == "summary-batched":
+        print(summary_batched(argv[2], int(argv[3]), argv[4]))
+        return
     if argv[1] == "updates":
         run_updates(argv[2], int(argv[3]))
         return
