@@ -133,7 +133,9 @@ __global__ void __launch_bounds__(kBlock) k_edge_keys(
 // offset per digit), then a stable scatter that ranks equal digits by wave
 // ballots (8 ballots isolate the lanes with the same digit).
 
-constexpr int kSortItems = 4;
+// 16 keys per thread: a tile of 4,096 keys leaves about 16 keys per digit
+// run, so the scatter writes runs of about 128 bytes
+constexpr int kSortItems = 16;
 constexpr int kSortTile = kBlock * kSortItems;
 
 // Edge keys from a COO source array (graphs without a tile schedule).
@@ -166,21 +168,48 @@ __global__ void __launch_bounds__(kBlock) k_sort_hist(const uint64_t* __restrict
     hist[static_cast<uint64_t>(threadIdx.x) * nblk + blockIdx.x] = s_h[threadIdx.x];
 }
 
+// Stable scatter of one tile: every key gets its rank within the tile by
+// digit (wave ballots isolate the lanes with the same digit; earlier rounds
+// and earlier waves come first), the tile is staged in LDS in digit order,
+// and each digit's run is then written out by consecutive threads.
 __global__ void __launch_bounds__(kBlock) k_sort_scatter(const uint64_t* __restrict__ in,
                                                          uint64_t* __restrict__ out, uint32_t m,
                                                          int shift, uint32_t nblk,
                                                          const uint32_t* __restrict__ offs) {
-    __shared__ uint32_t s_run[256];
+    __shared__ uint64_t s_keys[kSortTile];
+    __shared__ uint32_t s_run[256];     // global position of the tile's first key of each digit
+    __shared__ uint32_t s_start[256];   // LDS position of the same key
+    __shared__ uint32_t s_fill[256];    // keys of each digit placed so far
     __shared__ uint32_t s_cnt[kBlock / 64][256];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
-    s_run[tid] = offs[static_cast<uint64_t>(tid) * nblk + blockIdx.x];
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSortTile;
+    const uint32_t count = static_cast<uint32_t>(min(static_cast<uint64_t>(kSortTile), m - base));
+    // the tile's keys per digit, from the scanned digit-major histogram: the
+    // next entry is the next block of the same digit, or the first block of
+    // the next digit, and the last entry ends at m
+    const uint64_t idx = static_cast<uint64_t>(tid) * nblk + blockIdx.x;
+    const uint32_t run = offs[idx];
+    const uint32_t next = idx + 1 < static_cast<uint64_t>(nblk) * 256 ? offs[idx + 1] : m;
+    s_run[tid] = run;
+    s_start[tid] = next - run;
+    s_fill[tid] = 0;
     for (int w = 0; w < kBlock / 64; w++) s_cnt[w][tid] = 0;
     __syncthreads();
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSortTile;
+    // exclusive scan of the 256 digit counts (one per thread)
+    for (uint32_t d = 1; d < 256; d <<= 1) {
+        const uint32_t v = tid >= d ? s_start[tid - d] : 0;
+        __syncthreads();
+        s_start[tid] += v;
+        __syncthreads();
+    }
+    const uint32_t incl = s_start[tid];
+    __syncthreads();
+    s_start[tid] = incl - (next - run);
+    __syncthreads();
     for (int r = 0; r < kSortItems; r++) {
-        const uint64_t j = base + static_cast<uint64_t>(r) * kBlock + tid;
-        const bool valid = j < m;
-        const uint64_t key = valid ? in[j] : 0;
+        const uint32_t jl = static_cast<uint32_t>(r) * kBlock + tid;
+        const bool valid = jl < count;
+        const uint64_t key = valid ? in[base + jl] : 0;
         const uint32_t dig = static_cast<uint32_t>((key >> shift) & 0xFF);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -193,9 +222,9 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter(const uint64_t* __restr
         if (valid && below == 0) s_cnt[wid][dig] = static_cast<uint32_t>(__popcll(peers));
         __syncthreads();
         if (valid) {
-            uint32_t pos = s_run[dig] + rank;
+            uint32_t pos = s_start[dig] + s_fill[dig] + rank;
             for (uint32_t w = 0; w < wid; w++) pos += s_cnt[w][dig];
-            out[pos] = key;
+            if (pos < kSortTile) s_keys[pos] = key;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -203,8 +232,14 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter(const uint64_t* __restr
             add += s_cnt[w][tid];
             s_cnt[w][tid] = 0;
         }
-        s_run[tid] += add;
+        s_fill[tid] += add;
         __syncthreads();
+    }
+    for (uint32_t i = tid; i < count; i += kBlock) {
+        const uint64_t key = s_keys[i];
+        const uint32_t dig = static_cast<uint32_t>((key >> shift) & 0xFF);
+        const uint32_t pos = s_run[dig] + (i - s_start[dig]);
+        if (pos < m) out[pos] = key;
     }
 }
 
