@@ -48,6 +48,28 @@ __device__ __forceinline__ uint32_t owner(const uint64_t* off, uint32_t G, uint6
     return lo;
 }
 
+// owner() for the items of one block: the owners of the block's first and
+// last items bound the search (owners grow with the item), so each thread
+// searches only the few graphs the block spans.  Every thread of the block
+// must call it (it holds a barrier); count is the number of items.
+__device__ __forceinline__ uint32_t block_owner(const uint64_t* off, uint32_t G, uint64_t count, uint64_t x,
+                                                uint32_t* s_range) {
+    const uint64_t first = static_cast<uint64_t>(blockIdx.x) * kBlock;
+    const uint64_t last = min(first + kBlock, count) - 1;
+    if (threadIdx.x == 0) {
+        s_range[0] = owner(off, G, first);
+        s_range[1] = owner(off, G, last);
+    }
+    __syncthreads();
+    uint32_t lo = s_range[0], hi = s_range[1] + 1;
+    const uint64_t y = min(x, last);
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= y) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void k_type_counts(const GraphPtrs* gp, uint32_t G, uint32_t* cnt) {
     const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
     if (g < G) cnt[g] = gp[g].type_off[gp[g].n];
@@ -57,9 +79,10 @@ __global__ void k_union_vertices(const GraphPtrs* __restrict__ gp, const uint64_
                                  const uint64_t* __restrict__ eoff, const uint64_t* __restrict__ toff, uint32_t G,
                                  uint32_t n, uint32_t* __restrict__ row_off, uint32_t* __restrict__ type_off,
                                  uint8_t* __restrict__ alive, uint32_t* __restrict__ gid, RunStatus* status) {
+    __shared__ uint32_t s_range[2];
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t g = block_owner(voff, G, n, v, s_range);
     if (v >= n) return;
-    const uint32_t g = owner(voff, G, v);
     const GraphPtrs p = gp[g];
     const uint32_t l = v - static_cast<uint32_t>(voff[g]);
     row_off[v] = p.row_off[l] + static_cast<uint32_t>(eoff[g]);
@@ -76,9 +99,10 @@ template <typename LabT>
 __global__ void k_union_edges(const GraphPtrs* __restrict__ gp, const uint64_t* __restrict__ eoff,
                               const uint64_t* __restrict__ voff, uint32_t G, uint32_t m,
                               uint32_t* __restrict__ tgt, LabT* __restrict__ lab, RunStatus* status) {
+    __shared__ uint32_t s_range[2];
     const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t g = block_owner(eoff, G, m, e, s_range);
     if (e >= m) return;
-    const uint32_t g = owner(eoff, G, e);
     const GraphPtrs p = gp[g];
     const uint32_t l = e - static_cast<uint32_t>(eoff[g]);
     const uint32_t w = p.tgt[l];
@@ -89,9 +113,10 @@ __global__ void k_union_edges(const GraphPtrs* __restrict__ gp, const uint64_t* 
 
 __global__ void k_union_types(const GraphPtrs* __restrict__ gp, const uint64_t* __restrict__ toff, uint32_t G,
                               uint32_t nt, uint32_t* __restrict__ ids) {
+    __shared__ uint32_t s_range[2];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t g = block_owner(toff, G, nt, i, s_range);
     if (i >= nt) return;
-    const uint32_t g = owner(toff, G, i);
     ids[i] = gp[g].type_ids[i - static_cast<uint32_t>(toff[g])];
 }
 
@@ -125,9 +150,10 @@ __global__ void k_edge_starts(const uint32_t* __restrict__ se_src, uint32_t nse,
 
 __global__ void k_rebase_edges(const uint64_t* __restrict__ seoff, const uint64_t* __restrict__ bbase, uint32_t G,
                                uint32_t nse, uint32_t* __restrict__ se_src, uint32_t* __restrict__ se_dst) {
+    __shared__ uint32_t s_range[2];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t g = block_owner(seoff, G, nse, i, s_range);
     if (i >= nse) return;
-    const uint32_t g = owner(seoff, G, i);
     const uint32_t b = static_cast<uint32_t>(bbase[g]);
     se_src[i] -= b;
     se_dst[i] -= b;
