@@ -168,7 +168,7 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
         dead[:g.n] = g.alive == 0
     n = g.n
     scale = int(np.ceil(np.log2(max(g.n, 2))))
-    lat_i, lat_p, ops_total = [], [], 0
+    lat_i, lat_p, sizes, ops_total = [], [], [], 0
     for i in range(args.inc_batches):
         size = int(round(10 ** rng.uniform(3, np.log10(args.inc_max_ops))))
         d = gg.sample_update_ops(g.row_off, g.tgt, g.lab, n, dead, rng, size, max(g.n_labels, 1),
@@ -186,6 +186,7 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
         if nb[0] != nb[1]:
             raise RuntimeError("incremental and full recomputation disagree on batch %d" % i)
         ops_total += size
+        sizes.append(size)
         print("# update batch %d: %d ops, incremental %.2f ms, full recomputation %.2f ms"
               % (i, size, lat_i[-1], lat_p[-1]), file=sys.stderr, flush=True)
 
@@ -203,12 +204,18 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
     ctx_p.close()
     p50, p99 = percentile(lat_i, 0.5), percentile(lat_i, 0.99)
     q50, q99 = percentile(lat_p, 0.5), percentile(lat_p, 0.99)
+    # the same measurements, split at 10^4 operations per batch
+    small = [i for i, z in enumerate(sizes) if z < 10000]
+    by_size = {"batches_below_1e4_ops": len(small)}
+    if small:
+        by_size["p50_ms"] = percentile([lat_i[i] for i in small], 0.5)
+        by_size["plain_p50_ms"] = percentile([lat_p[i] for i in small], 0.5)
     return {"workload": "%s resident, k=4, update batches of log-uniform 10^3-%.0e ops (ADD/MOD/DEL 60/25/15, "
                         "%s endpoints for new edges)" % (workload, args.inc_max_ops,
                                                          "R-MAT" if rmat_endpoints else "uniform"),
             "batches": len(lat_i), "ops": ops_total, "p50_ms": p50, "p99_ms": p99,
             "plain_p50_ms": q50, "plain_p99_ms": q99, "speedup_p50": q50 / p50, "speedup_p99": q99 / p99,
-            "state_create_s": create_s, "summary_edges": False,
+            "small_batches": by_size, "state_create_s": create_s, "summary_edges": False,
             "snapshot_diff": {"ops": n_diff, "ms": diff_ms,
                               "what": "bsim_diff_snapshots between the first snapshot and the graph after "
                                       "all batches"},
