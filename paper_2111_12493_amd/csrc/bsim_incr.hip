@@ -396,9 +396,12 @@ __global__ void k_typ_write(const uint32_t* __restrict__ tl, uint32_t nT, const 
 }
 
 // Level 0 on the vertices whose types changed: C_0 = those whose t changed.
+// A changed vertex adds its in-list length to the striped counters, the
+// bound on the in-neighbours that level 1's frontier would take in.
 __global__ void k_level0(const uint32_t* __restrict__ tl, uint32_t nT, const uint32_t* __restrict__ type_off,
                          const uint32_t* __restrict__ type_ids, const uint8_t* __restrict__ alive,
-                         int untyped, uint64_t* __restrict__ t, uint32_t* cflag, uint32_t tag) {
+                         int untyped, uint64_t* __restrict__ t, uint32_t* cflag, uint32_t tag,
+                         const uint32_t* __restrict__ rev_off, uint32_t n_rev, uint64_t* in_sum) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= nT) return;
     const uint32_t v = tl[i];
@@ -406,6 +409,9 @@ __global__ void k_level0(const uint32_t* __restrict__ tl, uint32_t nT, const uin
     if (tv != t[v]) {
         t[v] = tv;
         cflag[v] = tag;
+        if (v < n_rev)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&in_sum[v & (kInStripes - 1)]),
+                      static_cast<unsigned long long>(rev_off[v + 1] - rev_off[v]));
     }
 }
 
@@ -1312,10 +1318,11 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
     for (uint32_t j = 1; j <= st->K; j++) {
         const uint32_t par = j & 1;
         const uint32_t tag = tag0 + j;
-        if (j >= 2 && st->ctx->frontier_limit_pct < 100) {
-            // F_j holds at most B plus the in-neighbours of C_{j-1}: when that
-            // bound is far past the limit (a changed hub), the expansion would
-            // only confirm that the level goes to the full kernels
+        if (st->ctx->frontier_limit_pct < 100) {
+            // F_j holds at most B plus the in-neighbours of C_{j-1} (C_0: the
+            // type changes): when that bound is far past the limit (a changed
+            // hub), the expansion would only confirm that the level goes to
+            // the full kernels
             uint64_t in_sum[kInStripes];
             uint32_t nb = 0;
             hip_check(hipMemcpyAsync(in_sum, st->cnt.p->in_sum[par ^ 1], sizeof(in_sum), hipMemcpyDeviceToHost, s),
@@ -1535,7 +1542,7 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
     if (nT)
         k_level0<<<grid_for(nT), kBlock, 0, s>>>(d_tl, nT, st->type_off[st->tcur].p, st->type_ids[st->tcur].p,
                                                  st->alive.p, st->untyped ? 1 : 0, st->levels[0].p, st->cflag.p,
-                                                 tag0);
+                                                 tag0, st->rev_off[st->rcur].p, st->n_rev, st->cnt.p->in_sum[0]);
     hip_check(hipGetLastError(), "level 0");
     classes_begin(st);
     classes_level(st, 0);
