@@ -103,6 +103,14 @@ typedef struct bsim_state bsim_state;
  *                          which must have no incident edge
  * Multi-edges and repeated triples are allowed and never change results.
  * mem_kind says whether all arrays are host or device pointers.
+ *
+ * Limits of this library (valid input beyond them gives BSIM_E_UNSUPPORTED,
+ * never a truncated table): offsets and type ids are 32-bit (the paper's
+ * workloads all have fewer than 2^32 edges, so one offset segment covers
+ * them; there is no 8-byte offset or 2-byte type-id variant); labels < 2^24;
+ * a class table of next_pow2(1.5 n + 1) slots must fit 2^32 slots (n below
+ * about 2.86 * 10^9); a resident state holds at most 2^30 edges; change
+ * detection needs next_pow2(2 m + 2) <= 2^32 table slots per snapshot.
  */
 typedef struct {
     uint32_t n_vertices;
@@ -376,17 +384,22 @@ typedef struct {
 /* n_workers concurrent requests (1..64); mem_budget_bytes 0 = 90 % of the
  * device memory free at creation. */
 int bsim_server_create(int device, uint64_t mem_budget_bytes, uint32_t n_workers, bsim_server** out);
-/* Queue a request.  BSIM_E_BUSY: its footprint exceeds the whole budget;
- * BSIM_E_INVALID / BSIM_E_RANGE: malformed request (nothing queued). */
+/* Queue a request.  BSIM_E_BUSY: its footprint exceeds what the server-owned
+ * states leave of the budget (a queued request that comes to exceed it,
+ * because a keep_state request created a state meanwhile, fails with
+ * BSIM_E_BUSY instead of waiting for good); BSIM_E_INVALID / BSIM_E_RANGE:
+ * malformed request, or a server being freed (nothing queued). */
 int bsim_server_submit(bsim_server* srv, const bsim_request* req, uint64_t* ticket);
 /* Result of a request: BSIM_OK with *out (and *state_out for keep_state)
  * once done, the request's own error status if it failed, BSIM_E_BUSY if it
- * is not done and wait == 0.  Each ticket is collected once. */
+ * is not done and wait == 0.  Each ticket is collected once: polling a
+ * ticket again, or one never issued, gives BSIM_E_INVALID at once. */
 int bsim_server_poll(bsim_server* srv, uint64_t ticket, int wait, bsim_result** out, bsim_state** state_out);
 int bsim_server_stats_get(bsim_server* srv, bsim_server_stats* out);
 /* Free a server-owned state and return its memory to the budget. */
 int bsim_server_release_state(bsim_server* srv, bsim_state* state);
-/* Waits for running requests, then frees everything the server owns. */
+/* Cancels the requests that have not started, waits for the running ones,
+ * then frees everything the server owns (uncollected results included). */
 void bsim_server_free(bsim_server* srv);
 
 #ifdef __cplusplus

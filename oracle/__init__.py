@@ -2,8 +2,11 @@
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg import this package.  It shares no code with
-the GPU library (`paper_2111_12493_amd`) and imports nothing from it; the
-graphs both sides consume come from the separate input-generator module.
+the GPU library: nothing here loads libbsim or its binding.  The one thing
+it takes from the package directory is the input-generator module
+(`paper_2111_12493_amd.graphgen`: the `Graph` container and seeded
+generators, none of the method's arithmetic), whose graphs both sides
+consume.
 
 Contents
   bsim_oracle.c  -- the step-by-step hash-spec oracle (plain C, single thread)

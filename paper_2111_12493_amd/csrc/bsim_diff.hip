@@ -197,9 +197,9 @@ EdgeSet edge_set(const Staged& g, Arena& arena, hipStream_t s) {
     uint32_t* src = arena.alloc<uint32_t>(static_cast<size_t>(es.m) + 1);
     if (es.m) k_edge_rows<<<ceil_div(es.m, kBlock), kBlock, 0, s>>>(g.row_off, g.n, es.m, src);
     es.src = src;
-    const uint32_t cap = next_pow2(2ull * es.m + 2);
+    const uint64_t cap = table_slots(2ull * es.m + 2, 64, "the edge-triple table of a snapshot");
     es.table = arena.alloc<uint32_t>(cap);
-    es.mask = cap - 1;
+    es.mask = static_cast<uint32_t>(cap - 1);
     hip_check(hipMemsetAsync(es.table, 0, static_cast<size_t>(cap) * 4, s), "triple table");
     if (es.m) k_triple_insert<<<ceil_div(es.m, kBlock), kBlock, 0, s>>>(es);
     hip_check(hipGetLastError(), "triple table launch");

@@ -48,6 +48,9 @@ constexpr uint32_t kWaveSlots = 1024; // LDS de-dup slots per wave (>= 2 * kSmal
 constexpr uint32_t kChunkEdges = 4096;  // edges per block of a large frontier vertex
 constexpr uint32_t kFrontGrid = 2048;   // blocks of the frontier kernels (grid-stride)
 constexpr uint32_t kMaxStateTypes = 4096;
+// A large frontier vertex of degree d takes a table of next_pow2(2 d) slots
+// with 32-bit slot arithmetic, which holds for d <= 2^30.
+constexpr uint64_t kMaxStateEdges = 1ull << 30;
 
 // Device counters of one update batch.
 constexpr uint32_t kInStripes = 64;     // striped in-degree sums of a level's changed vertices
@@ -727,7 +730,7 @@ struct bsim_state {
     uint32_t tag_base = 0;  // change / frontier tags of the next batch start above this
     uint64_t* cls_slots = nullptr;
     uint32_t* cls_list = nullptr;
-    uint32_t cls_cap = 0;  // power of two
+    uint64_t cls_cap = 0;  // power of two, at most kMaxTableSlots
     DevBuf<uint32_t> cls_cnt, kpos, chunk_owner, big_done;
     DevBuf<BigEntry> big;
     DevBuf<uint64_t> big_acc, scratch;
@@ -808,7 +811,7 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
     st->big_acc.ensure(nv, 0, s);
     // at most n joins per level: load <= 2/3, and a table small enough to
     // stay mostly in the last-level cache for the class passes' random CAS
-    const uint32_t want = next_pow2(std::max<uint64_t>(static_cast<uint64_t>(n_new) + n_new / 2 + 1, 1024));
+    const uint64_t want = table_slots(static_cast<uint64_t>(n_new) + n_new / 2 + 1, 1024, "the class table");
     if (want > st->cls_cap) {
         if (st->cls_slots) (void)hipFreeAsync(st->cls_slots, s);
         if (st->cls_list) (void)hipFreeAsync(st->cls_list, s);
@@ -822,7 +825,7 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
 
 void ensure_salt(bsim_state* st, uint32_t max_label) {
     if (st->salt.p && max_label < st->salt.cap) return;
-    const uint32_t count = next_pow2(static_cast<uint64_t>(max_label) + 1);
+    const uint64_t count = next_pow2(static_cast<uint64_t>(max_label) + 1);  // labels < 2^24
     st->salt.ensure(count, 0, st->s);
     k_salt_table<<<grid_for(st->salt.cap), kBlock, 0, st->s>>>(st->salt.p, static_cast<uint32_t>(st->salt.cap));
     hip_check(hipGetLastError(), "salt launch");
@@ -1108,7 +1111,8 @@ void merge_edges(bsim_state* st, const HostBatch& hb, uint32_t n_old, Arena& are
     const uint32_t nc = static_cast<uint32_t>(hb.cu.size());
     const int c = st->cur;
     const uint64_t m_cap = static_cast<uint64_t>(m_old) + hb.n_present;
-    if (m_cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "this library supports fewer than 2^32 edges"};
+    if (m_cap > kMaxStateEdges)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "a resident state holds at most 2^30 edges"};
     st->src[c ^ 1].ensure(m_cap + 1, 0, s);
     st->tgt[c ^ 1].ensure(m_cap + 1, 0, s);
     st->lab[c ^ 1].ensure((m_cap + 1) * sizeof(LabT), 0, s);
@@ -1239,7 +1243,7 @@ SplitTable class_table(const bsim_state* st) {
     SplitTable T;
     T.slots = st->cls_slots;
     T.list = st->cls_list;
-    T.mask = st->cls_cap - 1;
+    T.mask = static_cast<uint32_t>(st->cls_cap - 1);
     return T;
 }
 
@@ -1564,6 +1568,8 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
                           const std::function<void(bsim_state*)>* stored_levels = nullptr) {
     if (p.flags & BSIM_PREV_LEVEL_EDGES)
         throw DeviceError{BSIM_E_UNSUPPORTED, "BSIM_PREV_LEVEL_EDGES is supported without a state only"};
+    if (graph.n_edges > kMaxStateEdges)
+        throw DeviceError{BSIM_E_UNSUPPORTED, "a resident state holds at most 2^30 edges"};
     hipStream_t s = ctx->stream;
     PhaseTimer tm(s);
     tm.mark(0);

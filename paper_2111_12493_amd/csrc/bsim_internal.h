@@ -255,11 +255,29 @@ inline void hip_check(hipError_t e, const char* what) {
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
 
-inline uint32_t next_pow2(uint64_t x) {
+inline uint64_t next_pow2(uint64_t x) {
     uint64_t p = 1;
     while (p < x) p <<= 1;
-    return static_cast<uint32_t>(p);
+    return p;
 }
+
+// Largest open-addressing table the library builds: slot indices and masks
+// are 32-bit.
+constexpr uint64_t kMaxTableSlots = 1ull << 32;
+
+// Slot count of a power-of-two table with at least `want` slots (and at
+// least `min_slots`); BSIM_E_UNSUPPORTED when that is more than
+// kMaxTableSlots, so that a 32-bit mask (slots - 1) always covers it.
+inline uint64_t table_slots(uint64_t want, uint64_t min_slots, const char* what) {
+    const uint64_t cap = next_pow2(want > min_slots ? want : min_slots);
+    if (cap > kMaxTableSlots)
+        throw DeviceError{BSIM_E_UNSUPPORTED, std::string(what) + " would need more than 2^32 table slots"};
+    return cap;
+}
+
+// Split / class table of a graph with n vertices: at most n joins per level,
+// load <= 2/3.
+inline uint64_t split_table_slots(uint64_t n) { return table_slots(n + n / 2 + 1, 64, "the class table"); }
 
 inline int bit_width(uint64_t x) {
     int b = 0;

@@ -905,11 +905,11 @@ uint32_t query_hub_table_slots(int device, bool device_max) {
     return p;
 }
 
-static SplitTable make_table(Arena& arena, uint32_t cap) {
+static SplitTable make_table(Arena& arena, uint64_t cap) {
     SplitTable T;
     T.slots = arena.alloc<uint64_t>(cap);
     T.list = arena.alloc<uint32_t>(static_cast<size_t>(kStripes) * kListPerStripe);
-    T.mask = cap - 1;
+    T.mask = static_cast<uint32_t>(cap - 1);
     return T;
 }
 
@@ -920,7 +920,7 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
     rb.h[0] = arena.alloc<uint64_t>(n);
     rb.h[1] = arena.alloc<uint64_t>(n);
     rb.rep = arena.alloc<uint32_t>(n);
-    const uint32_t cap = std::max<uint32_t>(next_pow2(static_cast<uint64_t>(n) + n / 2 + 1), 64);
+    const uint64_t cap = split_table_slots(n);
     for (int i = 0; i < 2; i++) {
         rb.tab[i] = make_table(arena, cap);
         hip_check(hipMemsetAsync(rb.tab[i].slots, 0, static_cast<size_t>(cap) * sizeof(uint64_t), s),

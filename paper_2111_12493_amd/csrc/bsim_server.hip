@@ -6,9 +6,14 @@
 // A request is admitted when its estimated device footprint fits the budget
 // left by running requests and server-owned states; requests that do not fit
 // yet wait and start as memory frees up, in submission order among those
-// that fit.  Updates of one state are applied one at a time, in submission
-// order.  A server-owned state gets a context and stream of its own, so its
-// updates never share a context with other work.
+// that fit.  A request that cannot fit beside the server-owned states even
+// with nothing else running is refused (BSIM_E_BUSY) at submit, or failed
+// with BSIM_E_BUSY once that becomes true while it waits.  Updates of one
+// state are applied one at a time, in submission order.  A server-owned state
+// gets a context and stream of its own, so its updates never share a context
+// with other work.  The device bytes of every state the server has seen are
+// read only by the thread that runs its requests, and kept under the lock
+// for admission.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -77,11 +82,10 @@ uint64_t summarize_footprint(const bsim_graph& g, const bsim_params& p, bool kee
     return b;
 }
 
-uint64_t update_footprint(const bsim_state* st, uint64_t n_ops, uint32_t flags_edges) {
-    (void)flags_edges;
-    // per-call scratch: uploaded changes, prefix sums, finalize (estimated
-    // from the state's current size)
-    return n_ops * 96 + state_bytes(st) / 4 + (1u << 20);
+// Per-call scratch of an update: uploaded changes, prefix sums, finalize
+// (estimated from the state's device bytes).
+uint64_t update_footprint(uint64_t state_bytes_now, uint64_t n_ops) {
+    return n_ops * 96 + state_bytes_now / 4 + (1u << 20);
 }
 
 }  // namespace
@@ -97,7 +101,11 @@ struct bsim_server {
     std::deque<Request> queue;
     std::set<const bsim_state*> busy;
     std::map<uint64_t, Done> done;
+    std::vector<bool> collected;               // by ticket: result already handed out
     std::map<bsim_state*, OwnedState> owned;
+    uint64_t owned_bytes = 0;                  // sum of owned[].bytes (part of in_use)
+    std::map<const bsim_state*, uint64_t> sbytes;  // device bytes of each state seen
+    uint32_t running = 0;
     uint64_t next_ticket = 1, submitted = 0, completed = 0, failed = 0;
     bool stopping = false;
     std::vector<double> lat[3];
@@ -106,9 +114,44 @@ struct bsim_server {
 
     void worker(uint32_t w);
     bool pick(Request& out);
+    void finish_locked(const Request& r, const Done& d);
+    void fail_unfit_locked();
 };
 
+// Record a finished (or failed, or refused) request.  Holds mu.
+void bsim_server::finish_locked(const Request& r, const Done& d) {
+    const auto now = Clock::now();
+    const double ms = std::chrono::duration<double, std::milli>(now - r.t_submit).count();
+    lat[0].push_back(ms);
+    lat[r.kind == BSIM_REQ_SUMMARIZE ? 1 : 2].push_back(ms);
+    last_done = now;
+    completed++;
+    if (d.status != BSIM_OK) failed++;
+    done[r.ticket] = d;
+}
+
+// With nothing running, a queued request larger than what the owned states
+// leave of the budget can never start: fail it with BSIM_E_BUSY (one of a
+// state's updates failing this way does not reorder the others).  Holds mu.
+void bsim_server::fail_unfit_locked() {
+    if (running) return;
+    bool any = false;
+    for (auto it = queue.begin(); it != queue.end();) {
+        if (owned_bytes + it->footprint > budget) {
+            Done d;
+            d.status = BSIM_E_BUSY;
+            finish_locked(*it, d);
+            it = queue.erase(it);
+            any = true;
+        } else {
+            ++it;
+        }
+    }
+    if (any) cv_done.notify_all();
+}
+
 bool bsim_server::pick(Request& out) {
+    fail_unfit_locked();
     // first request in submission order that fits and keeps per-state order
     std::set<const bsim_state*> earlier;
     for (auto it = queue.begin(); it != queue.end(); ++it) {
@@ -134,6 +177,7 @@ void bsim_server::worker(uint32_t w) {
             cv_work.wait(lk, [&] { return (stopping && queue.empty()) || pick(r); });
             if (!r.kind) return;  // stopping with an empty queue
             in_use += r.footprint;
+            running++;
             if (r.kind == BSIM_REQ_UPDATE) busy.insert(r.state);
         }
         Done d;
@@ -156,25 +200,34 @@ void bsim_server::worker(uint32_t w) {
                 if (os.stream) (void)hipStreamDestroy(os.stream);
                 os = OwnedState{};
             }
-        } else {
+        }
+        uint64_t new_bytes = 0;
+        if (r.kind == BSIM_REQ_UPDATE) {
             d.status = bsim_apply_updates(r.state, r.ops.data(), r.ops.size(), &d.result);
+            // this thread still holds the state (busy): its size is stable
+            new_bytes = state_bytes(r.state);
         }
         {
             std::lock_guard<std::mutex> lk(mu);
             in_use -= r.footprint;
+            running--;
             if (os.ctx) {
                 owned[d.state] = os;
                 in_use += os.bytes;
+                owned_bytes += os.bytes;
+                sbytes[d.state] = os.bytes;
             }
-            if (r.kind == BSIM_REQ_UPDATE) busy.erase(r.state);
-            const auto now = Clock::now();
-            const double ms = std::chrono::duration<double, std::milli>(now - r.t_submit).count();
-            lat[0].push_back(ms);
-            lat[r.kind == BSIM_REQ_SUMMARIZE ? 1 : 2].push_back(ms);
-            last_done = now;
-            completed++;
-            if (d.status != BSIM_OK) failed++;
-            done[r.ticket] = d;
+            if (r.kind == BSIM_REQ_UPDATE) {
+                busy.erase(r.state);
+                sbytes[r.state] = new_bytes;
+                auto it = owned.find(r.state);
+                if (it != owned.end()) {  // an update may grow an owned state
+                    in_use = in_use - it->second.bytes + new_bytes;
+                    owned_bytes = owned_bytes - it->second.bytes + new_bytes;
+                    it->second.bytes = new_bytes;
+                }
+            }
+            finish_locked(r, d);
         }
         cv_done.notify_all();
         cv_work.notify_all();
@@ -261,7 +314,6 @@ int bsim_server_submit(bsim_server* s, const bsim_request* req, uint64_t* ticket
                     r.ops[i].types = r.op_types[i].data();
                 }
             }
-            r.footprint = update_footprint(r.state, r.ops.size(), 0);
         } else {
             return BSIM_E_INVALID;
         }
@@ -272,8 +324,26 @@ int bsim_server_submit(bsim_server* s, const bsim_request* req, uint64_t* ticket
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (r.footprint > s->budget) return BSIM_E_BUSY;
+        if (r.kind == BSIM_REQ_UPDATE) {
+            // with a request of the state queued or running, a worker may be
+            // resizing it: take its size as of the last request; otherwise
+            // nothing here touches it and it can be read now
+            bool in_flight = s->busy.count(r.state) != 0;
+            for (const Request& q : s->queue) in_flight = in_flight || q.state == r.state;
+            auto it = s->sbytes.find(r.state);
+            uint64_t sb = 0;
+            if (in_flight && it != s->sbytes.end()) {
+                sb = it->second;
+            } else {
+                sb = state_bytes(r.state);
+                s->sbytes[r.state] = sb;
+            }
+            r.footprint = update_footprint(sb, r.ops.size());
+        }
+        if (s->stopping) return BSIM_E_INVALID;
+        if (r.footprint + s->owned_bytes > s->budget) return BSIM_E_BUSY;
         r.ticket = s->next_ticket++;
+        s->collected.push_back(false);
         *ticket = r.ticket;
         if (!s->any_submit) {
             s->first_submit = r.t_submit;
@@ -292,6 +362,7 @@ int bsim_server_poll(bsim_server* s, uint64_t ticket, int wait, bsim_result** ou
     if (state_out) *state_out = nullptr;
     std::unique_lock<std::mutex> lk(s->mu);
     if (ticket == 0 || ticket >= s->next_ticket) return BSIM_E_INVALID;
+    if (s->collected[ticket - 1]) return BSIM_E_INVALID;  // each ticket is collected once
     auto ready = [&] { return s->done.count(ticket) != 0; };
     if (!ready()) {
         if (!wait) return BSIM_E_BUSY;
@@ -299,6 +370,7 @@ int bsim_server_poll(bsim_server* s, uint64_t ticket, int wait, bsim_result** ou
     }
     Done d = s->done[ticket];
     s->done.erase(ticket);
+    s->collected[ticket - 1] = true;
     *out = d.result;
     if (state_out) *state_out = d.state;
     return d.status;
@@ -342,7 +414,9 @@ int bsim_server_release_state(bsim_server* s, bsim_state* st) {
         });
         os = it->second;
         s->owned.erase(it);
+        s->sbytes.erase(st);
         s->in_use -= os.bytes;
+        s->owned_bytes -= os.bytes;
     }
     bsim_state_free(st);
     bsim_ctx_free(os.ctx);
@@ -354,10 +428,19 @@ int bsim_server_release_state(bsim_server* s, bsim_state* st) {
 void bsim_server_free(bsim_server* s) {
     if (!s) return;
     {
+        // requests that have not started are cancelled (BSIM_E_BUSY); the
+        // running ones finish
         std::lock_guard<std::mutex> lk(s->mu);
         s->stopping = true;
+        for (const Request& r : s->queue) {
+            Done d;
+            d.status = BSIM_E_BUSY;
+            s->finish_locked(r, d);
+        }
+        s->queue.clear();
     }
     s->cv_work.notify_all();
+    s->cv_done.notify_all();
     for (auto& t : s->workers) t.join();
     (void)hipSetDevice(s->device);
     for (auto& kv : s->done) {

@@ -162,3 +162,45 @@ def test_previous_level_edge_requests():
         assert e.value.status == binding.E_UNSUPPORTED
     finally:
         srv.free()
+
+
+def test_update_that_cannot_fit_beside_owned_states_is_refused():
+    # a server-owned state stays in the budget; an update needs a quarter of
+    # the state on top, so under a budget the state nearly fills it is refused
+    # at submit (BSIM_E_BUSY) instead of queueing for good
+    g = gg.uniform_graph(3000, 15000, 8, 8, seed=9)
+    budget = 80 << 20
+    srv = binding.Server(mem_budget=budget, workers=2)
+    try:
+        res, state = srv.poll(srv.submit_summarize(binding.HostGraph(g), k_max=3, stop_at_fixpoint=False,
+                                                   keep_state=True))
+        res.free()
+        owned = srv.stats()["bytes_in_use"]
+        assert owned + owned // 4 + (1 << 20) > budget, owned
+        d = gg.update_ops(g, np.random.default_rng(3), 50, n_labels=8, n_types=8)
+        batch = binding.UpdateBatch(gg.ops_as_tuples(d))
+        with pytest.raises(binding.BsimError) as e:
+            srv.submit_update(state, batch)
+        assert e.value.status == binding.E_BUSY
+        # small summaries still fit beside the state and run
+        t = srv.submit_summarize(binding.HostGraph(gg.chain(5)))
+        got = fetch(srv.poll(t)[0])
+        assert_same(got, orc.summarize(gg.chain(5), 7, True), "beside the state")
+        # a ticket is collected once; polling it again fails at once
+        with pytest.raises(binding.BsimError) as e:
+            srv.poll(t)
+        assert e.value.status == binding.E_INVALID
+        srv.release_state(state)
+        assert srv.stats()["bytes_in_use"] == 0
+    finally:
+        srv.free()
+
+
+def test_free_cancels_queued_requests():
+    # one worker, a queue of requests: free returns (the running request
+    # finishes, the queued ones are cancelled) instead of waiting for all
+    g = gg.uniform_graph(20000, 100000, 4, 4, seed=5)
+    srv = binding.Server(workers=1)
+    for _ in range(8):
+        srv.submit_summarize(binding.HostGraph(g), k_max=UNB)
+    srv.free()
