@@ -35,8 +35,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+CBGEN_SRC = os.path.join(PKG, "cbgen.c")
+CBGEN_LIB = os.path.join(PKG, "libcbgen.so")
+
+
+def build_cbgen(verbose: bool = False) -> str:
+    """The counter-based input generator (host C, OpenMP), used by
+    ``graphgen.cb_rmat_graph``; it is input generation, not part of libbsim."""
+    tmp = CBGEN_LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                           "-o", tmp, CBGEN_SRC, "-lm"])
+    os.replace(tmp, CBGEN_LIB)
+    if verbose:
+        print("built", CBGEN_LIB)
+    return CBGEN_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    build_cbgen(verbose)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with cf.ThreadPoolExecutor(jobs) as ex:

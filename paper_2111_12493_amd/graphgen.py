@@ -252,6 +252,86 @@ def with_u16_labels(g: Graph) -> Graph:
 
 
 # ---------------------------------------------------------------------------
+# Counter-based generator (cbgen.c) for the largest workload
+# ---------------------------------------------------------------------------
+
+_cb = None
+
+
+def _cbgen():
+    """The compiled counter-based generator (built on first use if absent)."""
+    global _cb
+    if _cb is None:
+        import ctypes
+        import os
+
+        from . import build as _build
+
+        if not os.path.exists(_build.CBGEN_LIB) or \
+                os.path.getmtime(_build.CBGEN_LIB) < os.path.getmtime(_build.CBGEN_SRC):
+            _build.build_cbgen()
+        L = ctypes.CDLL(_build.CBGEN_LIB)
+        u64, u32, i32, dbl, p = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        L.cb_philox_out.argtypes = [u32, u32, u32, u32, u32, u32, p]
+        L.cb_philox_out.restype = None
+        L.cb_rmat_edges.argtypes = [u64, u32, u64, dbl, dbl, dbl, u32, dbl, p, p, p, i32]
+        L.cb_rmat_edges.restype = i32
+        L.cb_csr.argtypes = [u32, u64, p, p, p, i32, p, p, p]
+        L.cb_csr.restype = i32
+        L.cb_type_counts.argtypes = [u64, u32, u32, u32, p]
+        L.cb_type_counts.restype = None
+        L.cb_type_ids.argtypes = [u64, u32, u32, dbl, p, p]
+        L.cb_type_ids.restype = i32
+        L.cb_threads.argtypes = []
+        L.cb_threads.restype = i32
+        _cb = L
+    return _cb
+
+
+def philox4x32_10(counter: Sequence[int], key: Sequence[int]) -> Tuple[int, int, int, int]:
+    """One block of the Philox4x32-10 generator that cb_rmat_graph draws from."""
+    out = np.zeros(4, dtype=np.uint32)
+    _cbgen().cb_philox_out(*[int(c) & 0xFFFFFFFF for c in counter], *[int(k) & 0xFFFFFFFF for k in key],
+                           out.ctypes.data)
+    return tuple(int(x) for x in out)
+
+
+def cb_rmat_graph(scale: int, m: int, n_types: int, n_labels: int, types_lo: int = 0, types_hi: int = 4,
+                  s_types: float = 1.1, s_labels: float = 1.1, a: float = 0.57, b: float = 0.19,
+                  c: float = 0.19, seed: int = 27, label_u16: bool = False) -> Graph:
+    """R-MAT graph on 2^scale vertices from the counter-based generator
+    (cbgen.c): the same recipe as rmat_graph, with every random draw a pure
+    function of (seed, item), so the graph is identical on every host and
+    for any thread count.  Edge labels are uint16 when ``label_u16``."""
+    L = _cbgen()
+    n = 1 << scale
+    src = np.empty(max(m, 1), dtype=np.uint32)
+    dst = np.empty(max(m, 1), dtype=np.uint32)
+    lab = np.empty(max(m, 1), dtype=np.uint16 if label_u16 else np.uint32)
+    if L.cb_rmat_edges(seed, scale, m, a, b, c, n_labels, s_labels, src.ctypes.data, dst.ctypes.data,
+                       lab.ctypes.data, 1 if label_u16 else 0) != 0:
+        raise MemoryError("generator out of memory")
+    row_off = np.empty(n + 1, dtype=np.uint64)
+    tgt = np.empty(max(m, 1), dtype=np.uint32)
+    lab_csr = np.empty_like(lab)
+    rc = L.cb_csr(n, m, src.ctypes.data, dst.ctypes.data, lab.ctypes.data, lab.itemsize, row_off.ctypes.data,
+                  tgt.ctypes.data, lab_csr.ctypes.data)
+    del src, dst, lab
+    if rc != 0:
+        raise MemoryError("CSR build failed (%d)" % rc)
+    cnt = np.empty(n, dtype=np.uint32)
+    L.cb_type_counts(seed, n, types_lo, types_hi, cnt.ctypes.data)
+    typ_off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(cnt, out=typ_off[1:])
+    del cnt
+    typ = np.empty(max(int(typ_off[-1]), 1), dtype=np.uint32)
+    if L.cb_type_ids(seed, n, n_types, s_types, typ_off.ctypes.data, typ.ctypes.data) != 0:
+        raise MemoryError("generator out of memory")
+    return Graph(n=n, row_off=row_off, tgt=tgt[:m], lab=lab_csr[:m], typ_off=typ_off, typ=typ[:int(typ_off[-1])],
+                 n_labels=n_labels, n_types=n_types)
+
+
+# ---------------------------------------------------------------------------
 # Named workloads
 # ---------------------------------------------------------------------------
 
@@ -269,6 +349,15 @@ CONFIGS = {
     # base graph of the incremental / serving workload.
     "rmat24": dict(kind="rmat", scale=24, m=1 << 27, n_types=128, n_labels=64,
                    types_lo=0, types_hi=4, s_types=1.1, s_labels=1.1, seed=5),
+    # R-MAT scale 27, 2^30 edges, 1,024 types (0-4 per vertex) and 256 edge
+    # labels, Zipf 1.2, labels stored as uint16; counter-based generator.
+    "rmat27": dict(kind="cb_rmat", scale=27, m=1 << 30, n_types=1024, n_labels=256, types_lo=0, types_hi=4,
+                   s_types=1.2, s_labels=1.2, seed=27, label_u16=True),
+    # The same recipe at reduced sizes (tests that must stay fast).
+    "cb_rmat16": dict(kind="cb_rmat", scale=16, m=1 << 19, n_types=1024, n_labels=256, types_lo=0, types_hi=4,
+                      s_types=1.2, s_labels=1.2, seed=27, label_u16=True),
+    "cb_rmat22": dict(kind="cb_rmat", scale=22, m=1 << 25, n_types=1024, n_labels=256, types_lo=0, types_hi=4,
+                      s_types=1.2, s_labels=1.2, seed=27, label_u16=True),
     # Reduced shapes of the same recipes, for tests that must stay fast.
     "rmat16_chains": dict(kind="rmat", scale=16, m=1 << 19, n_types=256, n_labels=64,
                           types_lo=0, types_hi=4, s_types=1.1, s_labels=1.1, seed=2,
@@ -285,6 +374,8 @@ def make_config(name: str, seed: Optional[int] = None) -> Graph:
     kind = cfg.pop("kind")
     if kind == "uniform":
         return uniform_graph(**cfg)
+    if kind == "cb_rmat":
+        return cb_rmat_graph(**cfg)
     chains = cfg.pop("chains", 0)
     chain_len = cfg.pop("chain_len", 0)
     g = rmat_graph(**cfg)

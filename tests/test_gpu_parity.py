@@ -26,6 +26,19 @@ def test_paper_example_and_fig1():
         check(gg.fig1_scenario(after), 1, stop=False)
 
 
+def test_hash_spec_vectors():
+    # the frozen hash-spec vectors (HASH_SPEC.md), independent of the oracle
+    import hash_vectors
+
+    v = hash_vectors.load()
+    g = hash_vectors.graph(v)
+    for k, want in ((0, v["t"]), (1, v["h1"]), (2, v["h2"])):
+        gpu = gpu_summarize(g, k, stop=False)
+        assert [int(x) for x in gpu["hashes"]] == want, k
+    gpu = gpu_summarize(g, 0, stop=False, untyped=True)
+    assert [int(x) for x in gpu["hashes"]] == [v["t({})"]] * g.n
+
+
 @pytest.mark.parametrize("L", [1, 7, 300])
 def test_chain_closed_form(L):
     gpu, _ = check(gg.chain(L), UNB, untyped=True)

@@ -7,6 +7,8 @@ bisimulation definition, a pairwise brute force of that definition, and
 invariants of the refinement.
 """
 
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +17,7 @@ from oracle import oracle as orc
 from paper_2111_12493_amd import graphgen as gg
 
 MASK = (1 << 64) - 1
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 # ---------------------------------------------------------------- the mixer
@@ -82,6 +85,45 @@ def test_vertex_step_is_a_set_function():
     assert base != orc.vertex_step(t, [1, 2], [1, 0], h_prev)            # pairing
     assert base != orc.vertex_step(t + 1, [1, 2], [0, 1], h_prev)        # own type
     assert base != orc.vertex_step(t, [1], [0], h_prev)                  # a dropped pair
+
+
+# ------------------------------------------------ frozen hash-spec vectors
+
+def test_hash_spec_vectors():
+    # HASH_SPEC.md: values worked out from the definition by an independent
+    # calculator (tests/golden/make_hash_vectors.py)
+    import hash_vectors
+
+    v = hash_vectors.load()
+    assert [orc.lib().bo_const_t(), orc.lib().bo_const_l(), orc.lib().bo_const_s(), orc.lib().bo_const_e()] == \
+        [v["C_T"], v["C_L"], v["C_S"], v["C_E"]]
+    for key, types in (("t({})", []), ("t({0})", [0]), ("t({0,1})", [0, 1]), ("t({0,1})", [1, 0, 1]),
+                       ("t({3})", [3])):
+        assert orc.type_hash(types) == v[key], key
+    assert orc.type_hash([7, 2], untyped=True) == v["t({})"]
+    assert orc.label_salt(0) == v["salt(0)"] and orc.label_salt(5) == v["salt(5)"]
+    g = hash_vectors.graph(v)
+    for k, prev in ((1, v["t"]), (2, v["h1"])):
+        h_prev = np.array(prev, dtype=np.uint64)
+        for u in range(g.n):
+            got = orc.vertex_step(v["t"][u], g.tgt[g.row_off[u]:g.row_off[u + 1]],
+                                  g.lab[g.row_off[u]:g.row_off[u + 1]], h_prev)
+            assert got == v["h%d" % k][u], (k, u)
+    h1, _ = orc.iterate(g, 1)
+    assert [int(x) for x in h1] == v["h1"]
+    r = orc.summarize(g, 2, False)
+    assert [int(x) for x in r["hashes"]] == v["h2"]
+    assert [int(x) for x in r["prev_hashes"]] == v["h1"]
+
+
+def test_hash_spec_document_is_current():
+    import subprocess
+    import sys
+
+    table = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "golden", "make_hash_vectors.py"),
+                            "--markdown"], check=True, capture_output=True, text=True).stdout.strip()
+    with open(os.path.join(ROOT, "HASH_SPEC.md")) as f:
+        assert table in f.read()
 
 
 # ------------------------------------------------------- paper fixtures

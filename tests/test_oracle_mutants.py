@@ -37,25 +37,38 @@ MUTANTS = {
     "prev_level_edges_use_final_classes": (
         "const uint32_t* dst_ids = ((flags & BO_PREV_LEVEL_EDGES) && k_done >= 1) ? ncls : block_ids;",
         "const uint32_t* dst_ids = block_ids;"),
-}
-
-# Mutations that keep a valid *set* hash change hash values but no partition.
-# The paper fixes no hash function, so nothing outside the written spec can
-# pin the values themselves ("parity unpinned" for raw hash values); these
-# cases document that blind spot instead of hiding it.
-UNPINNED_VALUE_MUTANTS = {
-    # the type set already lives in the previous class, so dropping t(v) from
-    # h^k changes the values only
+    # value-only mistakes: a valid set hash, the same partitions, other hash
+    # values; the frozen hash-spec vectors catch them
     "drop_own_type": ("return bo_mix(t_v ^ bo_mix(cs + sum));",
                       "return bo_mix(bo_mix(cs + sum));"),
     "sum_replaced_by_xor": ("for (size_t i = 0; i < u; i++) sum += bo_mix(keys[i] ^ ce);",
                             "for (size_t i = 0; i < u; i++) sum ^= bo_mix(keys[i] ^ ce);"),
+    "type_term_unmixed": ("for (size_t i = 0; i < u; i++) sum += bo_mix(ct ^ (uint64_t)tmp[i]);",
+                          "for (size_t i = 0; i < u; i++) sum += ct ^ (uint64_t)tmp[i];"),
+    "salt_domain_constant_dropped": ("uint64_t bo_label_salt(uint32_t label) { return bo_mix(bo_const_l() + (uint64_t)label); }",
+                                     "uint64_t bo_label_salt(uint32_t label) { return bo_mix((uint64_t)label); }"),
+    "signature_domain_constant_dropped": ("return bo_mix(t_v ^ bo_mix(cs + sum));",
+                                          "return bo_mix(t_v ^ bo_mix(sum));"),
 }
+
+def _hash_vectors_hold() -> bool:
+    """The frozen hash-spec vectors (HASH_SPEC.md) on the worked graph."""
+    import hash_vectors
+
+    v = hash_vectors.load()
+    if orc.type_hash([0, 1]) != v["t({0,1})"] or orc.type_hash([3]) != v["t({3})"]:
+        return False
+    if orc.label_salt(5) != v["salt(5)"]:
+        return False
+    r = orc.summarize(hash_vectors.graph(v), 2, False)
+    return [int(x) for x in r["hashes"]] == v["h2"] and [int(x) for x in r["prev_hashes"]] == v["h1"]
 
 
 def _pins_hold() -> bool:
     """A compact selection of the pin checks; False as soon as one fails."""
     try:
+        if not _hash_vectors_hold():
+            return False
         g = gg.paper_example()
         r = orc.summarize(g, 2, False, True)
         if list(r["block_ids"]) != [0, 1, 2, 2] or list(r["blocks_per_iter"]) != [1, 3, 3]:
@@ -136,17 +149,3 @@ def test_planted_mistake_is_caught(name, tmp_path):
     before, after = MUTANTS[name]
     assert not _pins_hold_with(_compile_mutant(before, after, tmp_path)), \
         "planted mistake went unnoticed: " + name
-
-
-@pytest.mark.parametrize("name", sorted(UNPINNED_VALUE_MUTANTS))
-def test_value_only_mutation_keeps_partitions(name, tmp_path):
-    before, after = UNPINNED_VALUE_MUTANTS[name]
-    so = _compile_mutant(before, after, tmp_path)
-    assert _pins_hold_with(so)
-    saved = orc._lib
-    try:
-        orc._lib = orc.load(so)
-        mutated = orc.summarize(gg.paper_example(), 2, False, True)["hashes"]
-    finally:
-        orc._lib = saved
-    assert not np.array_equal(mutated, orc.summarize(gg.paper_example(), 2, False, True)["hashes"])
