@@ -2,16 +2,20 @@
 """Benchmark of the MI355X k-bisimulation path.
 
 One step = one full batch summarization (staging, type hashes, refinement
-iterations to the fixpoint, relabel, block sizes, summary edges) of one
-device-resident synthetic graph through the C ABI.  Default workload: an
-R-MAT graph (a, b, c = 0.57, 0.19, 0.19) with 2^22 vertices and 2^25 edges,
-256 type labels (Zipf 1.1, 0-4 per vertex), 64 edge labels (Zipf 1.1), plus
-64 disjoint labeled chains of 2,000 edges, which force >= 2,001 iterations.
+iterations to the fixpoint or the cap, relabel, block sizes, summary edges)
+of one device-resident synthetic graph through the C ABI.  Default workload
+(rmat27): an R-MAT graph (a, b, c = 0.57, 0.19, 0.19) with 2^27 vertices and
+2^30 edges, 1,024 type labels (Zipf 1.2, 0-4 per vertex) and 256 edge labels
+(Zipf 1.2) stored as uint16, run to the fixpoint capped at k = 64; the graph
+comes from the counter-based generator, so the oracle digests of the same
+graph pin it.
 
 Prints ONE JSON line (rank 0, N = 1) with the whole-job throughput in
 edge-iterations/s (sum over executed iterations of |E|, over the wall time
-of the timed steps), the refinement kernel's HBM roofline figures and a
-bounded CPU-oracle baseline.
+of the timed steps), the refinement iteration's HBM roofline figures and a
+bounded CPU-oracle baseline.  Extra keys: the long k-chaining workload
+(rmat22_chains, 2^25 edges plus 64 chains of 2,000 edges, >= 2,001
+iterations), the incremental, serving, batched and direction legs.
 """
 
 from __future__ import annotations
@@ -53,19 +57,44 @@ def read_traffic(workload: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(g, iters: int):
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, stride: int):
+    """The oracle (one thread) on a bounded sample of the headline graph:
+    type hashes of all vertices (untimed), then the refinement step h^1 of
+    every stride-th vertex (its gathers reach the full h^0 array) and the
+    class refinement of those vertices, timed.  Edge-iterations/s = the
+    sample's edges over that time."""
+    import numpy as np
+
     from oracle import oracle as orc
 
     try:
         os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
     except Exception:
         pass
+    t = orc.type_hashes(g)
+    count = (g.n + stride - 1) // stride
+    deg = np.diff(g.row_off.astype(np.int64))
+    edges = int(deg[::stride].sum())
     t0 = time.perf_counter()
-    orc.iterate(g, iters)
+    h1 = orc.step_strided(g, t, t, 0, stride, count)
+    orc.refine_classes(np.zeros(count, dtype=np.uint32), h1)
     dt = time.perf_counter() - t0
-    return {"value": iters * g.m / dt, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": "type hashes + first %d refinement iterations of the same graph, single "
-                      "thread, %.1f s" % (iters, dt)}
+    return {"value": edges / dt, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu_model(),
+            "sample": "one refinement step (h^1 from h^0, gathers over the whole graph) and the class "
+                      "refinement of every %d-th vertex of the headline graph: %d vertices, %d edges, "
+                      "single thread, %.1f s" % (stride, count, edges, dt)}
 
 
 def percentile(v, q):
@@ -284,16 +313,101 @@ def batched_leg(args, binding, gg, torch):
             "speedup": tp / tb}
 
 
+WORKLOADS = {
+    # name: iteration cap of the workload's runs (None = to the fixpoint)
+    "rmat27": 64,
+    "rmat22_chains": None,
+    "uniform_10k_50k": 10,
+}
+
+
+def timed_summaries(binding, torch, ctx, dg, k_max, steps, warmup, tag):
+    """`warmup` untimed and `steps` timed summarizations (to the fixpoint,
+    capped at k_max); per-step records and the timed wall time."""
+
+    def step():
+        r = binding.summarize(ctx, dg, k_max=k_max, stop_at_fixpoint=True)
+        rec = dict(k_done=r.k_done, launches=r.n_iter_launches, ms_kernels=r.ms_iter_kernels,
+                   ms_hub=r.ms_hub_kernels, timed=r.n_timed_launches,
+                   ms_iterate=r.ms_iterate, ms_stage=r.ms_stage, ms_finalize=r.ms_finalize,
+                   ms_total=r.ms_total, n_blocks=r.n_blocks, n_se=r.n_summary_edges)
+        r.free()
+        return rec
+
+    for i in range(warmup):
+        rec = step()
+        print("# %s warmup %d: k_done=%d blocks=%d %.1f ms" % (tag, i, rec["k_done"], rec["n_blocks"],
+                                                               rec["ms_total"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for i, r in enumerate(recs):
+        print("# %s step %d: k_done=%d launches=%d stage %.2f ms, iterate %.2f ms (kernels %.2f + hubs %.2f over "
+              "%d timed launches), finalize %.2f ms" % (tag, i, r["k_done"], r["launches"], r["ms_stage"],
+                                                         r["ms_iterate"], r["ms_kernels"], r["ms_hub"], r["timed"],
+                                                         r["ms_finalize"]), file=sys.stderr, flush=True)
+    return recs, wall
+
+
+def roofline(recs, g, workload):
+    """HBM roofline of the refinement iteration (the refinement launch plus
+    the hub-bucket and hub-finish launches of the same iteration), from the
+    HIP events the library records on its own stream around the working
+    launches (1..k_done+1 of a run; the rest of the last queued chunk return
+    at once and are not timed)."""
+    label_bytes = 2 if g.lab.dtype.itemsize == 2 else 4
+    b_iter = iteration_bytes(g.n, g.m, label_bytes)
+    kern_ms = sum(r["ms_kernels"] for r in recs)
+    hub_ms = sum(r["ms_hub"] for r in recs)
+    timed = sum(r["timed"] for r in recs)
+    iter_us = (kern_ms + hub_ms) * 1e3 / max(timed, 1)
+    achieved = b_iter / (iter_us * 1e-6) / 1e9 if timed else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(workload),
+            "kernel": "k_iterate + k_hub + k_hub_finish (one refinement iteration)",
+            "algorithmic_bytes_per_launch": b_iter, "avg_launch_us": iter_us,
+            "k_iterate_avg_us": kern_ms * 1e3 / max(timed, 1), "hub_kernels_avg_us": hub_ms * 1e3 / max(timed, 1),
+            "timed_launches": timed, "working_launches": sum(min(r["k_done"] + 1, r["launches"]) for r in recs),
+            "launches_issued": sum(r["launches"] for r in recs)}
+
+
+def chaining_leg(args, binding, torch):
+    """The long k-chaining workload (rmat22_chains: R-MAT scale 22, 2^25 edges,
+    plus 64 chains of 2,000 edges; >= 2,001 iterations to the fixpoint)."""
+    from paper_2111_12493_amd import graphgen as gg
+
+    g = gg.make_config("rmat22_chains")
+    dg = binding.DeviceGraph(g)
+    ctx = binding.Context(0)
+    ctx.set_option("time_launches", 16)  # events on every launch would add gaps
+    recs, wall = timed_summaries(binding, torch, ctx, dg, binding.K_UNBOUNDED, args.chain_steps, 1, "rmat22_chains")
+    out = {"workload": "rmat22_chains", "vertices": g.n, "edges": g.m, "k_done": recs[-1]["k_done"],
+           "blocks": recs[-1]["n_blocks"], "steps": len(recs), "ms_per_step": wall * 1e3 / len(recs),
+           "edge_iterations_per_s": sum(r["k_done"] for r in recs) * g.m / wall,
+           "roofline": roofline(recs, g, "rmat22_chains")}
+    if not args.no_directions:
+        out["directions"] = directions_leg(binding, torch, ctx, dg, g)
+    ctx.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat22_chains")
-    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--workload", default="rmat27", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-stride", type=int, default=16,
+                    help="CPU baseline: the oracle's step on every N-th vertex of the headline graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--time-every", type=int, default=16,
-                    help="bracket every N-th refinement launch with HIP events")
+    ap.add_argument("--time-every", type=int, default=1,
+                    help="bracket every N-th refinement launch of the headline runs with HIP events")
+    ap.add_argument("--no-chaining", action="store_true")
+    ap.add_argument("--chain-steps", type=int, default=3)
     ap.add_argument("--no-incremental", action="store_true")
     ap.add_argument("--inc-workload", default="rmat24")
     ap.add_argument("--inc-batches", type=int, default=16)
@@ -325,8 +439,8 @@ def main() -> int:
     t_gen = time.perf_counter()
     g = gg.make_config(args.workload)
     gen_s = time.perf_counter() - t_gen
-    print("# workload %s: %d vertices, %d edges (generated in %.1f s)" % (args.workload, g.n, g.m, gen_s),
-          file=sys.stderr, flush=True)
+    print("# workload %s: %d vertices, %d edges (generated on the host in %.1f s)"
+          % (args.workload, g.n, g.m, gen_s), file=sys.stderr, flush=True)
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
         src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
@@ -339,53 +453,16 @@ def main() -> int:
         del src, dst
     dg = binding.DeviceGraph(g)
     ctx = binding.Context(0)
-    # time every 16th launch: events on every launch would add gaps to the timed run
     ctx.set_option("time_launches", args.time_every)
     torch.cuda.synchronize()
-
-    def step():
-        r = binding.summarize(ctx, dg, k_max=binding.K_UNBOUNDED)
-        rec = dict(k_done=r.k_done, launches=r.n_iter_launches, ms_kernels=r.ms_iter_kernels,
-                   ms_hub=r.ms_hub_kernels, timed=r.n_timed_launches,
-                   ms_iterate=r.ms_iterate, ms_stage=r.ms_stage, ms_finalize=r.ms_finalize,
-                   ms_total=r.ms_total, n_blocks=r.n_blocks, n_se=r.n_summary_edges)
-        r.free()
-        return rec
-
-    for i in range(args.warmup):
-        rec = step()
-        print("# warmup %d: k_done=%d blocks=%d %.1f ms" % (i, rec["k_done"], rec["n_blocks"], rec["ms_total"]),
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    recs = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        recs.append(step())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for i, r in enumerate(recs):
-        print("# step %d: k_done=%d launches=%d stage %.2f ms, iterate %.2f ms (kernels %.2f), "
-              "finalize %.2f ms" % (i, r["k_done"], r["launches"], r["ms_stage"], r["ms_iterate"],
-                                    r["ms_kernels"], r["ms_finalize"]), file=sys.stderr, flush=True)
-
+    k_cap = WORKLOADS[args.workload]
+    recs, wall = timed_summaries(binding, torch, ctx, dg, binding.K_UNBOUNDED if k_cap is None else k_cap,
+                                 args.steps, args.warmup, args.workload)
     edge_iters = sum(r["k_done"] for r in recs) * g.m
-    value = edge_iters / wall
-    label_bytes = 2 if g.lab.dtype.itemsize == 2 else 4
-    b_iter = iteration_bytes(g.n, g.m, label_bytes)
-    # live kernel timing: HIP events on the library's stream around every
-    # N-th refinement launch; launches 1..k_done+1 of a run do the work, the
-    # rest of the last queued chunk return at once and are not counted
-    kern_ms = sum(r["ms_kernels"] for r in recs)
-    hub_ms = sum(r["ms_hub"] for r in recs)
-    launches = sum(r["launches"] for r in recs)
-    working = sum(min(r["k_done"] + 1, r["launches"]) for r in recs)
-    timed = sum(r["timed"] for r in recs)
-    avg_us = kern_ms * 1e3 / max(timed, 1)
-    achieved = b_iter / (avg_us * 1e-6) / 1e9 if kern_ms > 0 else 0.0
-    traffic = read_traffic(args.workload)
+    iter_ms = sum(r["ms_iterate"] for r in recs)
     out = {
         "metric": "edge-iterations/s for k-bisimulation (% HBM roofline); p50/p99 update latency",
-        "value": value,
+        "value": edge_iters / wall,
         "unit": "edge-iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -397,22 +474,31 @@ def main() -> int:
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": args.workload, "vertices": g.n, "edges": g.m,
-                   "k_done": recs[-1]["k_done"], "blocks": recs[-1]["n_blocks"],
-                   "summary_edges": recs[-1]["n_se"],
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_iterate", "algorithmic_bytes_per_launch": b_iter,
-                     "avg_launch_us": avg_us, "timed_launches": timed, "working_launches": working,
-                     "launches_issued": launches, "hub_kernel_avg_us": hub_ms * 1e3 / max(timed, 1)},
+                   "k_cap": k_cap, "k_done": recs[-1]["k_done"], "fixpoint": None,
+                   "blocks": recs[-1]["n_blocks"], "summary_edges": recs[-1]["n_se"],
+                   "label_bytes": int(g.lab.dtype.itemsize), "parallelism": "single GPU"},
+        "roofline": roofline(recs, g, args.workload),
+        # the same steps split by phase (device events of each call)
+        "phases_ms_per_step": {"stage": sum(r["ms_stage"] for r in recs) / len(recs),
+                               "iterate": iter_ms / len(recs),
+                               "finalize": sum(r["ms_finalize"] for r in recs) / len(recs)},
+        "iteration_loop_edge_iterations_per_s": edge_iters / (iter_ms * 1e-3) if iter_ms else None,
+        "host_generation_s": gen_s,
     }
-    if not args.no_directions:
-        out["directions"] = directions_leg(binding, torch, ctx, dg, g)
+    r = binding.summarize(ctx, dg, k_max=binding.K_UNBOUNDED if k_cap is None else k_cap, stop_at_fixpoint=True,
+                          summary_edges=False)
+    out["config"]["fixpoint"] = int(r.fixpoint)
+    r.free()
     ctx.close()
     del dg
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_stride)
+        print("# cpu baseline: %.3g edge-iterations/s" % out["cpu_baseline"]["value"], file=sys.stderr, flush=True)
     del g
+    if not args.no_chaining:
+        out["long_chaining"] = chaining_leg(args, binding, torch)
+    torch.cuda.empty_cache()
     if not (args.no_incremental and args.no_serving):
         from paper_2111_12493_amd import devgen
 

@@ -336,6 +336,22 @@ int bsim_diff_snapshots(bsim_ctx* ctx, const bsim_graph* before, const bsim_grap
                         uint64_t* n_ops);
 void bsim_updates_free(bsim_update* ops);
 
+/* ---- measurement probes (the refinement's roofline) ---------------------- */
+
+/*
+ * bsim_probe_gather: *ms_per_pass = device time of one pass that streams
+ * targets[0..m) once and gathers one 8-byte value h[targets[e]] per edge
+ * (targets >= n are skipped), averaged over `reps` passes after one warm-up
+ * pass; the memory pattern that bounds a refinement iteration, without its
+ * labels, de-duplication or classes.  targets and h are device arrays the
+ * caller owns; the call allocates a small sink.  bsim_probe_copy: the same
+ * for a STREAM-style copy of `bytes` bytes between two arrays the call
+ * allocates (read + write).  BSIM_E_INVALID for null pointers or reps = 0.
+ */
+int bsim_probe_gather(bsim_ctx* ctx, const uint32_t* targets, uint64_t m, const uint64_t* h, uint32_t n,
+                      uint32_t reps, float* ms_per_pass);
+int bsim_probe_copy(bsim_ctx* ctx, uint64_t bytes, uint32_t reps, float* ms_per_pass);
+
 /* ---- batched summarization (many independent graphs, one launch stream) -- */
 
 /*

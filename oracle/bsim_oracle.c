@@ -359,6 +359,38 @@ int bo_iterate(uint32_t n, const uint64_t* row_off, const uint32_t* tgt, const u
 }
 
 /*
+ * Timing samples of one refinement step (the benchmark's CPU baseline on a
+ * graph too large to run whole): t(v) for every vertex, then the step of
+ * bo_summarize for every stride-th vertex from v0 (out[i] = h^k of vertex
+ * v0 + i * stride, given h_prev = h^{k-1}), and the class refinement of
+ * those vertices with bo_refine_classes.  The same per-vertex code as the
+ * full runs; nothing is reordered.
+ */
+void bo_type_hashes(uint32_t n, const uint64_t* typ_off, const uint32_t* typ, uint32_t flags, uint64_t* t) {
+    for (uint32_t v = 0; v < n; v++)
+        t[v] = bo_type_hash(typ + typ_off[v], (uint32_t)(typ_off[v + 1] - typ_off[v]), flags & BO_UNTYPED);
+}
+
+int bo_step_strided(uint32_t n, const uint64_t* row_off, const uint32_t* tgt, const uint32_t* lab,
+                    const uint64_t* t, const uint64_t* h_prev, uint32_t v0, uint32_t stride, uint32_t count,
+                    uint64_t* out) {
+    if (stride == 0 || (count && (uint64_t)v0 + (uint64_t)(count - 1) * stride >= n)) return BO_E_INVALID;
+    uint64_t maxd = 1;
+    for (uint32_t i = 0; i < count; i++) {
+        const uint32_t v = v0 + i * stride;
+        if (row_off[v + 1] - row_off[v] > maxd) maxd = row_off[v + 1] - row_off[v];
+    }
+    uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * maxd);
+    if (!keys) return BO_E_NOMEM;
+    for (uint32_t i = 0; i < count; i++) {
+        const uint32_t v = v0 + i * stride;
+        out[i] = vertex_step(t[v], tgt + row_off[v], lab + row_off[v], row_off[v + 1] - row_off[v], h_prev, keys);
+    }
+    free(keys);
+    return BO_OK;
+}
+
+/*
  * Direction and label parameterizations (Sec. 2.4: the label
  * parameterization keeps only the edges whose label is in a set P_l; the
  * direction parameterization takes outgoing edges, incoming edges or both;

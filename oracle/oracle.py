@@ -63,6 +63,10 @@ def load(path: str) -> ctypes.CDLL:
     L.bo_iterate.argtypes = [u32, p, p, p, p, p, u32, u32, p, p]
     L.bo_label_salt_in.restype = u64
     L.bo_label_salt_in.argtypes = [u32]
+    L.bo_type_hashes.restype = None
+    L.bo_type_hashes.argtypes = [u32, p, p, u32, p]
+    L.bo_step_strided.restype = ctypes.c_int
+    L.bo_step_strided.argtypes = [u32, p, p, p, p, p, u32, u32, u32, p]
     L.bo_summarize_ext.restype = ctypes.c_int
     L.bo_summarize_ext.argtypes = [u32, u64, p, p, p, p, p, p, u32, u32, p, u32,
                                    p, p, p, p, p, p, p, p, p, p, p]
@@ -222,3 +226,28 @@ def iterate(g, iters: int, untyped: bool = False):
     if rc != 0:
         raise RuntimeError("oracle iterate failed (%d)" % rc)
     return out[:g.n], counts
+
+
+def type_hashes(g, untyped: bool = False) -> np.ndarray:
+    """t(v) for every vertex of g (alive or not)."""
+    typ_off = np.ascontiguousarray(g.typ_off, dtype=np.uint64)
+    typ = np.ascontiguousarray(g.typ, dtype=np.uint32)
+    if typ.size == 0:
+        typ = np.zeros(1, dtype=np.uint32)
+    out = np.zeros(max(g.n, 1), dtype=np.uint64)
+    lib().bo_type_hashes(g.n, _ptr(typ_off), _ptr(typ), UNTYPED if untyped else 0, _ptr(out))
+    return out[:g.n]
+
+
+def step_strided(g, t: np.ndarray, h_prev: np.ndarray, v0: int, stride: int, count: int) -> np.ndarray:
+    """The refinement step of every stride-th vertex from v0 (h^k from
+    h_prev = h^{k-1}), as in the full runs."""
+    row_off = np.ascontiguousarray(g.row_off, dtype=np.uint64)
+    tgt = np.ascontiguousarray(g.tgt, dtype=np.uint32)
+    lab = np.ascontiguousarray(g.lab, dtype=np.uint32)
+    out = np.zeros(max(count, 1), dtype=np.uint64)
+    rc = lib().bo_step_strided(g.n, _ptr(row_off), _ptr(tgt), _ptr(lab), _ptr(np.ascontiguousarray(t)),
+                               _ptr(np.ascontiguousarray(h_prev)), v0, stride, count, _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the sample (%d)" % rc)
+    return out[:count]

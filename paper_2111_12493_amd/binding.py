@@ -107,6 +107,8 @@ EXPORTS = {
     "bsim_server_stats_get": (ctypes.c_int, [_p, ctypes.POINTER(BsimServerStats)]),
     "bsim_server_release_state": (ctypes.c_int, [_p, _p]),
     "bsim_server_free": (None, [_p]),
+    "bsim_probe_gather": (ctypes.c_int, [_p, _p, _u64, _p, _u32, _u32, ctypes.POINTER(ctypes.c_float)]),
+    "bsim_probe_copy": (ctypes.c_int, [_p, _u64, _u32, ctypes.POINTER(ctypes.c_float)]),
     "bsim_batch_summarize": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), _u32,
                                             ctypes.POINTER(BsimParams),
                                             ctypes.POINTER(ctypes.POINTER(BsimResult))]),
@@ -333,6 +335,22 @@ def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: b
                                               ids.ctypes.data_as(_p) if ids.size else None, ids.size,
                                               ctypes.byref(out)))
     return Result(out)
+
+
+def probe_gather(ctx: Context, graph: "DeviceGraph", h, reps: int = 10) -> float:
+    """ms per pass of the gather probe over graph's targets, gathering from
+    the device tensor h (int64, at least graph.n entries)."""
+    ms = ctypes.c_float()
+    ctx.check(lib().bsim_probe_gather(ctx.handle, graph.tgt.data_ptr(), graph.m, h.data_ptr(), graph.n, reps,
+                                      ctypes.byref(ms)))
+    return ms.value
+
+
+def probe_copy(ctx: Context, nbytes: int, reps: int = 10) -> float:
+    """ms per pass of a STREAM-style copy of nbytes bytes."""
+    ms = ctypes.c_float()
+    ctx.check(lib().bsim_probe_copy(ctx.handle, int(nbytes), reps, ctypes.byref(ms)))
+    return ms.value
 
 
 def diff_snapshots(ctx: Context, before, after, as_tuples: bool = True):

@@ -145,29 +145,98 @@ int cb_rmat_edges(uint64_t seed, uint32_t scale, uint64_t m, double a, double b,
  * CSR from an edge list, stable in edge order: row_off[n+1] (uint64), and
  * tgt / lab (label width lab_bytes) in CSR order.  Returns 0, -1 on memory,
  * -2 on an endpoint >= n.
+ *
+ * A parallel counting sort in two levels that keeps edge order within a
+ * source: edges go to source-range buckets (chunks of the edge list in
+ * order, edges in order within a chunk), then each bucket is counted and
+ * placed by exact source.  The result does not depend on the thread count.
  */
 int cb_csr(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst, const void* lab, int lab_bytes,
            uint64_t* row_off, uint32_t* tgt, void* lab_out) {
-    uint64_t* cur = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
-    if (!cur) return -1;
-    for (uint64_t i = 0; i < m; i++) {
-        if (src[i] >= n || dst[i] >= n) {
-            free(cur);
-            return -2;
+    int bits = 0;
+    while (bits < 32 && ((uint64_t)1 << bits) < (uint64_t)n) bits++;
+    const int bs = bits > 12 ? bits - 12 : 0;                 /* at most 4096 buckets */
+    const uint64_t B = n ? (((uint64_t)n - 1) >> bs) + 1 : 1;
+    const uint64_t C = 256;                                   /* edge chunks */
+    const uint64_t per = (m + C - 1) / C;
+    uint64_t* hist = (uint64_t*)calloc(C * B, sizeof(uint64_t));
+    uint64_t* bstart = (uint64_t*)malloc(sizeof(uint64_t) * (B + 1));
+    uint32_t* ts = (uint32_t*)malloc(sizeof(uint32_t) * (m ? m : 1));
+    uint32_t* td = (uint32_t*)malloc(sizeof(uint32_t) * (m ? m : 1));
+    uint8_t* tl = (uint8_t*)malloc((size_t)lab_bytes * (m ? m : 1));
+    if (!hist || !bstart || !ts || !td || !tl) {
+        free(hist); free(bstart); free(ts); free(td); free(tl);
+        return -1;
+    }
+    int bad = 0;
+    int64_t c;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|: bad)
+    for (c = 0; c < (int64_t)C; c++) {
+        const uint64_t i0 = (uint64_t)c * per, i1 = i0 + per < m ? i0 + per : m;
+        uint64_t* h = hist + (uint64_t)c * B;
+        for (uint64_t i = i0; i < i1; i++) {
+            if (src[i] >= n || dst[i] >= n) {
+                bad = 1;
+                break;
+            }
+            h[src[i] >> bs]++;
         }
-        cur[src[i]]++;
     }
-    row_off[0] = 0;
-    for (uint32_t v = 0; v < n; v++) row_off[v + 1] = row_off[v] + cur[v];
-    memcpy(cur, row_off, sizeof(uint64_t) * n);
-    for (uint64_t i = 0; i < m; i++) {
-        const uint64_t p = cur[src[i]]++;
-        tgt[p] = dst[i];
-        if (lab_bytes == 2) ((uint16_t*)lab_out)[p] = ((const uint16_t*)lab)[i];
-        else ((uint32_t*)lab_out)[p] = ((const uint32_t*)lab)[i];
+    if (bad) {
+        free(hist); free(bstart); free(ts); free(td); free(tl);
+        return -2;
     }
-    free(cur);
-    return 0;
+    /* bucket-major, chunk-minor exclusive prefix: hist becomes the offsets */
+    uint64_t pos = 0;
+    for (uint64_t b = 0; b < B; b++) {
+        bstart[b] = pos;
+        for (uint64_t cc = 0; cc < C; cc++) {
+            const uint64_t x = hist[cc * B + b];
+            hist[cc * B + b] = pos;
+            pos += x;
+        }
+    }
+    bstart[B] = pos;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (c = 0; c < (int64_t)C; c++) {
+        const uint64_t i0 = (uint64_t)c * per, i1 = i0 + per < m ? i0 + per : m;
+        uint64_t* cur = hist + (uint64_t)c * B;
+        for (uint64_t i = i0; i < i1; i++) {
+            const uint64_t p = cur[src[i] >> bs]++;
+            ts[p] = src[i];
+            td[p] = dst[i];
+            memcpy(tl + p * lab_bytes, (const uint8_t*)lab + i * lab_bytes, (size_t)lab_bytes);
+        }
+    }
+    int64_t b;
+    int oom = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|: oom)
+    for (b = 0; b < (int64_t)B; b++) {
+        const uint64_t v0 = (uint64_t)b << bs;
+        const uint64_t v1 = v0 + ((uint64_t)1 << bs) < n ? v0 + ((uint64_t)1 << bs) : n;
+        uint64_t* cnt = (uint64_t*)calloc((size_t)(v1 - v0) + 1, sizeof(uint64_t));
+        if (!cnt) {
+            oom = 1;
+            continue;
+        }
+        for (uint64_t p = bstart[b]; p < bstart[b + 1]; p++) cnt[ts[p] - v0]++;
+        uint64_t run = bstart[b];
+        for (uint64_t v = v0; v < v1; v++) {
+            const uint64_t x = cnt[v - v0];
+            row_off[v] = run;
+            cnt[v - v0] = run;
+            run += x;
+        }
+        for (uint64_t p = bstart[b]; p < bstart[b + 1]; p++) {
+            const uint64_t q = cnt[ts[p] - v0]++;
+            tgt[q] = td[p];
+            memcpy((uint8_t*)lab_out + q * lab_bytes, tl + p * lab_bytes, (size_t)lab_bytes);
+        }
+        free(cnt);
+    }
+    row_off[n] = m;
+    free(hist); free(bstart); free(ts); free(td); free(tl);
+    return oom ? -1 : 0;
 }
 
 /* Type counts per vertex (lo..hi), written to cnt[n]. */

@@ -42,6 +42,12 @@ int bsim_ctx_create(int device, void* hip_stream, bsim_ctx** out) {
         delete c;
         return BSIM_E_NOMEM;
     }
+    for (hipEvent_t& e : c->loop_ev) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            bsim_ctx_free(c);
+            return BSIM_E_DEVICE;
+        }
+    }
     // keep freed stream-ordered memory cached for later calls
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -57,6 +63,8 @@ void bsim_ctx_free(bsim_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+    for (hipEvent_t e : ctx->loop_ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 

@@ -12,6 +12,7 @@ struct bsim_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bsim::RunStatus* status_host = nullptr;  // pinned, 4 entries
+    hipEvent_t loop_ev[2] = {nullptr, nullptr};  // status-copy events of the refinement loop
     uint32_t chunk_max = 32;
     uint32_t time_launches = 0;
     uint32_t hub_table_slots = 8192;  // LDS slots per hub-bucket block on this device
@@ -68,8 +69,10 @@ struct LoopResult {
 // Iterations 0..k_done on a staged graph.  rep_prev (nullable, n entries)
 // receives the class representatives of level k_done - 1 (of level 0 when
 // k_done = 0; at a fixpoint those of level k_done, the same partition).
+// use_timers: bracket launches with HIP events when the ctx option asks for
+// it.
 LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
-                          LevelSink* sink, Arena& arena, uint32_t* rep_prev = nullptr);
+                          LevelSink* sink, Arena& arena, uint32_t* rep_prev = nullptr, bool use_timers = true);
 
 // finalize with summary edges into the classes named by rep_prev (their
 // first-occurrence block ids) instead of the final blocks.

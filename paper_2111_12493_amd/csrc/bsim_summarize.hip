@@ -83,7 +83,7 @@ void upload_graph(const bsim_graph& in, Staged& g, Arena& arena, hipStream_t s) 
 }
 
 LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
-                          LevelSink* sink, Arena& arena, uint32_t* rep_prev) {
+                          LevelSink* sink, Arena& arena, uint32_t* rep_prev, bool use_timers) {
     hipStream_t s = ctx->stream;
     const bool stop = (p.flags & BSIM_STOP_AT_FIXPOINT) != 0;
     const bool untyped = (p.flags & BSIM_UNTYPED) != 0;
@@ -98,9 +98,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     // and its launches are large: start with shorter chunks
     uint32_t chunk = rb.bc.gid ? 2u : 4u;
     int pending = -1;
-    hipEvent_t ev[2];
-    hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
-    hip_check(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming), "event");
+    hipEvent_t* ev = ctx->loop_ev;  // created with the ctx
     bool done = false;
     bool prev_taken = false;
     std::vector<hipEvent_t> timers;  // (start, after refinement, after hubs) per timed launch
@@ -137,7 +135,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                         rb.h[kk & 1] = sink->levels[std::min(kk, top)];
                     }
                     hipEvent_t et[3] = {nullptr, nullptr, nullptr};
-                    const bool timed = ctx->time_launches && kk % ctx->time_launches == 0;
+                    const bool timed = use_timers && ctx->time_launches && kk % ctx->time_launches == 0;
                     if (timed) {
                         timed_k.push_back(kk);
                         for (hipEvent_t& e : et) {
@@ -180,13 +178,9 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
         }
     } catch (...) {
         (void)hipStreamSynchronize(s);
-        (void)hipEventDestroy(ev[0]);
-        (void)hipEventDestroy(ev[1]);
         throw;
     }
     hip_check(hipStreamSynchronize(s), "loop sync");
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
     RunStatus st;
     hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
     // launch j (1-based) did work iff j <= k_done + 1: launch k_done + 2 finds

@@ -4,10 +4,15 @@
     python -m paper_2111_12493_amd.profiling trace  <kernel_trace.csv> <k_done>
     python -m paper_2111_12493_amd.profiling counters <counter_collection.csv> [calib_bytes [k_done]]
     python -m paper_2111_12493_amd.profiling summary <dir> <workload> <k_done> <algorithmic_bytes> <calib_bytes> <out_dir>
-    python -m paper_2111_12493_amd.profiling report <workload> <k_done> <algorithmic_bytes>
-        <kernel_trace.csv> <fetch_counters.csv> <write_counters.csv> <calib_bytes> <out.json>
+    python -m paper_2111_12493_amd.profiling probes <workload> <out_dir>
     python -m paper_2111_12493_amd.profiling updates <incremental|plain> <batches>
     python -m paper_2111_12493_amd.profiling summary-updates <dir> <batches> <out_dir>
+
+`summary` reads the kernel-trace run and the four counter passes that
+commands() lists and writes profiles/k_iterate_<workload>.md and its
+_counters.json (the traffic bench.py reports); `probes` times a STREAM-style
+copy and the gather pattern of the refinement (bsim_probe_copy,
+bsim_probe_gather) and writes profiles/probes_<workload>.md.
 
 `updates` runs the update workload (the resident rmat24 state, k = 4, the
 bench's seeded batches of 10^3-10^6 operations) in one form, for a profiler
@@ -82,7 +87,7 @@ def working_launch_durations(path: str, k_done: int):
             seen.clear()
             continue
         seen[k] += 1
-        if k in ("k_iterate", "k_hub") and seen[k] <= k_done + 1:
+        if k in ("k_iterate", "k_hub", "k_hub_finish") and seen[k] <= k_done + 1:
             out[k].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     return out
 
@@ -132,88 +137,215 @@ def counters(path: str, calib_bytes: int = 0, k_done: int = 0):
     return out, scale
 
 
-def report(workload: str, k_done: int, algo_bytes: int, trace_csv: str, fetch_csv: str,
-           write_csv: str, calib_bytes: int, out_json: str) -> dict:
-    """Traffic of the refinement kernel per working launch, for bench.py."""
-    dur = working_launch_durations(trace_csv, k_done)
-    f, fs = counters(fetch_csv, calib_bytes, k_done)
-    w, ws = counters(write_csv, calib_bytes, k_done)
-    res = {"workload": workload, "kernel": "k_iterate", "kernel_sources_sha256_16": kernel_fingerprint(),
-           "working_launches": len(dur["k_iterate"]),
-           "avg_us": sum(dur["k_iterate"]) / len(dur["k_iterate"]) / 1e3,
-           "hub_avg_us": sum(dur["k_hub"]) / max(len(dur["k_hub"]), 1) / 1e3,
-           "fetch_bytes_per_launch": f["k_iterate"]["fetch_size_bytes_per_dispatch"],
-           "write_bytes_per_launch": w["k_iterate"]["write_size_bytes_per_dispatch"],
-           "fetch_scale_bytes_per_unit": fs["FETCH_SIZE"], "write_scale_bytes_per_unit": ws["WRITE_SIZE"],
-           "raw_fetch_size_per_launch": f["k_iterate"]["avg"]["FETCH_SIZE"],
-           "raw_write_size_per_launch": w["k_iterate"]["avg"]["WRITE_SIZE"],
-           "algorithmic_bytes_per_launch": algo_bytes}
-    res["bytes_per_launch"] = res["fetch_bytes_per_launch"] + res["write_bytes_per_launch"]
-    with open(out_json, "w") as fh:
-        json.dump(res, fh, indent=1)
-    return res
+ITER_KERNELS = ("k_iterate", "k_hub", "k_hub_finish")
+
+# Counter passes (rocprofv3 collects no more than 4 TCC counters at once).
+#   fetch: bytes read past L2 = 128 TCC_BUBBLE + 64 (TCC_EA0_RDREQ - TCC_BUBBLE
+#          - TCC_EA0_RDREQ_32B) + 32 TCC_EA0_RDREQ_32B (rocprofv3's FETCH_SIZE
+#          for gfx950), and TCC_EA0_RDREQ_DRAM (requests that went to DRAM)
+#   l2:    TCC_HIT / TCC_MISS (the L2 hit rate of the gathers) and the write
+#          requests of WRITE_SIZE: 32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B) + 64 TCC_EA0_WRREQ_64B
+PASSES = {
+    "fetch": "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum TCC_EA0_RDREQ_DRAM_sum",
+    "l2": "TCC_HIT_sum TCC_MISS_sum TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum",
+    "sq1": "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_INSTS_VALU SQ_INSTS_LDS "
+           "SQ_LDS_BANK_CONFLICT",
+    "sq2": "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM "
+           "SQ_INST_CYCLES_VMEM_RD GRBM_GUI_ACTIVE",
+}
+BENCH_ARGS = "--no-cpu-baseline --no-chaining --no-incremental --no-batched --no-serving --no-directions"
 
 
-COMMANDS = """    rocprofv3 --kernel-trace --stats -d {d}/stats -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 2 --warmup 1
-    rocprofv3 --pmc FETCH_SIZE -d {d}/fetch -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0 --calibrate-copy 1024
-    rocprofv3 --pmc WRITE_SIZE -d {d}/write -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0 --calibrate-copy 1024
-    rocprofv3 --pmc SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_INSTS_VALU \\
-        SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT -d {d}/sq1 -o run --output-format csv -- \\
-        python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0
-    rocprofv3 --pmc SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS \\
-        SQ_ACTIVE_INST_VMEM SQ_INST_CYCLES_VMEM_RD GRBM_GUI_ACTIVE TCC_HIT -d {d}/sq2 -o run \\
-        --output-format csv -- python -u bench.py --no-cpu-baseline --no-incremental --no-batched --no-serving --no-directions --steps 1 --warmup 0
-"""
+def commands(d: str, workload: str) -> str:
+    b = "python -u bench.py --workload %s %s" % (workload, BENCH_ARGS)
+    lines = ["    rocprofv3 --kernel-trace --stats -d %s/stats -o run --output-format csv -- \\" % d,
+             "        %s --steps 2 --warmup 1" % b]
+    for name, ctrs in PASSES.items():
+        calib = " --calibrate-copy 1024" if name in ("fetch", "l2") else ""
+        lines += ["    timeout -s KILL 300 rocprofv3 --pmc %s -d %s/%s -o run --output-format csv -- \\" % (ctrs, d, name),
+                  "        %s --steps 1 --warmup 0%s" % (b, calib)]
+    return "\n".join(lines)
+
+
+def fetch_bytes(avg: dict) -> float:
+    bub, rd, r32 = avg.get("TCC_BUBBLE_sum", 0.0), avg.get("TCC_EA0_RDREQ_sum", 0.0), avg.get("TCC_EA0_RDREQ_32B_sum", 0.0)
+    return 128 * bub + 64 * (rd - bub - r32) + 32 * r32
+
+
+def write_bytes(avg: dict) -> float:
+    wr, w64 = avg.get("TCC_EA0_WRREQ_sum", 0.0), avg.get("TCC_EA0_WRREQ_64B_sum", 0.0)
+    return 32 * (wr - w64) + 64 * w64
+
+
+def pass_counters(path: str, k_done: int):
+    """Per kernel (working launches of the refinement loop only), the average
+    of every counter per dispatch, and the counters of the largest foreign
+    dispatch (the calibration copy)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    meta = {}
+    for r in csv.DictReader(open(path)):
+        key = r["Dispatch_Id"]
+        per[key][r["Counter_Name"]] += float(r["Counter_Value"])
+        meta[key] = (int(r["Start_Timestamp"]), r["Kernel_Name"])
+    by_kernel = collections.defaultdict(list)
+    seen = collections.Counter()
+    foreign = []
+    for key in sorted(per, key=lambda k: meta[k][0]):
+        k = short(meta[key][1])
+        if k not in OWN and k not in ITER_KERNELS and not k.startswith("k_"):
+            foreign.append(per[key])
+            continue
+        if k == "k_init":
+            seen.clear()
+        seen[k] += 1
+        if k in ITER_KERNELS and seen[k] > k_done + 1:
+            continue
+        by_kernel[k].append(per[key])
+    avg = {k: {c: sum(d.get(c, 0.0) for d in v) / len(v) for c in v[0]} for k, v in by_kernel.items()}
+    return avg, foreign
 
 
 def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: int, out_dir: str) -> str:
     """Write <out_dir>/k_iterate_<workload>.md and _counters.json from the
-    five rocprofv3 runs under directory d (see COMMANDS)."""
+    rocprofv3 runs under directory d (see commands())."""
     j = os.path.join
-    rep = report(workload, k_done, algo_bytes, j(d, "stats", "run_kernel_trace.csv"),
-                 j(d, "fetch", "run_counter_collection.csv"), j(d, "write", "run_counter_collection.csv"),
-                 calib_bytes, j(out_dir, "k_iterate_%s_counters.json" % workload))
+    dur = working_launch_durations(j(d, "stats", "run_kernel_trace.csv"), k_done)
+    iter_us = sum(sum(dur[k]) / len(dur[k]) for k in ITER_KERNELS if dur.get(k)) / 1e3
+    fa, ff = pass_counters(j(d, "fetch", "run_counter_collection.csv"), k_done)
+    la, lf = pass_counters(j(d, "l2", "run_counter_collection.csv"), k_done)
+    copy_read = max(fetch_bytes(c) for c in ff) if ff else 0.0
+    copy_write = max(write_bytes(c) for c in lf) if lf else 0.0
+    rs = calib_bytes / copy_read if copy_read else 1.0   # true bytes per counted byte
+    ws = calib_bytes / copy_write if copy_write else 1.0
+    fetch = sum(fetch_bytes(fa.get(k, {})) for k in ITER_KERNELS)
+    write = sum(write_bytes(la.get(k, {})) for k in ITER_KERNELS)
+    ki_f, ki_l = fa.get("k_iterate", {}), la.get("k_iterate", {})
+    hit, miss = ki_l.get("TCC_HIT_sum", 0.0), ki_l.get("TCC_MISS_sum", 0.0)
+    rep = {"workload": workload, "kernels": list(ITER_KERNELS), "kernel_sources_sha256_16": kernel_fingerprint(),
+           "working_launches": len(dur.get("k_iterate", [])), "iteration_avg_us": iter_us,
+           "avg_us": {k: sum(dur[k]) / len(dur[k]) / 1e3 for k in ITER_KERNELS if dur.get(k)},
+           "counted_fetch_bytes_per_iteration": fetch, "counted_write_bytes_per_iteration": write,
+           "copy_read_scale": rs, "copy_write_scale": ws,
+           "fetch_bytes_per_launch": fetch * rs, "write_bytes_per_launch": write * ws,
+           "k_iterate_l2_hit_rate": hit / (hit + miss) if hit + miss else None,
+           "k_iterate_dram_read_share": (ki_f.get("TCC_EA0_RDREQ_DRAM_sum", 0.0) / ki_f["TCC_EA0_RDREQ_sum"]
+                                         if ki_f.get("TCC_EA0_RDREQ_sum") else None),
+           "algorithmic_bytes_per_launch": algo_bytes}
+    rep["bytes_per_launch"] = rep["fetch_bytes_per_launch"] + rep["write_bytes_per_launch"]
+    with open(j(out_dir, "k_iterate_%s_counters.json" % workload), "w") as fh:
+        json.dump(rep, fh, indent=1)
     sq = []
     derived = {}
     for pas in ("sq1", "sq2"):
-        res, _ = counters(j(d, pas, "run_counter_collection.csv"), 0, k_done)
-        for k in ("k_iterate", "k_hub"):
+        res, _ = pass_counters(j(d, pas, "run_counter_collection.csv"), k_done)
+        for k in ITER_KERNELS:
             if k in res:
-                avg = res[k]["avg"]
-                derived.setdefault(k, {}).update(avg)
-                sq.append("%s %s" % (k, " ".join("%s=%.4g" % kv for kv in sorted(avg.items()))))
-    lines = ["# k_iterate / k_hub on %s (%d iterations)" % (workload, k_done), "",
+                derived.setdefault(k, {}).update(res[k])
+                sq.append("%s %s" % (k, " ".join("%s=%.4g" % kv for kv in sorted(res[k].items()))))
+    tcc = []
+    for k in ITER_KERNELS:
+        for name, src in (("fetch", fa), ("l2", la)):
+            if k in src:
+                tcc.append("%s %s" % (k, " ".join("%s=%.4g" % kv for kv in sorted(src[k].items()))))
+    lines = ["# One refinement iteration (k_iterate, k_hub, k_hub_finish) on %s (%d iterations per run)"
+             % (workload, k_done), "",
              "Kernel source fingerprint (%s): %s" % (", ".join(KERNEL_SOURCES), rep["kernel_sources_sha256_16"]), "",
-             "## Commands (repository root, one MI355X)", "", COMMANDS.format(d=d), "Summaries:", "",
+             "## Commands (repository root, one MI355X)", "", commands(d, workload), "", "Summaries:", "",
              "    python -m paper_2111_12493_amd.profiling summary %s %s %d %d %d profiles"
              % (d, workload, k_done, algo_bytes, calib_bytes), "",
              "## Kernel stats (every dispatch of the profiled runs)", "", "```",
              stats(j(d, "stats", "run_kernel_stats.csv")), "```", "",
              "Launches past the stop test of a run return at once; over the working launches "
              "(1..k_done+1 of every run):", "", "```", trace(j(d, "stats", "run_kernel_trace.csv"), k_done), "```", "",
-             "## HBM traffic per working k_iterate launch", "",
-             "Calibration kernel (torch bitwise_not over %d bytes: reads and writes that many): one FETCH_SIZE "
-             "unit = %.1f bytes, one WRITE_SIZE unit = %.1f bytes." % (calib_bytes, rep["fetch_scale_bytes_per_unit"],
-                                                                       rep["write_scale_bytes_per_unit"]), "",
-             "| | raw units | bytes |", "|---|---:|---:|",
-             "| FETCH_SIZE | %.0f | %.1f MB |" % (rep["raw_fetch_size_per_launch"], rep["fetch_bytes_per_launch"] / 1e6),
-             "| WRITE_SIZE | %.0f | %.1f MB |" % (rep["raw_write_size_per_launch"], rep["write_bytes_per_launch"] / 1e6),
-             "| total | | %.1f MB |" % (rep["bytes_per_launch"] / 1e6),
+             "One iteration = %.1f us; algorithmic bytes %.1f MB -> %.0f GB/s = %.1f %% of 8 TB/s."
+             % (iter_us, algo_bytes / 1e6, algo_bytes / iter_us / 1e3, algo_bytes / iter_us / 1e3 / 80), "",
+             "## Bytes past L2 per working iteration", "",
+             "Read bytes = 128 TCC_BUBBLE + 64 (TCC_EA0_RDREQ - TCC_BUBBLE - TCC_EA0_RDREQ_32B) + 32 TCC_EA0_RDREQ_32B "
+             "(rocprofv3's FETCH_SIZE for gfx950), write bytes = 32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B) + "
+             "64 TCC_EA0_WRREQ_64B.  The calibration copy (torch bitwise_not over %d bytes, reads and writes that "
+             "many) counted %.0f read and %.0f written bytes: true/counted = %.3f (read), %.3f (write)."
+             % (calib_bytes, copy_read, copy_write, rs, ws), "",
+             "| | counted | scaled by the copy |", "|---|---:|---:|",
+             "| read | %.1f MB | %.1f MB |" % (fetch / 1e6, rep["fetch_bytes_per_launch"] / 1e6),
+             "| written | %.1f MB | %.1f MB |" % (write / 1e6, rep["write_bytes_per_launch"] / 1e6),
+             "| total | %.1f MB | %.1f MB |" % ((fetch + write) / 1e6, rep["bytes_per_launch"] / 1e6),
              "| algorithmic | | %.1f MB |" % (algo_bytes / 1e6), "",
-             "Measured / algorithmic = %.2f." % (rep["bytes_per_launch"] / algo_bytes), "",
-             "## Issue counters per working launch", "", "```"] + sq + ["```", ""]
+             "Scaled traffic / algorithmic = %.2f." % (rep["bytes_per_launch"] / algo_bytes), ""]
+    if rep["k_iterate_l2_hit_rate"] is not None:
+        lines.append("k_iterate: L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS) = %.1f %%." % (100 * rep["k_iterate_l2_hit_rate"]))
+    if rep["k_iterate_dram_read_share"] is not None:
+        lines.append("k_iterate: TCC_EA0_RDREQ_DRAM / TCC_EA0_RDREQ = %.1f %% of the read requests past L2 went to "
+                     "DRAM; the rest were served by the memory-side cache." % (100 * rep["k_iterate_dram_read_share"]))
+    lines += ["", "## Counters per working launch", "", "```"] + tcc + sq + ["```", ""]
     k = derived.get("k_iterate", {})
     if k.get("GRBM_GUI_ACTIVE") and k.get("SQ_ACTIVE_INST_VALU"):
         busy = k["SQ_ACTIVE_INST_VALU"] * 4 / 1024 / (k["GRBM_GUI_ACTIVE"] / 8)
         wait = k.get("SQ_WAIT_ANY", 0) / max(k.get("SQ_WAVE_CYCLES", 1), 1)
         lines.append("k_iterate: VALU busy = SQ_ACTIVE_INST_VALU x 4 / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8 XCDs) "
                      "= %.0f %%; SQ_WAIT_ANY / SQ_WAVE_CYCLES = %.0f %%." % (100 * busy, 100 * wait))
+    if k.get("SQ_INSTS_LDS"):
+        lines.append("k_iterate: SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS = %.2f cycles per LDS instruction."
+                     % (k.get("SQ_LDS_BANK_CONFLICT", 0) / k["SQ_INSTS_LDS"]))
     path = j(out_dir, "k_iterate_%s.md" % workload)
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    return path
+
+
+def run_probes(workload: str, out_dir: str) -> str:
+    """The memory-pattern ceilings of the refinement on a workload: a
+    STREAM-style copy, and the gather probe (stream the targets, gather one
+    8-byte value per edge) over the graph's targets as generated, with the
+    vertices renumbered by descending in-degree, and with random ids."""
+    import torch
+
+    from . import binding
+    from . import graphgen as gg
+
+    torch.cuda.set_device(0)
+    ctx = binding.Context(0)
+    lines = ["# Memory-pattern ceilings on %s" % workload, "",
+             "Command (repository root, one MI355X):", "",
+             "    python -u -m paper_2111_12493_amd.profiling probes %s %s" % (workload, out_dir), ""]
+    gib = 4 << 30
+    ms = binding.probe_copy(ctx, gib, reps=10)
+    copy_gbs = 2 * gib / ms / 1e6
+    lines += ["STREAM-style copy of %d GiB (read + write): %.3f ms -> %.0f GB/s (%.1f %% of 8 TB/s)."
+              % (gib >> 30, ms, copy_gbs, copy_gbs / 80), ""]
+    g = gg.make_config(workload)
+    dg = binding.DeviceGraph(g)
+    n, m = g.n, g.m
+    del g
+    h = torch.zeros(max(n, 1), dtype=torch.int64, device="cuda")
+    tgt0 = dg.tgt.clone()
+    lines += ["Gather probe over the %d targets of %s (n = %d), gathering from an %d-entry 8-byte array; "
+              "algorithmic bytes = 12 per edge (4 B target + 8 B gathered value):" % (m, workload, n, n), "",
+              "| vertex ids | ms per pass | GB/s | %% of 8 TB/s |", "|---|---:|---:|---:|"]
+    indeg = torch.bincount(tgt0.to(torch.int64), minlength=n)
+    rank = torch.empty(n, dtype=torch.int64, device="cuda")
+    rank[torch.argsort(indeg, descending=True, stable=True)] = torch.arange(n, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    variants = (("as generated", tgt0),
+                ("renumbered by in-degree", rank[tgt0.to(torch.int64)].to(torch.int32)),
+                ("random permutation", torch.randperm(n, generator=gen, device="cuda")[tgt0.to(torch.int64)]
+                 .to(torch.int32)),
+                ("sequential (e mod n)", (torch.arange(m, device="cuda") % n).to(torch.int32)))
+    res = {}
+    for name, t in variants:
+        dg.tgt = t.contiguous()
+        ms = binding.probe_gather(ctx, dg, h, reps=10)
+        gbs = 12 * m / ms / 1e6
+        res[name] = ms
+        lines.append("| %s | %.3f | %.0f | %.1f |" % (name, ms, gbs, gbs / 80))
+    dg.tgt = tgt0
+    lines.append("")
+    ctx.close()
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "probes_%s.md" % workload)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
     return path
 
 
@@ -358,11 +490,11 @@ def main(argv):
     if argv[1] == "summary":
         print(summary(argv[2], argv[3], int(argv[4]), int(argv[5]), int(argv[6]), argv[7]))
         return
+    if argv[1] == "probes":
+        run_probes(argv[2], argv[3])
+        return
     if argv[1] == "stats":
         print(stats(argv[2]))
-    elif argv[1] == "report":
-        print(json.dumps(report(argv[2], int(argv[3]), int(argv[4]), argv[5], argv[6], argv[7],
-                                int(argv[8]), argv[9]), indent=1))
     elif argv[1] == "trace":
         print(trace(argv[2], int(argv[3])))
     else:

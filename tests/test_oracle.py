@@ -320,3 +320,15 @@ def test_dead_vertex_edge_is_rejected():
     g = gg.from_edges(3, [0], [1], [0], alive=np.array([1, 0, 1], dtype=np.uint8))
     with pytest.raises(ValueError):
         orc.summarize(g, 2)
+
+
+def test_timing_sample_helpers_match_full_runs():
+    # the benchmark's CPU-baseline sample runs the same per-vertex step
+    g = gg.make_config("uniform_10k_50k")
+    t = orc.type_hashes(g)
+    h0, _ = orc.iterate(g, 0)
+    h1, _ = orc.iterate(g, 1)
+    h2, _ = orc.iterate(g, 2)
+    assert np.array_equal(t, h0)
+    assert np.array_equal(orc.step_strided(g, t, t, 3, 16, (g.n - 3 + 15) // 16), h1[3::16])
+    assert np.array_equal(orc.step_strided(g, t, h1, 0, 7, (g.n + 6) // 7), h2[0::7])
