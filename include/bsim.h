@@ -227,6 +227,49 @@ const char* bsim_option_names(void);
 int bsim_summarize(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* params,
                    bsim_state** state_out, bsim_result** out);
 
+/* ---- summarization without device allocation ---------------------------- */
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * batch summarization as bsim_summarize (same kernels, bit-identical
+ * results), but it calls no device allocator (no hipMalloc, hipMallocAsync,
+ * hipFree, no allocating library routine): every temporary array lives in
+ * one static device array of bsim_noalloc_scratch_bytes() bytes (256 MiB)
+ * that each device holds for the life of the process, and the results go to
+ * arrays the caller owns.
+ *   graph   device-resident (mem_kind BSIM_MEM_DEVICE), else BSIM_E_INVALID
+ *   params  flags BSIM_STOP_AT_FIXPOINT, BSIM_UNTYPED, BSIM_NO_SUMMARY_EDGES
+ *           only (others: BSIM_E_UNSUPPORTED)
+ *   out     caller-owned; in: the arrays, out: the scalars
+ * Limit: a graph whose temporaries exceed the scratch (about 72 n + 56 m
+ * bytes plus two class tables of next_pow2(1.5 n + 1) 8-byte slots and
+ * 16 MiB) gives BSIM_E_UNSUPPORTED; the caller's arrays are then untouched.
+ * All calls on one device share its scratch, so calls that overlap in time
+ * on one device (other host threads or streams) race and must not be made;
+ * nothing of a call's scratch carries over to the next.
+ */
+typedef struct {
+    uint64_t* hashes;              /* device [n_vertices]: h^{k_done}, 0 for dead vertices */
+    uint32_t* block_ids;           /* device [n_vertices] */
+    uint32_t* block_sizes;         /* device [n_vertices]: first n_blocks entries written */
+    uint32_t* se_src;              /* device [n_edges] each (first n_summary_edges written), */
+    uint32_t* se_label;            /*   or unused with BSIM_NO_SUMMARY_EDGES */
+    uint32_t* se_dst;
+    uint32_t* blocks_per_iter;     /* host [blocks_per_iter_cap] */
+    uint32_t blocks_per_iter_cap;  /* >= min(k_max, n_vertices + 1) + 1 with the fixpoint test,
+                                      else >= k_max + 1 */
+    uint32_t k_done;               /* outputs, as in bsim_result */
+    uint32_t fixpoint;
+    uint32_t n_blocks;
+    uint64_t n_summary_edges;
+    uint64_t scratch_used;         /* bytes of scratch the call used */
+} bsim_noalloc_out;
+
+uint64_t bsim_noalloc_scratch_bytes(void);
+int bsim_summarize_noalloc(bsim_ctx* ctx, const bsim_graph* graph, const bsim_params* params,
+                           bsim_noalloc_out* out);
+
 /*
  * Summarize under the label parameterization (Sec. 2.4): only the edges whose
  * label is in labels[0..n_labels) count, for the signatures and for the

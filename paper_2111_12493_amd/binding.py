@@ -70,6 +70,12 @@ class BsimServerStats(ctypes.Structure):
                 ("busy_ms", ctypes.c_double)]
 
 
+class BsimNoallocOut(ctypes.Structure):
+    _fields_ = [("hashes", _p), ("block_ids", _p), ("block_sizes", _p), ("se_src", _p), ("se_label", _p),
+                ("se_dst", _p), ("blocks_per_iter", _p), ("blocks_per_iter_cap", _u32), ("k_done", _u32),
+                ("fixpoint", _u32), ("n_blocks", _u32), ("n_summary_edges", _u64), ("scratch_used", _u64)]
+
+
 REQ_SUMMARIZE, REQ_UPDATE = 1, 2
 
 EXPORTS = {
@@ -109,6 +115,9 @@ EXPORTS = {
     "bsim_server_free": (None, [_p]),
     "bsim_probe_gather": (ctypes.c_int, [_p, _p, _u64, _p, _u32, _u32, ctypes.POINTER(ctypes.c_float)]),
     "bsim_probe_copy": (ctypes.c_int, [_p, _u64, _u32, ctypes.POINTER(ctypes.c_float)]),
+    "bsim_noalloc_scratch_bytes": (_u64, []),
+    "bsim_summarize_noalloc": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), ctypes.POINTER(BsimParams),
+                                              ctypes.POINTER(BsimNoallocOut)]),
     "bsim_batch_summarize": (ctypes.c_int, [_p, ctypes.POINTER(BsimGraph), _u32,
                                             ctypes.POINTER(BsimParams),
                                             ctypes.POINTER(ctypes.POINTER(BsimResult))]),
@@ -335,6 +344,45 @@ def summarize(ctx: Context, graph, k_max: int = K_UNBOUNDED, stop_at_fixpoint: b
                                               ids.ctypes.data_as(_p) if ids.size else None, ids.size,
                                               ctypes.byref(out)))
     return Result(out)
+
+
+def summarize_noalloc(ctx: Context, graph: "DeviceGraph", k_max: int = K_UNBOUNDED, stop_at_fixpoint: bool = True,
+                      untyped: bool = False, summary_edges: bool = True) -> dict:
+    """bsim_summarize_noalloc on a DeviceGraph: the outputs are torch device
+    tensors allocated here (the call itself allocates no device memory);
+    returns the result as a dict like Result.to_dict, plus scratch_used."""
+    torch = _torch()
+    n, m = graph.n, graph.m
+    dev = graph.tgt.device
+    hashes = torch.zeros(max(n, 1), dtype=torch.int64, device=dev)
+    bids = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+    bsz = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+    se = [torch.zeros(max(m, 1), dtype=torch.int32, device=dev) for _ in range(3)] if summary_edges else None
+    k_bound = min(int(k_max), n + 1) if stop_at_fixpoint else int(k_max)
+    bpi = np.zeros(k_bound + 1, dtype=np.uint32)
+    o = BsimNoallocOut()
+    o.hashes, o.block_ids, o.block_sizes = hashes.data_ptr(), bids.data_ptr(), bsz.data_ptr()
+    if se is not None:
+        o.se_src, o.se_label, o.se_dst = (t.data_ptr() for t in se)
+    o.blocks_per_iter = bpi.ctypes.data
+    o.blocks_per_iter_cap = bpi.size
+    flags = (STOP_AT_FIXPOINT if stop_at_fixpoint else 0) | (UNTYPED if untyped else 0) | \
+            (0 if summary_edges else NO_SUMMARY_EDGES)
+    gs = graph.struct()
+    params = BsimParams(int(k_max), flags)
+    ctx.check(lib().bsim_summarize_noalloc(ctx.handle, ctypes.byref(gs), ctypes.byref(params), ctypes.byref(o)))
+    nb, ns = int(o.n_blocks), int(o.n_summary_edges)
+
+    def host(t, count, dt):
+        return t[:count].cpu().numpy().view(dt) if count else np.zeros(0, dtype=dt)
+
+    d = dict(k_done=int(o.k_done), fixpoint=int(o.fixpoint), n_blocks=nb,
+             blocks_per_iter=bpi[:int(o.k_done) + 1].copy(), hashes=host(hashes, n, np.uint64),
+             block_ids=host(bids, n, np.uint32), block_sizes=host(bsz, nb, np.uint32),
+             scratch_used=int(o.scratch_used))
+    if se is not None:
+        d["se_src"], d["se_label"], d["se_dst"] = (host(t, ns, np.uint32) for t in se)
+    return d
 
 
 def probe_gather(ctx: Context, graph: "DeviceGraph", h, reps: int = 10) -> float:

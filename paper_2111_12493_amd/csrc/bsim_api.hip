@@ -48,6 +48,12 @@ int bsim_ctx_create(int device, void* hip_stream, bsim_ctx** out) {
             return BSIM_E_DEVICE;
         }
     }
+    // the allocation-free entry point's scratch on this device (once per device)
+    const int rc = noalloc_scratch_init(device, &c->err);
+    if (rc != BSIM_OK) {
+        bsim_ctx_free(c);
+        return rc;
+    }
     // keep freed stream-ordered memory cached for later calls
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {

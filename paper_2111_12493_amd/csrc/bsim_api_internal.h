@@ -70,9 +70,13 @@ struct LoopResult {
 // receives the class representatives of level k_done - 1 (of level 0 when
 // k_done = 0; at a fixpoint those of level k_done, the same partition).
 // use_timers: bracket launches with HIP events when the ctx option asks for
-// it.
+// it (the allocation-free entry point passes false).
 LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, RunBuffers& rb,
                           LevelSink* sink, Arena& arena, uint32_t* rep_prev = nullptr, bool use_timers = true);
+
+// The allocation-free entry point's scratch: its device address on the
+// current device, looked up once per device (bsim_ctx_create calls it).
+int noalloc_scratch_init(int device, std::string* err);
 
 // finalize with summary edges into the classes named by rep_prev (their
 // first-occurrence block ids) instead of the final blocks.

@@ -207,6 +207,9 @@ class Arena {
         cap_ = base ? cap : 0;
         used_ = 0;
     }
+    // Serve every allocation from the backing memory: one that does not fit
+    // throws BSIM_E_UNSUPPORTED instead of reaching the pool.
+    void set_strict(bool strict) { strict_ = strict; }
     template <typename T>
     T* alloc(size_t count) {
         void* p = nullptr;
@@ -219,6 +222,9 @@ class Arena {
             used_ += bytes;
             return static_cast<T*>(p);
         }
+        if (strict_)
+            throw DeviceError{BSIM_E_UNSUPPORTED, "the temporaries need more than the " + std::to_string(cap_) +
+                                                      " bytes of scratch memory"};
         if (hipMallocAsync(&p, bytes, stream_) != hipSuccess)
             throw DeviceError{BSIM_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
         ptrs_.push_back(p);
@@ -245,6 +251,7 @@ class Arena {
     std::vector<void*> ptrs_;
     char* base_ = nullptr;
     size_t cap_ = 0, used_ = 0, demand_ = 0;
+    bool strict_ = false;
 };
 
 inline void hip_check(hipError_t e, const char* what) {
