@@ -103,74 +103,129 @@ def percentile(v, q):
 
 
 def serving_leg(args, binding, gg, torch, g, dbase):
-    """A burst of fresh summarize requests and update batches for a resident
-    state through the server (4 workers, admission by footprint) against the
-    plain form: the same requests one at a time through one worker."""
+    """Serving under Poisson arrivals: update batches for a resident state
+    (rmat24, k = 4) and fresh summarize requests (R-MAT, degree 8, device
+    resident, to the fixpoint) arrive at equal rates; the arrival rate sweeps
+    25/50/75/90 % of the measured capacity of the plain form.  Chosen form:
+    the server with 4 workers (continuous batching by footprint, overlapping
+    requests) and incremental updates.  Plain form: one worker, first come
+    first served, every update recomputed in full (frontier limit 0).  Both
+    forms see the same arrival sequence at each rate; latency is submit to
+    completion, from the server's own clock."""
     import numpy as np
 
     from paper_2111_12493_amd import devgen
 
     rng = np.random.default_rng(29)
-    fresh = []
-    for i in range(args.serve_requests // 2):
+    pool = []
+    for i in range(args.serve_pool):
         m = int(round(10 ** rng.uniform(4, np.log10(args.serve_max_edges))))
         n = max(2, m // 8)
-        fresh.append(devgen.rmat_device(int(np.ceil(np.log2(n))), m, n_types=128, n_labels=64, n=n,
-                                        seed=int(rng.integers(1, 1 << 30))))
-    dead = np.zeros(g.n + 1_000_000, dtype=bool)
+        pool.append(devgen.rmat_device(int(np.ceil(np.log2(n))), m, n_types=128, n_labels=64, n=n,
+                                       seed=int(rng.integers(1, 1 << 30))))
+    n_upd = max(args.serve_requests, args.serve_calib)  # each run applies a prefix to a fresh state
+    dead = np.zeros(g.n + 4_000_000, dtype=bool)
     n_v = g.n
     scale = int(np.ceil(np.log2(max(g.n, 2))))
     batches = []
-    for i in range(args.serve_requests // 2):
-        d = gg.sample_update_ops(g.row_off, g.tgt, g.lab, n_v, dead, rng, int(round(10 ** rng.uniform(3, 5))),
+    t0 = time.perf_counter()
+    for i in range(n_upd):
+        d = gg.sample_update_ops(g.row_off, g.tgt, g.lab, n_v, dead, rng,
+                                 int(round(10 ** rng.uniform(3, np.log10(args.serve_max_ops)))),
                                  max(g.n_labels, 1), max(g.n_types, 1), rmat_scale=scale)
         n_v = d["n_after"]
         batches.append(binding.UpdateBatch.from_op_arrays(d))
-    hg = fresh
+    print("# serving: %d fresh graphs in the pool, %d update batches sampled in %.1f s"
+          % (len(pool), len(batches), time.perf_counter() - t0), file=sys.stderr, flush=True)
 
-    def run(workers):
-        srv = binding.Server(workers=workers)
-        try:
-            res, state = srv.poll(srv.submit_summarize(dbase, k_max=4, stop_at_fixpoint=False,
-                                                       summary_edges=False, keep_state=True))
-            res.free()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            tickets = []
-            for i in range(max(len(hg), len(batches))):
-                if i < len(hg):
-                    tickets.append(srv.submit_summarize(hg[i], summary_edges=False))
-                if i < len(batches):
-                    tickets.append(srv.submit_update(state, batches[i]))
-            blocks = []
-            for t in tickets:
-                r, _ = srv.poll(t)
-                blocks.append(r.n_blocks)
+    def server(plain):
+        srv = binding.Server(workers=1 if plain else args.serve_workers)
+        if plain:
+            srv.set_option("frontier_limit_pct", 0)
+        res, state = srv.poll(srv.submit_summarize(dbase, k_max=4, stop_at_fixpoint=False, summary_edges=False,
+                                                   keep_state=True))
+        res.free()
+        return srv, state
+
+    # capacity of the plain form: mean service time over a calibration mix,
+    # one request at a time (the first update batches, on a state of its own)
+    srv, state = server(plain=True)
+    svc = {"summarize": [], "update": []}
+    try:
+        for i in range(args.serve_calib):
+            for kind in ("summarize", "update"):
+                t = time.perf_counter()
+                tk = srv.submit_summarize(pool[i % len(pool)], summary_edges=False) if kind == "summarize" \
+                    else srv.submit_update(state, batches[i])
+                r, _ = srv.poll(tk)
                 r.free()
-            wall = time.perf_counter() - t0
-            st = srv.stats()
-            srv.release_state(state)
-        finally:
-            srv.free()
-        return blocks, wall, st
+                svc[kind].append(time.perf_counter() - t)
+        srv.release_state(state)
+    finally:
+        srv.free()
+    mean_svc = (np.mean(svc["summarize"]) + np.mean(svc["update"])) / 2
+    capacity = 1.0 / mean_svc
+    print("# serving: plain service %.1f ms (summaries) / %.1f ms (updates) -> capacity %.1f requests/s"
+          % (1e3 * np.mean(svc["summarize"]), 1e3 * np.mean(svc["update"]), capacity), file=sys.stderr, flush=True)
 
-    b_mix, w_mix, s_mix = run(4)
-    b_one, w_one, s_one = run(1)
-    if b_mix != b_one:
-        raise RuntimeError("serving results differ between the mix and one-at-a-time runs")
-    req = len(b_mix)
-    return {"workload": "%s resident (k=4) + %d fresh R-MAT summaries (10^4-%.0e edges, device-resident, to "
-                        "fixpoint) + %d update batches (10^3-10^5 ops), submitted as one burst"
-                        % (args.inc_workload, len(hg), args.serve_max_edges, len(batches)),
-            "fresh_edges": int(sum(x.m for x in fresh)),
-            "requests": req, "workers": 4,
-            "p50_ms": s_mix["p50_ms"][0], "p99_ms": s_mix["p99_ms"][0],
-            "update_p50_ms": s_mix["p50_ms"][2], "update_p99_ms": s_mix["p99_ms"][2],
-            "summarize_p50_ms": s_mix["p50_ms"][1], "summarize_p99_ms": s_mix["p99_ms"][1],
-            "requests_per_s": req / w_mix,
-            "plain_p50_ms": s_one["p50_ms"][0], "plain_p99_ms": s_one["p99_ms"][0],
-            "plain_requests_per_s": req / w_one,
-            "plain_form": "same requests, one worker, one at a time (FIFO, no overlap)"}
+    points = []
+    for frac in args.serve_loads:
+        lam = frac * capacity
+        arng = np.random.default_rng(int(1000 * frac))
+        gaps = arng.exponential(1.0 / lam, size=args.serve_requests)
+        kinds = arng.random(args.serve_requests) < 0.5  # True: update
+        point = {"load": frac, "rate_per_s": lam, "requests": args.serve_requests}
+        blocks = {}
+        for form in ("chosen", "plain"):
+            srv, state = server(plain=form == "plain")
+            try:
+                tickets = []
+                ui = si = 0
+                torch.cuda.synchronize()
+                start = time.perf_counter()
+                due = start
+                for gap, upd in zip(gaps, kinds):
+                    due += gap
+                    wait = due - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    if upd:
+                        tickets.append(("u", srv.submit_update(state, batches[ui])))
+                        ui += 1
+                    else:
+                        tickets.append(("s", srv.submit_summarize(pool[si % len(pool)], summary_edges=False)))
+                        si += 1
+                nb = []
+                for kind, tk in tickets:
+                    r, _ = srv.poll(tk)
+                    nb.append(r.n_blocks)
+                    r.free()
+                st = srv.stats()
+                srv.release_state(state)
+            finally:
+                srv.free()
+            blocks[form] = nb
+            point[form] = {"p50_ms": st["p50_ms"][0], "p99_ms": st["p99_ms"][0],
+                           "summarize_p50_ms": st["p50_ms"][1], "summarize_p99_ms": st["p99_ms"][1],
+                           "update_p50_ms": st["p50_ms"][2], "update_p99_ms": st["p99_ms"][2],
+                           "requests_per_s": len(tickets) / (st["busy_ms"] / 1e3) if st["busy_ms"] else None}
+            print("# serving load %.2f (%.1f req/s) %s: p50 %.1f ms p99 %.1f ms (updates %.1f / %.1f, summaries "
+                  "%.1f / %.1f), %.1f req/s" % (frac, lam, form, point[form]["p50_ms"], point[form]["p99_ms"],
+                                                point[form]["update_p50_ms"], point[form]["update_p99_ms"],
+                                                point[form]["summarize_p50_ms"], point[form]["summarize_p99_ms"],
+                                                point[form]["requests_per_s"] or 0), file=sys.stderr, flush=True)
+        if blocks["chosen"] != blocks["plain"]:
+            raise RuntimeError("serving results differ between the two forms at load %.2f" % frac)
+        point["p99_ratio_plain_over_chosen"] = point["plain"]["p99_ms"] / point["chosen"]["p99_ms"]
+        points.append(point)
+    return {"workload": "%s resident (k=4): Poisson arrivals of update batches (log-uniform 10^3-%.0e ops, "
+                        "ADD/MOD/DEL 60/25/15) and fresh R-MAT summaries (log-uniform 10^4-%.0e edges, degree 8, "
+                        "to the fixpoint; %d distinct graphs) at equal rates"
+                        % (args.inc_workload, args.serve_max_ops, args.serve_max_edges, len(pool)),
+            "capacity_requests_per_s": capacity, "plain_service_ms": {k: 1e3 * float(np.mean(v)) for k, v in svc.items()},
+            "chosen_form": "%d workers, continuous batching by footprint, incremental updates" % args.serve_workers,
+            "plain_form": "one worker, first come first served, every update recomputed in full",
+            "points": points}
 
 
 def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoints=True):
@@ -415,7 +470,12 @@ def main() -> int:
                     help="second incremental workload (a uniform graph); empty to skip")
     ap.add_argument("--inc-max-ops", type=float, default=1e6)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9])
+    ap.add_argument("--serve-calib", type=int, default=8, help="calibration requests of each kind")
+    ap.add_argument("--serve-pool", type=int, default=24, help="distinct fresh graphs")
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-max-ops", type=float, default=1e5)
     ap.add_argument("--serve-max-edges", type=float, default=1e7)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-directions", action="store_true")

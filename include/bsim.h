@@ -455,6 +455,11 @@ int bsim_server_submit(bsim_server* srv, const bsim_request* req, uint64_t* tick
  * ticket again, or one never issued, gives BSIM_E_INVALID at once. */
 int bsim_server_poll(bsim_server* srv, uint64_t ticket, int wait, bsim_result** out, bsim_state** state_out);
 int bsim_server_stats_get(bsim_server* srv, bsim_server_stats* out);
+/* Set a context option (bsim_ctx_set_option's names and ranges) on every
+ * context of the server: the workers', the server-owned states' and those
+ * created later.  Only while no request is queued or running
+ * (BSIM_E_BUSY otherwise); errors as bsim_ctx_set_option. */
+int bsim_server_set_option(bsim_server* srv, const char* name, int64_t value);
 /* Free a server-owned state and return its memory to the budget. */
 int bsim_server_release_state(bsim_server* srv, bsim_state* state);
 /* Cancels the requests that have not started, waits for the running ones,

@@ -111,6 +111,7 @@ EXPORTS = {
     "bsim_server_poll": (ctypes.c_int, [_p, _u64, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(BsimResult)),
                                         ctypes.POINTER(_p)]),
     "bsim_server_stats_get": (ctypes.c_int, [_p, ctypes.POINTER(BsimServerStats)]),
+    "bsim_server_set_option": (ctypes.c_int, [_p, ctypes.c_char_p, ctypes.c_int64]),
     "bsim_server_release_state": (ctypes.c_int, [_p, _p]),
     "bsim_server_free": (None, [_p]),
     "bsim_probe_gather": (ctypes.c_int, [_p, _p, _u64, _p, _u32, _u32, ctypes.POINTER(ctypes.c_float)]),
@@ -700,6 +701,9 @@ class Server:
         return dict(submitted=s.submitted, completed=s.completed, failed=s.failed,
                     bytes_in_use=s.bytes_in_use, bytes_budget=s.bytes_budget,
                     p50_ms=list(s.p50_ms), p99_ms=list(s.p99_ms), busy_ms=s.busy_ms)
+
+    def set_option(self, name: str, value: int):
+        _check(lib().bsim_server_set_option(self.handle, name.encode(), int(value)), "server option " + name)
 
     def release_state(self, state):
         _check(lib().bsim_server_release_state(self.handle, state), "release state")

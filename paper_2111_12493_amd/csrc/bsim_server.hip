@@ -111,6 +111,7 @@ struct bsim_server {
     std::vector<double> lat[3];
     Clock::time_point first_submit, last_done;
     bool any_submit = false;
+    std::vector<std::pair<std::string, int64_t>> options;  // applied to every context of the server
 
     void worker(uint32_t w);
     bool pick(Request& out);
@@ -190,6 +191,12 @@ void bsim_server::worker(uint32_t w) {
                     d.status = BSIM_E_DEVICE;
                 } else if ((d.status = bsim_ctx_create(device, os.stream, &os.ctx)) == BSIM_OK) {
                     ctx = os.ctx;
+                    std::vector<std::pair<std::string, int64_t>> opts;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        opts = options;
+                    }
+                    for (const auto& o : opts) (void)bsim_ctx_set_option(ctx, o.first.c_str(), o.second);
                 }
             }
             if (d.status == BSIM_OK)
@@ -374,6 +381,21 @@ int bsim_server_poll(bsim_server* s, uint64_t ticket, int wait, bsim_result** ou
     *out = d.result;
     if (state_out) *state_out = d.state;
     return d.status;
+}
+
+int bsim_server_set_option(bsim_server* s, const char* name, int64_t value) {
+    if (!s || !name) return BSIM_E_INVALID;
+    // validated on a worker context first; contexts are not thread safe, so
+    // only while the server is idle
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->running || !s->queue.empty()) return BSIM_E_BUSY;
+    for (bsim_ctx* c : s->ctxs) {
+        const int rc = bsim_ctx_set_option(c, name, value);
+        if (rc != BSIM_OK) return rc;
+    }
+    for (auto& kv : s->owned) (void)bsim_ctx_set_option(kv.second.ctx, name, value);
+    s->options.emplace_back(name, value);
+    return BSIM_OK;
 }
 
 int bsim_server_stats_get(bsim_server* s, bsim_server_stats* out) {

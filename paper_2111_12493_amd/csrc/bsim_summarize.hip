@@ -94,9 +94,19 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     // launch k tests level k-2, so launch k_max + 2 always sees the cap
     const uint64_t k_last = static_cast<uint64_t>(p.k_max) + 2;
     uint64_t k = 1;
-    // a batched run covers many small graphs that stop within a few levels,
-    // and its launches are large: start with shorter chunks
-    uint32_t chunk = rb.bc.gid ? 2u : 4u;
+    // Launches queued per stop-flag check.  The host waits for the previous
+    // chunk's status while the current one runs, so a chunk only has to
+    // outlast that round trip; every launch queued past the stop is wasted
+    // (an early-exit launch still dispatches its whole grid).  So the chunk
+    // is capped at about 4 ms of estimated work (a refinement launch streams
+    // roughly 40,000 edges per microsecond): one launch at a time for a graph
+    // of 2^30 edges, chunks doubling up to chunk_max for small graphs and
+    // long k-chaining.  A batched run covers many small graphs that stop
+    // within a few levels, and its launches are large: it starts shorter.
+    const double est_us = (static_cast<double>(g.m) + g.n) / 40000.0 + 10.0;
+    const uint32_t chunk_cap =
+        static_cast<uint32_t>(std::max(1.0, std::min<double>(ctx->chunk_max, 4000.0 / est_us)));
+    uint32_t chunk = std::min<uint32_t>(rb.bc.gid ? 2u : 4u, chunk_cap);
     int pending = -1;
     hipEvent_t* ev = ctx->loop_ev;  // created with the ctx
     bool done = false;
@@ -169,7 +179,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                     done = ctx->status_host[pending].done != 0;
                 }
                 pending = slot;
-                chunk = std::min<uint32_t>(chunk * 2, ctx->chunk_max);
+                chunk = std::min<uint32_t>(chunk * 2, chunk_cap);
             } else {
                 hip_check(hipEventSynchronize(ev[pending]), "status wait");
                 done = ctx->status_host[pending].done != 0;
