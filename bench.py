@@ -334,7 +334,10 @@ def directions_leg(binding, torch, ctx, dg, g):
 
 
 def batched_leg(args, binding, gg, torch):
-    """One batched run over many R-MAT graphs against one call per graph."""
+    """One batched run over many R-MAT graphs against one call per graph.
+    The batched call's schedule (small graphs in the persistent launch or
+    not, hub-table size) is the autotuner's, picked during the warm-up call
+    and cached for the size class."""
     from paper_2111_12493_amd import devgen
 
     graphs = devgen.batched_device(args.batch_graphs, args.batch_max_edges, seed=23)
@@ -342,16 +345,26 @@ def batched_leg(args, binding, gg, torch):
     ctx = binding.Context(0)
     edges = sum(g.m for g in graphs)
     print("# batched: %d graphs, %d edges" % (len(graphs), edges), file=sys.stderr, flush=True)
-    rs = binding.batch_summarize(ctx, dgs, summary_edges=True)  # warm-up
+    t = time.perf_counter()
+    rs = binding.batch_summarize(ctx, dgs, summary_edges=True)  # warm-up; the autotuner's first call
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t
     for r in rs:
         r.free()
+    picked = {"small_graph_edges": ctx.get_option("batch_small_edges"),
+              "hub_table_slots": ctx.get_option("batch_hub_table_slots")}
     torch.cuda.synchronize()
     t = time.perf_counter()
     rs = binding.batch_summarize(ctx, dgs, summary_edges=True)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t
     work = sum(r.k_done * g.m for r, g in zip(rs, graphs))
+    # algorithmic bytes of the refinement levels each graph ran, over the
+    # call's refinement phase (device events)
+    algo = sum(r.k_done * iteration_bytes(g.n, g.m, 4) for r, g in zip(rs, graphs))
+    ms_iter = rs[0].ms_iterate
     kmax = max(r.k_done for r in rs)
+    phases = {"stage_ms": rs[0].ms_stage, "iterate_ms": ms_iter, "finalize_ms": rs[0].ms_finalize}
     for r in rs:
         r.free()
     torch.cuda.synchronize()
@@ -361,11 +374,43 @@ def batched_leg(args, binding, gg, torch):
     torch.cuda.synchronize()
     tp = time.perf_counter() - t
     ctx.close()
+    achieved = algo / (ms_iter * 1e-3) / 1e9 if ms_iter else 0.0
+    # the same batch plus small graphs with deep fixpoints (chains of 200
+    # edges): in the union they keep every launch going; the persistent
+    # small-graph launch finishes them in LDS.  Tuned schedule against the
+    # union-only one.
+    chains = [binding.DeviceGraph(gg.chain(200)) for _ in range(args.batch_chains)]
+    deep = {}
+    for name, opt in (("tuned", None), ("union_only", 0)):
+        c = binding.Context(0)
+        if opt is not None:
+            c.set_option("batch_small_edges", opt)
+        for r in binding.batch_summarize(c, dgs + chains, summary_edges=True):  # warm-up (tuning)
+            r.free()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs = binding.batch_summarize(c, dgs + chains, summary_edges=True)
+        torch.cuda.synchronize()
+        deep[name] = {"s": time.perf_counter() - t, "max_k_done": max(r.k_done for r in rs),
+                      "small_graph_edges": c.get_option("batch_small_edges")}
+        for r in rs:
+            r.free()
+        c.close()
+    deep["speedup"] = deep["union_only"]["s"] / deep["tuned"]["s"]
+    print("# batched + %d chains: tuned %.3f s, union only %.3f s" % (args.batch_chains, deep["tuned"]["s"],
+                                                                      deep["union_only"]["s"]),
+          file=sys.stderr, flush=True)
     return {"workload": "%d R-MAT graphs, edges log-uniform 10^2-%.0e, degree U(4,16), 32 types / 32 labels "
                         "(Zipf 1.0), each to its own fixpoint" % (len(graphs), args.batch_max_edges),
             "graphs": len(graphs), "edges": edges, "max_k_done": kmax, "edge_iterations": work,
             "batched_s": tb, "per_graph_s": tp, "value_batched": work / tb, "value_per_graph": work / tp,
-            "speedup": tp / tb}
+            "speedup": tp / tb, "schedule": picked, "autotune_first_call_s": tune_s, "phases": phases,
+            "with_deep_small_graphs": dict(deep, what="the same graphs plus %d chains of 200 edges"
+                                                        % args.batch_chains),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes": algo,
+                         "what": "refinement levels of every graph (its own k_done) over the batched call's "
+                                 "refinement phase"}}
 
 
 WORKLOADS = {
@@ -481,6 +526,7 @@ def main() -> int:
     ap.add_argument("--no-directions", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-max-edges", type=float, default=1e6)
+    ap.add_argument("--batch-chains", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one elementwise copy kernel over this many MiB, so that a "
                          "rocprofv3 counter run can scale FETCH_SIZE/WRITE_SIZE")

@@ -81,7 +81,12 @@ const char* bsim_option_names(void) {
            "time_launches (N, 0..1048576: time every N-th refinement launch with HIP events, 0 = off); "
            "hub_table_slots (LDS slots of a hub-bucket block: power of two, 64..device limit); "
            "frontier_limit_pct (0..100: an update level whose frontier exceeds this share of the vertices is "
-           "recomputed for all vertices; 0 = always, the plain full recomputation)";
+           "recomputed for all vertices; 0 = always, the plain full recomputation); "
+           "autotune (0/1: batched calls pick their schedule per size class by timing the candidates on the "
+           "first call of the class; 1 = default); "
+           "batch_small_edges (N >= 0: a fixed batched schedule, graphs of at most N edges that fit one "
+           "workgroup go to the small-graph launch, 0 = none; turns autotune off); "
+           "batch_hub_table_slots (read only: the hub-table slots of the last batched call)";
 }
 
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
@@ -99,6 +104,21 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
     if (!strcmp(name, "frontier_limit_pct")) {
         if (value < 0 || value > 100) return BSIM_E_RANGE;
         ctx->frontier_limit_pct = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "autotune")) {
+        if (value < 0 || value > 1) return BSIM_E_RANGE;
+        ctx->autotune = static_cast<uint32_t>(value);
+        if (!value) ctx->batch_tune.clear();
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "batch_small_edges")) {
+        // a fixed schedule for the next batched calls (0: no small-graph launch)
+        if (value < 0) return BSIM_E_RANGE;
+        ctx->autotune = 0;
+        ctx->batch_tune.clear();
+        ctx->last_batch.small_edges = static_cast<uint64_t>(value);
+        ctx->fixed_small_edges = static_cast<uint64_t>(value);
         return BSIM_OK;
     }
     if (!strcmp(name, "hub_table_slots")) {
@@ -127,6 +147,19 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     }
     if (!strcmp(name, "frontier_limit_pct")) {
         *value = ctx->frontier_limit_pct;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "autotune")) {
+        *value = ctx->autotune;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "batch_small_edges")) {
+        // the schedule of the last batched call (UINT64_MAX read as -1: every graph that fits)
+        *value = static_cast<int64_t>(ctx->last_batch.small_edges);
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "batch_hub_table_slots")) {
+        *value = ctx->last_batch.hub_table_slots;
         return BSIM_OK;
     }
     return BSIM_E_INVALID;

@@ -1,6 +1,7 @@
 // bsim_api_internal.h -- host-side objects behind the opaque ABI handles.
 #pragma once
 
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -17,6 +18,15 @@ struct bsim_ctx {
     uint32_t time_launches = 0;
     uint32_t hub_table_slots = 8192;  // LDS slots per hub-bucket block on this device
     uint32_t frontier_limit_pct = 2;  // incremental: larger frontiers recompute the level for all vertices
+    // batched calls: schedules picked by the autotuner, per size class
+    uint32_t autotune = 1;
+    struct BatchTune {
+        uint64_t small_edges;       // graphs of at most this many edges go to the small-graph launch
+        uint32_t hub_table_slots;   // LDS slots of a hub-bucket block
+    };
+    std::map<uint64_t, BatchTune> batch_tune;
+    BatchTune last_batch{0, 0};     // what the last batched call ran with
+    uint64_t fixed_small_edges = ~0ull;  // the schedule when autotune is off
 };
 
 namespace bsim {
@@ -92,9 +102,11 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
 bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,
                              const std::vector<uint32_t>* labels);
 
-// Many independent graphs in one refinement run (a disjoint union).
+// Many independent graphs in one refinement run (a disjoint union); graphs
+// of at most small_edges edges (0: none) that fit one workgroup go to the
+// persistent small-graph launch.
 void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t n_graphs, const bsim_params& p,
-                     bsim_result** outs);
+                     bsim_result** outs, uint64_t small_edges);
 
 // Batch path that also returns a resident state for incremental updates.
 int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_params& p,

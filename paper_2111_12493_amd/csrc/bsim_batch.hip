@@ -18,6 +18,7 @@
 // Each per-graph result is a view into the union's arrays, rebased to the
 // graph's own vertex and block ids: identical to summarizing it alone.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "bsim_api_internal.h"
@@ -264,10 +265,29 @@ void build_union(const bsim_graph* graphs, uint32_t G, Staged& u, uint32_t*& gid
     u.alive = alive;
 }
 
+// Capacities of a small-graph workgroup on this device: at most 1,024
+// vertices and 1,535 edges (below the hub degree, so a small graph has no
+// hub) when the device gives a workgroup the LDS for them, else half; and
+// the persistent grid (the workgroups that fit the CUs at once).
+void small_capacity(int device, uint32_t* max_v, uint32_t* max_e, uint32_t* grid) {
+    int lds = 0, cus = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 64;
+    uint32_t v = 1024, e = kHubMinDegree - 1;
+    while (v > 64 && small_graph_lds_bytes(v, e, nullptr) + 1024 > static_cast<uint64_t>(lds)) {
+        v /= 2;
+        e /= 2;
+    }
+    *max_v = v;
+    *max_e = e;
+    const uint64_t per_cu = std::max<uint64_t>(1, (160ull << 10) / (small_graph_lds_bytes(v, e, nullptr) + 1024));
+    *grid = static_cast<uint32_t>(std::max(cus, 1) * per_cu);
+}
+
 }  // namespace
 
 void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const bsim_params& p,
-                     bsim_result** outs) {
+                     bsim_result** outs, uint64_t small_edges) {
     hipStream_t s = ctx->stream;
     if (p.flags & BSIM_PREV_LEVEL_EDGES)
         throw DeviceError{BSIM_E_UNSUPPORTED, "BSIM_PREV_LEVEL_EDGES is supported by single-graph calls only"};
@@ -317,6 +337,39 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const 
     hip_check(hipMemsetAsync(rb.bc.fix, 0, G * 4ull, s), "fix");
     hip_check(hipMemsetAsync(rb.bc.n_done, 0, 4, s), "done count");
     hip_check(hipMemsetAsync(rb.bc.hist, 0, static_cast<size_t>(rb.bc.hist_cap) * G * 4, s), "history");
+    // small graphs: refined to their stop levels by the persistent launch,
+    // each inside one workgroup's LDS (not with a direction view, whose
+    // per-graph edge counts differ from the graphs' own)
+    if (!view && small_edges > 0 && (stop || p.k_max <= 4096)) {
+        uint32_t max_v = 0, max_e = 0, grid = 0;
+        small_capacity(ctx->device, &max_v, &max_e, &grid);
+        std::vector<uint32_t> list;
+        std::vector<uint8_t> ext(G, 0);
+        uint32_t max_n = 0;
+        for (uint32_t g = 0; g < G; g++) {
+            const bsim_graph& in = graphs[g];
+            if (in.n_vertices <= max_v && in.n_edges <= std::min<uint64_t>(max_e, small_edges)) {
+                list.push_back(g);
+                ext[g] = 1;
+                max_n = std::max(max_n, in.n_vertices);
+            }
+        }
+        if (!list.empty()) {
+            std::stable_sort(list.begin(), list.end(),
+                             [&](uint32_t x, uint32_t y) { return graphs[x].n_edges > graphs[y].n_edges; });
+            std::vector<uint64_t> voff(G + 1, 0);
+            for (uint32_t g = 0; g < G; g++) voff[g + 1] = voff[g] + graphs[g].n_vertices;
+            rb.small.glist = upload_vec(arena, list, s);
+            rb.small.n_small = static_cast<uint32_t>(list.size());
+            rb.small.voff = upload_vec(arena, voff, s);
+            rb.small.queue = arena.alloc<uint32_t>(1);
+            rb.small.max_v = max_v;
+            rb.small.max_e = max_e;
+            rb.small.max_n = max_n;
+            rb.small.grid = grid;
+            rb.bc.ext = upload_vec(arena, ext, s);
+        }
+    }
     hip_check(hipEventRecord(ev[1], s), "event");
     LoopResult lr = run_refinement(ctx, ur, p, rb, nullptr, arena);
     hip_check(hipEventRecord(ev[2], s), "event");
@@ -425,6 +478,77 @@ void batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const 
 
 }  // namespace bsim
 
+namespace bsim {
+namespace {
+
+// Size class of a batch for the autotuner's cache: graph count, total and
+// largest edge counts (powers of two), label width, memory kind and flags.
+uint64_t size_class(const bsim_graph* graphs, uint32_t G, const bsim_params& p) {
+    uint64_t total = 0, largest = 0;
+    for (uint32_t g = 0; g < G; g++) {
+        total += graphs[g].n_edges;
+        largest = std::max<uint64_t>(largest, graphs[g].n_edges);
+    }
+    return (static_cast<uint64_t>(bit_width(G)) << 56) | (static_cast<uint64_t>(bit_width(total)) << 48) |
+           (static_cast<uint64_t>(bit_width(largest)) << 40) | (static_cast<uint64_t>(graphs[0].label_bytes) << 36) |
+           (static_cast<uint64_t>(graphs[0].mem_kind) << 32) | p.flags;
+}
+
+// The autotuner: the first batched call of a size class on a context runs
+// every candidate schedule on the batch itself, keeps the fastest for the
+// class, and returns the results of a run with it.  A schedule never changes
+// a result (every graph's result equals its own summarization), only the
+// time.  Candidates: the small-graph launch off or on (graphs of up to the
+// workgroup capacity), and hub-bucket tables of 4,096 or 16,384 LDS slots.
+void tuned_batch(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t G, const bsim_params& p, bsim_result** outs) {
+    const uint32_t hub_default = ctx->hub_table_slots;
+    bsim_ctx::BatchTune pick{ctx->autotune ? ~0ull : ctx->fixed_small_edges, hub_default};
+    const uint64_t key = size_class(graphs, G, p);
+    auto it = ctx->batch_tune.find(key);
+    if (it != ctx->batch_tune.end()) {
+        pick = it->second;
+    } else if (ctx->autotune) {
+        std::vector<bsim_ctx::BatchTune> cand;
+        for (uint64_t small : {0ull, ~0ull})
+            for (uint32_t hub : {4096u, 16384u})
+                if (hub <= query_hub_table_slots(ctx->device, true)) cand.push_back({small, hub});
+        double best = 0;
+        for (const auto& c : cand) {
+            std::vector<bsim_result*> tmp(G, nullptr);
+            ctx->hub_table_slots = c.hub_table_slots;
+            const auto t0 = std::chrono::steady_clock::now();
+            try {
+                batch_summarize(ctx, graphs, G, p, tmp.data(), c.small_edges);
+            } catch (...) {
+                ctx->hub_table_slots = hub_default;
+                for (bsim_result* r : tmp)
+                    if (r) bsim_result_free(r);
+                throw;
+            }
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            for (bsim_result* r : tmp)
+                if (r) bsim_result_free(r);
+            if (best == 0 || dt < best) {
+                best = dt;
+                pick = c;
+            }
+        }
+        ctx->batch_tune[key] = pick;
+    }
+    ctx->hub_table_slots = pick.hub_table_slots;
+    ctx->last_batch = pick;
+    try {
+        batch_summarize(ctx, graphs, G, p, outs, pick.small_edges);
+    } catch (...) {
+        ctx->hub_table_slots = hub_default;
+        throw;
+    }
+    ctx->hub_table_slots = hub_default;
+}
+
+}  // namespace
+}  // namespace bsim
+
 extern "C" int bsim_batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uint32_t n_graphs,
                                     const bsim_params* params, bsim_result** outs) {
     if (!ctx || !params || !outs || (n_graphs && !graphs)) return BSIM_E_INVALID;
@@ -432,7 +556,7 @@ extern "C" int bsim_batch_summarize(bsim_ctx* ctx, const bsim_graph* graphs, uin
     if (n_graphs == 0) return BSIM_OK;
     try {
         bsim::hip_check(hipSetDevice(ctx->device), "set device");
-        bsim::batch_summarize(ctx, graphs, n_graphs, *params, outs);
+        bsim::tuned_batch(ctx, graphs, n_graphs, *params, outs);
         return BSIM_OK;
     } catch (const bsim::DeviceError& e) {
         ctx->err = e.msg;

@@ -117,6 +117,21 @@ struct BatchCtl {
     uint32_t n_graphs = 0;
     uint32_t hist_cap = 0;
     uint32_t virt_base = 0;         // level-0 virtual class of graph g: virt_base + g
+    // per graph: 1 when the persistent small-graph launch refines it (the
+    // refinement launches then leave its vertices alone), nullable
+    const uint8_t* ext = nullptr;
+};
+
+// The small graphs of a batched run, refined to their fixpoints inside one
+// workgroup's LDS each (bsim_small.hip) instead of by the union's launches.
+struct SmallPlan {
+    const uint32_t* glist = nullptr;  // graph ids, largest first
+    uint32_t n_small = 0;
+    const uint64_t* voff = nullptr;   // union vertex offsets (G + 1)
+    uint32_t* queue = nullptr;        // work-queue counter
+    uint32_t max_v = 0, max_e = 0;    // capacities of one workgroup
+    uint32_t max_n = 0;               // vertices of the largest listed graph
+    uint32_t grid = 0;                // persistent workgroups
 };
 
 // Arguments of one refinement launch k: split test of level k-1, h^k.
@@ -384,6 +399,7 @@ struct RunBuffers {
     uint64_t* hub_acc = nullptr;
     RunStatus* status = nullptr;
     BatchCtl bc;                   // batched runs only
+    SmallPlan small;               // batched runs only
 };
 
 void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& rb, Arena& arena,
@@ -414,6 +430,13 @@ void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_pre
 
 // Batched runs: per-graph stop test of level k-2, before launch k.
 void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool stop, hipStream_t s);
+
+// Batched runs: LDS bytes of a small-graph workgroup with the given
+// capacities (and its hash-table slots), and the launch that refines the
+// graphs of `sp` to their stop levels (after launch_init).
+uint64_t small_graph_lds_bytes(uint32_t max_v, uint32_t max_e, uint32_t* tab_slots);
+void launch_small_graphs(const Staged& g, const RunBuffers& rb, const SmallPlan& sp, uint32_t k_max, bool stop,
+                         hipStream_t s);
 
 // LDS slots the hub-bucket launch can use on this device.
 // device_max: the largest table the device allows (else the default size).

@@ -278,8 +278,9 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
         if (a.bc.gid) {
             gi = a.bc.gid[v];
             const uint32_t dl = a.bc.done_level[gi];
-            act_test = k - 1 <= dl;
-            act_hash = k <= dl;
+            const bool ext = a.bc.ext && a.bc.ext[gi];
+            act_test = !ext && k - 1 <= dl;
+            act_hash = !ext && k <= dl;
         }
         if (test) {
             rv = a.rep[v];
@@ -573,8 +574,9 @@ __device__ bool iso_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32
             if (a.bc.gid) {
                 gi[r] = a.bc.gid[v[r]];
                 const uint32_t dl = a.bc.done_level[gi[r]];
-                act_test = k - 1 <= dl;
-                act_hash[r] = k <= dl;
+                const bool ext = a.bc.ext && a.bc.ext[gi[r]];
+                act_test = !ext && k - 1 <= dl;
+                act_hash[r] = !ext && k <= dl;
             }
             if (test) {
                 rv[r] = a.rep[v[r]];

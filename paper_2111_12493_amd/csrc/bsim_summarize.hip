@@ -89,6 +89,24 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     const bool untyped = (p.flags & BSIM_UNTYPED) != 0;
     if (sink && !sink->levels.empty()) rb.h[0] = sink->levels[0];
     launch_init(g, rb, untyped, s);
+    if (rb.bc.gid && rb.small.n_small) {
+        // the small graphs of a batch go to their stop levels now, each in one
+        // workgroup; their per-level counts need history rows up to there
+        // (with the fixpoint test a graph of n vertices stops by level max(n, 1))
+        const uint64_t depth =
+            stop ? std::min<uint64_t>(p.k_max, static_cast<uint64_t>(rb.small.max_n) + 1) : p.k_max;
+        const uint64_t need = depth + 2;
+        if (need > rb.bc.hist_cap) {
+            const size_t G = rb.bc.n_graphs;
+            uint32_t* nh = arena.alloc<uint32_t>(need * G);
+            hip_check(hipMemsetAsync(nh, 0, need * G * 4, s), "history clear");
+            hip_check(hipMemcpyAsync(nh, rb.bc.hist, static_cast<size_t>(rb.bc.hist_cap) * G * 4,
+                                     hipMemcpyDeviceToDevice, s), "history copy");
+            rb.bc.hist = nh;
+            rb.bc.hist_cap = static_cast<uint32_t>(need);
+        }
+        launch_small_graphs(g, rb, rb.small, p.k_max, stop, s);
+    }
 
     LoopResult lr;
     // launch k tests level k-2, so launch k_max + 2 always sees the cap
