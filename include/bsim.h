@@ -209,8 +209,19 @@ const char* bsim_status_string(int status);
  * ms_hub_kernels (events on every launch add gaps between launches, so
  * sampling keeps the timed run close to an untimed one); "hub_table_slots" = LDS hash
  * slots of a hub-bucket block (power of two from 64 to the device limit,
- * the default; smaller values force more hash buckets per hub).  Values
- * outside the range give BSIM_E_RANGE, unknown names BSIM_E_INVALID. */
+ * the default; smaller values force more hash buckets per hub);
+ * "frontier_limit_pct" (0..100) = share of the vertices beyond which an
+ * update level is recomputed for all vertices (0: always, the plain form);
+ * "autotune" (0/1, default 1) = batched calls pick their schedule per size
+ * class by timing the candidates on the first call of the class;
+ * "batch_small_edges" (N >= 0) = a fixed batched schedule instead: graphs
+ * of at most N edges that fit one workgroup go to the small-graph launch
+ * (0: none; turns autotune off); "batch_hub_table_slots" (read only) = the
+ * hub-table size of the last batched call; "fail_alloc_after" (N, 0..2^40)
+ * = for tests of the failure paths, the N-th device allocation from now in
+ * this process fails as if the device were out of memory (0: off; reading
+ * it gives the allocations left).  Values outside the range give
+ * BSIM_E_RANGE, unknown names BSIM_E_INVALID. */
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value);
 int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value);
 const char* bsim_option_names(void);

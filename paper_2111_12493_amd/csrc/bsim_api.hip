@@ -10,6 +10,10 @@
 
 using namespace bsim;
 
+namespace bsim {
+std::atomic<int64_t> g_fail_alloc_countdown{0};
+}
+
 extern "C" {
 
 const char* bsim_status_string(int status) {
@@ -86,7 +90,9 @@ const char* bsim_option_names(void) {
            "first call of the class; 1 = default); "
            "batch_small_edges (N >= 0: a fixed batched schedule, graphs of at most N edges that fit one "
            "workgroup go to the small-graph launch, 0 = none; turns autotune off); "
-           "batch_hub_table_slots (read only: the hub-table slots of the last batched call)";
+           "batch_hub_table_slots (read only: the hub-table slots of the last batched call); "
+           "fail_alloc_after (N, 0..2^40: for tests of the failure paths, the N-th device allocation from now "
+           "in this process fails as if the device were out of memory; 0 = off; reads the allocations left)";
 }
 
 int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
@@ -104,6 +110,11 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
     if (!strcmp(name, "frontier_limit_pct")) {
         if (value < 0 || value > 100) return BSIM_E_RANGE;
         ctx->frontier_limit_pct = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "fail_alloc_after")) {
+        if (value < 0 || value > (1ll << 40)) return BSIM_E_RANGE;
+        g_fail_alloc_countdown.store(value);
         return BSIM_OK;
     }
     if (!strcmp(name, "autotune")) {
@@ -151,6 +162,10 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     }
     if (!strcmp(name, "autotune")) {
         *value = ctx->autotune;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "fail_alloc_after")) {
+        *value = g_fail_alloc_countdown.load();
         return BSIM_OK;
     }
     if (!strcmp(name, "batch_small_edges")) {

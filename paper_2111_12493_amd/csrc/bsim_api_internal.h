@@ -93,9 +93,10 @@ int noalloc_scratch_init(int device, std::string* err);
 void finalize_prev_level(const Staged& g, const uint32_t* rep, const uint32_t* rep_prev, bool want_edges,
                          FinalOut& out, Arena& arena, Arena& keep, hipStream_t s);
 
-// Assemble a bsim_result from finalize output (takes ownership of `keep`).
+// Assemble a bsim_result from finalize output (takes ownership of `keep`);
+// hashes_preset: an array of n entries in `keep` to receive the hashes.
 bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, const uint64_t* h,
-                         FinalOut& fo, Arena& keep, uint32_t flags);
+                         FinalOut& fo, Arena& keep, uint32_t flags, uint64_t* hashes_preset = nullptr);
 
 // Whole batch path for one graph; labels = the kept label set of the label
 // parameterization (nullptr: every edge).

@@ -286,7 +286,7 @@ namespace {
 // First-occurrence block ids of the classes named by `rep` into ids[n], the
 // block sizes into a new array of `sizes_arena`; returns the block count.
 uint32_t number_blocks(const Staged& g, const uint32_t* rep, uint32_t* ids, uint32_t** sizes_out, Arena& arena,
-                       Arena& sizes_arena, hipStream_t s) {
+                       Arena& sizes_arena, hipStream_t s, uint32_t* sizes_preset = nullptr) {
     const uint32_t n = g.n;
     uint32_t* cmin = arena.alloc<uint32_t>(n + 1);
     uint32_t* isrep = arena.alloc<uint32_t>(n);
@@ -302,7 +302,7 @@ uint32_t number_blocks(const Staged& g, const uint32_t* rep, uint32_t* ids, uint
     uint32_t nb = 0;
     hip_check(hipMemcpyAsync(&nb, total, 4, hipMemcpyDeviceToHost, s), "block count");
     hip_check(hipStreamSynchronize(s), "block count sync");
-    uint32_t* sizes = sizes_arena.alloc<uint32_t>(nb + 1);
+    uint32_t* sizes = sizes_preset ? sizes_preset : sizes_arena.alloc<uint32_t>(nb + 1);
     hip_check(hipMemsetAsync(sizes, 0, (static_cast<size_t>(nb) + 1) * 4, s), "sizes");
     if (n) k_fin_ids<<<ceil_div(n, kIdsPerBlock), kBlock, 0, s>>>(g.alive, n, rep, cmin, rank, ids, sizes);
     hip_check(hipGetLastError(), "finalize launch");
@@ -313,8 +313,9 @@ uint32_t number_blocks(const Staged& g, const uint32_t* rep, uint32_t* ids, uint
 void finalize_impl(const Staged& g, const uint32_t* rep, const uint32_t* rep_prev, bool want_edges,
                    FinalOut& out, Arena& arena, Arena& keep, hipStream_t s) {
     const uint32_t n = g.n;
-    out.block_ids = keep.alloc<uint32_t>(n);
-    const uint32_t nb = number_blocks(g, rep, out.block_ids, &out.block_sizes, arena, keep, s);
+    if (!out.preset) out.block_ids = keep.alloc<uint32_t>(n);
+    const uint32_t nb = number_blocks(g, rep, out.block_ids, &out.block_sizes, arena, keep, s,
+                                      out.preset ? out.block_sizes : nullptr);
     out.n_blocks = nb;
     // the target end of a summary edge: the final blocks, or the blocks of
     // the previous level's classes
@@ -329,9 +330,11 @@ void finalize_impl(const Staged& g, const uint32_t* rep, const uint32_t* rep_pre
     uint32_t* total = arena.alloc<uint32_t>(1);
     out.n_se = 0;
     if (!want_edges || g.m == 0) {
-        out.se_src = keep.alloc<uint32_t>(1);
-        out.se_label = keep.alloc<uint32_t>(1);
-        out.se_dst = keep.alloc<uint32_t>(1);
+        if (!out.preset) {
+            out.se_src = keep.alloc<uint32_t>(1);
+            out.se_label = keep.alloc<uint32_t>(1);
+            out.se_dst = keep.alloc<uint32_t>(1);
+        }
         return;
     }
     const uint32_t nb_max = std::max(nb, nb_dst);
@@ -372,9 +375,11 @@ void finalize_impl(const Staged& g, const uint32_t* rep, const uint32_t* rep_pre
     hip_check(hipMemcpyAsync(&nse, total, 4, hipMemcpyDeviceToHost, s), "edge count");
     hip_check(hipStreamSynchronize(s), "edge count sync");
     out.n_se = nse;
-    out.se_src = keep.alloc<uint32_t>(nse);
-    out.se_label = keep.alloc<uint32_t>(nse);
-    out.se_dst = keep.alloc<uint32_t>(nse);
+    if (!out.preset) {
+        out.se_src = keep.alloc<uint32_t>(nse);
+        out.se_label = keep.alloc<uint32_t>(nse);
+        out.se_dst = keep.alloc<uint32_t>(nse);
+    }
     k_unpack<<<ceil_div(m, kBlock), kBlock, 0, s>>>(sorted, m, flag, pos, lb, bb, out.se_src,
                                                     out.se_label, out.se_dst);
     hip_check(hipGetLastError(), "unpack launch");

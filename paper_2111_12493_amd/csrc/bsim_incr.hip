@@ -670,7 +670,7 @@ struct DevBuf {
         // headroom, so that the small growth of most batches allocates nothing
         const size_t nc = std::max<size_t>({n + n / 8, cap + cap / 2, 64});
         T* q = nullptr;
-        if (hipMallocAsync(reinterpret_cast<void**>(&q), nc * sizeof(T), s) != hipSuccess)
+        if (device_alloc(reinterpret_cast<void**>(&q), nc * sizeof(T), s) != hipSuccess)
             throw DeviceError{BSIM_E_NOMEM, "state allocation of " + std::to_string(nc * sizeof(T)) + " bytes failed"};
         if (p && keep)
             hip_check(hipMemcpyAsync(q, p, std::min(keep, cap) * sizeof(T), hipMemcpyDeviceToDevice, s), "state grow");
@@ -816,8 +816,8 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
         if (st->cls_slots) (void)hipFreeAsync(st->cls_slots, s);
         if (st->cls_list) (void)hipFreeAsync(st->cls_list, s);
         st->cls_slots = nullptr, st->cls_list = nullptr;
-        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_slots), sizeof(uint64_t) * want, s), "class table");
-        hip_check(hipMallocAsync(reinterpret_cast<void**>(&st->cls_list), 4ull * want, s), "class list");
+        hip_check(device_alloc(reinterpret_cast<void**>(&st->cls_slots), sizeof(uint64_t) * want, s), "class table");
+        hip_check(device_alloc(reinterpret_cast<void**>(&st->cls_list), 4ull * want, s), "class list");
         hip_check(hipMemsetAsync(st->cls_slots, 0, sizeof(uint64_t) * want, s), "class table clear");
         st->cls_cap = want;
     }
@@ -930,7 +930,17 @@ HostBatch resolve(bsim_state* st, const bsim_update* ops, uint64_t n_ops) {
         ty_pool.insert(ty_pool.end(), o.types, o.types + o.n_types);
         vtype[v] = static_cast<uint32_t>(ty_rec.size());
     };
-    try {
+    // the marks of the touched vertices are cleared on every way out,
+    // including a throw, so the next call starts from clean scratch
+    struct ClearMarks {
+        std::vector<uint32_t>& touched;
+        std::vector<uint8_t>& vmark;
+        std::vector<uint32_t>& vtype;
+        ~ClearMarks() {
+            for (uint32_t v : touched) vmark[v] = 0, vtype[v] = 0;
+        }
+    } clear_marks{touched, vmark, vtype};
+    {
         for (uint64_t i = 0; i < n_ops; i++) {
             const bsim_update& o = ops[i];
             const bool edge = o.op == BSIM_OP_ADD_E || o.op == BSIM_OP_DEL_E || o.op == BSIM_OP_MOD_E;
@@ -983,9 +993,6 @@ HostBatch resolve(bsim_state* st, const bsim_update* ops, uint64_t n_ops) {
                     throw DeviceError{BSIM_E_INVALID, "unknown update op code"};
             }
         }
-    } catch (...) {
-        for (uint32_t v : touched) vmark[v] = 0, vtype[v] = 0;
-        throw;
     }
     hb.n_new = n_cur;
     hb.tl = touched;
@@ -1061,7 +1068,6 @@ HostBatch resolve(bsim_state* st, const bsim_update* ops, uint64_t n_ops) {
             i = j;
         }
     }
-    for (uint32_t v : touched) vmark[v] = 0, vtype[v] = 0;
     for (size_t i = 0; i < hb.cu.size();) {
         size_t j = i;
         while (j < hb.cu.size() && hb.cu[j] == hb.cu[i]) j++;
@@ -1418,8 +1424,16 @@ std::vector<uint32_t> level_classes(bsim_state* st, uint32_t upto) {
     return read_class_counts(st, upto);
 }
 
+// Result arrays of an update, allocated before the update changes the state
+// (so an allocation failure cannot leave a half-applied batch behind).
+struct ResultReserve {
+    Arena* keep = nullptr;   // owns the arrays until they go to the result
+    FinalOut fo;             // preset output arrays
+    uint64_t* hashes = nullptr;
+};
+
 // Classes, fixpoint rule and finalize on the current levels.
-bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls) {
+bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls, ResultReserve* rr = nullptr) {
     hipStream_t s = st->s;
     std::vector<uint32_t> f = classes_end(st);
     std::vector<uint32_t> nk(st->K + 1);
@@ -1447,15 +1461,70 @@ bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls) {
     g.alive = st->alive.p;
     g.src = st->src[st->cur].p;
     g.max_label = st->max_label;
-    Arena keep(s);
+    Arena own_keep(s);
+    Arena& keep = rr ? *rr->keep : own_keep;
     FinalOut fo;
+    if (rr) fo = rr->fo;
     finalize(g, st->rep.p, !(st->flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
     if (fo.n_blocks != nk[k_done]) throw DeviceError{BSIM_E_DEVICE, "internal: class count mismatch in finalize"};
     LoopResult lr;
     lr.k_done = k_done;
     lr.fixpoint = fix;
     lr.blocks_per_iter.assign(nk.begin(), nk.begin() + k_done + 1);
-    return make_result(st->ctx, g, lr, st->levels[k_done].p, fo, keep, st->flags);
+    return make_result(st->ctx, g, lr, st->levels[k_done].p, fo, keep, st->flags, rr ? rr->hashes : nullptr);
+}
+
+// Every device allocation an update batch needs, made before the batch
+// changes anything: the state's arrays at their sizes after the batch (the
+// merges, the frontier scratch and counters then find them in place), a
+// workspace that holds the update's temporaries, and the result's arrays.
+// An allocation that fails here throws with the state as it was.
+void reserve_batch(bsim_state* st, const HostBatch& hb, ResultReserve& rr) {
+    hipStream_t s = st->s;
+    const uint32_t n_new = hb.n_new;
+    const uint64_t m_cap = st->m + hb.n_present;
+    if (m_cap > kMaxStateEdges) throw DeviceError{BSIM_E_UNSUPPORTED, "a resident state holds at most 2^30 edges"};
+    const uint64_t nt_cap = st->nt + hb.tl_ids.size();
+    if (nt_cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "too many type entries"};
+    ensure_vertices(st, n_new);
+    if (!hb.gsrc.empty() || !hb.dead.empty()) {
+        st->src[st->cur ^ 1].ensure(m_cap + 1, 0, s);
+        st->tgt[st->cur ^ 1].ensure(m_cap + 1, 0, s);
+        st->lab[st->cur ^ 1].ensure((m_cap + 1) * st->label_bytes, 0, s);
+    }
+    if (!hb.tl.empty()) {
+        st->type_own[st->tcur ^ 1].ensure(nt_cap + 1, 0, s);
+        st->type_ids[st->tcur ^ 1].ensure(nt_cap + 1, 0, s);
+    }
+    st->kpos.ensure(std::max(m_cap, nt_cap) + 1, 0, s);
+    if (!hb.rw.empty() || n_new > st->n_rev) {
+        const uint64_t cap = st->rm + hb.rw.size();
+        if (cap >= (1ull << 32)) throw DeviceError{BSIM_E_UNSUPPORTED, "reverse lists too long"};
+        st->rev_own[st->rcur ^ 1].ensure(cap + 1, 0, s);
+        st->rev_src[st->rcur ^ 1].ensure(cap + 1, 0, s);
+    }
+    ensure_salt(st, std::max(st->max_label, hb.max_label));
+    st->chunk_owner.ensure(static_cast<size_t>(n_new) + m_cap / kChunkEdges + 2, 0, s);
+    const uint64_t pct = st->ctx->frontier_limit_pct;
+    st->scratch.ensure(4 * (m_cap * 3 * pct / 100 + 4096) + 1024, 0, s);
+    st->cls_cnt.ensure(2ull * (st->K + 1), 0, s);
+    // the workspace: uploads of the batch, merge flags and scans, the
+    // staging of full levels, the reverse-list sort and finalize
+    const uint64_t items = hb.cu.size() + hb.rw.size() + hb.rgw.size() + hb.tl.size() + hb.tl_ids.size() +
+                           hb.dead.size() + 3 * hb.gsrc.size() + hb.tl_off.size();
+    const uint64_t bound = 40 * m_cap + 64ull * n_new + 24 * items + (64ull << 20);
+    st->work_want = std::max<uint64_t>(st->work_want, bound);
+    st->work.ensure(st->work_want, 0, s);
+    // the result's arrays
+    Arena& keep = *rr.keep;
+    rr.fo.preset = true;
+    rr.fo.block_ids = keep.alloc<uint32_t>(static_cast<size_t>(n_new) + 1);
+    rr.fo.block_sizes = keep.alloc<uint32_t>(static_cast<size_t>(n_new) + 1);
+    const uint64_t se = (st->flags & BSIM_NO_SUMMARY_EDGES) ? 1 : m_cap + 1;
+    rr.fo.se_src = keep.alloc<uint32_t>(se);
+    rr.fo.se_label = keep.alloc<uint32_t>(se);
+    rr.fo.se_dst = keep.alloc<uint32_t>(se);
+    rr.hashes = keep.alloc<uint64_t>(static_cast<size_t>(n_new) + 1);
 }
 
 struct PhaseTimer {
@@ -1482,11 +1551,13 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
     hipStream_t s = st->s;
     PhaseTimer tm(s);
     tm.mark(0);
+    Arena keep(s);
+    ResultReserve rr;
+    rr.keep = &keep;
+    reserve_batch(st, hb, rr);
     Arena arena(s);
-    st->work.ensure(st->work_want, 0, s);
     arena.back(st->work.p, st->work.cap);
     const uint32_t n_old = st->n, n_new = hb.n_new;
-    ensure_vertices(st, n_new);
     const size_t grow = n_new - n_old;
     if (grow) {
         hip_check(hipMemsetAsync(st->alive.p + n_old, 1, grow, s), "new alive");
@@ -1552,7 +1623,7 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
     classes_level(st, 0);
     propagate(st, d_tl, nT, tag0, arena);
     tm.mark(2);
-    bsim_result* r = finish(st, arena, nullptr);
+    bsim_result* r = finish(st, arena, nullptr, &rr);
     tm.mark(3);
     tm.fill(r);
     st->work_want = std::max(st->work_want, arena.demand());

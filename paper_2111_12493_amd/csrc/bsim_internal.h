@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -207,6 +208,26 @@ struct DeviceError {
     std::string msg;
 };
 
+// Test hook for the failure paths: the N-th device allocation from the time
+// it is set fails as if the device were out of memory (process-wide; 0 =
+// off).  Set with the ctx option "fail_alloc_after".
+extern std::atomic<int64_t> g_fail_alloc_countdown;
+
+// Every device allocation of the library goes through here.
+inline hipError_t device_alloc(void** p, size_t bytes, hipStream_t s) {
+    int64_t c = g_fail_alloc_countdown.load(std::memory_order_relaxed);
+    while (c > 0) {
+        if (g_fail_alloc_countdown.compare_exchange_weak(c, c - 1)) {
+            if (c == 1) {
+                *p = nullptr;
+                return hipErrorOutOfMemory;
+            }
+            break;
+        }
+    }
+    return hipMallocAsync(p, bytes, s);
+}
+
 // Stream-ordered device allocations released together (error paths included).
 class Arena {
   public:
@@ -240,7 +261,7 @@ class Arena {
         if (strict_)
             throw DeviceError{BSIM_E_UNSUPPORTED, "the temporaries need more than the " + std::to_string(cap_) +
                                                       " bytes of scratch memory"};
-        if (hipMallocAsync(&p, bytes, stream_) != hipSuccess)
+        if (device_alloc(&p, bytes, stream_) != hipSuccess)
             throw DeviceError{BSIM_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
         ptrs_.push_back(p);
         return static_cast<T*>(p);
@@ -458,6 +479,10 @@ uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Arena& aren
 
 // Finalize (a8): block ids, block sizes, sorted distinct quotient edges.
 struct FinalOut {
+    // preset: the output arrays below are already allocated by the caller
+    // (block_ids and block_sizes for n + 1 entries, the summary-edge columns
+    // for m + 1), and finalize allocates none of them
+    bool preset = false;
     uint32_t n_blocks = 0;
     uint64_t n_se = 0;
     uint32_t* block_ids = nullptr;

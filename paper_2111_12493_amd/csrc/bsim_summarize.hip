@@ -246,7 +246,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
 }
 
 bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, const uint64_t* h,
-                         FinalOut& fo, Arena& keep, uint32_t flags) {
+                         FinalOut& fo, Arena& keep, uint32_t flags, uint64_t* hashes_preset) {
     hipStream_t s = ctx->stream;
     bsim_result* r = new bsim_result();
     ResultPriv* p = new ResultPriv();
@@ -265,7 +265,7 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
     r->ms_hub_kernels = lr.ms_hub_kernels;
     r->n_timed_launches = lr.n_timed;
     r->blocks_per_iter = p->blocks_per_iter.data();
-    uint64_t* hashes = keep.alloc<uint64_t>(g.n);
+    uint64_t* hashes = hashes_preset ? hashes_preset : keep.alloc<uint64_t>(g.n);
     if (g.n) hip_check(hipMemcpyAsync(hashes, h, static_cast<size_t>(g.n) * 8, hipMemcpyDeviceToDevice, s),
                        "hashes");
     void* dev[] = {hashes, fo.block_ids, fo.block_sizes, fo.se_src, fo.se_label, fo.se_dst};
