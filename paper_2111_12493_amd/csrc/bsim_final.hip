@@ -340,6 +340,10 @@ void finalize_impl(const Staged& g, const uint32_t* rep, const uint32_t* rep_pre
     const uint32_t nb_max = std::max(nb, nb_dst);
     const int bb = std::max(1, bit_width(nb_max ? nb_max - 1 : 0));
     const int lb = std::max(1, bit_width(g.max_label));
+    if (bucketed_summary_edges_fit(g, lb, bb)) {
+        bucketed_summary_edges(g, out.block_ids, nb, dst_ids, lb, bb, out, arena, keep, s);
+        return;
+    }
     if (2 * bb + lb > 64)
         throw DeviceError{BSIM_E_UNSUPPORTED, "summary-edge triple does not fit 64 bits"};
     const uint32_t m = static_cast<uint32_t>(g.m);

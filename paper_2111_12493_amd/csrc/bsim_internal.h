@@ -492,6 +492,13 @@ struct FinalOut {
     uint32_t* se_dst = nullptr;
 };
 
+// Summary edges of a CSR graph with a tile schedule, bucketed by source
+// block (bid, nb blocks) and sorted within each block; false from the fit
+// test means the keys or the layout need the global sort instead.
+bool bucketed_summary_edges_fit(const Staged& g, int lb, int bb);
+void bucketed_summary_edges(const Staged& g, const uint32_t* bid, uint32_t nb, const uint32_t* dst_ids, int lb,
+                            int bb, FinalOut& out, Arena& arena, Arena& keep, hipStream_t s);
+
 // Blocks are the classes given by rep[] (first-occurrence numbering).
 void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& out, Arena& arena,
               Arena& keep, hipStream_t s);
