@@ -12,15 +12,16 @@
 //   2. every edge writes its value l << bb | block(w) into its vertex's range;
 //   3. every segment is sorted and de-duplicated in place, by size:
 //        1 value          nothing to do;
-//        2..256           tiles of consecutive segments, one LDS radix sort
-//                         per tile on (segment ordinal, value);
+//        2..256           one wave sorts the segments starting in 256
+//                         consecutive positions, LDS radix sort on
+//                         (segment ordinal, value);
 //        257..16,384      one workgroup per segment, LDS radix sort;
 //        more             one global LSD radix sort over all such segments
 //                         on (segment rank, value);
 //   4. an exclusive scan of the per-block distinct counts places the output;
 //      the distinct values are unpacked to (src, label, dst).
-// The LDS sorts rank digits with wave ballots into per-wave counters and
-// skip every digit on which a tile's keys agree.
+// The LDS radix sorts rank digits with wave ballots into per-wave counters
+// and skip every digit on which a segment's keys agree.
 #include "bsim_device.h"
 
 namespace bsim {
@@ -30,18 +31,20 @@ namespace {
 constexpr uint32_t kSegSmallMax = 256;     // tile-packed segments hold at most this many values
 constexpr uint32_t kSegMedMax = 4096;      // one 256-thread workgroup per segment
 constexpr uint32_t kSegBigMax = 16384;     // one 1,024-thread workgroup per segment
-constexpr uint32_t kSortIpt = 16;          // values per thread in an LDS sort
-constexpr uint32_t kSmallCap = kBlock * kSortIpt;            // 4,096 values per small tile
-constexpr uint32_t kSmallRange = kSmallCap - kSegSmallMax;   // segment starts per small tile
+constexpr uint32_t kSortIpt = 16;          // values per thread in an LDS sort (at most)
+constexpr uint32_t kSmallBlock = 64;       // a small tile is one wave
+constexpr uint32_t kSmallRange = 256;      // segment starts per small tile
+constexpr uint32_t kSmallCap = 512;        // values per small tile: kSmallRange + kSegSmallMax - 1 fit
 constexpr uint32_t kSmallMaxSeg = kSmallCap / 2;             // segments of >= 2 values
-constexpr int kOrdBits = 11;                                 // ordinals < 2,048
+constexpr int kOrdBits = 8;                                  // tile ordinals < 256
 constexpr uint32_t kUnpackTile = kBlock * 16;
 constexpr uint32_t kUnpackCache = 4096;    // block offsets a tile keeps in LDS
 constexpr uint32_t kBigBlock = 1024;
 
-static_assert(kSmallMaxSeg <= (1u << kOrdBits), "segment ordinals must fit their field");
 static_assert(kSmallRange + kSegSmallMax <= kSmallCap, "a small tile must hold its segments");
-static_assert(kBigBlock * kSortIpt == kSegBigMax && kSmallCap == kSegMedMax, "sort capacities");
+static_assert(kSmallMaxSeg <= (1u << kOrdBits), "tile ordinals must fit their field");
+static_assert(kSmallCap <= kSmallBlock * kSortIpt, "a small tile fits the sort's registers");
+static_assert(kBigBlock * kSortIpt == kSegBigMax && kBlock * kSortIpt == kSegMedMax, "sort capacities");
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const uint32_t lane = lane_id();
@@ -141,6 +144,7 @@ struct SegArgs {
 template <int NT>
 __device__ void sort_tile(const SegArgs& a, const SortSmem& S, uint32_t cnt, uint32_t nseg) {
     constexpr uint32_t W = NT / 64;
+    constexpr uint32_t DPT = NT >= 256 ? 1 : 256 / NT;  // digits per thread in the prefix step
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
     const uint32_t ipt = (cnt + NT - 1) / NT;  // rounds per wave; element = (w * ipt + r) * 64 + lane
     const uint64_t vmask = (1ull << a.vb) - 1;
@@ -204,18 +208,23 @@ __device__ void sort_tile(const SegArgs& a, const SortSmem& S, uint32_t cnt, uin
             lr[r] = base + static_cast<uint32_t>(__popcll(peers & lt));
         }
         __syncthreads();
-        // digit d of wave w starts at (keys of smaller digits) + (digit d in earlier waves)
+        // digit d of wave w starts at (keys of smaller digits) + (digit d in
+        // earlier waves); thread t owns digits [t DPT, (t + 1) DPT)
+        const bool owner = tid * DPT < 256;
         uint32_t tot = 0;
-        if (tid < 256)
-            for (uint32_t i = 0; i < W; i++) tot += S.wc[i * 256 + tid];
+        if (owner)
+            for (uint32_t c = 0; c < DPT; c++)
+                for (uint32_t i = 0; i < W; i++) tot += S.wc[i * 256 + tid * DPT + c];
         uint32_t all = 0;
-        uint32_t run = block_excl_scan<NT>(tid < 256 ? tot : 0u, S.red, &all);
-        if (tid < 256)
-            for (uint32_t i = 0; i < W; i++) {
-                const uint32_t c = S.wc[i * 256 + tid];
-                S.wc[i * 256 + tid] = run;
-                run += c;
-            }
+        uint32_t run = block_excl_scan<NT>(owner ? tot : 0u, S.red, &all);
+        if (owner)
+            for (uint32_t c = 0; c < DPT; c++)
+                for (uint32_t i = 0; i < W; i++) {
+                    const uint32_t d = tid * DPT + c;
+                    const uint32_t cc = S.wc[i * 256 + d];
+                    S.wc[i * 256 + d] = run;
+                    run += cc;
+                }
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < kSortIpt; r++) {
@@ -286,22 +295,24 @@ __device__ void sort_tile(const SegArgs& a, const SortSmem& S, uint32_t cnt, uin
 }
 
 // Small segments (2..256 values): tile t takes the small segments whose
-// first value lies in [t R, (t + 1) R), R = kSmallRange.
-__global__ void __launch_bounds__(kBlock) k_seg_small(SegArgs a) {
+// first value lies in [t R, (t + 1) R), R = kSmallRange, packs them back to
+// back and sorts them as one key set (segment ordinal << vb | value).  A
+// tile is one wave, so the sort's barriers cost next to nothing and many
+// tiles share a CU.
+__global__ void __launch_bounds__(kSmallBlock) k_seg_small(SegArgs a) {
     extern __shared__ uint64_t smem_small[];
-    const SortSmem S = carve<kBlock>(reinterpret_cast<uint8_t*>(smem_small), kSmallCap, kSmallMaxSeg);
+    const SortSmem S = carve<kSmallBlock>(reinterpret_cast<uint8_t*>(smem_small), kSmallCap, kSmallMaxSeg);
     const uint32_t t = blockIdx.x;
     const uint32_t b_lo = a.tile_first[t];
     const uint32_t b_hi = t + 1 < a.n_tiles ? a.tile_first[t + 1] : a.nb;
-    // number the tile's small segments and place them back to back
     uint32_t nseg = 0, cnt = 0;
-    for (uint32_t c = b_lo; c < b_hi; c += kBlock) {  // uniform trip count
+    for (uint32_t c = b_lo; c < b_hi; c += kSmallBlock) {  // uniform trip count
         const uint32_t b = c + threadIdx.x;
         uint32_t sz = 0;
         if (b < b_hi) sz = a.estart[b + 1] - a.estart[b];
         const bool small = sz >= 2 && sz <= kSegSmallMax;
         uint32_t tot = 0;
-        const uint32_t packed = block_excl_scan<kBlock>(small ? (1u << 20) | sz : 0u, S.red, &tot);
+        const uint32_t packed = block_excl_scan<kSmallBlock>(small ? (1u << 20) | sz : 0u, S.red, &tot);
         if (small) {
             const uint32_t o = nseg + (packed >> 20);
             S.lofs[o] = cnt + (packed & 0xFFFFF);
@@ -314,7 +325,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_small(SegArgs a) {
     if (nseg == 0) return;  // uniform
     if (threadIdx.x == 0) S.lofs[nseg] = cnt;
     __syncthreads();
-    sort_tile<kBlock>(a, S, cnt, nseg);
+    sort_tile<kSmallBlock>(a, S, cnt, nseg);
 }
 
 // Medium segments: one workgroup per listed block.
@@ -586,11 +597,7 @@ void bucketed_summary_edges(const Staged& g, const uint32_t* bid, uint32_t nb, c
                                                                                        n_st, tf);
         a.tile_first = tf;
         a.n_tiles = n_st;
-        const uint64_t bytes = sort_smem_bytes(kBlock, kSmallCap, kSmallMaxSeg);
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(k_seg_small),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)),
-                  "small-segment LDS");
-        k_seg_small<<<n_st, kBlock, bytes, s>>>(a);
+        k_seg_small<<<n_st, kSmallBlock, sort_smem_bytes(kSmallBlock, kSmallCap, kSmallMaxSeg), s>>>(a);
     }
     if (n_med) {
         a.list = l_med;
