@@ -165,11 +165,13 @@ typedef struct {
     float ms_total;
     float ms_iter_kernels; /* when the ctx option "time_launches" is N > 0: summed
                               durations of every N-th refinement-kernel launch
-                              among those that did work (launches 1..k_done+1;
-                              later ones return at once), else 0 */
+                              among those that hashed a level (launches
+                              1..k_done+1, less launch k_done+1 when it ran
+                              split; later ones return at once), else 0 */
     float ms_hub_kernels;  /* the same for the hub-vertex launches */
     uint32_t n_timed_launches; /* launches those sums cover */
-    uint32_t reserved;
+    uint32_t n_split_launches; /* refinement launches run as a split half and a
+                                  hash half (ctx option "tail_split_ppm") */
     void* priv;
 } bsim_result;
 
@@ -212,6 +214,12 @@ const char* bsim_status_string(int status);
  * the default; smaller values force more hash buckets per hub);
  * "frontier_limit_pct" (0..100) = share of the vertices beyond which an
  * update level is recomputed for all vertices (0: always, the plain form);
+ * "tail_split_ppm" (0..1000000, default 100) = when the refinement launches
+ * run one per stop check (graphs whose launch takes milliseconds, or
+ * chunk_max = 1), a level that founds at most this many classes per
+ * million vertices has the next level's split test run as a launch of its
+ * own before that level's hashes, so a run that reaches its fixpoint there
+ * hashes no further level (0: off);
  * "autotune" (0/1, default 1) = batched calls pick their schedule per size
  * class by timing the candidates on the first call of the class;
  * "batch_small_edges" (N >= 0) = a fixed batched schedule instead: graphs

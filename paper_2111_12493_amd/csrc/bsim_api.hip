@@ -46,6 +46,11 @@ int bsim_ctx_create(int device, void* hip_stream, bsim_ctx** out) {
         delete c;
         return BSIM_E_NOMEM;
     }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->count_host), kStripes * sizeof(uint32_t),
+                      hipHostMallocDefault) != hipSuccess) {
+        bsim_ctx_free(c);
+        return BSIM_E_NOMEM;
+    }
     for (hipEvent_t& e : c->loop_ev) {
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
             bsim_ctx_free(c);
@@ -73,6 +78,7 @@ void bsim_ctx_free(bsim_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+    if (ctx->count_host) (void)hipHostFree(ctx->count_host);
     for (hipEvent_t e : ctx->loop_ev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
@@ -86,6 +92,9 @@ const char* bsim_option_names(void) {
            "hub_table_slots (LDS slots of a hub-bucket block: power of two, 64..device limit); "
            "frontier_limit_pct (0..100: an update level whose frontier exceeds this share of the vertices is "
            "recomputed for all vertices; 0 = always, the plain full recomputation); "
+           "tail_split_ppm (0..1000000: when refinement launches run one per stop check, a level that founds "
+           "at most this many classes per million vertices has the next level's split run as a launch of its "
+           "own, so a run that stops there computes no further hashes; 0 = off, default 100); "
            "autotune (0/1: batched calls pick their schedule per size class by timing the candidates on the "
            "first call of the class; 1 = default); "
            "batch_small_edges (N >= 0: a fixed batched schedule, graphs of at most N edges that fit one "
@@ -110,6 +119,11 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
     if (!strcmp(name, "frontier_limit_pct")) {
         if (value < 0 || value > 100) return BSIM_E_RANGE;
         ctx->frontier_limit_pct = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "tail_split_ppm")) {
+        if (value < 0 || value > 1000000) return BSIM_E_RANGE;
+        ctx->tail_split_ppm = static_cast<uint32_t>(value);
         return BSIM_OK;
     }
     if (!strcmp(name, "fail_alloc_after")) {
@@ -162,6 +176,10 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     }
     if (!strcmp(name, "autotune")) {
         *value = ctx->autotune;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "tail_split_ppm")) {
+        *value = ctx->tail_split_ppm;
         return BSIM_OK;
     }
     if (!strcmp(name, "fail_alloc_after")) {

@@ -18,6 +18,10 @@ struct bsim_ctx {
     uint32_t time_launches = 0;
     uint32_t hub_table_slots = 8192;  // LDS slots per hub-bucket block on this device
     uint32_t frontier_limit_pct = 2;  // incremental: larger frontiers recompute the level for all vertices
+    // one launch per stop check: once a level founds at most this many
+    // classes per million vertices, the next level's split runs on its own
+    uint32_t tail_split_ppm = 100;
+    uint32_t* count_host = nullptr;   // pinned: a level's founded counts (kStripes entries)
     // batched calls: schedules picked by the autotuner, per size class
     uint32_t autotune = 1;
     struct BatchTune {
@@ -69,6 +73,7 @@ struct LoopResult {
     uint32_t k_done = 0;
     uint32_t fixpoint = 0;
     uint32_t launches = 0;
+    uint32_t split_launches = 0;  // launches run as a split half and a hash half
     float ms_kernels = 0.f;      // refinement launches that did work
     float ms_hub_kernels = 0.f;  // hub launches of those iterations
     uint32_t n_timed = 0;        // launches the two sums cover

@@ -80,6 +80,15 @@ constexpr int kListPerStripe = 4096;     // claimed split-table slots remembered
 constexpr uint32_t kNoRep = 0xFFFFFFFEu; // virtual class of every vertex before level 0
 
 // Device-side status of a refinement run.
+// Launch k normally tests level k-2, splits level k-1 and hashes level k
+// (kPhaseFused).  Near a fixpoint it can run as two launches: kPhaseSplit
+// (stop test of level k-2, split of level k-1, no hashes), then kPhaseHash
+// (stop test of level k-1, which the split launch completed, then h^k), so
+// a run that stops at level k-1 computes no h^k.
+constexpr uint32_t kPhaseFused = 0;
+constexpr uint32_t kPhaseSplit = 1;
+constexpr uint32_t kPhaseHash = 2;
+
 struct RunStatus {
     uint32_t done;      // sticky: set by the first launch that sees the stop condition
     uint32_t k_done;
@@ -175,6 +184,7 @@ struct IterArgs {
     uint32_t k_max;
     uint32_t stop;
     uint32_t hash_only;     // h^k only: no stop test, split test or recycling
+    uint32_t phase;         // kPhaseFused, or one half of a split launch (kPhaseSplit, kPhaseHash)
     BatchCtl bc;
 };
 
@@ -429,9 +439,10 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
 // Level 0: type hashes, h^0 = t, the type classes (rep) and n_0.
 void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s);
 
-// Launch k: stop test, split test of level k-1, h^k (tiles and hub chunks).
+// Launch k: stop test, split test of level k-1, h^k (tiles and hub chunks),
+// or one half of it (phase; see kPhaseFused).
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
-                      bool stop, bool all_levels, hipStream_t s);
+                      bool stop, bool all_levels, hipStream_t s, uint32_t phase = kPhaseFused);
 
 // Hub buckets of iteration k (only when the graph has hubs and k <= k_max).
 void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s);

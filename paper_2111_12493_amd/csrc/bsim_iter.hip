@@ -213,12 +213,20 @@ __device__ __forceinline__ void split_test(const IterArgs& a, uint32_t v, uint32
         atomicAdd(&a.bc.hist[static_cast<size_t>(a.k - 1) * a.bc.n_graphs + a.bc.gid[v]], 1u);
 }
 
+// What launch k does: the split test of level k-1, the hashes h^k, and the
+// stop test of level k - stop_lag (its split is complete by then).
+__device__ __forceinline__ bool run_test(const IterArgs& a) {
+    return !a.hash_only && a.phase != kPhaseHash && a.k >= 2 && a.k - 1 <= a.k_max;
+}
+__device__ __forceinline__ bool run_hash(const IterArgs& a) { return a.phase != kPhaseSplit && a.k <= a.k_max; }
+__device__ __forceinline__ uint32_t stop_lag(const IterArgs& a) { return a.phase == kPhaseHash ? 1u : 2u; }
+
 // The sticky done flag as this wave sees it (only to skip loads; see tile_block).
 __device__ __forceinline__ bool early_done(const IterArgs& a) {
     return !a.hash_only && __hip_atomic_load(&a.status->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Stop test of level k-2 (wave 0), from the values loaded at block start:
+// Stop test of level k - stop_lag (wave 0), from the values loaded at block start:
 // S.ctl[0] = 1 when the run is done; block 0 also records n_{k-2} and, on
 // stopping, the final status.  Visible to the block after its next barrier.
 __device__ __forceinline__ void stop_decision(const IterArgs& a, IterShared& S, uint32_t p_done,
@@ -227,8 +235,9 @@ __device__ __forceinline__ void stop_decision(const IterArgs& a, IterShared& S, 
     if (tid >= 64) return;
     uint32_t ex = p_done;
     // batched runs: the per-graph stop launch before this one sets done
-    if (!ex && k >= 2 && !a.bc.gid && !a.hash_only) {
-        const uint32_t lv = k - 2;
+    const uint32_t lag = stop_lag(a);
+    if (!ex && k >= lag && !a.bc.gid && !a.hash_only) {
+        const uint32_t lv = k - lag;
         const uint32_t c = wave_sum_u32(p_cnt);
         const uint32_t nl = lv == 0 ? c : p_tot + c;
         if (tid == 0) {
@@ -256,8 +265,8 @@ template <typename LabT>
 __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint32_t p_done, uint32_t p_cnt,
                            uint32_t p_tot) {
     const uint32_t tid = threadIdx.x, k = a.k;
-    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
-    const bool hash = k <= a.k_max;
+    const bool test = run_test(a);
+    const bool hash = run_hash(a);
     const uint32_t i0 = a.tile_i0[tile], nv = a.tile_i1[tile] - i0;
     const uint32_t ebase = a.tile_e0[tile];
     // A launch queued after the stop finds the sticky done flag set; every
@@ -384,8 +393,8 @@ template <typename LabT>
 __device__ bool hub_chunk_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32_t p_done, uint32_t p_cnt,
                                 uint32_t p_tot) {
     const uint32_t tid = threadIdx.x, k = a.k;
-    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
-    const bool hash = k <= a.k_max;
+    const bool test = run_test(a);
+    const bool hash = run_hash(a);
     const uint32_t hi = a.hc_hub[blk];
     const uint32_t e0 = a.hc_e0[blk];
     const uint32_t v = a.hub_v[hi];
@@ -469,8 +478,8 @@ template <typename LabT>
 __device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_t p_done, uint32_t p_cnt,
                            uint32_t p_tot) {
     const uint32_t tid = threadIdx.x, k = a.k;
-    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
-    const bool hash = k <= a.k_max;
+    const bool test = run_test(a);
+    const bool hash = run_hash(a);
     const uint32_t e0 = a.row_off[v];
     const uint32_t ne = early_done(a) ? 0u : a.row_off[v + 1] - e0;
     bool act_hash = true;
@@ -553,8 +562,8 @@ __device__ bool solo_block(const IterArgs& a, uint32_t v, IterShared& S, uint32_
 __device__ bool iso_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32_t p_done, uint32_t p_cnt,
                           uint32_t p_tot) {
     const uint32_t tid = threadIdx.x, k = a.k;
-    const bool test = !a.hash_only && k >= 2 && k - 1 <= a.k_max;
-    const bool hash = k <= a.k_max && (k <= 2 || a.all_levels);
+    const bool test = run_test(a);
+    const bool hash = run_hash(a) && (k <= 2 || a.all_levels);
     uint32_t v[kIsoPerThread], rv[kIsoPerThread], gi[kIsoPerThread];
     uint64_t hv_own[kIsoPerThread], hv_rep[kIsoPerThread], tv[kIsoPerThread];
     bool mine[kIsoPerThread], live[kIsoPerThread], probe[kIsoPerThread], act_hash[kIsoPerThread];
@@ -656,12 +665,13 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
     __shared__ IterShared S;
     const uint32_t tid = threadIdx.x;
     const uint32_t k = a.k;
-    // stop-test inputs (level k-2), loaded together with everything else
+    // stop-test inputs (level k - stop_lag), loaded together with everything else
     uint32_t p_done = 0, p_cnt = 0, p_tot = 0;
     if (tid < 64) {
         p_done = __hip_atomic_load(&a.status->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (k >= 2 && !a.bc.gid && !a.hash_only) {
-            const uint32_t lv = k - 2;
+        const uint32_t lag = stop_lag(a);
+        if (k >= lag && !a.bc.gid && !a.hash_only) {
+            const uint32_t lv = k - lag;
             p_cnt = a.lcnt[(lv & (kStripeRing - 1)) * kStripes + tid];
             p_tot = lv ? a.totals[lv - 1] : 0u;
         }
@@ -678,7 +688,8 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
         go = tile_block<LabT>(a, b - a.n_hub_chunks - a.n_solo - a.n_iso_blocks, S, p_done, p_cnt, p_tot);
     else
         go = null_block(a, S, p_done, p_cnt, p_tot);
-    if (go && !a.hash_only) recycle(a);
+    // the hash half of a split launch recycles nothing: its split half did
+    if (go && !a.hash_only && a.phase != kPhaseHash) recycle(a);
 }
 
 // ------------------------------------------------------------ hub buckets
@@ -953,8 +964,9 @@ void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_
 }
 
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
-                      bool stop, bool all_levels, hipStream_t s) {
+                      bool stop, bool all_levels, hipStream_t s, uint32_t phase) {
     IterArgs a{};
+    a.phase = phase;
     a.row_off = g.row_off;
     a.tgt = g.tgt;
     a.lab = g.lab;

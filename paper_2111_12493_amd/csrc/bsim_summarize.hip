@@ -131,13 +131,82 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     bool prev_taken = false;
     std::vector<hipEvent_t> timers;  // (start, after refinement, after hubs) per timed launch
     std::vector<uint32_t> timed_k;   // the launches timed
+    std::vector<uint8_t> timed_split;  // ... and whether each ran as a split launch
     struct TimerGuard {
         std::vector<hipEvent_t>& t;
         ~TimerGuard() {
             for (hipEvent_t e : t) (void)hipEventDestroy(e);
         }
     } timer_guard{timers};
+    // Queue refinement launch kk: fused, or as its split half then its hash half.
+    auto issue = [&](uint32_t kk, bool split_first) {
+        if (sink && !sink->levels.empty()) {
+            // keep every level: iteration kk reads levels[kk-1], writes levels[kk]
+            const uint32_t top = static_cast<uint32_t>(sink->levels.size()) - 1;
+            rb.h[(kk - 1) & 1] = sink->levels[std::min(kk - 1, top)];
+            rb.h[kk & 1] = sink->levels[std::min(kk, top)];
+        }
+        hipEvent_t et[3] = {nullptr, nullptr, nullptr};
+        const bool timed = use_timers && ctx->time_launches && kk % ctx->time_launches == 0;
+        if (timed) {
+            timed_k.push_back(kk);
+            timed_split.push_back(split_first ? 1 : 0);
+            for (hipEvent_t& e : et) {
+                hip_check(hipEventCreate(&e), "event");
+                timers.push_back(e);
+            }
+            hip_check(hipEventRecord(et[0], s), "event");
+        }
+        const bool all = sink && !sink->levels.empty();
+        if (rb.bc.gid) launch_graph_stop(rb, kk, p.k_max, stop, s);
+        if (split_first) {
+            launch_iteration(g, rb, kk, p.k_max, stop, all, s, kPhaseSplit);
+            launch_iteration(g, rb, kk, p.k_max, stop, all, s, kPhaseHash);
+        } else {
+            launch_iteration(g, rb, kk, p.k_max, stop, all, s);
+        }
+        if (rep_prev && kk == p.k_max && g.n) {
+            // launch k splits level k-1 and nothing after it in the launch
+            // changes the classes: rep now names the (k_max-1)-classes, or
+            // the final ones of a run that stopped earlier at a fixpoint
+            hip_check(hipMemcpyAsync(rep_prev, rb.rep, static_cast<size_t>(g.n) * 4, hipMemcpyDeviceToDevice, s),
+                      "previous classes");
+            prev_taken = true;
+        }
+        if (timed) hip_check(hipEventRecord(et[1], s), "event");
+        if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
+        if (timed) hip_check(hipEventRecord(et[2], s), "event");
+        lr.launches++;
+        if (split_first) lr.split_launches++;
+    };
+    // One launch per stop check (launches of milliseconds, or chunk_max 1):
+    // the host waits for every launch anyway, so it reads the founded count
+    // of the level the launch split.  A level that founds few classes is
+    // often the last to change; the next launch then runs its split half
+    // first and hashes only if the run goes on, instead of hashing a level
+    // that the fixpoint test discards (at most kMaxSplitLaunches per run).
+    constexpr uint32_t kMaxSplitLaunches = 8;
+    const bool one_by_one = !rb.bc.gid && stop && ctx->tail_split_ppm && (chunk_cap == 1 || ctx->chunk_max == 1);
     try {
+        if (one_by_one) {
+            bool split_first = false;
+            for (uint64_t kq = 1; kq <= k_last && !done; kq++) {
+                const uint32_t kk = static_cast<uint32_t>(kq);
+                issue(kk, split_first);
+                hip_check(hipMemcpyAsync(&ctx->status_host[0], rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost,
+                                         s), "status copy");
+                // launch kk completed the split of level kk-1 (k_init: level 0)
+                hip_check(hipMemcpyAsync(ctx->count_host, rb.lcnt + ((kk - 1) & (kStripeRing - 1)) * kStripes,
+                                         kStripes * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "count copy");
+                hip_check(hipStreamSynchronize(s), "status wait");
+                done = ctx->status_host[0].done != 0;
+                uint64_t founded = 0;
+                for (int i = 0; i < kStripes; i++) founded += ctx->count_host[i];
+                split_first = lr.split_launches < kMaxSplitLaunches &&
+                              founded * 1000000ull <= static_cast<uint64_t>(ctx->tail_split_ppm) * g.n;
+            }
+            if (!done) throw DeviceError{BSIM_E_DEVICE, "refinement did not reach its stop test"};
+        }
         while (!done) {
             if (k <= k_last) {
                 const uint32_t c = static_cast<uint32_t>(std::min<uint64_t>(chunk, k_last - k + 1));
@@ -154,40 +223,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                     rb.bc.hist = nh;
                     rb.bc.hist_cap = static_cast<uint32_t>(cap);
                 }
-                for (uint32_t i = 0; i < c; i++, k++) {
-                    const uint32_t kk = static_cast<uint32_t>(k);
-                    if (sink && !sink->levels.empty()) {
-                        // keep every level: iteration kk reads levels[kk-1], writes levels[kk]
-                        const uint32_t top = static_cast<uint32_t>(sink->levels.size()) - 1;
-                        rb.h[(kk - 1) & 1] = sink->levels[std::min(kk - 1, top)];
-                        rb.h[kk & 1] = sink->levels[std::min(kk, top)];
-                    }
-                    hipEvent_t et[3] = {nullptr, nullptr, nullptr};
-                    const bool timed = use_timers && ctx->time_launches && kk % ctx->time_launches == 0;
-                    if (timed) {
-                        timed_k.push_back(kk);
-                        for (hipEvent_t& e : et) {
-                            hip_check(hipEventCreate(&e), "event");
-                            timers.push_back(e);
-                        }
-                        hip_check(hipEventRecord(et[0], s), "event");
-                    }
-                    if (rb.bc.gid) launch_graph_stop(rb, kk, p.k_max, stop, s);
-                    launch_iteration(g, rb, kk, p.k_max, stop, sink && !sink->levels.empty(), s);
-                    if (rep_prev && kk == p.k_max && g.n) {
-                        // launch k splits level k-1 and nothing after it in
-                        // the launch changes the classes: rep now names the
-                        // (k_max-1)-classes, or the final ones of a run that
-                        // stopped earlier at a fixpoint
-                        hip_check(hipMemcpyAsync(rep_prev, rb.rep, static_cast<size_t>(g.n) * 4,
-                                                 hipMemcpyDeviceToDevice, s), "previous classes");
-                        prev_taken = true;
-                    }
-                    if (timed) hip_check(hipEventRecord(et[1], s), "event");
-                    if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
-                    if (timed) hip_check(hipEventRecord(et[2], s), "event");
-                    lr.launches++;
-                }
+                for (uint32_t i = 0; i < c; i++, k++) issue(static_cast<uint32_t>(k), false);
                 const int slot = pending < 0 ? 0 : (pending ^ 1);
                 hip_check(hipMemcpyAsync(&ctx->status_host[slot], rb.status, sizeof(RunStatus),
                                          hipMemcpyDeviceToHost, s), "status copy");
@@ -211,10 +247,12 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
     hip_check(hipStreamSynchronize(s), "loop sync");
     RunStatus st;
     hip_check(hipMemcpy(&st, rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost), "final status");
-    // launch j (1-based) did work iff j <= k_done + 1: launch k_done + 2 finds
-    // the stop at level k_done and returns at once, as do all later ones
+    // launch j (1-based) hashed iff j <= k_done + 1: launch k_done + 2 finds
+    // the stop at level k_done and returns at once, as do all later ones; a
+    // split launch k_done + 1 finds it in its hash half and hashes nothing
     for (size_t i = 0; i + 2 < timers.size(); i += 3) {
         if (timed_k[i / 3] > st.k_done + 1) break;
+        if (timed_k[i / 3] == st.k_done + 1 && timed_split[i / 3]) break;
         float a = 0.f, b = 0.f;
         hip_check(hipEventElapsedTime(&a, timers[i], timers[i + 1]), "launch timer");
         hip_check(hipEventElapsedTime(&b, timers[i + 1], timers[i + 2]), "launch timer");
@@ -264,6 +302,7 @@ bsim_result* make_result(bsim_ctx* ctx, const Staged& g, const LoopResult& lr, c
     r->ms_iter_kernels = lr.ms_kernels;
     r->ms_hub_kernels = lr.ms_hub_kernels;
     r->n_timed_launches = lr.n_timed;
+    r->n_split_launches = lr.split_launches;
     r->blocks_per_iter = p->blocks_per_iter.data();
     uint64_t* hashes = hashes_preset ? hashes_preset : keep.alloc<uint64_t>(g.n);
     if (g.n) hip_check(hipMemcpyAsync(hashes, h, static_cast<size_t>(g.n) * 8, hipMemcpyDeviceToDevice, s),
