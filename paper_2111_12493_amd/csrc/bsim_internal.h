@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "bsim.h"
+#include "bsim_host.h"
 
 namespace bsim {
 
@@ -213,11 +214,6 @@ struct HubArgs {
 
 // ------------------------------------------------------------ host helpers
 
-struct DeviceError {
-    int status;
-    std::string msg;
-};
-
 // Test hook for the failure paths: the N-th device allocation from the time
 // it is set fails as if the device were out of memory (process-wide; 0 =
 // off).  Set with the ctx option "fail_alloc_after".
@@ -331,15 +327,6 @@ inline uint64_t table_slots(uint64_t want, uint64_t min_slots, const char* what)
 // Split / class table of a graph with n vertices: at most n joins per level,
 // load <= 2/3.
 inline uint64_t split_table_slots(uint64_t n) { return table_slots(n + n / 2 + 1, 64, "the class table"); }
-
-inline int bit_width(uint64_t x) {
-    int b = 0;
-    while (x) {
-        b++;
-        x >>= 1;
-    }
-    return b;
-}
 
 // ------------------------------------------------------- library internals
 

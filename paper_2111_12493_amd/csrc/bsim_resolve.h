@@ -1,0 +1,285 @@
+// bsim_resolve.h -- host-side resolution of an update batch (Sec. 3.2):
+// the ordered operations of one bsim_apply_updates call become the net
+// change of every touched (u, label, w) triple and the final type set of
+// every touched vertex.  Host code only (no HIP), so it also builds into
+// the CPU tests, under the address and undefined-behaviour sanitizers.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "bsim.h"
+#include "bsim_host.h"
+
+namespace bsim {
+
+constexpr uint32_t kChgDeleted = 1u;  // change flags: the triple's old copies go
+constexpr uint32_t kChgPresent = 2u;  // ... and it exists after the batch
+constexpr uint32_t kMaxStateTypes = 4096;
+
+// Net effect of one update batch, resolved on the host.
+struct HostBatch {
+    uint32_t n_new = 0;
+    std::vector<uint32_t> cu, cw, cl, cf;      // changed triples, sorted by (u, w, l)
+    std::vector<uint32_t> gsrc, gbeg, gend;    // change range of every source
+    std::vector<uint32_t> rw, ru;              // reverse-list additions, sorted by (w, u)
+    std::vector<uint32_t> rgw, rgbeg, rgend;
+    std::vector<uint32_t> tl, tl_off, tl_ids;  // vertices with a new type set (sorted) and the sets
+    std::vector<uint32_t> dead;                // vertices deleted by the batch
+    uint32_t max_label = 0;
+    uint64_t n_present = 0;                    // changes that end present (upper bound of appends)
+};
+
+// Per-vertex marks of the resolution, kept between calls so a batch costs
+// O(batch) rather than O(n): vmark[v] = 0 untouched, 1 alive with a vertex
+// op, 2 deleted; vtype[v] = 1 + index of v's new type list (0: none).
+struct ResolveScratch {
+    std::vector<uint8_t> vmark;
+    std::vector<uint32_t> vtype;
+};
+
+// Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
+inline void host_radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int bits) {
+    constexpr int kDigit = 11;
+    constexpr uint32_t kBuckets = 1u << kDigit;
+    const size_t n = key.size();
+    std::vector<uint64_t> k2(n);
+    std::vector<uint32_t> v2(n);
+    std::vector<uint32_t> cnt(kBuckets);
+    for (int sh = 0; sh < bits; sh += kDigit) {
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (size_t i = 0; i < n; i++) cnt[(key[i] >> sh) & (kBuckets - 1)]++;
+        uint32_t run = 0;
+        for (uint32_t& c : cnt) {
+            const uint32_t t = c;
+            c = run;
+            run += t;
+        }
+        for (size_t i = 0; i < n; i++) {
+            const uint32_t p = cnt[(key[i] >> sh) & (kBuckets - 1)]++;
+            k2[p] = key[i];
+            v2[p] = val[i];
+        }
+        key.swap(k2);
+        val.swap(v2);
+    }
+}
+
+// The batch's net effect, by the sequential semantics of the operations:
+// every (u, l, w) the batch touches ends deleted and/or present, every
+// touched vertex ends alive with a type set or deleted.  n0 is the state's
+// vertex count, alive its alive mask (n0 entries), label_bytes its label
+// width.  Per-vertex marks live in the caller's scratch (all zero on entry
+// and again on every return or throw), and the edge records are radix
+// sorted, so a batch of 10^6 operations resolves in tens of milliseconds.
+// Throws DeviceError for an invalid batch (out-of-range ids or labels,
+// deleted vertices named, too many types, unknown op codes).
+inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vector<uint8_t>& alive,
+                             ResolveScratch& rs, const bsim_update* ops, uint64_t n_ops) {
+    HostBatch hb;
+    uint32_t n_cur = n0;
+    std::vector<uint8_t>& vmark = rs.vmark;
+    std::vector<uint32_t>& vtype = rs.vtype;
+    std::vector<uint32_t> touched;   // vertices with a vertex op, first touch order
+    std::vector<uint32_t> ty_pool;   // type lists of the vertex ops
+    std::vector<std::pair<uint32_t, uint32_t>> ty_rec;  // (offset, count) in ty_pool
+    auto grow = [&](uint32_t need) {
+        if (vmark.size() < need) {
+            vmark.resize(std::max<size_t>(need, vmark.size() + vmark.size() / 4), 0);
+            vtype.resize(vmark.size(), 0);
+        }
+    };
+    grow(n_cur);
+    auto alive_now = [&](uint32_t v) -> bool {
+        const uint8_t m = vmark[v];
+        return m ? m == 1 : alive[v] != 0;
+    };
+    struct Rec {
+        uint32_t u, w, l, add;
+    };
+    std::vector<Rec> recs;
+    recs.reserve(n_ops + n_ops / 8);
+    const uint64_t lab_lim = label_bytes == 2 ? (1ull << 16) : (1ull << 24);
+    uint32_t max_l = 0;
+    auto touch = [&](uint32_t v, uint8_t state) {
+        if (!vmark[v]) touched.push_back(v);
+        vmark[v] = state;
+    };
+    auto set_types = [&](uint32_t v, const bsim_update& o) {
+        ty_rec.emplace_back(static_cast<uint32_t>(ty_pool.size()), o.n_types);
+        ty_pool.insert(ty_pool.end(), o.types, o.types + o.n_types);
+        vtype[v] = static_cast<uint32_t>(ty_rec.size());
+    };
+    // the marks of the touched vertices are cleared on every way out,
+    // including a throw, so the next call starts from clean scratch
+    struct ClearMarks {
+        std::vector<uint32_t>& touched;
+        std::vector<uint8_t>& vmark;
+        std::vector<uint32_t>& vtype;
+        ~ClearMarks() {
+            for (uint32_t v : touched) vmark[v] = 0, vtype[v] = 0;
+        }
+    } clear_marks{touched, vmark, vtype};
+    {
+        for (uint64_t i = 0; i < n_ops; i++) {
+            const bsim_update& o = ops[i];
+            const bool edge = o.op == BSIM_OP_ADD_E || o.op == BSIM_OP_DEL_E || o.op == BSIM_OP_MOD_E;
+            // checks in the order: ids in range, ids alive, types, labels
+            if (o.op == BSIM_OP_MOD_V || o.op == BSIM_OP_DEL_V || edge) {
+                if (o.u >= n_cur || (edge && o.w >= n_cur))
+                    throw DeviceError{BSIM_E_RANGE, "vertex id out of range in update"};
+                if (!alive_now(o.u) || (edge && !alive_now(o.w)))
+                    throw DeviceError{BSIM_E_INVALID, "update names a deleted vertex"};
+            }
+            if (o.op == BSIM_OP_ADD_V || o.op == BSIM_OP_MOD_V) {
+                if (o.n_types > kMaxStateTypes) throw DeviceError{BSIM_E_UNSUPPORTED, "more than 4096 types on a vertex"};
+                if (o.n_types && !o.types) throw DeviceError{BSIM_E_INVALID, "types pointer is NULL"};
+            }
+            switch (o.op) {
+                case BSIM_OP_ADD_V: {
+                    if (n_cur >= 0xFFFFFFF0u) throw DeviceError{BSIM_E_UNSUPPORTED, "too many vertices"};
+                    const uint32_t v = n_cur++;
+                    grow(n_cur);
+                    touch(v, 1);
+                    set_types(v, o);
+                    break;
+                }
+                case BSIM_OP_MOD_V:
+                    touch(o.u, 1);
+                    set_types(o.u, o);
+                    break;
+                case BSIM_OP_DEL_V:
+                    touch(o.u, 2);
+                    vtype[o.u] = 0;
+                    break;
+                case BSIM_OP_ADD_E:
+                case BSIM_OP_DEL_E:
+                case BSIM_OP_MOD_E:
+                    if (o.label >= lab_lim || (o.op == BSIM_OP_MOD_E && o.new_label >= lab_lim))
+                        throw DeviceError{BSIM_E_RANGE, "edge label out of range in update"};
+                    if (o.op == BSIM_OP_ADD_E) {
+                        recs.push_back({o.u, o.w, o.label, 1});
+                        max_l = std::max(max_l, o.label);
+                    } else {
+                        recs.push_back({o.u, o.w, o.label, 0});
+                        max_l = std::max(max_l, o.label);
+                        if (o.op == BSIM_OP_MOD_E) {
+                            recs.push_back({o.u, o.w, o.new_label, 1});
+                            max_l = std::max(max_l, o.new_label);
+                        }
+                    }
+                    break;
+                default:
+                    throw DeviceError{BSIM_E_INVALID, "unknown update op code"};
+            }
+        }
+    }
+    hb.n_new = n_cur;
+    hb.tl = touched;
+    std::sort(hb.tl.begin(), hb.tl.end());
+    hb.tl_off.reserve(hb.tl.size() + 1);
+    hb.tl_off.push_back(0);
+    for (uint32_t v : hb.tl) {
+        if (vmark[v] == 2) {
+            hb.dead.push_back(v);
+        } else if (vtype[v]) {
+            const auto& r = ty_rec[vtype[v] - 1];
+            hb.tl_ids.insert(hb.tl_ids.end(), ty_pool.begin() + r.first, ty_pool.begin() + r.first + r.second);
+        }
+        hb.tl_off.push_back(static_cast<uint32_t>(hb.tl_ids.size()));
+    }
+    auto dead_at_end = [&](uint32_t v) { return vmark[v] == 2; };
+    // edge records in (u, w, l) order, input order within equal triples:
+    // the triple packed in one key when it fits 64 bits (the add flag rides
+    // in the value), else a comparison sort
+    const int bv = std::max(1, bit_width(n_cur)), bl = std::max(1, bit_width(max_l + 1));
+    const size_t nr = recs.size();
+    std::vector<uint64_t> key;
+    std::vector<uint32_t> val(nr);
+    auto emit = [&](uint32_t u, uint32_t w, uint32_t l, bool deleted, bool add) {
+        if (dead_at_end(u) || dead_at_end(w)) return;
+        hb.cu.push_back(u);
+        hb.cw.push_back(w);
+        hb.cl.push_back(l);
+        hb.cf.push_back((deleted ? kChgDeleted : 0u) | (add ? kChgPresent : 0u));
+        if (add) {
+            hb.n_present++;
+            hb.max_label = std::max(hb.max_label, l);
+            hb.rw.push_back(w);
+            hb.ru.push_back(u);
+        }
+    };
+    hb.cu.reserve(nr);
+    hb.cw.reserve(nr);
+    hb.cl.reserve(nr);
+    hb.cf.reserve(nr);
+    if (2 * bv + bl <= 64) {
+        key.resize(nr);
+        for (size_t i = 0; i < nr; i++) {
+            key[i] = (static_cast<uint64_t>(recs[i].u) << (bv + bl)) | (static_cast<uint64_t>(recs[i].w) << bl) |
+                     recs[i].l;
+            val[i] = recs[i].add;
+        }
+        host_radix_sort(key, val, 2 * bv + bl);
+        const uint64_t lmask = (1ull << bl) - 1, wmask = (1ull << bv) - 1;
+        for (size_t i = 0; i < nr;) {
+            size_t j = i;
+            bool deleted = false;
+            while (j < nr && key[j] == key[i]) deleted |= val[j++] == 0;
+            emit(static_cast<uint32_t>(key[i] >> (bv + bl)), static_cast<uint32_t>((key[i] >> bl) & wmask),
+                 static_cast<uint32_t>(key[i] & lmask), deleted, val[j - 1] != 0);
+            i = j;
+        }
+    } else {
+        for (size_t i = 0; i < nr; i++) val[i] = static_cast<uint32_t>(i);
+        std::stable_sort(val.begin(), val.end(), [&](uint32_t a, uint32_t b) {
+            const Rec &x = recs[a], &y = recs[b];
+            if (x.u != y.u) return x.u < y.u;
+            if (x.w != y.w) return x.w < y.w;
+            return x.l < y.l;
+        });
+        for (size_t i = 0; i < nr;) {
+            const Rec& first = recs[val[i]];
+            size_t j = i;
+            bool deleted = false;
+            while (j < nr && recs[val[j]].u == first.u && recs[val[j]].w == first.w && recs[val[j]].l == first.l)
+                deleted |= recs[val[j++]].add == 0;
+            emit(first.u, first.w, first.l, deleted, recs[val[j - 1]].add != 0);
+            i = j;
+        }
+    }
+    for (size_t i = 0; i < hb.cu.size();) {
+        size_t j = i;
+        while (j < hb.cu.size() && hb.cu[j] == hb.cu[i]) j++;
+        hb.gsrc.push_back(hb.cu[i]);
+        hb.gbeg.push_back(static_cast<uint32_t>(i));
+        hb.gend.push_back(static_cast<uint32_t>(j));
+        i = j;
+    }
+    // reverse additions, grouped by target (duplicate pairs are harmless)
+    std::vector<uint64_t> rk(hb.rw.size());
+    std::vector<uint32_t> rdummy(hb.rw.size(), 0);
+    for (size_t i = 0; i < rk.size(); i++) rk[i] = (static_cast<uint64_t>(hb.rw[i]) << bv) | hb.ru[i];
+    host_radix_sort(rk, rdummy, 2 * bv);
+    rk.erase(std::unique(rk.begin(), rk.end()), rk.end());
+    hb.rw.resize(rk.size());
+    hb.ru.resize(rk.size());
+    const uint64_t umask = (1ull << bv) - 1;
+    for (size_t i = 0; i < rk.size(); i++) {
+        hb.rw[i] = static_cast<uint32_t>(rk[i] >> bv);
+        hb.ru[i] = static_cast<uint32_t>(rk[i] & umask);
+    }
+    for (size_t i = 0; i < hb.rw.size();) {
+        size_t j = i;
+        while (j < hb.rw.size() && hb.rw[j] == hb.rw[i]) j++;
+        hb.rgw.push_back(hb.rw[i]);
+        hb.rgbeg.push_back(static_cast<uint32_t>(i));
+        hb.rgend.push_back(static_cast<uint32_t>(j));
+        i = j;
+    }
+    return hb;
+}
+
+}  // namespace bsim
