@@ -9,7 +9,11 @@ aborts the run) and run on seeded random inputs:
   - tests/native/resolve_check.cpp drives the host-side resolution of
     update batches (csrc/bsim_resolve.h, the same header the library
     compiles) against a plain sequential model of the operations, valid
-    and invalid batches alike.
+    and invalid batches alike;
+  - tests/native/sched_check.cpp drives the serving loop's scheduler
+    (csrc/bsim_sched.h) from submitter, worker and poller threads with a
+    fake executor, built once with the thread sanitizer and once with the
+    address and undefined-behaviour sanitizers.
 No GPU is involved."""
 
 import os
@@ -22,26 +26,28 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAN = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
 
 
-def _build(compiler, std, sources, exe_name):
+def _build(compiler, std, sources, exe_name, san=None):
     if shutil.which(compiler) is None:
         pytest.skip(compiler + " not found")
     out_dir = os.path.join(ROOT, "_build")
     os.makedirs(out_dir, exist_ok=True)
     exe = os.path.join(out_dir, exe_name)
-    cmd = [compiler, std, "-Wall", "-Wextra"] + SAN + [
+    cmd = [compiler, std, "-Wall", "-Wextra"] + (san or SAN) + [
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2111_12493_amd", "csrc")] + [
-        os.path.join(ROOT, s) for s in sources] + ["-o", exe]
+        os.path.join(ROOT, s) for s in sources] + ["-o", exe, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     return exe
 
 
 def _run(exe, seed):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1",
+               TSAN_OPTIONS="halt_on_error=1:second_deadlock_stack=1")
     r = subprocess.run([exe, str(seed)], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert r.stdout.strip().startswith("ok "), r.stdout
     assert "runtime error" not in r.stderr, r.stderr[-4000:]
+    assert "WARNING: ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     return int(r.stdout.split()[1])
 
 
@@ -63,3 +69,16 @@ def test_oracle_under_sanitizers(oracle_exe, seed):
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_update_resolution_under_sanitizers(resolve_exe, seed):
     assert _run(resolve_exe, seed) > 400
+
+
+@pytest.fixture(scope="module")
+def sched_exes():
+    src = ["tests/native/sched_check.cpp"]
+    return [_build("g++", "-std=c++17", src, "sched_check_tsan", ["-O1", "-g", "-fsanitize=thread"]),
+            _build("g++", "-std=c++17", src, "sched_check_asan")]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_scheduler_under_sanitizers(sched_exes, seed):
+    for exe in sched_exes:
+        assert _run(exe, seed) > 1000
