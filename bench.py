@@ -228,25 +228,26 @@ def serving_leg(args, binding, gg, torch, g, dbase):
             "points": points}
 
 
-def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoints=True):
-    """Update-batch latency on a resident graph (k = 4): the incremental form
-    (frontier re-hash, full levels once a frontier exceeds the limit) beside
-    the plain form (every level recomputed for all vertices) on the same
-    batches, each on its own copy of the state."""
+def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoints=True, k=4):
+    """Update-batch latency on a resident graph (levels 0..k): the
+    incremental form (frontier re-hash, full levels once a frontier exceeds
+    the limit, class index updated for the re-keyed vertices) beside the
+    plain form (every level recomputed and its classes rebuilt for all
+    vertices) on the same batches, each on its own copy of the state."""
     import numpy as np
 
     workload = workload or args.inc_workload
-    print("# incremental: %s, %d vertices, %d edges" % (workload, g.n, g.m), file=sys.stderr, flush=True)
+    print("# incremental: %s, k=%d, %d vertices, %d edges" % (workload, k, g.n, g.m), file=sys.stderr, flush=True)
     ctx_i, ctx_p = binding.Context(0), binding.Context(0)
     ctx_p.set_option("frontier_limit_pct", 0)
     t0 = time.perf_counter()
-    st_i = binding.State(ctx_i, dg, 4, stop_at_fixpoint=False, summary_edges=False)
+    st_i = binding.State(ctx_i, dg, k, stop_at_fixpoint=False, summary_edges=False)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
-    st_p = binding.State(ctx_p, dg, 4, stop_at_fixpoint=False, summary_edges=False)
+    st_p = binding.State(ctx_p, dg, k, stop_at_fixpoint=False, summary_edges=False)
     st_i.result.free()
     st_p.result.free()
-    rng = np.random.default_rng(17)
+    rng = np.random.default_rng(17)  # the same batches for every k
     dead = np.zeros(g.n + 4_000_000, dtype=bool)
     if g.alive is not None:
         dead[:g.n] = g.alive == 0
@@ -271,8 +272,8 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
             raise RuntimeError("incremental and full recomputation disagree on batch %d" % i)
         ops_total += size
         sizes.append(size)
-        print("# update batch %d: %d ops, incremental %.2f ms, full recomputation %.2f ms"
-              % (i, size, lat_i[-1], lat_p[-1]), file=sys.stderr, flush=True)
+        print("# update batch %d (k=%d): %d ops, incremental %.2f ms, full recomputation %.2f ms"
+              % (i, k, size, lat_i[-1], lat_p[-1]), file=sys.stderr, flush=True)
 
     # change detection: the ordered batch between the first snapshot and
     # the state's graph after all batches, from the two device CSRs
@@ -294,9 +295,10 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
     if small:
         by_size["p50_ms"] = percentile([lat_i[i] for i in small], 0.5)
         by_size["plain_p50_ms"] = percentile([lat_p[i] for i in small], 0.5)
-    return {"workload": "%s resident, k=4, update batches of log-uniform 10^3-%.0e ops (ADD/MOD/DEL 60/25/15, "
-                        "%s endpoints for new edges)" % (workload, args.inc_max_ops,
+    return {"workload": "%s resident, k=%d, update batches of log-uniform 10^3-%.0e ops (ADD/MOD/DEL 60/25/15, "
+                        "%s endpoints for new edges)" % (workload, k, args.inc_max_ops,
                                                          "R-MAT" if rmat_endpoints else "uniform"),
+            "k": k,
             "batches": len(lat_i), "ops": ops_total, "p50_ms": p50, "p99_ms": p99,
             "plain_p50_ms": q50, "plain_p99_ms": q99, "speedup_p50": q50 / p50, "speedup_p99": q99 / p99,
             "small_batches": by_size, "state_create_s": create_s, "summary_edges": False,
@@ -514,6 +516,8 @@ def main() -> int:
     ap.add_argument("--inc-uniform", default="uniform24",
                     help="second incremental workload (a uniform graph); empty to skip")
     ap.add_argument("--inc-max-ops", type=float, default=1e6)
+    ap.add_argument("--inc-k", type=int, nargs="+", default=[4, 2, 1],
+                    help="levels of the resident states (the first is the main line's)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9])
@@ -616,7 +620,9 @@ def main() -> int:
             g24 = gg.make_config(args.inc_workload)
             dg24 = binding.DeviceGraph(g24)
         if not args.no_incremental:
-            out["incremental"] = incremental_leg(args, binding, gg, torch, g24, dg24)
+            for i, k in enumerate(args.inc_k):
+                key = "incremental" if i == 0 else "incremental_k%d" % k
+                out[key] = incremental_leg(args, binding, gg, torch, g24, dg24, k=k)
         if not args.no_serving:
             out["serving"] = serving_leg(args, binding, gg, torch, g24, dg24)
         del g24, dg24
@@ -626,8 +632,10 @@ def main() -> int:
         # the same batches on a graph without hubs, where a change stays local
         dgu = devgen.make_device_config(args.inc_uniform)
         gu = dgu.to_host()
-        out["incremental_uniform"] = incremental_leg(args, binding, gg, torch, gu, dgu, workload=args.inc_uniform,
-                                                     rmat_endpoints=False)
+        for i, k in enumerate(args.inc_k):
+            key = "incremental_uniform" if i == 0 else "incremental_uniform_k%d" % k
+            out[key] = incremental_leg(args, binding, gg, torch, gu, dgu, workload=args.inc_uniform,
+                                       rmat_endpoints=False, k=k)
         del gu, dgu
     if not args.no_batched:
         out["batched"] = batched_leg(args, binding, gg, torch)

@@ -286,14 +286,16 @@ namespace {
 // First-occurrence block ids of the classes named by `rep` into ids[n], the
 // block sizes into a new array of `sizes_arena`; returns the block count.
 uint32_t number_blocks(const Staged& g, const uint32_t* rep, uint32_t* ids, uint32_t** sizes_out, Arena& arena,
-                       Arena& sizes_arena, hipStream_t s, uint32_t* sizes_preset = nullptr) {
+                       Arena& sizes_arena, hipStream_t s, uint32_t* sizes_preset = nullptr, uint64_t n_ids = 0) {
     const uint32_t n = g.n;
-    uint32_t* cmin = arena.alloc<uint32_t>(n + 1);
+    // class names are vertex ids, or below n_ids when given
+    const uint64_t ids_cap = std::max<uint64_t>(n, n_ids);
+    uint32_t* cmin = arena.alloc<uint32_t>(ids_cap + 1);
     uint32_t* isrep = arena.alloc<uint32_t>(n);
     uint32_t* rank = arena.alloc<uint32_t>(n);
     uint32_t* total = arena.alloc<uint32_t>(1);
     const uint32_t gb = std::max<uint32_t>(ceil_div(n, kBlock), 1);
-    hip_check(hipMemsetAsync(cmin, 0xFF, (static_cast<size_t>(n) + 1) * 4, s), "class minima");
+    hip_check(hipMemsetAsync(cmin, 0xFF, (ids_cap + 1) * 4, s), "class minima");
     if (n) {
         k_fin_min<<<gb, kBlock, 0, s>>>(rep, g.alive, n, cmin);
         k_fin_rep<<<gb, kBlock, 0, s>>>(rep, g.alive, n, cmin, isrep);
@@ -311,11 +313,11 @@ uint32_t number_blocks(const Staged& g, const uint32_t* rep, uint32_t* ids, uint
 }
 
 void finalize_impl(const Staged& g, const uint32_t* rep, const uint32_t* rep_prev, bool want_edges,
-                   FinalOut& out, Arena& arena, Arena& keep, hipStream_t s) {
+                   FinalOut& out, Arena& arena, Arena& keep, hipStream_t s, uint64_t n_ids = 0) {
     const uint32_t n = g.n;
     if (!out.preset) out.block_ids = keep.alloc<uint32_t>(n);
     const uint32_t nb = number_blocks(g, rep, out.block_ids, &out.block_sizes, arena, keep, s,
-                                      out.preset ? out.block_sizes : nullptr);
+                                      out.preset ? out.block_sizes : nullptr, n_ids);
     out.n_blocks = nb;
     // the target end of a summary edge: the final blocks, or the blocks of
     // the previous level's classes
@@ -392,8 +394,8 @@ void finalize_impl(const Staged& g, const uint32_t* rep, const uint32_t* rep_pre
 }  // namespace
 
 void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& out, Arena& arena,
-              Arena& keep, hipStream_t s) {
-    finalize_impl(g, rep, nullptr, want_edges, out, arena, keep, s);
+              Arena& keep, hipStream_t s, uint64_t n_ids) {
+    finalize_impl(g, rep, nullptr, want_edges, out, arena, keep, s, n_ids);
 }
 
 void finalize_prev_level(const Staged& g, const uint32_t* rep, const uint32_t* rep_prev, bool want_edges,

@@ -712,12 +712,19 @@ struct bsim_state {
     DevBuf<uint8_t> alive;
     std::vector<DevBuf<uint64_t>> levels;
     DevBuf<uint64_t> salt;
-    DevBuf<uint32_t> rep, dflag, bmark, fmark, chg_lo, chg_hi, tidx, kept, deg, blist, flist[2], cflag;
+    DevBuf<uint32_t> dflag, bmark, fmark, chg_lo, chg_hi, tidx, kept, deg, blist, flist[2], cflag;
     uint32_t tag_base = 0;  // change / frontier tags of the next batch start above this
-    uint64_t* cls_slots = nullptr;
-    uint32_t* cls_list = nullptr;
-    uint64_t cls_cap = 0;  // power of two, at most kMaxTableSlots
-    DevBuf<uint32_t> cls_cnt, kpos, chunk_owner, big_done;
+    // class index (bsim_cindex.hip), one per level: tables of ci_cap slots,
+    // the class slot of every vertex; per level the counters (classes,
+    // claimed slots); the vertex list of an update and the lists of the
+    // vertices whose class changed (by level parity), with their counts
+    std::vector<DevBuf<uint64_t>> ci_word, ci_keyh;
+    std::vector<DevBuf<uint32_t>> ci_cnt, ci_cid;
+    uint64_t ci_cap = 0;
+    DevBuf<uint64_t> ci_ctr;
+    DevBuf<uint32_t> ci_dmark, ci_d, ci_q[2], ci_n;  // ci_n: lengths of ci_d, ci_q[0], ci_q[1]
+    uint32_t ci_rebuild_from = 0;  // levels from this one on are rebuilt at the next update (> K: none)
+    DevBuf<uint32_t> kpos, chunk_owner, big_done;
     DevBuf<BigEntry> big;
     DevBuf<uint64_t> big_acc, scratch;
     DevBuf<IncCounters> cnt;
@@ -728,11 +735,10 @@ struct bsim_state {
     // touched vertex's state after the batch so far (1 alive, 2 deleted) and
     // 1 + the index of its latest type list
     ResolveScratch rs;  // per-vertex marks of the op resolution
-    // the class passes of the stored levels run on a second stream, each
-    // after an event that follows the launches writing its level
+    // class-index rebuilds run on a second stream, each after an event that
+    // follows the launches writing its level, so they overlap the next levels
     hipStream_t s2 = nullptr;
     hipEvent_t ev_level = nullptr, ev_classes = nullptr;
-    uint32_t cls_next = 0;  // the next level whose class pass is due
     // backing of an update's temporary arrays, grown to the largest demand
     // seen: large temporaries then never pass through the stream-ordered
     // pool, which can return freed memory to the driver (tens of ms) and map
@@ -750,14 +756,17 @@ struct bsim_state {
         }
         alive.release(s);
         for (auto& l : levels) l.release(s);
-        salt.release(s), rep.release(s), dflag.release(s), bmark.release(s), fmark.release(s), cflag.release(s);
+        salt.release(s), dflag.release(s), bmark.release(s), fmark.release(s), cflag.release(s);
         chg_lo.release(s), chg_hi.release(s), tidx.release(s), kept.release(s), deg.release(s);
-        blist.release(s), cls_cnt.release(s), kpos.release(s), chunk_owner.release(s);
+        blist.release(s), kpos.release(s), chunk_owner.release(s);
         big_done.release(s), big.release(s), big_acc.release(s), scratch.release(s), cnt.release(s);
         status.release(s), work.release(s);
-        if (cls_slots) (void)hipFreeAsync(cls_slots, s);
-        if (cls_list) (void)hipFreeAsync(cls_list, s);
-        cls_slots = nullptr, cls_list = nullptr;
+        for (auto& b : ci_word) b.release(s);
+        for (auto& b : ci_keyh) b.release(s);
+        for (auto& b : ci_cnt) b.release(s);
+        for (auto& b : ci_cid) b.release(s);
+        ci_ctr.release(s), ci_dmark.release(s), ci_d.release(s), ci_q[0].release(s), ci_q[1].release(s);
+        ci_n.release(s);
         (void)hipStreamSynchronize(s);
         if (ev_level) (void)hipEventDestroy(ev_level);
         if (ev_classes) (void)hipEventDestroy(ev_classes);
@@ -789,22 +798,34 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
     st->tidx.ensure(nv, keep_v, s);
     st->fmark.ensure(nv, keep_v, s);
     st->cflag.ensure(nv, keep_v, s);
-    for (DevBuf<uint32_t>* b : {&st->rep, &st->dflag, &st->bmark, &st->kept, &st->deg, &st->blist,
-                                &st->flist[0], &st->flist[1], &st->big_done, &st->chunk_owner})
+    for (DevBuf<uint32_t>* b : {&st->dflag, &st->bmark, &st->kept, &st->deg, &st->blist, &st->flist[0],
+                                &st->flist[1], &st->big_done, &st->chunk_owner})
         b->ensure(nv, 0, s);
     st->big.ensure(nv, 0, s);
     st->big_acc.ensure(nv, 0, s);
-    // at most n joins per level: load <= 2/3, and a table small enough to
-    // stay mostly in the last-level cache for the class passes' random CAS
-    const uint64_t want = table_slots(static_cast<uint64_t>(n_new) + n_new / 2 + 1, 1024, "the class table");
-    if (want > st->cls_cap) {
-        if (st->cls_slots) (void)hipFreeAsync(st->cls_slots, s);
-        if (st->cls_list) (void)hipFreeAsync(st->cls_list, s);
-        st->cls_slots = nullptr, st->cls_list = nullptr;
-        hip_check(device_alloc(reinterpret_cast<void**>(&st->cls_slots), sizeof(uint64_t) * want, s), "class table");
-        hip_check(device_alloc(reinterpret_cast<void**>(&st->cls_list), 4ull * want, s), "class list");
-        hip_check(hipMemsetAsync(st->cls_slots, 0, sizeof(uint64_t) * want, s), "class table clear");
-        st->cls_cap = want;
+    // class index: the new vertices have no class and no list mark yet
+    const size_t L = static_cast<size_t>(st->K) + 1;
+    st->ci_word.resize(L), st->ci_keyh.resize(L), st->ci_cnt.resize(L), st->ci_cid.resize(L);
+    for (auto& c : st->ci_cid) {
+        c.ensure(nv, keep_v, s);
+        hip_check(hipMemsetAsync(c.p + keep_v, 0xFF, (nv - keep_v) * 4, s), "new classes");
+    }
+    st->ci_dmark.ensure(nv, keep_v, s);
+    hip_check(hipMemsetAsync(st->ci_dmark.p + keep_v, 0, (nv - keep_v) * 4, s), "new list marks");
+    for (DevBuf<uint32_t>* b : {&st->ci_d, &st->ci_q[0], &st->ci_q[1]}) b->ensure(nv, 0, s);
+    st->ci_n.ensure(4, 0, s);
+    st->ci_ctr.ensure(2 * L, 2 * L, s);
+    // a table holds the classes of n vertices at load <= 2/3 and the slots
+    // that later batches claim; a larger one starts over
+    const uint64_t want = split_table_slots(static_cast<uint64_t>(n_new));
+    if (want > st->ci_cap) {
+        for (size_t j = 0; j < L; j++) {
+            st->ci_word[j].ensure(want, 0, s);
+            st->ci_keyh[j].ensure(want, 0, s);
+            st->ci_cnt[j].ensure(want, 0, s);
+        }
+        st->ci_cap = want;
+        st->ci_rebuild_from = 0;
     }
 }
 
@@ -982,51 +1003,74 @@ void merge_reverse(bsim_state* st, const HostBatch& hb, Arena& arena) {
 }
 
 // The class passes of an update, level by level as the levels become final.
-// Level j's pass (its split of the level j-1 classes by h^j, into st->rep)
-// runs on the second stream once the launches that write h^j, enqueued on
-// the state's stream before the call, are done; so it overlaps the launches
-// of the levels after it.  classes_end joins the streams and returns the
-// founded count per level.
-void classes_begin(bsim_state* st) {
-    st->cls_cnt.ensure(2ull * (st->K + 1), 0, st->s);
-    hip_check(hipMemsetAsync(st->cls_cnt.p, 0, 8ull * (st->K + 1), st->s), "class counts");
-    st->cls_next = 0;
+CiLevel ci_level(bsim_state* st, uint32_t j) {
+    CiLevel L;
+    L.word = st->ci_word[j].p;
+    L.key_h = st->ci_keyh[j].p;
+    L.cnt = st->ci_cnt[j].p;
+    L.cid = st->ci_cid[j].p;
+    L.mask = static_cast<uint32_t>(st->ci_cap - 1);
+    return L;
 }
 
-SplitTable class_table(const bsim_state* st) {
-    SplitTable T;
-    T.slots = st->cls_slots;
-    T.list = st->cls_list;
-    T.mask = static_cast<uint32_t>(st->cls_cap - 1);
-    return T;
-}
-
-void classes_level(bsim_state* st, uint32_t j) {
-    if (j != st->cls_next || j > st->K) throw DeviceError{BSIM_E_DEVICE, "internal: class passes out of order"};
+// Level j's class index from scratch, on the second stream once the
+// launches that write h^j (queued on the state's stream) are done, so it
+// overlaps the later levels' launches.  Every later level is rebuilt too:
+// the class slots of level j are new.
+void index_rebuild(bsim_state* st, uint32_t j) {
+    st->ci_rebuild_from = std::min(st->ci_rebuild_from, j);
     hip_check(hipEventRecord(st->ev_level, st->s), "level event");
     hip_check(hipStreamWaitEvent(st->s2, st->ev_level, 0), "level wait");
-    const SplitTable T = class_table(st);
-    launch_level_classes(st->levels[j].p, st->rep.p, st->alive.p, st->n, j, T, st->cls_cnt.p + 2 * j,
-                         st->cls_cnt.p + 2 * j + 1, st->s2);
-    launch_level_clear(T, st->cls_cnt.p + 2 * j + 1, st->s2);
-    st->cls_next = j + 1;
+    ci_rebuild(ci_level(st, j), st->ci_cap, j ? st->ci_cid[j - 1].p : nullptr, st->levels[j].p, st->alive.p, st->n,
+               st->ci_ctr.p + 2 * j, st->s2);
 }
 
-std::vector<uint32_t> read_class_counts(bsim_state* st, uint32_t upto) {
+// Level j's class index once h^j is final: rebuilt (from ci_rebuild_from
+// on), else updated for the vertices whose h^j changed (candidates of list
+// a with flag[v] == tag, or all of a when flag is null) or whose level j-1
+// class changed (list b).  The vertices whose level-j class changes are
+// listed for level j+1.
+void index_level(bsim_state* st, uint32_t j, const uint32_t* a, uint32_t na, const uint32_t* na_dev,
+                 const uint32_t* flag, uint32_t tag, const uint32_t* b, uint32_t nb, const uint32_t* nb_dev,
+                 Arena& arena) {
+    if (j >= st->ci_rebuild_from) {
+        index_rebuild(st, j);
+        return;
+    }
     hipStream_t s = st->s;
-    std::vector<uint32_t> c(2ull * (upto + 1));
-    hip_check(hipMemcpyAsync(c.data(), st->cls_cnt.p, c.size() * 4, hipMemcpyDeviceToHost, s), "class counts");
-    hip_check(hipStreamSynchronize(s), "class sync");
-    std::vector<uint32_t> founded(upto + 1);
-    for (uint32_t j = 0; j <= upto; j++) founded[j] = c[2 * j];
-    return founded;
+    uint32_t* counts = st->ci_n.p;  // [0] the update's list, [1 + parity] the moved lists, [3] errors
+    ci_list(a, na, na_dev, flag, tag, b, nb, nb_dev, st->ci_dmark.p, tag, st->ci_d.p, counts, kFrontGrid, s);
+    uint32_t* hw = st->ctx->count_host;
+    uint64_t used = 0;
+    hip_check(hipMemcpyAsync(hw, counts, 4, hipMemcpyDeviceToHost, s), "class list length");
+    hip_check(hipMemcpyAsync(&used, st->ci_ctr.p + 2 * j + 1, 8, hipMemcpyDeviceToHost, s), "claimed slots");
+    hip_check(hipStreamSynchronize(s), "class list sync");
+    const uint32_t nd = *hw;
+    // each listed vertex may claim one slot: past 85 % of the table, start over
+    if ((used + nd) * 20 > st->ci_cap * 17) {
+        index_rebuild(st, j);
+        return;
+    }
+    ci_update(ci_level(st, j), j ? st->ci_cid[j - 1].p : nullptr, st->levels[j].p, st->alive.p, st->ci_d.p, nd,
+              st->ci_ctr.p + 2 * j, st->ci_q[j & 1].p, counts + 1 + (j & 1), counts + 3, hw, arena, s);
 }
 
-std::vector<uint32_t> classes_end(bsim_state* st) {
-    if (st->cls_next != st->K + 1) throw DeviceError{BSIM_E_DEVICE, "internal: a level's class pass is missing"};
+// After the last level: join the rebuild stream; per level the classes and
+// the claimed slots.
+std::vector<uint64_t> index_end(bsim_state* st) {
     hip_check(hipEventRecord(st->ev_classes, st->s2), "classes event");
     hip_check(hipStreamWaitEvent(st->s, st->ev_classes, 0), "classes wait");
-    return read_class_counts(st, st->K);
+    std::vector<uint64_t> c(2ull * (st->K + 1));
+    uint32_t err = 0;
+    hip_check(hipMemcpyAsync(c.data(), st->ci_ctr.p, c.size() * 8, hipMemcpyDeviceToHost, st->s), "class counts");
+    hip_check(hipMemcpyAsync(&err, st->ci_n.p + 3, 4, hipMemcpyDeviceToHost, st->s), "class index errors");
+    hip_check(hipStreamSynchronize(st->s), "class sync");
+    if (err) {
+        // cannot happen while index_level keeps free slots; rebuild next time
+        st->ci_rebuild_from = 0;
+        throw DeviceError{BSIM_E_DEVICE, "internal: a class index table ran full"};
+    }
+    return c;
 }
 
 // Levels j0..K for every vertex with the refinement kernels (hash-only
@@ -1053,7 +1097,7 @@ void full_levels(bsim_state* st, uint32_t j0, Arena& arena) {
     alloc_hash_scratch(g, hs, arena, s);
     for (uint32_t j = j0; j <= st->K; j++) {
         launch_hash_level(g, st->levels[0].p, st->levels[j - 1].p, st->levels[j].p, hs, j, s);
-        classes_level(st, j);
+        index_rebuild(st, j);
     }
 }
 
@@ -1153,23 +1197,10 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
         if (lb == 2) k_big_chunks<uint16_t><<<512, kBlock, 0, s>>>(a);
         else k_big_chunks<uint32_t><<<512, kBlock, 0, s>>>(a);
         hip_check(hipGetLastError(), "frontier launch");
-        classes_level(st, j);
+        const uint32_t qp = (j - 1) & 1;
+        index_level(st, j, st->flist[par].p, 0, &st->cnt.p->f_count[par], st->cflag.p, tag, st->ci_q[qp].p, 0,
+                    st->ci_n.p + 1 + qp, arena);
     }
-}
-
-// Classes of levels 0..upto into st->rep on the state's stream; returns the
-// founded count per level.
-std::vector<uint32_t> level_classes(bsim_state* st, uint32_t upto) {
-    hipStream_t s = st->s;
-    const SplitTable T = class_table(st);
-    st->cls_cnt.ensure(2ull * (upto + 1), 0, s);
-    hip_check(hipMemsetAsync(st->cls_cnt.p, 0, 8ull * (upto + 1), s), "class counts");
-    for (uint32_t j = 0; j <= upto; j++) {
-        launch_level_classes(st->levels[j].p, st->rep.p, st->alive.p, st->n, j, T, st->cls_cnt.p + 2 * j,
-                             st->cls_cnt.p + 2 * j + 1, s);
-        launch_level_clear(T, st->cls_cnt.p + 2 * j + 1, s);
-    }
-    return read_class_counts(st, upto);
 }
 
 // Result arrays of an update, allocated before the update changes the state
@@ -1183,10 +1214,16 @@ struct ResultReserve {
 // Classes, fixpoint rule and finalize on the current levels.
 bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls, ResultReserve* rr = nullptr) {
     hipStream_t s = st->s;
-    std::vector<uint32_t> f = classes_end(st);
+    const std::vector<uint64_t> c = index_end(st);
     std::vector<uint32_t> nk(st->K + 1);
-    uint32_t run = 0;
-    for (uint32_t j = 0; j <= st->K; j++) nk[j] = run += f[j];
+    for (uint32_t j = 0; j <= st->K; j++) nk[j] = static_cast<uint32_t>(c[2 * j]);
+    // the next update rebuilds the tables whose claimed slots passed 70 %
+    st->ci_rebuild_from = st->K + 1;
+    for (uint32_t j = 0; j <= st->K; j++)
+        if (c[2 * j + 1] * 10 > st->ci_cap * 7) {
+            st->ci_rebuild_from = j;
+            break;
+        }
     const bool stop = (st->flags & BSIM_STOP_AT_FIXPOINT) != 0;
     uint32_t k_done = st->K, fix = 0;
     for (uint32_t j = 0; j <= st->K; j++) {
@@ -1197,7 +1234,6 @@ bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls, ResultReserve* 
             break;
         }
     }
-    if (k_done < st->K) level_classes(st, k_done);
     (void)ms_cls;
     Staged g;
     g.n = st->n;
@@ -1213,7 +1249,8 @@ bsim_result* finish(bsim_state* st, Arena& arena, float* ms_cls, ResultReserve* 
     Arena& keep = rr ? *rr->keep : own_keep;
     FinalOut fo;
     if (rr) fo = rr->fo;
-    finalize(g, st->rep.p, !(st->flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s);
+    // the classes of level k_done, named by their slots in that level's table
+    finalize(g, st->ci_cid[k_done].p, !(st->flags & BSIM_NO_SUMMARY_EDGES), fo, arena, keep, s, st->ci_cap);
     if (fo.n_blocks != nk[k_done]) throw DeviceError{BSIM_E_DEVICE, "internal: class count mismatch in finalize"};
     LoopResult lr;
     lr.k_done = k_done;
@@ -1255,12 +1292,11 @@ void reserve_batch(bsim_state* st, const HostBatch& hb, ResultReserve& rr) {
     st->chunk_owner.ensure(static_cast<size_t>(n_new) + m_cap / kChunkEdges + 2, 0, s);
     const uint64_t pct = st->ctx->frontier_limit_pct;
     st->scratch.ensure(4 * (m_cap * 3 * pct / 100 + 4096) + 1024, 0, s);
-    st->cls_cnt.ensure(2ull * (st->K + 1), 0, s);
     // the workspace: uploads of the batch, merge flags and scans, the
     // staging of full levels, the reverse-list sort and finalize
     const uint64_t items = hb.cu.size() + hb.rw.size() + hb.rgw.size() + hb.tl.size() + hb.tl_ids.size() +
                            hb.dead.size() + 3 * hb.gsrc.size() + hb.tl_off.size();
-    const uint64_t bound = 40 * m_cap + 64ull * n_new + 24 * items + (64ull << 20);
+    const uint64_t bound = 40 * m_cap + 128ull * n_new + 24 * items + (64ull << 20);
     st->work_want = std::max<uint64_t>(st->work_want, bound);
     st->work.ensure(st->work_want, 0, s);
     // the result's arrays
@@ -1358,6 +1394,7 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
     if (st->tag_base > 0xFFFFFFFFu - 2 * (st->K + 2)) {
         hip_check(hipMemsetAsync(st->fmark.p, 0, st->fmark.cap * 4, s), "tags");
         hip_check(hipMemsetAsync(st->cflag.p, 0, st->cflag.cap * 4, s), "tags");
+        hip_check(hipMemsetAsync(st->ci_dmark.p, 0, st->ci_dmark.cap * 4, s), "tags");
         st->tag_base = 0;
     }
     const uint32_t tag0 = st->tag_base + 1;
@@ -1367,8 +1404,8 @@ bsim_result* apply_batch(bsim_state* st, const HostBatch& hb) {
                                                  st->alive.p, st->untyped ? 1 : 0, st->levels[0].p, st->cflag.p,
                                                  tag0, st->rev_off[st->rcur].p, st->n_rev, st->cnt.p->in_sum[0]);
     hip_check(hipGetLastError(), "level 0");
-    classes_begin(st);
-    classes_level(st, 0);
+    hip_check(hipMemsetAsync(st->ci_n.p + 3, 0, 4, s), "class index errors");
+    index_level(st, 0, d_tl, nT, nullptr, nullptr, tag0, d_dead, nd, nullptr, arena);
     propagate(st, d_tl, nT, tag0, arena);
     tm.mark(2);
     bsim_result* r = finish(st, arena, nullptr, &rr);
@@ -1482,8 +1519,8 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
         run_refinement(ctx, g, bp, rb, &sink, arena);
     }
     tm.mark(2);
-    classes_begin(st);
-    for (uint32_t j = 0; j <= st->K; j++) classes_level(st, j);
+    hip_check(hipMemsetAsync(st->ci_n.p, 0, 4 * 4, s), "class list counts");
+    for (uint32_t j = 0; j <= st->K; j++) index_rebuild(st, j);
     bsim_result* r = finish(st, arena, nullptr);
     tm.mark(3);
     tm.fill(r);
@@ -1520,11 +1557,15 @@ uint64_t state_bytes(const bsim_state* st) {
     }
     add(st->alive);
     for (const auto& l : st->levels) add(l);
-    add(st->salt), add(st->rep), add(st->dflag), add(st->bmark), add(st->fmark), add(st->chg_lo);
+    add(st->salt), add(st->dflag), add(st->bmark), add(st->fmark), add(st->chg_lo);
     add(st->chg_hi), add(st->tidx), add(st->kept), add(st->deg), add(st->blist), add(st->cflag);
-    add(st->cls_cnt), add(st->kpos), add(st->chunk_owner), add(st->big_done), add(st->big), add(st->big_acc);
+    add(st->kpos), add(st->chunk_owner), add(st->big_done), add(st->big), add(st->big_acc);
     add(st->scratch), add(st->work);
-    b += static_cast<uint64_t>(st->cls_cap) * (sizeof(uint64_t) + 4);
+    for (const auto& x : st->ci_word) add(x);
+    for (const auto& x : st->ci_keyh) add(x);
+    for (const auto& x : st->ci_cnt) add(x);
+    for (const auto& x : st->ci_cid) add(x);
+    add(st->ci_ctr), add(st->ci_dmark), add(st->ci_d), add(st->ci_q[0]), add(st->ci_q[1]), add(st->ci_n);
     return b;
 }
 

@@ -461,16 +461,6 @@ void launch_small_graphs(const Staged& g, const RunBuffers& rb, const SmallPlan&
 // device_max: the largest table the device allows (else the default size).
 uint32_t query_hub_table_slots(int device, bool device_max = false);
 
-// Classes of one stored level: level 0 groups alive vertices by h (= t),
-// level j >= 1 splits the classes in rep[] by h = h^j.  T must be empty; its
-// `list` (mask + 1 entries) receives the founded slots, *slot_count their
-// number, *founded_total grows by the number of classes founded.
-void launch_level_classes(const uint64_t* h, uint32_t* rep, const uint8_t* alive, uint32_t n,
-                          uint32_t level, const SplitTable& T, uint32_t* founded_total,
-                          uint32_t* slot_count, hipStream_t s);
-// Empty T again after launch_level_classes (slots listed by it).
-void launch_level_clear(const SplitTable& T, const uint32_t* slot_count, hipStream_t s);
-
 // Sort m 64-bit keys ascending on bits [0, bits); returns a or b, whichever
 // holds the result.
 uint64_t* radix_sort(uint64_t* a, uint64_t* b, uint32_t m, int bits, Arena& arena, hipStream_t s);
@@ -490,6 +480,35 @@ struct FinalOut {
     uint32_t* se_dst = nullptr;
 };
 
+// Class index of a resident state, one per level (bsim_cindex.hip): a hash
+// table of the level's classes keyed by (class at level j-1, h^j) with
+// member counts, and the class (table slot) of every vertex.
+constexpr uint32_t kNoClass = 0xFFFFFFFFu;
+struct CiLevel {
+    uint64_t* word;   // [cap] 0 = empty, else (level j-1 class + 1) << 32 | owner
+    uint64_t* key_h;  // [cap] the key's hash
+    uint32_t* cnt;    // [cap] members
+    uint32_t* cid;    // [vertices] class slot, kNoClass for a dead vertex
+    uint32_t mask;    // cap - 1
+};
+// Every vertex from scratch; ctr[0] = classes, ctr[1] = claimed slots.
+void ci_rebuild(const CiLevel& L, uint64_t cap, const uint32_t* cid_prev, const uint64_t* h, const uint8_t* alive,
+                uint32_t n, uint64_t* ctr, hipStream_t s);
+// d = (candidates of a with flag[v] == ftag, or all of a when flag is null)
+// plus b, each vertex once (dmark[v] = dtag marks it); counts from the _dev
+// pointers when given; *nd = its length.
+void ci_list(const uint32_t* a, uint32_t na, const uint32_t* na_dev, const uint32_t* flag, uint32_t ftag,
+             const uint32_t* b, uint32_t nb, const uint32_t* nb_dev, uint32_t* dmark, uint32_t dtag, uint32_t* d,
+             uint32_t* nd, uint32_t grid, hipStream_t s);
+// Re-key the nd vertices of d; q / *nq = those whose class changed.
+// ctr[0] changes by the classes born less those gone (mod 2^64), ctr[1] by
+// the slots claimed.  The table must have at least nd free slots; a full
+// one sets *err (device) instead of probing on.  host_word: pinned scratch
+// for one count.
+void ci_update(const CiLevel& L, const uint32_t* cid_prev, const uint64_t* h, const uint8_t* alive,
+               const uint32_t* d, uint32_t nd, uint64_t* ctr, uint32_t* q, uint32_t* nq, uint32_t* err,
+               uint32_t* host_word, Arena& arena, hipStream_t s);
+
 // Summary edges of a CSR graph with a tile schedule, bucketed by source
 // block (bid, nb blocks) and sorted within each block; false from the fit
 // test means the keys or the layout need the global sort instead.
@@ -499,6 +518,6 @@ void bucketed_summary_edges(const Staged& g, const uint32_t* bid, uint32_t nb, c
 
 // Blocks are the classes given by rep[] (first-occurrence numbering).
 void finalize(const Staged& g, const uint32_t* rep, bool want_edges, FinalOut& out, Arena& arena,
-              Arena& keep, hipStream_t s);
+              Arena& keep, hipStream_t s, uint64_t n_ids = 0);
 
 }  // namespace bsim

@@ -854,55 +854,6 @@ __global__ void __launch_bounds__(kBlock) k_graph_stop(BatchCtl bc, uint32_t k, 
 // alive vertices by t(v); level j >= 1 splits every class by h^j with the
 // same split test as launch j+1 of the refinement loop.
 
-__global__ void __launch_bounds__(kBlock) k_level_classes(const uint64_t* __restrict__ h,
-                                                          uint32_t* __restrict__ rep,
-                                                          const uint8_t* __restrict__ alive, uint32_t n,
-                                                          uint32_t level, SplitTable T,
-                                                          uint32_t* __restrict__ founded_total,
-                                                          uint32_t* __restrict__ slot_count) {
-    __shared__ uint32_t s_red[kBlock / 64];
-    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
-    uint32_t founded = 0, slot = 0xFFFFFFFFu;
-    bool part = false;
-    uint32_t r = kNoRep;
-    uint64_t hv = 0;
-    if (v < n) {
-        if (!alive[v]) {
-            if (level == 0) rep[v] = 0xFFFFFFFFu;
-        } else {
-            hv = h[v];
-            if (level == 0) {
-                part = true;
-            } else {
-                r = rep[v];
-                part = r != v && hv != h[r];
-            }
-        }
-    }
-    const uint64_t o = wave_split_join(T, h, part, r, hv, v, &founded, &slot);
-    if (part) rep[v] = static_cast<uint32_t>(o);
-    // founded slots are listed so that only they are cleared afterwards (one
-    // counter atomic per wave: level 0 founds a class per distinct type set)
-    const bool listed = founded && slot != 0xFFFFFFFFu;
-    const uint64_t ball = __ballot(listed);
-    if (ball) {
-        const uint32_t lane = lane_id();
-        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(slot_count, static_cast<uint32_t>(__popcll(ball)));
-        base = static_cast<uint32_t>(__shfl(static_cast<int>(base), static_cast<int>(leader), 64));
-        const uint32_t pos = base + static_cast<uint32_t>(__popcll(ball & ((1ull << lane) - 1)));
-        if (listed && pos <= T.mask) T.list[pos] = slot;
-    }
-    const uint32_t c = block_sum_u32(founded, s_red);
-    if (threadIdx.x == 0 && c) atomicAdd(founded_total, c);
-}
-
-__global__ void __launch_bounds__(kBlock) k_level_clear(SplitTable T, const uint32_t* __restrict__ slot_count) {
-    const uint32_t cnt = min(*slot_count, T.mask + 1);
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) T.slots[T.list[i]] = 0;
-}
-
 }  // namespace
 
 uint32_t query_hub_table_slots(int device, bool device_max) {
@@ -1124,20 +1075,6 @@ void launch_hash_level(const Staged& g, const uint64_t* t, const uint64_t* h_pre
 void launch_graph_stop(const RunBuffers& rb, uint32_t k, uint32_t k_max, bool stop, hipStream_t s) {
     k_graph_stop<<<ceil_div(rb.bc.n_graphs, kBlock), kBlock, 0, s>>>(rb.bc, k, k_max, stop ? 1u : 0u, rb.status);
     hip_check(hipGetLastError(), "graph stop launch");
-}
-
-void launch_level_classes(const uint64_t* h, uint32_t* rep, const uint8_t* alive, uint32_t n,
-                          uint32_t level, const SplitTable& T, uint32_t* founded_total,
-                          uint32_t* slot_count, hipStream_t s) {
-    if (n == 0) return;
-    k_level_classes<<<ceil_div(n, kBlock), kBlock, 0, s>>>(h, rep, alive, n, level, T, founded_total,
-                                                           slot_count);
-    hip_check(hipGetLastError(), "level classes launch");
-}
-
-void launch_level_clear(const SplitTable& T, const uint32_t* slot_count, hipStream_t s) {
-    k_level_clear<<<1024, kBlock, 0, s>>>(T, slot_count);
-    hip_check(hipGetLastError(), "level clear launch");
 }
 
 }  // namespace bsim

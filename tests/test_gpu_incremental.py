@@ -216,3 +216,19 @@ def test_invalid_batches_leave_state_unchanged():
         assert rows(s.state.graph()) == rows(s.g)
     s.apply([("add_e", 3, 1, 0)], what="after errors")
     s.close()
+
+
+def test_class_index_through_many_batches():
+    # A small state taking many batches: the level tables of the class index
+    # keep every key they ever held, so the claimed slots pass the load
+    # limit and the tables are rebuilt between batches; classes empty out
+    # and come back (vertex deletions, type changes back and forth).
+    rng = np.random.default_rng(37)
+    g = gg.uniform_graph(150, 500, 3, 3, seed=8)
+    for pct in (100, 10):
+        with FrontierLimit(pct):
+            s = Session(g, 3)
+            for i in range(40):
+                d = gg.update_ops(s.g, rng, int(rng.integers(1, 120)), n_labels=3, n_types=3)
+                s.apply(gg.ops_as_tuples(d), what=("churn", pct, i))
+            s.close()
