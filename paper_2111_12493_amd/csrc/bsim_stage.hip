@@ -162,7 +162,10 @@ __global__ void __launch_bounds__(kBlock) k_stage_vertices(
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 1; i < kBlock / 64; i++) wmax = max(wmax, s_max[i]);
-        if (wmax) atomicMax(&status->max_types, wmax);
+        // the maximum only grows: a block that cannot raise it (nearly all
+        // of them once a few have run) issues no atomic at all
+        if (wmax && wmax > __hip_atomic_load(&status->max_types, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&status->max_types, wmax);
     }
     bool hub = (b >= a) && d >= kHubMinDegree;
     if (in) {
@@ -202,7 +205,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_edges(const uint32_t* __restri
             mx = max(mx, s_mx[i]);
             err |= s_err[i];
         }
-        if (mx) atomicMax(&status->max_label, mx);
+        if (mx && mx > __hip_atomic_load(&status->max_label, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&status->max_label, mx);
         if (err) atomicOr(&status->error, err);
     }
 }
