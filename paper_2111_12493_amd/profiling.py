@@ -3,7 +3,7 @@
     python -m paper_2111_12493_amd.profiling stats  <kernel_stats.csv>
     python -m paper_2111_12493_amd.profiling trace  <kernel_trace.csv> <k_done>
     python -m paper_2111_12493_amd.profiling counters <counter_collection.csv> [calib_bytes [k_done]]
-    python -m paper_2111_12493_amd.profiling summary <dir> <workload> <k_done> <algorithmic_bytes> <calib_bytes> <out_dir>
+    python -m paper_2111_12493_amd.profiling summary <dir> <workload> <k_done> <algorithmic_bytes> <calib_bytes> <out_dir> [hash_launches]
     python -m paper_2111_12493_amd.profiling probes <workload> <out_dir>
     python -m paper_2111_12493_amd.profiling updates <incremental|plain> <batches>
     python -m paper_2111_12493_amd.profiling summary-updates <dir> <batches> <out_dir>
@@ -22,7 +22,10 @@ to wrap; `summary-updates` turns the two kernel-stat tables
 `trace` splits the dispatch sequence into summarization runs (one k_init
 dispatch starts each run) and averages each kernel over the launches that
 did work: refinement launches 1..k_done+1 of every run (the later ones of
-the last queued chunk find the stop flag and return at once).
+the last queued chunk find the stop flag and return at once), or 1..k_done
+when the run's launch k_done+1 ran as a split launch (its hash half finds
+the stop, so only launches 1..k_done hashed a level): `hash_launches` says
+which.
 
 `counters` averages every counter per dispatch for each kernel (with k_done,
 over the working refinement launches only).  When the profiled run also
@@ -76,8 +79,10 @@ def stats(path: str) -> str:
     return "\n".join(lines)
 
 
-def working_launch_durations(path: str, k_done: int):
-    """Per kernel, durations (ns) of the working refinement-loop launches."""
+def working_launch_durations(path: str, k_done: int, n_work: int = 0):
+    """Per kernel, durations (ns) of the working refinement-loop launches
+    (the first n_work of every run; default k_done + 1)."""
+    n_work = n_work or k_done + 1
     rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
     seen = collections.Counter()
     out = collections.defaultdict(list)
@@ -87,13 +92,13 @@ def working_launch_durations(path: str, k_done: int):
             seen.clear()
             continue
         seen[k] += 1
-        if k in ("k_iterate", "k_hub", "k_hub_finish") and seen[k] <= k_done + 1:
+        if k in ("k_iterate", "k_hub", "k_hub_finish") and seen[k] <= n_work:
             out[k].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     return out
 
 
-def trace(path: str, k_done: int) -> str:
-    d = working_launch_durations(path, k_done)
+def trace(path: str, k_done: int, n_work: int = 0) -> str:
+    d = working_launch_durations(path, k_done, n_work)
     lines = ["%-12s %10s %12s   (working launches only)" % ("kernel", "launches", "avg_us")]
     for k, v in sorted(d.items()):
         lines.append("%-12s %10d %12.2f" % (k, len(v), sum(v) / len(v) / 1e3))
@@ -177,7 +182,7 @@ def write_bytes(avg: dict) -> float:
     return 32 * (wr - w64) + 64 * w64
 
 
-def pass_counters(path: str, k_done: int):
+def pass_counters(path: str, k_done: int, n_work: int = 0):
     """Per kernel (working launches of the refinement loop only), the average
     of every counter per dispatch, and the counters of the largest foreign
     dispatch (the calibration copy)."""
@@ -198,21 +203,24 @@ def pass_counters(path: str, k_done: int):
         if k == "k_init":
             seen.clear()
         seen[k] += 1
-        if k in ITER_KERNELS and seen[k] > k_done + 1:
+        if k in ITER_KERNELS and seen[k] > (n_work or k_done + 1):
             continue
         by_kernel[k].append(per[key])
     avg = {k: {c: sum(d.get(c, 0.0) for d in v) / len(v) for c in v[0]} for k, v in by_kernel.items()}
     return avg, foreign
 
 
-def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: int, out_dir: str) -> str:
+def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: int, out_dir: str,
+            n_work: int = 0) -> str:
     """Write <out_dir>/k_iterate_<workload>.md and _counters.json from the
-    rocprofv3 runs under directory d (see commands())."""
+    rocprofv3 runs under directory d (see commands()).  n_work: the
+    refinement launches per run that hashed a level (default k_done + 1)."""
     j = os.path.join
-    dur = working_launch_durations(j(d, "stats", "run_kernel_trace.csv"), k_done)
+    n_work = n_work or k_done + 1
+    dur = working_launch_durations(j(d, "stats", "run_kernel_trace.csv"), k_done, n_work)
     iter_us = sum(sum(dur[k]) / len(dur[k]) for k in ITER_KERNELS if dur.get(k)) / 1e3
-    fa, ff = pass_counters(j(d, "fetch", "run_counter_collection.csv"), k_done)
-    la, lf = pass_counters(j(d, "l2", "run_counter_collection.csv"), k_done)
+    fa, ff = pass_counters(j(d, "fetch", "run_counter_collection.csv"), k_done, n_work)
+    la, lf = pass_counters(j(d, "l2", "run_counter_collection.csv"), k_done, n_work)
     copy_read = max(fetch_bytes(c) for c in ff) if ff else 0.0
     copy_write = max(write_bytes(c) for c in lf) if lf else 0.0
     rs = calib_bytes / copy_read if copy_read else 1.0   # true bytes per counted byte
@@ -237,7 +245,7 @@ def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: in
     sq = []
     derived = {}
     for pas in ("sq1", "sq2"):
-        res, _ = pass_counters(j(d, pas, "run_counter_collection.csv"), k_done)
+        res, _ = pass_counters(j(d, pas, "run_counter_collection.csv"), k_done, n_work)
         for k in ITER_KERNELS:
             if k in res:
                 derived.setdefault(k, {}).update(res[k])
@@ -251,12 +259,13 @@ def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: in
              % (workload, k_done), "",
              "Kernel source fingerprint (%s): %s" % (", ".join(KERNEL_SOURCES), rep["kernel_sources_sha256_16"]), "",
              "## Commands (repository root, one MI355X)", "", commands(d, workload), "", "Summaries:", "",
-             "    python -m paper_2111_12493_amd.profiling summary %s %s %d %d %d profiles"
-             % (d, workload, k_done, algo_bytes, calib_bytes), "",
+             "    python -m paper_2111_12493_amd.profiling summary %s %s %d %d %d profiles %d"
+             % (d, workload, k_done, algo_bytes, calib_bytes, n_work), "",
              "## Kernel stats (every dispatch of the profiled runs)", "", "```",
              stats(j(d, "stats", "run_kernel_stats.csv")), "```", "",
-             "Launches past the stop test of a run return at once; over the working launches "
-             "(1..k_done+1 of every run):", "", "```", trace(j(d, "stats", "run_kernel_trace.csv"), k_done), "```", "",
+             "Launches past the stop test of a run return at once; over the launches that hashed a "
+             "level (1..%d of every run):" % n_work, "", "```",
+             trace(j(d, "stats", "run_kernel_trace.csv"), k_done, n_work), "```", "",
              "One iteration = %.1f us; algorithmic bytes %.1f MB -> %.0f GB/s = %.1f %% of 8 TB/s."
              % (iter_us, algo_bytes / 1e6, algo_bytes / iter_us / 1e3, algo_bytes / iter_us / 1e3 / 80), "",
              "## Bytes past L2 per working iteration", "",
@@ -320,7 +329,7 @@ def run_probes(workload: str, out_dir: str) -> str:
     tgt0 = dg.tgt.clone()
     lines += ["Gather probe over the %d targets of %s (n = %d), gathering from an %d-entry 8-byte array; "
               "algorithmic bytes = 12 per edge (4 B target + 8 B gathered value):" % (m, workload, n, n), "",
-              "| vertex ids | ms per pass | GB/s | %% of 8 TB/s |", "|---|---:|---:|---:|"]
+              "| vertex ids | ms per pass | GB/s | % of 8 TB/s |", "|---|---:|---:|---:|"]
     indeg = torch.bincount(tgt0.to(torch.int64), minlength=n)
     rank = torch.empty(n, dtype=torch.int64, device="cuda")
     rank[torch.argsort(indeg, descending=True, stable=True)] = torch.arange(n, device="cuda")
@@ -488,7 +497,8 @@ def main(argv):
         print(summary_updates(argv[2], int(argv[3]), argv[4]))
         return
     if argv[1] == "summary":
-        print(summary(argv[2], argv[3], int(argv[4]), int(argv[5]), int(argv[6]), argv[7]))
+        print(summary(argv[2], argv[3], int(argv[4]), int(argv[5]), int(argv[6]), argv[7],
+                      int(argv[8]) if len(argv) > 8 else 0))
         return
     if argv[1] == "probes":
         run_probes(argv[2], argv[3])
