@@ -45,6 +45,7 @@ constexpr uint32_t kFlagTypes = 2u;   // dflag: the type list is replaced
 constexpr uint32_t kSmallDeg = 512;   // frontier vertices handled by one wave
 constexpr uint32_t kWaveSlots = 1024; // LDS de-dup slots per wave (>= 2 * kSmallDeg)
 constexpr uint32_t kChunkEdges = 4096;  // edges per block of a large frontier vertex
+constexpr uint32_t kInChunk = 4096;     // in-list entries per wave of a large changed vertex
 constexpr uint32_t kFrontGrid = 2048;   // blocks of the frontier kernels (grid-stride)
 // A large frontier vertex of degree d takes a table of next_pow2(2 d) slots
 // with 32-bit slot arithmetic, which holds for d <= 2^30.
@@ -58,7 +59,7 @@ struct IncCounters {
     uint32_t f_count[2];   // frontier of a level (by parity)
     uint32_t big_count;    // large frontier vertices deferred to chunk blocks
     uint32_t chunk_count;
-    uint32_t pad;
+    uint32_t in_chunk_count;  // chunks of the in-lists of large changed vertices
     uint64_t slot_top;     // scratch table slots handed out
     // sum of the in-degrees of the vertices whose hash changed at a level
     // (by parity, striped by vertex id): bounds the next level's frontier
@@ -457,6 +458,7 @@ __global__ void k_level_reset(IncCounters* cnt, uint32_t parity) {
         cnt->f_count[parity] = 0;
         cnt->big_count = 0;
         cnt->chunk_count = 0;
+        cnt->in_chunk_count = 0;
         cnt->slot_top = 0;
     }
     for (uint32_t i = threadIdx.x; i < kInStripes; i += blockDim.x) {
@@ -478,12 +480,17 @@ __global__ void k_front_base(const uint32_t* __restrict__ blist, IncCounters* cn
 }
 
 // F_j grows by the in-neighbours of C_{j-1}: the vertices of the previous
-// list whose change tag is prev_tag (one wave per listed vertex).
+// list whose change tag is prev_tag (one wave per listed vertex).  The
+// in-list of a vertex with more than kInChunk in-neighbours (a changed hub)
+// is cut into chunks, listed as (vertex << 32 | chunk) in `chunks` (room for
+// chunk_cap), and walked by k_front_inchunks, many waves at once; a wave
+// whose chunks find no room walks its list itself, and the slots it took
+// within the room hold ~0 (skipped).
 __global__ void k_front_innbrs(const uint32_t* __restrict__ prev, const uint32_t* prev_count, uint32_t prev_n,
                                const uint32_t* __restrict__ cflag, uint32_t prev_tag,
                                const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
                                uint32_t tag, uint32_t* fmark, uint32_t* flist, IncCounters* cnt, uint32_t parity,
-                               const uint32_t* __restrict__ row_off) {
+                               const uint32_t* __restrict__ row_off, uint64_t* chunks, uint64_t chunk_cap) {
     const uint32_t np = prev_count ? *prev_count : prev_n;
     const uint32_t lane = lane_id();
     const uint32_t waves = gridDim.x * (kBlock / 64);
@@ -491,6 +498,40 @@ __global__ void k_front_innbrs(const uint32_t* __restrict__ prev, const uint32_t
         const uint32_t w = prev[i];
         if (cflag[w] != prev_tag) continue;
         const uint32_t a = rev_off[w], b = rev_off[w + 1];
+        if (b - a > kInChunk) {
+            const uint32_t nch = (b - a + kInChunk - 1) / kInChunk;
+            uint32_t c0 = 0;
+            if (lane == 0) c0 = atomicAdd(&cnt->in_chunk_count, nch);
+            c0 = __shfl(c0, 0);
+            const bool room = static_cast<uint64_t>(c0) + nch <= chunk_cap;
+            for (uint32_t c = lane; c < nch && static_cast<uint64_t>(c0) + c < chunk_cap; c += 64)
+                chunks[c0 + c] = room ? (static_cast<uint64_t>(w) << 32 | c) : ~0ull;
+            if (room) continue;
+        }
+        for (uint32_t j0 = a; j0 < b; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const bool valid = j < b;
+            tag_append_deg(valid, valid ? rev_src[j] : 0u, tag, fmark, flist, &cnt->f_count[parity], row_off,
+                           cnt->out_sum[parity]);
+        }
+    }
+}
+
+// The chunks that k_front_innbrs listed: one wave per chunk of kInChunk
+// in-list entries.
+__global__ void k_front_inchunks(const uint64_t* __restrict__ chunks, uint64_t chunk_cap,
+                                 const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
+                                 uint32_t tag, uint32_t* fmark, uint32_t* flist, IncCounters* cnt, uint32_t parity,
+                                 const uint32_t* __restrict__ row_off) {
+    const uint32_t nc = static_cast<uint32_t>(min(static_cast<uint64_t>(cnt->in_chunk_count), chunk_cap));
+    const uint32_t lane = lane_id();
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < nc; i += waves) {
+        const uint64_t item = chunks[i];
+        if (item == ~0ull) continue;
+        const uint32_t w = static_cast<uint32_t>(item >> 32);
+        const uint32_t a = rev_off[w] + static_cast<uint32_t>(item) * kInChunk;
+        const uint32_t b = min(rev_off[w + 1], a + kInChunk);
         for (uint32_t j0 = a; j0 < b; j0 += 64) {
             const uint32_t j = j0 + lane;
             const bool valid = j < b;
@@ -1142,15 +1183,21 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
         const uint32_t* row_off = st->row_off[st->cur].p;
         k_front_base<<<256, kBlock, 0, s>>>(st->blist.p, st->cnt.p, par, tag, st->fmark.p, st->flist[par].p,
                                             row_off);
+        // the scratch table is free until k_front_hash hands out its slots
+        uint64_t* in_chunks = st->scratch.p;
+        const uint64_t in_cap = st->scratch.cap;
         if (j == 1)
             k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(d_tl, nullptr, nT, st->cflag.p, tag0, st->rev_off[st->rcur].p,
                                                          st->rev_src[st->rcur].p, tag, st->fmark.p, st->flist[par].p,
-                                                         st->cnt.p, par, row_off);
+                                                         st->cnt.p, par, row_off, in_chunks, in_cap);
         else
             k_front_innbrs<<<kFrontGrid, kBlock, 0, s>>>(st->flist[par ^ 1].p, &st->cnt.p->f_count[par ^ 1], 0,
                                                          st->cflag.p, tag - 1, st->rev_off[st->rcur].p,
                                                          st->rev_src[st->rcur].p, tag, st->fmark.p, st->flist[par].p,
-                                                         st->cnt.p, par, row_off);
+                                                         st->cnt.p, par, row_off, in_chunks, in_cap);
+        k_front_inchunks<<<kFrontGrid, kBlock, 0, s>>>(in_chunks, in_cap, st->rev_off[st->rcur].p,
+                                                       st->rev_src[st->rcur].p, tag, st->fmark.p, st->flist[par].p,
+                                                       st->cnt.p, par, row_off);
         hip_check(hipGetLastError(), "frontier marks");
         uint64_t out_sum[kInStripes];
         hip_check(hipMemcpyAsync(&fcount, &st->cnt.p->f_count[par], 4, hipMemcpyDeviceToHost, s), "frontier count");

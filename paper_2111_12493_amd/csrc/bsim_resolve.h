@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -41,27 +42,52 @@ struct ResolveScratch {
 };
 
 // Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
+// Large inputs are split over host threads: per pass, every thread counts
+// the digits of its share, one prefix over (digit, thread) places them, and
+// every thread scatters its share (so equal digits keep their order).
 inline void host_radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int bits) {
     constexpr int kDigit = 11;
     constexpr uint32_t kBuckets = 1u << kDigit;
     const size_t n = key.size();
+    if (n < 2) return;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const size_t T = std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hw ? hw : 1), 8, n / 65536}));
     std::vector<uint64_t> k2(n);
     std::vector<uint32_t> v2(n);
-    std::vector<uint32_t> cnt(kBuckets);
+    std::vector<uint32_t> cnt(kBuckets * T);
+    auto par = [&](auto f) {
+        std::vector<std::thread> th;
+        size_t t = 1;
+        try {
+            for (; t < T; t++) th.emplace_back(f, t);
+        } catch (...) {
+        }
+        for (size_t u = t; u < T; u++) f(u);  // shares no thread could take
+        f(0);
+        for (auto& x : th) x.join();
+    };
     for (int sh = 0; sh < bits; sh += kDigit) {
-        std::fill(cnt.begin(), cnt.end(), 0u);
-        for (size_t i = 0; i < n; i++) cnt[(key[i] >> sh) & (kBuckets - 1)]++;
+        par([&](size_t t) {
+            uint32_t* c = &cnt[t * kBuckets];
+            std::fill(c, c + kBuckets, 0u);
+            for (size_t i = n * t / T, e = n * (t + 1) / T; i < e; i++) c[(key[i] >> sh) & (kBuckets - 1)]++;
+        });
         uint32_t run = 0;
-        for (uint32_t& c : cnt) {
-            const uint32_t t = c;
-            c = run;
-            run += t;
-        }
-        for (size_t i = 0; i < n; i++) {
-            const uint32_t p = cnt[(key[i] >> sh) & (kBuckets - 1)]++;
-            k2[p] = key[i];
-            v2[p] = val[i];
-        }
+        for (uint32_t d = 0; d < kBuckets; d++)
+            for (size_t t = 0; t < T; t++) {
+                uint32_t& c = cnt[t * kBuckets + d];
+                const uint32_t x = c;
+                c = run;
+                run += x;
+            }
+        par([&](size_t t) {
+            uint32_t* c = &cnt[t * kBuckets];
+            for (size_t i = n * t / T, e = n * (t + 1) / T; i < e; i++) {
+                const uint32_t p = c[(key[i] >> sh) & (kBuckets - 1)]++;
+                k2[p] = key[i];
+                v2[p] = val[i];
+            }
+        });
         key.swap(k2);
         val.swap(v2);
     }
@@ -123,7 +149,21 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
         }
     } clear_marks{touched, vmark, vtype};
     {
+        // the per-vertex marks and the alive mask are read at random: the
+        // marks of the operation kPf places ahead are fetched meanwhile
+        constexpr uint64_t kPf = 24;
+        auto prefetch = [&](const bsim_update& o) {
+            const size_t lim = std::min(vmark.size(), alive.size());
+            if (!lim) return;
+            const size_t u = std::min<size_t>(o.u, lim - 1), w = std::min<size_t>(o.w, lim - 1);
+            __builtin_prefetch(&vmark[u]);
+            __builtin_prefetch(&alive[u]);
+            __builtin_prefetch(&vmark[w]);
+            __builtin_prefetch(&alive[w]);
+        };
+        for (uint64_t i = 0; i < n_ops && i < kPf; i++) prefetch(ops[i]);
         for (uint64_t i = 0; i < n_ops; i++) {
+            if (i + kPf < n_ops) prefetch(ops[i + kPf]);
             const bsim_update& o = ops[i];
             const bool edge = o.op == BSIM_OP_ADD_E || o.op == BSIM_OP_DEL_E || o.op == BSIM_OP_MOD_E;
             // checks in the order: ids in range, ids alive, types, labels
@@ -190,7 +230,10 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
         }
         hb.tl_off.push_back(static_cast<uint32_t>(hb.tl_ids.size()));
     }
-    auto dead_at_end = [&](uint32_t v) { return vmark[v] == 2; };
+    // deletions are few: a binary search of their sorted list stays in cache
+    auto dead_at_end = [&](uint32_t v) {
+        return !hb.dead.empty() && std::binary_search(hb.dead.begin(), hb.dead.end(), v);
+    };
     // edge records in (u, w, l) order, input order within equal triples:
     // the triple packed in one key when it fits 64 bits (the add flag rides
     // in the value), else a comparison sort

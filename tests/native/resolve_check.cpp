@@ -370,6 +370,43 @@ int main(int argc, char** argv) {
             check_batch(b, ops, rs);
         }
     }
+    // edge batches large enough for the threaded radix sort (over 2^17
+    // records; no vertex deletions, which the model handles in O(edges))
+    {
+        const Base b = make_base(50000, 100000, 2, 65535);
+        ResolveScratch rs;
+        rs.vmark.assign(b.n, 0);
+        rs.vtype.assign(b.n, 0);
+        std::vector<Triple> known;
+        for (const auto& kv : b.edges) known.push_back(kv.first);
+        auto alive_vertex = [&]() {
+            for (;;) {
+                const uint32_t v = rnd(b.n);
+                if (b.alive[v]) return v;
+            }
+        };
+        for (int k = 0; k < 2; k++) {
+            std::vector<bsim_update> ops(150000 + rnd(50000));
+            for (bsim_update& o : ops) {
+                o = bsim_update{};
+                const uint32_t x = rnd(100);
+                if (x < 60) {
+                    o.op = BSIM_OP_ADD_E;
+                    o.u = alive_vertex();
+                    o.w = rnd(4) ? alive_vertex() : o.u;
+                    o.label = rnd(65536);
+                } else {
+                    const Triple t = known[rnd(static_cast<uint32_t>(known.size()))];
+                    o.op = x < 85 ? BSIM_OP_MOD_E : BSIM_OP_DEL_E;
+                    o.u = std::get<0>(t);
+                    o.label = std::get<1>(t);
+                    o.w = std::get<2>(t);
+                    o.new_label = rnd(65536);
+                }
+            }
+            check_batch(b, ops, rs);
+        }
+    }
     std::printf("ok %d\n", g_batch);
     return 0;
 }

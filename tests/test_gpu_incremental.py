@@ -184,6 +184,32 @@ def test_frontier_through_large_vertices(pct):
         s.close()
 
 
+def test_frontier_through_large_in_lists():
+    # changed vertices with more in-neighbours than one wave walks (4,096):
+    # their in-lists are cut into chunks that many waves expand at once
+    rng = np.random.default_rng(41)
+    n = 20000
+    hubs = {0: 5000, 1: 9000, 2: 13000, 3: 4096, 4: 4097}
+    src = [rng.integers(5, n, size=d) for d in hubs.values()]
+    dst = [np.full(d, h) for h, d in hubs.items()]
+    src.append(rng.integers(0, n, size=30000))
+    dst.append(rng.integers(0, n, size=30000))
+    src, dst = np.concatenate(src), np.concatenate(dst)
+    lab = rng.integers(0, 4, size=len(src))
+    g = gg.from_edges(n, src, dst, lab, types=[[int(x)] for x in rng.integers(0, 3, n)], n_labels=4)
+    with FrontierLimit(100):
+        s = Session(g, 3)
+        # level 1: the hubs' types change (their in-lists join F_1)
+        s.apply([("mod_v", h, [int(rng.integers(3, 6))]) for h in hubs], what="hub types")
+        # level 2: the hubs' out-edges change, so h^1 of each changes
+        s.apply([("add_e", h, int(rng.integers(0, 4)), int(rng.integers(0, n))) for h in hubs],
+                what="hub rows")
+        # both at once, with random changes elsewhere
+        d = gg.update_ops(s.g, rng, 300, n_labels=4, n_types=6)
+        s.apply([("mod_v", 2, [1, 2]), ("add_e", 1, 3, 7)] + gg.ops_as_tuples(d), what="mixed")
+        s.close()
+
+
 def test_incremental_equals_gpu_batch_on_state_graph():
     rng = np.random.default_rng(37)
     g = gg.rmat_graph(12, 1 << 15, n_types=16, n_labels=8, seed=4)
