@@ -57,6 +57,20 @@ def read_traffic(workload: str):
     return d.get("bytes_per_launch")
 
 
+def traffic_detail(workload: str):
+    """The counted bytes behind read_traffic and the copy-kernel scales that
+    turn them into bytes (None where read_traffic is None)."""
+    if read_traffic(workload) is None:
+        return None
+    with open(os.path.join(ROOT, "profiles", "k_iterate_%s_counters.json" % workload)) as f:
+        d = json.load(f)
+    return {"counted_read_bytes": d.get("counted_fetch_bytes_per_iteration"),
+            "counted_write_bytes": d.get("counted_write_bytes_per_iteration"),
+            "copy_read_scale": d.get("copy_read_scale"), "copy_write_scale": d.get("copy_write_scale"),
+            "l2_hit_rate": d.get("k_iterate_l2_hit_rate"),
+            "source": "profiles/k_iterate_%s_counters.json (rocprofv3 TCC counter passes)" % workload}
+
+
 def host_cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -486,10 +500,11 @@ def roofline(recs, g, workload):
     achieved = b_iter / (iter_us * 1e-6) / 1e9 if timed else 0.0
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(workload),
+            "traffic_detail": traffic_detail(workload),
             "kernel": "k_iterate + k_hub + k_hub_finish (one refinement iteration)",
             "algorithmic_bytes_per_launch": b_iter, "avg_launch_us": iter_us,
             "k_iterate_avg_us": kern_ms * 1e3 / max(timed, 1), "hub_kernels_avg_us": hub_ms * 1e3 / max(timed, 1),
-            "timed_launches": timed, "working_launches": sum(min(r["k_done"] + 1, r["launches"]) for r in recs),
+            "timed_launches": timed,
             "launches_issued": sum(r["launches"] for r in recs)}
 
 
