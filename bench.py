@@ -253,6 +253,10 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
     workload = workload or args.inc_workload
     print("# incremental: %s, k=%d, %d vertices, %d edges" % (workload, k, g.n, g.m), file=sys.stderr, flush=True)
     ctx_i, ctx_p = binding.Context(0), binding.Context(0)
+    if args.inc_frontier_pct is not None:
+        ctx_i.set_option("frontier_limit_pct", args.inc_frontier_pct)
+    if args.inc_frontier_edge_pct is not None:
+        ctx_i.set_option("frontier_edge_pct", args.inc_frontier_edge_pct)
     ctx_p.set_option("frontier_limit_pct", 0)
     t0 = time.perf_counter()
     st_i = binding.State(ctx_i, dg, k, stop_at_fixpoint=False, summary_edges=False)
@@ -547,6 +551,10 @@ def main() -> int:
     ap.add_argument("--inc-uniform", default="uniform24",
                     help="second incremental workload (a uniform graph); empty to skip")
     ap.add_argument("--inc-max-ops", type=float, default=1e6)
+    ap.add_argument("--inc-frontier-pct", type=int, default=None,
+                    help="frontier limit of the incremental form (the library's default if not given)")
+    ap.add_argument("--inc-frontier-edge-pct", type=int, default=None,
+                    help="frontier edge limit of the incremental form (the library's default if not given)")
     ap.add_argument("--inc-k", type=int, nargs="+", default=[4, 2, 1],
                     help="levels of the resident states (the first is the main line's)")
     ap.add_argument("--no-serving", action="store_true")

@@ -212,8 +212,10 @@ const char* bsim_status_string(int status);
  * sampling keeps the timed run close to an untimed one); "hub_table_slots" = LDS hash
  * slots of a hub-bucket block (power of two from 64 to the device limit,
  * the default; smaller values force more hash buckets per hub);
- * "frontier_limit_pct" (0..100) = share of the vertices beyond which an
- * update level is recomputed for all vertices (0: always, the plain form);
+ * "frontier_limit_pct" (0..100, default 10) = share of the vertices beyond
+ * which an update level is recomputed for all vertices (0: always, the
+ * plain form); "frontier_edge_pct" (1..100, default 15) = the same for the
+ * share of the out-edges that a level's frontier reads;
  * "tail_split_ppm" (0..1000000, default 100) = when the refinement launches
  * run one per stop check (graphs whose launch takes milliseconds, or
  * chunk_max = 1), a level that founds at most this many classes per

@@ -91,7 +91,8 @@ const char* bsim_option_names(void) {
            "time_launches (N, 0..1048576: time every N-th refinement launch with HIP events, 0 = off); "
            "hub_table_slots (LDS slots of a hub-bucket block: power of two, 64..device limit); "
            "frontier_limit_pct (0..100: an update level whose frontier exceeds this share of the vertices is "
-           "recomputed for all vertices; 0 = always, the plain full recomputation); "
+           "recomputed for all vertices; 0 = always, the plain full recomputation; default 10); "
+           "frontier_edge_pct (1..100: the same for a frontier's share of the out-edges; default 15); "
            "tail_split_ppm (0..1000000: when refinement launches run one per stop check, a level that founds "
            "at most this many classes per million vertices has the next level's split run as a launch of its "
            "own, so a run that stops there computes no further hashes; 0 = off, default 100); "
@@ -119,6 +120,11 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
     if (!strcmp(name, "frontier_limit_pct")) {
         if (value < 0 || value > 100) return BSIM_E_RANGE;
         ctx->frontier_limit_pct = static_cast<uint32_t>(value);
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "frontier_edge_pct")) {
+        if (value < 1 || value > 100) return BSIM_E_RANGE;
+        ctx->frontier_edge_pct = static_cast<uint32_t>(value);
         return BSIM_OK;
     }
     if (!strcmp(name, "tail_split_ppm")) {
@@ -172,6 +178,10 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     }
     if (!strcmp(name, "frontier_limit_pct")) {
         *value = ctx->frontier_limit_pct;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "frontier_edge_pct")) {
+        *value = ctx->frontier_edge_pct;
         return BSIM_OK;
     }
     if (!strcmp(name, "autotune")) {

@@ -17,7 +17,8 @@ struct bsim_ctx {
     uint32_t chunk_max = 32;
     uint32_t time_launches = 0;
     uint32_t hub_table_slots = 8192;  // LDS slots per hub-bucket block on this device
-    uint32_t frontier_limit_pct = 2;  // incremental: larger frontiers recompute the level for all vertices
+    uint32_t frontier_limit_pct = 10;  // incremental: larger frontiers recompute the level for all vertices
+    uint32_t frontier_edge_pct = 15;   // ... and so do frontiers with more than this share of the edges
     // one launch per stop check: once a level founds at most this many
     // classes per million vertices, the next level's split runs on its own
     uint32_t tail_split_ppm = 100;

@@ -26,7 +26,7 @@
 // temporary table; one representative per new key claims an empty slot in
 // a later kernel (no reader probes concurrently, and the keys are distinct
 // and absent, so a claim never needs to match); then every vertex moves.
-#include "bsim_device.h"
+#include "bsim_append.h"
 
 namespace bsim {
 
@@ -140,12 +140,11 @@ __global__ void __launch_bounds__(kBlock) k_ci_dlist(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ b, uint32_t nb,
                                                      const uint32_t* __restrict__ nb_dev, uint32_t* __restrict__ dmark,
                                                      uint32_t dtag, uint32_t* __restrict__ d, uint32_t* __restrict__ nd) {
+    __shared__ uint32_t s_wave[kBlock / 64 + 1];
     const uint32_t ca = na_dev ? *na_dev : na, cb = nb_dev ? *nb_dev : nb;
     const uint64_t total = static_cast<uint64_t>(ca) + cb;
-    const uint32_t lane = lane_id();
-    const uint64_t lt = (1ull << lane) - 1;
     for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kBlock; base < total;
-         base += static_cast<uint64_t>(gridDim.x) * kBlock) {  // uniform trip count
+         base += static_cast<uint64_t>(gridDim.x) * kBlock) {  // the same trip count in every thread of a block
         const uint64_t i = base + threadIdx.x;
         bool take = false;
         uint32_t v = 0;
@@ -154,13 +153,8 @@ __global__ void __launch_bounds__(kBlock) k_ci_dlist(const uint32_t* __restrict_
             const bool cand = i >= ca || !flag || flag[v] == ftag;
             take = cand && atomicExch(&dmark[v], dtag) != dtag;
         }
-        const uint64_t ball = __ballot(take);
-        if (!ball) continue;
-        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
-        uint32_t pos = 0;
-        if (lane == leader) pos = atomicAdd(nd, static_cast<uint32_t>(__popcll(ball)));
-        pos = static_cast<uint32_t>(__shfl(static_cast<int>(pos), static_cast<int>(leader), 64));
-        if (take) d[pos + static_cast<uint32_t>(__popcll(ball & lt))] = v;
+        const uint32_t pos = block_reserve(take, nd, s_wave);
+        if (take) d[pos] = v;
     }
 }
 
@@ -173,8 +167,8 @@ __global__ void __launch_bounds__(kBlock) k_ci_probe(CiLevel L, const uint32_t* 
                                                      uint32_t* __restrict__ ns, uint32_t* __restrict__ pend,
                                                      uint32_t* __restrict__ pend_pc, uint64_t* __restrict__ pend_h,
                                                      uint32_t* __restrict__ n_pend, uint32_t* __restrict__ err) {
+    __shared__ uint32_t s_wave[kBlock / 64 + 1];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t lane = lane_id();
     bool miss = false;
     uint32_t pc = 0;
     uint64_t hv = 0;
@@ -208,14 +202,8 @@ __global__ void __launch_bounds__(kBlock) k_ci_probe(CiLevel L, const uint32_t* 
             }
         }
     }
-    const uint64_t ball = __ballot(miss);
-    if (!ball) return;
-    const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
-    uint32_t pos = 0;
-    if (lane == leader) pos = atomicAdd(n_pend, static_cast<uint32_t>(__popcll(ball)));
-    pos = static_cast<uint32_t>(__shfl(static_cast<int>(pos), static_cast<int>(leader), 64));
+    const uint32_t p = block_reserve(miss, n_pend, s_wave);
     if (miss) {
-        const uint32_t p = pos + static_cast<uint32_t>(__popcll(ball & ((1ull << lane) - 1)));
         pend[p] = i;
         pend_pc[p] = pc;
         pend_h[p] = hv;
@@ -288,6 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_ci_move(CiLevel L, const uint32_t* _
                                                     const uint32_t* __restrict__ ns, uint64_t* __restrict__ ctr,
                                                     uint32_t* __restrict__ q, uint32_t* __restrict__ nq) {
     __shared__ int32_t s_red[kBlock / 64];
+    __shared__ uint32_t s_wave[kBlock / 64 + 1];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t lane = lane_id();
     int32_t delta = 0;
@@ -303,14 +292,8 @@ __global__ void __launch_bounds__(kBlock) k_ci_move(CiLevel L, const uint32_t* _
             moved = true;
         }
     }
-    const uint64_t ball = __ballot(moved);
-    if (ball) {
-        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
-        uint32_t pos = 0;
-        if (lane == leader) pos = atomicAdd(nq, static_cast<uint32_t>(__popcll(ball)));
-        pos = static_cast<uint32_t>(__shfl(static_cast<int>(pos), static_cast<int>(leader), 64));
-        if (moved) q[pos + static_cast<uint32_t>(__popcll(ball & ((1ull << lane) - 1)))] = v;
-    }
+    const uint32_t pos = block_reserve(moved, nq, s_wave);
+    if (moved) q[pos] = v;
     // block sum of the signed class-count changes
     int32_t x = delta;
 #pragma unroll

@@ -33,6 +33,7 @@
 
 #include "bsim_api_internal.h"
 #include "bsim_device.h"
+#include "bsim_append.h"
 #include "bsim_resolve.h"
 
 using namespace bsim;
@@ -43,6 +44,8 @@ namespace {
 constexpr uint32_t kFlagRows = 1u;    // dflag: the out-edge row is rebuilt
 constexpr uint32_t kFlagTypes = 2u;   // dflag: the type list is replaced
 constexpr uint32_t kSmallDeg = 512;   // frontier vertices handled by one wave
+constexpr uint32_t kFrontLanes = 16;   // lanes per frontier vertex of at most this many out-edges
+constexpr uint32_t kFrontGroups = 64 / kFrontLanes;
 constexpr uint32_t kWaveSlots = 1024; // LDS de-dup slots per wave (>= 2 * kSmallDeg)
 constexpr uint32_t kChunkEdges = 4096;  // edges per block of a large frontier vertex
 constexpr uint32_t kInChunk = 4096;     // in-list entries per wave of a large changed vertex
@@ -100,24 +103,22 @@ __device__ __forceinline__ void mark_append(bool valid, uint32_t v, uint32_t* ma
     wave_append(first, v, list, count);
 }
 
-// The same with a tag instead of a flag: marks of earlier levels and
-// batches carry other tags, so the mark array is never cleared.
-__device__ __forceinline__ void tag_append(bool valid, uint32_t v, uint32_t tag, uint32_t* mark, uint32_t* list,
-                                           uint32_t* count) {
+// Tag v for this level (valid lanes); the first tagger lists v through the
+// wave's appender and adds v's out-degree to the lane's sum `deg`.  All
+// lanes of the wave call it together.
+__device__ __forceinline__ void tag_push(WaveAppender& ap, uint64_t& deg, bool valid, uint32_t v, uint32_t tag,
+                                         uint32_t* mark, const uint32_t* __restrict__ row_off) {
     bool first = false;
     if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) != tag) first = atomicExch(&mark[v], tag) != tag;
-    wave_append(first, v, list, count);
+    if (first) deg += row_off[v + 1] - row_off[v];
+    ap.push(first, v);
 }
 
-// tag_append that also adds the out-degrees of the vertices it lists to a
-// striped counter (one atomic per wave).  All lanes of the wave must call it.
-__device__ __forceinline__ void tag_append_deg(bool valid, uint32_t v, uint32_t tag, uint32_t* mark, uint32_t* list,
-                                               uint32_t* count, const uint32_t* __restrict__ row_off,
-                                               uint64_t* out_sum) {
-    bool first = false;
-    if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) != tag) first = atomicExch(&mark[v], tag) != tag;
-    wave_append(first, v, list, count);
-    const uint64_t d = wave_sum_u64(first ? static_cast<uint64_t>(row_off[v + 1] - row_off[v]) : 0ull);
+// The end of a wave's tagging: its buffered list entries, and its out-degree
+// sum added to one of the striped counters.
+__device__ __forceinline__ void tag_finish(WaveAppender& ap, uint64_t deg, uint64_t* out_sum) {
+    ap.flush();
+    const uint64_t d = wave_sum_u64(deg);
     if (lane_id() == 0 && d)
         atomicAdd(reinterpret_cast<unsigned long long*>(&out_sum[blockIdx.x & (kInStripes - 1)]),
                   static_cast<unsigned long long>(d));
@@ -470,13 +471,16 @@ __global__ void k_level_reset(IncCounters* cnt, uint32_t parity) {
 // F_j starts as the base set B.
 __global__ void k_front_base(const uint32_t* __restrict__ blist, IncCounters* cnt, uint32_t parity, uint32_t tag,
                              uint32_t* fmark, uint32_t* flist, const uint32_t* __restrict__ row_off) {
+    __shared__ uint32_t s_app[kBlock / 64][kAppendBuf];
+    WaveAppender ap{s_app[threadIdx.x >> 6], flist, &cnt->f_count[parity], 0};
+    uint64_t deg = 0;
     const uint32_t nb = cnt->b_count;
     for (uint32_t i0 = blockIdx.x * kBlock; i0 < nb; i0 += gridDim.x * kBlock) {
         const uint32_t i = i0 + threadIdx.x;
         const bool valid = i < nb;
-        tag_append_deg(valid, valid ? blist[i] : 0u, tag, fmark, flist, &cnt->f_count[parity], row_off,
-                       cnt->out_sum[parity]);
+        tag_push(ap, deg, valid, valid ? blist[i] : 0u, tag, fmark, row_off);
     }
+    tag_finish(ap, deg, cnt->out_sum[parity]);
 }
 
 // F_j grows by the in-neighbours of C_{j-1}: the vertices of the previous
@@ -491,6 +495,9 @@ __global__ void k_front_innbrs(const uint32_t* __restrict__ prev, const uint32_t
                                const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
                                uint32_t tag, uint32_t* fmark, uint32_t* flist, IncCounters* cnt, uint32_t parity,
                                const uint32_t* __restrict__ row_off, uint64_t* chunks, uint64_t chunk_cap) {
+    __shared__ uint32_t s_app[kBlock / 64][kAppendBuf];
+    WaveAppender ap{s_app[threadIdx.x >> 6], flist, &cnt->f_count[parity], 0};
+    uint64_t deg = 0;
     const uint32_t np = prev_count ? *prev_count : prev_n;
     const uint32_t lane = lane_id();
     const uint32_t waves = gridDim.x * (kBlock / 64);
@@ -511,10 +518,10 @@ __global__ void k_front_innbrs(const uint32_t* __restrict__ prev, const uint32_t
         for (uint32_t j0 = a; j0 < b; j0 += 64) {
             const uint32_t j = j0 + lane;
             const bool valid = j < b;
-            tag_append_deg(valid, valid ? rev_src[j] : 0u, tag, fmark, flist, &cnt->f_count[parity], row_off,
-                           cnt->out_sum[parity]);
+            tag_push(ap, deg, valid, valid ? rev_src[j] : 0u, tag, fmark, row_off);
         }
     }
+    tag_finish(ap, deg, cnt->out_sum[parity]);
 }
 
 // The chunks that k_front_innbrs listed: one wave per chunk of kInChunk
@@ -523,6 +530,9 @@ __global__ void k_front_inchunks(const uint64_t* __restrict__ chunks, uint64_t c
                                  const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
                                  uint32_t tag, uint32_t* fmark, uint32_t* flist, IncCounters* cnt, uint32_t parity,
                                  const uint32_t* __restrict__ row_off) {
+    __shared__ uint32_t s_app[kBlock / 64][kAppendBuf];
+    WaveAppender ap{s_app[threadIdx.x >> 6], flist, &cnt->f_count[parity], 0};
+    uint64_t deg = 0;
     const uint32_t nc = static_cast<uint32_t>(min(static_cast<uint64_t>(cnt->in_chunk_count), chunk_cap));
     const uint32_t lane = lane_id();
     const uint32_t waves = gridDim.x * (kBlock / 64);
@@ -535,10 +545,10 @@ __global__ void k_front_inchunks(const uint64_t* __restrict__ chunks, uint64_t c
         for (uint32_t j0 = a; j0 < b; j0 += 64) {
             const uint32_t j = j0 + lane;
             const bool valid = j < b;
-            tag_append_deg(valid, valid ? rev_src[j] : 0u, tag, fmark, flist, &cnt->f_count[parity], row_off,
-                           cnt->out_sum[parity]);
+            tag_push(ap, deg, valid, valid ? rev_src[j] : 0u, tag, fmark, row_off);
         }
     }
+    tag_finish(ap, deg, cnt->out_sum[parity]);
 }
 
 struct FrontArgs {
@@ -565,21 +575,79 @@ struct FrontArgs {
     uint64_t* in_sum;         // kInStripes counters of this level
 };
 
-// Store h^j(v); a changed value tags v for the next level's frontier and
-// adds its in-degree to the bound on that frontier.
-__device__ __forceinline__ void publish(const FrontArgs& a, uint32_t v, uint64_t h) {
+// Store h^j(v); a changed value tags v for the next level's frontier.
+// Returns v's in-degree when the value changed (the caller adds it to the
+// bound on that frontier), else 0.
+__device__ __forceinline__ uint64_t publish(const FrontArgs& a, uint32_t v, uint64_t h) {
     if (a.h_cur[v] != h) {
         a.h_cur[v] = h;
         a.cflag[v] = a.tag;
-        if (v < a.n_rev)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.in_sum[v & (kInStripes - 1)]),
-                      static_cast<unsigned long long>(a.rev_off[v + 1] - a.rev_off[v]));
+        if (v < a.n_rev) return a.rev_off[v + 1] - a.rev_off[v];
     }
+    return 0;
 }
 
-// h^j of every frontier vertex: one wave per vertex of degree <= kSmallDeg,
-// de-duplicating its pair keys in a wave-private LDS region; larger vertices
-// are deferred to chunk blocks with a global table.
+__device__ __forceinline__ void add_in_sum(const FrontArgs& a, uint64_t x) {
+    if (x) atomicAdd(reinterpret_cast<unsigned long long*>(&a.in_sum[blockIdx.x & (kInStripes - 1)]),
+                     static_cast<unsigned long long>(x));
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, uint32_t src) {
+    const uint32_t lo = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(x)), static_cast<int>(src), 64));
+    const uint32_t hi = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(x >> 32)), static_cast<int>(src), 64));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// h^j of one alive frontier vertex with the whole wave: its pair keys
+// de-duplicated in the wave's LDS region (degree <= kSmallDeg), or the
+// vertex deferred to the chunk blocks with a global table (larger).  All
+// lanes of the wave call it with the same v.
+template <typename LabT>
+__device__ void front_vertex_wave(const FrontArgs& a, const LabT* __restrict__ lab, volatile uint64_t* tab,
+                                  uint32_t v, uint32_t lane, uint64_t& ins) {
+    const uint32_t e0 = a.row_off[v], deg = a.row_off[v + 1] - e0;
+    if (deg > kSmallDeg) {
+        if (lane == 0) {
+            const uint32_t nch = (deg + kChunkEdges - 1) / kChunkEdges;
+            const uint32_t slots = next_pow2_dev(2 * deg);
+            const uint32_t bi = atomicAdd(&a.cnt->big_count, 1u);
+            const uint32_t c0 = atomicAdd(&a.cnt->chunk_count, nch);
+            const uint64_t s0 = atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt->slot_top),
+                                          static_cast<unsigned long long>(slots));
+            a.big[bi] = BigEntry{v, c0, nch, slots, s0};
+            a.big_acc[bi] = 0;
+            a.big_done[bi] = 0;
+            for (uint32_t c = 0; c < nch; c++) a.chunk_owner[c0 + c] = bi;
+        }
+        return;
+    }
+    const uint32_t slots = max(64u, next_pow2_dev(2 * deg));
+    for (uint32_t j = lane; j < slots; j += 64) tab[j] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t acc = 0;
+    for (uint32_t j = lane; j < deg; j += 64) {
+        const uint32_t w = a.tgt[e0 + j];
+        const uint32_t l = static_cast<uint32_t>(lab[e0 + j]);
+        const uint64_t f = mix64((a.h_prev[w] ^ a.salt[l]) ^ kCE);
+        if (f != 0 && lds_insert(const_cast<uint64_t*>(tab), static_cast<uint32_t>(f) & (slots - 1), 0, slots, f))
+            acc += f;
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0) ins += publish(a, v, mix64(a.t[v] ^ mix64(kCS + acc)));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// h^j of every frontier vertex.  A wave takes kFrontGroups consecutive
+// frontier vertices at a time, kFrontLanes lanes each: a dead vertex, or
+// one of at most kFrontLanes out-edges, is done by its lane group alone
+// (one edge per lane, its keys de-duplicated by comparing every lane with
+// the earlier lanes of its group, the distinct keys summed across the
+// group).  The others then take the whole wave one after another
+// (front_vertex_wave).
 template <typename LabT>
 __global__ void __launch_bounds__(kBlock) k_front_hash(FrontArgs a) {
     __shared__ uint64_t s_tab[kBlock / 64][kWaveSlots];
@@ -588,48 +656,48 @@ __global__ void __launch_bounds__(kBlock) k_front_hash(FrontArgs a) {
     const uint32_t nf = *a.f_count;
     const uint32_t waves = gridDim.x * (kBlock / 64);
     const LabT* __restrict__ lab = static_cast<const LabT*>(a.lab);
-    for (uint32_t i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < nf; i += waves) {
-        const uint32_t v = a.flist[i];
-        if (!a.alive[v]) {
-            if (lane == 0) publish(a, v, 0);
-            continue;
+    const uint32_t j = lane % kFrontLanes, gbase = lane - j;
+    uint64_t ins = 0;  // in-degrees of the vertices whose hash changed
+    for (uint32_t i0 = ((blockIdx.x * kBlock + threadIdx.x) >> 6) * kFrontGroups; i0 < nf;
+         i0 += waves * kFrontGroups) {
+        const uint32_t i = i0 + lane / kFrontLanes;
+        const bool valid = i < nf;
+        const uint32_t v = valid ? a.flist[i] : 0u;
+        const bool live = valid && a.alive[v] != 0;
+        uint32_t e0 = 0, deg = 0;
+        if (live) {
+            e0 = a.row_off[v];
+            deg = a.row_off[v + 1] - e0;
         }
-        const uint32_t e0 = a.row_off[v], deg = a.row_off[v + 1] - e0;
-        if (deg > kSmallDeg) {
-            if (lane == 0) {
-                const uint32_t nch = (deg + kChunkEdges - 1) / kChunkEdges;
-                const uint32_t slots = next_pow2_dev(2 * deg);
-                const uint32_t bi = atomicAdd(&a.cnt->big_count, 1u);
-                const uint32_t c0 = atomicAdd(&a.cnt->chunk_count, nch);
-                const uint64_t s0 = atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt->slot_top),
-                                              static_cast<unsigned long long>(slots));
-                a.big[bi] = BigEntry{v, c0, nch, slots, s0};
-                a.big_acc[bi] = 0;
-                a.big_done[bi] = 0;
-                for (uint32_t c = 0; c < nch; c++) a.chunk_owner[c0 + c] = bi;
-            }
-            continue;
-        }
-        const uint32_t slots = max(64u, next_pow2_dev(2 * deg));
-        for (uint32_t j = lane; j < slots; j += 64) tab[j] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        uint64_t acc = 0;
-        for (uint32_t j = lane; j < deg; j += 64) {
+        const bool small = valid && deg <= kFrontLanes;
+        uint64_t f = 0;
+        if (small && j < deg) {
             const uint32_t w = a.tgt[e0 + j];
             const uint32_t l = static_cast<uint32_t>(lab[e0 + j]);
-            const uint64_t f = mix64((a.h_prev[w] ^ a.salt[l]) ^ kCE);
-            if (f != 0 && lds_insert(const_cast<uint64_t*>(tab), static_cast<uint32_t>(f) & (slots - 1), 0,
-                                     slots, f))
-                acc += f;
+            f = mix64((a.h_prev[w] ^ a.salt[l]) ^ kCE);
         }
-        acc = wave_sum_u64(acc);
-        if (lane == 0) publish(a, v, mix64(a.t[v] ^ mix64(kCS + acc)));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // a key counts at the first lane of its group that holds it (a key
+        // of 0 adds nothing either way)
+        bool dup = false;
+#pragma unroll
+        for (uint32_t t = 0; t < kFrontLanes; t++) {
+            const uint64_t o = shfl_u64(f, gbase + t);
+            dup |= t < j && o == f;
+        }
+        uint64_t acc = dup ? 0ull : f;
+#pragma unroll
+        for (int d = 1; d < static_cast<int>(kFrontLanes); d <<= 1) acc += shfl_xor_u64(acc, d);
+        if (small && j == 0) ins += publish(a, v, live ? mix64(a.t[v] ^ mix64(kCS + acc)) : 0ull);
+        uint64_t rest = __ballot(j == 0 && valid && !small);
+        while (rest) {
+            const uint32_t src = static_cast<uint32_t>(__ffsll(static_cast<long long>(rest)) - 1);
+            rest &= rest - 1;
+            const uint32_t vb = static_cast<uint32_t>(__shfl(static_cast<int>(v), static_cast<int>(src), 64));
+            front_vertex_wave<LabT>(a, lab, tab, vb, lane, ins);
+        }
     }
+    ins = wave_sum_u64(ins);
+    if (lane == 0) add_in_sum(a, ins);
 }
 
 __global__ void k_big_clear(IncCounters* cnt, uint64_t* scratch) {
@@ -684,7 +752,7 @@ __global__ void __launch_bounds__(kBlock) k_big_chunks(FrontArgs a) {
             if (s_last) {
                 __threadfence();
                 const uint64_t total = atomicAdd(reinterpret_cast<unsigned long long*>(&a.big_acc[bi]), 0ull);
-                publish(a, v, mix64(a.t[v] ^ mix64(kCS + total)));
+                add_in_sum(a, publish(a, v, mix64(a.t[v] ^ mix64(kCS + total))));
             }
         }
         __syncthreads();
@@ -1114,6 +1182,13 @@ std::vector<uint64_t> index_end(bsim_state* st) {
     return c;
 }
 
+// The most out-edges a frontier level may read before the level is
+// recomputed for all vertices (the deferred large vertices' table slots,
+// at most 4 per edge, are sized from it).
+uint64_t frontier_edge_limit(const bsim_ctx* ctx, uint64_t m) {
+    return ctx->frontier_limit_pct ? m * ctx->frontier_edge_pct / 100 + 4096 : 4096;
+}
+
 // Levels j0..K for every vertex with the refinement kernels (hash-only
 // mode): used when a frontier covers a large share of the graph, and as the
 // plain form (full recomputation per update).
@@ -1150,7 +1225,7 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
     hipStream_t s = st->s;
     const uint32_t n = st->n;
     const uint64_t limit = static_cast<uint64_t>(n) * st->ctx->frontier_limit_pct / 100;
-    const uint64_t edge_limit = static_cast<uint64_t>(st->m) * 3 * st->ctx->frontier_limit_pct / 100 + 4096;
+    const uint64_t edge_limit = frontier_edge_limit(st->ctx, st->m);
     if (st->ctx->frontier_limit_pct == 0) {
         if (st->K >= 1) full_levels(st, 1, arena);
         return;
@@ -1237,7 +1312,8 @@ void propagate(bsim_state* st, const uint32_t* d_tl, uint32_t nT, uint32_t tag0,
         a.rev_off = st->rev_off[st->rcur].p;
         a.n_rev = st->n_rev;
         a.in_sum = st->cnt.p->in_sum[par];
-        const uint32_t grid = std::max<uint32_t>(std::min<uint32_t>(ceil_div(fcount, kBlock / 64), kFrontGrid), 1);
+        const uint32_t grid =
+            std::max<uint32_t>(std::min<uint32_t>(ceil_div(fcount, kBlock / 64 * kFrontGroups), kFrontGrid), 1);
         if (lb == 2) k_front_hash<uint16_t><<<grid, kBlock, 0, s>>>(a);
         else k_front_hash<uint32_t><<<grid, kBlock, 0, s>>>(a);
         k_big_clear<<<256, kBlock, 0, s>>>(st->cnt.p, st->scratch.p);
@@ -1337,8 +1413,7 @@ void reserve_batch(bsim_state* st, const HostBatch& hb, ResultReserve& rr) {
     }
     ensure_salt(st, std::max(st->max_label, hb.max_label));
     st->chunk_owner.ensure(static_cast<size_t>(n_new) + m_cap / kChunkEdges + 2, 0, s);
-    const uint64_t pct = st->ctx->frontier_limit_pct;
-    st->scratch.ensure(4 * (m_cap * 3 * pct / 100 + 4096) + 1024, 0, s);
+    st->scratch.ensure(4 * frontier_edge_limit(st->ctx, m_cap) + 1024, 0, s);
     // the workspace: uploads of the batch, merge flags and scans, the
     // staging of full levels, the reverse-list sort and finalize
     const uint64_t items = hb.cu.size() + hb.rw.size() + hb.rgw.size() + hb.tl.size() + hb.tl_ids.size() +
@@ -1537,7 +1612,7 @@ bsim_result* create_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_par
     st->rs.vtype.assign(st->rs.vmark.size(), 0);
     // the frontier scratch up to the frontier edge limit (4 slots per edge),
     // allocated here rather than in an update's latency
-    st->scratch.ensure(4 * (static_cast<uint64_t>(st->m) * 3 * ctx->frontier_limit_pct / 100 + 4096) + 1024, 0, s);
+    st->scratch.ensure(4 * frontier_edge_limit(ctx, st->m) + 1024, 0, s);
     // the workspace of an update's temporary arrays (the full-level staging
     // and the merges take about 8 B per edge and 8 B per vertex), and the
     // second copies of the CSR and type arrays that the first merges write,

@@ -37,7 +37,7 @@ def state_rows(sg, vs):
     return rows, types, alive
 
 
-@pytest.mark.parametrize("pct", [2, 0])
+@pytest.mark.parametrize("pct", [10, 2, 0])
 def test_rmat24_batches_equal_batch_summary(pct):
     dg = devgen.make_device_config("rmat24")
     host = dg.to_host()

@@ -100,19 +100,22 @@ def test_each_operation_kind():
 
 
 class FrontierLimit:
-    """Set the ctx option frontier_limit_pct for the duration of a test:
-    100 keeps every level on the frontier kernels, 0 recomputes every level
-    for all vertices (the plain form), values between switch mid-batch."""
+    """Set the ctx options frontier_limit_pct (and frontier_edge_pct) for the
+    duration of a test: 100 keeps every level on the frontier kernels, 0
+    recomputes every level for all vertices (the plain form), values between
+    switch mid-batch."""
 
-    def __init__(self, pct):
-        self.pct = pct
+    def __init__(self, pct, edge_pct=100):
+        self.pct, self.edge_pct = pct, edge_pct
 
     def __enter__(self):
-        self.old = ctx().get_option("frontier_limit_pct")
+        self.old = ctx().get_option("frontier_limit_pct"), ctx().get_option("frontier_edge_pct")
         ctx().set_option("frontier_limit_pct", self.pct)
+        ctx().set_option("frontier_edge_pct", self.edge_pct)
 
     def __exit__(self, *exc):
-        ctx().set_option("frontier_limit_pct", self.old)
+        ctx().set_option("frontier_limit_pct", self.old[0])
+        ctx().set_option("frontier_edge_pct", self.old[1])
 
 
 @pytest.mark.parametrize("pct", [100, 10, 0])
@@ -135,12 +138,13 @@ def test_rmat_updates_switch_to_full_levels():
     # frontier limit then hands the remaining levels to the full kernels
     rng = np.random.default_rng(71)
     g = gg.rmat_graph(13, 1 << 16, n_types=16, n_labels=8, seed=12)
-    for pct in (2, 30):
-        with FrontierLimit(pct):
+    # (the vertex limit, the edge limit): the edge limit alone also switches
+    for pct, edge_pct in ((2, 100), (30, 100), (100, 1), (10, 15)):
+        with FrontierLimit(pct, edge_pct):
             s = Session(g, 4)
             for i in range(4):
                 d = gg.update_ops(s.g, rng, int(rng.integers(5, 500)), n_labels=8, n_types=16, rmat_scale=13)
-                s.apply(gg.ops_as_tuples(d), what=("rmat", pct, i))
+                s.apply(gg.ops_as_tuples(d), what=("rmat", pct, edge_pct, i))
             s.close()
 
 
@@ -162,13 +166,19 @@ def test_untyped_and_fixpoint_stop():
 
 @pytest.mark.parametrize("pct", [100, 0])
 def test_frontier_through_large_vertices(pct):
-    # vertices of degree above the wave limit take the chunked global-table path
+    # vertices of degree above the wave limit take the chunked global-table
+    # path; degrees around the lane-group width (16) take the group path or
+    # the whole wave
     rng = np.random.default_rng(31)
     n = 3000
-    src = [np.full(d, v) for v, d in enumerate([600, 5000, 9000, 513, 512])]
+    degs = [600, 5000, 9000, 513, 512, 16, 17, 15, 32, 1]
+    src = [np.full(d, v) for v, d in enumerate(degs)]
     dst = [rng.integers(0, n, size=len(x)) for x in src]
     lab = [rng.integers(0, 6, size=len(x)) for x in src]
-    src.append(rng.integers(5, n, size=12000))
+    # repeated pairs inside a group: vertex 5's 16 edges use 3 targets and 2 labels
+    dst[5] = rng.integers(0, 3, size=16)
+    lab[5] = rng.integers(0, 2, size=16)
+    src.append(rng.integers(len(degs), n, size=12000))
     dst.append(rng.integers(0, n, size=12000))
     lab.append(rng.integers(0, 6, size=12000))
     g = gg.from_edges(n, np.concatenate(src), np.concatenate(dst), np.concatenate(lab),
@@ -181,6 +191,9 @@ def test_frontier_through_large_vertices(pct):
             s.apply(gg.ops_as_tuples(d), what=("large", i))
         s.apply([("add_e", 1, 5, 7), ("del_e", 2, int(s.g.lab[s.g.row_off[2]]), int(s.g.tgt[s.g.row_off[2]]))],
                 what="large rows")
+        # the rows at the group width change: 16 -> 17 and 17 -> 16 edges
+        s.apply([("add_e", 5, 5, 11), ("del_e", 6, int(s.g.lab[s.g.row_off[6]]), int(s.g.tgt[s.g.row_off[6]]))],
+                what="group width rows")
         s.close()
 
 
