@@ -296,14 +296,14 @@ def incremental_leg(args, binding, gg, torch, g, dg, workload=None, rmat_endpoin
             r = st.apply(batch)
             lat.append((time.perf_counter() - t) * 1e3)
             nb[id(st)] = r.n_blocks
-            ph[id(st)] = (r.ms_stage, r.ms_iterate, r.ms_finalize)
+            ph[id(st)] = (r.ms_resolve, r.ms_stage, r.ms_iterate, r.ms_finalize)
             r.free()
         if nb[id(st_i)] != nb[id(st_p)]:
             raise RuntimeError("incremental and full recomputation disagree on batch %d" % i)
         ops_total += size
         sizes.append(size)
         print("# update batch %d (k=%d): %d ops, incremental %.2f ms, full recomputation %.2f ms "
-              "(device phases merge/levels/finalize %.1f/%.1f/%.1f and %.1f/%.1f/%.1f ms)"
+              "(host op resolution, then device merge/levels/finalize: %.1f, %.1f/%.1f/%.1f and %.1f, %.1f/%.1f/%.1f ms)"
               % ((i, k, size, lat_i[-1], lat_p[-1]) + ph[id(st_i)] + ph[id(st_p)]), file=sys.stderr, flush=True)
 
     # change detection: the ordered batch between the first snapshot and

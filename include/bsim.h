@@ -172,6 +172,9 @@ typedef struct {
     uint32_t n_timed_launches; /* launches those sums cover */
     uint32_t n_split_launches; /* refinement launches run as a split half and a
                                   hash half (ctx option "tail_split_ppm") */
+    float ms_resolve;      /* bsim_apply_updates: host time of the batch's op
+                              resolution (validation and net changes), before
+                              any device work; 0 for the other calls */
     void* priv;
 } bsim_result;
 

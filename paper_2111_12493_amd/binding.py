@@ -51,7 +51,8 @@ class BsimResult(ctypes.Structure):
                 ("se_dst", _p), ("ms_stage", ctypes.c_float), ("ms_iterate", ctypes.c_float),
                 ("ms_finalize", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_iter_kernels", ctypes.c_float), ("ms_hub_kernels", ctypes.c_float),
-                ("n_timed_launches", _u32), ("n_split_launches", _u32), ("priv", _p)]
+                ("n_timed_launches", _u32), ("n_split_launches", _u32), ("ms_resolve", ctypes.c_float),
+                ("priv", _p)]
 
 
 class BsimUpdate(ctypes.Structure):
@@ -276,6 +277,7 @@ class Result:
         self.ms_hub_kernels = r.ms_hub_kernels
         self.n_timed_launches = r.n_timed_launches
         self.n_split_launches = r.n_split_launches
+        self.ms_resolve = r.ms_resolve
 
     def _len(self, field):
         if field in ("hashes", "block_ids"):

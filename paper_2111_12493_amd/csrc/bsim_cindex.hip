@@ -15,13 +15,16 @@
 // removed, so probe chains stay intact; a table whose claimed slots pass a
 // load limit is rebuilt from scratch.
 //
-// Table layout: word[s] = 0 (empty) or (pc << 32) | owner, pc = level j-1
-// class + 1 (1 at level 0); key_h[s] = the key's hash; cnt[s] = members.
-// A vertex's class id at level j is the slot of its key.
+// Table layout: slot s is the pair (word, key) at slot[2 s], slot[2 s + 1]:
+// word = 0 (empty) or (pc << 32) | owner, pc = level j-1 class + 1 (1 at
+// level 0), key = the key's hash, so one probe reads one 16-byte line;
+// cnt[s] = members.  A vertex's class id at level j is the slot of its key.
 //
-// Rebuild (all vertices): one insertion pass in which every key compares
-// against the owner vertex's hash in the level array (immutable during the
-// pass), then key_h is filled from the owners.  Incremental update (a list
+// Rebuild (all vertices): one insertion pass over a cleared table.  The
+// vertex that claims a slot writes the key after its CAS on the word; a
+// prober that finds the word already set but the key still 0 compares
+// against the owner's hash in the level array instead (immutable during
+// the pass, and the key's source).  Incremental update (a list
 // of vertices): a read-only probe; the misses are de-duplicated in a small
 // temporary table; one representative per new key claims an empty slot in
 // a later kernel (no reader probes concurrently, and the keys are distinct
@@ -65,6 +68,36 @@ __device__ uint32_t ci_join_owner(uint64_t* word, uint32_t mask, const uint64_t*
     }
 }
 
+// The slot of key (pc, h) in a level table during a rebuild, claiming an
+// empty one for it when absent (*founded = 1); keys[owner] is the owner's
+// hash for a slot whose key is not written yet (see above).
+__device__ uint32_t ci_join_level(const CiLevel& L, const uint64_t* __restrict__ keys, uint32_t pc, uint64_t h,
+                                  uint32_t owner, uint32_t* founded) {
+    const uint64_t mine = (static_cast<uint64_t>(pc) << 32) | owner;
+    uint32_t slot = ci_home(pc, h, L.mask);
+    *founded = 0;
+    for (;;) {
+        const ulonglong2 sk = *reinterpret_cast<const ulonglong2*>(&L.slot[2ull * slot]);  // a stale pair only costs the CAS
+        uint64_t cur = sk.x;
+        uint64_t key = sk.y;
+        if (cur == 0) {
+            cur = atomicCAS(reinterpret_cast<unsigned long long*>(&L.slot[2ull * slot]), 0ull,
+                            static_cast<unsigned long long>(mine));
+            if (cur == 0) {
+                L.slot[2ull * slot + 1] = h;
+                *founded = 1;
+                return slot;
+            }
+            key = 0;  // claimed meanwhile: its key may not be written yet
+        }
+        if ((cur >> 32) == pc) {
+            if (key == 0) key = keys[static_cast<uint32_t>(cur)];
+            if (key == h) return slot;
+        }
+        slot = (slot + 1) & L.mask;
+    }
+}
+
 // Rebuild: every alive vertex joins the class of (its level j-1 class, h^j).
 // Lanes of a wave with one key (every vertex without out-edges of one type
 // set and class, say) reach the table once.
@@ -103,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) k_ci_build(CiLevel L, const uint32_t* 
     }
     const bool lead = part && leader_of == lane;
     uint32_t slot = 0, founded = 0;
-    if (lead) slot = ci_join_owner(L.word, L.mask, h, pc, hv, v, &founded);
+    if (lead) slot = ci_join_level(L, h, pc, hv, v, &founded);
     slot = static_cast<uint32_t>(__shfl(static_cast<int>(slot), static_cast<int>(leader_of), 64));
     if (part) L.cid[v] = slot;
     // each leader adds its group's size
@@ -118,15 +151,6 @@ __global__ void __launch_bounds__(kBlock) k_ci_build(CiLevel L, const uint32_t* 
     if (threadIdx.x == 0 && c) {
         atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[0]), static_cast<unsigned long long>(c));
         atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[1]), static_cast<unsigned long long>(c));
-    }
-}
-
-// After a rebuild: each claimed slot's key hash from its owner.
-__global__ void __launch_bounds__(kBlock) k_ci_keys(CiLevel L, const uint64_t* __restrict__ h, uint64_t cap) {
-    for (uint64_t s = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; s < cap;
-         s += static_cast<uint64_t>(gridDim.x) * kBlock) {
-        const uint64_t w = L.word[s];
-        if (w) L.key_h[s] = h[static_cast<uint32_t>(w)];
     }
 }
 
@@ -189,12 +213,12 @@ __global__ void __launch_bounds__(kBlock) k_ci_probe(CiLevel L, const uint32_t* 
                     ns[i] = kNoClass;
                     break;
                 }
-                const uint64_t w = L.word[slot];
-                if (w == 0) {
+                const ulonglong2 sk = *reinterpret_cast<const ulonglong2*>(&L.slot[2ull * slot]);
+                if (sk.x == 0) {
                     miss = true;
                     break;
                 }
-                if ((w >> 32) == pc && L.key_h[slot] == hv) {
+                if ((sk.x >> 32) == pc && sk.y == hv) {
                     ns[i] = slot;
                     break;
                 }
@@ -246,14 +270,14 @@ __global__ void __launch_bounds__(kBlock) k_ci_claim(CiLevel L, const uint32_t* 
                 slot = kNoClass;
                 break;
             }
-            if (L.word[slot] == 0 &&
-                atomicCAS(reinterpret_cast<unsigned long long*>(&L.word[slot]), 0ull,
+            if (L.slot[2ull * slot] == 0 &&
+                atomicCAS(reinterpret_cast<unsigned long long*>(&L.slot[2ull * slot]), 0ull,
                           static_cast<unsigned long long>(mine)) == 0ull)
                 break;
             slot = (slot + 1) & L.mask;
         }
         if (slot != kNoClass) {
-            L.key_h[slot] = hv;
+            L.slot[2ull * slot + 1] = hv;
             claimed = 1;
         }
         rslot[p] = slot;
@@ -312,11 +336,10 @@ __global__ void __launch_bounds__(kBlock) k_ci_move(CiLevel L, const uint32_t* _
 
 void ci_rebuild(const CiLevel& L, uint64_t cap, const uint32_t* cid_prev, const uint64_t* h, const uint8_t* alive,
                 uint32_t n, uint64_t* ctr, hipStream_t s) {
-    hip_check(hipMemsetAsync(L.word, 0, cap * sizeof(uint64_t), s), "class index clear");
+    hip_check(hipMemsetAsync(L.slot, 0, 2 * cap * sizeof(uint64_t), s), "class index clear");
     hip_check(hipMemsetAsync(L.cnt, 0, cap * sizeof(uint32_t), s), "class index counts");
     hip_check(hipMemsetAsync(ctr, 0, 2 * sizeof(uint64_t), s), "class index counters");
     if (n) k_ci_build<<<ceil_div(n, kBlock), kBlock, 0, s>>>(L, cid_prev, h, alive, n, ctr);
-    k_ci_keys<<<static_cast<uint32_t>(std::min<uint64_t>(ceil_div(cap, kBlock), 8192)), kBlock, 0, s>>>(L, h, cap);
     hip_check(hipGetLastError(), "class index rebuild");
 }
 

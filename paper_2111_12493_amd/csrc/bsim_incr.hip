@@ -23,9 +23,15 @@
 //      holds the vertices whose own inputs changed (types or out-edge set)
 //      and C_{j-1} the vertices whose h^{j-1} changed.  Every other vertex
 //      keeps h^j: all its inputs are unchanged;
-//   4. device: classes of levels 0..K from the stored levels, the fixpoint
-//      rule, and finalize (block ids, sizes, summary edges) as in batch.
+//      A level whose frontier passes the ctx's limits (a share of the
+//      vertices or of the out-edges) is recomputed for all vertices, and so
+//      is every later one;
+//   4. device: the class index of every level (bsim_cindex.hip) follows the
+//      vertices whose hash or previous-level class changed, or is rebuilt
+//      after a level recomputed in full; then the fixpoint rule and
+//      finalize (block ids, sizes, summary edges) as in batch.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -84,23 +90,14 @@ __device__ __forceinline__ uint32_t next_pow2_dev(uint32_t x) {
     return x <= 1 ? 1u : 1u << (32 - __clz(static_cast<int>(x - 1)));
 }
 
-__device__ __forceinline__ void wave_append(bool pred, uint32_t val, uint32_t* list, uint32_t* count) {
-    const uint64_t b = __ballot(pred);
-    if (!b) return;
-    const uint32_t lane = lane_id();
-    const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(b)) - 1);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(count, static_cast<uint32_t>(__popcll(b)));
-    base = static_cast<uint32_t>(__shfl(static_cast<int>(base), static_cast<int>(leader), 64));
-    if (pred) list[base + static_cast<uint32_t>(__popcll(b & ((1ull << lane) - 1)))] = val;
-}
-
-// Set mark[v] once; the first setter appends v to the list.
-__device__ __forceinline__ void mark_append(bool valid, uint32_t v, uint32_t* mark, uint32_t* list,
-                                            uint32_t* count) {
+// Set mark[v] once; the first setter appends v to the list (one atomic on
+// the count per block; every thread of the block calls it).
+__device__ __forceinline__ void block_mark_append(bool valid, uint32_t v, uint32_t* mark, uint32_t* list,
+                                                  uint32_t* count, uint32_t* s_wave) {
     bool first = false;
     if (valid && *reinterpret_cast<volatile uint32_t*>(&mark[v]) == 0) first = atomicOr(&mark[v], 1u) == 0;
-    wave_append(first, v, list, count);
+    const uint32_t pos = block_reserve(first, count, s_wave);
+    if (first) list[pos] = v;
 }
 
 // Tag v for this level (valid lanes); the first tagger lists v through the
@@ -199,6 +196,7 @@ __global__ void k_mark_groups(const uint32_t* __restrict__ gsrc, const uint32_t*
                               const uint32_t* __restrict__ gend, uint32_t ng, uint32_t* dflag,
                               uint32_t* chg_lo, uint32_t* chg_hi, uint32_t* bmark, uint32_t* blist,
                               IncCounters* cnt) {
+    __shared__ uint32_t s_wave[kBlock / 64 + 1];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     const bool valid = i < ng;
     uint32_t u = 0;
@@ -208,7 +206,7 @@ __global__ void k_mark_groups(const uint32_t* __restrict__ gsrc, const uint32_t*
         chg_lo[u] = gbeg[i];
         chg_hi[u] = gend[i];
     }
-    mark_append(valid, u, bmark, blist, &cnt->b_count);
+    block_mark_append(valid, u, bmark, blist, &cnt->b_count, s_wave);
 }
 
 __global__ void k_clear_groups(const uint32_t* __restrict__ gsrc, uint32_t ng, uint32_t* chg_lo,
@@ -226,29 +224,35 @@ __global__ void k_mark_dead(const uint32_t* __restrict__ dead, uint32_t nd,
                             const uint32_t* __restrict__ rev_off, const uint32_t* __restrict__ rev_src,
                             uint32_t n_rev, uint32_t* dflag, uint32_t* bmark, uint32_t* blist,
                             IncCounters* cnt) {
+    __shared__ uint32_t s_app[kBlock / 64][kAppendBuf];
     const uint32_t lane = lane_id();
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-    if (wave >= nd) return;
+    if (wave >= nd) return;  // the whole wave
     const uint32_t d = dead[wave];
     if (lane == 0) atomicOr(&dflag[d], kFlagRows);
-    if (d >= n_rev) return;
+    if (d >= n_rev) return;  // the whole wave
+    WaveAppender ap{s_app[threadIdx.x >> 6], blist, &cnt->b_count, 0};
     const uint32_t a = rev_off[d], b = rev_off[d + 1];
     for (uint32_t j0 = a; j0 < b; j0 += 64) {
         const uint32_t j = j0 + lane;
         const bool valid = j < b;
+        bool first = false;
         uint32_t s = 0;
         if (valid) {
             s = rev_src[j];
             if ((*reinterpret_cast<volatile uint32_t*>(&dflag[s]) & kFlagRows) == 0)
                 atomicOr(&dflag[s], kFlagRows);
+            first = *reinterpret_cast<volatile uint32_t*>(&bmark[s]) == 0 && atomicOr(&bmark[s], 1u) == 0;
         }
-        mark_append(valid, s, bmark, blist, &cnt->b_count);
+        ap.push(first, s);
     }
+    ap.flush();
 }
 
 // Vertices whose type set changes (new, modified, deleted).
 __global__ void k_mark_types(const uint32_t* __restrict__ tl, uint32_t nT, uint32_t* dflag,
                              uint32_t* tidx, uint32_t* bmark, uint32_t* blist, IncCounters* cnt) {
+    __shared__ uint32_t s_wave[kBlock / 64 + 1];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     const bool valid = i < nT;
     uint32_t v = 0;
@@ -257,7 +261,7 @@ __global__ void k_mark_types(const uint32_t* __restrict__ tl, uint32_t nT, uint3
         atomicOr(&dflag[v], kFlagTypes);
         tidx[v] = i + 1;
     }
-    mark_append(valid, v, bmark, blist, &cnt->b_count);
+    block_mark_append(valid, v, bmark, blist, &cnt->b_count, s_wave);
 }
 
 __global__ void k_clear_tidx(const uint32_t* __restrict__ tl, uint32_t nT, uint32_t* tidx) {
@@ -827,7 +831,7 @@ struct bsim_state {
     // the class slot of every vertex; per level the counters (classes,
     // claimed slots); the vertex list of an update and the lists of the
     // vertices whose class changed (by level parity), with their counts
-    std::vector<DevBuf<uint64_t>> ci_word, ci_keyh;
+    std::vector<DevBuf<uint64_t>> ci_slot;
     std::vector<DevBuf<uint32_t>> ci_cnt, ci_cid;
     uint64_t ci_cap = 0;
     DevBuf<uint64_t> ci_ctr;
@@ -870,8 +874,7 @@ struct bsim_state {
         blist.release(s), kpos.release(s), chunk_owner.release(s);
         big_done.release(s), big.release(s), big_acc.release(s), scratch.release(s), cnt.release(s);
         status.release(s), work.release(s);
-        for (auto& b : ci_word) b.release(s);
-        for (auto& b : ci_keyh) b.release(s);
+        for (auto& b : ci_slot) b.release(s);
         for (auto& b : ci_cnt) b.release(s);
         for (auto& b : ci_cid) b.release(s);
         ci_ctr.release(s), ci_dmark.release(s), ci_d.release(s), ci_q[0].release(s), ci_q[1].release(s);
@@ -914,7 +917,7 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
     st->big_acc.ensure(nv, 0, s);
     // class index: the new vertices have no class and no list mark yet
     const size_t L = static_cast<size_t>(st->K) + 1;
-    st->ci_word.resize(L), st->ci_keyh.resize(L), st->ci_cnt.resize(L), st->ci_cid.resize(L);
+    st->ci_slot.resize(L), st->ci_cnt.resize(L), st->ci_cid.resize(L);
     for (auto& c : st->ci_cid) {
         c.ensure(nv, keep_v, s);
         hip_check(hipMemsetAsync(c.p + keep_v, 0xFF, (nv - keep_v) * 4, s), "new classes");
@@ -929,8 +932,7 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
     const uint64_t want = split_table_slots(static_cast<uint64_t>(n_new));
     if (want > st->ci_cap) {
         for (size_t j = 0; j < L; j++) {
-            st->ci_word[j].ensure(want, 0, s);
-            st->ci_keyh[j].ensure(want, 0, s);
+            st->ci_slot[j].ensure(2 * want, 0, s);
             st->ci_cnt[j].ensure(want, 0, s);
         }
         st->ci_cap = want;
@@ -1114,8 +1116,7 @@ void merge_reverse(bsim_state* st, const HostBatch& hb, Arena& arena) {
 // The class passes of an update, level by level as the levels become final.
 CiLevel ci_level(bsim_state* st, uint32_t j) {
     CiLevel L;
-    L.word = st->ci_word[j].p;
-    L.key_h = st->ci_keyh[j].p;
+    L.slot = st->ci_slot[j].p;
     L.cnt = st->ci_cnt[j].p;
     L.cid = st->ci_cid[j].p;
     L.mask = static_cast<uint32_t>(st->ci_cap - 1);
@@ -1683,8 +1684,7 @@ uint64_t state_bytes(const bsim_state* st) {
     add(st->chg_hi), add(st->tidx), add(st->kept), add(st->deg), add(st->blist), add(st->cflag);
     add(st->kpos), add(st->chunk_owner), add(st->big_done), add(st->big), add(st->big_acc);
     add(st->scratch), add(st->work);
-    for (const auto& x : st->ci_word) add(x);
-    for (const auto& x : st->ci_keyh) add(x);
+    for (const auto& x : st->ci_slot) add(x);
     for (const auto& x : st->ci_cnt) add(x);
     for (const auto& x : st->ci_cid) add(x);
     add(st->ci_ctr), add(st->ci_dmark), add(st->ci_d), add(st->ci_q[0]), add(st->ci_q[1]), add(st->ci_n);
@@ -1885,8 +1885,11 @@ int bsim_apply_updates(bsim_state* st, const bsim_update* ops, uint64_t n_ops, b
     if (!st || !out || (n_ops && !ops)) return BSIM_E_INVALID;
     try {
         hip_check(hipSetDevice(st->ctx->device), "set device");
-        HostBatch hb = resolve_ops(st->n, st->label_bytes, st->alive_host, st->rs, ops, n_ops);
+        const auto t0 = std::chrono::steady_clock::now();
+        const HostBatch& hb = resolve_ops_into(st->rs.hb, st->n, st->label_bytes, st->alive_host, st->rs, ops, n_ops);
+        const float ms_resolve = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = apply_batch(st, hb);
+        (*out)->ms_resolve = ms_resolve;
         return BSIM_OK;
     } catch (const DeviceError& e) {
         st->ctx->err = e.msg;

@@ -485,8 +485,8 @@ struct FinalOut {
 // member counts, and the class (table slot) of every vertex.
 constexpr uint32_t kNoClass = 0xFFFFFFFFu;
 struct CiLevel {
-    uint64_t* word;   // [cap] 0 = empty, else (level j-1 class + 1) << 32 | owner
-    uint64_t* key_h;  // [cap] the key's hash
+    uint64_t* slot;   // [2 cap] pairs: slot[2 s] = 0 (empty) or (level j-1 class + 1) << 32 | owner,
+                      // slot[2 s + 1] = the key's hash (one 16-byte line per probe)
     uint32_t* cnt;    // [cap] members
     uint32_t* cid;    // [vertices] class slot, kNoClass for a dead vertex
     uint32_t mask;    // cap - 1

@@ -33,27 +33,43 @@ struct HostBatch {
     uint64_t n_present = 0;                    // changes that end present (upper bound of appends)
 };
 
+// One edge operation's record: (u, w, l) and whether it adds the triple.
+struct ResolveRec {
+    uint32_t u, w, l, add;
+};
+
 // Per-vertex marks of the resolution, kept between calls so a batch costs
 // O(batch) rather than O(n): vmark[v] = 0 untouched, 1 alive with a vertex
-// op, 2 deleted; vtype[v] = 1 + index of v's new type list (0: none).
+// op, 2 deleted; vtype[v] = 1 + index of v's new type list (0: none).  The
+// other members are buffers reused from batch to batch: a large batch
+// spends much of its host time on first touches of freshly allocated
+// memory otherwise.
 struct ResolveScratch {
     std::vector<uint8_t> vmark;
     std::vector<uint32_t> vtype;
+    std::vector<std::vector<ResolveRec>> part;  // edge records per thread
+    std::vector<ResolveRec> recs;
+    std::vector<uint64_t> key, key2;
+    std::vector<uint32_t> val, val2;
+    HostBatch hb;  // the result of resolve_ops_into
 };
 
 // Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
 // Large inputs are split over host threads: per pass, every thread counts
 // the digits of its share, one prefix over (digit, thread) places them, and
 // every thread scatters its share (so equal digits keep their order).
-inline void host_radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int bits) {
+// k2 and v2 are buffers of the caller (resized to n; their contents are
+// lost).
+inline void host_radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int bits,
+                            std::vector<uint64_t>& k2, std::vector<uint32_t>& v2) {
     constexpr int kDigit = 11;
     constexpr uint32_t kBuckets = 1u << kDigit;
     const size_t n = key.size();
     if (n < 2) return;
     const unsigned hw = std::thread::hardware_concurrency();
     const size_t T = std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hw ? hw : 1), 8, n / 65536}));
-    std::vector<uint64_t> k2(n);
-    std::vector<uint32_t> v2(n);
+    k2.resize(n);
+    v2.resize(n);
     std::vector<uint32_t> cnt(kBuckets * T);
     auto par = [&](auto f) {
         std::vector<std::thread> th;
@@ -102,9 +118,16 @@ inline void host_radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& v
 // sorted, so a batch of 10^6 operations resolves in tens of milliseconds.
 // Throws DeviceError for an invalid batch (out-of-range ids or labels,
 // deleted vertices named, too many types, unknown op codes).
-inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vector<uint8_t>& alive,
-                             ResolveScratch& rs, const bsim_update* ops, uint64_t n_ops) {
-    HostBatch hb;
+// The same into hb (its vectors are cleared first; their capacity is kept).
+inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_bytes,
+                                   const std::vector<uint8_t>& alive, ResolveScratch& rs, const bsim_update* ops,
+                                   uint64_t n_ops) {
+    for (std::vector<uint32_t>* v : {&hb.cu, &hb.cw, &hb.cl, &hb.cf, &hb.gsrc, &hb.gbeg, &hb.gend, &hb.rw, &hb.ru,
+                                     &hb.rgw, &hb.rgbeg, &hb.rgend, &hb.tl, &hb.tl_off, &hb.tl_ids, &hb.dead})
+        v->clear();
+    hb.n_new = 0;
+    hb.max_label = 0;
+    hb.n_present = 0;
     uint32_t n_cur = n0;
     std::vector<uint8_t>& vmark = rs.vmark;
     std::vector<uint32_t>& vtype = rs.vtype;
@@ -122,11 +145,9 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
         const uint8_t m = vmark[v];
         return m ? m == 1 : alive[v] != 0;
     };
-    struct Rec {
-        uint32_t u, w, l, add;
-    };
-    std::vector<Rec> recs;
-    recs.reserve(n_ops + n_ops / 8);
+    using Rec = ResolveRec;
+    std::vector<Rec>& recs = rs.recs;
+    recs.clear();
     const uint64_t lab_lim = label_bytes == 2 ? (1ull << 16) : (1ull << 24);
     uint32_t max_l = 0;
     auto touch = [&](uint32_t v, uint8_t state) {
@@ -148,73 +169,154 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
             for (uint32_t v : touched) vmark[v] = 0, vtype[v] = 0;
         }
     } clear_marks{touched, vmark, vtype};
-    {
-        // the per-vertex marks and the alive mask are read at random: the
-        // marks of the operation kPf places ahead are fetched meanwhile
-        constexpr uint64_t kPf = 24;
-        auto prefetch = [&](const bsim_update& o) {
-            const size_t lim = std::min(vmark.size(), alive.size());
-            if (!lim) return;
-            const size_t u = std::min<size_t>(o.u, lim - 1), w = std::min<size_t>(o.w, lim - 1);
-            __builtin_prefetch(&vmark[u]);
-            __builtin_prefetch(&alive[u]);
-            __builtin_prefetch(&vmark[w]);
-            __builtin_prefetch(&alive[w]);
-        };
-        for (uint64_t i = 0; i < n_ops && i < kPf; i++) prefetch(ops[i]);
-        for (uint64_t i = 0; i < n_ops; i++) {
-            if (i + kPf < n_ops) prefetch(ops[i + kPf]);
-            const bsim_update& o = ops[i];
-            const bool edge = o.op == BSIM_OP_ADD_E || o.op == BSIM_OP_DEL_E || o.op == BSIM_OP_MOD_E;
-            // checks in the order: ids in range, ids alive, types, labels
-            if (o.op == BSIM_OP_MOD_V || o.op == BSIM_OP_DEL_V || edge) {
-                if (o.u >= n_cur || (edge && o.w >= n_cur))
-                    throw DeviceError{BSIM_E_RANGE, "vertex id out of range in update"};
-                if (!alive_now(o.u) || (edge && !alive_now(o.w)))
-                    throw DeviceError{BSIM_E_INVALID, "update names a deleted vertex"};
+    // Which ids exist and live changes only with the vertex operations, so
+    // they run first, in order, up to the first invalid one; every edge
+    // operation is then checked against the positions of those changes, on
+    // several threads.  The batch's error is the one of its first invalid
+    // operation, as in a sequential pass.
+    struct Fail {
+        uint64_t pos = UINT64_MAX;
+        int status = BSIM_OK;
+        const char* msg = nullptr;
+    };
+    Fail vfail;
+    std::vector<uint64_t> add_pos;                     // ADD_V positions, by new id - n0
+    std::vector<std::pair<uint32_t, uint64_t>> dels;   // (vertex, DEL_V position)
+    for (uint64_t i = 0; i < n_ops && vfail.pos == UINT64_MAX; i++) {
+        const bsim_update& o = ops[i];
+        const uint32_t op = o.op;
+        if (op >= BSIM_OP_ADD_E && op <= BSIM_OP_DEL_E) continue;
+        auto fail = [&](int st, const char* msg) { vfail = Fail{i, st, msg}; };
+        if (op < BSIM_OP_ADD_V || op > BSIM_OP_DEL_E) {
+            fail(BSIM_E_INVALID, "unknown update op code");
+            break;
+        }
+        // checks in the order: ids in range, ids alive, types
+        if (op != BSIM_OP_ADD_V) {
+            if (o.u >= n_cur) {
+                fail(BSIM_E_RANGE, "vertex id out of range in update");
+                break;
             }
-            if (o.op == BSIM_OP_ADD_V || o.op == BSIM_OP_MOD_V) {
-                if (o.n_types > kMaxStateTypes) throw DeviceError{BSIM_E_UNSUPPORTED, "more than 4096 types on a vertex"};
-                if (o.n_types && !o.types) throw DeviceError{BSIM_E_INVALID, "types pointer is NULL"};
-            }
-            switch (o.op) {
-                case BSIM_OP_ADD_V: {
-                    if (n_cur >= 0xFFFFFFF0u) throw DeviceError{BSIM_E_UNSUPPORTED, "too many vertices"};
-                    const uint32_t v = n_cur++;
-                    grow(n_cur);
-                    touch(v, 1);
-                    set_types(v, o);
-                    break;
-                }
-                case BSIM_OP_MOD_V:
-                    touch(o.u, 1);
-                    set_types(o.u, o);
-                    break;
-                case BSIM_OP_DEL_V:
-                    touch(o.u, 2);
-                    vtype[o.u] = 0;
-                    break;
-                case BSIM_OP_ADD_E:
-                case BSIM_OP_DEL_E:
-                case BSIM_OP_MOD_E:
-                    if (o.label >= lab_lim || (o.op == BSIM_OP_MOD_E && o.new_label >= lab_lim))
-                        throw DeviceError{BSIM_E_RANGE, "edge label out of range in update"};
-                    if (o.op == BSIM_OP_ADD_E) {
-                        recs.push_back({o.u, o.w, o.label, 1});
-                        max_l = std::max(max_l, o.label);
-                    } else {
-                        recs.push_back({o.u, o.w, o.label, 0});
-                        max_l = std::max(max_l, o.label);
-                        if (o.op == BSIM_OP_MOD_E) {
-                            recs.push_back({o.u, o.w, o.new_label, 1});
-                            max_l = std::max(max_l, o.new_label);
-                        }
-                    }
-                    break;
-                default:
-                    throw DeviceError{BSIM_E_INVALID, "unknown update op code"};
+            if (!alive_now(o.u)) {
+                fail(BSIM_E_INVALID, "update names a deleted vertex");
+                break;
             }
         }
+        if (op != BSIM_OP_DEL_V) {
+            if (o.n_types > kMaxStateTypes) {
+                fail(BSIM_E_UNSUPPORTED, "more than 4096 types on a vertex");
+                break;
+            }
+            if (o.n_types && !o.types) {
+                fail(BSIM_E_INVALID, "types pointer is NULL");
+                break;
+            }
+        }
+        if (op == BSIM_OP_ADD_V) {
+            if (n_cur >= 0xFFFFFFF0u) {
+                fail(BSIM_E_UNSUPPORTED, "too many vertices");
+                break;
+            }
+            const uint32_t v = n_cur++;
+            grow(n_cur);
+            touch(v, 1);
+            set_types(v, o);
+            add_pos.push_back(i);
+        } else if (op == BSIM_OP_MOD_V) {
+            touch(o.u, 1);
+            set_types(o.u, o);
+        } else {
+            touch(o.u, 2);
+            vtype[o.u] = 0;
+            dels.emplace_back(o.u, i);
+        }
+    }
+    std::sort(dels.begin(), dels.end());
+    // v exists at position i: an old id, or added before i
+    auto exists_at = [&](uint32_t v, uint64_t i) {
+        return v < n0 || (static_cast<uint64_t>(v) - n0 < add_pos.size() && add_pos[v - n0] < i);
+    };
+    // v (existing at i) lives at i: alive before the batch or added, and
+    // not deleted before i
+    auto alive_at = [&](uint32_t v, uint64_t i) {
+        if (v < n0 && !alive[v]) return false;
+        if (vmark[v] != 2) return true;
+        const auto it = std::lower_bound(dels.begin(), dels.end(), std::make_pair(v, uint64_t(0)));
+        return !(it != dels.end() && it->first == v && it->second < i);
+    };
+    const uint64_t lab_lim_e = lab_lim;
+    const uint64_t end = std::min<uint64_t>(n_ops, vfail.pos);  // later operations do not count
+    const unsigned hw = std::thread::hardware_concurrency();
+    const size_t T = std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hw ? hw : 1), 8, end / 65536}));
+    std::vector<std::vector<Rec>>& part = rs.part;
+    if (part.size() < T) part.resize(T);
+    std::vector<Fail> efail(T);
+    std::vector<uint32_t> part_max(T, 0);
+    auto check_edges = [&](size_t t) {
+        const uint64_t a = end * t / T, b = end * (t + 1) / T;
+        std::vector<Rec>& out = part[t];
+        out.clear();
+        out.reserve((b - a) + (b - a) / 4);
+        uint32_t ml = 0;
+        // the marks and the alive mask are read at random: the entries of
+        // the operation kPf places ahead are fetched meanwhile
+        constexpr uint64_t kPf = 24;
+        const size_t lim = std::min(vmark.size(), alive.size());
+        auto prefetch = [&](const bsim_update& o) {
+            if (!lim) return;
+            __builtin_prefetch(&alive[std::min<size_t>(o.u, lim - 1)]);
+            __builtin_prefetch(&alive[std::min<size_t>(o.w, lim - 1)]);
+            __builtin_prefetch(&vmark[std::min<size_t>(o.u, lim - 1)]);
+            __builtin_prefetch(&vmark[std::min<size_t>(o.w, lim - 1)]);
+        };
+        for (uint64_t i = a; i < b && i < a + kPf; i++) prefetch(ops[i]);
+        for (uint64_t i = a; i < b; i++) {
+            if (i + kPf < b) prefetch(ops[i + kPf]);
+            const bsim_update& o = ops[i];
+            if (o.op < BSIM_OP_ADD_E || o.op > BSIM_OP_DEL_E) continue;
+            // checks in the order: ids in range, ids alive, labels
+            if (!exists_at(o.u, i) || !exists_at(o.w, i)) {
+                efail[t] = Fail{i, BSIM_E_RANGE, "vertex id out of range in update"};
+                break;
+            }
+            if (!alive_at(o.u, i) || !alive_at(o.w, i)) {
+                efail[t] = Fail{i, BSIM_E_INVALID, "update names a deleted vertex"};
+                break;
+            }
+            if (o.label >= lab_lim_e || (o.op == BSIM_OP_MOD_E && o.new_label >= lab_lim_e)) {
+                efail[t] = Fail{i, BSIM_E_RANGE, "edge label out of range in update"};
+                break;
+            }
+            out.push_back({o.u, o.w, o.label, o.op == BSIM_OP_ADD_E ? 1u : 0u});
+            ml = std::max(ml, o.label);
+            if (o.op == BSIM_OP_MOD_E) {
+                out.push_back({o.u, o.w, o.new_label, 1});
+                ml = std::max(ml, o.new_label);
+            }
+        }
+        part_max[t] = ml;
+    };
+    {
+        std::vector<std::thread> th;
+        size_t t = 1;
+        try {
+            for (; t < T; t++) th.emplace_back(check_edges, t);
+        } catch (...) {
+        }
+        for (size_t u = t; u < T; u++) check_edges(u);  // shares no thread could take
+        check_edges(0);
+        for (auto& x : th) x.join();
+    }
+    Fail first = vfail;
+    for (const Fail& f : efail)
+        if (f.pos < first.pos) first = f;
+    if (first.pos != UINT64_MAX) throw DeviceError{first.status, first.msg};
+    size_t nrec = 0;
+    for (const auto& q : part) nrec += q.size();
+    recs.reserve(nrec);
+    for (size_t t = 0; t < T; t++) {
+        recs.insert(recs.end(), part[t].begin(), part[t].end());
+        max_l = std::max(max_l, part_max[t]);
     }
     hb.n_new = n_cur;
     hb.tl = touched;
@@ -239,8 +341,10 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
     // in the value), else a comparison sort
     const int bv = std::max(1, bit_width(n_cur)), bl = std::max(1, bit_width(max_l + 1));
     const size_t nr = recs.size();
-    std::vector<uint64_t> key;
-    std::vector<uint32_t> val(nr);
+    std::vector<uint64_t>& key = rs.key;
+    std::vector<uint32_t>& val = rs.val;
+    key.clear();
+    val.resize(nr);
     auto emit = [&](uint32_t u, uint32_t w, uint32_t l, bool deleted, bool add) {
         if (dead_at_end(u) || dead_at_end(w)) return;
         hb.cu.push_back(u);
@@ -265,7 +369,7 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
                      recs[i].l;
             val[i] = recs[i].add;
         }
-        host_radix_sort(key, val, 2 * bv + bl);
+        host_radix_sort(key, val, 2 * bv + bl, rs.key2, rs.val2);
         const uint64_t lmask = (1ull << bl) - 1, wmask = (1ull << bv) - 1;
         for (size_t i = 0; i < nr;) {
             size_t j = i;
@@ -302,10 +406,12 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
         i = j;
     }
     // reverse additions, grouped by target (duplicate pairs are harmless)
-    std::vector<uint64_t> rk(hb.rw.size());
-    std::vector<uint32_t> rdummy(hb.rw.size(), 0);
+    std::vector<uint64_t>& rk = rs.key;  // the edge records' keys are done with
+    std::vector<uint32_t>& rdummy = rs.val;
+    rk.resize(hb.rw.size());
+    rdummy.resize(hb.rw.size());
     for (size_t i = 0; i < rk.size(); i++) rk[i] = (static_cast<uint64_t>(hb.rw[i]) << bv) | hb.ru[i];
-    host_radix_sort(rk, rdummy, 2 * bv);
+    host_radix_sort(rk, rdummy, 2 * bv, rs.key2, rs.val2);
     rk.erase(std::unique(rk.begin(), rk.end()), rk.end());
     hb.rw.resize(rk.size());
     hb.ru.resize(rk.size());
@@ -322,6 +428,14 @@ inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vecto
         hb.rgend.push_back(static_cast<uint32_t>(j));
         i = j;
     }
+    return hb;
+}
+
+// The net effect of the batch as a new HostBatch.
+inline HostBatch resolve_ops(uint32_t n0, uint32_t label_bytes, const std::vector<uint8_t>& alive,
+                             ResolveScratch& rs, const bsim_update* ops, uint64_t n_ops) {
+    HostBatch hb;
+    resolve_ops_into(hb, n0, label_bytes, alive, rs, ops, n_ops);
     return hb;
 }
 

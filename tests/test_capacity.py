@@ -23,7 +23,7 @@ def results():
         pytest.skip("hipcc not found")
     out_dir = os.path.join(ROOT, "_build")
     os.makedirs(out_dir, exist_ok=True)
-    exe = os.path.join(out_dir, "table_slots_check")
+    exe = os.path.join(out_dir, "table_slots_check_%d" % os.getpid())  # one per test process
     src = os.path.join(ROOT, "tests", "native", "table_slots_check.cpp")
     subprocess.run([HIPCC, "-O1", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
                     "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2111_12493_amd", "csrc"),

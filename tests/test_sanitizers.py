@@ -31,7 +31,7 @@ def _build(compiler, std, sources, exe_name, san=None):
         pytest.skip(compiler + " not found")
     out_dir = os.path.join(ROOT, "_build")
     os.makedirs(out_dir, exist_ok=True)
-    exe = os.path.join(out_dir, exe_name)
+    exe = os.path.join(out_dir, "%s_%d" % (exe_name, os.getpid()))  # one per test process
     cmd = [compiler, std, "-Wall", "-Wextra"] + (san or SAN) + [
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2111_12493_amd", "csrc")] + [
         os.path.join(ROOT, s) for s in sources] + ["-o", exe, "-lpthread"]
