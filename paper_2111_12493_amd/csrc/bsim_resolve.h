@@ -51,6 +51,8 @@ struct ResolveScratch {
     std::vector<ResolveRec> recs;
     std::vector<uint64_t> key, key2;
     std::vector<uint32_t> val, val2;
+    std::vector<uint64_t> vpos;   // positions of the vertex operations
+    std::vector<uint64_t> dbits;  // deleted vertices
     HostBatch hb;  // the result of resolve_ops_into
 };
 
@@ -182,10 +184,45 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     Fail vfail;
     std::vector<uint64_t> add_pos;                     // ADD_V positions, by new id - n0
     std::vector<std::pair<uint32_t, uint64_t>> dels;   // (vertex, DEL_V position)
-    for (uint64_t i = 0; i < n_ops && vfail.pos == UINT64_MAX; i++) {
+    // the positions of the vertex operations (and of unknown op codes)
+    std::vector<uint64_t>& vpos = rs.vpos;
+    vpos.clear();
+    {
+        const unsigned hwv = std::thread::hardware_concurrency();
+        const size_t TV = std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hwv ? hwv : 1), 8, n_ops / 65536}));
+        std::vector<std::vector<uint64_t>> found(TV);
+        auto scan = [&](size_t t) {
+            for (uint64_t i = n_ops * t / TV, e = n_ops * (t + 1) / TV; i < e; i++)
+                if (ops[i].op < BSIM_OP_ADD_E || ops[i].op > BSIM_OP_DEL_E) found[t].push_back(i);
+        };
+        std::vector<std::thread> th;
+        size_t t = 1;
+        try {
+            for (; t < TV; t++) th.emplace_back(scan, t);
+        } catch (...) {
+        }
+        for (size_t u = t; u < TV; u++) scan(u);
+        scan(0);
+        for (auto& x : th) x.join();
+        for (const auto& f : found) vpos.insert(vpos.end(), f.begin(), f.end());
+    }
+    // the marks of the vertex kPv operations ahead are fetched meanwhile
+    constexpr size_t kPv = 16;
+    auto prefetch_v = [&](size_t k) {
+        if (k >= vpos.size()) return;
+        const uint32_t u = ops[vpos[k]].u;
+        if (u < vmark.size()) {
+            __builtin_prefetch(&vmark[u]);
+            __builtin_prefetch(&vtype[u]);
+        }
+        if (u < alive.size()) __builtin_prefetch(&alive[u]);
+    };
+    for (size_t k = 0; k < kPv; k++) prefetch_v(k);
+    for (size_t k = 0; k < vpos.size() && vfail.pos == UINT64_MAX; k++) {
+        prefetch_v(k + kPv);
+        const uint64_t i = vpos[k];
         const bsim_update& o = ops[i];
         const uint32_t op = o.op;
-        if (op >= BSIM_OP_ADD_E && op <= BSIM_OP_DEL_E) continue;
         auto fail = [&](int st, const char* msg) { vfail = Fail{i, st, msg}; };
         if (op < BSIM_OP_ADD_V || op > BSIM_OP_DEL_E) {
             fail(BSIM_E_INVALID, "unknown update op code");
@@ -323,7 +360,12 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     std::sort(hb.tl.begin(), hb.tl.end());
     hb.tl_off.reserve(hb.tl.size() + 1);
     hb.tl_off.push_back(0);
-    for (uint32_t v : hb.tl) {
+    for (size_t k = 0; k < hb.tl.size(); k++) {
+        if (k + 16 < hb.tl.size()) {
+            __builtin_prefetch(&vmark[hb.tl[k + 16]]);
+            __builtin_prefetch(&vtype[hb.tl[k + 16]]);
+        }
+        const uint32_t v = hb.tl[k];
         if (vmark[v] == 2) {
             hb.dead.push_back(v);
         } else if (vtype[v]) {
@@ -332,10 +374,14 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
         }
         hb.tl_off.push_back(static_cast<uint32_t>(hb.tl_ids.size()));
     }
-    // deletions are few: a binary search of their sorted list stays in cache
-    auto dead_at_end = [&](uint32_t v) {
-        return !hb.dead.empty() && std::binary_search(hb.dead.begin(), hb.dead.end(), v);
-    };
+    // the deleted vertices as a bitmap (n bits: mostly in cache)
+    std::vector<uint64_t>& dbits = rs.dbits;
+    const bool any_dead = !hb.dead.empty();
+    if (any_dead) {
+        dbits.assign((static_cast<size_t>(n_cur) + 63) / 64, 0);
+        for (uint32_t v : hb.dead) dbits[v >> 6] |= 1ull << (v & 63);
+    }
+    auto dead_at_end = [&](uint32_t v) { return any_dead && ((dbits[v >> 6] >> (v & 63)) & 1); };
     // edge records in (u, w, l) order, input order within equal triples:
     // the triple packed in one key when it fits 64 bits (the add flag rides
     // in the value), else a comparison sort
