@@ -16,13 +16,17 @@
 //      (MergeMessages' hash table), sums the mixed distinct keys
 //      (the order-independent Hash) and writes h^k; a hub chunk block writes
 //      its mixed keys to the hub's scratch area instead.
-// Then k_hub de-duplicates each hub's scratch keys bucket by bucket in LDS;
-// the last bucket block of a hub finishes its h^k.
+// Then k_hub de-duplicates each hub's scratch keys bucket by bucket in LDS
+// and adds each bucket's distinct sum to the hub's accumulator;
+// k_hub_finish turns the sums into h^k.
 //
 // The stop test lags the hashes by two launches, so once the block count
 // stops growing at level j, launch j+1 has computed h^{j+1} that is never
 // used and launch j+2 sets the sticky done flag; every later launch returns
-// at once, so the host can queue launches ahead.
+// at once, so the host can queue launches ahead.  A launch can also run as
+// two (kPhaseSplit, then kPhaseHash): the host reads the classes that the
+// split half founded before it decides on the hash half, which lets a run
+// that reaches its fixpoint there hash no further level.
 #include "bsim_device.h"
 
 namespace bsim {
