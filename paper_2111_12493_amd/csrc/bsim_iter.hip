@@ -106,6 +106,23 @@ __device__ uint64_t wave_split_join(const SplitTable& T, const uint64_t* __restr
     return shfl_u64(o, leader_of);
 }
 
+// base[key] += 1 for every taking lane, one atomic per distinct key in the
+// wave (a batched run's founders are counted per graph, and a wave's
+// vertices mostly belong to one graph).  All lanes of the wave call it.
+__device__ void wave_count_by_key(bool take, uint32_t key, uint32_t* base) {
+    const uint32_t lane = lane_id();
+    bool pending = take;
+    for (;;) {
+        const uint64_t ball = __ballot(pending);
+        if (!ball) break;
+        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
+        const uint32_t lk = static_cast<uint32_t>(__shfl(static_cast<int>(key), static_cast<int>(leader), 64));
+        const uint64_t same = __ballot(pending && key == lk);
+        if (lane == leader) atomicAdd(&base[lk], static_cast<uint32_t>(__popcll(same)));
+        if (key == lk) pending = false;
+    }
+}
+
 // Count the classes founded by this block at `level` (stripe counter) and
 // remember their slots so the table can be cleared selectively.
 __device__ void record_founders(const SplitTable& T, uint32_t* lcnt, uint32_t level,
@@ -178,10 +195,8 @@ __global__ void __launch_bounds__(kBlock) k_init(const uint64_t* __restrict__ t,
     uint64_t key = 0;
     if (part) key = t[v];
     const uint64_t o = wave_split_join(T, t, part, vr, key, v, &founded, &slot);
-    if (part) {
-        r = static_cast<uint32_t>(o);
-        if (bc.gid && founded) atomicAdd(&bc.hist[gi], 1u);
-    }
+    if (part) r = static_cast<uint32_t>(o);
+    if (bc.gid) wave_count_by_key(founded != 0, gi, bc.hist);
     if (v < n) rep[v] = r;
     record_founders(T, lcnt, 0, founded, slot, s_red, &s_base);
 }
@@ -339,11 +354,9 @@ __device__ bool tile_block(const IterArgs& a, uint32_t tile, IterShared& S, uint
     if (test) {
         // leave the class of rep[v] if h^{k-1} differs
         uint32_t founded = 0, slot = 0xFFFFFFFFu;
-        if (probe && hv_own != hv_rep) {
+        if (probe && hv_own != hv_rep)
             a.rep[v] = static_cast<uint32_t>(split_join(a.test_tab, a.h_prev, rv, hv_own, v, &founded, &slot));
-            if (a.bc.gid && founded)
-                atomicAdd(&a.bc.hist[static_cast<size_t>(k - 1) * a.bc.n_graphs + gi], 1u);
-        }
+        if (a.bc.gid) wave_count_by_key(founded != 0, gi, a.bc.hist + static_cast<size_t>(k - 1) * a.bc.n_graphs);
         record_founders(a.test_tab, a.lcnt, k - 1, founded, slot, S.red, &S.ctl[1]);
     }
     if (!hash) return true;
@@ -612,11 +625,9 @@ __device__ bool iso_block(const IterArgs& a, uint32_t blk, IterShared& S, uint32
             uint32_t founded = 0, slot = 0xFFFFFFFFu;
             const bool part = probe[r] && hv_own[r] != hv_rep[r];
             const uint64_t o = wave_split_join(a.test_tab, a.h_prev, part, rv[r], hv_own[r], v[r], &founded, &slot);
-            if (part) {
-                a.rep[v[r]] = static_cast<uint32_t>(o);
-                if (a.bc.gid && founded)
-                    atomicAdd(&a.bc.hist[static_cast<size_t>(k - 1) * a.bc.n_graphs + gi[r]], 1u);
-            }
+            if (part) a.rep[v[r]] = static_cast<uint32_t>(o);
+            if (a.bc.gid)
+                wave_count_by_key(founded != 0, gi[r], a.bc.hist + static_cast<size_t>(k - 1) * a.bc.n_graphs);
             record_founders(a.test_tab, a.lcnt, k - 1, founded, slot, S.red, &S.ctl[1]);
         }
     }
