@@ -20,7 +20,8 @@
 // level 0), key = the key's hash, so one probe reads one 16-byte line;
 // cnt[s] = members.  A vertex's class id at level j is the slot of its key.
 //
-// Rebuild (all vertices): one insertion pass over a cleared table.  The
+// Rebuild (all vertices): one insertion pass over a cleared table; the
+// member counts are left to k_ci_count, run when an update first needs them.  The
 // vertex that claims a slot writes the key after its CAS on the word; a
 // prober that finds the word already set but the key still 0 compares
 // against the owner's hash in the level array instead (immutable during
@@ -120,7 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_ci_build(CiLevel L, const uint32_t* 
             hv = h[v];
         }
     }
-    // group the lanes by key, one insertion (and one count update) per group
+    // group the lanes by key, one insertion per group
     uint32_t leader_of = lane;
     bool pending = part;
     for (;;) {
@@ -139,18 +140,30 @@ __global__ void __launch_bounds__(kBlock) k_ci_build(CiLevel L, const uint32_t* 
     if (lead) slot = ci_join_level(L, h, pc, hv, v, &founded);
     slot = static_cast<uint32_t>(__shfl(static_cast<int>(slot), static_cast<int>(leader_of), 64));
     if (part) L.cid[v] = slot;
-    // each leader adds its group's size
-    uint64_t leaders = __ballot(lead);
-    while (leaders) {
-        const uint32_t l = static_cast<uint32_t>(__ffsll(static_cast<long long>(leaders)) - 1);
-        leaders &= leaders - 1;
-        const uint64_t members = __ballot(part && leader_of == l);
-        if (lane == l) atomicAdd(&L.cnt[slot], static_cast<uint32_t>(__popcll(members)));
-    }
     const uint32_t c = block_sum_u32(founded, s_red);
     if (threadIdx.x == 0 && c) {
         atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[0]), static_cast<unsigned long long>(c));
         atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[1]), static_cast<unsigned long long>(c));
+    }
+}
+
+// Member counts of a rebuilt level, from the class ids (cnt cleared since
+// the rebuild): every vertex with a class counts, lanes of a wave with one
+// class add once.
+__global__ void __launch_bounds__(kBlock) k_ci_count(CiLevel L, uint32_t n) {
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t c = v < n ? L.cid[v] : kNoClass;
+    const bool part = c != kNoClass;
+    bool pending = part;
+    for (;;) {
+        const uint64_t ball = __ballot(pending);
+        if (!ball) break;
+        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(ball)) - 1);
+        const uint32_t lc = static_cast<uint32_t>(__shfl(static_cast<int>(c), static_cast<int>(leader), 64));
+        const uint64_t same = __ballot(pending && c == lc);
+        if (lane == leader) atomicAdd(&L.cnt[lc], static_cast<uint32_t>(__popcll(same)));
+        if (c == lc) pending = false;
     }
 }
 
@@ -341,6 +354,11 @@ void ci_rebuild(const CiLevel& L, uint64_t cap, const uint32_t* cid_prev, const 
     hip_check(hipMemsetAsync(ctr, 0, 2 * sizeof(uint64_t), s), "class index counters");
     if (n) k_ci_build<<<ceil_div(n, kBlock), kBlock, 0, s>>>(L, cid_prev, h, alive, n, ctr);
     hip_check(hipGetLastError(), "class index rebuild");
+}
+
+void ci_count(const CiLevel& L, uint32_t n, hipStream_t s) {
+    if (n) k_ci_count<<<ceil_div(n, kBlock), kBlock, 0, s>>>(L, n);
+    hip_check(hipGetLastError(), "class index counts");
 }
 
 void ci_list(const uint32_t* a, uint32_t na, const uint32_t* na_dev, const uint32_t* flag, uint32_t ftag,

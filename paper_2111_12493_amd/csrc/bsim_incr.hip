@@ -852,6 +852,9 @@ struct bsim_state {
     // follows the launches writing its level, so they overlap the next levels
     hipStream_t s2 = nullptr;
     hipEvent_t ev_level = nullptr, ev_classes = nullptr;
+    // per level: the member counts of the class index are up to date (a
+    // rebuild leaves them to the first update that moves vertices there)
+    std::vector<uint8_t> ci_counted;
     // backing of an update's temporary arrays, grown to the largest demand
     // seen: large temporaries then never pass through the stream-ordered
     // pool, which can return freed memory to the driver (tens of ms) and map
@@ -918,6 +921,7 @@ void ensure_vertices(bsim_state* st, uint32_t n_new) {
     // class index: the new vertices have no class and no list mark yet
     const size_t L = static_cast<size_t>(st->K) + 1;
     st->ci_slot.resize(L), st->ci_cnt.resize(L), st->ci_cid.resize(L);
+    st->ci_counted.resize(L, 0);
     for (auto& c : st->ci_cid) {
         c.ensure(nv, keep_v, s);
         hip_check(hipMemsetAsync(c.p + keep_v, 0xFF, (nv - keep_v) * 4, s), "new classes");
@@ -1131,8 +1135,14 @@ void index_rebuild(bsim_state* st, uint32_t j) {
     st->ci_rebuild_from = std::min(st->ci_rebuild_from, j);
     hip_check(hipEventRecord(st->ev_level, st->s), "level event");
     hip_check(hipStreamWaitEvent(st->s2, st->ev_level, 0), "level wait");
+    // the member counts matter only to a later update that moves vertices
+    // of this level, and their atomics cost about as much as the rest of
+    // the rebuild (and slow the refinement launches beside it): they are
+    // counted by the first update that needs them (ci_count), so a level
+    // that is recomputed in full again never counts them
     ci_rebuild(ci_level(st, j), st->ci_cap, j ? st->ci_cid[j - 1].p : nullptr, st->levels[j].p, st->alive.p, st->n,
                st->ci_ctr.p + 2 * j, st->s2);
+    st->ci_counted[j] = 0;
 }
 
 // Level j's class index once h^j is final: rebuilt (from ci_rebuild_from
@@ -1161,7 +1171,14 @@ void index_level(bsim_state* st, uint32_t j, const uint32_t* a, uint32_t na, con
         index_rebuild(st, j);
         return;
     }
-    ci_update(ci_level(st, j), j ? st->ci_cid[j - 1].p : nullptr, st->levels[j].p, st->alive.p, st->ci_d.p, nd,
+    const CiLevel L = ci_level(st, j);
+    if (!st->ci_counted[j]) {
+        // the level was rebuilt without its counts (they are cleared); the
+        // rebuild stream was joined by the end of the update that rebuilt it
+        ci_count(L, st->n, s);
+        st->ci_counted[j] = 1;
+    }
+    ci_update(L, j ? st->ci_cid[j - 1].p : nullptr, st->levels[j].p, st->alive.p, st->ci_d.p, nd,
               st->ci_ctr.p + 2 * j, st->ci_q[j & 1].p, counts + 1 + (j & 1), counts + 3, hw, arena, s);
 }
 

@@ -491,9 +491,12 @@ struct CiLevel {
     uint32_t* cid;    // [vertices] class slot, kNoClass for a dead vertex
     uint32_t mask;    // cap - 1
 };
-// Every vertex from scratch; ctr[0] = classes, ctr[1] = claimed slots.
+// Every vertex from scratch; ctr[0] = classes, ctr[1] = claimed slots; the
+// member counts are left cleared for ci_count.
 void ci_rebuild(const CiLevel& L, uint64_t cap, const uint32_t* cid_prev, const uint64_t* h, const uint8_t* alive,
                 uint32_t n, uint64_t* ctr, hipStream_t s);
+// The member counts of a rebuilt level (vertices < n).
+void ci_count(const CiLevel& L, uint32_t n, hipStream_t s);
 // d = (candidates of a with flag[v] == ftag, or all of a when flag is null)
 // plus b, each vertex once (dmark[v] = dtag marks it); counts from the _dev
 // pointers when given; *nd = its length.

@@ -271,3 +271,20 @@ def test_class_index_through_many_batches():
                 d = gg.update_ops(s.g, rng, int(rng.integers(1, 120)), n_labels=3, n_types=3)
                 s.apply(gg.ops_as_tuples(d), what=("churn", pct, i))
             s.close()
+
+
+def test_switching_between_plain_and_incremental_on_one_state():
+    # A state that recomputes every level in full skips the class index's
+    # member counts; once it takes incremental batches again it counts them
+    # first.  Alternate the two forms on one state and check every batch.
+    rng = np.random.default_rng(43)
+    g = gg.uniform_graph(400, 1600, 4, 4, seed=9)
+    with FrontierLimit(0):
+        s = Session(g, 3)
+    try:
+        for i in range(12):
+            with FrontierLimit(0 if i % 3 == 0 else 100):
+                d = gg.update_ops(s.g, rng, int(rng.integers(1, 60)), n_labels=4, n_types=4)
+                s.apply(gg.ops_as_tuples(d), what=("switch", i))
+    finally:
+        s.close()
