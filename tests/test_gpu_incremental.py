@@ -288,3 +288,22 @@ def test_switching_between_plain_and_incremental_on_one_state():
                 s.apply(gg.ops_as_tuples(d), what=("switch", i))
     finally:
         s.close()
+
+
+def test_frontier_options_and_their_ranges():
+    c = binding.Context(0)
+    try:
+        assert c.get_option("frontier_limit_pct") == 10
+        assert c.get_option("frontier_edge_pct") == 15
+        for name, bad in (("frontier_limit_pct", -1), ("frontier_limit_pct", 101),
+                          ("frontier_edge_pct", 0), ("frontier_edge_pct", 101)):
+            with pytest.raises(binding.BsimError) as e:
+                c.set_option(name, bad)
+            assert e.value.status == binding.E_RANGE
+        c.set_option("frontier_edge_pct", 1)
+        assert c.get_option("frontier_edge_pct") == 1
+        with pytest.raises(binding.BsimError) as e:
+            c.set_option("frontier_no_such_option", 1)
+        assert e.value.status == binding.E_INVALID
+    finally:
+        c.close()
