@@ -196,7 +196,39 @@ class Context:
         return int(v.value)
 
 
-class DeviceGraph:
+class PackedGraph:
+    """Keeps a graph's bsim_graph struct packed once, so that a call over
+    thousands of graphs marshals each with one bytes copy.  Assigning any
+    attribute of the graph drops the packed copy (the arrays' addresses are
+    read again on the next call); subclasses build the struct in
+    _make_struct."""
+
+    def __setattr__(self, name, value):
+        object.__setattr__(self, name, value)
+        if name != "_packed":
+            object.__setattr__(self, "_packed", None)
+
+    def packed(self) -> bytes:
+        p = getattr(self, "_packed", None)
+        if p is None:
+            p = bytes(self._make_struct())
+            object.__setattr__(self, "_packed", p)
+        return p
+
+    def struct(self) -> BsimGraph:
+        return BsimGraph.from_buffer_copy(self.packed())
+
+
+def pack_graphs(graphs: Sequence) -> ctypes.Array:
+    """A bsim_graph array (at least one entry) for the given graphs."""
+    G = len(graphs)
+    raw = b"".join(g.packed() if isinstance(g, PackedGraph) else bytes(g.struct()) for g in graphs)
+    if G == 0:
+        return (BsimGraph * 1)()
+    return (BsimGraph * G).from_buffer_copy(raw)
+
+
+class DeviceGraph(PackedGraph):
     """A graph whose CSR arrays are torch tensors on the GPU (bit-preserving
     signed views of the unsigned arrays)."""
 
@@ -221,13 +253,13 @@ class DeviceGraph:
         self.typ = up(np.asarray(g.typ, dtype=np.uint32), np.int32)
         self.alive = None if g.alive is None else up(np.asarray(g.alive, dtype=np.uint8), np.uint8)
 
-    def struct(self) -> BsimGraph:
+    def _make_struct(self) -> BsimGraph:
         return BsimGraph(self.n, self.label_bytes, self.m, self.row_off.data_ptr(), self.tgt.data_ptr(),
                          self.lab.data_ptr(), self.type_off.data_ptr(), self.typ.data_ptr(),
                          self.alive.data_ptr() if self.alive is not None else None, MEM_DEVICE, 0)
 
 
-class HostGraph:
+class HostGraph(PackedGraph):
     """A graph given as host numpy arrays (the library copies it)."""
 
     def __init__(self, g):
@@ -244,7 +276,7 @@ class HostGraph:
             self.typ = np.zeros(1, dtype=np.uint32)
         self.alive = None if g.alive is None else np.ascontiguousarray(g.alive, dtype=np.uint8)
 
-    def struct(self) -> BsimGraph:
+    def _make_struct(self) -> BsimGraph:
         def ptr(a):
             return None if a is None else a.ctypes.data
 
@@ -259,25 +291,31 @@ class Result:
     FIELDS = {"hashes": np.uint64, "block_ids": np.uint32, "block_sizes": np.uint32,
               "se_src": np.uint32, "se_label": np.uint32, "se_dst": np.uint32}
 
+    SCALARS = ("n_vertices", "k_done", "fixpoint", "n_blocks", "n_summary_edges", "n_iter_launches", "mem_kind",
+               "ms_stage", "ms_iterate", "ms_finalize", "ms_total", "ms_iter_kernels", "ms_hub_kernels",
+               "n_timed_launches", "n_split_launches", "ms_resolve")
+
     def __init__(self, ptr):
+        # the struct's fields are read on first use (a batched call returns
+        # thousands of results, most of which are never looked at)
         self.ptr = ptr
-        r = ptr.contents
-        self.n_vertices = r.n_vertices
-        self.k_done = r.k_done
-        self.fixpoint = r.fixpoint
-        self.n_blocks = r.n_blocks
-        self.n_summary_edges = r.n_summary_edges
-        self.n_iter_launches = r.n_iter_launches
-        self.mem_kind = r.mem_kind
-        self.blocks_per_iter = np.array([r.blocks_per_iter[i] for i in range(r.k_done + 1)],
-                                        dtype=np.uint32)
-        self.ms_stage, self.ms_iterate = r.ms_stage, r.ms_iterate
-        self.ms_finalize, self.ms_total = r.ms_finalize, r.ms_total
-        self.ms_iter_kernels = r.ms_iter_kernels
-        self.ms_hub_kernels = r.ms_hub_kernels
-        self.n_timed_launches = r.n_timed_launches
-        self.n_split_launches = r.n_split_launches
-        self.ms_resolve = r.ms_resolve
+
+    def __getattr__(self, name):
+        if name in Result.SCALARS or name == "blocks_per_iter":
+            if not self.__dict__.get("ptr"):
+                raise AttributeError("%s of a result freed before it was read" % name)
+            self._load()
+            return self.__dict__[name]
+        raise AttributeError(name)
+
+    def _load(self):
+        r = self.ptr.contents
+        d = self.__dict__
+        for f in Result.SCALARS:
+            d[f] = getattr(r, f)
+        k = r.k_done + 1
+        d["blocks_per_iter"] = (np.ctypeslib.as_array(r.blocks_per_iter, shape=(k,)).astype(np.uint32)
+                                if r.blocks_per_iter else np.zeros(0, dtype=np.uint32))
 
     def _len(self, field):
         if field in ("hashes", "block_ids"):
@@ -314,7 +352,9 @@ class Result:
         return d
 
     def free(self):
-        if self.ptr:
+        if self.__dict__.get("ptr"):
+            if "k_done" not in self.__dict__:
+                self._load()  # the fields stay readable after the free
             lib().bsim_result_free(self.ptr)
             self.ptr = None
 
@@ -645,7 +685,7 @@ def batch_summarize(ctx: Context, graphs: Sequence, k_max: int = K_UNBOUNDED, st
             (0 if summary_edges else NO_SUMMARY_EDGES) | (RESULT_ON_HOST if result_on_host else 0) | \
             DIRECTION_FLAGS[direction]
     G = len(graphs)
-    arr = (BsimGraph * max(G, 1))(*[g.struct() for g in graphs])
+    arr = pack_graphs(graphs)
     outs = (ctypes.POINTER(BsimResult) * max(G, 1))()
     params = BsimParams(int(k_max), flags)
     ctx.check(lib().bsim_batch_summarize(ctx.handle, arr, G, ctypes.byref(params), outs))

@@ -24,6 +24,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import graphgen as gg
+from .binding import PackedGraph
 
 _CHUNK = 1 << 25
 
@@ -77,7 +78,7 @@ def _rmat_endpoints(gen, scale: int, m: int, a: float, b: float, c: float, devic
 
 
 @dataclasses.dataclass
-class DeviceCSR:
+class DeviceCSR(PackedGraph):
     """A CSR graph held as torch tensors on the GPU (int32 views of the
     unsigned arrays, int16 labels when ``label_bytes`` is 2)."""
 
@@ -92,7 +93,7 @@ class DeviceCSR:
     n_labels: int
     n_types: int
 
-    def struct(self):
+    def _make_struct(self):
         from .binding import BsimGraph, MEM_DEVICE
 
         return BsimGraph(self.n, self.label_bytes, self.m, self.row_off.data_ptr(), self.tgt.data_ptr(),
