@@ -230,7 +230,11 @@ const char* bsim_status_string(int status);
  * "batch_small_edges" (N >= 0) = a fixed batched schedule instead: graphs
  * of at most N edges that fit one workgroup go to the small-graph launch
  * (0: none; turns autotune off); "batch_hub_table_slots" (read only) = the
- * hub-table size of the last batched call; "fail_alloc_after" (N, 0..2^40)
+ * hub-table size of the last batched call; "keep_work" (0/1, default 1) =
+ * summarize and batched calls keep their device temporaries in one buffer
+ * of the largest size an earlier call on the ctx needed, held until
+ * bsim_ctx_free (0: every call takes them from the stream-ordered pool and
+ * returns them, and setting 0 releases the buffer at once); "fail_alloc_after" (N, 0..2^40)
  * = for tests of the failure paths, the N-th device allocation from now in
  * this process fails as if the device were out of memory (0: off; reading
  * it gives the allocations left).  Values outside the range give
@@ -411,7 +415,9 @@ void bsim_updates_free(bsim_update* ops);
  * (targets >= n are skipped), averaged over `reps` passes after one warm-up
  * pass; the memory pattern that bounds a refinement iteration, without its
  * labels, de-duplication or classes.  targets and h are device arrays the
- * caller owns; the call allocates a small sink.  bsim_probe_copy: the same
+ * caller owns; the pass gathers from a copy of h in the ctx's work memory
+ * (option keep_work), where the refinement keeps its hash arrays, and the
+ * call allocates a small sink there.  bsim_probe_copy: the same
  * for a STREAM-style copy of `bytes` bytes between two arrays the call
  * allocates (read + write).  BSIM_E_INVALID for null pointers or reps = 0.
  */
@@ -482,7 +488,9 @@ int bsim_server_stats_get(bsim_server* srv, bsim_server_stats* out);
 /* Set a context option (bsim_ctx_set_option's names and ranges) on every
  * context of the server: the workers', the server-owned states' and those
  * created later.  Only while no request is queued or running
- * (BSIM_E_BUSY otherwise); errors as bsim_ctx_set_option. */
+ * (BSIM_E_BUSY otherwise); errors as bsim_ctx_set_option.  "keep_work" is
+ * off on a server's contexts (its memory budget counts a request's
+ * temporaries while the request runs) and gives BSIM_E_UNSUPPORTED. */
 int bsim_server_set_option(bsim_server* srv, const char* name, int64_t value);
 /* Free a server-owned state and return its memory to the budget. */
 int bsim_server_release_state(bsim_server* srv, bsim_state* state);

@@ -11,8 +11,40 @@
 using namespace bsim;
 
 namespace bsim {
+
 std::atomic<int64_t> g_fail_alloc_countdown{0};
+
+// Allocating and returning the hundred-odd pool blocks of a large call costs
+// milliseconds of host time per call (hipFreeAsync alone averages over
+// 100 us on large blocks); one kept buffer costs nothing once grown.
+void ctx_back_arena(bsim_ctx* ctx, Arena& arena, size_t at_least) {
+    if (!ctx->keep_work) return;
+    ctx->work_want = std::max(ctx->work_want, at_least);
+    if (ctx->work_want > ctx->work_cap) {
+        ctx_release_work(ctx);
+        void* p = nullptr;
+        if (device_alloc(&p, ctx->work_want, ctx->stream) == hipSuccess) {
+            ctx->work = p;
+            ctx->work_cap = ctx->work_want;
+        } else {
+            (void)hipGetLastError();
+            ctx->work_want = 0;  // learn the demand again
+        }
+    }
+    if (ctx->work) arena.back(ctx->work, ctx->work_cap);
 }
+
+void ctx_note_demand(bsim_ctx* ctx, const Arena& arena) {
+    if (ctx->keep_work) ctx->work_want = std::max(ctx->work_want, arena.demand());
+}
+
+void ctx_release_work(bsim_ctx* ctx) {
+    if (ctx->work) (void)hipFreeAsync(ctx->work, ctx->stream);
+    ctx->work = nullptr;
+    ctx->work_cap = 0;
+}
+
+}  // namespace bsim
 
 extern "C" {
 
@@ -76,6 +108,7 @@ int bsim_ctx_create(int device, void* hip_stream, bsim_ctx** out) {
 void bsim_ctx_free(bsim_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    ctx_release_work(ctx);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->status_host) (void)hipHostFree(ctx->status_host);
     if (ctx->count_host) (void)hipHostFree(ctx->count_host);
@@ -101,6 +134,9 @@ const char* bsim_option_names(void) {
            "batch_small_edges (N >= 0: a fixed batched schedule, graphs of at most N edges that fit one "
            "workgroup go to the small-graph launch, 0 = none; turns autotune off); "
            "batch_hub_table_slots (read only: the hub-table slots of the last batched call); "
+           "keep_work (0/1: summarize and batched calls keep their temporaries in one device buffer of the "
+           "largest size an earlier call needed, released with the ctx; 0 = every call allocates and returns "
+           "them, and the buffer is released now; 1 = default); "
            "fail_alloc_after (N, 0..2^40: for tests of the failure paths, the N-th device allocation from now "
            "in this process fails as if the device were out of memory; 0 = off; reads the allocations left)";
 }
@@ -135,6 +171,16 @@ int bsim_ctx_set_option(bsim_ctx* ctx, const char* name, int64_t value) {
     if (!strcmp(name, "fail_alloc_after")) {
         if (value < 0 || value > (1ll << 40)) return BSIM_E_RANGE;
         g_fail_alloc_countdown.store(value);
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "keep_work")) {
+        if (value < 0 || value > 1) return BSIM_E_RANGE;
+        ctx->keep_work = static_cast<uint32_t>(value);
+        if (!value) {
+            ctx_release_work(ctx);
+            ctx->work_want = 0;
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess) return BSIM_E_DEVICE;
+        }
         return BSIM_OK;
     }
     if (!strcmp(name, "autotune")) {
@@ -186,6 +232,10 @@ int bsim_ctx_get_option(const bsim_ctx* ctx, const char* name, int64_t* value) {
     }
     if (!strcmp(name, "autotune")) {
         *value = ctx->autotune;
+        return BSIM_OK;
+    }
+    if (!strcmp(name, "keep_work")) {
+        *value = ctx->keep_work;
         return BSIM_OK;
     }
     if (!strcmp(name, "tail_split_ppm")) {

@@ -32,6 +32,12 @@ struct bsim_ctx {
     std::map<uint64_t, BatchTune> batch_tune;
     BatchTune last_batch{0, 0};     // what the last batched call ran with
     uint64_t fixed_small_edges = ~0ull;  // the schedule when autotune is off
+    // temporaries of summarize and batched calls: one device buffer, grown
+    // to the largest demand of the earlier calls (keep_work = 0: every call
+    // takes them from the stream-ordered pool and returns them)
+    uint32_t keep_work = 1;
+    void* work = nullptr;
+    size_t work_cap = 0, work_want = 0;
 };
 
 namespace bsim {
@@ -122,6 +128,15 @@ int summarize_with_state(bsim_ctx* ctx, const bsim_graph& graph, const bsim_para
 // directions: whether the caller takes BSIM_BACKWARD / BSIM_BOTH_DIRECTIONS
 // (only the single-graph summarization does).
 void validate_params(const bsim_graph& graph, const bsim_params& p, bool directions = false);
+
+// Back `arena` with the ctx's work buffer, grown first to the largest
+// demand of the ctx's earlier calls and to at_least bytes (what does not
+// fit comes from the pool; a failed growth leaves the arena on the pool).
+// ctx_note_demand records a finished call's demand; ctx_release_work frees
+// the buffer.
+void ctx_back_arena(bsim_ctx* ctx, Arena& arena, size_t at_least = 0);
+void ctx_note_demand(bsim_ctx* ctx, const Arena& arena);
+void ctx_release_work(bsim_ctx* ctx);
 
 // Device bytes a resident state holds.
 uint64_t state_bytes(const bsim_state* st);

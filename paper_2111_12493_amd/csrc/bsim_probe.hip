@@ -56,8 +56,14 @@ int bsim_probe_gather(bsim_ctx* ctx, const uint32_t* tgt, uint64_t m, const uint
         const uint64_t per_block = static_cast<uint64_t>(kProbeBlock) * kProbePerThread;
         const uint64_t blocks = std::max<uint64_t>((m + per_block - 1) / per_block, 1);
         if (blocks > 0x7FFFFFFFull) throw DeviceError{BSIM_E_UNSUPPORTED, "graph too large for the probe"};
+        // gather from a copy of h in the ctx's work memory, where the
+        // refinement keeps its hash arrays
         Arena arena(s);
+        ctx_back_arena(ctx, arena, static_cast<size_t>(n) * 8 + blocks * 8 + 1024);
+        uint64_t* hc = arena.alloc<uint64_t>(n);
         uint64_t* sink = arena.alloc<uint64_t>(blocks);
+        if (n) hip_check(hipMemcpyAsync(hc, h, static_cast<size_t>(n) * 8, hipMemcpyDeviceToDevice, s), "probe copy");
+        h = hc;
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");

@@ -105,6 +105,7 @@ void bsim_server::worker(uint32_t w) {
                     d.status = BSIM_E_DEVICE;
                 } else if ((d.status = bsim_ctx_create(device, os.stream, &os.ctx)) == BSIM_OK) {
                     ctx = os.ctx;
+                    ctx->keep_work = 0;
                     std::vector<std::pair<std::string, int64_t>> opts;
                     {
                         std::lock_guard<std::mutex> lk(opt_mu);
@@ -160,6 +161,9 @@ int bsim_server_create(int device, uint64_t budget, uint32_t n_workers, bsim_ser
             bsim_server_free(s);
             return rc;
         }
+        // the scheduler's memory budget counts a request's temporaries
+        // while it runs only: workers keep no buffer between requests
+        c->keep_work = 0;
         s->streams.push_back(st);
         s->ctxs.push_back(c);
     }
@@ -245,6 +249,7 @@ int bsim_server_poll(bsim_server* s, uint64_t ticket, int wait, bsim_result** ou
 
 int bsim_server_set_option(bsim_server* s, const char* name, int64_t value) {
     if (!s || !name) return BSIM_E_INVALID;
+    if (!strcmp(name, "keep_work")) return BSIM_E_UNSUPPORTED;  // the memory budget needs it off
     // validated on a worker context first; contexts are not thread safe, so
     // only while the server is idle
     return s->sched->with_idle([&](std::map<const void*, OwnedState>& owned) {

@@ -349,6 +349,7 @@ bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_
     validate_params(graph, p, true);
     hipStream_t s = ctx->stream;
     Arena arena(s), keep(s);
+    ctx_back_arena(ctx, arena);
     hipEvent_t ev[4];
     for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
     struct EvGuard {
@@ -394,6 +395,7 @@ bsim_result* summarize_graph(bsim_ctx* ctx, const bsim_graph& graph, const bsim_
     (void)hipEventElapsedTime(&r->ms_iterate, ev[1], ev[2]);
     (void)hipEventElapsedTime(&r->ms_finalize, ev[2], ev[3]);
     (void)hipEventElapsedTime(&r->ms_total, ev[0], ev[3]);
+    ctx_note_demand(ctx, arena);
     return r;
 }
 

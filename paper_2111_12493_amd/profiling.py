@@ -79,19 +79,30 @@ def stats(path: str) -> str:
     return "\n".join(lines)
 
 
-def working_launch_durations(path: str, k_done: int, n_work: int = 0):
+# Every profiled command runs one warm-up summarization first (it sizes the
+# context's kept work buffer, so the measured runs place their temporaries
+# as the timed bench steps do); the summaries skip that run.
+SKIP_RUNS = 1
+
+
+def working_launch_durations(path: str, k_done: int, n_work: int = 0, skip_runs: int = SKIP_RUNS):
     """Per kernel, durations (ns) of the working refinement-loop launches
-    (the first n_work of every run; default k_done + 1)."""
+    (the first n_work of every run after the first skip_runs; default
+    n_work = k_done + 1)."""
     n_work = n_work or k_done + 1
     rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
     seen = collections.Counter()
     out = collections.defaultdict(list)
+    run = 0
     for r in rows:
         k = short(r["Kernel_Name"])
         if k == "k_init":
             seen.clear()
+            run += 1
             continue
         seen[k] += 1
+        if run <= skip_runs:
+            continue
         if k in ("k_iterate", "k_hub", "k_hub_finish") and seen[k] <= n_work:
             out[k].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     return out
@@ -168,7 +179,7 @@ def commands(d: str, workload: str) -> str:
     for name, ctrs in PASSES.items():
         calib = " --calibrate-copy 1024" if name in ("fetch", "l2") else ""
         lines += ["    timeout -s KILL 300 rocprofv3 --pmc %s -d %s/%s -o run --output-format csv -- \\" % (ctrs, d, name),
-                  "        %s --steps 1 --warmup 0%s" % (b, calib)]
+                  "        %s --steps 1 --warmup 1%s" % (b, calib)]
     return "\n".join(lines)
 
 
@@ -182,10 +193,10 @@ def write_bytes(avg: dict) -> float:
     return 32 * (wr - w64) + 64 * w64
 
 
-def pass_counters(path: str, k_done: int, n_work: int = 0):
-    """Per kernel (working launches of the refinement loop only), the average
-    of every counter per dispatch, and the counters of the largest foreign
-    dispatch (the calibration copy)."""
+def pass_counters(path: str, k_done: int, n_work: int = 0, skip_runs: int = SKIP_RUNS):
+    """Per kernel (working launches of the refinement loop only, runs after
+    the first skip_runs), the average of every counter per dispatch, and the
+    counters of the foreign dispatches (the calibration copy)."""
     per = collections.defaultdict(lambda: collections.defaultdict(float))
     meta = {}
     for r in csv.DictReader(open(path)):
@@ -195,6 +206,7 @@ def pass_counters(path: str, k_done: int, n_work: int = 0):
     by_kernel = collections.defaultdict(list)
     seen = collections.Counter()
     foreign = []
+    run = 0
     for key in sorted(per, key=lambda k: meta[k][0]):
         k = short(meta[key][1])
         if k not in OWN and k not in ITER_KERNELS and not k.startswith("k_"):
@@ -202,7 +214,10 @@ def pass_counters(path: str, k_done: int, n_work: int = 0):
             continue
         if k == "k_init":
             seen.clear()
+            run += 1
         seen[k] += 1
+        if run <= skip_runs:
+            continue
         if k in ITER_KERNELS and seen[k] > (n_work or k_done + 1):
             continue
         by_kernel[k].append(per[key])
@@ -264,7 +279,8 @@ def summary(d: str, workload: str, k_done: int, algo_bytes: int, calib_bytes: in
              "## Kernel stats (every dispatch of the profiled runs)", "", "```",
              stats(j(d, "stats", "run_kernel_stats.csv")), "```", "",
              "Launches past the stop test of a run return at once; over the launches that hashed a "
-             "level (1..%d of every run):" % n_work, "", "```",
+             "level (1..%d of every run but the first, the warm-up run that sizes the context's work "
+             "buffer; the counter tables below skip it too):" % n_work, "", "```",
              trace(j(d, "stats", "run_kernel_trace.csv"), k_done, n_work), "```", "",
              "One iteration = %.1f us; algorithmic bytes %.1f MB -> %.0f GB/s = %.1f %% of 8 TB/s."
              % (iter_us, algo_bytes / 1e6, algo_bytes / iter_us / 1e3, algo_bytes / iter_us / 1e3 / 80), "",
