@@ -186,6 +186,7 @@ struct IterArgs {
     uint32_t stop;
     uint32_t hash_only;     // h^k only: no stop test, split test or recycling
     uint32_t phase;         // kPhaseFused, or one half of a split launch (kPhaseSplit, kPhaseHash)
+    uint32_t stop_only;     // one workgroup that records the stop the host already knows of
     BatchCtl bc;
 };
 
@@ -427,9 +428,13 @@ void alloc_run_buffers(const Staged& g, uint32_t k_max, bool stop, RunBuffers& r
 void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_t s);
 
 // Launch k: stop test, split test of level k-1, h^k (tiles and hub chunks),
-// or one half of it (phase; see kPhaseFused).
+// or one half of it (phase; see kPhaseFused).  stop_only: the hash half of a
+// launch whose split half ended the run (the host has read the founded
+// count): a single workgroup takes the stop decision and records it, where
+// the whole grid would only dispatch and exit.
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
-                      bool stop, bool all_levels, hipStream_t s, uint32_t phase = kPhaseFused);
+                      bool stop, bool all_levels, hipStream_t s, uint32_t phase = kPhaseFused,
+                      bool stop_only = false);
 
 // Hub buckets of iteration k (only when the graph has hubs and k <= k_max).
 void launch_hubs(const Staged& g, const RunBuffers& rb, uint32_t k, hipStream_t s);

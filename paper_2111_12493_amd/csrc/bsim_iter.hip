@@ -693,7 +693,9 @@ __global__ void __launch_bounds__(kBlock) k_iterate(IterArgs a) {
     }
     bool go;
     const uint32_t b = blockIdx.x;
-    if (b < a.n_hub_chunks)
+    if (a.stop_only)
+        go = null_block(a, S, p_done, p_cnt, p_tot);
+    else if (b < a.n_hub_chunks)
         go = hub_chunk_block<LabT>(a, b, S, p_done, p_cnt, p_tot);
     else if (b - a.n_hub_chunks < a.n_solo)
         go = solo_block<LabT>(a, a.solo_v[b - a.n_hub_chunks], S, p_done, p_cnt, p_tot);
@@ -930,9 +932,10 @@ void launch_init(const Staged& g, const RunBuffers& rb, bool untyped, hipStream_
 }
 
 void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_t k_max,
-                      bool stop, bool all_levels, hipStream_t s, uint32_t phase) {
+                      bool stop, bool all_levels, hipStream_t s, uint32_t phase, bool stop_only) {
     IterArgs a{};
     a.phase = phase;
+    a.stop_only = stop_only ? 1u : 0u;
     a.row_off = g.row_off;
     a.tgt = g.tgt;
     a.lab = g.lab;
@@ -971,7 +974,8 @@ void launch_iteration(const Staged& g, const RunBuffers& rb, uint32_t k, uint32_
     a.stop = stop ? 1u : 0u;
     a.all_levels = all_levels ? 1u : 0u;
     a.bc = rb.bc;
-    const uint32_t grid = std::max<uint32_t>(g.n_hub_chunks + g.n_solo + a.n_iso_blocks + g.n_tiles, 1);
+    const uint32_t grid =
+        stop_only ? 1u : std::max<uint32_t>(g.n_hub_chunks + g.n_solo + a.n_iso_blocks + g.n_tiles, 1);
     if (g.label_bytes == 2)
         k_iterate<uint16_t><<<grid, kBlock, 0, s>>>(a);
     else

@@ -7,6 +7,7 @@
 // ctx->chunk_max, so a run of thousands of iterations (long k-chaining)
 // costs only the kernels themselves plus a few early-exit launches.
 #include <algorithm>
+#include <functional>
 #include <cstdlib>
 #include <cstring>
 
@@ -138,8 +139,10 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
             for (hipEvent_t e : t) (void)hipEventDestroy(e);
         }
     } timer_guard{timers};
-    // Queue refinement launch kk: fused, or as its split half then its hash half.
-    auto issue = [&](uint32_t kk, bool split_first) {
+    // Queue refinement launch kk: fused, or as its split half then its hash
+    // half.  ends_run, if given, runs between the halves and says whether the
+    // split half ended the run; the hash half then only records the stop.
+    auto issue = [&](uint32_t kk, bool split_first, const std::function<bool()>& ends_run) {
         if (sink && !sink->levels.empty()) {
             // keep every level: iteration kk reads levels[kk-1], writes levels[kk]
             const uint32_t top = static_cast<uint32_t>(sink->levels.size()) - 1;
@@ -159,9 +162,11 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
         }
         const bool all = sink && !sink->levels.empty();
         if (rb.bc.gid) launch_graph_stop(rb, kk, p.k_max, stop, s);
+        bool stop_only = false;
         if (split_first) {
             launch_iteration(g, rb, kk, p.k_max, stop, all, s, kPhaseSplit);
-            launch_iteration(g, rb, kk, p.k_max, stop, all, s, kPhaseHash);
+            stop_only = ends_run && ends_run();
+            launch_iteration(g, rb, kk, p.k_max, stop, all, s, kPhaseHash, stop_only);
         } else {
             launch_iteration(g, rb, kk, p.k_max, stop, all, s);
         }
@@ -174,7 +179,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
             prev_taken = true;
         }
         if (timed) hip_check(hipEventRecord(et[1], s), "event");
-        if (kk <= p.k_max) launch_hubs(g, rb, kk, s);
+        if (kk <= p.k_max && !stop_only) launch_hubs(g, rb, kk, s);
         if (timed) hip_check(hipEventRecord(et[2], s), "event");
         lr.launches++;
         if (split_first) lr.split_launches++;
@@ -192,7 +197,20 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
             bool split_first = false;
             for (uint64_t kq = 1; kq <= k_last && !done; kq++) {
                 const uint32_t kk = static_cast<uint32_t>(kq);
-                issue(kk, split_first);
+                // the stop test of the hash half (level kk-1) from the split
+                // half's founded count: a fixpoint or the level cap
+                bool predicted = false;
+                const std::function<bool()> ends_run = [&]() {
+                    hip_check(hipMemcpyAsync(ctx->count_host, rb.lcnt + ((kk - 1) & (kStripeRing - 1)) * kStripes,
+                                             kStripes * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "count copy");
+                    hip_check(hipStreamSynchronize(s), "split wait");
+                    uint64_t c = 0;
+                    for (int i = 0; i < kStripes; i++) c += ctx->count_host[i];
+                    const uint32_t lv = kk - 1;
+                    predicted = (lv >= 1 && c == 0) || lv >= p.k_max;
+                    return predicted;
+                };
+                issue(kk, split_first, ends_run);
                 hip_check(hipMemcpyAsync(&ctx->status_host[0], rb.status, sizeof(RunStatus), hipMemcpyDeviceToHost,
                                          s), "status copy");
                 // launch kk completed the split of level kk-1 (k_init: level 0)
@@ -200,6 +218,8 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                                          kStripes * sizeof(uint32_t), hipMemcpyDeviceToHost, s), "count copy");
                 hip_check(hipStreamSynchronize(s), "status wait");
                 done = ctx->status_host[0].done != 0;
+                if (predicted && !done)
+                    throw DeviceError{BSIM_E_DEVICE, "internal: a stop-only launch found the run going on"};
                 uint64_t founded = 0;
                 for (int i = 0; i < kStripes; i++) founded += ctx->count_host[i];
                 split_first = lr.split_launches < kMaxSplitLaunches &&
@@ -223,7 +243,7 @@ LoopResult run_refinement(bsim_ctx* ctx, const Staged& g, const bsim_params& p, 
                     rb.bc.hist = nh;
                     rb.bc.hist_cap = static_cast<uint32_t>(cap);
                 }
-                for (uint32_t i = 0; i < c; i++, k++) issue(static_cast<uint32_t>(k), false);
+                for (uint32_t i = 0; i < c; i++, k++) issue(static_cast<uint32_t>(k), false, nullptr);
                 const int slot = pending < 0 ? 0 : (pending ^ 1);
                 hip_check(hipMemcpyAsync(&ctx->status_host[slot], rb.status, sizeof(RunStatus),
                                          hipMemcpyDeviceToHost, s), "status copy");
