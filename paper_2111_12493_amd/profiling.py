@@ -484,9 +484,10 @@ def summary_batched(d: str, runs: int, out_dir: str) -> str:
     lines = ["# Batched summarization of 4,096 R-MAT graphs", "",
              "4,096 graphs with edge counts log-uniform in 10^2-10^6 (4.28e8 edges in all), degree U(4, 16), "
              "32 types and 32 labels (Zipf 1.0), drawn on the GPU; %d batched calls (each graph to its own "
-             "fixpoint) on a fresh context.  The first call of the size class autotunes: it runs every "
-             "candidate schedule on the batch and then the fastest, so the profile holds %d batched runs; "
-             "ms/run divides by them." % (runs, n_run), "",
+             "fixpoint) on a fresh context.  The first call of the size class autotunes: it runs the first "
+             "candidate once untimed (that run sizes the context's work buffer), every candidate schedule on "
+             "the batch, and then the fastest, so the profile holds %d batched runs; ms/run divides by them."
+             % (runs, n_run), "",
              "## Command (repository root, one MI355X)", "",
              BATCHED_COMMAND.format(d=d, runs=runs), "",
              "## Library kernels (all runs)", "", "```",
