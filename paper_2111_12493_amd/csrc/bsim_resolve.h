@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <thread>
 #include <utility>
@@ -53,8 +54,51 @@ struct ResolveScratch {
     std::vector<uint32_t> val, val2;
     std::vector<uint64_t> vpos;   // positions of the vertex operations
     std::vector<uint64_t> dbits;  // deleted vertices
+    // one thread's share of the changes and reverse additions, with its
+    // groups (offsets within the share)
+    struct Part {
+        std::vector<uint32_t> cu, cw, cl, cf, rw, ru, gsrc, gbeg;
+        uint64_t n_present = 0;
+        uint32_t max_label = 0;
+    };
+    std::vector<Part> parts;
     HostBatch hb;  // the result of resolve_ops_into
 };
+
+// Run f(0..T-1) on T host threads (share 0 on the calling thread; a share
+// whose thread cannot be started runs on the calling thread too).
+template <typename F>
+inline void host_parallel(size_t T, F f) {
+    std::vector<std::thread> th;
+    size_t t = 1;
+    try {
+        for (; t < T; t++) th.emplace_back(f, t);
+    } catch (...) {
+    }
+    for (size_t u = t; u < T; u++) f(u);
+    f(0);
+    for (auto& x : th) x.join();
+}
+
+// Host threads for n items: one per 65,536, at most 8 and the hardware's.
+inline size_t host_threads(uint64_t n) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    return std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hw ? hw : 1), 8, static_cast<size_t>(n / 65536)}));
+}
+
+// Boundaries of T ranges over [0, n) that never separate item i from item
+// i-1 when same(i) holds (so a group of equal items stays in one range).
+template <typename Same>
+inline std::vector<size_t> group_cuts(size_t n, size_t T, Same same) {
+    std::vector<size_t> cut(T + 1, n);
+    cut[0] = 0;
+    for (size_t t = 1; t < T; t++) {
+        size_t p = std::max(n * t / T, cut[t - 1]);
+        while (p > 0 && p < n && same(p)) p++;
+        cut[t] = p;
+    }
+    return cut;
+}
 
 // Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
 // Large inputs are split over host threads: per pass, every thread counts
@@ -68,22 +112,11 @@ inline void host_radix_sort(std::vector<uint64_t>& key, std::vector<uint32_t>& v
     constexpr uint32_t kBuckets = 1u << kDigit;
     const size_t n = key.size();
     if (n < 2) return;
-    const unsigned hw = std::thread::hardware_concurrency();
-    const size_t T = std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hw ? hw : 1), 8, n / 65536}));
+    const size_t T = host_threads(n);
     k2.resize(n);
     v2.resize(n);
     std::vector<uint32_t> cnt(kBuckets * T);
-    auto par = [&](auto f) {
-        std::vector<std::thread> th;
-        size_t t = 1;
-        try {
-            for (; t < T; t++) th.emplace_back(f, t);
-        } catch (...) {
-        }
-        for (size_t u = t; u < T; u++) f(u);  // shares no thread could take
-        f(0);
-        for (auto& x : th) x.join();
-    };
+    auto par = [&](auto f) { host_parallel(T, f); };
     for (int sh = 0; sh < bits; sh += kDigit) {
         par([&](size_t t) {
             uint32_t* c = &cnt[t * kBuckets];
@@ -188,22 +221,16 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     std::vector<uint64_t>& vpos = rs.vpos;
     vpos.clear();
     {
-        const unsigned hwv = std::thread::hardware_concurrency();
-        const size_t TV = std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hwv ? hwv : 1), 8, n_ops / 65536}));
+        const size_t TV = host_threads(n_ops);
         std::vector<std::vector<uint64_t>> found(TV);
-        auto scan = [&](size_t t) {
+        host_parallel(TV, [&](size_t t) {
+            // appends go to a vector of the thread's own (the headers in
+            // `found` share cache lines)
+            std::vector<uint64_t> f;
             for (uint64_t i = n_ops * t / TV, e = n_ops * (t + 1) / TV; i < e; i++)
-                if (ops[i].op < BSIM_OP_ADD_E || ops[i].op > BSIM_OP_DEL_E) found[t].push_back(i);
-        };
-        std::vector<std::thread> th;
-        size_t t = 1;
-        try {
-            for (; t < TV; t++) th.emplace_back(scan, t);
-        } catch (...) {
-        }
-        for (size_t u = t; u < TV; u++) scan(u);
-        scan(0);
-        for (auto& x : th) x.join();
+                if (ops[i].op < BSIM_OP_ADD_E || ops[i].op > BSIM_OP_DEL_E) f.push_back(i);
+            found[t].swap(f);
+        });
         for (const auto& f : found) vpos.insert(vpos.end(), f.begin(), f.end());
     }
     // the marks of the vertex kPv operations ahead are fetched meanwhile
@@ -283,15 +310,22 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     };
     const uint64_t lab_lim_e = lab_lim;
     const uint64_t end = std::min<uint64_t>(n_ops, vfail.pos);  // later operations do not count
-    const unsigned hw = std::thread::hardware_concurrency();
-    const size_t T = std::max<size_t>(1, std::min<size_t>({static_cast<size_t>(hw ? hw : 1), 8, end / 65536}));
+    const size_t T = host_threads(end);
     std::vector<std::vector<Rec>>& part = rs.part;
     if (part.size() < T) part.resize(T);
     std::vector<Fail> efail(T);
     std::vector<uint32_t> part_max(T, 0);
     auto check_edges = [&](size_t t) {
         const uint64_t a = end * t / T, b = end * (t + 1) / T;
-        std::vector<Rec>& out = part[t];
+        // the thread appends to a vector object of its own, holding part[t]'s
+        // storage (the headers in `part` share cache lines)
+        std::vector<Rec> out;
+        out.swap(part[t]);
+        struct Back {
+            std::vector<Rec>& a;
+            std::vector<Rec>& b;
+            ~Back() { a.swap(b); }
+        } back{out, part[t]};
         out.clear();
         out.reserve((b - a) + (b - a) / 4);
         uint32_t ml = 0;
@@ -333,17 +367,7 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
         }
         part_max[t] = ml;
     };
-    {
-        std::vector<std::thread> th;
-        size_t t = 1;
-        try {
-            for (; t < T; t++) th.emplace_back(check_edges, t);
-        } catch (...) {
-        }
-        for (size_t u = t; u < T; u++) check_edges(u);  // shares no thread could take
-        check_edges(0);
-        for (auto& x : th) x.join();
-    }
+    host_parallel(T, check_edges);
     Fail first = vfail;
     for (const Fail& f : efail)
         if (f.pos < first.pos) first = f;
@@ -391,23 +415,82 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     std::vector<uint32_t>& val = rs.val;
     key.clear();
     val.resize(nr);
-    auto emit = [&](uint32_t u, uint32_t w, uint32_t l, bool deleted, bool add) {
-        if (dead_at_end(u) || dead_at_end(w)) return;
-        hb.cu.push_back(u);
-        hb.cw.push_back(w);
-        hb.cl.push_back(l);
-        hb.cf.push_back((deleted ? kChgDeleted : 0u) | (add ? kChgPresent : 0u));
-        if (add) {
-            hb.n_present++;
-            hb.max_label = std::max(hb.max_label, l);
-            hb.rw.push_back(w);
-            hb.ru.push_back(u);
+    // The changes, one per distinct triple, in (u, w, l) order: deleted if
+    // any of its records removes it, present if its last record adds it;
+    // triples with an endpoint that ends deleted are dropped (the device
+    // removes all their edges).  Several threads each take a range of
+    // sources and fill a part of their own (with the source groups and the
+    // reverse additions); the parts are then joined in order.
+    std::vector<ResolveScratch::Part>& parts = rs.parts;
+    auto join_parts = [&](size_t TP) {
+        std::vector<size_t> co(TP + 1, 0), ro(TP + 1, 0), go(TP + 1, 0);
+        for (size_t t = 0; t < TP; t++) {
+            co[t + 1] = co[t] + parts[t].cu.size();
+            ro[t + 1] = ro[t] + parts[t].rw.size();
+            go[t + 1] = go[t] + parts[t].gsrc.size();
+            hb.n_present += parts[t].n_present;
+            hb.max_label = std::max(hb.max_label, parts[t].max_label);
         }
+        for (std::vector<uint32_t>* v : {&hb.cu, &hb.cw, &hb.cl, &hb.cf}) v->resize(co[TP]);
+        for (std::vector<uint32_t>* v : {&hb.rw, &hb.ru}) v->resize(ro[TP]);
+        for (std::vector<uint32_t>* v : {&hb.gsrc, &hb.gbeg, &hb.gend}) v->resize(go[TP]);
+        host_parallel(TP, [&](size_t t) {
+            const ResolveScratch::Part& P = parts[t];
+            std::copy(P.cu.begin(), P.cu.end(), hb.cu.begin() + co[t]);
+            std::copy(P.cw.begin(), P.cw.end(), hb.cw.begin() + co[t]);
+            std::copy(P.cl.begin(), P.cl.end(), hb.cl.begin() + co[t]);
+            std::copy(P.cf.begin(), P.cf.end(), hb.cf.begin() + co[t]);
+            std::copy(P.rw.begin(), P.rw.end(), hb.rw.begin() + ro[t]);
+            std::copy(P.ru.begin(), P.ru.end(), hb.ru.begin() + ro[t]);
+            std::copy(P.gsrc.begin(), P.gsrc.end(), hb.gsrc.begin() + go[t]);
+            const size_t ng = P.gsrc.size();
+            for (size_t g = 0; g < ng; g++) {
+                hb.gbeg[go[t] + g] = static_cast<uint32_t>(co[t] + P.gbeg[g]);
+                hb.gend[go[t] + g] = static_cast<uint32_t>(co[t] + (g + 1 < ng ? P.gbeg[g + 1] : P.cu.size()));
+            }
+        });
     };
-    hb.cu.reserve(nr);
-    hb.cw.reserve(nr);
-    hb.cl.reserve(nr);
-    hb.cf.reserve(nr);
+    // trip(i): the (u, w, l) of sorted record i; adds(i): whether it adds
+    auto emit_all = [&](auto trip, auto adds) {
+        const size_t TP = host_threads(nr);
+        if (parts.size() < TP) parts.resize(TP);
+        const std::vector<size_t> cut = group_cuts(nr, TP, [&](size_t i) { return trip(i)[0] == trip(i - 1)[0]; });
+        host_parallel(TP, [&](size_t t) {
+            // a Part object of the thread's own, holding parts[t]'s storage
+            // (the Parts' headers share cache lines)
+            ResolveScratch::Part P;
+            std::swap(P, parts[t]);
+            for (std::vector<uint32_t>* v : {&P.cu, &P.cw, &P.cl, &P.cf, &P.rw, &P.ru, &P.gsrc, &P.gbeg}) v->clear();
+            P.n_present = 0;
+            P.max_label = 0;
+            for (size_t i = cut[t], e = cut[t + 1]; i < e;) {
+                const auto x = trip(i);
+                size_t j = i;
+                bool deleted = false;
+                while (j < e && trip(j) == x) deleted |= !adds(j++);
+                const bool add = adds(j - 1);
+                i = j;
+                if (dead_at_end(x[0]) || dead_at_end(x[1])) continue;
+                if (P.gsrc.empty() || P.gsrc.back() != x[0]) {
+                    P.gsrc.push_back(x[0]);
+                    P.gbeg.push_back(static_cast<uint32_t>(P.cu.size()));
+                }
+                P.cu.push_back(x[0]);
+                P.cw.push_back(x[1]);
+                P.cl.push_back(x[2]);
+                P.cf.push_back((deleted ? kChgDeleted : 0u) | (add ? kChgPresent : 0u));
+                if (add) {
+                    P.n_present++;
+                    P.max_label = std::max(P.max_label, x[2]);
+                    P.rw.push_back(x[1]);
+                    P.ru.push_back(x[0]);
+                }
+            }
+            std::swap(P, parts[t]);
+        });
+        join_parts(TP);
+    };
+    using Trip = std::array<uint32_t, 3>;
     if (2 * bv + bl <= 64) {
         key.resize(nr);
         for (size_t i = 0; i < nr; i++) {
@@ -417,14 +500,12 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
         }
         host_radix_sort(key, val, 2 * bv + bl, rs.key2, rs.val2);
         const uint64_t lmask = (1ull << bl) - 1, wmask = (1ull << bv) - 1;
-        for (size_t i = 0; i < nr;) {
-            size_t j = i;
-            bool deleted = false;
-            while (j < nr && key[j] == key[i]) deleted |= val[j++] == 0;
-            emit(static_cast<uint32_t>(key[i] >> (bv + bl)), static_cast<uint32_t>((key[i] >> bl) & wmask),
-                 static_cast<uint32_t>(key[i] & lmask), deleted, val[j - 1] != 0);
-            i = j;
-        }
+        emit_all(
+            [&](size_t i) {
+                return Trip{static_cast<uint32_t>(key[i] >> (bv + bl)), static_cast<uint32_t>((key[i] >> bl) & wmask),
+                            static_cast<uint32_t>(key[i] & lmask)};
+            },
+            [&](size_t i) { return val[i] != 0; });
     } else {
         for (size_t i = 0; i < nr; i++) val[i] = static_cast<uint32_t>(i);
         std::stable_sort(val.begin(), val.end(), [&](uint32_t a, uint32_t b) {
@@ -433,46 +514,58 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
             if (x.w != y.w) return x.w < y.w;
             return x.l < y.l;
         });
-        for (size_t i = 0; i < nr;) {
-            const Rec& first = recs[val[i]];
-            size_t j = i;
-            bool deleted = false;
-            while (j < nr && recs[val[j]].u == first.u && recs[val[j]].w == first.w && recs[val[j]].l == first.l)
-                deleted |= recs[val[j++]].add == 0;
-            emit(first.u, first.w, first.l, deleted, recs[val[j - 1]].add != 0);
-            i = j;
-        }
+        emit_all([&](size_t i) { return Trip{recs[val[i]].u, recs[val[i]].w, recs[val[i]].l}; },
+                 [&](size_t i) { return recs[val[i]].add != 0; });
     }
-    for (size_t i = 0; i < hb.cu.size();) {
-        size_t j = i;
-        while (j < hb.cu.size() && hb.cu[j] == hb.cu[i]) j++;
-        hb.gsrc.push_back(hb.cu[i]);
-        hb.gbeg.push_back(static_cast<uint32_t>(i));
-        hb.gend.push_back(static_cast<uint32_t>(j));
-        i = j;
-    }
-    // reverse additions, grouped by target (duplicate pairs are harmless)
+    // reverse additions, sorted by (w, u) without duplicates and grouped by
+    // target: sorted on one thread pool, then de-duplicated and grouped per
+    // range of targets
     std::vector<uint64_t>& rk = rs.key;  // the edge records' keys are done with
     std::vector<uint32_t>& rdummy = rs.val;
-    rk.resize(hb.rw.size());
-    rdummy.resize(hb.rw.size());
-    for (size_t i = 0; i < rk.size(); i++) rk[i] = (static_cast<uint64_t>(hb.rw[i]) << bv) | hb.ru[i];
+    const size_t nrv = hb.rw.size();
+    rk.resize(nrv);
+    rdummy.resize(nrv);
+    for (size_t i = 0; i < nrv; i++) rk[i] = (static_cast<uint64_t>(hb.rw[i]) << bv) | hb.ru[i];
     host_radix_sort(rk, rdummy, 2 * bv, rs.key2, rs.val2);
-    rk.erase(std::unique(rk.begin(), rk.end()), rk.end());
-    hb.rw.resize(rk.size());
-    hb.ru.resize(rk.size());
-    const uint64_t umask = (1ull << bv) - 1;
-    for (size_t i = 0; i < rk.size(); i++) {
-        hb.rw[i] = static_cast<uint32_t>(rk[i] >> bv);
-        hb.ru[i] = static_cast<uint32_t>(rk[i] & umask);
-    }
-    for (size_t i = 0; i < hb.rw.size();) {
-        size_t j = i;
-        while (j < hb.rw.size() && hb.rw[j] == hb.rw[i]) j++;
-        hb.rgw.push_back(hb.rw[i]);
-        hb.rgbeg.push_back(static_cast<uint32_t>(i));
-        hb.rgend.push_back(static_cast<uint32_t>(j));
-        i = j;
+    {
+        const uint64_t umask = (1ull << bv) - 1;
+        const size_t TP = host_threads(nrv);
+        if (parts.size() < TP) parts.resize(TP);
+        const std::vector<size_t> cut = group_cuts(nrv, TP, [&](size_t i) { return (rk[i] >> bv) == (rk[i - 1] >> bv); });
+        host_parallel(TP, [&](size_t t) {
+            ResolveScratch::Part P;  // rw, ru, gsrc (targets) and gbeg; parts[t]'s storage
+            std::swap(P, parts[t]);
+            for (std::vector<uint32_t>* v : {&P.rw, &P.ru, &P.gsrc, &P.gbeg}) v->clear();
+            for (size_t i = cut[t], e = cut[t + 1]; i < e; i++) {
+                if (i > cut[t] && rk[i] == rk[i - 1]) continue;
+                const uint32_t w = static_cast<uint32_t>(rk[i] >> bv);
+                if (P.gsrc.empty() || P.gsrc.back() != w) {
+                    P.gsrc.push_back(w);
+                    P.gbeg.push_back(static_cast<uint32_t>(P.rw.size()));
+                }
+                P.rw.push_back(w);
+                P.ru.push_back(static_cast<uint32_t>(rk[i] & umask));
+            }
+            std::swap(P, parts[t]);
+        });
+        std::vector<size_t> ro(TP + 1, 0), go(TP + 1, 0);
+        for (size_t t = 0; t < TP; t++) {
+            ro[t + 1] = ro[t] + parts[t].rw.size();
+            go[t + 1] = go[t] + parts[t].gsrc.size();
+        }
+        for (std::vector<uint32_t>* v : {&hb.rw, &hb.ru}) v->resize(ro[TP]);
+        for (std::vector<uint32_t>* v : {&hb.rgw, &hb.rgbeg, &hb.rgend}) v->resize(go[TP]);
+        host_parallel(TP, [&](size_t t) {
+            const ResolveScratch::Part& P = parts[t];
+            std::copy(P.rw.begin(), P.rw.end(), hb.rw.begin() + ro[t]);
+            std::copy(P.ru.begin(), P.ru.end(), hb.ru.begin() + ro[t]);
+            std::copy(P.gsrc.begin(), P.gsrc.end(), hb.rgw.begin() + go[t]);
+            const size_t ng = P.gsrc.size();
+            for (size_t g = 0; g < ng; g++) {
+                hb.rgbeg[go[t] + g] = static_cast<uint32_t>(ro[t] + P.gbeg[g]);
+                hb.rgend[go[t] + g] = static_cast<uint32_t>(ro[t] + (g + 1 < ng ? P.gbeg[g + 1] : P.rw.size()));
+            }
+        });
     }
     return hb;
 }

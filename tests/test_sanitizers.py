@@ -1,6 +1,6 @@
 """Address and undefined-behaviour sanitizer runs of the host-side code (CPU).
 
-Two programs are built with -fsanitize=address,undefined (any finding
+Three programs are built with -fsanitize=address,undefined (any finding
 aborts the run) and run on seeded random inputs:
   - tests/native/oracle_check.c drives every entry point of the C oracle
     and checks its results against the invariants they must satisfy and
@@ -9,7 +9,8 @@ aborts the run) and run on seeded random inputs:
   - tests/native/resolve_check.cpp drives the host-side resolution of
     update batches (csrc/bsim_resolve.h, the same header the library
     compiles) against a plain sequential model of the operations, valid
-    and invalid batches alike;
+    and invalid batches alike (also built with the thread sanitizer, for
+    the passes that split a large batch over host threads);
   - tests/native/sched_check.cpp drives the serving loop's scheduler
     (csrc/bsim_sched.h) from submitter, worker and poller threads with a
     fake executor, built once with the thread sanitizer and once with the
@@ -69,6 +70,14 @@ def test_oracle_under_sanitizers(oracle_exe, seed):
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_update_resolution_under_sanitizers(resolve_exe, seed):
     assert _run(resolve_exe, seed) > 400
+
+
+def test_update_resolution_under_the_thread_sanitizer():
+    # the large batches split their checks, sorts and emit passes over
+    # several host threads
+    exe = _build("g++", "-std=c++17", ["tests/native/resolve_check.cpp"], "resolve_check_tsan",
+                 ["-O1", "-g", "-fsanitize=thread"])
+    assert _run(exe, 1) > 400
 
 
 @pytest.fixture(scope="module")
