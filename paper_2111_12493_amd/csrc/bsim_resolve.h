@@ -372,11 +372,11 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     for (const Fail& f : efail)
         if (f.pos < first.pos) first = f;
     if (first.pos != UINT64_MAX) throw DeviceError{first.status, first.msg};
-    size_t nrec = 0;
-    for (const auto& q : part) nrec += q.size();
-    recs.reserve(nrec);
+    // the edge records stay in the threads' parts: part[t] holds records
+    // roff[t] .. roff[t+1] of the batch, in operation order
+    std::vector<size_t> roff(T + 1, 0);
     for (size_t t = 0; t < T; t++) {
-        recs.insert(recs.end(), part[t].begin(), part[t].end());
+        roff[t + 1] = roff[t] + part[t].size();
         max_l = std::max(max_l, part_max[t]);
     }
     hb.n_new = n_cur;
@@ -410,7 +410,7 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     // the triple packed in one key when it fits 64 bits (the add flag rides
     // in the value), else a comparison sort
     const int bv = std::max(1, bit_width(n_cur)), bl = std::max(1, bit_width(max_l + 1));
-    const size_t nr = recs.size();
+    const size_t nr = roff[T];
     std::vector<uint64_t>& key = rs.key;
     std::vector<uint32_t>& val = rs.val;
     key.clear();
@@ -493,11 +493,13 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     using Trip = std::array<uint32_t, 3>;
     if (2 * bv + bl <= 64) {
         key.resize(nr);
-        for (size_t i = 0; i < nr; i++) {
-            key[i] = (static_cast<uint64_t>(recs[i].u) << (bv + bl)) | (static_cast<uint64_t>(recs[i].w) << bl) |
-                     recs[i].l;
-            val[i] = recs[i].add;
-        }
+        host_parallel(T, [&](size_t t) {
+            const std::vector<Rec>& q = part[t];
+            for (size_t i = 0, o = roff[t]; i < q.size(); i++, o++) {
+                key[o] = (static_cast<uint64_t>(q[i].u) << (bv + bl)) | (static_cast<uint64_t>(q[i].w) << bl) | q[i].l;
+                val[o] = q[i].add;
+            }
+        });
         host_radix_sort(key, val, 2 * bv + bl, rs.key2, rs.val2);
         const uint64_t lmask = (1ull << bl) - 1, wmask = (1ull << bv) - 1;
         emit_all(
@@ -507,6 +509,8 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
             },
             [&](size_t i) { return val[i] != 0; });
     } else {
+        recs.reserve(nr);
+        for (size_t t = 0; t < T; t++) recs.insert(recs.end(), part[t].begin(), part[t].end());
         for (size_t i = 0; i < nr; i++) val[i] = static_cast<uint32_t>(i);
         std::stable_sort(val.begin(), val.end(), [&](uint32_t a, uint32_t b) {
             const Rec &x = recs[a], &y = recs[b];
