@@ -380,8 +380,17 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
         max_l = std::max(max_l, part_max[t]);
     }
     hb.n_new = n_cur;
-    hb.tl = touched;
-    std::sort(hb.tl.begin(), hb.tl.end());
+    {
+        // the touched vertices in id order (radix: a comparison sort of
+        // 10^5 ids costs milliseconds); rs.key/val are free until the edge
+        // records' keys
+        std::vector<uint64_t>& tk = rs.key;
+        std::vector<uint32_t>& tv = rs.val;
+        tk.assign(touched.begin(), touched.end());
+        tv.resize(touched.size());
+        host_radix_sort(tk, tv, std::max(1, bit_width(n_cur)), rs.key2, rs.val2);
+        hb.tl.assign(tk.begin(), tk.end());
+    }
     hb.tl_off.reserve(hb.tl.size() + 1);
     hb.tl_off.push_back(0);
     for (size_t k = 0; k < hb.tl.size(); k++) {
