@@ -17,6 +17,9 @@
 #include <utility>
 #include <vector>
 
+#include <sys/types.h>
+#include <unistd.h>
+
 #include "bsim.h"
 #include "bsim_host.h"
 
@@ -29,6 +32,8 @@ constexpr uint32_t kMaxStateTypes = 4096;
 // Host threads kept for the parallel passes of the resolution.  A large
 // batch runs about thirty such passes; starting and joining threads for
 // each cost about a fifth of the resolution of a 5 * 10^5-operation batch.
+// One pool serves the process (shared_host_pool); a pass that finds it busy
+// (another state's resolution on another thread) starts threads of its own.
 class HostPool {
   public:
     explicit HostPool(size_t workers) {
@@ -53,11 +58,15 @@ class HostPool {
 
     // f(0 .. T-1) with shares 1 .. W on the workers (W = min(T - 1,
     // workers)) and the others on the calling thread; returns when all are
-    // done and rethrows the first exception of any share.
-    void run(size_t T, const std::function<void(size_t)>& f) {
+    // done and rethrows the first exception of any share.  Returns false
+    // at once, running nothing, when the pool is running another job or
+    // belongs to another process (a fork keeps no threads).
+    bool try_run(size_t T, const std::function<void(size_t)>& f) {
         const size_t W = std::min(T ? T - 1 : 0, th_.size());
         {
             std::lock_guard<std::mutex> lk(mu_);
+            if (busy_ || owner_ != getpid()) return false;
+            busy_ = true;
             job_ = &f;
             job_n_ = W;
             pending_ = W;
@@ -75,8 +84,10 @@ class HostPool {
         std::unique_lock<std::mutex> lk(mu_);
         done_.wait(lk, [&] { return pending_ == 0; });
         job_ = nullptr;
+        busy_ = false;
         if (mine) std::rethrow_exception(mine);
         if (err_) std::rethrow_exception(err_);
+        return true;
     }
 
   private:
@@ -110,8 +121,21 @@ class HostPool {
     size_t job_n_ = 0, pending_ = 0;
     uint64_t gen_ = 0;
     std::exception_ptr err_;
-    bool stop_ = false;
+    bool stop_ = false, busy_ = false;
+    const pid_t owner_ = getpid();
 };
+
+// The process's pool: min(hardware threads, 8) - 1 workers, started on
+// first use.  It is never destroyed: its idle workers end with the process,
+// and a process forked from this one (which has none of its threads) never
+// joins them.
+inline HostPool& shared_host_pool() {
+    static HostPool* pool = new HostPool([] {
+        const unsigned hw = std::thread::hardware_concurrency();
+        return static_cast<size_t>(std::min(hw ? hw : 1u, 8u) - 1);
+    }());
+    return *pool;
+}
 
 // Net effect of one update batch, resolved on the host.
 struct HostBatch {
@@ -154,7 +178,6 @@ struct ResolveScratch {
         uint32_t max_label = 0;
     };
     std::vector<Part> parts;
-    std::unique_ptr<HostPool> pool;  // started by the first batch large enough to split
     HostBatch hb;  // the result of resolve_ops_into
 };
 
@@ -167,10 +190,7 @@ inline void host_parallel(size_t T, F f, HostPool* pool = nullptr) {
         if (T) f(0);
         return;
     }
-    if (pool) {
-        pool->run(T, std::function<void(size_t)>(f));
-        return;
-    }
+    if (pool && pool->try_run(T, std::function<void(size_t)>(f))) return;
     std::vector<std::thread> th;
     size_t t = 1;
     try {
@@ -265,10 +285,9 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
     hb.n_new = 0;
     hb.max_label = 0;
     hb.n_present = 0;
-    // the host threads of the parallel passes, started by the first batch
-    // large enough to split and kept with the scratch
-    if (!rs.pool && host_threads(n_ops) > 1) rs.pool.reset(new HostPool(host_threads(UINT64_MAX) - 1));
-    HostPool* const pool = rs.pool.get();
+    // the host threads of the parallel passes (the process's pool, started
+    // by the first batch large enough to split)
+    HostPool* const pool = host_threads(n_ops) > 1 ? &shared_host_pool() : nullptr;
     auto par = [pool](size_t T, auto f) { host_parallel(T, f, pool); };
     uint32_t n_cur = n0;
     std::vector<uint8_t>& vmark = rs.vmark;
