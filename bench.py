@@ -92,18 +92,28 @@ def cpu_baseline(g, stride: int):
 
     from oracle import oracle as orc
 
+    # one core for the oracle; the mask is restored afterwards, since every
+    # thread started later (the library's host threads, the server's
+    # workers) inherits it
+    mask = os.sched_getaffinity(0)
     try:
-        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+        os.sched_setaffinity(0, {sorted(mask)[0]})
     except Exception:
         pass
-    t = orc.type_hashes(g)
-    count = (g.n + stride - 1) // stride
-    deg = np.diff(g.row_off.astype(np.int64))
-    edges = int(deg[::stride].sum())
-    t0 = time.perf_counter()
-    h1 = orc.step_strided(g, t, t, 0, stride, count)
-    orc.refine_classes(np.zeros(count, dtype=np.uint32), h1)
-    dt = time.perf_counter() - t0
+    try:
+        t = orc.type_hashes(g)
+        count = (g.n + stride - 1) // stride
+        deg = np.diff(g.row_off.astype(np.int64))
+        edges = int(deg[::stride].sum())
+        t0 = time.perf_counter()
+        h1 = orc.step_strided(g, t, t, 0, stride, count)
+        orc.refine_classes(np.zeros(count, dtype=np.uint32), h1)
+        dt = time.perf_counter() - t0
+    finally:
+        try:
+            os.sched_setaffinity(0, mask)
+        except Exception:
+            pass
     return {"value": edges / dt, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
             "host_cpu": host_cpu_model(),
             "sample": "one refinement step (h^1 from h^0, gathers over the whole graph) and the class "
