@@ -169,7 +169,7 @@ struct ResolveScratch {
     std::vector<uint64_t> key, key2;
     std::vector<uint32_t> val, val2;
     std::vector<uint64_t> vpos;   // positions of the vertex operations
-    std::vector<uint64_t> dbits;  // deleted vertices
+    std::vector<uint64_t> dbits, dfilt;  // deleted vertices, and a small filter of them
     // one thread's share of the changes and reverse additions, with its
     // groups (offsets within the share)
     struct Part {
@@ -534,13 +534,24 @@ inline HostBatch& resolve_ops_into(HostBatch& hb, uint32_t n0, uint32_t label_by
         hb.tl_off.push_back(static_cast<uint32_t>(hb.tl_ids.size()));
     }
     // the deleted vertices as a bitmap (n bits: mostly in cache)
+    // ... and a 64 KiB filter of them (bit v mod 2^19) that stays in cache:
+    // the emit pass asks for both ends of every change, and most answers
+    // are "no" from the filter alone
     std::vector<uint64_t>& dbits = rs.dbits;
+    std::vector<uint64_t>& dfilt = rs.dfilt;
+    constexpr uint32_t kFiltMask = (1u << 19) - 1;
     const bool any_dead = !hb.dead.empty();
     if (any_dead) {
         dbits.assign((static_cast<size_t>(n_cur) + 63) / 64, 0);
-        for (uint32_t v : hb.dead) dbits[v >> 6] |= 1ull << (v & 63);
+        dfilt.assign((kFiltMask + 1) / 64, 0);
+        for (uint32_t v : hb.dead) {
+            dbits[v >> 6] |= 1ull << (v & 63);
+            dfilt[(v & kFiltMask) >> 6] |= 1ull << (v & 63);
+        }
     }
-    auto dead_at_end = [&](uint32_t v) { return any_dead && ((dbits[v >> 6] >> (v & 63)) & 1); };
+    auto dead_at_end = [&](uint32_t v) {
+        return any_dead && ((dfilt[(v & kFiltMask) >> 6] >> (v & 63)) & 1) && ((dbits[v >> 6] >> (v & 63)) & 1);
+    };
     // edge records in (u, w, l) order, input order within equal triples:
     // the triple packed in one key when it fits 64 bits (the add flag rides
     // in the value), else a comparison sort
