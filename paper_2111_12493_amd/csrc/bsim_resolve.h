@@ -75,11 +75,12 @@ class HostPool {
         }
         if (W) cv_.notify_all();
         std::exception_ptr mine;
-        try {
-            for (size_t u = W + 1; u < T; u++) f(u);
-            f(0);
-        } catch (...) {
-            mine = std::current_exception();
+        for (size_t u = W + 1; u <= T; u++) {  // shares W+1 .. T-1, then 0
+            try {
+                f(u < T ? u : 0);
+            } catch (...) {
+                if (!mine) mine = std::current_exception();
+            }
         }
         std::unique_lock<std::mutex> lk(mu_);
         done_.wait(lk, [&] { return pending_ == 0; });
@@ -183,7 +184,8 @@ struct ResolveScratch {
 
 // Run f(0..T-1) on T host threads (share 0 on the calling thread; a share
 // whose thread cannot be started runs on the calling thread too), on the
-// pool's threads when one is given.
+// pool's threads when one is given and free.  Every share runs; the first
+// exception of any share is rethrown after all have ended.
 template <typename F>
 inline void host_parallel(size_t T, F f, HostPool* pool = nullptr) {
     if (T <= 1) {
@@ -191,15 +193,28 @@ inline void host_parallel(size_t T, F f, HostPool* pool = nullptr) {
         return;
     }
     if (pool && pool->try_run(T, std::function<void(size_t)>(f))) return;
+    // threads of the call's own; every share runs, and the first exception
+    // of any share is rethrown once all have ended
+    std::mutex mu;
+    std::exception_ptr err;
+    auto share = [&](size_t u) {
+        try {
+            f(u);
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (!err) err = std::current_exception();
+        }
+    };
     std::vector<std::thread> th;
     size_t t = 1;
     try {
-        for (; t < T; t++) th.emplace_back(f, t);
+        for (; t < T; t++) th.emplace_back(share, t);
     } catch (...) {
     }
-    for (size_t u = t; u < T; u++) f(u);
-    f(0);
+    for (size_t u = t; u < T; u++) share(u);
+    share(0);
     for (auto& x : th) x.join();
+    if (err) std::rethrow_exception(err);
 }
 
 // Host threads for n items: one per 65,536, at most 8 and the hardware's.

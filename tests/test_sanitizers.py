@@ -1,6 +1,6 @@
 """Address and undefined-behaviour sanitizer runs of the host-side code (CPU).
 
-Three programs are built with -fsanitize=address,undefined (any finding
+Four programs are built with -fsanitize=address,undefined (any finding
 aborts the run) and run on seeded random inputs:
   - tests/native/oracle_check.c drives every entry point of the C oracle
     and checks its results against the invariants they must satisfy and
@@ -11,6 +11,9 @@ aborts the run) and run on seeded random inputs:
     compiles) against a plain sequential model of the operations, valid
     and invalid batches alike (also built with the thread sanitizer, for
     the passes that split a large batch over host threads);
+  - tests/native/pool_check.cpp drives the host thread pool of those
+    passes: every share once, concurrent callers, exceptions (built with
+    each sanitizer);
   - tests/native/sched_check.cpp drives the serving loop's scheduler
     (csrc/bsim_sched.h) from submitter, worker and poller threads with a
     fake executor, built once with the thread sanitizer and once with the
@@ -70,6 +73,13 @@ def test_oracle_under_sanitizers(oracle_exe, seed):
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_update_resolution_under_sanitizers(resolve_exe, seed):
     assert _run(resolve_exe, seed) > 400
+
+
+@pytest.mark.parametrize("san", ["asan", "tsan"])
+def test_resolution_thread_pool_under_sanitizers(san):
+    flags = ["-O1", "-g", "-fsanitize=thread"] if san == "tsan" else None
+    exe = _build("g++", "-std=c++17", ["tests/native/pool_check.cpp"], "pool_check_" + san, flags)
+    assert _run(exe, 1) > 400
 
 
 def test_update_resolution_under_the_thread_sanitizer():
