@@ -14,8 +14,8 @@
 //     its mixed pair keys to d scratch slots, and into 2^b hash buckets that
 //     each fit the LDS table of the hub-bucket launch.
 #include <algorithm>
-#include <numeric>
 
+#include "bsim_resolve.h"  // host_radix_sort
 #include "bsim_internal.h"
 
 namespace bsim {
@@ -405,11 +405,19 @@ void stage_graph(Staged& g, RunStatus* status_dev, RunStatus* status_host, Arena
         hip_check(hipMemcpyAsync(g.host_hub_deg.data(), hdeg, g.n_hubs * sizeof(uint32_t),
                                  hipMemcpyDeviceToHost, s), "hub degrees");
         hip_check(hipStreamSynchronize(s), "hubs sync");
+        // by degree, largest first, ties in hub order: a stable radix sort
+        // on the complemented degree (a graph of 2^30 edges has some 10^5
+        // hubs, which a comparison sort orders in milliseconds)
         std::vector<uint32_t> order(g.n_hubs);
-        std::iota(order.begin(), order.end(), 0u);
-        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-            return g.host_hub_deg[a] > g.host_hub_deg[b];
-        });
+        {
+            std::vector<uint64_t> key(g.n_hubs), k2;
+            std::vector<uint32_t> v2;
+            for (uint32_t i = 0; i < g.n_hubs; i++) {
+                key[i] = 0xFFFFFFFFull - g.host_hub_deg[i];
+                order[i] = i;
+            }
+            host_radix_sort(key, order, 32, k2, v2);
+        }
         // a hub of degree d > kSoloMaxEdges: ceil(d / kTileMaxEdges) chunk
         // blocks, and 2^b bucket blocks so that a bucket expects at most 3/4
         // of the LDS slots; the others are solo blocks (no chunks, no buckets)
